@@ -1,0 +1,236 @@
+"""Plain FP64 CPU oracle for the alternating proximal-gradient GLRM fit.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only users.  The product library never imports,
+links or calls anything here, and this package imports nothing from the
+product package.
+
+The arithmetic lives in ``glrm_oracle.c`` (double precision, sequential loops
+over the observed entries).  This module only marshals arrays: it turns a
+dense table plus mask, or a row-sorted COO list, into the row-compressed list
+of observed entries the C code walks, and builds the transposed list for the
+column half-step (Section 7.2 defines the Y update as the X update with the
+roles of X and Y swapped and every matrix argument transposed).
+
+Loss kinds: 0 quadratic, 1 Huber(delta = param), 2 logistic, 3 hinge,
+4 ordinal hinge over 1..levels.  Regularizer kinds: 0 zero, 1 quadratic
+w*||x||^2, 2 l1 w*||x||_1, 3 nonnegative indicator.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "glrm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build():
+    """Compile the oracle with gcc (plain -O2, no fast-math: IEEE double)."""
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
+                           "-o", _LIB, _SRC, "-lm"])
+
+
+class _Loss(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("levels", ctypes.c_int32), ("param", ctypes.c_double)]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
+                ("ecode", ctypes.c_void_p), ("losses", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P, D, I64, I32 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int32
+        L.oracle_loss.restype = D
+        L.oracle_loss.argtypes = [P, D, D]
+        L.oracle_dloss.restype = D
+        L.oracle_dloss.argtypes = [P, D, D]
+        L.oracle_reg.restype = D
+        L.oracle_reg.argtypes = [I32, D, P, I32]
+        L.oracle_prox.restype = None
+        L.oracle_prox.argtypes = [I32, D, D, P, I32]
+        L.oracle_loss_sum.restype = D
+        L.oracle_loss_sum.argtypes = [P, P, P]
+        L.oracle_loss_grad_rows.restype = None
+        L.oracle_loss_grad_rows.argtypes = [P, P, P, P]
+        L.oracle_half_step.restype = I64
+        L.oracle_half_step.argtypes = [P, P, P, P, I32, D, D, D, P, P, P, P]
+        L.oracle_init_alpha.restype = None
+        L.oracle_init_alpha.argtypes = [P, D, P]
+        L.oracle_reg_sum.restype = D
+        L.oracle_reg_sum.argtypes = [I32, D, P, I64, I32]
+        L.oracle_objective.restype = D
+        L.oracle_objective.argtypes = [P, P, P, I32, D, I32, D]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---- scalar helpers (for pin tests) -----------------------------------------
+def loss(kind, u, a, levels=0, param=1.0):
+    L = _Loss(kind, levels, param)
+    return lib().oracle_loss(ctypes.byref(L), float(u), float(a))
+
+
+def dloss(kind, u, a, levels=0, param=1.0):
+    L = _Loss(kind, levels, param)
+    return lib().oracle_dloss(ctypes.byref(L), float(u), float(a))
+
+
+def reg(kind, w, x):
+    x = _f64(x).ravel()
+    return lib().oracle_reg(kind, float(w), _ptr(x), x.size)
+
+
+def prox(kind, w, alpha, v):
+    v = _f64(v).ravel().copy()
+    lib().oracle_prox(kind, float(w), float(alpha), _ptr(v), v.size)
+    return v
+
+
+class _View:
+    """One row-compressed list of observed entries (kept alive with its arrays)."""
+
+    def __init__(self, m, n, k, row_ptr, col, val, ecode, loss_arr):
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.val = _f64(val)
+        self.ecode = np.ascontiguousarray(ecode, dtype=np.uint8)
+        self._loss_arr = loss_arr
+        self.s = _Problem(m, n, k, self.row_ptr.ctypes.data, self.col.ctypes.data,
+                          self.val.ctypes.data, self.ecode.ctypes.data,
+                          ctypes.addressof(loss_arr))
+        self.m, self.n = m, n
+
+
+class Problem:
+    """A GLRM instance in the oracle's form.
+
+    Build it with :meth:`from_dense` (A m x n, mask m x n bool or None) or
+    :meth:`from_coo` (row-sorted unique (i, j) pairs and values).
+    ``col_loss`` holds one loss-table index per column; ``losses`` is a list of
+    ``(kind, levels, param)``; ``rx`` / ``ry`` are ``(kind, weight)``.
+    """
+
+    def __init__(self, m, n, k, rows, cols, vals, col_loss, losses, rx, ry):
+        self.m, self.n, self.k = int(m), int(n), int(k)
+        self.rx, self.ry = (int(rx[0]), float(rx[1])), (int(ry[0]), float(ry[1]))
+        self.losses = list(losses)
+        self._loss_arr = (_Loss * max(1, len(losses)))(*[_Loss(int(a), int(b), float(c)) for a, b, c in losses])
+        rows = np.asarray(rows, dtype=np.int64)
+        cols = np.asarray(cols, dtype=np.int64)
+        vals = np.asarray(vals, dtype=np.float64)
+        ecode = np.asarray(col_loss, dtype=np.uint8)[cols]
+        # row view: entries ordered by (row, column)
+        o = np.lexsort((cols, rows))
+        rp = np.zeros(self.m + 1, dtype=np.int64)
+        np.add.at(rp, rows + 1, 1)
+        self.row = _View(self.m, self.n, self.k, np.cumsum(rp), cols[o], vals[o], ecode[o], self._loss_arr)
+        # transposed view for the column half-step: ordered by (column, row)
+        o = np.lexsort((rows, cols))
+        cp = np.zeros(self.n + 1, dtype=np.int64)
+        np.add.at(cp, cols + 1, 1)
+        self.colv = _View(self.n, self.m, self.k, np.cumsum(cp), rows[o], vals[o], ecode[o], self._loss_arr)
+        self.nnz = int(rows.size)
+
+    @classmethod
+    def from_dense(cls, A, mask, k, col_loss, losses, rx, ry):
+        A = np.asarray(A)
+        m, n = A.shape
+        if mask is None:
+            rows, cols = np.divmod(np.arange(m * n, dtype=np.int64), n)
+        else:
+            rows, cols = np.nonzero(np.asarray(mask))
+        return cls(m, n, k, rows, cols, A[rows, cols], col_loss, losses, rx, ry)
+
+    @classmethod
+    def from_coo(cls, m, n, k, rows, cols, vals, col_loss, losses, rx, ry):
+        return cls(m, n, k, rows, cols, vals, col_loss, losses, rx, ry)
+
+    # ---- the method ----------------------------------------------------------
+    def objective(self, X, Y):
+        X, Y = _f64(X), _f64(Y)
+        return lib().oracle_objective(ctypes.byref(self.row.s), _ptr(X), _ptr(Y),
+                                      self.rx[0], self.rx[1], self.ry[0], self.ry[1])
+
+    def loss_sum(self, X, Y):
+        X, Y = _f64(X), _f64(Y)
+        return lib().oracle_loss_sum(ctypes.byref(self.row.s), _ptr(X), _ptr(Y))
+
+    def grad(self, X, Y):
+        """Loss-part gradients (dX m x k, dY n x k)."""
+        X, Y = _f64(X), _f64(Y)
+        dX = np.empty_like(X)
+        dY = np.empty_like(Y)
+        lib().oracle_loss_grad_rows(ctypes.byref(self.row.s), _ptr(X), _ptr(Y), _ptr(dX))
+        lib().oracle_loss_grad_rows(ctypes.byref(self.colv.s), _ptr(Y), _ptr(X), _ptr(dY))
+        return dX, dY
+
+    def init_alpha(self, s=1.0):
+        ax = np.empty(self.m)
+        ay = np.empty(self.n)
+        lib().oracle_init_alpha(ctypes.byref(self.row.s), float(s), _ptr(ax))
+        lib().oracle_init_alpha(ctypes.byref(self.colv.s), float(s), _ptr(ay))
+        return ax, ay
+
+    def half_step_x(self, X, Y, ax, step_up=1.05, step_down=0.7):
+        """X half-step in place on float64 arrays; returns (rejected, f_old, f_new, accepted)."""
+        fo, fn, acc = np.empty(self.m), np.empty(self.m), np.empty(self.m, dtype=np.uint8)
+        scr = np.empty(2 * self.k)
+        rej = lib().oracle_half_step(ctypes.byref(self.row.s), _ptr(X), _ptr(Y), _ptr(ax),
+                                     self.rx[0], self.rx[1], float(step_up), float(step_down),
+                                     _ptr(fo), _ptr(fn), _ptr(acc), _ptr(scr))
+        return rej, fo, fn, acc
+
+    def half_step_y(self, X, Y, ay, step_up=1.05, step_down=0.7):
+        """Y half-step in place (the X half-step on the transposed problem)."""
+        fo, fn, acc = np.empty(self.n), np.empty(self.n), np.empty(self.n, dtype=np.uint8)
+        scr = np.empty(2 * self.k)
+        rej = lib().oracle_half_step(ctypes.byref(self.colv.s), _ptr(Y), _ptr(X), _ptr(ay),
+                                     self.ry[0], self.ry[1], float(step_up), float(step_down),
+                                     _ptr(fo), _ptr(fn), _ptr(acc), _ptr(scr))
+        return rej, fo, fn, acc
+
+    def sweep(self, X, Y, ax, ay, step_up=1.05, step_down=0.7):
+        """One iteration t of Algorithm 2 (Gauss-Seidel: the Y half-step sees X^t).
+
+        Works in place on float64 arrays and returns a dict of diagnostics."""
+        rx_, fxo, fxn, accx = self.half_step_x(X, Y, ax, step_up, step_down)
+        ry_, fyo, fyn, accy = self.half_step_y(X, Y, ay, step_up, step_down)
+        return dict(rows_rejected=rx_, cols_rejected=ry_, f_row_old=fxo, f_row_new=fxn, row_accepted=accx,
+                    f_col_old=fyo, f_col_new=fyn, col_accepted=accy)
+
+    def fit(self, X0, Y0, sweeps, alpha=None, alpha_scale=1.0, step_up=1.05, step_down=0.7):
+        """Run ``sweeps`` iterations from (X0, Y0); alpha=None starts from s/n_i.
+
+        Returns X, Y, ax, ay, history (objective after each sweep), rejects."""
+        X, Y = _f64(X0).copy(), _f64(Y0).copy()
+        if alpha is None:
+            ax, ay = self.init_alpha(alpha_scale)
+        else:
+            ax, ay = _f64(alpha[0]).copy(), _f64(alpha[1]).copy()
+        hist, rej = [], []
+        for _ in range(int(sweeps)):
+            d = self.sweep(X, Y, ax, ay, step_up, step_down)
+            hist.append(self.objective(X, Y))
+            rej.append((d["rows_rejected"], d["cols_rejected"]))
+        return X, Y, ax, ay, np.array(hist), rej

@@ -1,0 +1,251 @@
+/*
+ * Plain FP64 CPU oracle for the alternating proximal-gradient fit of a
+ * generalized low rank model (Udell, Horn, Zadeh, Boyd: "Generalized Low Rank
+ * Models", arXiv 1410.0342).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, calls or
+ * includes this file; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it.  It shares no code, header, table or
+ * helper with the HIP path.
+ *
+ * Everything is double precision, sequential, and walks only the observed
+ * entries, in the order rows → entries of the row.  No blocking, fusion or
+ * reordering beyond what the paper's definitions state.
+ *
+ * Problem (eq. gpca, Section 4; abstract form eq. apca, Section 5):
+ *     minimize  sum_{(i,j) in Omega} L_ij(x_i . y_j, A_ij)
+ *               + sum_i r(x_i) + sum_j rt(y_j)
+ * X is m x k (row x_i), Y is stored n x k (row j holds the paper's column y_j).
+ *
+ * The observed set is handed over as a row-compressed list of entries
+ * (row_ptr / col / val / ecode, ecode = index into the loss table).  The
+ * column half-step is the row half-step on the transposed problem, which is
+ * exactly how Section 7.2 defines it: swap the roles of X and Y, use rt for r,
+ * transpose every matrix argument.  The caller builds the transposed list.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+
+enum { OR_QUAD = 0, OR_HUBER = 1, OR_LOGISTIC = 2, OR_HINGE = 3, OR_ORDINAL = 4 };
+enum { OR_RZERO = 0, OR_RQUAD = 1, OR_RL1 = 2, OR_RNONNEG = 3 };
+
+typedef struct {
+    int32_t kind;
+    int32_t levels;   /* ordinal: number of levels d (data in 1..d) */
+    double param;     /* Huber: threshold delta */
+} oracle_loss_t;
+
+typedef struct {
+    int64_t m, n;                 /* rows of the updated factor, rows of the fixed factor */
+    int32_t k;
+    const int64_t *row_ptr;       /* m+1 */
+    const int32_t *col;           /* nnz, index into the fixed factor */
+    const double *val;            /* nnz, A_ij */
+    const uint8_t *ecode;         /* nnz, loss of the entry (its column's loss) */
+    const oracle_loss_t *losses;  /* table */
+} oracle_problem_t;
+
+static double pos(double t) { return t > 0.0 ? t : 0.0; }
+
+/* ---- losses, value (Section 4 and Section 5.1 / 5.3) ----------------------- */
+double oracle_loss(const oracle_loss_t *L, double u, double a)
+{
+    switch (L->kind) {
+    case OR_QUAD:          /* (a-u)^2, eq. qpca */
+        return (a - u) * (a - u);
+    case OR_HUBER: {       /* huber(u-a): half r^2 inside the threshold, linear outside */
+        double r = u - a, d = L->param, ar = fabs(r);
+        return ar <= d ? 0.5 * r * r : d * ar - 0.5 * d * d;
+    }
+    case OR_LOGISTIC: {    /* log(1 + exp(-a u)), written without overflow */
+        double t = -a * u;
+        return pos(t) + log1p(exp(-fabs(t)));
+    }
+    case OR_HINGE:         /* (1 - a u)_+ */
+        return pos(1.0 - a * u);
+    case OR_ORDINAL: {     /* eq. ord-pca: one hinge per level below and above a */
+        double s = 0.0;
+        for (int lv = 1; lv <= L->levels; ++lv) {
+            if ((double)lv < a) s += pos(1.0 - u + (double)lv);
+            else if ((double)lv > a) s += pos(1.0 + u - (double)lv);
+        }
+        return s;
+    }
+    }
+    return NAN;
+}
+
+/* ---- losses, derivative in u (a subgradient at kinks, Section 7.2 gradient
+ * method: any subgradient may be used; the strict-inequality branch is taken,
+ * so a kink contributes 0) --------------------------------------------------- */
+double oracle_dloss(const oracle_loss_t *L, double u, double a)
+{
+    switch (L->kind) {
+    case OR_QUAD:
+        return 2.0 * (u - a);
+    case OR_HUBER: {
+        double r = u - a, d = L->param;
+        return r > d ? d : (r < -d ? -d : r);
+    }
+    case OR_LOGISTIC:      /* d/du log(1+exp(-au)) = -a / (1 + exp(a u)) */
+        return -a / (1.0 + exp(a * u));
+    case OR_HINGE:
+        return (a * u < 1.0) ? -a : 0.0;
+    case OR_ORDINAL: {
+        double g = 0.0;
+        for (int lv = 1; lv <= L->levels; ++lv) {
+            if ((double)lv < a) { if (1.0 - u + (double)lv > 0.0) g -= 1.0; }
+            else if ((double)lv > a) { if (1.0 + u - (double)lv > 0.0) g += 1.0; }
+        }
+        return g;
+    }
+    }
+    return NAN;
+}
+
+/* ---- regularizers (Section 3) and their proximal operators (Section 7.2,
+ * prox_f(z) = argmin_x f(x) + 1/2 ||x - z||^2) ------------------------------ */
+double oracle_reg(int32_t kind, double w, const double *x, int32_t k)
+{
+    double s = 0.0;
+    switch (kind) {
+    case OR_RZERO: return 0.0;
+    case OR_RQUAD: for (int c = 0; c < k; ++c) s += x[c] * x[c]; return w * s;
+    case OR_RL1:   for (int c = 0; c < k; ++c) s += fabs(x[c]); return w * s;
+    case OR_RNONNEG:
+        for (int c = 0; c < k; ++c) if (x[c] < 0.0) return INFINITY;
+        return 0.0;
+    }
+    return NAN;
+}
+
+void oracle_prox(int32_t kind, double w, double alpha, double *v, int32_t k)
+{
+    for (int c = 0; c < k; ++c) {
+        switch (kind) {
+        case OR_RZERO: break;
+        case OR_RQUAD: v[c] = v[c] / (1.0 + 2.0 * alpha * w); break;
+        case OR_RL1: {
+            double t = fabs(v[c]) - alpha * w;
+            v[c] = t > 0.0 ? (v[c] > 0.0 ? t : -t) : 0.0;
+            break;
+        }
+        case OR_RNONNEG: v[c] = v[c] > 0.0 ? v[c] : 0.0; break;
+        }
+    }
+}
+
+static double dot(const double *a, const double *b, int32_t k)
+{
+    double s = 0.0;
+    for (int c = 0; c < k; ++c) s += a[c] * b[c];
+    return s;
+}
+
+/* Loss part of one row's objective: sum over the row's observed entries. */
+static double row_loss(const oracle_problem_t *P, int64_t i, const double *u, const double *V)
+{
+    double f = 0.0;
+    for (int64_t e = P->row_ptr[i]; e < P->row_ptr[i + 1]; ++e)
+        f += oracle_loss(&P->losses[P->ecode[e]], dot(u, V + (int64_t)P->col[e] * P->k, P->k), P->val[e]);
+    return f;
+}
+
+/* Sum of the loss over all observed entries (the first term of eq. gpca). */
+double oracle_loss_sum(const oracle_problem_t *P, const double *U, const double *V)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < P->m; ++i) s += row_loss(P, i, U + i * P->k, V);
+    return s;
+}
+
+/* Gradient of the loss sum with respect to the rows of U:
+ * dU_i = sum_j dL(u_i . v_j, A_ij) v_j.  Calling it on the transposed problem
+ * with the factors swapped gives the gradient with respect to Y. */
+void oracle_loss_grad_rows(const oracle_problem_t *P, const double *U, const double *V, double *dU)
+{
+    const int32_t k = P->k;
+    for (int64_t i = 0; i < P->m; ++i) {
+        double *g = dU + i * k;
+        for (int c = 0; c < k; ++c) g[c] = 0.0;
+        for (int64_t e = P->row_ptr[i]; e < P->row_ptr[i + 1]; ++e) {
+            const double *v = V + (int64_t)P->col[e] * k;
+            double d = oracle_dloss(&P->losses[P->ecode[e]], dot(U + i * k, v, k), P->val[e]);
+            for (int c = 0; c < k; ++c) g[c] += d * v[c];
+        }
+    }
+}
+
+/*
+ * One half-step of Algorithm 2 with the proximal gradient update and the
+ * per-row step-size rule of Section 7.2 ("Choosing a step size"):
+ *   f    = sum_j L(u_i . v_j, A_ij) + r(u_i)
+ *   g    = sum_j dL(u_i . v_j, A_ij) v_j
+ *   u+   = prox_{alpha_i r}(u_i - alpha_i g)
+ *   f+   = sum_j L(u+ . v_j, A_ij) + r(u+)
+ *   f+ <= f : keep u+ and multiply alpha_i by step_up
+ *   else    : keep u_i and multiply alpha_i by step_down
+ * Rows are independent.  Returns the number of rejected rows.  f_old / f_new
+ * (length m) receive f and f+ when not NULL; accepted receives the decision.
+ */
+int64_t oracle_half_step(const oracle_problem_t *P, double *U, const double *V, double *alpha,
+                         int32_t reg_kind, double reg_w, double step_up, double step_down,
+                         double *f_old, double *f_new, uint8_t *accepted, double *scratch_2k)
+{
+    const int32_t k = P->k;
+    double *g = scratch_2k, *up = scratch_2k + k;
+    int64_t rejected = 0;
+    for (int64_t i = 0; i < P->m; ++i) {
+        double *u = U + i * k;
+        double f = row_loss(P, i, u, V) + oracle_reg(reg_kind, reg_w, u, k);
+        for (int c = 0; c < k; ++c) g[c] = 0.0;
+        for (int64_t e = P->row_ptr[i]; e < P->row_ptr[i + 1]; ++e) {
+            const double *v = V + (int64_t)P->col[e] * k;
+            double d = oracle_dloss(&P->losses[P->ecode[e]], dot(u, v, k), P->val[e]);
+            for (int c = 0; c < k; ++c) g[c] += d * v[c];
+        }
+        for (int c = 0; c < k; ++c) up[c] = u[c] - alpha[i] * g[c];
+        oracle_prox(reg_kind, reg_w, alpha[i], up, k);
+        double fp = row_loss(P, i, up, V) + oracle_reg(reg_kind, reg_w, up, k);
+        int acc = (fp <= f);
+        if (acc) {
+            for (int c = 0; c < k; ++c) u[c] = up[c];
+            alpha[i] *= step_up;
+        } else {
+            alpha[i] *= step_down;
+            ++rejected;
+        }
+        if (f_old) f_old[i] = f;
+        if (f_new) f_new[i] = fp;
+        if (accepted) accepted[i] = (uint8_t)acc;
+    }
+    return rejected;
+}
+
+/* Initial step sizes (Section 7.2): alpha_i = s / n_i, n_i the number of
+ * observations in row i; an empty row takes s. */
+void oracle_init_alpha(const oracle_problem_t *P, double s, double *alpha)
+{
+    for (int64_t i = 0; i < P->m; ++i) {
+        int64_t ni = P->row_ptr[i + 1] - P->row_ptr[i];
+        alpha[i] = s / (double)(ni > 0 ? ni : 1);
+    }
+}
+
+/* Sum of r over the rows of U (the regularizer terms of eq. gpca). */
+double oracle_reg_sum(int32_t kind, double w, const double *U, int64_t rows, int32_t k)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < rows; ++i) s += oracle_reg(kind, w, U + i * k, k);
+    return s;
+}
+
+/* The full objective of eq. gpca: loss over the observed entries plus both
+ * regularizer sums.  P is the row view (U = X, V = Y). */
+double oracle_objective(const oracle_problem_t *P, const double *X, const double *Y,
+                        int32_t rx_kind, double rx_w, int32_t ry_kind, double ry_w)
+{
+    return oracle_loss_sum(P, X, Y) + oracle_reg_sum(rx_kind, rx_w, X, P->m, P->k)
+         + oracle_reg_sum(ry_kind, ry_w, Y, P->n, P->k);
+}

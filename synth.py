@@ -1,0 +1,253 @@
+"""Seeded synthetic GLRM inputs shaped like the paper's workloads.
+
+This module only draws data: tables, observation patterns, loss tables,
+regularizers and starting points.  It holds none of the fitting arithmetic and
+is the one thing the HIP path and the oracle share.
+
+Random streams: ``numpy.random.default_rng([14100342, config, stream])`` with
+stream 0 = hidden factors, 1 = noise / outliers / flips, 2 = observation
+pattern, 3 = starting point, 4 = sampled coordinates.
+
+Loss kinds: 0 quadratic, 1 Huber, 2 logistic, 3 hinge, 4 ordinal hinge.
+Regularizer kinds: 0 zero, 1 quadratic, 2 l1, 3 nonnegative.
+"""
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+SEED = 14100342
+
+QUAD, HUBER, LOGISTIC, HINGE, ORDINAL = 0, 1, 2, 3, 4
+RZERO, RQUAD, RL1, RNONNEG = 0, 1, 2, 3
+
+
+def rng(config: int, stream: int, extra: int = 0) -> np.random.Generator:
+    return np.random.default_rng([SEED, int(config), int(stream), int(extra)])
+
+
+@dataclass
+class Case:
+    name: str
+    m: int
+    n: int
+    k: int
+    layout: str                          # "dense" or "coo"
+    col_loss: np.ndarray                 # uint8 [n], index into losses
+    losses: List[Tuple[int, int, float]]  # (kind, levels, param)
+    rx: Tuple[int, float]
+    ry: Tuple[int, float]
+    X0: np.ndarray                       # float32 [m, k]
+    Y0: np.ndarray                       # float32 [n, k]
+    A: Optional[np.ndarray] = None       # dense float32 [m, n]
+    mask: Optional[np.ndarray] = None    # dense uint8 [m, n], None = all observed
+    rows: Optional[np.ndarray] = None    # coo int32, row-sorted, unique
+    cols: Optional[np.ndarray] = None
+    vals: Optional[np.ndarray] = None    # coo float32
+    sweeps: int = 0
+    notes: dict = field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        if self.layout == "coo":
+            return int(self.rows.size)
+        return self.m * self.n if self.mask is None else int(np.count_nonzero(self.mask))
+
+
+def _normal32(g, shape, scale=1.0):
+    return (g.standard_normal(shape, dtype=np.float32) * np.float32(scale)).astype(np.float32)
+
+
+def _bernoulli_mask(g, m, n, p_obs):
+    out = np.empty((m, n), dtype=np.uint8)
+    step = max(1, (1 << 24) // max(n, 1))
+    for r0 in range(0, m, step):
+        r1 = min(m, r0 + step)
+        out[r0:r1] = g.random((r1 - r0, n), dtype=np.float32) < np.float32(p_obs)
+    return out
+
+
+def _lowrank_plus_noise(g_f, g_n, m, n, r, noise, chunk_rows=1 << 14):
+    U = g_f.standard_normal((m, r)).astype(np.float32)
+    V = g_f.standard_normal((r, n)).astype(np.float32)
+    A = np.empty((m, n), dtype=np.float32)
+    for r0 in range(0, m, chunk_rows):
+        r1 = min(m, r0 + chunk_rows)
+        A[r0:r1] = U[r0:r1] @ V + _normal32(g_n, (r1 - r0, n), noise)
+    return A
+
+
+# ---- the five workload shapes ------------------------------------------------
+
+def plain_pca(m=200, n=50, k=5, sweeps=500, config=1):
+    """Quadratic loss, no regularizer, fully observed, A = U V + 0.1 N."""
+    A = _lowrank_plus_noise(rng(config, 0), rng(config, 1), m, n, k, 0.1)
+    g = rng(config, 3)
+    return Case("plain_pca_%dx%d_k%d" % (m, n, k), m, n, k, "dense",
+                np.zeros(n, np.uint8), [(QUAD, 0, 0.0)], (RZERO, 0.0), (RZERO, 0.0),
+                _normal32(g, (m, k)), _normal32(g, (n, k)), A=A, mask=None, sweeps=sweeps)
+
+
+def dense_quadratic(m=100_000, n=1_000, k=20, missing=0.2, gamma=0.1, sweeps=200, config=2):
+    """Rank-k Gaussian product + 0.1 N noise, entries missing at random."""
+    A = _lowrank_plus_noise(rng(config, 0), rng(config, 1), m, n, k, 0.1)
+    mask = _bernoulli_mask(rng(config, 2), m, n, 1.0 - missing)
+    g = rng(config, 3)
+    return Case("dense_quadratic_%dx%d_k%d" % (m, n, k), m, n, k, "dense",
+                np.zeros(n, np.uint8), [(QUAD, 0, 0.0)], (RQUAD, gamma), (RQUAD, gamma),
+                _normal32(g, (m, k)), _normal32(g, (n, k)), A=A, mask=mask, sweeps=sweeps)
+
+
+def heterogeneous(m=1_000_000, n=200, k=10, missing=0.3, sweeps=200, config=3,
+                  n_real=None, n_bool=None, levels=7):
+    """Mixed table from a hidden rank-k model: Huber real columns with Laplace
+    outliers, logistic Boolean columns with flips, ordinal-hinge columns made by
+    cutting each standardized latent column into equal-width bins."""
+    n_real = n // 2 if n_real is None else n_real
+    n_bool = (3 * n) // 10 if n_bool is None else n_bool
+    n_ord = n - n_real - n_bool
+    gf, gn = rng(config, 0), rng(config, 1)
+    Xt = gf.standard_normal((m, k)).astype(np.float32)
+    Yt = gf.standard_normal((k, n)).astype(np.float32)
+    A = np.empty((m, n), dtype=np.float32)
+    chunk = max(1, (1 << 22) // n)
+    # per-column spread of the latent, from a fixed sample of rows (data generation only)
+    lat_std = (Xt[: min(m, 65536)] @ Yt).std(axis=0).astype(np.float32) + np.float32(1e-12)
+    edges = np.linspace(-3.0, 3.0, levels + 1)[1:-1].astype(np.float32)
+    for r0 in range(0, m, chunk):
+        r1 = min(m, r0 + chunk)
+        L = Xt[r0:r1] @ Yt
+        rr = r1 - r0
+        out = gn.random((rr, n_real), dtype=np.float32) < 0.05
+        lap = gn.laplace(0.0, 10.0, (rr, n_real)).astype(np.float32)
+        A[r0:r1, :n_real] = L[:, :n_real] + np.where(out, lap, 0).astype(np.float32)
+        b = np.where(L[:, n_real:n_real + n_bool] >= 0, 1.0, -1.0).astype(np.float32)
+        flip = gn.random((rr, n_bool), dtype=np.float32) < 0.05
+        A[r0:r1, n_real:n_real + n_bool] = np.where(flip, -b, b)
+        zs = L[:, n_real + n_bool:] / lat_std[n_real + n_bool:]
+        A[r0:r1, n_real + n_bool:] = (np.searchsorted(edges, zs.ravel(), side="right").reshape(zs.shape) + 1).astype(np.float32)
+    mask = _bernoulli_mask(rng(config, 2), m, n, 1.0 - missing)
+    col_loss = np.zeros(n, np.uint8)
+    col_loss[n_real:n_real + n_bool] = 1
+    col_loss[n_real + n_bool:] = 2
+    losses = [(HUBER, 0, 1.0), (LOGISTIC, 0, 0.0), (ORDINAL, levels, 0.0)]
+    g = rng(config, 3)
+    X0 = np.abs(_normal32(g, (m, k)))
+    return Case("heterogeneous_%dx%d_k%d" % (m, n, k), m, n, k, "dense", col_loss, losses,
+                (RNONNEG, 0.0), (RQUAD, 0.1), X0, _normal32(g, (n, k)), A=A, mask=mask, sweeps=sweeps)
+
+
+def autograd_point(m=50_000, n=2_000, k=64, missing=0.1, config=4):
+    """Logistic +-1 columns (a = +1 with probability sigmoid(latent)) next to
+    quadratic columns (latent + N(0,1)); the evaluation point has entries of
+    variance k^-1/2 so that x_i . y_j is of order one."""
+    gf, gn = rng(config, 0), rng(config, 1)
+    s = float(k) ** -0.25
+    Xt = _normal32(gf, (m, k), s)
+    Yt = _normal32(gf, (k, n), s)
+    nl = n // 2
+    A = np.empty((m, n), dtype=np.float32)
+    chunk = max(1, (1 << 22) // n)
+    for r0 in range(0, m, chunk):
+        r1 = min(m, r0 + chunk)
+        L = Xt[r0:r1] @ Yt
+        p = 1.0 / (1.0 + np.exp(-L[:, :nl].astype(np.float64)))
+        A[r0:r1, :nl] = np.where(gn.random(p.shape) < p, 1.0, -1.0)
+        A[r0:r1, nl:] = L[:, nl:] + _normal32(gn, (r1 - r0, n - nl))
+    mask = _bernoulli_mask(rng(config, 2), m, n, 1.0 - missing)
+    col_loss = np.zeros(n, np.uint8)
+    col_loss[:nl] = 1
+    g = rng(config, 3)
+    return Case("autograd_%dx%d_k%d" % (m, n, k), m, n, k, "dense", col_loss,
+                [(QUAD, 0, 0.0), (LOGISTIC, 0, 0.0)], (RZERO, 0.0), (RZERO, 0.0),
+                _normal32(g, (m, k), s), _normal32(g, (n, k), s), A=A, mask=mask)
+
+
+def sparse_completion(m=2_000_000, n=20_000, k=32, density=0.01, noise=0.05, gamma=1.0,
+                      sweeps=50, config=5):
+    """Each row observes each column independently with probability ``density``
+    (drawn as geometric gaps), values from a rank-k Gaussian model plus noise;
+    COO sorted by row then column, int32 indices."""
+    gf, gn, gp = rng(config, 0), rng(config, 1), rng(config, 2)
+    Xt = gf.standard_normal((m, k)).astype(np.float32)
+    Yt = gf.standard_normal((n, k)).astype(np.float32)
+    rows_l, cols_l, vals_l = [], [], []
+    chunk = max(1, (1 << 24) // max(1, int(n * density * 3) + 8))
+    for r0 in range(0, m, chunk):
+        r1 = min(m, r0 + chunk)
+        rr = r1 - r0
+        # geometric gaps give an exact Bernoulli(density) pattern per row
+        per = int(n * density * 2 + 64)
+        gaps = gp.geometric(density, size=(rr, per)).astype(np.int64)
+        pos = np.cumsum(gaps, axis=1) - 1
+        while True:
+            short = pos[:, -1] < n
+            if not short.any():
+                break
+            extra = gp.geometric(density, size=(rr, per)).astype(np.int64)
+            pos = np.concatenate([pos, pos[:, -1:] + np.cumsum(extra, axis=1)], axis=1)
+        keep = pos < n
+        rr_idx = np.repeat(np.arange(r0, r1, dtype=np.int64), keep.sum(axis=1))
+        cc = pos[keep]
+        v = np.einsum("ij,ij->i", Xt[rr_idx], Yt[cc]).astype(np.float32) + _normal32(gn, cc.size, noise)
+        rows_l.append(rr_idx.astype(np.int32))
+        cols_l.append(cc.astype(np.int32))
+        vals_l.append(v)
+    rows = np.concatenate(rows_l)
+    cols = np.concatenate(cols_l)
+    vals = np.concatenate(vals_l)
+    g = rng(config, 3)
+    return Case("sparse_completion_%dx%d_k%d" % (m, n, k), m, n, k, "coo",
+                np.zeros(n, np.uint8), [(QUAD, 0, 0.0)], (RQUAD, gamma), (RQUAD, gamma),
+                _normal32(g, (m, k)), _normal32(g, (n, k)), rows=rows, cols=cols, vals=vals,
+                sweeps=sweeps)
+
+
+# ---- small mixed cases for tests -----------------------------------------------
+
+def small_mixed(m, n, k, seed, missing=0.25, layout="dense", rx=(RQUAD, 0.1), ry=(RQUAD, 0.1),
+                kinds=(QUAD, HUBER, LOGISTIC, HINGE, ORDINAL), levels=5, x_nonneg=False, empty_row=None,
+                empty_col=None):
+    """A table that mixes every requested loss kind column by column, with a
+    hidden rank-k model under it.  Optional fully unobserved row / column."""
+    gf, gn, gp, g0 = rng(100, 0, seed), rng(100, 1, seed), rng(100, 2, seed), rng(100, 3, seed)
+    L = gf.standard_normal((m, k)) @ gf.standard_normal((k, n)) / np.sqrt(k)
+    col_loss = np.array([i % len(kinds) for i in range(n)], dtype=np.uint8)
+    losses = []
+    for kd in kinds:
+        losses.append((kd, levels if kd == ORDINAL else 0, 1.0 if kd == HUBER else 0.0))
+    A = np.empty((m, n), dtype=np.float32)
+    for j in range(n):
+        kd = kinds[col_loss[j]]
+        lj = L[:, j]
+        if kd in (QUAD, HUBER):
+            A[:, j] = lj + 0.1 * gn.standard_normal(m)
+        elif kd in (LOGISTIC, HINGE):
+            A[:, j] = np.where(lj + 0.3 * gn.standard_normal(m) >= 0, 1.0, -1.0)
+        else:
+            A[:, j] = np.clip(np.round(lj + (levels + 1) / 2.0), 1, levels)
+    mask = (gp.random((m, n)) >= missing).astype(np.uint8)
+    if empty_row is not None:
+        mask[empty_row, :] = 0
+    if empty_col is not None:
+        mask[:, empty_col] = 0
+    X0 = (g0.standard_normal((m, k)) / np.sqrt(k) ** 0.5).astype(np.float32)
+    Y0 = (g0.standard_normal((n, k)) / np.sqrt(k) ** 0.5).astype(np.float32)
+    if x_nonneg:
+        X0 = np.abs(X0)
+    c = Case("small_%s_%dx%d_k%d_s%d" % (layout, m, n, k, seed), m, n, k, "dense", col_loss, losses,
+             tuple(rx), tuple(ry), X0, Y0, A=A, mask=mask)
+    if layout == "coo":
+        r, cidx = np.nonzero(mask)
+        c.layout, c.rows, c.cols = "coo", r.astype(np.int32), cidx.astype(np.int32)
+        c.vals = A[r, cidx].astype(np.float32)
+        c.A = None
+        c.mask = None
+    return c
+
+
+def sample_indices(config, count, upper, stream_extra=0):
+    """Seeded sample of distinct indices in [0, upper)."""
+    g = rng(config, 4, stream_extra)
+    count = min(int(count), int(upper))
+    return np.sort(g.choice(upper, size=count, replace=False))

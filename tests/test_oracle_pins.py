@@ -1,0 +1,329 @@
+"""Pins for the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it follows.  None of them re-types the oracle's
+formulas: values come from hand-worked fixtures, closed forms, library
+routines (SVD, norms, scalar minimisation) and invariants.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize_scalar
+
+import oracle
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load_losses():
+    rows = []
+    for line in open(os.path.join(GOLD, "losses.txt")):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        kind, levels, param, u, a, val, der = line.split()
+        rows.append((int(kind), int(levels), float(param), float(u), float(a), float(val), float(der)))
+    return rows
+
+
+@pytest.mark.parametrize("row", _load_losses())
+def test_loss_hand_values(row):
+    """Hand-worked values of each loss (Sections 2.2, 4.2, 5.1, eq. ord-pca)."""
+    kind, levels, param, u, a, val, der = row
+    assert oracle.loss(kind, u, a, levels, param) == pytest.approx(val, rel=1e-14, abs=1e-14)
+    assert oracle.dloss(kind, u, a, levels, param) == pytest.approx(der, rel=1e-14, abs=1e-14)
+
+
+SMOOTH = [(0, 0, 0.0), (1, 0, 1.0), (1, 0, 0.3), (2, 0, 0.0)]
+KINKED = [(3, 0, 0.0), (4, 5, 0.0), (4, 7, 0.0)]
+
+
+@pytest.mark.parametrize("loss", SMOOTH + KINKED)
+def test_loss_derivative_matches_central_difference(loss):
+    """dL/du against FP64 central differences away from kinks (Section 7.2
+    uses the gradient of each loss)."""
+    kind, levels, param = loss
+    g = np.random.default_rng(7)
+    h = 1e-6
+    checked = 0
+    for _ in range(400):
+        if kind in (2, 3):
+            a = float(g.choice([-1.0, 1.0]))
+        elif kind == 4:
+            a = float(g.integers(1, levels + 1))
+        else:
+            a = float(g.normal() * 3)
+        u = float(g.normal() * 4)
+        # stay off kinks: hinge at a*u = 1, ordinal at integers +- 1, Huber at |u-a| = param
+        if kind == 3 and abs(a * u - 1.0) < 1e-3:
+            continue
+        if kind == 4 and abs(u - round(u)) < 1e-3:
+            continue
+        fd = (oracle.loss(kind, u + h, a, levels, param) - oracle.loss(kind, u - h, a, levels, param)) / (2 * h)
+        assert oracle.dloss(kind, u, a, levels, param) == pytest.approx(fd, rel=1e-6, abs=1e-6)
+        checked += 1
+    assert checked > 300
+
+
+@pytest.mark.parametrize("loss", KINKED + [(1, 0, 1.0)])
+def test_subgradient_inequality_at_kinks(loss):
+    """At a kink the chosen value must still be a subgradient (Section 7.2):
+    L(u + t) >= L(u) + g t for t of both signs."""
+    kind, levels, param = loss
+    if kind == 3:
+        pts = [(1.0, 1.0), (-1.0, -1.0)]
+    elif kind == 1:
+        pts = [(2.0 + param, 2.0), (2.0 - param, 2.0)]
+    else:
+        pts = [(float(u), float(a)) for a in range(1, levels + 1) for u in range(0, levels + 2)]
+    for u, a in pts:
+        g = oracle.dloss(kind, u, a, levels, param)
+        for t in (1e-3, -1e-3, 0.5, -0.5, 2.0, -2.0):
+            assert oracle.loss(kind, u + t, a, levels, param) >= oracle.loss(kind, u, a, levels, param) + g * t - 1e-12
+
+
+def test_ordinal_hinge_is_zero_at_its_level_and_grows_one_per_level():
+    """eq. ord-pca: zero at u = a, and one unit per level of error beyond the
+    neighbouring level."""
+    d = 7
+    for a in range(1, d + 1):
+        assert oracle.loss(4, float(a), float(a), d) == 0.0
+        for s in range(1, d - a + 1):  # u = a + s: hinges a' = a+1 .. a+s contribute s, s-1, ..., 1
+            assert oracle.loss(4, float(a + s), float(a), d) == pytest.approx(s * (s + 1) / 2)
+
+
+@pytest.mark.parametrize("kind,w", [(0, 0.0), (1, 0.3), (1, 2.0), (2, 0.4), (2, 1.5), (3, 0.0)])
+def test_prox_is_the_minimiser_of_its_definition(kind, w):
+    """prox_{alpha r}(v) = argmin_x alpha r(x) + 1/2 ||x - v||^2 (Section 7.2),
+    checked against bounded scalar minimisation coordinate by coordinate."""
+    g = np.random.default_rng(11 + kind)
+    for _ in range(40):
+        v = g.normal(size=4) * 3
+        alpha = float(g.uniform(0.05, 2.0))
+        p = oracle.prox(kind, w, alpha, v)
+        for c in range(v.size):
+            def obj(x):
+                return alpha * oracle.reg(kind, w, [x]) + 0.5 * (x - v[c]) ** 2
+            lo, hi = (0.0, abs(v[c]) + 10) if kind == 3 else (-abs(v[c]) - 10, abs(v[c]) + 10)
+            r = minimize_scalar(obj, bounds=(lo, hi), method="bounded", options={"xatol": 1e-12})
+            assert p[c] == pytest.approx(r.x, abs=1e-7)
+            assert obj(p[c]) <= obj(r.x) + 1e-12
+
+
+def test_regularizer_values():
+    """Section 3: quadratic w||x||^2, l1 w||x||_1, nonnegative indicator."""
+    x = np.array([1.0, -2.0, 0.5])
+    assert oracle.reg(0, 3.0, x) == 0.0
+    assert oracle.reg(1, 0.5, x) == pytest.approx(0.5 * np.linalg.norm(x) ** 2)
+    assert oracle.reg(2, 0.5, x) == pytest.approx(0.5 * np.linalg.norm(x, 1))
+    assert oracle.reg(3, 0.0, x) == np.inf
+    assert oracle.reg(3, 0.0, np.abs(x)) == 0.0
+
+
+def _problem(case):
+    if case.layout == "coo":
+        return oracle.Problem.from_coo(case.m, case.n, case.k, case.rows, case.cols, case.vals,
+                                       case.col_loss, case.losses, case.rx, case.ry)
+    return oracle.Problem.from_dense(case.A, case.mask, case.k, case.col_loss, case.losses, case.rx, case.ry)
+
+
+def test_objective_reduces_to_frobenius_norm():
+    """With quadratic loss, full Omega and gamma the objective is eq. qpca:
+    ||A - XY||_F^2 + gamma ||X||_F^2 + gamma ||Y||_F^2 (library norms)."""
+    c = synth.plain_pca(m=40, n=30, k=4)
+    for gam in (0.0, 0.7):
+        P = oracle.Problem.from_dense(c.A, None, c.k, c.col_loss, c.losses, (1, gam), (1, gam))
+        X, Y = c.X0.astype(np.float64), c.Y0.astype(np.float64)
+        ref = (np.linalg.norm(c.A.astype(np.float64) - X @ Y.T) ** 2
+               + gam * np.linalg.norm(X) ** 2 + gam * np.linalg.norm(Y) ** 2)
+        assert P.objective(X, Y) == pytest.approx(ref, rel=1e-13)
+
+
+def test_objective_masked_matches_masked_norm():
+    """Section 2.4 (matrix completion): only observed entries enter."""
+    c = synth.dense_quadratic(m=50, n=40, k=3)
+    P = _problem(c)
+    X, Y = c.X0.astype(np.float64), c.Y0.astype(np.float64)
+    R = (c.A.astype(np.float64) - X @ Y.T) * c.mask
+    ref = np.linalg.norm(R) ** 2 + 0.1 * (np.linalg.norm(X) ** 2 + np.linalg.norm(Y) ** 2)
+    assert P.objective(X, Y) == pytest.approx(ref, rel=1e-13)
+
+
+def test_objective_invariant_under_orthogonal_change_of_basis():
+    """(XT, T^T Y) gives the same product and, for quadratic or zero
+    regularizers, the same objective (Section 2.3)."""
+    c = synth.small_mixed(23, 17, 4, seed=3, rx=(1, 0.2), ry=(1, 0.3))
+    P = _problem(c)
+    X, Y = c.X0.astype(np.float64), c.Y0.astype(np.float64)
+    Q, _ = np.linalg.qr(np.random.default_rng(1).normal(size=(4, 4)))
+    assert P.objective(X @ Q, Y @ Q) == pytest.approx(P.objective(X, Y), rel=1e-12)
+
+
+def test_objective_invariant_under_rescaling_without_regularizer():
+    c = synth.small_mixed(23, 17, 3, seed=4, rx=(0, 0.0), ry=(0, 0.0))
+    P = _problem(c)
+    X, Y = c.X0.astype(np.float64), c.Y0.astype(np.float64)
+    assert P.objective(2.5 * X, Y / 2.5) == pytest.approx(P.objective(X, Y), rel=1e-12)
+
+
+def test_objective_equivariant_under_row_and_column_permutation():
+    c = synth.small_mixed(19, 13, 3, seed=5)
+    P = _problem(c)
+    g = np.random.default_rng(2)
+    pr, pc = g.permutation(c.m), g.permutation(c.n)
+    P2 = oracle.Problem.from_dense(c.A[pr][:, pc], c.mask[pr][:, pc], c.k, c.col_loss[pc], c.losses, c.rx, c.ry)
+    X, Y = c.X0.astype(np.float64), c.Y0.astype(np.float64)
+    assert P2.objective(X[pr], Y[pc]) == pytest.approx(P.objective(X, Y), rel=1e-12)
+
+
+@pytest.mark.parametrize("seed,kinds", [(1, (0, 1, 2)), (2, (0, 2)), (3, (1,))])
+def test_gradient_matches_central_difference(seed, kinds):
+    """Loss gradient (Section 7.2: g = sum_j dL(x_i y_j, A_ij) y_j) against FP64
+    central differences of the loss sum, for smooth losses."""
+    c = synth.small_mixed(9, 7, 3, seed=seed, kinds=kinds)
+    P = _problem(c)
+    X, Y = c.X0.astype(np.float64), c.Y0.astype(np.float64)
+    dX, dY = P.grad(X, Y)
+    h = 1e-6
+    for M, D in ((X, dX), (Y, dY)):
+        for idx in np.ndindex(M.shape):
+            old = M[idx]
+            M[idx] = old + h
+            fp = P.loss_sum(X, Y)
+            M[idx] = old - h
+            fm = P.loss_sum(X, Y)
+            M[idx] = old
+            assert D[idx] == pytest.approx((fp - fm) / (2 * h), rel=1e-6, abs=1e-7)
+
+
+def test_hand_worked_sweeps():
+    """Sweeps worked by hand from Algorithm 2 and the step rule of Section 7.2."""
+    d = json.load(open(os.path.join(GOLD, "sweeps.json")))
+    for case in d["cases"]:
+        A = np.array(case["A"], dtype=np.float64)
+        mask = None if case["mask"] is None else np.array(case["mask"], dtype=np.uint8)
+        P = oracle.Problem.from_dense(A, mask, case["k"], np.array(case["col_loss"]), case["losses"],
+                                      case["rx"], case["ry"])
+        X = np.array(case["X0"], dtype=np.float64)
+        Y = np.array(case["Y0"], dtype=np.float64)
+        ax, ay = P.init_alpha(1.0)
+        for t, exp in enumerate(case["sweeps"]):
+            diag = P.sweep(X, Y, ax, ay)
+            tag = "%s sweep %d" % (case["name"], t + 1)
+            np.testing.assert_allclose(X, exp["X"], rtol=1e-12, atol=1e-12, err_msg=tag)
+            np.testing.assert_allclose(Y, exp["Y"], rtol=1e-12, atol=1e-12, err_msg=tag)
+            np.testing.assert_allclose(ax, exp["ax"], rtol=1e-12, err_msg=tag)
+            np.testing.assert_allclose(ay, exp["ay"], rtol=1e-12, err_msg=tag)
+            assert P.objective(X, Y) == pytest.approx(exp["F"], rel=1e-12), tag
+            assert diag["rows_rejected"] == exp["rows_rejected"], tag
+            assert diag["cols_rejected"] == exp["cols_rejected"], tag
+
+
+def test_eckart_young_plain_pca():
+    """Quadratic loss, no regularizer, full Omega, rank 5 on the 200 x 50
+    table (Section 2.3): the fit reaches the truncated SVD, so the objective
+    equals the sum of the trailing 45 squared singular values."""
+    c = synth.plain_pca()
+    P = _problem(c)
+    X, Y, ax, ay, hist, _ = P.fit(c.X0, c.Y0, c.sweeps)
+    s = np.linalg.svd(c.A.astype(np.float64), compute_uv=False)
+    target = float(np.sum(s[c.k:] ** 2))
+    assert hist[-1] == pytest.approx(target, rel=1e-8)
+    assert np.all(np.diff(hist) <= 1e-12 * hist[:-1])
+
+
+def test_quadratically_regularized_pca_closed_form():
+    """eq. qpca with gamma > 0 and full Omega: soft-thresholded truncated SVD
+    (Section 2.3 and Appendix A).  Optimal value sum_{i>k} s_i^2 +
+    sum_{i<=k} (2 gamma s_i - gamma^2 if s_i >= gamma else s_i^2); Appendix A
+    shows there are no other local minima."""
+    c = synth.plain_pca(m=60, n=40, k=4, config=11)
+    s = np.linalg.svd(c.A.astype(np.float64), compute_uv=False)
+    gam = float(0.5 * (s[2] + s[3]))  # makes the 4th component inactive
+    P = oracle.Problem.from_dense(c.A, None, c.k, c.col_loss, c.losses, (1, gam), (1, gam))
+    X, Y, ax, ay, hist, _ = P.fit(c.X0, c.Y0, 3000)
+    top = s[: c.k]
+    target = float(np.sum(s[c.k:] ** 2) + np.sum(np.where(top >= gam, 2 * gam * top - gam ** 2, top ** 2)))
+    assert hist[-1] == pytest.approx(target, rel=1e-8)
+    # stationary points balance the factors: X^T X = Y Y^T (Appendix A)
+    np.testing.assert_allclose(X.T @ X, Y.T @ Y, atol=1e-4 * np.abs(X.T @ X).max())
+
+
+def test_objective_never_increases():
+    """The step rule keeps every row and column objective from increasing
+    (Section 7.2), so F is non-increasing after each half-step."""
+    c = synth.small_mixed(40, 30, 3, seed=9, rx=(1, 0.1), ry=(2, 0.05))
+    P = _problem(c)
+    X, Y = c.X0.astype(np.float64).copy(), c.Y0.astype(np.float64).copy()
+    ax, ay = P.init_alpha(4.0)  # large start: forces rejections
+    F = P.objective(X, Y)
+    rejected = 0
+    for _ in range(60):
+        r, *_ = P.half_step_x(X, Y, ax)
+        F1 = P.objective(X, Y)
+        assert F1 <= F * (1 + 1e-13) + 1e-13
+        r2, *_ = P.half_step_y(X, Y, ay)
+        F2 = P.objective(X, Y)
+        assert F2 <= F1 * (1 + 1e-13) + 1e-13
+        F = F2
+        rejected += r + r2
+    assert rejected > 0
+
+
+def test_step_sizes_move_by_exact_factors_and_rejected_rows_stay():
+    c = synth.small_mixed(30, 20, 3, seed=10)
+    P = _problem(c)
+    X, Y = c.X0.astype(np.float64).copy(), c.Y0.astype(np.float64).copy()
+    ax, ay = P.init_alpha(3.0)
+    for _ in range(5):
+        X_old, ax_old = X.copy(), ax.copy()
+        r, fo, fn, acc = P.half_step_x(X, Y, ax)
+        acc = acc.astype(bool)
+        assert np.all(ax[acc] == ax_old[acc] * 1.05)
+        assert np.all(ax[~acc] == ax_old[~acc] * 0.7)
+        assert np.array_equal(X[~acc], X_old[~acc])
+        assert np.array_equal(acc, fn <= fo)
+        P.half_step_y(X, Y, ay)
+
+
+def test_initial_step_is_inverse_count():
+    """alpha_i^0 = 1/n_i (Section 7.2), empty rows take the scale itself."""
+    c = synth.small_mixed(12, 9, 2, seed=12, empty_row=3, empty_col=4)
+    P = _problem(c)
+    ax, ay = P.init_alpha(1.0)
+    ni = c.mask.sum(1)
+    mj = c.mask.sum(0)
+    np.testing.assert_array_equal(ax, 1.0 / np.maximum(ni, 1))
+    np.testing.assert_array_equal(ay, 1.0 / np.maximum(mj, 1))
+
+
+def test_dense_and_coo_forms_agree():
+    cd = synth.small_mixed(20, 15, 3, seed=13)
+    cc = synth.small_mixed(20, 15, 3, seed=13, layout="coo")
+    Pd, Pc = _problem(cd), _problem(cc)
+    X, Y = cd.X0.astype(np.float64), cd.Y0.astype(np.float64)
+    assert Pd.objective(X, Y) == Pc.objective(X, Y)
+
+
+def test_global_optimality_certificate_after_convergence():
+    """Convex loss + quadratic regularizer with missing entries (Section 7.6):
+    at a global optimum ||G / gamma' + U V^T||_2 <= 1, where gamma' = 2 gamma
+    because the regularizer here is gamma ||x||^2 (the factored problem of
+    Section 7.6 carries gamma'/2), G is the loss gradient matrix (zero off
+    Omega) and XY = U S V^T.  The converged fit must satisfy it; an
+    unconverged start must not."""
+    c = synth.dense_quadratic(m=40, n=30, k=4, missing=0.3, gamma=2.0, config=12)
+    P = _problem(c)
+
+    def cert(X, Y):
+        Z = X @ Y.T
+        G = np.where(c.mask.astype(bool), 2.0 * (Z - c.A.astype(np.float64)), 0.0)
+        U, s, Vt = np.linalg.svd(Z, full_matrices=False)
+        r = int(np.sum(s > 1e-8 * s[0]))
+        return np.linalg.norm(G / (2 * 2.0) + U[:, :r] @ Vt[:r], 2)
+
+    X, Y, *_ = P.fit(c.X0, c.Y0, 4000)
+    assert cert(X, Y) <= 1.0 + 1e-4
+    assert cert(c.X0.astype(np.float64), c.Y0.astype(np.float64)) > 1.0 + 1e-2
