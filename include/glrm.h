@@ -1,0 +1,211 @@
+/*
+ * glrm.h — C ABI of the MI355X (gfx950) alternating proximal-gradient fit of a
+ * generalized low rank model.
+ *
+ * The method is the one of Udell, Horn, Zadeh and Boyd, "Generalized Low Rank
+ * Models" (arXiv 1410.0342):
+ *
+ *     minimize  sum_{(i,j) in Omega} L_j(x_i . y_j, A_ij) + sum_i r(x_i) + sum_j rt(y_j)
+ *
+ * (eq. gpca in Section 4, with the per-column losses of the abstract-data form
+ * eq. apca in Section 5), fitted by Algorithm 2 of Section 7.2 with the
+ * proximal gradient update and the per-row / per-column step-size rule of
+ * Section 7.2 ("Choosing a step size").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - X is m x k, row-major, float32 (row i is the paper's x_i).
+ *  - Y is stored n x k, row-major, float32: row j is the paper's column y_j
+ *    (the paper's k x n matrix Y kept column-major, so y_j is contiguous).
+ *  - Array arguments are DEVICE pointers unless marked "host".  The glrm_data
+ *    struct, the loss table, the per-column loss codes and the glrm_fit_opts /
+ *    glrm_fit_info structs live in host memory.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *    it; entry points that return a host value synchronize it.
+ *  - Every entry point validates its arguments on the host before it enqueues
+ *    anything; on an error it returns a negative code, writes no output, and
+ *    glrm_last_error() describes the problem.
+ *  - The library never allocates or frees caller-visible device memory.
+ *    Scratch space is the caller's `ws` buffer (device memory, 256-byte
+ *    aligned) of at least glrm_workspace_size() bytes.  Calls that share a
+ *    workspace must be ordered (same stream, or synchronized).
+ */
+#ifndef GLRM_H
+#define GLRM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ----------------------------------------------------------- */
+#define GLRM_OK            0
+#define GLRM_EINVAL       -1  /* null pointer, bad size, bad kind, unsorted / out-of-range COO, bad loss code */
+#define GLRM_EUNSUPPORTED -2  /* valid request outside what is built (e.g. k > 64, dense fit with n > 2048) */
+#define GLRM_ENOMEM       -3  /* workspace smaller than glrm_workspace_size() */
+#define GLRM_EHIP         -4  /* a HIP runtime call failed; the message names it */
+
+/* ---- loss kinds (Section 4 and Section 5.1) ----------------------------------
+ *  QUADRATIC  (a - u)^2                              eq. qpca
+ *  HUBER      huber(u - a) with threshold `param`:   Section 4.2 ("Huber PCA",
+ *             0.5 r^2 if |r| <= param else           the paper fixes param = 1)
+ *             param |r| - 0.5 param^2
+ *  LOGISTIC   log(1 + exp(-a u)), a in {-1, +1}      Section 5.1 ("Logistic PCA")
+ *  HINGE      max(0, 1 - a u),     a in {-1, +1}      Section 5.1 ("Boolean PCA")
+ *  ORDINAL    sum_{a'<a} (1 - u + a')_+ +            eq. ord-pca, a in {1..levels}
+ *             sum_{a'>a} (1 + u - a')_+
+ * The derivative used at a kink is the strict-inequality branch (the kink
+ * contributes 0); Section 7.2 allows any subgradient. */
+enum { GLRM_LOSS_QUADRATIC = 0, GLRM_LOSS_HUBER = 1, GLRM_LOSS_LOGISTIC = 2,
+       GLRM_LOSS_HINGE = 3, GLRM_LOSS_ORDINAL = 4 };
+
+/* ---- regularizer kinds (Section 3) and their proxes (Section 7.2) -------------
+ *  ZERO       0                                  prox: v
+ *  QUADRATIC  weight * ||x||_2^2                 prox: v / (1 + 2 alpha weight)
+ *  L1         weight * ||x||_1                   prox: sign(v) max(|v| - alpha weight, 0)
+ *  NONNEG     0 if x >= 0 else +inf              prox: max(v, 0) */
+enum { GLRM_REG_ZERO = 0, GLRM_REG_QUADRATIC = 1, GLRM_REG_L1 = 2, GLRM_REG_NONNEG = 3 };
+
+/* ---- data layouts -------------------------------------------------------------- */
+enum { GLRM_DENSE = 0, GLRM_COO_ROWSORTED = 1 };
+
+/* ---- arithmetic of the contractions z = x_i . y_j, G Y^T and X^T G ---------------
+ *  FP32        float32 operands, float32 matrix-core products (v_mfma_f32_16x16x4_f32)
+ *  BF16        z from three bfloat16 products (hi*hi + hi*lo + lo*hi, float32
+ *              accumulation); both gradient contractions from one bfloat16 product;
+ *              loss, prox, step rule and objective in float32
+ *  FP64        float64 throughout (glrm_objective only: the final / convergence check)
+ *  BF16_PLAIN  every contraction from one bfloat16 product (fastest, least accurate)
+ * For the COO layout the products run on the vector ALUs in the same precisions. */
+enum { GLRM_FP32 = 0, GLRM_BF16 = 1, GLRM_FP64 = 2, GLRM_BF16_PLAIN = 3 };
+
+#define GLRM_MAX_LOSSES 16
+#define GLRM_MAX_K 64
+
+typedef struct {
+    int32_t kind;    /* GLRM_LOSS_* */
+    int32_t levels;  /* ORDINAL: number of levels d >= 2, data in 1..d; else ignored */
+    float   param;   /* HUBER: threshold > 0; else ignored */
+} glrm_loss;
+
+typedef struct {
+    int32_t kind;    /* GLRM_REG_* */
+    float   weight;  /* >= 0; ignored for ZERO and NONNEG */
+} glrm_reg;
+
+/* The problem (eq. gpca / eq. apca).  Host struct. */
+typedef struct {
+    int64_t m, n;             /* rows and columns of A, both >= 1 */
+    int32_t k;                /* rank, 1 <= k <= GLRM_MAX_K */
+    int32_t layout;           /* GLRM_DENSE or GLRM_COO_ROWSORTED */
+    /* dense: A is m x n row-major with leading dimension lda >= n (device).
+     *        mask has the same shape and leading dimension, 1 = observed
+     *        (device, NULL = every entry observed).  Observed values must be
+     *        finite.
+     * COO:   A holds the nnz observed values (device); row / col are the nnz
+     *        0-based indices (device int32), sorted by row then column, no
+     *        duplicates.  mask and lda are ignored. */
+    const float   *A;
+    int64_t        lda;
+    const uint8_t *mask;
+    const int32_t *row;
+    const int32_t *col;
+    int64_t        nnz;
+    /* per-column loss: col_loss[j] indexes losses[] (host, n bytes; NULL = all 0) */
+    const uint8_t   *col_loss;
+    const glrm_loss *losses;  /* host, n_losses entries */
+    int32_t          n_losses;/* 1 .. GLRM_MAX_LOSSES */
+    glrm_reg rx;              /* r on the rows of X */
+    glrm_reg ry;              /* rt on the columns of the paper's Y */
+} glrm_data;
+
+/* Flags for the compute entry points. */
+#define GLRM_WS_PREPARED 1u   /* `ws` already holds what glrm_prepare() builds for this
+                                 exact data (same pointers, sizes and contents); skip it */
+
+/* Bytes of device workspace any entry point needs for this problem.  The same
+ * size serves glrm_prepare, glrm_objective, glrm_grad and glrm_fit, and the
+ * prepared part sits at the same offsets for all of them.  Returns 0 when the
+ * problem is invalid (glrm_last_error() then says why). */
+size_t glrm_workspace_size(const glrm_data *d);
+
+/* Build the data-derived state in `ws`: the per-column loss codes, the row /
+ * column observation counts n_i and m_j, the dense table with unobserved
+ * entries folded in (dense), and the row pointers and column-grouped copy of
+ * the entries (COO).  Asynchronous on `stream`, except that it waits for the
+ * small host-to-device copy of the loss codes.  Call it again after the data
+ * change; then pass GLRM_WS_PREPARED to skip it inside the other calls. */
+int glrm_prepare(const glrm_data *d, void *ws, size_t ws_bytes, void *stream);
+
+/* F(X, Y) of eq. gpca: the loss over Omega plus both regularizer sums
+ * (Section 4).  Per-entry losses are evaluated in `precision` (FP32, BF16,
+ * BF16_PLAIN or FP64) and summed in float64.  Writes *obj_host (host) and
+ * synchronizes `stream`. */
+int glrm_objective(const glrm_data *d, const float *X, const float *Y, int precision,
+                   double *obj_host, void *ws, size_t ws_bytes, unsigned flags, void *stream);
+
+/* Loss-part gradients (Section 7.2, g = sum_j dL(x_i . y_j, A_ij) y_j):
+ *   dX[i,:] = sum_{j:(i,j) in Omega} G_ij y_j        (m x k, row-major, device)
+ *   dY[j,:] = sum_{i:(i,j) in Omega} G_ij x_i        (n x k, row-major, device)
+ * with G_ij = dL_j(x_i . y_j, A_ij).  Regularizer gradients are not added.
+ * Precision FP32, BF16 or BF16_PLAIN.  If obj_host is not NULL the objective
+ * (as glrm_objective at the same precision) is written there and `stream` is
+ * synchronized; otherwise the call is asynchronous. */
+int glrm_grad(const glrm_data *d, const float *X, const float *Y, int precision,
+              float *dX, float *dY, double *obj_host, void *ws, size_t ws_bytes,
+              unsigned flags, void *stream);
+
+/* In place V[i,:] <- prox_{alpha[i] r}(V[i,:]) for i < rows (Section 7.2,
+ * prox_f(z) = argmin_x f(x) + 1/2 ||x - z||^2).  V is rows x k with leading
+ * dimension ldv >= k (device); alpha has `rows` entries (device) or is NULL
+ * for alpha = 1.  Asynchronous. */
+int glrm_prox(const glrm_reg *reg, float *V, int64_t rows, int32_t k, int64_t ldv,
+              const float *alpha, void *stream);
+
+typedef struct {
+    int32_t max_sweeps;   /* sweeps to run, >= 0 */
+    int32_t precision;    /* GLRM_FP32, GLRM_BF16 or GLRM_BF16_PLAIN */
+    int32_t init_alpha;   /* 1: alpha_x[i] = alpha_scale / max(n_i, 1) and likewise
+                             alpha_y (Section 7.2); 0: use the caller's alpha (resume) */
+    float   alpha_scale;  /* the paper's initial scale, 1 */
+    float   step_up;      /* factor after a step that did not increase the row objective (1.05) */
+    float   step_down;    /* factor after a step that increased it (0.7) */
+    double  tol;          /* > 0: stop once (F_prev - F) <= tol * |F_prev| after a sweep
+                             (reads F back to the host every sweep); 0: run max_sweeps */
+    uint32_t flags;       /* GLRM_WS_PREPARED */
+} glrm_fit_opts;
+
+typedef struct {
+    int32_t sweeps;          /* sweeps run */
+    double  objective;       /* F after the last sweep, recomputed in float64 on the GPU */
+    double  objective_fp32;  /* F after the last sweep as the sweep tracked it (float32 terms) */
+    int64_t rows_rejected;   /* rows whose step was rejected in the last sweep */
+    int64_t cols_rejected;   /* columns whose step was rejected in the last sweep */
+} glrm_fit_info;
+
+/* Run Algorithm 2 (Section 7.2): per sweep, every row takes one proximal
+ * gradient step against Y^{t-1} and keeps it only if its row objective did not
+ * increase; then every column does the same against the updated X^t
+ * (Gauss-Seidel).  Step sizes are per row / per column and move by step_up /
+ * step_down.  X (m x k), Y (n x k), alpha_x (m) and alpha_y (n) are device
+ * arrays updated in place, so a second call resumes the fit.  history
+ * (device, max_sweeps doubles, may be NULL) receives F after each sweep as the
+ * sweep tracked it.  info_host (host, may be NULL) is filled at the end.
+ * Synchronizes `stream`. */
+int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alpha_y,
+             const glrm_fit_opts *opts, glrm_fit_info *info_host, double *history,
+             void *ws, size_t ws_bytes, void *stream);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *glrm_last_error(void);
+
+/* Library version string. */
+const char *glrm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLRM_H */

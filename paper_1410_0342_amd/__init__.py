@@ -1,0 +1,286 @@
+"""Python binding of libglrm.so, the gfx950 alternating proximal-gradient fit of
+a generalized low rank model (Udell et al., arXiv 1410.0342, Algorithm 2 of
+Section 7.2).
+
+This module only marshals arguments: it turns torch tensors into device
+pointers, fills the C structs of ``include/glrm.h`` and calls the entry points
+of the same names.  Every step of the method runs in the HIP kernels.  There
+is no fallback: if the library is not built, importing the entry points raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "GLRMError", "Data", "glrm_workspace_size", "glrm_prepare", "glrm_objective", "glrm_grad", "glrm_prox",
+    "glrm_fit", "glrm_last_error", "library_path", "FP32", "BF16", "FP64", "BF16_PLAIN", "DENSE", "COO_ROWSORTED",
+    "WS_PREPARED",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libglrm.so")
+
+FP32, BF16, FP64, BF16_PLAIN = 0, 1, 2, 3
+DENSE, COO_ROWSORTED = 0, 1
+WS_PREPARED = 1
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp64": FP64, "bf16_plain": BF16_PLAIN}
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
+
+
+class GLRMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("glrm error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Loss(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("levels", ctypes.c_int32), ("param", ctypes.c_float)]
+
+
+class _Reg(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("weight", ctypes.c_float)]
+
+
+class _Data(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("mask", ctypes.c_void_p),
+                ("row", ctypes.c_void_p), ("col", ctypes.c_void_p), ("nnz", ctypes.c_int64),
+                ("col_loss", ctypes.c_void_p), ("losses", ctypes.c_void_p), ("n_losses", ctypes.c_int32),
+                ("rx", _Reg), ("ry", _Reg)]
+
+
+class _FitOpts(ctypes.Structure):
+    _fields_ = [("max_sweeps", ctypes.c_int32), ("precision", ctypes.c_int32), ("init_alpha", ctypes.c_int32),
+                ("alpha_scale", ctypes.c_float), ("step_up", ctypes.c_float), ("step_down", ctypes.c_float),
+                ("tol", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class _FitInfo(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("objective", ctypes.c_double), ("objective_fp32", ctypes.c_double),
+                ("rows_rejected", ctypes.c_int64), ("cols_rejected", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError("libglrm.so is not built (%s); run __graft_entry__.build() first" % _LIB_PATH)
+        L = ctypes.CDLL(_LIB_PATH)
+        P, D = ctypes.c_void_p, ctypes.POINTER(_Data)
+        L.glrm_workspace_size.restype = ctypes.c_size_t
+        L.glrm_workspace_size.argtypes = [D]
+        L.glrm_prepare.restype = ctypes.c_int
+        L.glrm_prepare.argtypes = [D, P, ctypes.c_size_t, P]
+        L.glrm_objective.restype = ctypes.c_int
+        L.glrm_objective.argtypes = [D, P, P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), P, ctypes.c_size_t,
+                                     ctypes.c_uint, P]
+        L.glrm_grad.restype = ctypes.c_int
+        L.glrm_grad.argtypes = [D, P, P, ctypes.c_int, P, P, ctypes.POINTER(ctypes.c_double), P, ctypes.c_size_t,
+                                ctypes.c_uint, P]
+        L.glrm_prox.restype = ctypes.c_int
+        L.glrm_prox.argtypes = [ctypes.POINTER(_Reg), P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, P, P]
+        L.glrm_fit.restype = ctypes.c_int
+        L.glrm_fit.argtypes = [D, P, P, P, P, ctypes.POINTER(_FitOpts), ctypes.POINTER(_FitInfo), P, P,
+                               ctypes.c_size_t, P]
+        L.glrm_last_error.restype = ctypes.c_char_p
+        L.glrm_last_error.argtypes = []
+        L.glrm_version.restype = ctypes.c_char_p
+        L.glrm_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def glrm_last_error():
+    return _L().glrm_last_error().decode()
+
+
+def _check(rc):
+    if rc != OK:
+        raise GLRMError(rc, glrm_last_error())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype, name, numel=None):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a GPU tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must have %d elements (got %d)" % (name, numel, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Data:
+    """A problem on the device: the ``glrm_data`` struct and the tensors and host
+    arrays it points to (kept alive here), plus a cached workspace.
+
+    ``losses`` is a list of ``(kind, levels, param)``; ``col_loss`` a host array
+    of one loss index per column (None = all 0); ``rx`` / ``ry`` are
+    ``(kind, weight)``.
+    """
+
+    def __init__(self, m, n, k, *, A, mask=None, row=None, col=None, layout=DENSE, lda=None, col_loss=None,
+                 losses=((0, 0, 0.0),), rx=(0, 0.0), ry=(0, 0.0)):
+        torch = _torch()
+        self.m, self.n, self.k, self.layout = int(m), int(n), int(k), int(layout)
+        self.A, self.mask, self.row, self.col = A, mask, row, col
+        self.losses = [tuple(x) for x in losses]
+        self.rx, self.ry = (int(rx[0]), float(rx[1])), (int(ry[0]), float(ry[1]))
+        self._loss_arr = (_Loss * len(self.losses))(*[_Loss(int(a), int(b), float(c)) for a, b, c in self.losses])
+        self.col_loss = None if col_loss is None else np.ascontiguousarray(col_loss, dtype=np.uint8)
+        s = _Data()
+        s.m, s.n, s.k, s.layout = self.m, self.n, self.k, self.layout
+        if self.layout == DENSE:
+            s.A = _dev_ptr(A, torch.float32, "A")
+            s.lda = int(lda if lda is not None else self.n)
+            s.mask = _dev_ptr(mask, torch.uint8, "mask") if mask is not None else None
+            s.nnz = 0
+        else:
+            s.A = _dev_ptr(A, torch.float32, "A (values)")
+            s.row = _dev_ptr(row, torch.int32, "row")
+            s.col = _dev_ptr(col, torch.int32, "col")
+            s.nnz = int(A.numel())
+            s.lda = 0
+        s.col_loss = self.col_loss.ctypes.data if self.col_loss is not None else None
+        s.losses = ctypes.addressof(self._loss_arr)
+        s.n_losses = len(self.losses)
+        s.rx = _Reg(*self.rx)
+        s.ry = _Reg(*self.ry)
+        self.s = s
+        self._ws = None
+        self.device = A.device
+
+    @classmethod
+    def from_case(cls, case, device="cuda"):
+        """Upload a synthetic case (see ``synth.Case``) to the device."""
+        torch = _torch()
+        if case.layout == "coo":
+            return cls(case.m, case.n, case.k, layout=COO_ROWSORTED,
+                       A=torch.from_numpy(np.ascontiguousarray(case.vals, np.float32)).to(device),
+                       row=torch.from_numpy(np.ascontiguousarray(case.rows, np.int32)).to(device),
+                       col=torch.from_numpy(np.ascontiguousarray(case.cols, np.int32)).to(device),
+                       col_loss=case.col_loss, losses=case.losses, rx=case.rx, ry=case.ry)
+        mask = None if case.mask is None else torch.from_numpy(np.ascontiguousarray(case.mask, np.uint8)).to(device)
+        return cls(case.m, case.n, case.k, layout=DENSE,
+                   A=torch.from_numpy(np.ascontiguousarray(case.A, np.float32)).to(device), mask=mask,
+                   col_loss=case.col_loss, losses=case.losses, rx=case.rx, ry=case.ry)
+
+    def with_regs(self, rx, ry):
+        """Same data and losses with other regularizers (shares the tensors)."""
+        return Data(self.m, self.n, self.k, A=self.A, mask=self.mask, row=self.row, col=self.col,
+                    layout=self.layout, lda=self.s.lda if self.layout == DENSE else None, col_loss=self.col_loss,
+                    losses=self.losses, rx=rx, ry=ry)
+
+    def workspace(self):
+        """Device workspace of glrm_workspace_size() bytes, 256-byte aligned, cached."""
+        torch = _torch()
+        size = glrm_workspace_size(self)
+        if self._ws is None or self._ws[1] < size:
+            buf = torch.empty(size + 256, dtype=torch.uint8, device=self.device)
+            off = (-buf.data_ptr()) % 256
+            self._ws = (buf, size, off)
+        buf, size, off = self._ws
+        return ctypes.c_void_p(buf.data_ptr() + off), size
+
+
+def glrm_workspace_size(data):
+    size = _L().glrm_workspace_size(ctypes.byref(data.s))
+    if size == 0:
+        raise GLRMError(EINVAL, glrm_last_error())
+    return size
+
+
+def glrm_prepare(data, stream=None):
+    ws, wsb = data.workspace()
+    _check(_L().glrm_prepare(ctypes.byref(data.s), ws, wsb, _stream(stream)))
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def glrm_objective(data, X, Y, precision=FP32, flags=0, stream=None):
+    """F(X, Y) of eq. gpca (loss over the observed entries + both regularizers)."""
+    torch = _torch()
+    ws, wsb = data.workspace()
+    out = ctypes.c_double(0.0)
+    _check(_L().glrm_objective(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
+                               _dev_ptr(Y, torch.float32, "Y", data.n * data.k), _prec(precision),
+                               ctypes.byref(out), ws, wsb, int(flags), _stream(stream)))
+    return out.value
+
+
+def glrm_grad(data, X, Y, precision=FP32, dX=None, dY=None, want_objective=False, flags=0, stream=None):
+    """Loss-part gradients dX (m x k) and dY (n x k); optionally the objective."""
+    torch = _torch()
+    if dX is None:
+        dX = torch.empty((data.m, data.k), dtype=torch.float32, device=X.device)
+    if dY is None:
+        dY = torch.empty((data.n, data.k), dtype=torch.float32, device=X.device)
+    ws, wsb = data.workspace()
+    out = ctypes.c_double(0.0)
+    _check(_L().glrm_grad(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
+                          _dev_ptr(Y, torch.float32, "Y", data.n * data.k), _prec(precision),
+                          _dev_ptr(dX, torch.float32, "dX", data.m * data.k),
+                          _dev_ptr(dY, torch.float32, "dY", data.n * data.k),
+                          ctypes.byref(out) if want_objective else None, ws, wsb, int(flags), _stream(stream)))
+    return (dX, dY, out.value) if want_objective else (dX, dY)
+
+
+def glrm_prox(reg, V, alpha=None, stream=None):
+    """In place V[i] <- prox_{alpha_i r}(V[i]) for a rows x k float32 tensor."""
+    torch = _torch()
+    rows, k = V.shape
+    r = _Reg(int(reg[0]), float(reg[1]))
+    _check(_L().glrm_prox(ctypes.byref(r), _dev_ptr(V, torch.float32, "V"), int(rows), int(k), int(k),
+                          _dev_ptr(alpha, torch.float32, "alpha", rows) if alpha is not None else None,
+                          _stream(stream)))
+    return V
+
+
+def glrm_fit(data, X, Y, alpha_x, alpha_y, max_sweeps, precision=BF16, init_alpha=True, alpha_scale=1.0,
+             step_up=1.05, step_down=0.7, tol=0.0, history=None, flags=0, stream=None):
+    """Run Algorithm 2 in place on X, Y, alpha_x, alpha_y; returns the info dict.
+
+    ``history`` (optional float64 GPU tensor of max_sweeps entries) receives F
+    after each sweep."""
+    torch = _torch()
+    o = _FitOpts(int(max_sweeps), _prec(precision), 1 if init_alpha else 0, float(alpha_scale), float(step_up),
+                 float(step_down), float(tol), int(flags))
+    info = _FitInfo()
+    ws, wsb = data.workspace()
+    _check(_L().glrm_fit(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
+                         _dev_ptr(Y, torch.float32, "Y", data.n * data.k),
+                         _dev_ptr(alpha_x, torch.float32, "alpha_x", data.m),
+                         _dev_ptr(alpha_y, torch.float32, "alpha_y", data.n), ctypes.byref(o), ctypes.byref(info),
+                         _dev_ptr(history, torch.float64, "history") if history is not None else None,
+                         ws, wsb, _stream(stream)))
+    return dict(sweeps=info.sweeps, objective=info.objective, objective_fp32=info.objective_fp32,
+                rows_rejected=info.rows_rejected, cols_rejected=info.cols_rejected)

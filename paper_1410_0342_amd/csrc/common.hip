@@ -1,0 +1,143 @@
+// Set-up and element-wise kernels: packing the dense table, observation
+// counts and initial step sizes (Section 7.2: alpha^0 = scale / n_i), the prox
+// of a regularizer over the rows of a factor, regularizer sums, and fixed-order
+// double reductions.
+#include "glrm_device.h"
+#include "glrm_kernels.h"
+
+namespace glrm {
+
+// One workgroup per 16 rows of the padded table.  Unobserved and padding
+// entries become quiet NaN.  Row counts are exact block sums; column counts
+// are integer atomics (order-free, so deterministic).
+__global__ __launch_bounds__(256) void pack_dense_kernel(PackArgs a)
+{
+    __shared__ int s_cnt[4];
+    const int64_t i0 = (int64_t)blockIdx.x * 16;
+    const float qnan = __builtin_nanf("");
+    for (int ii = 0; ii < 16; ++ii) {
+        const int64_t i = i0 + ii;
+        int cnt = 0;
+        for (int64_t j = threadIdx.x; j < a.ldp; j += 256) {
+            float v = qnan;
+            if (i < a.m && j < a.n) {
+                const bool obs = a.mask ? (a.mask[i * a.lda + j] != 0) : true;
+                if (obs) { v = a.A[i * a.lda + j]; ++cnt; }
+            }
+            a.Ap[i * a.ldp + j] = v;
+        }
+        cnt = (int)sum_lanes<64>((float)cnt);
+        if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0 && i < a.m) a.row_count[i] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        __syncthreads();
+    }
+    for (int64_t j = threadIdx.x; j < a.n; j += 256) {
+        int cnt = 0;
+        for (int ii = 0; ii < 16; ++ii) {
+            const int64_t i = i0 + ii;
+            if (i < a.m) cnt += a.mask ? (a.mask[i * a.lda + j] != 0) : 1;
+        }
+        if (cnt) atomicAdd(&a.col_count[j], cnt);
+    }
+}
+
+hipError_t launch_pack_dense(const PackArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(pack_dense_kernel, dim3((unsigned)(a.mp / 16)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+__global__ void init_alpha_kernel(const int32_t *count, int64_t len, float scale, float *alpha)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < len) {
+        const int c = count[t];
+        alpha[t] = scale / (float)(c > 0 ? c : 1);
+    }
+}
+
+hipError_t launch_init_alpha(const int32_t *count, int64_t len, float scale, float *alpha, hipStream_t st)
+{
+    if (len <= 0) return hipSuccess;
+    hipLaunchKernelGGL(init_alpha_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, count, len, scale,
+                       alpha);
+    return hipGetLastError();
+}
+
+__global__ void prox_kernel(Reg r, float *V, int64_t rows, int32_t k, int64_t ldv, const float *alpha)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= rows * k) return;
+    const int64_t i = t / k;
+    const int c = (int)(t % k);
+    const float al = alpha ? alpha[i] : 1.0f;
+    V[i * ldv + c] = prox_elem(r, al, V[i * ldv + c]);
+}
+
+hipError_t launch_prox(Reg r, float *V, int64_t rows, int32_t k, int64_t ldv, const float *alpha, hipStream_t st)
+{
+    const int64_t total = rows * k;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(prox_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, r, V, rows, k, ldv,
+                       alpha);
+    return hipGetLastError();
+}
+
+// Regularizer sum over a factor, in double; one partial per workgroup.
+__global__ __launch_bounds__(256) void regsum_kernel(Reg r, const float *V, int64_t rows, int32_t k, double *part)
+{
+    __shared__ double s[4];
+    double acc = 0.0;
+    const int64_t total = rows * k;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256)
+        acc += reg_elem64(r, (double)V[t]);
+    acc = sum_lanes64<64>(acc);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+hipError_t launch_regsum(Reg r, const float *V, int64_t rows, int32_t k, double *part, int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(regsum_kernel, dim3(blocks), dim3(256), 0, st, r, V, rows, k, part);
+    return hipGetLastError();
+}
+
+// out = sum(a) + sum(b), fixed order (one workgroup, tree in LDS).
+__global__ __launch_bounds__(256) void sum_doubles_kernel(const double *a, int32_t na, const double *b, int32_t nb,
+                                                          double *out)
+{
+    __shared__ double s[256];
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < na; q += 256) acc += a[q];
+    for (int q = threadIdx.x; q < nb; q += 256) acc += b[q];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+hipError_t launch_sum_doubles(const double *a, int32_t na, const double *b, int32_t nb, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(sum_doubles_kernel, dim3(1), dim3(256), 0, st, a, na, b, nb, out);
+    return hipGetLastError();
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int64_t len, int32_t v)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < len) p[t] = v;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t len, int32_t v, hipStream_t st)
+{
+    if (len <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, p, len, v);
+    return hipGetLastError();
+}
+
+}  // namespace glrm

@@ -1,0 +1,584 @@
+// Host side of the C ABI declared in include/glrm.h: argument validation,
+// workspace layout, and the sweep driver of Algorithm 2 (Section 7.2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <string>
+
+#include "../../include/glrm.h"
+#include "glrm_kernels.h"
+#include "coo.h"
+
+using namespace glrm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(GLRM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int P_MAX = 256;     // workgroups of the persistent dense kernels
+constexpr int NWAVES = 8;      // wavefronts per dense workgroup (matches the kernels)
+constexpr int REG_BLOCKS = 64; // partials of a regularizer sum
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int kp_of(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
+
+// Tiles per wavefront needed to cover `ntiles` column tiles in one workgroup.
+int tpw_for(int64_t ntiles)
+{
+    for (int t : {1, 2, 4, 8})
+        if ((int64_t)NWAVES * t >= ntiles) return t;
+    return 0;
+}
+
+struct Layout {
+    int64_t m, n, k, kp, mp, ldp;
+    size_t total = 0;
+    // offsets
+    size_t codes, row_count, col_count, Ap;
+    size_t part_dy, part_h, part_hp, part_rowreg, part_rej, part_dx, part_obj;
+    size_t ycur_f32, ycur_t32, ycur_hi, ycur_lo, ycur_tb;
+    size_t yp_f32, yp_t32, yp_hi, yp_lo, yp_tb;
+    size_t Yplus, h_old, ry_plus, ry_old, part_F, part_rejc, stats, istats, regpart, scal;
+    size_t coo;            // start of the COO region
+    CooLayout cl;
+    int64_t cb_grad;       // column blocks of the gradient kernel
+    int tpw_grad;
+
+    size_t take(size_t bytes)
+    {
+        size_t off = total;
+        total += round_up((int64_t)bytes, 256);
+        return off;
+    }
+};
+
+bool make_layout(const glrm_data *d, Layout &L)
+{
+    L = Layout();
+    L.m = d->m;
+    L.n = d->n;
+    L.k = d->k;
+    L.kp = kp_of(d->k);
+    L.mp = round_up(d->m, 16);
+    L.ldp = round_up(d->n, 16);
+    const int64_t ntiles = L.ldp / 16;
+    L.tpw_grad = tpw_for(ntiles);
+    if (L.tpw_grad == 0 || L.tpw_grad > 4) L.tpw_grad = 4;
+    if (L.kp == 64 && L.tpw_grad > 4) L.tpw_grad = 4;
+    L.cb_grad = (ntiles + NWAVES * L.tpw_grad - 1) / (NWAVES * L.tpw_grad);
+    const int64_t kp = L.kp, ldp = L.ldp, n = L.n, m = L.m;
+    L.codes = L.take(ldp);
+    L.row_count = L.take(sizeof(int32_t) * m);
+    L.col_count = L.take(sizeof(int32_t) * n);
+    L.stats = L.take(sizeof(double) * 8);
+    L.istats = L.take(sizeof(long long) * 8);
+    L.scal = L.take(sizeof(double) * 8);
+    L.regpart = L.take(sizeof(double) * 2 * REG_BLOCKS);
+    L.ycur_f32 = L.take(sizeof(float) * ldp * kp);
+    L.ycur_t32 = L.take(sizeof(float) * ldp * kp);
+    L.ycur_hi = L.take(2 * ldp * kp);
+    L.ycur_lo = L.take(2 * ldp * kp);
+    L.ycur_tb = L.take(2 * ldp * kp);
+    L.yp_f32 = L.take(sizeof(float) * ldp * kp);
+    L.yp_t32 = L.take(sizeof(float) * ldp * kp);
+    L.yp_hi = L.take(2 * ldp * kp);
+    L.yp_lo = L.take(2 * ldp * kp);
+    L.yp_tb = L.take(2 * ldp * kp);
+    L.Yplus = L.take(sizeof(float) * n * L.k);
+    L.h_old = L.take(sizeof(float) * n);
+    L.ry_plus = L.take(sizeof(float) * n);
+    L.ry_old = L.take(sizeof(float) * n);
+    const int64_t ya_blocks = (n * kp + 255) / 256;
+    L.part_F = L.take(sizeof(double) * ya_blocks);
+    L.part_rejc = L.take(sizeof(int32_t) * ya_blocks);
+    if (d->layout == GLRM_DENSE) {
+        L.Ap = L.take(sizeof(float) * L.mp * ldp);
+        L.part_dy = L.take(sizeof(float) * P_MAX * ldp * kp);
+        L.part_h = L.take(sizeof(float) * P_MAX * ldp);
+        L.part_hp = L.take(sizeof(float) * P_MAX * ldp);
+        L.part_rowreg = L.take(sizeof(float) * P_MAX);
+        L.part_rej = L.take(sizeof(int32_t) * P_MAX);
+        L.part_dx = L.cb_grad > 1 ? L.take(sizeof(float) * L.cb_grad * m * L.k) : 0;
+        L.part_obj = L.take(sizeof(double) * P_MAX * std::max<int64_t>(L.cb_grad, 1));
+    } else {
+        L.coo = L.take(0);
+        coo_layout(d, L.kp, L.cl);
+        L.coo = L.take(L.cl.total);
+    }
+    return true;
+}
+
+template <typename T>
+T *at(void *ws, size_t off) { return reinterpret_cast<T *>(static_cast<char *>(ws) + off); }
+
+int validate_data(const glrm_data *d)
+{
+    if (!d) return fail(GLRM_EINVAL, "data is NULL");
+    if (d->m < 1 || d->n < 1) return fail(GLRM_EINVAL, "m and n must be >= 1 (got %lld, %lld)", (long long)d->m, (long long)d->n);
+    if (d->m > (int64_t)INT32_MAX || d->n > (int64_t)INT32_MAX) return fail(GLRM_EUNSUPPORTED, "m and n must fit in int32");
+    if (d->k < 1) return fail(GLRM_EINVAL, "k must be >= 1 (got %d)", d->k);
+    if (d->k > GLRM_MAX_K) return fail(GLRM_EUNSUPPORTED, "k = %d exceeds GLRM_MAX_K = %d", d->k, GLRM_MAX_K);
+    if (!d->A) return fail(GLRM_EINVAL, "A is NULL");
+    if (d->layout == GLRM_DENSE) {
+        if (d->lda < d->n) return fail(GLRM_EINVAL, "lda (%lld) < n (%lld)", (long long)d->lda, (long long)d->n);
+    } else if (d->layout == GLRM_COO_ROWSORTED) {
+        if (!d->row || !d->col) return fail(GLRM_EINVAL, "COO row / col is NULL");
+        if (d->nnz < 0) return fail(GLRM_EINVAL, "nnz < 0");
+        if (d->nnz > (int64_t)INT32_MAX) return fail(GLRM_EUNSUPPORTED, "nnz must fit in int32 for this build");
+    } else {
+        return fail(GLRM_EINVAL, "unknown layout %d", d->layout);
+    }
+    if (d->n_losses < 1 || d->n_losses > GLRM_MAX_LOSSES)
+        return fail(GLRM_EINVAL, "n_losses must be in 1..%d (got %d)", GLRM_MAX_LOSSES, d->n_losses);
+    if (!d->losses) return fail(GLRM_EINVAL, "losses is NULL");
+    for (int q = 0; q < d->n_losses; ++q) {
+        const glrm_loss &l = d->losses[q];
+        if (l.kind < GLRM_LOSS_QUADRATIC || l.kind > GLRM_LOSS_ORDINAL) return fail(GLRM_EINVAL, "loss %d: unknown kind %d", q, l.kind);
+        if (l.kind == GLRM_LOSS_HUBER && !(l.param > 0.0f && std::isfinite(l.param)))
+            return fail(GLRM_EINVAL, "loss %d: Huber threshold must be finite and > 0", q);
+        if (l.kind == GLRM_LOSS_ORDINAL && (l.levels < 2 || l.levels > 1000000))
+            return fail(GLRM_EINVAL, "loss %d: ordinal levels must be in 2..1e6", q);
+    }
+    if (d->col_loss) {
+        for (int64_t j = 0; j < d->n; ++j)
+            if (d->col_loss[j] >= d->n_losses) return fail(GLRM_EINVAL, "col_loss[%lld] = %d >= n_losses", (long long)j, d->col_loss[j]);
+    }
+    for (const glrm_reg *r : {&d->rx, &d->ry}) {
+        if (r->kind < GLRM_REG_ZERO || r->kind > GLRM_REG_NONNEG) return fail(GLRM_EINVAL, "unknown regularizer kind %d", r->kind);
+        if (!(r->weight >= 0.0f) || !std::isfinite(r->weight)) return fail(GLRM_EINVAL, "regularizer weight must be finite and >= 0");
+    }
+    return GLRM_OK;
+}
+
+LossTab make_losstab(const glrm_data *d)
+{
+    LossTab t;
+    memset(&t, 0, sizeof t);
+    t.n = d->n_losses;
+    for (int q = 0; q < d->n_losses; ++q) {
+        t.kind[q] = d->losses[q].kind;
+        t.levels[q] = d->losses[q].levels;
+        t.param[q] = d->losses[q].param;
+    }
+    t.uniform = -1;
+    if (!d->col_loss) t.uniform = 0;
+    else {
+        int u = d->col_loss[0];
+        for (int64_t j = 1; j < d->n; ++j)
+            if (d->col_loss[j] != u) { u = -1; break; }
+        t.uniform = u;
+    }
+    return t;
+}
+
+Reg make_reg(const glrm_reg &r) { return Reg{r.kind, r.weight}; }
+
+YShadow shadow(void *ws, const Layout &L, bool plus)
+{
+    YShadow s;
+    s.f32 = at<float>(ws, plus ? L.yp_f32 : L.ycur_f32);
+    s.t32 = at<float>(ws, plus ? L.yp_t32 : L.ycur_t32);
+    s.hi = at<__bf16>(ws, plus ? L.yp_hi : L.ycur_hi);
+    s.lo = at<__bf16>(ws, plus ? L.yp_lo : L.ycur_lo);
+    s.tb = at<__bf16>(ws, plus ? L.yp_tb : L.ycur_tb);
+    return s;
+}
+
+int check_ws(const Layout &L, void *ws, size_t ws_bytes)
+{
+    if (!ws) return fail(GLRM_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return fail(GLRM_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total) return fail(GLRM_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    return GLRM_OK;
+}
+
+int prepare(const glrm_data *d, const Layout &L, void *ws, hipStream_t st)
+{
+    // loss codes: host -> workspace (padded columns get code 0)
+    std::string codes((size_t)L.ldp, '\0');
+    if (d->col_loss) memcpy(&codes[0], d->col_loss, (size_t)d->n);
+    HIP_TRY(hipMemcpyAsync(at<uint8_t>(ws, L.codes), codes.data(), (size_t)L.ldp, hipMemcpyHostToDevice, st));
+    if (d->layout == GLRM_DENSE) {
+        HIP_TRY(launch_fill_i32(at<int32_t>(ws, L.col_count), L.n, 0, st));
+        PackArgs p;
+        p.m = L.m; p.n = L.n; p.lda = d->lda; p.mp = L.mp; p.ldp = L.ldp;
+        p.A = d->A; p.mask = d->mask;
+        p.Ap = at<float>(ws, L.Ap);
+        p.row_count = at<int32_t>(ws, L.row_count);
+        p.col_count = at<int32_t>(ws, L.col_count);
+        HIP_TRY(launch_pack_dense(p, st));
+    } else {
+        int rc = coo_prepare(d, L.kp, L.cl, at<char>(ws, L.coo), at<int32_t>(ws, L.row_count),
+                             at<int32_t>(ws, L.col_count), st);
+        if (rc != GLRM_OK) return rc;
+    }
+    // the host string must outlive the copy
+    HIP_TRY(hipStreamSynchronize(st));
+    if (d->layout != GLRM_DENSE) {
+        int bad = coo_check_result(L.cl, at<char>(ws, L.coo), st);
+        if (bad) return fail(GLRM_EINVAL, "COO indices are out of range, unsorted or duplicated");
+    }
+    return GLRM_OK;
+}
+
+int write_shadows(const Layout &L, const float *Y, void *ws, int prec, bool clear_plus, hipStream_t st)
+{
+    YShadowArgs a;
+    a.n = L.n; a.ldp = L.ldp; a.k = (int32_t)L.k; a.Y = Y;
+    a.ys = shadow(ws, L, false);
+    a.yp = clear_plus ? shadow(ws, L, true) : YShadow{nullptr, nullptr, nullptr, nullptr, nullptr};
+    HIP_TRY(launch_yshadow(a, (int)L.kp, prec, st));
+    return GLRM_OK;
+}
+
+// Regularizer sums of X and Y into regpart[0..2*REG_BLOCKS).
+int reg_sums(const glrm_data *d, const Layout &L, const float *X, const float *Y, void *ws, hipStream_t st)
+{
+    double *rp = at<double>(ws, L.regpart);
+    HIP_TRY(launch_regsum(make_reg(d->rx), X, L.m, (int32_t)L.k, rp, REG_BLOCKS, st));
+    HIP_TRY(launch_regsum(make_reg(d->ry), Y, L.n, (int32_t)L.k, rp + REG_BLOCKS, REG_BLOCKS, st));
+    return GLRM_OK;
+}
+
+int objective64(const glrm_data *d, const Layout &L, const float *X, const float *Y, void *ws, double *out_dev,
+                hipStream_t st)
+{
+    double *po = at<double>(ws, d->layout == GLRM_DENSE ? L.part_obj : L.scal);
+    int nparts = 0;
+    if (d->layout == GLRM_DENSE) {
+        Obj64Args a;
+        a.m = L.m; a.n = L.n; a.mp = L.mp; a.ldp = L.ldp; a.k = (int32_t)L.k;
+        a.Ap = at<float>(ws, L.Ap);
+        a.codes = at<uint8_t>(ws, L.codes);
+        a.lt = make_losstab(d);
+        a.X = X; a.Y = Y;
+        a.part_obj = po;
+        nparts = P_MAX;
+        HIP_TRY(launch_objective64(a, nparts, st));
+    } else {
+        int rc = coo_objective(d, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
+                               GLRM_FP64, &po, &nparts, st);
+        if (rc != GLRM_OK) return rc;
+    }
+    int rc = reg_sums(d, L, X, Y, ws, st);
+    if (rc != GLRM_OK) return rc;
+    double *rp = at<double>(ws, L.regpart);
+    double *tmp = at<double>(ws, L.scal) + 4;
+    HIP_TRY(launch_sum_doubles(po, nparts, rp, 2 * REG_BLOCKS, tmp, st));
+    HIP_TRY(hipMemcpyAsync(out_dev, tmp, sizeof(double), hipMemcpyDeviceToDevice, st));
+    return GLRM_OK;
+}
+
+// Dense loss (+ gradient) pass at fp32 / bf16 precision.
+int dense_lossgrad(const glrm_data *d, const Layout &L, const float *X, const float *Y, int prec, float *dX,
+                   float *dY, bool want_grad, void *ws, hipStream_t st)
+{
+    int rc = write_shadows(L, Y, ws, prec, false, st);
+    if (rc != GLRM_OK) return rc;
+    const int64_t npanels = L.mp / 16;
+    const int gx = (int)std::min<int64_t>(P_MAX, std::max<int64_t>(1, npanels));
+    const int gy = (int)L.cb_grad;
+    LossGradArgs a;
+    a.m = L.m; a.mp = L.mp; a.ldp = L.ldp; a.k = (int32_t)L.k;
+    a.Ap = at<float>(ws, L.Ap);
+    a.codes = at<uint8_t>(ws, L.codes);
+    a.lt = make_losstab(d);
+    a.X = X;
+    a.ycur = shadow(ws, L, false);
+    a.dX = dX;
+    a.part_dx = (want_grad && gy > 1) ? at<float>(ws, L.part_dx) : nullptr;
+    a.part_dy = at<float>(ws, L.part_dy);
+    a.part_obj = at<double>(ws, L.part_obj);
+    HIP_TRY(launch_lossgrad(a, (int)L.kp, L.tpw_grad, prec, want_grad, gx, gy, st));
+    if (want_grad) {
+        ReduceArgs r;
+        r.m = L.m; r.n = L.n; r.ldp = L.ldp; r.k = (int32_t)L.k; r.P = gx; r.CB = gy;
+        r.part_dy = a.part_dy; r.part_dx = a.part_dx; r.dY = dY; r.dX = dX;
+        HIP_TRY(launch_reduce_dy(r, (int)L.kp, st));
+        if (gy > 1) HIP_TRY(launch_reduce_dx(r, st));
+    }
+    return GLRM_OK;
+}
+
+int check_prec(int prec, bool allow64)
+{
+    if (prec == GLRM_FP32 || prec == GLRM_BF16 || prec == GLRM_BF16_PLAIN) return GLRM_OK;
+    if (prec == GLRM_FP64 && allow64) return GLRM_OK;
+    return fail(GLRM_EINVAL, "unsupported precision %d for this call", prec);
+}
+
+}  // namespace
+
+namespace glrm {
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+}  // namespace glrm
+
+extern "C" {
+
+const char *glrm_last_error(void) { return g_err.c_str(); }
+
+const char *glrm_version(void) { return "glrm-gfx950 0.1"; }
+
+size_t glrm_workspace_size(const glrm_data *d)
+{
+    if (validate_data(d) != GLRM_OK) return 0;
+    Layout L;
+    make_layout(d, L);
+    return L.total;
+}
+
+int glrm_prepare(const glrm_data *d, void *ws, size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    int rc = validate_data(d);
+    if (rc) return rc;
+    Layout L;
+    make_layout(d, L);
+    if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+    return prepare(d, L, ws, (hipStream_t)stream);
+}
+
+int glrm_objective(const glrm_data *d, const float *X, const float *Y, int precision, double *obj_host, void *ws,
+                   size_t ws_bytes, unsigned flags, void *stream)
+{
+    g_err.clear();
+    int rc = validate_data(d);
+    if (rc) return rc;
+    if (!X || !Y || !obj_host) return fail(GLRM_EINVAL, "X, Y and obj_host must not be NULL");
+    if ((rc = check_prec(precision, true))) return rc;
+    Layout L;
+    make_layout(d, L);
+    if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    double *res = at<double>(ws, L.scal);
+    if (precision == GLRM_FP64) {
+        if ((rc = objective64(d, L, X, Y, ws, res, st))) return rc;
+    } else {
+        double *po = nullptr;
+        int nparts = 0;
+        if (d->layout == GLRM_DENSE) {
+            if ((rc = dense_lossgrad(d, L, X, Y, precision, nullptr, nullptr, false, ws, st))) return rc;
+            po = at<double>(ws, L.part_obj);
+            nparts = (int)(std::min<int64_t>(P_MAX, std::max<int64_t>(1, L.mp / 16)) * L.cb_grad);
+        } else {
+            if ((rc = coo_objective(d, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
+                                    precision, &po, &nparts, st)))
+                return rc;
+        }
+        if ((rc = reg_sums(d, L, X, Y, ws, st))) return rc;
+        HIP_TRY(launch_sum_doubles(po, nparts, at<double>(ws, L.regpart), 2 * REG_BLOCKS, res, st));
+    }
+    HIP_TRY(hipMemcpyAsync(obj_host, res, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GLRM_OK;
+}
+
+int glrm_grad(const glrm_data *d, const float *X, const float *Y, int precision, float *dX, float *dY,
+              double *obj_host, void *ws, size_t ws_bytes, unsigned flags, void *stream)
+{
+    g_err.clear();
+    int rc = validate_data(d);
+    if (rc) return rc;
+    if (!X || !Y || !dX || !dY) return fail(GLRM_EINVAL, "X, Y, dX and dY must not be NULL");
+    if ((rc = check_prec(precision, false))) return rc;
+    Layout L;
+    make_layout(d, L);
+    if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    double *po = nullptr;
+    int nparts = 0;
+    if (d->layout == GLRM_DENSE) {
+        if ((rc = dense_lossgrad(d, L, X, Y, precision, dX, dY, true, ws, st))) return rc;
+        po = at<double>(ws, L.part_obj);
+        nparts = (int)(std::min<int64_t>(P_MAX, std::max<int64_t>(1, L.mp / 16)) * L.cb_grad);
+    } else {
+        if ((rc = coo_grad(d, L.kp, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
+                           precision, dX, dY, &po, &nparts, st)))
+            return rc;
+    }
+    if (obj_host) {
+        double *res = at<double>(ws, L.scal);
+        if ((rc = reg_sums(d, L, X, Y, ws, st))) return rc;
+        HIP_TRY(launch_sum_doubles(po, nparts, at<double>(ws, L.regpart), 2 * REG_BLOCKS, res, st));
+        HIP_TRY(hipMemcpyAsync(obj_host, res, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return GLRM_OK;
+}
+
+int glrm_prox(const glrm_reg *reg, float *V, int64_t rows, int32_t k, int64_t ldv, const float *alpha, void *stream)
+{
+    g_err.clear();
+    if (!reg) return fail(GLRM_EINVAL, "reg is NULL");
+    if (reg->kind < GLRM_REG_ZERO || reg->kind > GLRM_REG_NONNEG) return fail(GLRM_EINVAL, "unknown regularizer kind %d", reg->kind);
+    if (!(reg->weight >= 0.0f) || !std::isfinite(reg->weight)) return fail(GLRM_EINVAL, "regularizer weight must be finite and >= 0");
+    if (rows < 0 || k < 1 || ldv < k) return fail(GLRM_EINVAL, "need rows >= 0, k >= 1, ldv >= k");
+    if (rows > 0 && !V) return fail(GLRM_EINVAL, "V is NULL");
+    HIP_TRY(launch_prox(make_reg(*reg), V, rows, k, ldv, alpha, (hipStream_t)stream));
+    return GLRM_OK;
+}
+
+int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alpha_y, const glrm_fit_opts *o,
+             glrm_fit_info *info, double *history, void *ws, size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    int rc = validate_data(d);
+    if (rc) return rc;
+    if (!X || !Y || !alpha_x || !alpha_y || !o) return fail(GLRM_EINVAL, "X, Y, alpha_x, alpha_y and opts must not be NULL");
+    if (o->max_sweeps < 0) return fail(GLRM_EINVAL, "max_sweeps < 0");
+    if ((rc = check_prec(o->precision, false))) return rc;
+    if (!(o->step_up > 0.0f) || !(o->step_down > 0.0f) || !std::isfinite(o->step_up) || !std::isfinite(o->step_down))
+        return fail(GLRM_EINVAL, "step factors must be finite and > 0");
+    if (o->init_alpha && !(o->alpha_scale > 0.0f && std::isfinite(o->alpha_scale)))
+        return fail(GLRM_EINVAL, "alpha_scale must be finite and > 0");
+    if (!(o->tol >= 0.0)) return fail(GLRM_EINVAL, "tol must be >= 0");
+    Layout L;
+    make_layout(d, L);
+    if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+    const int prec = o->precision;
+    int tpw = 0;
+    if (d->layout == GLRM_DENSE) {
+        tpw = tpw_for(L.ldp / 16);
+        if (tpw == 0 || (L.kp == 64 && tpw > 4))
+            return fail(GLRM_EUNSUPPORTED, "dense fit supports n <= %d for k <= 32 and n <= 512 for k > 32; "
+                        "use the COO layout for wider tables", 16 * NWAVES * 8);
+    } else {
+        if ((rc = coo_fit_supported(d, L.kp, L.cl, prec))) return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (!(o->flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    if (o->init_alpha) {
+        HIP_TRY(launch_init_alpha(at<int32_t>(ws, L.row_count), L.m, o->alpha_scale, alpha_x, st));
+        HIP_TRY(launch_init_alpha(at<int32_t>(ws, L.col_count), L.n, o->alpha_scale, alpha_y, st));
+    }
+    const LossTab lt = make_losstab(d);
+    double *stats = at<double>(ws, L.stats);
+    long long *istats = at<long long>(ws, L.istats);
+    int sweeps = 0;
+    double F_prev = NAN;
+
+    if (d->layout == GLRM_DENSE) {
+        if ((rc = write_shadows(L, Y, ws, prec, true, st))) return rc;
+        const int64_t npanels = L.mp / 16;
+        const int grid = (int)std::min<int64_t>(P_MAX, npanels);
+        XStepArgs xa;
+        xa.m = L.m; xa.mp = L.mp; xa.ldp = L.ldp; xa.k = (int32_t)L.k;
+        xa.Ap = at<float>(ws, L.Ap);
+        xa.codes = at<uint8_t>(ws, L.codes);
+        xa.lt = lt;
+        xa.rx = make_reg(d->rx);
+        xa.X = X;
+        xa.alpha = alpha_x;
+        xa.step_up = o->step_up; xa.step_down = o->step_down;
+        xa.ycur = shadow(ws, L, false);
+        xa.part_dy = at<float>(ws, L.part_dy);
+        xa.part_h = at<float>(ws, L.part_h);
+        xa.part_rowreg = at<float>(ws, L.part_rowreg);
+        xa.part_rej = at<int32_t>(ws, L.part_rej);
+
+        YProxArgs pa;
+        pa.n = L.n; pa.ldp = L.ldp; pa.k = (int32_t)L.k; pa.P = grid;
+        pa.part_dy = xa.part_dy; pa.part_h = xa.part_h;
+        pa.ry = make_reg(d->ry);
+        pa.Y = Y; pa.alpha = alpha_y;
+        pa.Yplus = at<float>(ws, L.Yplus);
+        pa.yplus = shadow(ws, L, true);
+        pa.h_old = at<float>(ws, L.h_old);
+        pa.ry_plus = at<float>(ws, L.ry_plus);
+        pa.ry_old = at<float>(ws, L.ry_old);
+
+        YCheckArgs ca;
+        ca.m = L.m; ca.mp = L.mp; ca.ldp = L.ldp; ca.k = (int32_t)L.k;
+        ca.Ap = xa.Ap; ca.codes = xa.codes; ca.lt = lt; ca.X = X;
+        ca.yplus = pa.yplus;
+        ca.part_hp = at<float>(ws, L.part_hp);
+
+        YAcceptArgs aa;
+        aa.n = L.n; aa.ldp = L.ldp; aa.k = (int32_t)L.k; aa.P = grid;
+        aa.part_hp = ca.part_hp; aa.ry_plus = pa.ry_plus; aa.h_old = pa.h_old;
+        aa.alpha = alpha_y; aa.step_up = o->step_up; aa.step_down = o->step_down;
+        aa.Yplus = pa.Yplus; aa.Y = Y;
+        aa.yplus = pa.yplus; aa.ycur = xa.ycur;
+        aa.part_F = at<double>(ws, L.part_F);
+        aa.part_rejc = at<int32_t>(ws, L.part_rejc);
+        const int ya_blocks = yaccept_blocks(L.n, (int)L.kp);
+
+        FinalizeArgs fa;
+        fa.part_F = aa.part_F; fa.part_rejc = aa.part_rejc; fa.n_colparts = ya_blocks;
+        fa.part_rowreg = xa.part_rowreg; fa.part_rej = xa.part_rej; fa.n_rowparts = grid;
+        fa.stats = stats; fa.istats = istats; fa.history = history;
+
+        for (int t = 0; t < o->max_sweeps; ++t) {
+            HIP_TRY(launch_xstep(xa, (int)L.kp, tpw, prec, grid, st));
+            HIP_TRY(launch_yprox(pa, (int)L.kp, prec, st));
+            HIP_TRY(launch_ycheck(ca, (int)L.kp, tpw, prec, grid, st));
+            HIP_TRY(launch_yaccept(aa, (int)L.kp, prec, ya_blocks, st));
+            fa.sweep = t;
+            HIP_TRY(launch_finalize(fa, st));
+            sweeps = t + 1;
+            if (o->tol > 0.0) {
+                double F;
+                HIP_TRY(hipMemcpyAsync(&F, stats, sizeof(double), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                if (t > 0 && (F_prev - F) <= o->tol * std::fabs(F_prev)) break;
+                F_prev = F;
+            }
+        }
+    } else {
+        rc = coo_fit(d, L.kp, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), lt, X, Y, alpha_x, alpha_y, o,
+                     history, stats, istats, &sweeps, st);
+        if (rc != GLRM_OK) return rc;
+    }
+
+    double *obj64 = at<double>(ws, L.scal) + 1;
+    if ((rc = objective64(d, L, X, Y, ws, obj64, st))) return rc;
+    double hs[2] = {0, 0};
+    long long is[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&hs[0], obj64, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&hs[1], stats, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(is, istats, 2 * sizeof(long long), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (info) {
+        info->sweeps = sweeps;
+        info->objective = hs[0];
+        info->objective_fp32 = sweeps > 0 ? hs[1] : NAN;
+        info->rows_rejected = sweeps > 0 ? is[0] : 0;
+        info->cols_rejected = sweeps > 0 ? is[1] : 0;
+    }
+    return GLRM_OK;
+}
+
+}  // extern "C"

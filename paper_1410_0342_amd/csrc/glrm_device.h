@@ -1,0 +1,234 @@
+// Device-side building blocks of the GLRM sweep on gfx950: losses, their
+// derivatives, regularizers, proximal operators, bfloat16 splitting, the
+// matrix-core fragment products and wavefront reductions.
+//
+// Losses: Section 4 (quadratic eq. qpca, Huber), Section 5.1 (hinge, logistic,
+// ordinal hinge eq. ord-pca).  Regularizers: Section 3.  Proximal operators:
+// definition in Section 7.2.  At a kink the derivative takes the
+// strict-inequality branch (the kink contributes 0).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace glrm {
+
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) short i16x4;
+
+enum { L_QUAD = 0, L_HUBER = 1, L_LOGISTIC = 2, L_HINGE = 3, L_ORDINAL = 4 };
+enum { R_ZERO = 0, R_QUAD = 1, R_L1 = 2, R_NONNEG = 3 };
+enum { P_FP32 = 0, P_BF16 = 1, P_FP64 = 2, P_BF16_PLAIN = 3 };
+
+constexpr int MAX_LOSSES = 16;
+
+// Loss table handed to kernels by value.
+struct LossTab {
+    int32_t kind[MAX_LOSSES];
+    int32_t levels[MAX_LOSSES];
+    float param[MAX_LOSSES];
+    int32_t n;
+    int32_t uniform;   // >= 0: every column uses losses[uniform]; -1: mixed
+};
+
+struct Reg {
+    int32_t kind;
+    float w;
+};
+
+// ---- losses ------------------------------------------------------------------
+
+// Ordinal hinge in closed form.  With c = u - 1 the lower hinges (1 - u + a')_+
+// for a' = 1..a-1 are positive exactly for a' > c; with c2 = u + 1 the upper
+// hinges (1 + u - a')_+ for a' = a+1..d are positive exactly for a' < c2.  Each
+// positive run is an arithmetic series.
+template <typename T>
+__device__ __forceinline__ void ordinal_loss(T u, T a, int d, T &l, T &g, bool want_g)
+{
+    const int ai = (int)a;
+    // lower hinges: a' in [lo, a-1], lo = smallest integer > u - 1, at least 1
+    // only levels 1..d matter, so the integer bounds are taken on clamped values
+    T c = u - T(1);
+    T cc = c < T(-1) ? T(-1) : (c > T(d + 1) ? T(d + 1) : c);
+    int lo = (int)floor(cc) + 1;
+    lo = lo < 1 ? 1 : lo;
+    int n1 = ai - lo;
+    n1 = n1 < 0 ? 0 : n1;
+    // upper hinges: a' in [a+1, hi], hi = largest integer < u + 1, at most d
+    T c2 = u + T(1);
+    T cc2 = c2 < T(0) ? T(0) : (c2 > T(d + 2) ? T(d + 2) : c2);
+    int hi = (int)ceil(cc2) - 1;
+    hi = hi > d ? d : hi;
+    int n2 = hi - ai;
+    n2 = n2 < 0 ? 0 : n2;
+    T s1 = T(n1) * (T(lo + ai - 1) * T(0.5) - c);
+    T s2 = T(n2) * (c2 - T(ai + 1 + hi) * T(0.5));
+    l = s1 + s2;
+    if (want_g) g = T(n2 - n1);
+}
+
+// Loss value and derivative in u, float.
+__device__ __forceinline__ void loss_lg(int kind, int levels, float param, float u, float a, float &l, float &g)
+{
+    switch (kind) {
+    case L_QUAD: {
+        float d = u - a;
+        l = d * d;
+        g = 2.0f * d;
+        break;
+    }
+    case L_HUBER: {
+        float r = u - a, ar = fabsf(r);
+        if (ar <= param) { l = 0.5f * r * r; g = r; }
+        else { l = param * ar - 0.5f * param * param; g = r > 0.0f ? param : -param; }
+        break;
+    }
+    case L_LOGISTIC: {
+        // t = -a u;  l = max(t,0) + log1p(exp(-|t|));  dl/du = -a sigmoid(t)
+        float t = -a * u;
+        float e = __expf(-fabsf(t));
+        float inv = __builtin_amdgcn_rcpf(1.0f + e);
+        l = fmaxf(t, 0.0f) + log1pf(e);
+        float sig = t >= 0.0f ? inv : e * inv;
+        g = -a * sig;
+        break;
+    }
+    case L_HINGE: {
+        float au = a * u;
+        if (au < 1.0f) { l = 1.0f - au; g = -a; }
+        else { l = 0.0f; g = 0.0f; }
+        break;
+    }
+    default: {  // L_ORDINAL
+        ordinal_loss<float>(u, a, levels, l, g, true);
+        break;
+    }
+    }
+}
+
+__device__ __forceinline__ float loss_l(int kind, int levels, float param, float u, float a)
+{
+    switch (kind) {
+    case L_QUAD: {
+        float d = u - a;
+        return d * d;
+    }
+    case L_HUBER: {
+        float r = u - a, ar = fabsf(r);
+        return ar <= param ? 0.5f * r * r : param * ar - 0.5f * param * param;
+    }
+    case L_LOGISTIC: {
+        float t = -a * u;
+        return fmaxf(t, 0.0f) + log1pf(__expf(-fabsf(t)));
+    }
+    case L_HINGE: {
+        float au = a * u;
+        return au < 1.0f ? 1.0f - au : 0.0f;
+    }
+    default: {
+        float l, g;
+        ordinal_loss<float>(u, a, levels, l, g, false);
+        return l;
+    }
+    }
+}
+
+// Double precision loss value (final objective check).
+__device__ __forceinline__ double loss_l64(int kind, int levels, double param, double u, double a)
+{
+    switch (kind) {
+    case L_QUAD: {
+        double d = u - a;
+        return d * d;
+    }
+    case L_HUBER: {
+        double r = u - a, ar = fabs(r);
+        return ar <= param ? 0.5 * r * r : param * ar - 0.5 * param * param;
+    }
+    case L_LOGISTIC: {
+        double t = -a * u;
+        return fmax(t, 0.0) + log1p(exp(-fabs(t)));
+    }
+    case L_HINGE: {
+        double au = a * u;
+        return au < 1.0 ? 1.0 - au : 0.0;
+    }
+    default: {
+        double l, g;
+        ordinal_loss<double>(u, a, levels, l, g, false);
+        return l;
+    }
+    }
+}
+
+// ---- regularizers -------------------------------------------------------------
+
+// One coordinate's share of r(x) (the sum over coordinates is r).
+__device__ __forceinline__ float reg_elem(const Reg &r, float x)
+{
+    switch (r.kind) {
+    case R_QUAD: return r.w * x * x;
+    case R_L1: return r.w * fabsf(x);
+    case R_NONNEG: return x < 0.0f ? __builtin_huge_valf() : 0.0f;
+    default: return 0.0f;
+    }
+}
+
+__device__ __forceinline__ double reg_elem64(const Reg &r, double x)
+{
+    switch (r.kind) {
+    case R_QUAD: return (double)r.w * x * x;
+    case R_L1: return (double)r.w * fabs(x);
+    case R_NONNEG: return x < 0.0 ? __builtin_huge_val() : 0.0;
+    default: return 0.0;
+    }
+}
+
+// prox_{alpha r}(v), coordinate-wise (every supported r is separable).
+__device__ __forceinline__ float prox_elem(const Reg &r, float alpha, float v)
+{
+    switch (r.kind) {
+    case R_QUAD: return v / (1.0f + 2.0f * alpha * r.w);
+    case R_L1: {
+        float t = fabsf(v) - alpha * r.w;
+        return t > 0.0f ? copysignf(t, v) : 0.0f;
+    }
+    case R_NONNEG: return v > 0.0f ? v : 0.0f;
+    default: return v;
+    }
+}
+
+// ---- bfloat16 ----------------------------------------------------------------
+
+__device__ __forceinline__ __bf16 to_bf16(float x) { return (__bf16)x; }
+__device__ __forceinline__ float from_bf16(__bf16 x) { return (float)x; }
+
+// x = hi + lo + O(2^-16 |x|): the two-term split used for z.
+__device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo)
+{
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+
+__device__ __forceinline__ short bf16_bits(__bf16 x) { return __builtin_bit_cast(short, x); }
+
+// ---- wavefront reductions ----------------------------------------------------
+
+template <int WIDTH>
+__device__ __forceinline__ float sum_lanes(float v)
+{
+#pragma unroll
+    for (int o = WIDTH / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int WIDTH>
+__device__ __forceinline__ double sum_lanes64(double v)
+{
+#pragma unroll
+    for (int o = WIDTH / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace glrm

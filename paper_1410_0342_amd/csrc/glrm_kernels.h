@@ -1,0 +1,163 @@
+// Kernel argument blocks and launchers shared by the host driver and the
+// kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "glrm_device.h"
+
+#define GLRM_MAXK_DEV 64
+
+namespace glrm {
+
+// Padded shadows of Y (or of the trial Y+) in the layouts the matrix-core
+// operands want.  Rows are padded to ldp (a multiple of 16), k to kp.
+struct YShadow {
+    float *f32;      // ldp x kp   (FP32 operand rows)
+    float *t32;      // kp x ldp   (FP32, transposed: S3 operand)
+    __bf16 *hi;      // ldp x kp   (bf16 high part)
+    __bf16 *lo;      // ldp x kp   (bf16 low part, split precision)
+    __bf16 *tb;      // kp x ldp   (bf16 high part, transposed: S3 operand)
+};
+
+struct XStepArgs {
+    int64_t m, mp, ldp;
+    int32_t k;
+    const float *Ap;        // mp x ldp, NaN = unobserved
+    const uint8_t *codes;   // ldp
+    LossTab lt;
+    Reg rx;
+    float *X;               // m x k (in/out)
+    float *alpha;           // m (in/out)
+    float step_up, step_down;
+    YShadow ycur;
+    float *part_dy;         // P x ldp x kp
+    float *part_h;          // P x ldp
+    float *part_rowreg;     // P
+    int32_t *part_rej;      // P
+};
+
+struct YProxArgs {
+    int64_t n, ldp;
+    int32_t k, P;
+    const float *part_dy;
+    const float *part_h;
+    Reg ry;
+    const float *Y;         // n x k
+    const float *alpha;     // n
+    float *Yplus;           // n x k
+    YShadow yplus;
+    float *h_old, *ry_plus, *ry_old;  // n
+};
+
+struct YCheckArgs {
+    int64_t m, mp, ldp;
+    int32_t k;
+    const float *Ap;
+    const uint8_t *codes;
+    LossTab lt;
+    const float *X;
+    YShadow yplus;
+    float *part_hp;         // P x ldp
+};
+
+struct YAcceptArgs {
+    int64_t n, ldp;
+    int32_t k, P;
+    const float *part_hp;
+    const float *ry_plus, *h_old;
+    float *alpha;
+    float step_up, step_down;
+    const float *Yplus;
+    float *Y;
+    YShadow yplus, ycur;
+    double *part_F;
+    int32_t *part_rejc;
+};
+
+struct FinalizeArgs {
+    const double *part_F;
+    const int32_t *part_rejc;
+    int32_t n_colparts;
+    const float *part_rowreg;
+    const int32_t *part_rej;
+    int32_t n_rowparts;
+    double *stats;          // [0] = F tracked by the sweep
+    long long *istats;      // [0] rows rejected, [1] columns rejected
+    double *history;        // may be null
+    int32_t sweep;
+};
+
+struct YShadowArgs {
+    int64_t n, ldp;
+    int32_t k;
+    const float *Y;
+    YShadow ys;
+    YShadow yp;             // trial shadows to clear (pointers may be null)
+};
+
+struct LossGradArgs {
+    int64_t m, mp, ldp;
+    int32_t k;
+    const float *Ap;
+    const uint8_t *codes;
+    LossTab lt;
+    const float *X;
+    YShadow ycur;
+    float *dX;              // m x k, written when part_dx is null
+    float *part_dx;         // CB x m x k or null
+    float *part_dy;         // P x ldp x kp
+    double *part_obj;       // P * CB
+};
+
+struct ReduceArgs {
+    int64_t m, n, ldp;
+    int32_t k, P, CB;
+    const float *part_dy;
+    const float *part_dx;
+    float *dY, *dX;
+};
+
+struct Obj64Args {
+    int64_t m, n, mp, ldp;
+    int32_t k;
+    const float *Ap;
+    const uint8_t *codes;
+    LossTab lt;
+    const float *X, *Y;
+    double *part_obj;
+};
+
+struct PackArgs {
+    int64_t m, n, lda, mp, ldp;
+    const float *A;
+    const uint8_t *mask;
+    float *Ap;
+    int32_t *row_count;     // m (zeroed by the kernel itself)
+    int32_t *col_count;     // n (zeroed beforehand)
+};
+
+// ---- launchers (dense.hip) ----
+hipError_t launch_xstep(const XStepArgs &a, int kp, int tpw, int prec, int grid, hipStream_t st);
+hipError_t launch_ycheck(const YCheckArgs &a, int kp, int tpw, int prec, int grid, hipStream_t st);
+hipError_t launch_yprox(const YProxArgs &a, int kp, int prec, hipStream_t st);
+hipError_t launch_yaccept(const YAcceptArgs &a, int kp, int prec, int blocks, hipStream_t st);
+int yaccept_blocks(int64_t n, int kp);
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st);
+hipError_t launch_yshadow(const YShadowArgs &a, int kp, int prec, hipStream_t st);
+hipError_t launch_lossgrad(const LossGradArgs &a, int kp, int tpw, int prec, bool want_grad, int gx, int gy,
+                           hipStream_t st);
+hipError_t launch_reduce_dy(const ReduceArgs &a, int kp, hipStream_t st);
+hipError_t launch_reduce_dx(const ReduceArgs &a, hipStream_t st);
+hipError_t launch_objective64(const Obj64Args &a, int grid, hipStream_t st);
+
+// ---- launchers (common.hip) ----
+hipError_t launch_pack_dense(const PackArgs &a, hipStream_t st);
+hipError_t launch_init_alpha(const int32_t *count, int64_t len, float scale, float *alpha, hipStream_t st);
+hipError_t launch_prox(Reg r, float *V, int64_t rows, int32_t k, int64_t ldv, const float *alpha, hipStream_t st);
+hipError_t launch_regsum(Reg r, const float *V, int64_t rows, int32_t k, double *part, int blocks, hipStream_t st);
+hipError_t launch_sum_doubles(const double *a, int32_t na, const double *b, int32_t nb, double *out, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int64_t len, int32_t v, hipStream_t st);
+
+}  // namespace glrm

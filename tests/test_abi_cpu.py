@@ -1,0 +1,103 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point include/glrm.h declares, and rejects bad arguments before
+any HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1410_0342_amd as g
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "glrm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(glrm_[a-z_0-9]+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(g.library_path())
+    names = _declared()
+    assert {"glrm_objective", "glrm_grad", "glrm_prox", "glrm_fit", "glrm_workspace_size", "glrm_prepare",
+            "glrm_last_error"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _data(**kw):
+    s = g._Data()
+    s.m, s.n, s.k, s.layout = kw.get("m", 10), kw.get("n", 8), kw.get("k", 3), kw.get("layout", g.DENSE)
+    s.A = kw.get("A", 0x1000)
+    s.lda = kw.get("lda", s.n)
+    s.mask = None
+    s.row = kw.get("row", None)
+    s.col = kw.get("col", None)
+    s.nnz = kw.get("nnz", 0)
+    losses = kw.get("losses", [(0, 0, 0.0)])
+    arr = (g._Loss * len(losses))(*[g._Loss(*x) for x in losses])
+    s.losses = ctypes.addressof(arr)
+    s.n_losses = kw.get("n_losses", len(losses))
+    codes = kw.get("col_loss", None)
+    if codes is not None:
+        codes = np.ascontiguousarray(codes, np.uint8)
+        s.col_loss = codes.ctypes.data
+    s.rx = g._Reg(*kw.get("rx", (0, 0.0)))
+    s.ry = g._Reg(*kw.get("ry", (0, 0.0)))
+    return s, (arr, codes)
+
+
+def test_workspace_size_of_a_valid_problem():
+    s, keep = _data(m=1000, n=100, k=20)
+    assert g._L().glrm_workspace_size(ctypes.byref(s)) >= 1000 * 112 * 4
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(m=0), "m and n"),
+    (dict(k=0), "k must be"),
+    (dict(k=65), "GLRM_MAX_K"),
+    (dict(A=None), "A is NULL"),
+    (dict(lda=3), "lda"),
+    (dict(layout=7), "unknown layout"),
+    (dict(layout=1, row=None, col=None), "COO row"),
+    (dict(losses=[(9, 0, 0.0)]), "unknown kind"),
+    (dict(losses=[(1, 0, 0.0)]), "Huber"),
+    (dict(losses=[(4, 1, 0.0)]), "ordinal"),
+    (dict(n_losses=0), "n_losses"),
+    (dict(col_loss=[0, 0, 0, 1, 0, 0, 0, 0]), "col_loss"),
+    (dict(rx=(5, 0.0)), "regularizer"),
+    (dict(ry=(1, -1.0)), "weight"),
+])
+def test_invalid_problems_are_rejected_on_the_host(kw, msg):
+    s, keep = _data(**kw)
+    assert g._L().glrm_workspace_size(ctypes.byref(s)) == 0
+    assert msg in g.glrm_last_error()
+    assert g._L().glrm_prepare(ctypes.byref(s), None, 0, None) in (g.EINVAL, g.EUNSUPPORTED)
+
+
+def test_workspace_checks_before_any_launch():
+    s, keep = _data()
+    assert g._L().glrm_prepare(ctypes.byref(s), None, 0, None) == g.EINVAL
+    assert "workspace is NULL" in g.glrm_last_error()
+    assert g._L().glrm_prepare(ctypes.byref(s), ctypes.c_void_p(0x1001), 1 << 30, None) == g.EINVAL
+    assert "aligned" in g.glrm_last_error()
+    assert g._L().glrm_prepare(ctypes.byref(s), ctypes.c_void_p(0x1000), 16, None) == g.ENOMEM
+
+
+def test_prox_and_fit_argument_errors():
+    r = g._Reg(9, 0.0)
+    assert g._L().glrm_prox(ctypes.byref(r), ctypes.c_void_p(0x1000), 4, 2, 2, None, None) == g.EINVAL
+    r = g._Reg(1, 1.0)
+    assert g._L().glrm_prox(ctypes.byref(r), ctypes.c_void_p(0x1000), 4, 2, 1, None, None) == g.EINVAL
+    s, keep = _data()
+    o = g._FitOpts(5, g.FP64, 1, 1.0, 1.05, 0.7, 0.0, 0)
+    P = ctypes.c_void_p(0x1000)
+    assert g._L().glrm_fit(ctypes.byref(s), P, P, P, P, ctypes.byref(o), None, None, P, 1 << 40, None) == g.EINVAL
+    assert "precision" in g.glrm_last_error()
+    o = g._FitOpts(-1, g.FP32, 1, 1.0, 1.05, 0.7, 0.0, 0)
+    assert g._L().glrm_fit(ctypes.byref(s), P, P, P, P, ctypes.byref(o), None, None, P, 1 << 40, None) == g.EINVAL
+    o = g._FitOpts(5, g.FP32, 1, 1.0, 1.05, 0.7, 0.0, 0)
+    s, keep = _data(n=3000)
+    assert g._L().glrm_fit(ctypes.byref(s), P, P, P, P, ctypes.byref(o), None, None, P, 1 << 40, None) == g.EUNSUPPORTED

@@ -1,0 +1,223 @@
+"""GPU parity of the dense path against the FP64 oracle, through the C ABI.
+
+Tolerances: objective rel. err <= 1e-5 in FP32 and <= 1e-3 in BF16 (split);
+gradients <= 1e-4 rel. (Frobenius) in FP32.  FP64 objectives agree to 1e-10
+(only summation order differs).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import oracle_problem, rel_fro, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1410_0342_amd as g  # noqa: E402
+
+DEV = torch.device("cuda:0")
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+CASES = [
+    dict(m=37, n=23, k=3, seed=1),                      # ragged rows and columns, one tile
+    dict(m=130, n=70, k=5, seed=2, missing=0.4),        # several panels and tiles
+    dict(m=64, n=200, k=12, seed=3),                    # kp = 16, 13 tiles
+    dict(m=300, n=45, k=20, seed=4),                    # kp = 32
+    dict(m=50, n=129, k=40, seed=5),                    # kp = 64
+    dict(m=33, n=17, k=7, seed=6, empty_row=5, empty_col=3),
+]
+
+
+def _case(spec, **kw):
+    spec = dict(spec)
+    spec.update(kw)
+    return synth.small_mixed(spec.pop("m"), spec.pop("n"), spec.pop("k"), **spec)
+
+
+def _setup(case):
+    data = g.Data.from_case(case, DEV)
+    X = to_dev(case.X0, DEV)
+    Y = to_dev(case.Y0, DEV)
+    return data, X, Y, oracle_problem(case)
+
+
+@pytest.mark.parametrize("spec", CASES)
+def test_objective_fp64_matches_oracle(spec):
+    case = _case(spec)
+    data, X, Y, P = _setup(case)
+    ref = P.objective(case.X0, case.Y0)
+    got = g.glrm_objective(data, X, Y, g.FP64)
+    assert got == pytest.approx(ref, rel=1e-10)
+
+
+@pytest.mark.parametrize("spec", CASES)
+@pytest.mark.parametrize("prec,tol", [(g.FP32, 1e-5), (g.BF16, 1e-4), (g.BF16_PLAIN, 3e-2)])
+def test_objective_matches_oracle(spec, prec, tol):
+    case = _case(spec)
+    data, X, Y, P = _setup(case)
+    ref = P.objective(case.X0, case.Y0)
+    got = g.glrm_objective(data, X, Y, prec)
+    assert abs(got - ref) <= tol * abs(ref)
+
+
+@pytest.mark.parametrize("spec", CASES)
+@pytest.mark.parametrize("prec,tol", [(g.FP32, 1e-4), (g.BF16, 2e-2)])
+def test_gradient_matches_oracle(spec, prec, tol):
+    case = _case(spec)
+    data, X, Y, P = _setup(case)
+    dXr, dYr = P.grad(case.X0, case.Y0)
+    dX, dY, obj = g.glrm_grad(data, X, Y, prec, want_objective=True)
+    assert rel_fro(dX.cpu().numpy(), dXr) <= tol
+    assert rel_fro(dY.cpu().numpy(), dYr) <= tol
+    assert obj == pytest.approx(P.objective(case.X0, case.Y0), rel=1e-5 if prec == g.FP32 else 1e-3)
+
+
+def test_gradient_wide_table_uses_column_blocks():
+    """n = 700 > 512 columns per gradient block: partial dX over blocks."""
+    case = synth.small_mixed(90, 700, 8, seed=21, kinds=(0, 2))
+    data, X, Y, P = _setup(case)
+    dXr, dYr = P.grad(case.X0, case.Y0)
+    dX, dY = g.glrm_grad(data, X, Y, g.FP32)
+    assert rel_fro(dX.cpu().numpy(), dXr) <= 1e-4
+    assert rel_fro(dY.cpu().numpy(), dYr) <= 1e-4
+
+
+@pytest.mark.parametrize("kind,w", [(0, 0.0), (1, 0.3), (2, 0.4), (3, 0.0)])
+def test_prox_matches_oracle(kind, w):
+    import oracle
+    rng = np.random.default_rng(kind)
+    V = rng.normal(size=(1000, 7)).astype(np.float32) * 2
+    al = rng.uniform(0.01, 3.0, size=1000).astype(np.float32)
+    Vd = to_dev(V, DEV)
+    g.glrm_prox((kind, w), Vd, to_dev(al, DEV))
+    ref = np.stack([oracle.prox(kind, w, float(al[i]), V[i].astype(np.float64)) for i in range(V.shape[0])])
+    np.testing.assert_allclose(Vd.cpu().numpy(), ref, rtol=2e-6, atol=1e-7)
+
+
+def test_hand_worked_sweeps_on_the_gpu():
+    """The sweeps worked by hand from Algorithm 2 (tests/golden/sweeps.json)."""
+    d = json.load(open(os.path.join(GOLD, "sweeps.json")))
+    for case in d["cases"]:
+        A = np.array(case["A"], dtype=np.float32)
+        m, n = A.shape
+        k = case["k"]
+        mask = None if case["mask"] is None else to_dev(np.array(case["mask"], dtype=np.uint8), DEV)
+        data = g.Data(m, n, k, A=to_dev(A, DEV), mask=mask, col_loss=np.array(case["col_loss"]),
+                      losses=[tuple(x) for x in case["losses"]], rx=tuple(case["rx"]), ry=tuple(case["ry"]))
+        X = to_dev(np.array(case["X0"], dtype=np.float32), DEV)
+        Y = to_dev(np.array(case["Y0"], dtype=np.float32), DEV)
+        ax = torch.empty(m, dtype=torch.float32, device=DEV)
+        ay = torch.empty(n, dtype=torch.float32, device=DEV)
+        for t, exp in enumerate(case["sweeps"]):
+            info = g.glrm_fit(data, X, Y, ax, ay, 1, precision=g.FP32, init_alpha=(t == 0))
+            tag = "%s sweep %d" % (case["name"], t + 1)
+            np.testing.assert_allclose(X.cpu().numpy(), exp["X"], rtol=1e-6, atol=1e-6, err_msg=tag)
+            np.testing.assert_allclose(Y.cpu().numpy(), exp["Y"], rtol=1e-6, atol=1e-6, err_msg=tag)
+            np.testing.assert_allclose(ax.cpu().numpy(), exp["ax"], rtol=1e-6, err_msg=tag)
+            np.testing.assert_allclose(ay.cpu().numpy(), exp["ay"], rtol=1e-6, err_msg=tag)
+            assert info["objective"] == pytest.approx(exp["F"], rel=1e-6), tag
+            assert info["rows_rejected"] == exp["rows_rejected"], tag
+            assert info["cols_rejected"] == exp["cols_rejected"], tag
+
+
+def _ambiguous(fo, fn, rel=2e-5):
+    return np.abs(fn - fo) <= rel * np.maximum(np.abs(fo), 1e-30)
+
+
+@pytest.mark.parametrize("spec", CASES)
+@pytest.mark.parametrize("prec", [g.FP32, g.BF16])
+def test_one_sweep_matches_oracle(spec, prec):
+    """One sweep from an identical state: rows and columns whose accept/reject
+    decision the oracle takes by a clear margin must match; ambiguous ones are
+    excluded (and counted)."""
+    case = _case(spec, rx=(1, 0.1), ry=(2, 0.05))
+    data, X, Y, P = _setup(case)
+    ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
+    ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
+    info = g.glrm_fit(data, X, Y, ax, ay, 1, precision=prec, init_alpha=True, alpha_scale=2.0)
+    Xo = case.X0.astype(np.float64).copy()
+    Yo = case.Y0.astype(np.float64).copy()
+    axo, ayo = P.init_alpha(2.0)
+    rej, fo, fn, accx = P.half_step_x(Xo, Yo, axo)
+    amb_r = _ambiguous(fo, fn)
+    ok_r = ~amb_r
+    tol = 2e-5 if prec == g.FP32 else 2e-3
+    Xg = X.cpu().numpy()
+    np.testing.assert_allclose(Xg[ok_r], Xo[ok_r], rtol=tol, atol=tol * np.abs(Xo).max())
+    np.testing.assert_allclose(ax.cpu().numpy()[ok_r], axo[ok_r], rtol=1e-6)
+    # the Y half-step from the oracle's X^t
+    rej_c, ho, hn, accy = P.half_step_y(Xo, Yo, ayo)
+    amb_c = _ambiguous(ho, hn, 1e-4 if prec == g.FP32 else 5e-3)
+    if amb_r.any():
+        return  # the GPU's X^t differs in an ambiguous row: column comparison no longer like for like
+    ok_c = ~amb_c
+    np.testing.assert_allclose(Y.cpu().numpy()[ok_c], Yo[ok_c], rtol=tol * 5, atol=tol * 5 * np.abs(Yo).max())
+    np.testing.assert_allclose(ay.cpu().numpy()[ok_c], ayo[ok_c], rtol=1e-6)
+    assert info["objective"] == pytest.approx(P.objective(Xo, Yo), rel=1e-5 if prec == g.FP32 else 1e-3)
+
+
+@pytest.mark.parametrize("prec,tol", [(g.FP32, 1e-5), (g.BF16, 1e-3)])
+def test_fit_objective_matches_oracle(prec, tol):
+    case = synth.small_mixed(200, 60, 4, seed=31, missing=0.3)
+    data, X, Y, P = _setup(case)
+    ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
+    ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
+    hist = torch.zeros(30, dtype=torch.float64, device=DEV)
+    info = g.glrm_fit(data, X, Y, ax, ay, 30, precision=prec, history=hist)
+    *_, href, _ = P.fit(case.X0, case.Y0, 30)
+    assert info["sweeps"] == 30
+    assert abs(info["objective"] - href[-1]) <= tol * abs(href[-1])
+    h = hist.cpu().numpy()
+    assert np.all(np.diff(h) <= 1e-5 * np.abs(h[:-1]))
+    assert info["objective"] == pytest.approx(P.objective(X.cpu().numpy(), Y.cpu().numpy()), rel=1e-12)
+
+
+def test_eckart_young_on_the_gpu():
+    """Plain PCA, 200 x 50, k = 5, 500 sweeps: the objective reaches the sum of
+    the trailing squared singular values (Section 2.3)."""
+    case = synth.plain_pca()
+    data, X, Y, P = _setup(case)
+    ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
+    ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
+    info = g.glrm_fit(data, X, Y, ax, ay, case.sweeps, precision=g.FP32)
+    s = np.linalg.svd(case.A.astype(np.float64), compute_uv=False)
+    target = float(np.sum(s[case.k:] ** 2))
+    assert info["objective"] == pytest.approx(target, rel=1e-5)
+
+
+def test_step_sizes_move_by_exact_factors_and_rejected_rows_stay():
+    case = synth.small_mixed(120, 40, 4, seed=41)
+    data, X, Y, P = _setup(case)
+    ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
+    ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
+    g.glrm_fit(data, X, Y, ax, ay, 1, precision=g.FP32, alpha_scale=3.0)
+    for _ in range(4):
+        X0, ax0, ay0, Y0 = X.cpu().numpy(), ax.cpu().numpy(), ay.cpu().numpy(), Y.cpu().numpy()
+        g.glrm_fit(data, X, Y, ax, ay, 1, precision=g.FP32, init_alpha=False)
+        X1, ax1, ay1, Y1 = X.cpu().numpy(), ax.cpu().numpy(), ay.cpu().numpy(), Y.cpu().numpy()
+        up = ax1 == (ax0 * np.float32(1.05)).astype(np.float32)
+        dn = ax1 == (ax0 * np.float32(0.7)).astype(np.float32)
+        assert np.all(up | dn)
+        assert np.array_equal(X1[dn], X0[dn])
+        upc = ay1 == (ay0 * np.float32(1.05)).astype(np.float32)
+        dnc = ay1 == (ay0 * np.float32(0.7)).astype(np.float32)
+        assert np.all(upc | dnc)
+        assert np.array_equal(Y1[dnc], Y0[dnc])
+
+
+def test_fit_is_deterministic():
+    case = synth.small_mixed(150, 90, 6, seed=51)
+    outs = []
+    for _ in range(2):
+        data, X, Y, P = _setup(case)
+        ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
+        ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
+        g.glrm_fit(data, X, Y, ax, ay, 7, precision=g.BF16)
+        outs.append((X.cpu().numpy(), Y.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
