@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the alternating proximal-gradient GLRM sweep on one MI355X.
+
+Workload (default): the dense quadratic GLRM, A = 100,000 x 1,000 = rank-20
+Gaussian product + N(0, 0.1^2) noise, 20% of entries missing at random, rank
+k = 20, quadratic regularizer 0.1 on both factors.  One step is one sweep of
+Algorithm 2 (row half-step, column half-step, objective).  The split-BF16
+matrix-core form and the FP32 form run the same number of sweeps from the same
+seeded start; their final objectives (recomputed in float64 on the GPU) are
+reported side by side.  Printed: one JSON line on stdout.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "xstep_counters_dense_quadratic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("dense.hip", "glrm_device.h", "glrm_kernels.h"):
+        with open(os.path.join(ROOT, "paper_1410_0342_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name):
+    import synth
+    if name == "dense_quadratic":
+        return synth.dense_quadratic()
+    if name == "heterogeneous":
+        return synth.heterogeneous()
+    if name == "sparse_completion":
+        return synth.sparse_completion()
+    if name == "plain_pca":
+        return synth.plain_pca()
+    raise SystemExit("unknown workload " + name)
+
+
+def run_gpu(case, precisions, steps, warmup):
+    import numpy as np
+    import torch
+
+    import paper_1410_0342_amd as g
+
+    dev = torch.device("cuda:0")
+    data = g.Data.from_case(case, dev)
+    g.glrm_prepare(data)
+    torch.cuda.synchronize()
+    nnz = case.nnz
+    out = {}
+    for pname in precisions:
+        prec = g.PRECISIONS[pname]
+        X = torch.from_numpy(case.X0).to(dev)
+        Y = torch.from_numpy(case.Y0).to(dev)
+        ax = torch.empty(case.m, dtype=torch.float32, device=dev)
+        ay = torch.empty(case.n, dtype=torch.float32, device=dev)
+        if warmup > 0:
+            g.glrm_fit(data, X, Y, ax, ay, warmup, precision=prec, init_alpha=True, flags=g.WS_PREPARED)
+        else:
+            g.glrm_fit(data, X, Y, ax, ay, 0, precision=prec, init_alpha=True, flags=g.WS_PREPARED)
+        hist = torch.zeros(max(steps, 1), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = g.glrm_fit(data, X, Y, ax, ay, steps, precision=prec, init_alpha=False,
+                          flags=g.WS_PREPARED | g.TIME_KERNELS, history=hist)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms = (t1 - t0) * 1e3 / max(steps, 1)
+        out[pname] = dict(ms_per_step=ms, value=nnz / (ms * 1e-3), objective=info["objective"],
+                          objective_tracked=info["objective_fp32"], rows_rejected=info["rows_rejected"],
+                          cols_rejected=info["cols_rejected"], kernel_ms=info["kernel_ms"],
+                          kernel_calls=info["kernel_calls"], history_first=float(hist[0]),
+                          history_last=float(hist[steps - 1]) if steps else None)
+        log("%s: %.4f ms/sweep, %.4g entries/s, F = %.10g (tracked %.10g), kernels ms %s"
+            % (pname, ms, out[pname]["value"], info["objective"], info["objective_fp32"],
+               ["%.3f" % v for v in info["kernel_ms"]]))
+        del X, Y, ax, ay
+    return out
+
+
+def copy_calibration():
+    """A plain device copy of known size (for scaling rocprofv3 byte counters)."""
+    import torch
+    src = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy calibration: 5 copies of %d bytes" % (src.numel() * 4))
+
+
+def cpu_baseline(case, rows, sweeps):
+    """The FP64 oracle on the first `rows` rows of the same workload."""
+    import numpy as np
+
+    import oracle
+    sub_mask = None if case.mask is None else case.mask[:rows]
+    P = oracle.Problem.from_dense(case.A[:rows], sub_mask, case.k, case.col_loss, case.losses, case.rx, case.ry)
+    X = case.X0[:rows].astype(np.float64).copy()
+    Y = case.Y0.astype(np.float64).copy()
+    ax, ay = P.init_alpha(1.0)
+    t0 = time.perf_counter()
+    for _ in range(sweeps):
+        P.sweep(X, Y, ax, ay)
+    dt = time.perf_counter() - t0
+    return dict(value=P.nnz * sweeps / dt, unit="entries/s", cores=1, kind="oracle",
+                sample="first %d of %d rows (%d observed entries), %d sweep(s) of the FP64 oracle, "
+                       "single thread, %.1f s" % (rows, case.m, P.nnz, sweeps, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="dense_quadratic",
+                    choices=["dense_quadratic", "heterogeneous", "sparse_completion", "plain_pca"])
+    ap.add_argument("--precision", default="both", choices=["both", "bf16", "fp32", "bf16_plain"])
+    ap.add_argument("--cpu-rows", type=int, default=100000)
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the GLRM sweep here is built and measured on a single MI355X "
+              "(the multi-GPU row sharding is a design in DESIGN.md, not built); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    t0 = time.perf_counter()
+    case = workload(args.workload)
+    log("workload %s: m=%d n=%d k=%d observed=%d (generated in %.1f s)"
+        % (case.name, case.m, case.n, case.k, case.nnz, time.perf_counter() - t0))
+    if case.layout == "coo":
+        precisions = ["fp32"]
+    else:
+        precisions = ["bf16", "fp32"] if args.precision == "both" else [args.precision]
+    res = run_gpu(case, precisions, args.steps, args.warmup)
+    if args.copy_calibration:
+        copy_calibration()
+
+    head = precisions[0]
+    r = res[head]
+    m, n, k = case.m, case.n, case.k
+    # dominant kernel: the fused row pass (kernel kind 0)
+    calls = max(r["kernel_calls"][0], 1)
+    avg_ms = r["kernel_ms"][0] / calls
+    if case.layout == "dense":
+        alg_bytes = 4.0 * m * n + 8.0 * m * k + 8.0 * m
+    else:
+        alg_bytes = 12.0 * case.nnz + 8.0 * m * k + 8.0 * m
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(PROFILE_COUNTERS) and args.workload == "dense_quadratic":
+        try:
+            pc = json.load(open(PROFILE_COUNTERS))
+            if pc.get("kernel_source_hash") == kernel_source_hash() and pc.get("precision") == head:
+                traffic = pc.get("traffic_bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+    line = {
+        "metric": "observed entries/s per prox-grad sweep, bf16-MFMA vs fp32 at equal objective",
+        "value": r["value"],
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16" if head.startswith("bf16") else "f32",
+        "data": "synthetic",
+        "config": {"workload": case.name, "m": m, "n": n, "k": k, "observed_entries": case.nnz,
+                   "layout": case.layout, "precision": head,
+                   "sweeps_timed": args.steps, "sweeps_total": args.steps + args.warmup},
+        "roofline": {"bound": "hbm", "kernel": "xstep (fused row pass)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": alg_bytes},
+        "objective": {p: res[p]["objective"] for p in res},
+    }
+    if "bf16" in res and "fp32" in res:
+        fb, ff = res["bf16"]["objective"], res["fp32"]["objective"]
+        line["equal_objective"] = {"bf16": fb, "fp32": ff, "rel_diff": abs(fb - ff) / abs(ff),
+                                   "within_1e-3": abs(fb - ff) <= 1e-3 * abs(ff)}
+        line["fp32"] = {"value": res["fp32"]["value"], "ms_per_step": res["fp32"]["ms_per_step"]}
+        line["bf16_over_fp32"] = res["bf16"]["value"] / res["fp32"]["value"]
+    line["kernel_ms_per_sweep"] = {p: [v / max(args.steps, 1) for v in res[p]["kernel_ms"]] for p in res}
+    if not args.no_cpu_baseline and case.layout == "dense":
+        rows = min(args.cpu_rows, case.m)
+        line["cpu_baseline"] = cpu_baseline(case, rows, args.cpu_sweeps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

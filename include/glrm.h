@@ -43,7 +43,7 @@ extern "C" {
 /* ---- return codes ----------------------------------------------------------- */
 #define GLRM_OK            0
 #define GLRM_EINVAL       -1  /* null pointer, bad size, bad kind, unsorted / out-of-range COO, bad loss code */
-#define GLRM_EUNSUPPORTED -2  /* valid request outside what is built (e.g. k > 64, dense fit with n > 2048) */
+#define GLRM_EUNSUPPORTED -2  /* valid request outside what is built (e.g. k > 64, dense fit with n > 1024) */
 #define GLRM_ENOMEM       -3  /* workspace smaller than glrm_workspace_size() */
 #define GLRM_EHIP         -4  /* a HIP runtime call failed; the message names it */
 
@@ -78,7 +78,8 @@ enum { GLRM_DENSE = 0, GLRM_COO_ROWSORTED = 1 };
  *              loss, prox, step rule and objective in float32
  *  FP64        float64 throughout (glrm_objective only: the final / convergence check)
  *  BF16_PLAIN  every contraction from one bfloat16 product (fastest, least accurate)
- * For the COO layout the products run on the vector ALUs in the same precisions. */
+ * The COO layout computes its dot products on the vector ALUs in FP32 (FP64 for the
+ * objective); it returns GLRM_EUNSUPPORTED for BF16 and BF16_PLAIN. */
 enum { GLRM_FP32 = 0, GLRM_BF16 = 1, GLRM_FP64 = 2, GLRM_BF16_PLAIN = 3 };
 
 #define GLRM_MAX_LOSSES 16
@@ -124,6 +125,8 @@ typedef struct {
 /* Flags for the compute entry points. */
 #define GLRM_WS_PREPARED 1u   /* `ws` already holds what glrm_prepare() builds for this
                                  exact data (same pointers, sizes and contents); skip it */
+#define GLRM_TIME_KERNELS 2u  /* glrm_fit only: record HIP events on `stream` around every
+                                 kernel launch and report per-kernel totals in glrm_fit_info */
 
 /* Bytes of device workspace any entry point needs for this problem.  The same
  * size serves glrm_prepare, glrm_objective, glrm_grad and glrm_fit, and the
@@ -174,7 +177,7 @@ typedef struct {
     float   step_down;    /* factor after a step that increased it (0.7) */
     double  tol;          /* > 0: stop once (F_prev - F) <= tol * |F_prev| after a sweep
                              (reads F back to the host every sweep); 0: run max_sweeps */
-    uint32_t flags;       /* GLRM_WS_PREPARED */
+    uint32_t flags;       /* GLRM_WS_PREPARED | GLRM_TIME_KERNELS */
 } glrm_fit_opts;
 
 typedef struct {
@@ -183,6 +186,12 @@ typedef struct {
     double  objective_fp32;  /* F after the last sweep as the sweep tracked it (float32 terms) */
     int64_t rows_rejected;   /* rows whose step was rejected in the last sweep */
     int64_t cols_rejected;   /* columns whose step was rejected in the last sweep */
+    /* with GLRM_TIME_KERNELS: summed event time (ms) and launch count per kernel kind.
+     * Dense: [0] fused row pass (X step + column partials), [1] column prox, [2] column
+     * check pass, [3] column accept + objective.  COO: [0] row walk, [1] column walk,
+     * [3] objective. */
+    double  kernel_ms[4];
+    int32_t kernel_calls[4];
 } glrm_fit_info;
 
 /* Run Algorithm 2 (Section 7.2): per sweep, every row takes one proximal

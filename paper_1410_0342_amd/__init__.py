@@ -15,7 +15,7 @@ import numpy as np
 __all__ = [
     "GLRMError", "Data", "glrm_workspace_size", "glrm_prepare", "glrm_objective", "glrm_grad", "glrm_prox",
     "glrm_fit", "glrm_last_error", "library_path", "FP32", "BF16", "FP64", "BF16_PLAIN", "DENSE", "COO_ROWSORTED",
-    "WS_PREPARED",
+    "WS_PREPARED", "TIME_KERNELS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -24,6 +24,7 @@ _LIB_PATH = os.path.join(_HERE, "libglrm.so")
 FP32, BF16, FP64, BF16_PLAIN = 0, 1, 2, 3
 DENSE, COO_ROWSORTED = 0, 1
 WS_PREPARED = 1
+TIME_KERNELS = 2
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp64": FP64, "bf16_plain": BF16_PLAIN}
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
@@ -59,7 +60,8 @@ class _FitOpts(ctypes.Structure):
 
 class _FitInfo(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int32), ("objective", ctypes.c_double), ("objective_fp32", ctypes.c_double),
-                ("rows_rejected", ctypes.c_int64), ("cols_rejected", ctypes.c_int64)]
+                ("rows_rejected", ctypes.c_int64), ("cols_rejected", ctypes.c_int64),
+                ("kernel_ms", ctypes.c_double * 4), ("kernel_calls", ctypes.c_int32 * 4)]
 
 
 _lib = None
@@ -283,4 +285,5 @@ def glrm_fit(data, X, Y, alpha_x, alpha_y, max_sweeps, precision=BF16, init_alph
                          _dev_ptr(history, torch.float64, "history") if history is not None else None,
                          ws, wsb, _stream(stream)))
     return dict(sweeps=info.sweeps, objective=info.objective, objective_fp32=info.objective_fp32,
-                rows_rejected=info.rows_rejected, cols_rejected=info.cols_rejected)
+                rows_rejected=info.rows_rejected, cols_rejected=info.cols_rejected,
+                kernel_ms=list(info.kernel_ms), kernel_calls=list(info.kernel_calls))

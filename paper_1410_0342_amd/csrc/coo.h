@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
+
 #include "../../include/glrm.h"
 #include "glrm_device.h"
 
@@ -44,6 +46,7 @@ int coo_grad(const glrm_data *d, int kp, const CooLayout &cl, char *base, const 
 int coo_fit_supported(const glrm_data *d, int kp, const CooLayout &cl, int prec);
 int coo_fit(const glrm_data *d, int kp, const CooLayout &cl, char *base, const uint8_t *codes, const LossTab &lt,
             float *X, float *Y, float *alpha_x, float *alpha_y, const glrm_fit_opts *o, double *history,
-            double *stats, long long *istats, int *sweeps, hipStream_t st);
+            double *stats, long long *istats, int *sweeps, hipStream_t st,
+            const std::function<hipError_t(int)> &tstart, const std::function<hipError_t()> &tstop);
 
 }  // namespace glrm

@@ -505,7 +505,8 @@ int coo_fit_supported(const glrm_data *d, int kp, const CooLayout &cl, int prec)
 
 int coo_fit(const glrm_data *d, int kp, const CooLayout &cl, char *base, const uint8_t *codes, const LossTab &lt,
             float *X, float *Y, float *alpha_x, float *alpha_y, const glrm_fit_opts *o, double *history,
-            double *stats, long long *istats, int *sweeps, hipStream_t st)
+            double *stats, long long *istats, int *sweeps, hipStream_t st,
+            const std::function<hipError_t(int)> &tstart, const std::function<hipError_t()> &tstop)
 {
     CooPtrs p = ptrs(cl, base);
     int rc = pad_factors(d, kp, p, X, Y, st);
@@ -522,12 +523,18 @@ int coo_fit(const glrm_data *d, int kp, const CooLayout &cl, char *base, const u
     double F_prev = NAN;
     *sweeps = 0;
     for (int t = 0; t < o->max_sweeps; ++t) {
-        hipError_t e = launch_walk<1>(ra, kp, grid_r, st);
+        hipError_t e = tstart(0);
+        if (e == hipSuccess) e = launch_walk<1>(ra, kp, grid_r, st);
+        if (e == hipSuccess) e = tstop();
+        if (e == hipSuccess) e = tstart(1);
         if (e == hipSuccess) e = launch_walk<1>(ca, kp, grid_c, st);
+        if (e == hipSuccess) e = tstop();
+        if (e == hipSuccess) e = tstart(3);
         if (e != hipSuccess) return set_error(GLRM_EHIP, "COO sweep: %s", hipGetErrorString(e));
         // F = decided column objectives (loss + rt) + r of the decided rows
         hipLaunchKernelGGL(coo_finalize_kernel, dim3(1), dim3(256), 0, st, p.partB, p.ipartB, grid_c * CW, p.partA,
                            p.ipartA, grid_r * CW, stats, istats, history, t);
+        if ((e = tstop()) != hipSuccess) return set_error(GLRM_EHIP, "COO timing: %s", hipGetErrorString(e));
         if ((e = hipGetLastError()) != hipSuccess) return set_error(GLRM_EHIP, "COO finalize: %s", hipGetErrorString(e));
         *sweeps = t + 1;
         if (o->tol > 0.0) {

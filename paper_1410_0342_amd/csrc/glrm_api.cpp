@@ -8,6 +8,7 @@
 #include <cstring>
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "../../include/glrm.h"
 #include "glrm_kernels.h"
@@ -322,6 +323,52 @@ int dense_lossgrad(const glrm_data *d, const Layout &L, const float *X, const fl
     return GLRM_OK;
 }
 
+// Optional per-kernel event timing of a fit (GLRM_TIME_KERNELS).
+struct KernelTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    size_t used = 0;
+    int init(bool enable, size_t launches)
+    {
+        on = enable;
+        if (!on) return GLRM_OK;
+        ev.resize(2 * launches);
+        kind.resize(launches);
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(GLRM_EHIP, "hipEventCreate failed");
+        return GLRM_OK;
+    }
+    hipError_t start(int k, hipStream_t st)
+    {
+        if (!on || used >= kind.size()) return hipSuccess;
+        kind[used] = k;
+        return hipEventRecord(ev[2 * used], st);
+    }
+    hipError_t stop(hipStream_t st)
+    {
+        if (!on || used >= kind.size()) return hipSuccess;
+        hipError_t e = hipEventRecord(ev[2 * used + 1], st);
+        ++used;
+        return e;
+    }
+    void report(glrm_fit_info *info)
+    {
+        if (!on) return;
+        for (size_t i = 0; i < used; ++i) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess && info) {
+                info->kernel_ms[kind[i]] += ms;
+                info->kernel_calls[kind[i]] += 1;
+            }
+        }
+    }
+    ~KernelTimer()
+    {
+        for (auto &e : ev) hipEventDestroy(e);
+    }
+};
+
 int check_prec(int prec, bool allow64)
 {
     if (prec == GLRM_FP32 || prec == GLRM_BF16 || prec == GLRM_BF16_PLAIN) return GLRM_OK;
@@ -479,6 +526,9 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
         if ((rc = coo_fit_supported(d, L.kp, L.cl, prec))) return rc;
     }
     hipStream_t st = (hipStream_t)stream;
+    if (info) memset(info, 0, sizeof *info);
+    KernelTimer timer;
+    if ((rc = timer.init((o->flags & GLRM_TIME_KERNELS) != 0, (size_t)o->max_sweeps * 4))) return rc;
     if (!(o->flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
     if (o->init_alpha) {
         HIP_TRY(launch_init_alpha(at<int32_t>(ws, L.row_count), L.m, o->alpha_scale, alpha_x, st));
@@ -542,12 +592,20 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
         fa.stats = stats; fa.istats = istats; fa.history = history;
 
         for (int t = 0; t < o->max_sweeps; ++t) {
+            HIP_TRY(timer.start(0, st));
             HIP_TRY(launch_xstep(xa, (int)L.kp, tpw, prec, grid, st));
+            HIP_TRY(timer.stop(st));
+            HIP_TRY(timer.start(1, st));
             HIP_TRY(launch_yprox(pa, (int)L.kp, prec, st));
+            HIP_TRY(timer.stop(st));
+            HIP_TRY(timer.start(2, st));
             HIP_TRY(launch_ycheck(ca, (int)L.kp, tpw, prec, grid, st));
+            HIP_TRY(timer.stop(st));
+            HIP_TRY(timer.start(3, st));
             HIP_TRY(launch_yaccept(aa, (int)L.kp, prec, ya_blocks, st));
             fa.sweep = t;
             HIP_TRY(launch_finalize(fa, st));
+            HIP_TRY(timer.stop(st));
             sweeps = t + 1;
             if (o->tol > 0.0) {
                 double F;
@@ -559,7 +617,8 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
         }
     } else {
         rc = coo_fit(d, L.kp, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), lt, X, Y, alpha_x, alpha_y, o,
-                     history, stats, istats, &sweeps, st);
+                     history, stats, istats, &sweeps, st,
+                     [&](int k) { return timer.start(k, st); }, [&]() { return timer.stop(st); });
         if (rc != GLRM_OK) return rc;
     }
 
@@ -571,6 +630,7 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
     HIP_TRY(hipMemcpyAsync(&hs[1], stats, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(is, istats, 2 * sizeof(long long), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    timer.report(info);
     if (info) {
         info->sweeps = sweeps;
         info->objective = hs[0];
