@@ -131,7 +131,10 @@ class Problem:
     ``(kind, levels, param)``; ``rx`` / ``ry`` are ``(kind, weight)``.
     """
 
-    def __init__(self, m, n, k, rows, cols, vals, col_loss, losses, rx, ry):
+    def __init__(self, m, n, k, rows, cols, vals, col_loss, losses, rx, ry, col_order=None, row_sorted=False):
+        """rows / cols / vals list the observed entries.  ``row_sorted`` says they
+        are already ordered by (row, column); ``col_order`` optionally gives the
+        permutation that orders them by (column, row)."""
         self.m, self.n, self.k = int(m), int(n), int(k)
         self.rx, self.ry = (int(rx[0]), float(rx[1])), (int(ry[0]), float(ry[1]))
         self.losses = list(losses)
@@ -141,14 +144,16 @@ class Problem:
         vals = np.asarray(vals, dtype=np.float64)
         ecode = np.asarray(col_loss, dtype=np.uint8)[cols]
         # row view: entries ordered by (row, column)
-        o = np.lexsort((cols, rows))
+        o = None if row_sorted else np.lexsort((cols, rows))
+        pick = (lambda a: a) if o is None else (lambda a: a[o])
         rp = np.zeros(self.m + 1, dtype=np.int64)
-        np.add.at(rp, rows + 1, 1)
-        self.row = _View(self.m, self.n, self.k, np.cumsum(rp), cols[o], vals[o], ecode[o], self._loss_arr)
+        np.add.at(rp, rows + 1, 1) if rows.size < (1 << 22) else rp.__setitem__(
+            slice(1, None), np.bincount(rows, minlength=self.m))
+        self.row = _View(self.m, self.n, self.k, np.cumsum(rp), pick(cols), pick(vals), pick(ecode), self._loss_arr)
         # transposed view for the column half-step: ordered by (column, row)
-        o = np.lexsort((rows, cols))
+        o = np.lexsort((rows, cols)) if col_order is None else col_order
         cp = np.zeros(self.n + 1, dtype=np.int64)
-        np.add.at(cp, cols + 1, 1)
+        cp[1:] = np.bincount(cols, minlength=self.n)
         self.colv = _View(self.n, self.m, self.k, np.cumsum(cp), rows[o], vals[o], ecode[o], self._loss_arr)
         self.nnz = int(rows.size)
 
@@ -157,14 +162,29 @@ class Problem:
         A = np.asarray(A)
         m, n = A.shape
         if mask is None:
-            rows, cols = np.divmod(np.arange(m * n, dtype=np.int64), n)
+            flat = np.arange(m * n, dtype=np.int64)
+            rows, cols = np.divmod(flat, n)
+            colflat = np.arange(m * n, dtype=np.int64)
+            cj, ci = np.divmod(colflat, m)           # column-major walk
+            order = ci * n + cj                      # position of (ci, cj) in the row-major list
         else:
-            rows, cols = np.nonzero(np.asarray(mask))
-        return cls(m, n, k, rows, cols, A[rows, cols], col_loss, losses, rx, ry)
+            mask = np.asarray(mask).astype(bool, copy=False)
+            rows, cols = np.nonzero(mask)
+            # entries in column-major order, as positions in the row-major list
+            rank = np.zeros(mask.shape, dtype=np.int64)
+            rank[rows, cols] = np.arange(rows.size, dtype=np.int64)
+            cj, ci = np.nonzero(mask.T)
+            order = rank[ci, cj]
+            del rank
+        return cls(m, n, k, rows, cols, A[rows, cols], col_loss, losses, rx, ry, col_order=order, row_sorted=True)
 
     @classmethod
     def from_coo(cls, m, n, k, rows, cols, vals, col_loss, losses, rx, ry):
-        return cls(m, n, k, rows, cols, vals, col_loss, losses, rx, ry)
+        rows = np.asarray(rows, dtype=np.int64)
+        cols = np.asarray(cols, dtype=np.int64)
+        row_sorted = bool(rows.size < 2 or np.all((rows[1:] > rows[:-1]) | ((rows[1:] == rows[:-1]) & (cols[1:] > cols[:-1]))))
+        order = np.argsort(cols, kind="stable") if row_sorted else None
+        return cls(m, n, k, rows, cols, vals, col_loss, losses, rx, ry, col_order=order, row_sorted=row_sorted)
 
     # ---- the method ----------------------------------------------------------
     def objective(self, X, Y):

@@ -274,13 +274,26 @@ __global__ __launch_bounds__(NT, 1) void xstep_kernel(XStepArgs a)
         f32x4 dx[KP / 16];
 #pragma unroll
         for (int kb = 0; kb < KP / 16; ++kb) dx[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        {
+            // all of this wavefront's table loads in flight at once, then staged in LDS
+            // tiles past the last one re-load the last tile (in bounds, never used)
+            const float *arow = a.Ap + (i0 + li) * a.ldp + 4 * g;
+            const int nt = (int)ntiles;
+            float4 areg[TPW];
+#pragma unroll
+            for (int s = 0; s < TPW; ++s) {
+                const int t = min(w + NW * s, nt - 1);
+                areg[s] = *reinterpret_cast<const float4 *>(arow + 16 * t);
+            }
+#pragma unroll
+            for (int s = 0; s < TPW; ++s) apan[s * 64 + lane] = areg[s];
+        }
 #pragma unroll 2
         for (int s = 0; s < TPW; ++s) {
             const int64_t t = w + NW * s;
             if (t < ntiles) {
                 const int64_t j0 = 16 * t;
-                const float4 av = *reinterpret_cast<const float4 *>(a.Ap + (i0 + li) * a.ldp + j0 + 4 * g);
-                apan[s * 64 + lane] = av;
+                const float4 av = apan[s * 64 + lane];
                 Frag<KP, PREC> yf;
                 frag_load_y<KP, PREC>(yf, a.ycur, j0 + li, g);
                 const f32x4 z = zprod<KP, PREC>(yf, xf);
