@@ -77,16 +77,22 @@ def test_one_sweep_matches_oracle(spec):
     assert info["objective"] == pytest.approx(P.objective(Xo, Yo), rel=1e-5)
 
 
-def test_fit_objective_matches_oracle_and_never_increases():
-    case = synth.small_mixed(400, 150, 6, seed=31, missing=0.8, layout="coo")
+def test_fit_reaches_the_oracles_converged_objective():
+    """Smooth convex losses + quadratic regularizers on a sparse pattern: the
+    converged objectives agree, the first sweeps agree, F never increases."""
+    case = synth.small_mixed(400, 150, 6, seed=31, missing=0.8, layout="coo", kinds=(0, 1, 2), rx=(1, 0.5),
+                             ry=(1, 0.5))
     data, X, Y, P = _setup(case)
+    T = 1500
     ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
     ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
-    hist = torch.zeros(30, dtype=torch.float64, device=DEV)
-    info = g.glrm_fit(data, X, Y, ax, ay, 30, precision=g.FP32, history=hist)
-    *_, href, _ = P.fit(case.X0, case.Y0, 30)
+    hist = torch.zeros(T, dtype=torch.float64, device=DEV)
+    info = g.glrm_fit(data, X, Y, ax, ay, T, precision=g.FP32, history=hist)
+    *_, href, _ = P.fit(case.X0, case.Y0, T)
+    assert abs(href[-1] - href[-50]) <= 1e-9 * abs(href[-1])
     assert abs(info["objective"] - href[-1]) <= 1e-5 * abs(href[-1])
     h = hist.cpu().numpy()
+    np.testing.assert_allclose(h[:2], href[:2], rtol=1e-5)
     assert np.all(np.diff(h) <= 1e-5 * np.abs(h[:-1]))
     assert h[-1] == pytest.approx(info["objective"], rel=1e-5)
 

@@ -133,47 +133,59 @@ def _ambiguous(fo, fn, rel=2e-5):
 @pytest.mark.parametrize("spec", CASES)
 @pytest.mark.parametrize("prec", [g.FP32, g.BF16])
 def test_one_sweep_matches_oracle(spec, prec):
-    """One sweep from an identical state: rows and columns whose accept/reject
-    decision the oracle takes by a clear margin must match; ambiguous ones are
-    excluded (and counted)."""
+    """One sweep from an identical state.  Rows and columns whose accept /
+    reject decision the oracle takes by a clear margin must match; ambiguous
+    ones are excluded.  FP32: element-wise.  BF16: the gradient contractions
+    use one bfloat16 product, so the step x+ - x carries a relative error of
+    order 2^-8; it is compared as a step, in Frobenius norm."""
     case = _case(spec, rx=(1, 0.1), ry=(2, 0.05))
     data, X, Y, P = _setup(case)
     ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
     ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
     info = g.glrm_fit(data, X, Y, ax, ay, 1, precision=prec, init_alpha=True, alpha_scale=2.0)
-    Xo = case.X0.astype(np.float64).copy()
-    Yo = case.Y0.astype(np.float64).copy()
+    X0, Y0 = case.X0.astype(np.float64), case.Y0.astype(np.float64)
+    Xo, Yo = X0.copy(), Y0.copy()
     axo, ayo = P.init_alpha(2.0)
     rej, fo, fn, accx = P.half_step_x(Xo, Yo, axo)
-    amb_r = _ambiguous(fo, fn)
+    amb_r = _ambiguous(fo, fn, 2e-5 if prec == g.FP32 else 2e-3)
     ok_r = ~amb_r
-    tol = 2e-5 if prec == g.FP32 else 2e-3
     Xg = X.cpu().numpy()
-    np.testing.assert_allclose(Xg[ok_r], Xo[ok_r], rtol=tol, atol=tol * np.abs(Xo).max())
     np.testing.assert_allclose(ax.cpu().numpy()[ok_r], axo[ok_r], rtol=1e-6)
-    # the Y half-step from the oracle's X^t
+    if prec == g.FP32:
+        np.testing.assert_allclose(Xg[ok_r], Xo[ok_r], rtol=2e-5, atol=2e-5 * np.abs(Xo).max())
+    else:
+        assert rel_fro((Xg - X0)[ok_r], (Xo - X0)[ok_r]) <= 2e-2
     rej_c, ho, hn, accy = P.half_step_y(Xo, Yo, ayo)
-    amb_c = _ambiguous(ho, hn, 1e-4 if prec == g.FP32 else 5e-3)
     if amb_r.any():
-        return  # the GPU's X^t differs in an ambiguous row: column comparison no longer like for like
-    ok_c = ~amb_c
-    np.testing.assert_allclose(Y.cpu().numpy()[ok_c], Yo[ok_c], rtol=tol * 5, atol=tol * 5 * np.abs(Yo).max())
+        return  # the GPU's X^t differs in an ambiguous row: columns no longer like for like
+    ok_c = ~_ambiguous(ho, hn, 1e-4 if prec == g.FP32 else 5e-3)
+    Yg = Y.cpu().numpy()
     np.testing.assert_allclose(ay.cpu().numpy()[ok_c], ayo[ok_c], rtol=1e-6)
+    if prec == g.FP32:
+        np.testing.assert_allclose(Yg[ok_c], Yo[ok_c], rtol=1e-4, atol=1e-4 * np.abs(Yo).max())
+    else:
+        assert rel_fro((Yg - Y0)[ok_c], (Yo - Y0)[ok_c]) <= 5e-2
     assert info["objective"] == pytest.approx(P.objective(Xo, Yo), rel=1e-5 if prec == g.FP32 else 1e-3)
 
 
-@pytest.mark.parametrize("prec,tol", [(g.FP32, 1e-5), (g.BF16, 1e-3)])
-def test_fit_objective_matches_oracle(prec, tol):
-    case = synth.small_mixed(200, 60, 4, seed=31, missing=0.3)
+@pytest.mark.parametrize("prec,tol", [(g.FP32, 1e-5), (g.BF16, 1e-4)])
+def test_fit_reaches_the_oracles_converged_objective(prec, tol):
+    """Smooth convex losses with quadratic regularizers: after enough sweeps
+    both the GPU and the oracle have converged (the oracle's last sweeps change
+    F by < 1e-9 relative), and the objectives agree.  The first sweeps, before
+    any near-tie decision can separate the trajectories, agree closely too."""
+    case = synth.small_mixed(200, 60, 4, seed=31, missing=0.3, kinds=(0, 1, 2), rx=(1, 0.5), ry=(1, 0.5))
     data, X, Y, P = _setup(case)
+    T = 1500
     ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
     ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
-    hist = torch.zeros(30, dtype=torch.float64, device=DEV)
-    info = g.glrm_fit(data, X, Y, ax, ay, 30, precision=prec, history=hist)
-    *_, href, _ = P.fit(case.X0, case.Y0, 30)
-    assert info["sweeps"] == 30
+    hist = torch.zeros(T, dtype=torch.float64, device=DEV)
+    info = g.glrm_fit(data, X, Y, ax, ay, T, precision=prec, history=hist)
+    *_, href, _ = P.fit(case.X0, case.Y0, T)
+    assert abs(href[-1] - href[-50]) <= 1e-9 * abs(href[-1])
     assert abs(info["objective"] - href[-1]) <= tol * abs(href[-1])
     h = hist.cpu().numpy()
+    np.testing.assert_allclose(h[:2], href[:2], rtol=1e-5 if prec == g.FP32 else 1e-3)
     assert np.all(np.diff(h) <= 1e-5 * np.abs(h[:-1]))
     assert info["objective"] == pytest.approx(P.objective(X.cpu().numpy(), Y.cpu().numpy()), rel=1e-12)
 
