@@ -9,15 +9,19 @@ ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build", "glrm")
 LIB = os.path.join(HERE, "libglrm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["glrm_api.cpp", "common.hip", "dense.hip", "coo.hip"]
+# (source, extra flags, object name): dense_prec.hip is built once per precision
+SOURCES = [("glrm_api.cpp", [], "glrm_api"), ("common.hip", [], "common"), ("dense.hip", [], "dense"),
+           ("coo.hip", [], "coo")] + [("dense_prec.hip", ["-DGLRM_PREC=%d" % p], "dense_prec%d" % p) for p in (0, 1, 3)]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-pragma-unroll-threshold=1000000",
          "-I" + os.path.join(ROOT, "include")]
 
 
-def _compile(src):
-    out = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
+def _compile(item):
+    src, extra, name = item
+    out = os.path.join(BUILD, name + ".o")
+    cmd = [HIPCC] + FLAGS + extra + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     err = "\n".join(l for l in (r.stderr or "").splitlines() if noise not in l)

@@ -1,0 +1,965 @@
+// Dense-layout kernels of the GLRM sweep for gfx950 (templates; instantiated
+// per precision in dense_prec.hip).
+//
+// The table sits in the workspace as a padded copy (rows to a multiple of 16,
+// columns to a multiple of 16) in which every unobserved entry is a quiet NaN,
+// so one 4-byte load gives both the value and the observation bit.
+//
+// Work decomposition: a workgroup of 8 wavefronts walks 16-row panels.  The
+// panel's columns are cut into 16-wide tiles and tile t belongs to wavefront
+// t mod 8 for the whole launch, so each wavefront can keep per-column
+// accumulators (column objective, Y gradient) in registers across panels.
+//
+// Matrix-core products per 16 x 16 tile (i = row of the panel, j = column):
+//   z     Z^T(16j x 16i) = Y_tile(16j x kp) . X_panel^T        -> lane holds z(i=l%16, j=4(l/16)+r)
+//   S3    dX(16i x 16kc) += G(16i x 16j) . Y_tile(16j x 16kc)   (G straight from the z layout)
+//   S6    dY(16j x 16kc) += G^T(16j x 16i) . X(16i x 16kc)      (G transposed through LDS)
+// The k index each lane feeds is a free choice as long as both operands use
+// the same one: lane group g = l/16 feeds the contiguous run k = g*kp/4 ...
+// (g+1)*kp/4 - 1, which makes every operand load one contiguous vector.
+#pragma once
+
+#include "glrm_device.h"
+#include "glrm_kernels.h"
+
+namespace glrm {
+
+constexpr int NW = 8;            // wavefronts per workgroup
+constexpr int NT = NW * 64;      // threads per workgroup
+constexpr int GS = 20;           // row stride (floats) of the per-wave transpose tile
+
+// ---------------------------------------------------------------------------
+// operand fragments
+// ---------------------------------------------------------------------------
+template <int KP, int PREC>
+struct Frag {
+    // lane group g's run of kp/4 coordinates, packed: fp32 values, or bf16
+    // high / low parts in vectors of eight (four at kp = 16)
+    static constexpr int C = KP / 4;
+    static constexpr int NV = C >= 8 ? C / 8 : 1;
+    float f[PREC == P_FP32 ? C : 1];
+    bf16x8 hi[PREC == P_FP32 ? 1 : NV];
+    bf16x8 lo[PREC == P_BF16 ? NV : 1];
+};
+
+// From fp32 values (LDS panel row or registers).
+template <int KP, int PREC>
+__device__ __forceinline__ void frag_from_f32(Frag<KP, PREC> &fr, const float *src)
+{
+#pragma unroll
+    for (int q = 0; q < KP / 4; ++q) {
+        const float v = src[q];
+        if constexpr (PREC == P_FP32) {
+            fr.f[q] = v;
+        } else if constexpr (PREC == P_BF16) {
+            __bf16 h, l;
+            split_bf16(v, h, l);
+            fr.hi[q / 8][q % 8] = h;
+            fr.lo[q / 8][q % 8] = l;
+        } else {
+            fr.hi[q / 8][q % 8] = to_bf16(v);
+        }
+    }
+}
+
+// Row j of a padded shadow of Y (or Y+) in global memory, lane group g's run.
+template <int KP, int PREC>
+__device__ __forceinline__ void frag_load_y(Frag<KP, PREC> &fr, const YShadow &ys, int64_t j, int g)
+{
+    constexpr int C = KP / 4;
+    if constexpr (PREC == P_FP32) {
+        const float4 *p = reinterpret_cast<const float4 *>(ys.f32 + j * KP + g * C);
+#pragma unroll
+        for (int q = 0; q < C / 4; ++q) {
+            float4 v = p[q];
+            fr.f[4 * q + 0] = v.x; fr.f[4 * q + 1] = v.y; fr.f[4 * q + 2] = v.z; fr.f[4 * q + 3] = v.w;
+        }
+    } else {
+        const __bf16 *ph = ys.hi + j * KP + g * C;
+        const __bf16 *pl = ys.lo + j * KP + g * C;
+        if constexpr (C == 4) {
+            uint2 h = *reinterpret_cast<const uint2 *>(ph);
+            uint4 hv = {h.x, h.y, 0u, 0u};
+            fr.hi[0] = __builtin_bit_cast(bf16x8, hv);
+            if constexpr (PREC == P_BF16) {
+                uint2 l = *reinterpret_cast<const uint2 *>(pl);
+                uint4 lv = {l.x, l.y, 0u, 0u};
+                fr.lo[0] = __builtin_bit_cast(bf16x8, lv);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < C / 8; ++q) {
+                fr.hi[q] = __builtin_bit_cast(bf16x8, reinterpret_cast<const uint4 *>(ph)[q]);
+                if constexpr (PREC == P_BF16)
+                    fr.lo[q] = __builtin_bit_cast(bf16x8, reinterpret_cast<const uint4 *>(pl)[q]);
+            }
+        }
+    }
+}
+
+// Z^T tile = Y_tile . X_panel^T.  Split bf16: the two small cross terms first.
+template <int KP>
+__device__ __forceinline__ f32x4 mfma_vec(const bf16x8 *a, const bf16x8 *b, f32x4 acc)
+{
+    if constexpr (KP == 16) {
+        const uint4 av = __builtin_bit_cast(uint4, a[0]), bv = __builtin_bit_cast(uint4, b[0]);
+        const uint2 a2 = {av.x, av.y}, b2 = {bv.x, bv.y};
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(i16x4, a2), __builtin_bit_cast(i16x4, b2),
+                                                         acc, 0, 0, 0);
+    } else {
+#pragma unroll
+        for (int q = 0; q < KP / 32; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[q], b[q], acc, 0, 0, 0);
+        return acc;
+    }
+}
+
+template <int KP, int PREC>
+__device__ __forceinline__ f32x4 zprod(const Frag<KP, PREC> &y, const Frag<KP, PREC> &x)
+{
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (PREC == P_FP32) {
+#pragma unroll
+        for (int q = 0; q < KP / 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(y.f[q], x.f[q], acc, 0, 0, 0);
+    } else {
+        if constexpr (PREC == P_BF16) {
+            acc = mfma_vec<KP>(y.lo, x.hi, acc);
+            acc = mfma_vec<KP>(y.hi, x.lo, acc);
+        }
+        acc = mfma_vec<KP>(y.hi, x.hi, acc);
+    }
+    return acc;
+}
+
+// S3: dX block kb (16 rows x 16 of k) += G(16i x 16j) . Y_tile(16j x 16kc).
+// G[r] = G(i = l%16, j = 4g + r).  Y^T shadow row kc holds y_j for all j.
+template <int KP, int PREC>
+__device__ __forceinline__ void s3_accum(f32x4 (&dx)[KP / 16], const float (&G)[4], const YShadow &ys,
+                                         int64_t ldp, int64_t j0, int li, int g)
+{
+#pragma unroll
+    for (int kb = 0; kb < KP / 16; ++kb) {
+        const int64_t off = (int64_t)(16 * kb + li) * ldp + j0 + 4 * g;
+        if constexpr (PREC == P_FP32) {
+            float4 b = *reinterpret_cast<const float4 *>(ys.t32 + off);
+            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[0], b.x, dx[kb], 0, 0, 0);
+            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[1], b.y, dx[kb], 0, 0, 0);
+            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[2], b.z, dx[kb], 0, 0, 0);
+            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[3], b.w, dx[kb], 0, 0, 0);
+        } else {
+            i16x4 av, bv;
+            *reinterpret_cast<uint2 *>(&bv) = *reinterpret_cast<const uint2 *>(ys.tb + off);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) av[s] = bf16_bits(to_bf16(G[s]));
+            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, dx[kb], 0, 0, 0);
+        }
+    }
+}
+
+// S6: dY block (16 j x 16 kc) += G^T(16j x 16i) . X(16i x 16kc).  gT[s] =
+// G(i = 4g + s, j = l%16); xat is the panel's X transposed in LDS ([kc][i]).
+template <int KP, int PREC>
+__device__ __forceinline__ void s6_accum(f32x4 (&dy)[KP / 16], const float (&gT)[4], const float *xat, int li, int g)
+{
+#pragma unroll
+    for (int kb = 0; kb < KP / 16; ++kb) {
+        float4 b = *reinterpret_cast<const float4 *>(xat + (16 * kb + li) * GS + 4 * g);
+        if constexpr (PREC == P_FP32) {
+            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gT[0], b.x, dy[kb], 0, 0, 0);
+            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gT[1], b.y, dy[kb], 0, 0, 0);
+            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gT[2], b.z, dy[kb], 0, 0, 0);
+            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gT[3], b.w, dy[kb], 0, 0, 0);
+        } else {
+            i16x4 av, bv;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) av[s] = bf16_bits(to_bf16(gT[s]));
+            bv[0] = bf16_bits(to_bf16(b.x)); bv[1] = bf16_bits(to_bf16(b.y));
+            bv[2] = bf16_bits(to_bf16(b.z)); bv[3] = bf16_bits(to_bf16(b.w));
+            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, dy[kb], 0, 0, 0);
+        }
+    }
+}
+
+// Transpose the wave's 16x16 G tile through LDS.
+__device__ __forceinline__ void transpose_g(float *gsc, const float (&G)[4], float (&gT)[4], int li, int g)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gsc[(4 * g + r) * GS + li] = G[r];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float4 v = *reinterpret_cast<const float4 *>(gsc + li * GS + 4 * g);
+    gT[0] = v.x; gT[1] = v.y; gT[2] = v.z; gT[3] = v.w;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Loss codes of the lane's four columns.
+__device__ __forceinline__ void load_codes(const uint8_t *codes, int64_t j, int (&cd)[4])
+{
+    uchar4 c = *reinterpret_cast<const uchar4 *>(codes + j);
+    cd[0] = c.x; cd[1] = c.y; cd[2] = c.z; cd[3] = c.w;
+}
+
+__device__ __forceinline__ void entry_lg(const LossTab &lt, int code, float u, float a, float &l, float &gr)
+{
+    const int q = lt.uniform >= 0 ? lt.uniform : code;
+    loss_lg(lt.kind[q], lt.levels[q], lt.param[q], u, a, l, gr);
+}
+
+__device__ __forceinline__ float entry_l(const LossTab &lt, int code, float u, float a)
+{
+    const int q = lt.uniform >= 0 ? lt.uniform : code;
+    return loss_l(lt.kind[q], lt.levels[q], lt.param[q], u, a);
+}
+
+// Load the 16 x k panel of a factor into LDS as fp32 [16][KP] (zero padded).
+template <int KP>
+__device__ __forceinline__ void load_panel(float (*xs)[KP], const float *X, int64_t i0, int64_t m, int k)
+{
+    for (int t = threadIdx.x; t < 16 * KP; t += NT) {
+        const int i = t / KP, c = t % KP;
+        const int64_t gi = i0 + i;
+        xs[i][c] = (gi < m && c < k) ? X[gi * k + c] : 0.0f;
+    }
+}
+
+// The two passes over the table run four wavefronts per workgroup, one per
+// SIMD, so each wavefront may hold up to 512 registers: its tiles' Y operands
+// stay resident for the whole launch and the column-gradient accumulators
+// live in registers.
+constexpr int NWX = 4;
+constexpr int NTX = NWX * 64;
+
+// ---------------------------------------------------------------------------
+// panel staging: the next 16-row panel's table tiles, X rows and step sizes
+// travel straight from HBM into an LDS buffer while the current panel
+// computes (global_load_lds: lane l's 16 or 4 bytes land at base + l * size).
+// The two buffers are separate LDS objects and each panel body reads one of
+// them by name, so the compiler never has to wait for the prefetch into the
+// other one before an LDS read.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+__device__ __forceinline__ void lds_dma16(const void *src, void *wave_dst)
+{
+    __builtin_amdgcn_global_load_lds((glb_void_t *)src, (lds_void_t *)wave_dst, 16, 0, 0);
+}
+
+__device__ __forceinline__ void lds_dma4(const void *src, void *wave_dst)
+{
+    __builtin_amdgcn_global_load_lds((glb_void_t *)src, (lds_void_t *)wave_dst, 4, 0, 0);
+}
+
+template <int KP, int TPW>
+struct PanelBuf {
+    float4 apan[NWX][TPW * 64];   // wavefront w's tiles: [tile slot][lane]
+    float xrow[16 * KP];         // the panel's X rows, contiguous (16 * k floats)
+    float alpha[16];
+};
+
+// Issue the loads of panel p into `pb` (every wavefront issues its own tiles;
+// X rows and step sizes are spread over the wavefronts).
+template <int KP, int TPW>
+__device__ __forceinline__ void stage_panel(PanelBuf<KP, TPW> &pb, const float *Ap, int64_t ldp, int nt,
+                                            const float *X, int64_t m, int k, const float *alpha, int64_t p,
+                                            int w, int lane)
+{
+    const int li = lane & 15, g = lane >> 4;
+    const int64_t i0 = p * 16;
+    const float *arow = Ap + (i0 + li) * ldp + 4 * g;
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = min(w + NWX * s, nt - 1);
+        lds_dma16(arow + 16 * t, &pb.apan[w][s * 64]);
+    }
+    const int64_t rows = min<int64_t>(16, m - i0);
+    const int nx = (int)(rows * k);            // valid floats of the row block
+    const float *xb = X + i0 * k;
+    for (int q = w; q * 64 < nx; q += NWX)
+        if (q * 64 + lane < nx) lds_dma4(xb + q * 64 + lane, &pb.xrow[q * 64]);
+    if (alpha && w == NWX - 1 && lane < rows) lds_dma4(alpha + i0 + lane, &pb.alpha[0]);
+}
+
+__device__ __forceinline__ void wait_staged()
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Resident operands of the wavefront's tiles (Y is fixed during a half-step).
+template <int KP, int PREC>
+struct YtFrag {
+    float4 f[PREC == P_FP32 ? KP / 16 : 1];
+    i16x4 b[PREC == P_FP32 ? 1 : KP / 16];
+};
+
+template <int KP, int PREC>
+__device__ __forceinline__ void ytfrag_load(YtFrag<KP, PREC> &yt, const YShadow &ys, int64_t ldp, int64_t j0, int li,
+                                            int g)
+{
+#pragma unroll
+    for (int kb = 0; kb < KP / 16; ++kb) {
+        const int64_t off = (int64_t)(16 * kb + li) * ldp + j0 + 4 * g;
+        if constexpr (PREC == P_FP32) yt.f[kb] = *reinterpret_cast<const float4 *>(ys.t32 + off);
+        else *reinterpret_cast<uint2 *>(&yt.b[kb]) = *reinterpret_cast<const uint2 *>(ys.tb + off);
+    }
+}
+
+// S3 with a resident operand: dX(16i x 16kc) += G(16i x 16j) . Y_tile(16j x 16kc).
+template <int KP, int PREC>
+__device__ __forceinline__ void s3_resident(f32x4 (&dx)[KP / 16], const float (&G)[4], const YtFrag<KP, PREC> &yt)
+{
+    if constexpr (PREC == P_FP32) {
+#pragma unroll
+        for (int kb = 0; kb < KP / 16; ++kb) {
+            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[0], yt.f[kb].x, dx[kb], 0, 0, 0);
+            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[1], yt.f[kb].y, dx[kb], 0, 0, 0);
+            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[2], yt.f[kb].z, dx[kb], 0, 0, 0);
+            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[3], yt.f[kb].w, dx[kb], 0, 0, 0);
+        }
+    } else {
+        i16x4 av;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) av[s] = bf16_bits(to_bf16(G[s]));
+#pragma unroll
+        for (int kb = 0; kb < KP / 16; ++kb)
+            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, yt.b[kb], dx[kb], 0, 0, 0);
+    }
+}
+
+__device__ __forceinline__ void codes_of(const LossU &lu, const uint8_t *s_codes, int j, int (&cd)[4])
+{
+    if (lu.kind >= 0) {
+        cd[0] = cd[1] = cd[2] = cd[3] = 0;
+    } else {
+        uchar4 c = *reinterpret_cast<const uchar4 *>(s_codes + j);
+        cd[0] = c.x; cd[1] = c.y; cd[2] = c.z; cd[3] = c.w;
+    }
+}
+
+// A uniform loss comes from scalar arguments; a per-column table from LDS.
+__device__ __forceinline__ void entry_lg_u(const LossU &lu, const LossTab &tab, int code, float u, float a, float &l,
+                                           float &gr)
+{
+    if (lu.kind >= 0) loss_lg(lu.kind, lu.levels, lu.param, u, a, l, gr);
+    else loss_lg(tab.kind[code], tab.levels[code], tab.param[code], u, a, l, gr);
+}
+
+__device__ __forceinline__ float entry_l_u(const LossU &lu, const LossTab &tab, int code, float u, float a)
+{
+    if (lu.kind >= 0) return loss_l(lu.kind, lu.levels, lu.param, u, a);
+    return loss_l(tab.kind[code], tab.levels[code], tab.param[code], u, a);
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: fused X half-step (S1-S5) + Y-gradient and column-objective partials (S6)
+// ---------------------------------------------------------------------------
+template <int KP, int TPW, int PREC>
+struct XStepShared {
+    PanelBuf<KP, TPW> buf0, buf1;
+    float xs[16][KP];        // the panel's X (zero padded), later the accepted X
+    float xp[16][KP];        // trial rows
+    union alignas(16) {
+        float red_g[NWX][16][KP + 1];     // row-gradient partials (S3 -> S4)
+        struct {
+            float gsc[NWX][16 * GS];      // per-wavefront G transpose tiles (S6)
+            float xat[KP * GS];           // accepted X transposed ([kc][i]) for S6
+        } d;
+    } u;
+    float red_f[NWX][16];
+    LossTab lt;                 // per-column loss table (mixed tables only)
+    float s_h[16 * NWX * TPW];  // column objectives of this workgroup
+    uint8_t s_codes[16 * NWX * TPW];
+    float s_f[16], s_rx[16], s_rxp[16], s_al[16];
+    int s_acc[16];
+    float s_blk[NWX];
+    int s_rej[NWX];
+};
+
+template <int KP, int TPW, int PREC, int BUF>
+__device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, TPW, PREC> &sh, int64_t p,
+                                            int64_t p_next, const Frag<KP, PREC> (&yfr)[TPW],
+                                            const YtFrag<KP, PREC> (&ytf)[TPW], f32x4 (&dyacc)[TPW][KP / 16],
+                                            float &rowreg_acc, int &rej_acc)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    constexpr int C = KP / 4;
+    const int nt = (int)(a.ldp / 16);
+    PanelBuf<KP, TPW> &cur = BUF == 0 ? sh.buf0 : sh.buf1;
+    PanelBuf<KP, TPW> &nxt = BUF == 0 ? sh.buf1 : sh.buf0;
+    const float4 *apan = cur.apan[w];
+    const int64_t i0 = p * 16;
+
+    wait_staged();
+
+    // the panel's X rows, zero padded to kp; rows past m are zero
+    for (int t = threadIdx.x; t < 16 * KP; t += NTX) {
+        const int i = t / KP, c = t % KP;
+        sh.xs[i][c] = (i0 + i < a.m && c < a.k) ? cur.xrow[i * a.k + c] : 0.0f;
+    }
+    if (threadIdx.x < 16) sh.s_al[threadIdx.x] = i0 + threadIdx.x < a.m ? cur.alpha[threadIdx.x] : 0.0f;
+    __syncthreads();
+
+    // ---- S1-S3: z, loss, derivative, row objective, row gradient ------------------
+    Frag<KP, PREC> xf;
+    frag_from_f32<KP, PREC>(xf, &sh.xs[li][g * C]);
+    float fpart = 0.0f;
+    f32x4 dx[KP / 16];
+#pragma unroll
+    for (int kb = 0; kb < KP / 16; ++kb) dx[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = w + NWX * s;
+        if (t < nt) {
+            const float4 av = apan[s * 64 + lane];
+            const f32x4 z = zprod<KP, PREC>(yfr[s], xf);
+            int cd[4];
+            codes_of(a.lu, sh.s_codes, 16 * t + 4 * g, cd);
+            const float avr[4] = {av.x, av.y, av.z, av.w};
+            float G[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float l = 0.f, gr = 0.f;
+                if (avr[r] == avr[r]) entry_lg_u(a.lu, sh.lt, cd[r], z[r], avr[r], l, gr);
+                fpart += l;
+                G[r] = gr;
+            }
+            s3_resident<KP, PREC>(dx, G, ytf[s]);
+        }
+    }
+    fpart += __shfl_xor(fpart, 16, 64);
+    fpart += __shfl_xor(fpart, 32, 64);
+    if (g == 0) sh.red_f[w][li] = fpart;
+#pragma unroll
+    for (int kb = 0; kb < KP / 16; ++kb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sh.u.red_g[w][4 * g + r][16 * kb + li] = dx[kb][r];
+    __syncthreads();
+
+    // ---- S4: prox step and regularizer values ------------------------------------
+    for (int t = threadIdx.x; t < 16 * KP; t += NTX) {
+        const int i = t / KP, c = t % KP;
+        float gs = 0.0f;
+#pragma unroll
+        for (int q = 0; q < NWX; ++q) gs += sh.u.red_g[q][i][c];
+        const float x = sh.xs[i][c];
+        const float al = sh.s_al[i];
+        const float xv = (c < a.k) ? prox_elem(a.rx, al, x - al * gs) : 0.0f;
+        sh.xp[i][c] = xv;
+        float rc = c < a.k ? reg_elem(a.rx, x) : 0.0f;
+        float rcp = c < a.k ? reg_elem(a.rx, xv) : 0.0f;
+        rc = sum_lanes<KP>(rc);
+        rcp = sum_lanes<KP>(rcp);
+        if (c == 0) {
+            float f = 0.0f;
+#pragma unroll
+            for (int q = 0; q < NWX; ++q) f += sh.red_f[q][i];
+            sh.s_f[i] = f + rc;
+            sh.s_rx[i] = rc;
+            sh.s_rxp[i] = rcp;
+        }
+    }
+    __syncthreads();
+
+    // ---- S5: row objective at the trial rows ---------------------------------------
+    Frag<KP, PREC> xpf;
+    frag_from_f32<KP, PREC>(xpf, &sh.xp[li][g * C]);
+    float fppart = 0.0f;
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = w + NWX * s;
+        if (t < nt) {
+            const float4 av = apan[s * 64 + lane];
+            const f32x4 zp = zprod<KP, PREC>(yfr[s], xpf);
+            int cd[4];
+            codes_of(a.lu, sh.s_codes, 16 * t + 4 * g, cd);
+            const float avr[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (avr[r] == avr[r]) fppart += entry_l_u(a.lu, sh.lt, cd[r], zp[r], avr[r]);
+        }
+    }
+    fppart += __shfl_xor(fppart, 16, 64);
+    fppart += __shfl_xor(fppart, 32, 64);
+    if (g == 0) sh.red_f[w][li] = fppart;
+    __syncthreads();
+
+    // ---- decision per row ------------------------------------------------------------
+    if (threadIdx.x < 16) {
+        const int i = threadIdx.x;
+        const int64_t gi = i0 + i;
+        int acc = 0;
+        if (gi < a.m) {
+            float fp = 0.0f;
+#pragma unroll
+            for (int q = 0; q < NWX; ++q) fp += sh.red_f[q][i];
+            fp += sh.s_rxp[i];
+            acc = (fp <= sh.s_f[i]) ? 1 : 0;
+            const float al = sh.s_al[i];
+            a.alpha[gi] = acc ? al * a.step_up : al * a.step_down;
+            rowreg_acc += acc ? sh.s_rxp[i] : sh.s_rx[i];
+            rej_acc += acc ? 0 : 1;
+        }
+        sh.s_acc[i] = acc;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 16 * KP; t += NTX) {
+        const int i = t / KP, c = t % KP;
+        const float xa = sh.s_acc[i] ? sh.xp[i][c] : sh.xs[i][c];
+        sh.u.d.xat[c * GS + i] = xa;
+        sh.xs[i][c] = xa;
+        if (sh.s_acc[i] && c < a.k) a.X[(i0 + i) * a.k + c] = xa;
+    }
+    __syncthreads();
+
+    // The next panel's loads go out now: the compiler drains outstanding
+    // direct-to-LDS loads at every barrier, and S6 below has none.
+    if (p_next >= 0) stage_panel<KP, TPW>(nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
+
+    // ---- S6: column objective and Y gradient from the accepted rows -------------------
+    float *gsc = sh.u.d.gsc[w];
+    Frag<KP, PREC> xaf;
+    frag_from_f32<KP, PREC>(xaf, &sh.xs[li][g * C]);
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = w + NWX * s;
+        if (t < nt) {
+            const int j0 = 16 * t;
+            const f32x4 zs = zprod<KP, PREC>(yfr[s], xaf);
+            int cd[4];
+            codes_of(a.lu, sh.s_codes, j0 + 4 * g, cd);
+            const float4 av = apan[s * 64 + lane];
+            const float avr[4] = {av.x, av.y, av.z, av.w};
+            float G[4], gT[4], hl[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float l = 0.f, gr = 0.f;
+                if (avr[r] == avr[r]) entry_lg_u(a.lu, sh.lt, cd[r], zs[r], avr[r], l, gr);
+                hl[r] = sum_lanes<16>(l);
+                G[r] = gr;
+            }
+            if (li == 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sh.s_h[j0 + 4 * g + r] += hl[r];
+            }
+            transpose_g(gsc, G, gT, li, g);
+            s6_accum<KP, PREC>(dyacc[s], gT, sh.u.d.xat, li, g);
+        }
+    }
+}
+
+template <int KP, int TPW, int PREC>
+__global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    __shared__ XStepShared<KP, TPW, PREC> sh;
+    const int nt = (int)(a.ldp / 16);
+    const int64_t npanels = a.mp / 16;
+    const int64_t G = gridDim.x;
+
+    for (int j = threadIdx.x; j < a.ldp; j += NTX) {
+        sh.s_h[j] = 0.0f;
+        sh.s_codes[j] = a.codes[j];
+    }
+    if (threadIdx.x == 0) sh.lt = a.lt;
+    // this wavefront's tiles of Y (fixed during the X half-step), resident in registers
+    Frag<KP, PREC> yfr[TPW];
+    YtFrag<KP, PREC> ytf[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = min(w + NWX * s, nt - 1);
+        frag_load_y<KP, PREC>(yfr[s], a.ycur, 16 * t + li, g);
+        ytfrag_load<KP, PREC>(ytf[s], a.ycur, a.ldp, 16 * t, li, g);
+    }
+    f32x4 dyacc[TPW][KP / 16];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s)
+#pragma unroll
+        for (int kb = 0; kb < KP / 16; ++kb) dyacc[s][kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float rowreg_acc = 0.0f;
+    int rej_acc = 0;
+
+    if (blockIdx.x < npanels)
+        stage_panel<KP, TPW>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, blockIdx.x, w, lane);
+    for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
+        const int64_t p1 = p + G, p2 = p + 2 * G;
+        xstep_panel<KP, TPW, PREC, 0>(a, sh, p, p1 < npanels ? p1 : -1, yfr, ytf, dyacc, rowreg_acc, rej_acc);
+        if (p1 < npanels)
+            xstep_panel<KP, TPW, PREC, 1>(a, sh, p1, p2 < npanels ? p2 : -1, yfr, ytf, dyacc, rowreg_acc,
+                                          rej_acc);
+    }
+    __syncthreads();
+
+    // ---- this workgroup's partials ---------------------------------------------------
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = w + NWX * s;
+        if (t < nt) {
+            const int64_t j0 = 16 * t;
+#pragma unroll
+            for (int kb = 0; kb < KP / 16; ++kb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    a.part_dy[((int64_t)blockIdx.x * a.ldp + j0 + 4 * g + r) * KP + 16 * kb + li] = dyacc[s][kb][r];
+        }
+    }
+    for (int64_t j = threadIdx.x; j < a.ldp; j += NTX) a.part_h[(int64_t)blockIdx.x * a.ldp + j] = sh.s_h[j];
+    // row regularizers and rejections live on threads 0..15 of wavefront 0
+    float rr = sum_lanes<64>(rowreg_acc);
+    int rj = (int)sum_lanes<64>((float)rej_acc);
+    if (lane == 0) { sh.s_blk[w] = rr; sh.s_rej[w] = rj; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.part_rowreg[blockIdx.x] = sh.s_blk[0];
+        a.part_rej[blockIdx.x] = sh.s_rej[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Y prox: reduce the partial gradients, step, prox (S7); remember h_j (old)
+// ---------------------------------------------------------------------------
+template <int KP, int PREC>
+__global__ __launch_bounds__(256) void yprox_kernel(YProxArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = t / KP;
+    const int c = (int)(t % KP);
+    const bool valid = j < a.n;
+    float gsum = 0.0f;
+    if (valid)
+        for (int p = 0; p < a.P; ++p) gsum += a.part_dy[((int64_t)p * a.ldp + j) * KP + c];
+    const float y = (valid && c < a.k) ? a.Y[j * a.k + c] : 0.0f;
+    const float al = valid ? a.alpha[j] : 0.0f;
+    const float yv = (valid && c < a.k) ? prox_elem(a.ry, al, y - al * gsum) : 0.0f;
+    if (valid) {
+        if (c < a.k) a.Yplus[j * a.k + c] = yv;
+        if constexpr (PREC == P_FP32) {
+            a.yplus.f32[j * KP + c] = yv;
+        } else {
+            __bf16 hi, lo;
+            split_bf16(yv, hi, lo);
+            a.yplus.hi[j * KP + c] = hi;
+            a.yplus.lo[j * KP + c] = lo;
+        }
+    }
+    float rc = (valid && c < a.k) ? reg_elem(a.ry, y) : 0.0f;
+    float rcp = (valid && c < a.k) ? reg_elem(a.ry, yv) : 0.0f;
+    rc = sum_lanes<KP>(rc);
+    rcp = sum_lanes<KP>(rcp);
+    if (valid && c == 0) {
+        float h = 0.0f;
+        for (int p = 0; p < a.P; ++p) h += a.part_h[(int64_t)p * a.ldp + j];
+        a.h_old[j] = h + rc;
+        a.ry_plus[j] = rcp;
+        a.ry_old[j] = rc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pass 2: column objective at the trial Y+ (S8)
+// ---------------------------------------------------------------------------
+template <int KP, int TPW>
+struct YCheckShared {
+    PanelBuf<KP, TPW> buf0, buf1;
+    float xs[16][KP];
+    LossTab lt;
+    uint8_t s_codes[16 * NWX * TPW];
+};
+
+template <int KP, int TPW, int PREC, int BUF>
+__device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP, TPW> &sh, int64_t p,
+                                             int64_t p_next, const Frag<KP, PREC> (&yfr)[TPW], f32x4 (&hacc)[TPW])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    constexpr int C = KP / 4;
+    const int nt = (int)(a.ldp / 16);
+    PanelBuf<KP, TPW> &cur = BUF == 0 ? sh.buf0 : sh.buf1;
+    PanelBuf<KP, TPW> &nxt = BUF == 0 ? sh.buf1 : sh.buf0;
+    const float4 *apan = cur.apan[w];
+    const int64_t i0 = p * 16;
+
+    wait_staged();
+    for (int t = threadIdx.x; t < 16 * KP; t += NTX) {
+        const int i = t / KP, c = t % KP;
+        sh.xs[i][c] = (i0 + i < a.m && c < a.k) ? cur.xrow[i * a.k + c] : 0.0f;
+    }
+    __syncthreads();
+    // no barrier until the next panel: the prefetch overlaps this panel's products
+    if (p_next >= 0) stage_panel<KP, TPW>(nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, p_next, w, lane);
+    Frag<KP, PREC> xf;
+    frag_from_f32<KP, PREC>(xf, &sh.xs[li][g * C]);
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = w + NWX * s;
+        if (t < nt) {
+            const float4 av = apan[s * 64 + lane];
+            const f32x4 zp = zprod<KP, PREC>(yfr[s], xf);
+            int cd[4];
+            codes_of(a.lu, sh.s_codes, 16 * t + 4 * g, cd);
+            const float avr[4] = {av.x, av.y, av.z, av.w};
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (avr[r] == avr[r]) hacc[s][r] += entry_l_u(a.lu, sh.lt, cd[r], zp[r], avr[r]);
+        }
+    }
+}
+
+template <int KP, int TPW, int PREC>
+__global__ __launch_bounds__(NTX, 1) void ycheck_kernel(YCheckArgs a)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    __shared__ YCheckShared<KP, TPW> sh;
+    const int nt = (int)(a.ldp / 16);
+    const int64_t npanels = a.mp / 16;
+    const int64_t G = gridDim.x;
+
+    for (int j = threadIdx.x; j < a.ldp; j += NTX) sh.s_codes[j] = a.codes[j];
+    if (threadIdx.x == 0) sh.lt = a.lt;
+    Frag<KP, PREC> yfr[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = min(w + NWX * s, nt - 1);
+        frag_load_y<KP, PREC>(yfr[s], a.yplus, 16 * t + li, g);
+    }
+    f32x4 hacc[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) hacc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    if (blockIdx.x < npanels)
+        stage_panel<KP, TPW>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, blockIdx.x, w, lane);
+    for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
+        const int64_t p1 = p + G, p2 = p + 2 * G;
+        ycheck_panel<KP, TPW, PREC, 0>(a, sh, p, p1 < npanels ? p1 : -1, yfr, hacc);
+        if (p1 < npanels) ycheck_panel<KP, TPW, PREC, 1>(a, sh, p1, p2 < npanels ? p2 : -1, yfr, hacc);
+    }
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = w + NWX * s;
+        if (t < nt) {
+            const int64_t j0 = 16 * t;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float h = sum_lanes<16>(hacc[s][r]);
+                if (li == 0) a.part_hp[(int64_t)blockIdx.x * a.ldp + j0 + 4 * g + r] = h;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// column decisions (S8), Y shadows for the next sweep, objective partials
+// ---------------------------------------------------------------------------
+template <int KP, int PREC>
+__global__ __launch_bounds__(256) void yaccept_kernel(YAcceptArgs a)
+{
+    __shared__ double s_F[4];
+    __shared__ int s_r[4];
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = t / KP;
+    const int c = (int)(t % KP);
+    const bool valid = j < a.n;
+    int acc = 0;
+    double Fj = 0.0;
+    int rj = 0;
+    if (valid) {
+        float hp = 0.0f;
+        for (int p = 0; p < a.P; ++p) hp += a.part_hp[(int64_t)p * a.ldp + j];
+        hp += a.ry_plus[j];
+        const float h = a.h_old[j];
+        acc = hp <= h ? 1 : 0;
+        if (c == 0) {
+            const float al = a.alpha[j];
+            a.alpha[j] = acc ? al * a.step_up : al * a.step_down;
+            Fj = acc ? (double)hp : (double)h;
+            rj = acc ? 0 : 1;
+        }
+        if (acc) {
+            const float yv = c < a.k ? a.Yplus[j * a.k + c] : 0.0f;
+            if (c < a.k) a.Y[j * a.k + c] = yv;
+            if constexpr (PREC == P_FP32) {
+                a.ycur.f32[j * KP + c] = yv;
+                a.ycur.t32[(int64_t)c * a.ldp + j] = yv;
+            } else {
+                a.ycur.hi[j * KP + c] = a.yplus.hi[j * KP + c];
+                if constexpr (PREC == P_BF16) a.ycur.lo[j * KP + c] = a.yplus.lo[j * KP + c];
+                a.ycur.tb[(int64_t)c * a.ldp + j] = a.yplus.hi[j * KP + c];
+            }
+        }
+    }
+    Fj = sum_lanes64<64>(Fj);
+    rj = (int)sum_lanes<64>((float)rj);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { s_F[w] = Fj; s_r[w] = rj; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.part_F[blockIdx.x] = s_F[0] + s_F[1] + s_F[2] + s_F[3];
+        a.part_rejc[blockIdx.x] = s_r[0] + s_r[1] + s_r[2] + s_r[3];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Y shadows from Y (fit start)
+// ---------------------------------------------------------------------------
+template <int KP, int PREC>
+__global__ __launch_bounds__(256) void yshadow_kernel(YShadowArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = t / KP;
+    const int c = (int)(t % KP);
+    if (j >= a.ldp) return;
+    const float yv = (j < a.n && c < a.k) ? a.Y[j * a.k + c] : 0.0f;
+    if constexpr (PREC == P_FP32) {
+        a.ys.f32[j * KP + c] = yv;
+        a.ys.t32[(int64_t)c * a.ldp + j] = yv;
+        if (a.yp.f32) a.yp.f32[j * KP + c] = 0.0f;
+    } else {
+        __bf16 hi, lo;
+        split_bf16(yv, hi, lo);
+        a.ys.hi[j * KP + c] = hi;
+        if constexpr (PREC == P_BF16) a.ys.lo[j * KP + c] = lo;
+        a.ys.tb[(int64_t)c * a.ldp + j] = hi;
+        if (a.yp.hi) {
+            a.yp.hi[j * KP + c] = to_bf16(0.0f);
+            if constexpr (PREC == P_BF16) a.yp.lo[j * KP + c] = to_bf16(0.0f);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// objective and gradient (single pass, no decisions)
+// ---------------------------------------------------------------------------
+// grid: x = row chunks, y = column blocks of NW*TPW tiles
+template <int KP, int TPW, int PREC, bool WANT_GRAD>
+__global__ __launch_bounds__(NT, 1) void lossgrad_kernel(LossGradArgs a)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    constexpr int C = KP / 4;
+    __shared__ float xs[16][KP];
+    __shared__ __attribute__((aligned(16))) float xat[KP * GS];
+    __shared__ float red_g[NW][16][KP + 1];
+    __shared__ __attribute__((aligned(16))) float gsc_all[NW][16 * GS];
+    __shared__ double s_obj[NW];
+    float *gsc = gsc_all[w];
+    const int64_t ntiles = a.ldp / 16;
+    const int64_t npanels = a.mp / 16;
+    const int64_t tile0 = (int64_t)blockIdx.y * NW * TPW;
+
+    f32x4 dyacc[TPW][KP / 16];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s)
+#pragma unroll
+        for (int kb = 0; kb < KP / 16; ++kb) dyacc[s][kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    double obj = 0.0;
+
+    for (int64_t p = blockIdx.x; p < npanels; p += gridDim.x) {
+        const int64_t i0 = p * 16;
+        load_panel<KP>(xs, a.X, i0, a.m, a.k);
+        if (WANT_GRAD) {
+            for (int t = threadIdx.x; t < 16 * KP; t += NT) {
+                const int i = t / KP, c = t % KP;
+                xat[c * GS + i] = (i0 + i < a.m && c < a.k) ? a.X[(i0 + i) * a.k + c] : 0.0f;
+            }
+        }
+        __syncthreads();
+        Frag<KP, PREC> xf;
+        frag_from_f32<KP, PREC>(xf, &xs[li][g * C]);
+        f32x4 dx[KP / 16];
+#pragma unroll
+        for (int kb = 0; kb < KP / 16; ++kb) dx[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        float opart = 0.0f;
+#pragma unroll
+        for (int s = 0; s < TPW; ++s) {
+            const int64_t t = tile0 + w + NW * s;
+            if (t < ntiles) {
+                const int64_t j0 = 16 * t;
+                const float4 av = *reinterpret_cast<const float4 *>(a.Ap + (i0 + li) * a.ldp + j0 + 4 * g);
+                Frag<KP, PREC> yf;
+                frag_load_y<KP, PREC>(yf, a.ycur, j0 + li, g);
+                const f32x4 z = zprod<KP, PREC>(yf, xf);
+                int cd[4];
+                load_codes(a.codes, j0 + 4 * g, cd);
+                const float avr[4] = {av.x, av.y, av.z, av.w};
+                float G[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float l = 0.f, gr = 0.f;
+                    if (avr[r] == avr[r]) {
+                        if (WANT_GRAD) entry_lg(a.lt, cd[r], z[r], avr[r], l, gr);
+                        else l = entry_l(a.lt, cd[r], z[r], avr[r]);
+                    }
+                    opart += l;
+                    G[r] = gr;
+                }
+                if (WANT_GRAD) {
+                    s3_accum<KP, PREC>(dx, G, a.ycur, a.ldp, j0, li, g);
+                    float gT[4];
+                    transpose_g(gsc, G, gT, li, g);
+                    s6_accum<KP, PREC>(dyacc[s], gT, xat, li, g);
+                }
+            }
+        }
+        obj += (double)opart;
+        if (WANT_GRAD) {
+#pragma unroll
+            for (int kb = 0; kb < KP / 16; ++kb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) red_g[w][4 * g + r][16 * kb + li] = dx[kb][r];
+            __syncthreads();
+            for (int t = threadIdx.x; t < 16 * KP; t += NT) {
+                const int i = t / KP, c = t % KP;
+                if (i0 + i < a.m && c < a.k) {
+                    float s = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) s += red_g[q][i][c];
+                    if (a.part_dx) a.part_dx[((int64_t)blockIdx.y * a.m + i0 + i) * a.k + c] = s;
+                    else a.dX[(i0 + i) * a.k + c] = s;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (WANT_GRAD) {
+#pragma unroll
+        for (int s = 0; s < TPW; ++s) {
+            const int64_t t = tile0 + w + NW * s;
+            if (t < ntiles) {
+                const int64_t j0 = 16 * t;
+#pragma unroll
+                for (int kb = 0; kb < KP / 16; ++kb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        a.part_dy[((int64_t)blockIdx.x * a.ldp + j0 + 4 * g + r) * KP + 16 * kb + li] = dyacc[s][kb][r];
+            }
+        }
+    }
+    obj = sum_lanes64<64>(obj);
+    if (lane == 0) s_obj[w] = obj;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int q = 0; q < NW; ++q) s += s_obj[q];
+        a.part_obj[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// dY = sum over row chunks of the partials; dX = sum over column blocks.
+template <int KP>
+__global__ __launch_bounds__(256) void reduce_dy_kernel(ReduceArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = t / KP;
+    const int c = (int)(t % KP);
+    if (j >= a.n || c >= a.k) return;
+    float s = 0.0f;
+    for (int p = 0; p < a.P; ++p) s += a.part_dy[((int64_t)p * a.ldp + j) * KP + c];
+    a.dY[j * a.k + c] = s;
+}
+
+}  // namespace glrm

@@ -1,0 +1,108 @@
+// Precision-dependent launchers of the dense kernels.  This file is compiled
+// once per contraction precision with -DGLRM_PREC=<0|1|3> (FP32, split BF16,
+// plain BF16), so the three sets of kernel instances build in parallel.
+#include "dense_kernels.h"
+
+#ifndef GLRM_PREC
+#error "compile with -DGLRM_PREC=0, 1 or 3"
+#endif
+
+namespace glrm {
+
+#define GLRM_DISPATCH_KP(KPV, ...)                                    \
+    switch (KPV) {                                                    \
+    case 16: { constexpr int KP = 16; __VA_ARGS__; } break;           \
+    case 32: { constexpr int KP = 32; __VA_ARGS__; } break;           \
+    case 64: { constexpr int KP = 64; __VA_ARGS__; } break;           \
+    default: return hipErrorInvalidValue;                              \
+    }
+#define GLRM_DISPATCH_PREC(PV, ...)                                   \
+    switch (PV) {                                                     \
+    case P_FP32: { constexpr int PREC = P_FP32; __VA_ARGS__; } break; \
+    case P_BF16: { constexpr int PREC = P_BF16; __VA_ARGS__; } break; \
+    case P_BF16_PLAIN: { constexpr int PREC = P_BF16_PLAIN; __VA_ARGS__; } break; \
+    default: return hipErrorInvalidValue;                              \
+    }
+#define GLRM_DISPATCH_TPW(TV, ...)                                    \
+    switch (TV) {                                                     \
+    case 1: { constexpr int TPW = 1; __VA_ARGS__; } break;            \
+    case 2: { constexpr int TPW = 2; __VA_ARGS__; } break;            \
+    case 4: { constexpr int TPW = 4; __VA_ARGS__; } break;            \
+    case 8: { constexpr int TPW = 8; __VA_ARGS__; } break;            \
+    default: return hipErrorInvalidValue;                              \
+    }
+
+#define GLRM_DISPATCH_TPWX(TV, ...)                                   \
+    switch (TV) {                                                     \
+    case 1: { constexpr int TPW = 1; __VA_ARGS__; } break;            \
+    case 2: { constexpr int TPW = 2; __VA_ARGS__; } break;            \
+    case 4: { constexpr int TPW = 4; __VA_ARGS__; } break;            \
+    case 8: { constexpr int TPW = 8; __VA_ARGS__; } break;            \
+    case 16: { constexpr int TPW = 16; __VA_ARGS__; } break;          \
+    default: return hipErrorInvalidValue;                              \
+    }
+
+
+template <int PREC>
+hipError_t launch_xstep_p(const XStepArgs &a, int kp, int tpw, int grid, hipStream_t st)
+{
+    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPWX(tpw,
+        if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
+        else hipLaunchKernelGGL((xstep_kernel<KP, TPW, PREC>), dim3(grid), dim3(NTX), 0, st, a)));
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_ycheck_p(const YCheckArgs &a, int kp, int tpw, int grid, hipStream_t st)
+{
+    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPWX(tpw,
+        if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
+        else hipLaunchKernelGGL((ycheck_kernel<KP, TPW, PREC>), dim3(grid), dim3(NTX), 0, st, a)));
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_yprox_p(const YProxArgs &a, int kp, hipStream_t st)
+{
+    const int blocks = (int)((a.n * (int64_t)kp + 255) / 256);
+    GLRM_DISPATCH_KP(kp, hipLaunchKernelGGL((yprox_kernel<KP, PREC>), dim3(blocks), dim3(256), 0, st, a));
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_yaccept_p(const YAcceptArgs &a, int kp, int blocks, hipStream_t st)
+{
+    GLRM_DISPATCH_KP(kp, hipLaunchKernelGGL((yaccept_kernel<KP, PREC>), dim3(blocks), dim3(256), 0, st, a));
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_yshadow_p(const YShadowArgs &a, int kp, hipStream_t st)
+{
+    const int blocks = (int)((a.ldp * (int64_t)kp + 255) / 256);
+    GLRM_DISPATCH_KP(kp, hipLaunchKernelGGL((yshadow_kernel<KP, PREC>), dim3(blocks), dim3(256), 0, st, a));
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_lossgrad_p(const LossGradArgs &a, int kp, int tpw, bool want_grad, int gx, int gy, hipStream_t st)
+{
+    if (want_grad) {
+        GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW(tpw,
+            if constexpr (KP == 64 && TPW == 8) return hipErrorInvalidValue;
+            else hipLaunchKernelGGL((lossgrad_kernel<KP, TPW, PREC, true>), dim3(gx, gy), dim3(NT), 0, st, a)));
+    } else {
+        GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW(tpw,
+            hipLaunchKernelGGL((lossgrad_kernel<KP, TPW, PREC, false>), dim3(gx, gy), dim3(NT), 0, st, a)));
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_xstep_p<GLRM_PREC>(const XStepArgs &, int, int, int, hipStream_t);
+template hipError_t launch_ycheck_p<GLRM_PREC>(const YCheckArgs &, int, int, int, hipStream_t);
+template hipError_t launch_yprox_p<GLRM_PREC>(const YProxArgs &, int, hipStream_t);
+template hipError_t launch_yaccept_p<GLRM_PREC>(const YAcceptArgs &, int, int, hipStream_t);
+template hipError_t launch_yshadow_p<GLRM_PREC>(const YShadowArgs &, int, hipStream_t);
+template hipError_t launch_lossgrad_p<GLRM_PREC>(const LossGradArgs &, int, int, bool, int, int, hipStream_t);
+
+}  // namespace glrm

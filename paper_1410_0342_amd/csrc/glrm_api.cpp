@@ -53,6 +53,16 @@ int tpw_for(int64_t ntiles)
     return 0;
 }
 
+// The same for the two passes of the fit (pass_waves() wavefronts, up to 16
+// tiles each; 8 at kp = 64).
+int tpw_fit(int64_t ntiles, int kp)
+{
+    const int maxt = kp == 64 ? 8 : 16;
+    for (int t : {1, 2, 4, 8, 16})
+        if (t <= maxt && (int64_t)pass_waves() * t >= ntiles) return t;
+    return 0;
+}
+
 struct Layout {
     int64_t m, n, k, kp, mp, ldp;
     size_t total = 0;
@@ -195,6 +205,21 @@ LossTab make_losstab(const glrm_data *d)
 }
 
 Reg make_reg(const glrm_reg &r) { return Reg{r.kind, r.weight}; }
+
+LossU make_lossu(const LossTab &t)
+{
+    LossU u;
+    if (t.uniform >= 0) {
+        u.kind = t.kind[t.uniform];
+        u.levels = t.levels[t.uniform];
+        u.param = t.param[t.uniform];
+    } else {
+        u.kind = -1;
+        u.levels = 0;
+        u.param = 0.0f;
+    }
+    return u;
+}
 
 YShadow shadow(void *ws, const Layout &L, bool plus)
 {
@@ -518,10 +543,10 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
     const int prec = o->precision;
     int tpw = 0;
     if (d->layout == GLRM_DENSE) {
-        tpw = tpw_for(L.ldp / 16);
-        if (tpw == 0 || (L.kp == 64 && tpw > 4))
-            return fail(GLRM_EUNSUPPORTED, "dense fit supports n <= %d for k <= 32 and n <= 512 for k > 32; "
-                        "use the COO layout for wider tables", 16 * NWAVES * 8);
+        tpw = tpw_fit(L.ldp / 16, (int)L.kp);
+        if (tpw == 0)
+            return fail(GLRM_EUNSUPPORTED, "dense fit supports n <= %d for k <= 32 and n <= %d for k > 32; "
+                        "use the COO layout for wider tables", 16 * pass_waves() * 16, 16 * pass_waves() * 8);
     } else {
         if ((rc = coo_fit_supported(d, L.kp, L.cl, prec))) return rc;
     }
@@ -549,6 +574,7 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
         xa.Ap = at<float>(ws, L.Ap);
         xa.codes = at<uint8_t>(ws, L.codes);
         xa.lt = lt;
+        xa.lu = make_lossu(lt);
         xa.rx = make_reg(d->rx);
         xa.X = X;
         xa.alpha = alpha_x;
@@ -572,7 +598,7 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
 
         YCheckArgs ca;
         ca.m = L.m; ca.mp = L.mp; ca.ldp = L.ldp; ca.k = (int32_t)L.k;
-        ca.Ap = xa.Ap; ca.codes = xa.codes; ca.lt = lt; ca.X = X;
+        ca.Ap = xa.Ap; ca.codes = xa.codes; ca.lt = lt; ca.lu = xa.lu; ca.X = X;
         ca.yplus = pa.yplus;
         ca.part_hp = at<float>(ws, L.part_hp);
 

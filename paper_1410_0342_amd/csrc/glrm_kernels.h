@@ -21,12 +21,19 @@ struct YShadow {
     __bf16 *tb;      // kp x ldp   (bf16 high part, transposed: S3 operand)
 };
 
+// A loss shared by every column, as scalars (kind < 0: per-column table).
+struct LossU {
+    int32_t kind, levels;
+    float param;
+};
+
 struct XStepArgs {
     int64_t m, mp, ldp;
     int32_t k;
     const float *Ap;        // mp x ldp, NaN = unobserved
     const uint8_t *codes;   // ldp
     LossTab lt;
+    LossU lu;
     Reg rx;
     float *X;               // m x k (in/out)
     float *alpha;           // m (in/out)
@@ -57,6 +64,7 @@ struct YCheckArgs {
     const float *Ap;
     const uint8_t *codes;
     LossTab lt;
+    LossU lu;
     const float *X;
     YShadow yplus;
     float *part_hp;         // P x ldp
@@ -141,6 +149,7 @@ struct PackArgs {
 // ---- launchers (dense.hip) ----
 hipError_t launch_xstep(const XStepArgs &a, int kp, int tpw, int prec, int grid, hipStream_t st);
 hipError_t launch_ycheck(const YCheckArgs &a, int kp, int tpw, int prec, int grid, hipStream_t st);
+int pass_waves();   // wavefronts per workgroup of the two table passes
 hipError_t launch_yprox(const YProxArgs &a, int kp, int prec, hipStream_t st);
 hipError_t launch_yaccept(const YAcceptArgs &a, int kp, int prec, int blocks, hipStream_t st);
 int yaccept_blocks(int64_t n, int kp);
