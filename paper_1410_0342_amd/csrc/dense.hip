@@ -43,51 +43,51 @@ __global__ __launch_bounds__(256) void reduce_dx_kernel(ReduceArgs a)
     a.dX[t] = s;
 }
 
-// FP64 objective: z in double from the fp32 factors, loss in double.
+// FP64 objective: z in double from the fp32 factors, loss in double.  A
+// workgroup takes 16 rows x 256 columns; each thread owns one column, keeps
+// y_j in registers and reads the 16 x rows as LDS broadcasts.
+template <int KP>
 __global__ __launch_bounds__(256) void objective64_kernel(Obj64Args a)
 {
-    __shared__ double xsd[16][GLRM_MAXK_DEV + 1];
-    __shared__ double ysd[64][GLRM_MAXK_DEV + 1];
+    __shared__ double xsd[16][KP];
     __shared__ double sred[4];
-    const int64_t ntile_j = (a.ldp + 63) / 64;
+    const int64_t ntile_j = (a.ldp + 255) / 256;
     const int64_t npanels = a.mp / 16;
     double acc = 0.0;
     for (int64_t blk = blockIdx.x; blk < npanels * ntile_j; blk += gridDim.x) {
         const int64_t p = blk / ntile_j, jt = blk % ntile_j;
-        const int64_t i0 = p * 16, j0 = jt * 64;
-        for (int t = threadIdx.x; t < 16 * a.k; t += 256) {
-            const int i = t / a.k, c = t % a.k;
-            xsd[i][c] = i0 + i < a.m ? (double)a.X[(i0 + i) * a.k + c] : 0.0;
-        }
-        for (int t = threadIdx.x; t < 64 * a.k; t += 256) {
-            const int jj = t / a.k, c = t % a.k;
-            ysd[jj][c] = j0 + jj < a.n ? (double)a.Y[(j0 + jj) * a.k + c] : 0.0;
+        const int64_t i0 = p * 16, j = jt * 256 + threadIdx.x;
+        __syncthreads();
+        for (int t = threadIdx.x; t < 16 * KP; t += 256) {
+            const int i = t / KP, c = t % KP;
+            xsd[i][c] = (i0 + i < a.m && c < a.k) ? (double)a.X[(i0 + i) * a.k + c] : 0.0;
         }
         __syncthreads();
-        const int jj = threadIdx.x & 63;
-        const int64_t j = j0 + jj;
         if (j < a.n) {
-            const int code = a.codes[j];
-            const int q = a.lt.uniform >= 0 ? a.lt.uniform : code;
-            for (int ii = threadIdx.x >> 6; ii < 16; ii += 4) {
+            double y[KP];
+#pragma unroll
+            for (int c = 0; c < KP; ++c) y[c] = c < a.k ? (double)a.Y[j * a.k + c] : 0.0;
+            const int q = a.lt.uniform >= 0 ? a.lt.uniform : a.codes[j];
+            const int kind = a.lt.kind[q], lev = a.lt.levels[q];
+            const double par = (double)a.lt.param[q];
+            for (int ii = 0; ii < 16; ++ii) {
                 const int64_t i = i0 + ii;
                 if (i >= a.m) break;
                 const float av = a.Ap[i * a.ldp + j];
                 if (av == av) {
                     double z = 0.0;
-                    for (int c = 0; c < a.k; ++c) z += xsd[ii][c] * ysd[jj][c];
-                    acc += loss_l64(a.lt.kind[q], a.lt.levels[q], (double)a.lt.param[q], z, (double)av);
+#pragma unroll
+                    for (int c = 0; c < KP; ++c) z += xsd[ii][c] * y[c];
+                    acc += loss_l64(kind, lev, par, z, (double)av);
                 }
             }
         }
-        __syncthreads();
     }
     acc = sum_lanes64<64>(acc);
     if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) a.part_obj[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
 }
-
 
 // ---------------------------------------------------------------------------
 // dispatch by precision (instances live in dense_prec.hip)
@@ -181,7 +181,12 @@ hipError_t launch_reduce_dx(const ReduceArgs &a, hipStream_t st)
 
 hipError_t launch_objective64(const Obj64Args &a, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(objective64_kernel, dim3(grid), dim3(256), 0, st, a);
+    const int kp = a.k <= 16 ? 16 : (a.k <= 32 ? 32 : 64);
+    switch (kp) {
+    case 16: hipLaunchKernelGGL((objective64_kernel<16>), dim3(grid), dim3(256), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((objective64_kernel<32>), dim3(grid), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((objective64_kernel<64>), dim3(grid), dim3(256), 0, st, a); break;
+    }
     return hipGetLastError();
 }
 

@@ -353,6 +353,77 @@ __device__ __forceinline__ float entry_l_u(const LossU &lu, const LossTab &tab, 
     return loss_l(tab.kind[code], tab.levels[code], tab.param[code], u, a);
 }
 
+template <int K, bool WANT_G>
+__device__ __forceinline__ void tile4(int lev, float par, const f32x4 &z, const float (&a4)[4], float (&l)[4],
+                                      float (&g)[4])
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        float lr = 0.f, gr = 0.f;
+        if (a4[r] == a4[r]) {
+            if constexpr (WANT_G) loss_lg_k<K>(lev, par, z[r], a4[r], lr, gr);
+            else lr = loss_l_k<K>(lev, par, z[r], a4[r]);
+        }
+        l[r] = lr;
+        g[r] = gr;
+    }
+}
+
+// Losses (and, with WANT_G, derivatives) of the lane's four entries of tile t.
+// LK >= 0: every column has loss kind LK (compile time).  LK < 0: a tile whose
+// sixteen columns share one loss takes it from a scalar branch on the tile's
+// code; a tile that mixes losses goes entry by entry.
+template <int LK, bool WANT_G>
+__device__ __forceinline__ void tile_loss(const LossU &lu, const LossTab &tab, const uint8_t *s_codes,
+                                          const int8_t *s_tcode, int t, const f32x4 &z, const float4 &av,
+                                          float (&l)[4], float (&g)[4])
+{
+    const float a4[4] = {av.x, av.y, av.z, av.w};
+    if constexpr (LK >= 0) {
+        tile4<LK, WANT_G>(lu.levels, lu.param, z, a4, l, g);
+    } else {
+        const int tc = __builtin_amdgcn_readfirstlane((int)s_tcode[t]);
+        if (tc >= 0) {
+            const int kind = __builtin_amdgcn_readfirstlane(tab.kind[tc]);
+            const int lev = __builtin_amdgcn_readfirstlane(tab.levels[tc]);
+            const float par = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, tab.param[tc])));
+            switch (kind) {
+            case L_QUAD: tile4<L_QUAD, WANT_G>(lev, par, z, a4, l, g); break;
+            case L_HUBER: tile4<L_HUBER, WANT_G>(lev, par, z, a4, l, g); break;
+            case L_LOGISTIC: tile4<L_LOGISTIC, WANT_G>(lev, par, z, a4, l, g); break;
+            case L_HINGE: tile4<L_HINGE, WANT_G>(lev, par, z, a4, l, g); break;
+            default: tile4<L_ORDINAL, WANT_G>(lev, par, z, a4, l, g); break;
+            }
+        } else {
+            const int lane = threadIdx.x & 63;
+            const uchar4 c = *reinterpret_cast<const uchar4 *>(s_codes + 16 * t + 4 * (lane >> 4));
+            const int cd[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float lr = 0.f, gr = 0.f;
+                if (a4[r] == a4[r]) {
+                    if constexpr (WANT_G) loss_lg(tab.kind[cd[r]], tab.levels[cd[r]], tab.param[cd[r]], z[r], a4[r], lr, gr);
+                    else lr = loss_l(tab.kind[cd[r]], tab.levels[cd[r]], tab.param[cd[r]], z[r], a4[r]);
+                }
+                l[r] = lr;
+                g[r] = gr;
+            }
+        }
+    }
+}
+
+// Per-tile loss codes: the tile's code when its sixteen columns share one
+// loss, else -1.
+__device__ __forceinline__ void tile_codes(const uint8_t *s_codes, int nt, int8_t *s_tcode, int nthreads)
+{
+    for (int t = threadIdx.x; t < nt; t += nthreads) {
+        const uint8_t c0 = s_codes[16 * t];
+        bool same = true;
+        for (int q = 1; q < 16; ++q) same = same && s_codes[16 * t + q] == c0;
+        s_tcode[t] = same ? (int8_t)c0 : (int8_t)-1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // pass 1: fused X half-step (S1-S5) + Y-gradient and column-objective partials (S6)
 // ---------------------------------------------------------------------------
@@ -372,13 +443,14 @@ struct XStepShared {
     LossTab lt;                 // per-column loss table (mixed tables only)
     float s_h[16 * NWX * TPW];  // column objectives of this workgroup
     uint8_t s_codes[16 * NWX * TPW];
+    int8_t s_tcode[NWX * TPW];
     float s_f[16], s_rx[16], s_rxp[16], s_al[16];
     int s_acc[16];
     float s_blk[NWX];
     int s_rej[NWX];
 };
 
-template <int KP, int TPW, int PREC, int BUF>
+template <int KP, int TPW, int PREC, int LK, int BUF>
 __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, TPW, PREC> &sh, int64_t p,
                                             int64_t p_next, const Frag<KP, PREC> (&yfr)[TPW],
                                             const YtFrag<KP, PREC> (&ytf)[TPW], f32x4 (&dyacc)[TPW][KP / 16],
@@ -416,17 +488,9 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         if (t < nt) {
             const float4 av = apan[s * 64 + lane];
             const f32x4 z = zprod<KP, PREC>(yfr[s], xf);
-            int cd[4];
-            codes_of(a.lu, sh.s_codes, 16 * t + 4 * g, cd);
-            const float avr[4] = {av.x, av.y, av.z, av.w};
-            float G[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float l = 0.f, gr = 0.f;
-                if (avr[r] == avr[r]) entry_lg_u(a.lu, sh.lt, cd[r], z[r], avr[r], l, gr);
-                fpart += l;
-                G[r] = gr;
-            }
+            float L4[4], G[4];
+            tile_loss<LK, true>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, z, av, L4, G);
+            fpart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
             s3_resident<KP, PREC>(dx, G, ytf[s]);
         }
     }
@@ -474,12 +538,9 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         if (t < nt) {
             const float4 av = apan[s * 64 + lane];
             const f32x4 zp = zprod<KP, PREC>(yfr[s], xpf);
-            int cd[4];
-            codes_of(a.lu, sh.s_codes, 16 * t + 4 * g, cd);
-            const float avr[4] = {av.x, av.y, av.z, av.w};
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (avr[r] == avr[r]) fppart += entry_l_u(a.lu, sh.lt, cd[r], zp[r], avr[r]);
+            float L4[4], G4[4];
+            tile_loss<LK, false>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av, L4, G4);
+            fppart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
         }
     }
     fppart += __shfl_xor(fppart, 16, 64);
@@ -529,18 +590,11 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         if (t < nt) {
             const int j0 = 16 * t;
             const f32x4 zs = zprod<KP, PREC>(yfr[s], xaf);
-            int cd[4];
-            codes_of(a.lu, sh.s_codes, j0 + 4 * g, cd);
             const float4 av = apan[s * 64 + lane];
-            const float avr[4] = {av.x, av.y, av.z, av.w};
-            float G[4], gT[4], hl[4];
+            float L4[4], G[4], gT[4], hl[4];
+            tile_loss<LK, true>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zs, av, L4, G);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float l = 0.f, gr = 0.f;
-                if (avr[r] == avr[r]) entry_lg_u(a.lu, sh.lt, cd[r], zs[r], avr[r], l, gr);
-                hl[r] = sum_lanes<16>(l);
-                G[r] = gr;
-            }
+            for (int r = 0; r < 4; ++r) hl[r] = sum_lanes<16>(L4[r]);
             if (li == 0) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) sh.s_h[j0 + 4 * g + r] += hl[r];
@@ -551,7 +605,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     }
 }
 
-template <int KP, int TPW, int PREC>
+template <int KP, int TPW, int PREC, int LK>
 __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -566,6 +620,8 @@ __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
         sh.s_codes[j] = a.codes[j];
     }
     if (threadIdx.x == 0) sh.lt = a.lt;
+    __syncthreads();
+    tile_codes(sh.s_codes, nt, sh.s_tcode, NTX);
     // this wavefront's tiles of Y (fixed during the X half-step), resident in registers
     Frag<KP, PREC> yfr[TPW];
     YtFrag<KP, PREC> ytf[TPW];
@@ -587,9 +643,9 @@ __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
         stage_panel<KP, TPW>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, blockIdx.x, w, lane);
     for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
         const int64_t p1 = p + G, p2 = p + 2 * G;
-        xstep_panel<KP, TPW, PREC, 0>(a, sh, p, p1 < npanels ? p1 : -1, yfr, ytf, dyacc, rowreg_acc, rej_acc);
+        xstep_panel<KP, TPW, PREC, LK, 0>(a, sh, p, p1 < npanels ? p1 : -1, yfr, ytf, dyacc, rowreg_acc, rej_acc);
         if (p1 < npanels)
-            xstep_panel<KP, TPW, PREC, 1>(a, sh, p1, p2 < npanels ? p2 : -1, yfr, ytf, dyacc, rowreg_acc,
+            xstep_panel<KP, TPW, PREC, LK, 1>(a, sh, p1, p2 < npanels ? p2 : -1, yfr, ytf, dyacc, rowreg_acc,
                                           rej_acc);
     }
     __syncthreads();
@@ -629,9 +685,20 @@ __global__ __launch_bounds__(256) void yprox_kernel(YProxArgs a)
     const int64_t j = t / KP;
     const int c = (int)(t % KP);
     const bool valid = j < a.n;
+    // fixed-order reduction of the P partials, eight independent running sums
     float gsum = 0.0f;
-    if (valid)
-        for (int p = 0; p < a.P; ++p) gsum += a.part_dy[((int64_t)p * a.ldp + j) * KP + c];
+    if (valid) {
+        const float *src = a.part_dy + j * KP + c;
+        const int64_t stride = a.ldp * KP;
+        float s8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        int p = 0;
+        for (; p + 8 <= a.P; p += 8) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s8[q] += src[(p + q) * stride];
+        }
+        for (; p < a.P; ++p) s8[0] += src[p * stride];
+        gsum = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+    }
     const float y = (valid && c < a.k) ? a.Y[j * a.k + c] : 0.0f;
     const float al = valid ? a.alpha[j] : 0.0f;
     const float yv = (valid && c < a.k) ? prox_elem(a.ry, al, y - al * gsum) : 0.0f;
@@ -650,9 +717,13 @@ __global__ __launch_bounds__(256) void yprox_kernel(YProxArgs a)
     float rcp = (valid && c < a.k) ? reg_elem(a.ry, yv) : 0.0f;
     rc = sum_lanes<KP>(rc);
     rcp = sum_lanes<KP>(rcp);
+    // column objective: the KP lanes of the column split the partials, then a
+    // butterfly (identical in every lane) combines them
+    float h = 0.0f;
+    if (valid)
+        for (int p = c; p < a.P; p += KP) h += a.part_h[(int64_t)p * a.ldp + j];
+    h = sum_lanes<KP>(h);
     if (valid && c == 0) {
-        float h = 0.0f;
-        for (int p = 0; p < a.P; ++p) h += a.part_h[(int64_t)p * a.ldp + j];
         a.h_old[j] = h + rc;
         a.ry_plus[j] = rcp;
         a.ry_old[j] = rc;
@@ -668,9 +739,10 @@ struct YCheckShared {
     float xs[16][KP];
     LossTab lt;
     uint8_t s_codes[16 * NWX * TPW];
+    int8_t s_tcode[NWX * TPW];
 };
 
-template <int KP, int TPW, int PREC, int BUF>
+template <int KP, int TPW, int PREC, int LK, int BUF>
 __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP, TPW> &sh, int64_t p,
                                              int64_t p_next, const Frag<KP, PREC> (&yfr)[TPW], f32x4 (&hacc)[TPW])
 {
@@ -699,17 +771,15 @@ __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP
         if (t < nt) {
             const float4 av = apan[s * 64 + lane];
             const f32x4 zp = zprod<KP, PREC>(yfr[s], xf);
-            int cd[4];
-            codes_of(a.lu, sh.s_codes, 16 * t + 4 * g, cd);
-            const float avr[4] = {av.x, av.y, av.z, av.w};
+            float L4[4], G4[4];
+            tile_loss<LK, false>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av, L4, G4);
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (avr[r] == avr[r]) hacc[s][r] += entry_l_u(a.lu, sh.lt, cd[r], zp[r], avr[r]);
+            for (int r = 0; r < 4; ++r) hacc[s][r] += L4[r];
         }
     }
 }
 
-template <int KP, int TPW, int PREC>
+template <int KP, int TPW, int PREC, int LK>
 __global__ __launch_bounds__(NTX, 1) void ycheck_kernel(YCheckArgs a)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -721,6 +791,8 @@ __global__ __launch_bounds__(NTX, 1) void ycheck_kernel(YCheckArgs a)
 
     for (int j = threadIdx.x; j < a.ldp; j += NTX) sh.s_codes[j] = a.codes[j];
     if (threadIdx.x == 0) sh.lt = a.lt;
+    __syncthreads();
+    tile_codes(sh.s_codes, nt, sh.s_tcode, NTX);
     Frag<KP, PREC> yfr[TPW];
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
@@ -735,8 +807,8 @@ __global__ __launch_bounds__(NTX, 1) void ycheck_kernel(YCheckArgs a)
         stage_panel<KP, TPW>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, blockIdx.x, w, lane);
     for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
         const int64_t p1 = p + G, p2 = p + 2 * G;
-        ycheck_panel<KP, TPW, PREC, 0>(a, sh, p, p1 < npanels ? p1 : -1, yfr, hacc);
-        if (p1 < npanels) ycheck_panel<KP, TPW, PREC, 1>(a, sh, p1, p2 < npanels ? p2 : -1, yfr, hacc);
+        ycheck_panel<KP, TPW, PREC, LK, 0>(a, sh, p, p1 < npanels ? p1 : -1, yfr, hacc);
+        if (p1 < npanels) ycheck_panel<KP, TPW, PREC, LK, 1>(a, sh, p1, p2 < npanels ? p2 : -1, yfr, hacc);
     }
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
@@ -767,9 +839,11 @@ __global__ __launch_bounds__(256) void yaccept_kernel(YAcceptArgs a)
     int acc = 0;
     double Fj = 0.0;
     int rj = 0;
+    float hp = 0.0f;
+    if (valid)
+        for (int p = c; p < a.P; p += KP) hp += a.part_hp[(int64_t)p * a.ldp + j];
+    hp = sum_lanes<KP>(hp);   // the same value in every lane of the column
     if (valid) {
-        float hp = 0.0f;
-        for (int p = 0; p < a.P; ++p) hp += a.part_hp[(int64_t)p * a.ldp + j];
         hp += a.ry_plus[j];
         const float h = a.h_old[j];
         acc = hp <= h ? 1 : 0;

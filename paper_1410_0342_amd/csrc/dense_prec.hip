@@ -43,21 +43,29 @@ namespace glrm {
     }
 
 
+// The quadratic loss (every column) gets its own instances; everything else
+// goes through the per-tile loss selection.
+#define GLRM_DISPATCH_LK(QUAD_ONLY, ...)                              \
+    if (QUAD_ONLY) { constexpr int LK = L_QUAD; __VA_ARGS__; }        \
+    else { constexpr int LK = -1; __VA_ARGS__; }
+
 template <int PREC>
 hipError_t launch_xstep_p(const XStepArgs &a, int kp, int tpw, int grid, hipStream_t st)
 {
-    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPWX(tpw,
+    const bool quad = a.lu.kind == L_QUAD;
+    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPWX(tpw, GLRM_DISPATCH_LK(quad,
         if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
-        else hipLaunchKernelGGL((xstep_kernel<KP, TPW, PREC>), dim3(grid), dim3(NTX), 0, st, a)));
+        else hipLaunchKernelGGL((xstep_kernel<KP, TPW, PREC, LK>), dim3(grid), dim3(NTX), 0, st, a))));
     return hipGetLastError();
 }
 
 template <int PREC>
 hipError_t launch_ycheck_p(const YCheckArgs &a, int kp, int tpw, int grid, hipStream_t st)
 {
-    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPWX(tpw,
+    const bool quad = a.lu.kind == L_QUAD;
+    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPWX(tpw, GLRM_DISPATCH_LK(quad,
         if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
-        else hipLaunchKernelGGL((ycheck_kernel<KP, TPW, PREC>), dim3(grid), dim3(NTX), 0, st, a)));
+        else hipLaunchKernelGGL((ycheck_kernel<KP, TPW, PREC, LK>), dim3(grid), dim3(NTX), 0, st, a))));
     return hipGetLastError();
 }
 

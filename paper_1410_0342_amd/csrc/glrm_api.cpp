@@ -243,8 +243,12 @@ int check_ws(const Layout &L, void *ws, size_t ws_bytes)
 int prepare(const glrm_data *d, const Layout &L, void *ws, hipStream_t st)
 {
     // loss codes: host -> workspace (padded columns get code 0)
+    // padding columns repeat the last column's code, so the last tile keeps one loss
     std::string codes((size_t)L.ldp, '\0');
-    if (d->col_loss) memcpy(&codes[0], d->col_loss, (size_t)d->n);
+    if (d->col_loss) {
+        memcpy(&codes[0], d->col_loss, (size_t)d->n);
+        for (int64_t j = d->n; j < L.ldp; ++j) codes[(size_t)j] = (char)d->col_loss[d->n - 1];
+    }
     HIP_TRY(hipMemcpyAsync(at<uint8_t>(ws, L.codes), codes.data(), (size_t)L.ldp, hipMemcpyHostToDevice, st));
     if (d->layout == GLRM_DENSE) {
         HIP_TRY(launch_fill_i32(at<int32_t>(ws, L.col_count), L.n, 0, st));

@@ -68,69 +68,76 @@ __device__ __forceinline__ void ordinal_loss(T u, T a, int d, T &l, T &g, bool w
     if (want_g) g = T(n2 - n1);
 }
 
-// Loss value and derivative in u, float.
+// Loss value and derivative in u, float, for a loss kind known at compile time.
+template <int K>
+__device__ __forceinline__ void loss_lg_k(int levels, float param, float u, float a, float &l, float &g)
+{
+    if constexpr (K == L_QUAD) {
+        const float d = u - a;
+        l = d * d;
+        g = 2.0f * d;
+    } else if constexpr (K == L_HUBER) {
+        const float r = u - a, ar = fabsf(r);
+        if (ar <= param) { l = 0.5f * r * r; g = r; }
+        else { l = param * ar - 0.5f * param * param; g = r > 0.0f ? param : -param; }
+    } else if constexpr (K == L_LOGISTIC) {
+        // t = -a u;  l = max(t,0) + log1p(exp(-|t|));  dl/du = -a sigmoid(t)
+        const float t = -a * u;
+        const float e = __expf(-fabsf(t));
+        const float inv = __builtin_amdgcn_rcpf(1.0f + e);
+        l = fmaxf(t, 0.0f) + log1pf(e);
+        g = -a * (t >= 0.0f ? inv : e * inv);
+    } else if constexpr (K == L_HINGE) {
+        const float au = a * u;
+        if (au < 1.0f) { l = 1.0f - au; g = -a; }
+        else { l = 0.0f; g = 0.0f; }
+    } else {
+        ordinal_loss<float>(u, a, levels, l, g, true);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ float loss_l_k(int levels, float param, float u, float a)
+{
+    if constexpr (K == L_QUAD) {
+        const float d = u - a;
+        return d * d;
+    } else if constexpr (K == L_HUBER) {
+        const float r = u - a, ar = fabsf(r);
+        return ar <= param ? 0.5f * r * r : param * ar - 0.5f * param * param;
+    } else if constexpr (K == L_LOGISTIC) {
+        const float t = -a * u;
+        return fmaxf(t, 0.0f) + log1pf(__expf(-fabsf(t)));
+    } else if constexpr (K == L_HINGE) {
+        const float au = a * u;
+        return au < 1.0f ? 1.0f - au : 0.0f;
+    } else {
+        float l, g;
+        ordinal_loss<float>(u, a, levels, l, g, false);
+        return l;
+    }
+}
+
+// The same with the kind chosen at run time.
 __device__ __forceinline__ void loss_lg(int kind, int levels, float param, float u, float a, float &l, float &g)
 {
     switch (kind) {
-    case L_QUAD: {
-        float d = u - a;
-        l = d * d;
-        g = 2.0f * d;
-        break;
-    }
-    case L_HUBER: {
-        float r = u - a, ar = fabsf(r);
-        if (ar <= param) { l = 0.5f * r * r; g = r; }
-        else { l = param * ar - 0.5f * param * param; g = r > 0.0f ? param : -param; }
-        break;
-    }
-    case L_LOGISTIC: {
-        // t = -a u;  l = max(t,0) + log1p(exp(-|t|));  dl/du = -a sigmoid(t)
-        float t = -a * u;
-        float e = __expf(-fabsf(t));
-        float inv = __builtin_amdgcn_rcpf(1.0f + e);
-        l = fmaxf(t, 0.0f) + log1pf(e);
-        float sig = t >= 0.0f ? inv : e * inv;
-        g = -a * sig;
-        break;
-    }
-    case L_HINGE: {
-        float au = a * u;
-        if (au < 1.0f) { l = 1.0f - au; g = -a; }
-        else { l = 0.0f; g = 0.0f; }
-        break;
-    }
-    default: {  // L_ORDINAL
-        ordinal_loss<float>(u, a, levels, l, g, true);
-        break;
-    }
+    case L_QUAD: loss_lg_k<L_QUAD>(levels, param, u, a, l, g); break;
+    case L_HUBER: loss_lg_k<L_HUBER>(levels, param, u, a, l, g); break;
+    case L_LOGISTIC: loss_lg_k<L_LOGISTIC>(levels, param, u, a, l, g); break;
+    case L_HINGE: loss_lg_k<L_HINGE>(levels, param, u, a, l, g); break;
+    default: loss_lg_k<L_ORDINAL>(levels, param, u, a, l, g); break;
     }
 }
 
 __device__ __forceinline__ float loss_l(int kind, int levels, float param, float u, float a)
 {
     switch (kind) {
-    case L_QUAD: {
-        float d = u - a;
-        return d * d;
-    }
-    case L_HUBER: {
-        float r = u - a, ar = fabsf(r);
-        return ar <= param ? 0.5f * r * r : param * ar - 0.5f * param * param;
-    }
-    case L_LOGISTIC: {
-        float t = -a * u;
-        return fmaxf(t, 0.0f) + log1pf(__expf(-fabsf(t)));
-    }
-    case L_HINGE: {
-        float au = a * u;
-        return au < 1.0f ? 1.0f - au : 0.0f;
-    }
-    default: {
-        float l, g;
-        ordinal_loss<float>(u, a, levels, l, g, false);
-        return l;
-    }
+    case L_QUAD: return loss_l_k<L_QUAD>(levels, param, u, a);
+    case L_HUBER: return loss_l_k<L_HUBER>(levels, param, u, a);
+    case L_LOGISTIC: return loss_l_k<L_LOGISTIC>(levels, param, u, a);
+    case L_HINGE: return loss_l_k<L_HINGE>(levels, param, u, a);
+    default: return loss_l_k<L_ORDINAL>(levels, param, u, a);
     }
 }
 
