@@ -64,17 +64,19 @@ __global__ __launch_bounds__(256) void objective64_kernel(Obj64Args a)
         }
         __syncthreads();
         if (j < a.n) {
+            float avs[16];   // the column's 16 entries, all loads in flight at once
+#pragma unroll
+            for (int ii = 0; ii < 16; ++ii) avs[ii] = a.Ap[(i0 + ii) * a.ldp + j];
             double y[KP];
 #pragma unroll
             for (int c = 0; c < KP; ++c) y[c] = c < a.k ? (double)a.Y[j * a.k + c] : 0.0;
             const int q = a.lt.uniform >= 0 ? a.lt.uniform : a.codes[j];
             const int kind = a.lt.kind[q], lev = a.lt.levels[q];
             const double par = (double)a.lt.param[q];
+#pragma unroll
             for (int ii = 0; ii < 16; ++ii) {
-                const int64_t i = i0 + ii;
-                if (i >= a.m) break;
-                const float av = a.Ap[i * a.ldp + j];
-                if (av == av) {
+                const float av = avs[ii];
+                if (i0 + ii < a.m && av == av) {
                     double z = 0.0;
 #pragma unroll
                     for (int c = 0; c < KP; ++c) z += xsd[ii][c] * y[c];

@@ -40,6 +40,7 @@ int fail(int code, const char *fmt, ...)
 constexpr int P_MAX = 256;     // workgroups of the persistent dense kernels
 constexpr int NWAVES = 8;      // wavefronts per dense workgroup (matches the kernels)
 constexpr int REG_BLOCKS = 64; // partials of a regularizer sum
+constexpr int OBJ64_BLOCKS = 2048;  // workgroups (and partials) of the FP64 objective
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -71,7 +72,7 @@ struct Layout {
     size_t part_dy, part_h, part_hp, part_rowreg, part_rej, part_dx, part_obj;
     size_t ycur_f32, ycur_t32, ycur_hi, ycur_lo, ycur_tb;
     size_t yp_f32, yp_t32, yp_hi, yp_lo, yp_tb;
-    size_t Yplus, h_old, ry_plus, ry_old, part_F, part_rejc, stats, istats, regpart, scal;
+    size_t Yplus, h_old, ry_plus, ry_old, part_F, part_rejc, stats, istats, regpart, scal, part_obj64;
     size_t coo;            // start of the COO region
     CooLayout cl;
     int64_t cb_grad;       // column blocks of the gradient kernel
@@ -107,6 +108,7 @@ bool make_layout(const glrm_data *d, Layout &L)
     L.istats = L.take(sizeof(long long) * 8);
     L.scal = L.take(sizeof(double) * 8);
     L.regpart = L.take(sizeof(double) * 2 * REG_BLOCKS);
+    L.part_obj64 = L.take(sizeof(double) * OBJ64_BLOCKS);
     L.ycur_f32 = L.take(sizeof(float) * ldp * kp);
     L.ycur_t32 = L.take(sizeof(float) * ldp * kp);
     L.ycur_hi = L.take(2 * ldp * kp);
@@ -295,7 +297,7 @@ int reg_sums(const glrm_data *d, const Layout &L, const float *X, const float *Y
 int objective64(const glrm_data *d, const Layout &L, const float *X, const float *Y, void *ws, double *out_dev,
                 hipStream_t st)
 {
-    double *po = at<double>(ws, d->layout == GLRM_DENSE ? L.part_obj : L.scal);
+    double *po = at<double>(ws, d->layout == GLRM_DENSE ? L.part_obj64 : L.scal);
     int nparts = 0;
     if (d->layout == GLRM_DENSE) {
         Obj64Args a;
@@ -305,7 +307,8 @@ int objective64(const glrm_data *d, const Layout &L, const float *X, const float
         a.lt = make_losstab(d);
         a.X = X; a.Y = Y;
         a.part_obj = po;
-        nparts = P_MAX;
+        const int64_t tiles = (L.mp / 16) * ((L.ldp + 255) / 256);
+        nparts = (int)std::min<int64_t>(OBJ64_BLOCKS, std::max<int64_t>(1, tiles));
         HIP_TRY(launch_objective64(a, nparts, st));
     } else {
         int rc = coo_objective(d, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
