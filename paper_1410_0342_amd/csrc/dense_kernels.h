@@ -320,12 +320,49 @@ __device__ __forceinline__ void s3_resident(f32x4 (&dx)[KP / 16], const float (&
             dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[3], yt.f[kb].w, dx[kb], 0, 0, 0);
         }
     } else {
-        i16x4 av;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) av[s] = bf16_bits(to_bf16(G[s]));
+        const i16x4 av = pack_bf16x4(G[0], G[1], G[2], G[3]);
 #pragma unroll
         for (int kb = 0; kb < KP / 16; ++kb)
             dx[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, yt.b[kb], dx[kb], 0, 0, 0);
+    }
+}
+
+// The S6 operand X(16i x 16kc) of a panel, from the transposed accepted rows
+// (xat, [kc][i]): fixed for the whole panel, so it is read and rounded once.
+template <int KP, int PREC>
+struct XatFrag {
+    float4 f[PREC == P_FP32 ? KP / 16 : 1];
+    i16x4 b[PREC == P_FP32 ? 1 : KP / 16];
+};
+
+template <int KP, int PREC>
+__device__ __forceinline__ void xatfrag_load(XatFrag<KP, PREC> &xa, const float *xat, int li, int g)
+{
+#pragma unroll
+    for (int kb = 0; kb < KP / 16; ++kb) {
+        const float4 b = *reinterpret_cast<const float4 *>(xat + (16 * kb + li) * GS + 4 * g);
+        if constexpr (PREC == P_FP32) xa.f[kb] = b;
+        else xa.b[kb] = pack_bf16x4(b.x, b.y, b.z, b.w);
+    }
+}
+
+// S6 with the panel operand in registers: dY(16j x 16kc) += G^T(16j x 16i) . X(16i x 16kc).
+template <int KP, int PREC>
+__device__ __forceinline__ void s6_resident(f32x4 (&dy)[KP / 16], const float (&gT)[4], const XatFrag<KP, PREC> &xa)
+{
+    if constexpr (PREC == P_FP32) {
+#pragma unroll
+        for (int kb = 0; kb < KP / 16; ++kb) {
+            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gT[0], xa.f[kb].x, dy[kb], 0, 0, 0);
+            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gT[1], xa.f[kb].y, dy[kb], 0, 0, 0);
+            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gT[2], xa.f[kb].z, dy[kb], 0, 0, 0);
+            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gT[3], xa.f[kb].w, dy[kb], 0, 0, 0);
+        }
+    } else {
+        const i16x4 av = pack_bf16x4(gT[0], gT[1], gT[2], gT[3]);
+#pragma unroll
+        for (int kb = 0; kb < KP / 16; ++kb)
+            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, xa.b[kb], dy[kb], 0, 0, 0);
     }
 }
 
@@ -427,57 +464,74 @@ __device__ __forceinline__ void tile_codes(const uint8_t *s_codes, int nt, int8_
 // ---------------------------------------------------------------------------
 // pass 1: fused X half-step (S1-S5) + Y-gradient and column-objective partials (S6)
 // ---------------------------------------------------------------------------
+// Row stride (floats) of the per-panel [16][kp] arrays: with kp + 4 the four
+// lane groups of a fragment read, and of the S3 partial writes, fall in
+// different LDS banks.
+template <int KP>
+constexpr int RS = KP + 4;
+
 template <int KP, int TPW, int PREC>
 struct XStepShared {
     PanelBuf<KP, TPW> buf0, buf1;
-    float xs[16][KP];        // the panel's X (zero padded), later the accepted X
-    float xp[16][KP];        // trial rows
+    float xs[16][RS<KP>];    // the accepted rows (S6 operand)
+    float xp[16][RS<KP>];    // trial rows
     union alignas(16) {
-        float red_g[NWX][16][KP + 1];     // row-gradient partials (S3 -> S4)
+        float red_g[NWX][16][RS<KP>];     // row-gradient partials (S3 -> S4)
         struct {
             float gsc[NWX][16 * GS];      // per-wavefront G transpose tiles (S6)
             float xat[KP * GS];           // accepted X transposed ([kc][i]) for S6
         } d;
     } u;
-    float red_f[NWX][16];
+    float red_f[NWX][4][16];    // row-objective partials per wavefront and lane group
     LossTab lt;                 // per-column loss table (mixed tables only)
     float s_h[16 * NWX * TPW];  // column objectives of this workgroup
     uint8_t s_codes[16 * NWX * TPW];
     int8_t s_tcode[NWX * TPW];
-    float s_f[16], s_rx[16], s_rxp[16], s_al[16];
-    int s_acc[16];
+    float s_f[16], s_rx[16], s_rxp[16];
     float s_blk[NWX];
     int s_rej[NWX];
 };
 
+// One 16-row panel of the fused X half-step.  Five workgroup barriers: the
+// staged panel, the row-gradient partials, the trial rows, the trial
+// objective partials and the accepted rows.  The row steps (S4) and the
+// decisions run on sixteen lanes per row (256 threads = 16 rows x 16 lanes),
+// so their row sums are DPP row reductions.
 template <int KP, int TPW, int PREC, int LK, int BUF>
 __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, TPW, PREC> &sh, int64_t p,
                                             int64_t p_next, const Frag<KP, PREC> (&yfr)[TPW],
                                             const YtFrag<KP, PREC> (&ytf)[TPW], f32x4 (&dyacc)[TPW][KP / 16],
                                             float &rowreg_acc, int &rej_acc)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    static_assert(NTX == 256, "row steps map 16 rows x 16 lanes onto the workgroup");
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     constexpr int C = KP / 4;
     const int nt = (int)(a.ldp / 16);
+    const int k = a.k;
     PanelBuf<KP, TPW> &cur = BUF == 0 ? sh.buf0 : sh.buf1;
     PanelBuf<KP, TPW> &nxt = BUF == 0 ? sh.buf1 : sh.buf0;
     const float4 *apan = cur.apan[w];
     const int64_t i0 = p * 16;
+    const int rows = (int)min<int64_t>(16, a.m - i0);
+    // the row-step thread map: row ri, coordinates c0 + 16 q
+    const int ri = threadIdx.x >> 4, c0 = threadIdx.x & 15;
+    const bool rv = ri < rows;
 
     wait_staged();
 
-    // the panel's X rows, zero padded to kp; rows past m are zero
-    for (int t = threadIdx.x; t < 16 * KP; t += NTX) {
-        const int i = t / KP, c = t % KP;
-        sh.xs[i][c] = (i0 + i < a.m && c < a.k) ? cur.xrow[i * a.k + c] : 0.0f;
-    }
-    if (threadIdx.x < 16) sh.s_al[threadIdx.x] = i0 + threadIdx.x < a.m ? cur.alpha[threadIdx.x] : 0.0f;
-    __syncthreads();
-
     // ---- S1-S3: z, loss, derivative, row objective, row gradient ------------------
+    // the panel's X rows straight from the staged block (16 x k, contiguous)
     Frag<KP, PREC> xf;
-    frag_from_f32<KP, PREC>(xf, &sh.xs[li][g * C]);
+    {
+        float xv[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int c = g * C + q;
+            xv[q] = (li < rows && c < k) ? cur.xrow[li * k + c] : 0.0f;
+        }
+        frag_from_f32<KP, PREC>(xf, xv);
+    }
     float fpart = 0.0f;
     f32x4 dx[KP / 16];
 #pragma unroll
@@ -494,9 +548,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             s3_resident<KP, PREC>(dx, G, ytf[s]);
         }
     }
-    fpart += __shfl_xor(fpart, 16, 64);
-    fpart += __shfl_xor(fpart, 32, 64);
-    if (g == 0) sh.red_f[w][li] = fpart;
+    sh.red_f[w][g][li] = fpart;
 #pragma unroll
     for (int kb = 0; kb < KP / 16; ++kb)
 #pragma unroll
@@ -504,26 +556,32 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     __syncthreads();
 
     // ---- S4: prox step and regularizer values ------------------------------------
-    for (int t = threadIdx.x; t < 16 * KP; t += NTX) {
-        const int i = t / KP, c = t % KP;
-        float gs = 0.0f;
+    {
+        const float al = rv ? cur.alpha[ri] : 0.0f;
+        float rc = 0.0f, rcp = 0.0f;
 #pragma unroll
-        for (int q = 0; q < NWX; ++q) gs += sh.u.red_g[q][i][c];
-        const float x = sh.xs[i][c];
-        const float al = sh.s_al[i];
-        const float xv = (c < a.k) ? prox_elem(a.rx, al, x - al * gs) : 0.0f;
-        sh.xp[i][c] = xv;
-        float rc = c < a.k ? reg_elem(a.rx, x) : 0.0f;
-        float rcp = c < a.k ? reg_elem(a.rx, xv) : 0.0f;
-        rc = sum_lanes<KP>(rc);
-        rcp = sum_lanes<KP>(rcp);
-        if (c == 0) {
+        for (int q = 0; q < KP / 16; ++q) {
+            const int c = c0 + 16 * q;
+            float gs = 0.0f;
+#pragma unroll
+            for (int v = 0; v < NWX; ++v) gs += sh.u.red_g[v][ri][c];
+            const bool ok = rv && c < k;
+            const float x = ok ? cur.xrow[ri * k + c] : 0.0f;
+            const float xv = ok ? prox_elem(a.rx, al, x - al * gs) : 0.0f;
+            sh.xp[ri][c] = xv;
+            rc += ok ? reg_elem(a.rx, x) : 0.0f;
+            rcp += ok ? reg_elem(a.rx, xv) : 0.0f;
+        }
+        rc = row16_sum(rc);
+        rcp = row16_sum(rcp);
+        if (c0 == 0) {
             float f = 0.0f;
 #pragma unroll
-            for (int q = 0; q < NWX; ++q) f += sh.red_f[q][i];
-            sh.s_f[i] = f + rc;
-            sh.s_rx[i] = rc;
-            sh.s_rxp[i] = rcp;
+            for (int v = 0; v < NWX; ++v)
+                f += (sh.red_f[v][0][ri] + sh.red_f[v][1][ri]) + (sh.red_f[v][2][ri] + sh.red_f[v][3][ri]);
+            sh.s_f[ri] = f + rc;
+            sh.s_rx[ri] = rc;
+            sh.s_rxp[ri] = rcp;
         }
     }
     __syncthreads();
@@ -543,36 +601,32 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             fppart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
         }
     }
-    fppart += __shfl_xor(fppart, 16, 64);
-    fppart += __shfl_xor(fppart, 32, 64);
-    if (g == 0) sh.red_f[w][li] = fppart;
+    sh.red_f[w][g][li] = fppart;
     __syncthreads();
 
-    // ---- decision per row ------------------------------------------------------------
-    if (threadIdx.x < 16) {
-        const int i = threadIdx.x;
-        const int64_t gi = i0 + i;
-        int acc = 0;
-        if (gi < a.m) {
-            float fp = 0.0f;
+    // ---- decision per row and the accepted rows ---------------------------------------
+    {
+        float fp = 0.0f;
 #pragma unroll
-            for (int q = 0; q < NWX; ++q) fp += sh.red_f[q][i];
-            fp += sh.s_rxp[i];
-            acc = (fp <= sh.s_f[i]) ? 1 : 0;
-            const float al = sh.s_al[i];
-            a.alpha[gi] = acc ? al * a.step_up : al * a.step_down;
-            rowreg_acc += acc ? sh.s_rxp[i] : sh.s_rx[i];
+        for (int v = 0; v < NWX; ++v)
+            fp += (sh.red_f[v][0][ri] + sh.red_f[v][1][ri]) + (sh.red_f[v][2][ri] + sh.red_f[v][3][ri]);
+        fp += sh.s_rxp[ri];
+        const bool acc = rv && fp <= sh.s_f[ri];
+#pragma unroll
+        for (int q = 0; q < KP / 16; ++q) {
+            const int c = c0 + 16 * q;
+            const bool ok = rv && c < k;
+            const float xa = acc ? sh.xp[ri][c] : (ok ? cur.xrow[ri * k + c] : 0.0f);
+            sh.u.d.xat[c * GS + ri] = xa;
+            sh.xs[ri][c] = xa;
+            if (acc && c < k) a.X[(i0 + ri) * k + c] = xa;
+        }
+        if (c0 == 0 && rv) {
+            const float al = cur.alpha[ri];
+            a.alpha[i0 + ri] = acc ? al * a.step_up : al * a.step_down;
+            rowreg_acc += acc ? sh.s_rxp[ri] : sh.s_rx[ri];
             rej_acc += acc ? 0 : 1;
         }
-        sh.s_acc[i] = acc;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < 16 * KP; t += NTX) {
-        const int i = t / KP, c = t % KP;
-        const float xa = sh.s_acc[i] ? sh.xp[i][c] : sh.xs[i][c];
-        sh.u.d.xat[c * GS + i] = xa;
-        sh.xs[i][c] = xa;
-        if (sh.s_acc[i] && c < a.k) a.X[(i0 + i) * a.k + c] = xa;
     }
     __syncthreads();
 
@@ -582,6 +636,8 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
 
     // ---- S6: column objective and Y gradient from the accepted rows -------------------
     float *gsc = sh.u.d.gsc[w];
+    XatFrag<KP, PREC> xa;
+    xatfrag_load<KP, PREC>(xa, sh.u.d.xat, li, g);
     Frag<KP, PREC> xaf;
     frag_from_f32<KP, PREC>(xaf, &sh.xs[li][g * C]);
 #pragma unroll
@@ -594,13 +650,16 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             float L4[4], G[4], gT[4], hl[4];
             tile_loss<LK, true>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zs, av, L4, G);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) hl[r] = sum_lanes<16>(L4[r]);
+            for (int r = 0; r < 4; ++r) hl[r] = row16_sum(L4[r]);
+            // column j belongs to this wavefront alone: no other lane adds to it
             if (li == 0) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) sh.s_h[j0 + 4 * g + r] += hl[r];
+                for (int r = 0; r < 4; ++r)
+                    __hip_atomic_fetch_add(&sh.s_h[j0 + 4 * g + r], hl[r], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
             }
             transpose_g(gsc, G, gT, li, g);
-            s6_accum<KP, PREC>(dyacc[s], gT, sh.u.d.xat, li, g);
+            s6_resident<KP, PREC>(dyacc[s], gT, xa);
         }
     }
 }
@@ -608,7 +667,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
 template <int KP, int TPW, int PREC, int LK>
 __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     __shared__ XStepShared<KP, TPW, PREC> sh;
     const int nt = (int)(a.ldp / 16);
@@ -664,14 +723,18 @@ __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
         }
     }
     for (int64_t j = threadIdx.x; j < a.ldp; j += NTX) a.part_h[(int64_t)blockIdx.x * a.ldp + j] = sh.s_h[j];
-    // row regularizers and rejections live on threads 0..15 of wavefront 0
+    // row regularizers and rejections live on the first lane of each row's sixteen
     float rr = sum_lanes<64>(rowreg_acc);
     int rj = (int)sum_lanes<64>((float)rej_acc);
     if (lane == 0) { sh.s_blk[w] = rr; sh.s_rej[w] = rj; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        a.part_rowreg[blockIdx.x] = sh.s_blk[0];
-        a.part_rej[blockIdx.x] = sh.s_rej[0];
+        float rsum = 0.0f;
+        int jsum = 0;
+#pragma unroll
+        for (int v = 0; v < NWX; ++v) { rsum += sh.s_blk[v]; jsum += sh.s_rej[v]; }
+        a.part_rowreg[blockIdx.x] = rsum;
+        a.part_rej[blockIdx.x] = jsum;
     }
 }
 
@@ -736,7 +799,6 @@ __global__ __launch_bounds__(256) void yprox_kernel(YProxArgs a)
 template <int KP, int TPW>
 struct YCheckShared {
     PanelBuf<KP, TPW> buf0, buf1;
-    float xs[16][KP];
     LossTab lt;
     uint8_t s_codes[16 * NWX * TPW];
     int8_t s_tcode[NWX * TPW];
@@ -746,7 +808,7 @@ template <int KP, int TPW, int PREC, int LK, int BUF>
 __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP, TPW> &sh, int64_t p,
                                              int64_t p_next, const Frag<KP, PREC> (&yfr)[TPW], f32x4 (&hacc)[TPW])
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     constexpr int C = KP / 4;
     const int nt = (int)(a.ldp / 16);
@@ -756,15 +818,20 @@ __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP
     const int64_t i0 = p * 16;
 
     wait_staged();
-    for (int t = threadIdx.x; t < 16 * KP; t += NTX) {
-        const int i = t / KP, c = t % KP;
-        sh.xs[i][c] = (i0 + i < a.m && c < a.k) ? cur.xrow[i * a.k + c] : 0.0f;
+    // the panel's X rows straight from the staged block (16 x k, contiguous)
+    const int rows = (int)min<int64_t>(16, a.m - i0);
+    Frag<KP, PREC> xf;
+    {
+        float xv[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int c = g * C + q;
+            xv[q] = (li < rows && c < a.k) ? cur.xrow[li * a.k + c] : 0.0f;
+        }
+        frag_from_f32<KP, PREC>(xf, xv);
     }
-    __syncthreads();
     // no barrier until the next panel: the prefetch overlaps this panel's products
     if (p_next >= 0) stage_panel<KP, TPW>(nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, p_next, w, lane);
-    Frag<KP, PREC> xf;
-    frag_from_f32<KP, PREC>(xf, &sh.xs[li][g * C]);
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
         const int t = w + NWX * s;
@@ -782,7 +849,7 @@ __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP
 template <int KP, int TPW, int PREC, int LK>
 __global__ __launch_bounds__(NTX, 1) void ycheck_kernel(YCheckArgs a)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     __shared__ YCheckShared<KP, TPW> sh;
     const int nt = (int)(a.ldp / 16);
@@ -912,7 +979,7 @@ __global__ __launch_bounds__(256) void yshadow_kernel(YShadowArgs a)
 template <int KP, int TPW, int PREC, bool WANT_GRAD>
 __global__ __launch_bounds__(NT, 1) void lossgrad_kernel(LossGradArgs a)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     constexpr int C = KP / 4;
     __shared__ float xs[16][KP];

@@ -220,7 +220,35 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 &hi, __bf16 &lo)
 
 __device__ __forceinline__ short bf16_bits(__bf16 x) { return __builtin_bit_cast(short, x); }
 
+// Four values to bf16 (round to nearest even), packed as one matrix-core operand.
+__device__ __forceinline__ i16x4 pack_bf16x4(float a, float b, float c, float d)
+{
+    typedef __attribute__((ext_vector_type(2))) float f32x2;
+    typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+    const bf16x2 p0 = __builtin_convertvector((f32x2){a, b}, bf16x2);
+    const bf16x2 p1 = __builtin_convertvector((f32x2){c, d}, bf16x2);
+    const uint2 u = {__builtin_bit_cast(uint32_t, p0), __builtin_bit_cast(uint32_t, p1)};
+    return __builtin_bit_cast(i16x4, u);
+}
+
 // ---- wavefront reductions ----------------------------------------------------
+
+// Sum over each row of sixteen lanes with DPP moves (no LDS traffic); every
+// lane of the row gets a sum, lane 0 of the row always in the same order.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ float row16_sum(float v)
+{
+    v += dpp_mov<0x128>(v);   // row_ror:8
+    v += dpp_mov<0x124>(v);   // row_ror:4
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    return v;
+}
 
 template <int WIDTH>
 __device__ __forceinline__ float sum_lanes(float v)
