@@ -282,6 +282,16 @@ __device__ __forceinline__ void stage_panel(PanelBuf<KP, TPW> &pb, const float *
     if (alpha && w == NWX - 1 && lane < rows) lds_dma4(alpha + i0 + lane, &pb.alpha[0]);
 }
 
+// The lane's four table entries of tile slot s.  A slot past the last tile
+// (its wavefront has fewer tiles than slots) reads as unobserved, so every
+// slot runs the same code and contributes exactly zero.
+__device__ __forceinline__ float4 tile_entries(const float4 *apan, int s, int lane, bool valid)
+{
+    const float4 v = apan[s * 64 + lane];
+    const float qnan = __builtin_nanf("");
+    return valid ? v : float4{qnan, qnan, qnan, qnan};
+}
+
 __device__ __forceinline__ void wait_staged()
 {
     __builtin_amdgcn_s_waitcnt(0);
@@ -390,10 +400,32 @@ __device__ __forceinline__ float entry_l_u(const LossU &lu, const LossTab &tab, 
     return loss_l(tab.kind[code], tab.levels[code], tab.param[code], u, a);
 }
 
-template <int K, bool WANT_G>
+// HALF (quadratic loss only): g is half the derivative, z - a; the caller
+// doubles its reductions instead (exact: a power of two).
+template <int K, bool WANT_G, bool HALF = false>
 __device__ __forceinline__ void tile4(int lev, float par, const f32x4 &z, const float (&a4)[4], float (&l)[4],
                                       float (&g)[4])
 {
+    if constexpr (K == L_QUAD && WANT_G && HALF) {
+        // an unobserved entry (NaN) gives d = 0, hence l = g = 0
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float d = a4[r] == a4[r] ? z[r] - a4[r] : 0.0f;
+            l[r] = d * d;
+            g[r] = d;
+        }
+        return;
+    }
+    if constexpr (K == L_QUAD && !WANT_G) {
+        // NaN propagates into d * d and the IEEE maximum with 0 drops it
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float d = z[r] - a4[r];
+            l[r] = __builtin_fmaxf(d * d, 0.0f);
+            g[r] = 0.0f;
+        }
+        return;
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         float lr = 0.f, gr = 0.f;
@@ -406,6 +438,10 @@ __device__ __forceinline__ void tile4(int lev, float par, const f32x4 &z, const 
     }
 }
 
+// Scale of the derivatives tile_loss<LK> returns (see tile4's HALF).
+template <int LK>
+constexpr float GRAD_SCALE = LK == L_QUAD ? 2.0f : 1.0f;
+
 // Losses (and, with WANT_G, derivatives) of the lane's four entries of tile t.
 // LK >= 0: every column has loss kind LK (compile time).  LK < 0: a tile whose
 // sixteen columns share one loss takes it from a scalar branch on the tile's
@@ -417,7 +453,7 @@ __device__ __forceinline__ void tile_loss(const LossU &lu, const LossTab &tab, c
 {
     const float a4[4] = {av.x, av.y, av.z, av.w};
     if constexpr (LK >= 0) {
-        tile4<LK, WANT_G>(lu.levels, lu.param, z, a4, l, g);
+        tile4<LK, WANT_G, LK == L_QUAD>(lu.levels, lu.param, z, a4, l, g);
     } else {
         const int tc = __builtin_amdgcn_readfirstlane((int)s_tcode[t]);
         if (tc >= 0) {
@@ -484,13 +520,66 @@ struct XStepShared {
     } u;
     float red_f[NWX][4][16];    // row-objective partials per wavefront and lane group
     LossTab lt;                 // per-column loss table (mixed tables only)
-    float s_h[16 * NWX * TPW];  // column objectives of this workgroup
     uint8_t s_codes[16 * NWX * TPW];
     int8_t s_tcode[NWX * TPW];
     float s_f[16], s_rx[16], s_rxp[16];
     float s_blk[NWX];
     int s_rej[NWX];
 };
+
+// Reduce-scatter of four column values over a row of sixteen lanes (DPP):
+// lane li gets column r = 2 (li/8 mod 2) + (li/4 mod 2) summed over itself and
+// its mirror partners (lanes of one quad together hold the whole column).
+__device__ __forceinline__ float col_partial(const float (&v)[4], int li)
+{
+    const bool b8 = li & 8, b4 = li & 4;
+    float k0 = b8 ? v[2] : v[0], k1 = b8 ? v[3] : v[1];
+    const float s0 = b8 ? v[0] : v[2], s1 = b8 ? v[1] : v[3];
+    k0 += dpp_mov<0x140>(s0);   // row_mirror: partner 15 - li
+    k1 += dpp_mov<0x140>(s1);
+    float kk = b4 ? k1 : k0;
+    const float ss = b4 ? k0 : k1;
+    kk += dpp_mov<0x141>(ss);   // row_half_mirror: partner 7 - (li mod 8)
+    return kk;
+}
+
+// S6 of one panel, with the next panel's loads issued first.  The LDS
+// operands come in as restrict pointers so that the compiler can tell the
+// direct-to-LDS loads into the other buffer apart from the reads here and
+// need not wait for them (the compiler drains them at every barrier anyway,
+// and S6 has none).
+template <int KP, int TPW, int PREC, int LK>
+__device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW> *__restrict__ nxt, int64_t p_next,
+                                         const float4 *__restrict__ apan, float *__restrict__ gsc,
+                                         const LossTab *__restrict__ lt, const uint8_t *__restrict__ s_codes,
+                                         const int8_t *__restrict__ s_tcode, const Frag<KP, PREC> (&yfr)[TPW],
+                                         const XatFrag<KP, PREC> &xa, const Frag<KP, PREC> &xaf,
+                                         f32x4 (&dyacc)[TPW][KP / 16], float (&hacc)[TPW])
+{
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, g = lane >> 4;
+    const int nt = (int)(a.ldp / 16);
+    if (p_next >= 0) stage_panel<KP, TPW>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = w + NWX * s;
+        // a branch per tile: straight-line tiles raise register pressure past
+        // what the resident operands leave
+        if (t >= nt) continue;
+        const int j0 = 16 * t;
+        const f32x4 zs = zprod<KP, PREC>(yfr[s], xaf);
+        const float4 av = apan[s * 64 + lane];
+        float L4[4], G[4], gT[4];
+        tile_loss<LK, true>(a.lu, *lt, s_codes, s_tcode, t, zs, av, L4, G);
+        // column objective: a reduce-scatter of the lane's four entries over
+        // the row of sixteen lanes leaves lane li with a partial sum of column
+        // 4g + 2 (li/8 mod 2) + (li/4 mod 2); it accumulates in a register
+        // across panels and the quad's four partials are added at the end
+        hacc[s] += col_partial(L4, li);
+        transpose_g(gsc, G, gT, li, g);
+        s6_resident<KP, PREC>(dyacc[s], gT, xa);
+    }
+}
 
 // One 16-row panel of the fused X half-step.  Five workgroup barriers: the
 // staged panel, the row-gradient partials, the trial rows, the trial
@@ -501,7 +590,7 @@ template <int KP, int TPW, int PREC, int LK, int BUF>
 __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, TPW, PREC> &sh, int64_t p,
                                             int64_t p_next, const Frag<KP, PREC> (&yfr)[TPW],
                                             const YtFrag<KP, PREC> (&ytf)[TPW], f32x4 (&dyacc)[TPW][KP / 16],
-                                            float &rowreg_acc, int &rej_acc)
+                                            float (&hacc)[TPW], float &rowreg_acc, int &rej_acc)
 {
     static_assert(NTX == 256, "row steps map 16 rows x 16 lanes onto the workgroup");
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -565,6 +654,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             float gs = 0.0f;
 #pragma unroll
             for (int v = 0; v < NWX; ++v) gs += sh.u.red_g[v][ri][c];
+            gs *= GRAD_SCALE<LK>;
             const bool ok = rv && c < k;
             const float x = ok ? cur.xrow[ri * k + c] : 0.0f;
             const float xv = ok ? prox_elem(a.rx, al, x - al * gs) : 0.0f;
@@ -630,38 +720,13 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     }
     __syncthreads();
 
-    // The next panel's loads go out now: the compiler drains outstanding
-    // direct-to-LDS loads at every barrier, and S6 below has none.
-    if (p_next >= 0) stage_panel<KP, TPW>(nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
-
     // ---- S6: column objective and Y gradient from the accepted rows -------------------
-    float *gsc = sh.u.d.gsc[w];
     XatFrag<KP, PREC> xa;
     xatfrag_load<KP, PREC>(xa, sh.u.d.xat, li, g);
     Frag<KP, PREC> xaf;
     frag_from_f32<KP, PREC>(xaf, &sh.xs[li][g * C]);
-#pragma unroll
-    for (int s = 0; s < TPW; ++s) {
-        const int t = w + NWX * s;
-        if (t < nt) {
-            const int j0 = 16 * t;
-            const f32x4 zs = zprod<KP, PREC>(yfr[s], xaf);
-            const float4 av = apan[s * 64 + lane];
-            float L4[4], G[4], gT[4], hl[4];
-            tile_loss<LK, true>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zs, av, L4, G);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) hl[r] = row16_sum(L4[r]);
-            // column j belongs to this wavefront alone: no other lane adds to it
-            if (li == 0) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    __hip_atomic_fetch_add(&sh.s_h[j0 + 4 * g + r], hl[r], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-            transpose_g(gsc, G, gT, li, g);
-            s6_resident<KP, PREC>(dyacc[s], gT, xa);
-        }
-    }
+    xstep_s6<KP, TPW, PREC, LK>(a, &nxt, p_next, apan, sh.u.d.gsc[w], &sh.lt, sh.s_codes, sh.s_tcode, yfr, xa, xaf,
+                                dyacc, hacc);
 }
 
 template <int KP, int TPW, int PREC, int LK>
@@ -674,10 +739,7 @@ __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
     const int64_t npanels = a.mp / 16;
     const int64_t G = gridDim.x;
 
-    for (int j = threadIdx.x; j < a.ldp; j += NTX) {
-        sh.s_h[j] = 0.0f;
-        sh.s_codes[j] = a.codes[j];
-    }
+    for (int j = threadIdx.x; j < a.ldp; j += NTX) sh.s_codes[j] = a.codes[j];
     if (threadIdx.x == 0) sh.lt = a.lt;
     __syncthreads();
     tile_codes(sh.s_codes, nt, sh.s_tcode, NTX);
@@ -695,6 +757,9 @@ __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
     for (int s = 0; s < TPW; ++s)
 #pragma unroll
         for (int kb = 0; kb < KP / 16; ++kb) dyacc[s][kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float hacc[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) hacc[s] = 0.0f;
     float rowreg_acc = 0.0f;
     int rej_acc = 0;
 
@@ -702,10 +767,11 @@ __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
         stage_panel<KP, TPW>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, blockIdx.x, w, lane);
     for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
         const int64_t p1 = p + G, p2 = p + 2 * G;
-        xstep_panel<KP, TPW, PREC, LK, 0>(a, sh, p, p1 < npanels ? p1 : -1, yfr, ytf, dyacc, rowreg_acc, rej_acc);
-        if (p1 < npanels)
-            xstep_panel<KP, TPW, PREC, LK, 1>(a, sh, p1, p2 < npanels ? p2 : -1, yfr, ytf, dyacc, rowreg_acc,
+        xstep_panel<KP, TPW, PREC, LK, 0>(a, sh, p, p1 < npanels ? p1 : -1, yfr, ytf, dyacc, hacc, rowreg_acc,
                                           rej_acc);
+        if (p1 < npanels)
+            xstep_panel<KP, TPW, PREC, LK, 1>(a, sh, p1, p2 < npanels ? p2 : -1, yfr, ytf, dyacc, hacc, rowreg_acc,
+                                              rej_acc);
     }
     __syncthreads();
 
@@ -719,10 +785,15 @@ __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
             for (int kb = 0; kb < KP / 16; ++kb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    a.part_dy[((int64_t)blockIdx.x * a.ldp + j0 + 4 * g + r) * KP + 16 * kb + li] = dyacc[s][kb][r];
+                    a.part_dy[((int64_t)blockIdx.x * a.ldp + j0 + 4 * g + r) * KP + 16 * kb + li] =
+                        GRAD_SCALE<LK> * dyacc[s][kb][r];
+            // the quad's four partials of column 4g + 2 (li/8 mod 2) + (li/4 mod 2)
+            float h = hacc[s];
+            h += dpp_mov<0x4E>(h);   // quad_perm [2,3,0,1]
+            h += dpp_mov<0xB1>(h);   // quad_perm [1,0,3,2]
+            if ((li & 3) == 0) a.part_h[(int64_t)blockIdx.x * a.ldp + j0 + 4 * g + (li >> 2)] = h;
         }
     }
-    for (int64_t j = threadIdx.x; j < a.ldp; j += NTX) a.part_h[(int64_t)blockIdx.x * a.ldp + j] = sh.s_h[j];
     // row regularizers and rejections live on the first lane of each row's sixteen
     float rr = sum_lanes<64>(rowreg_acc);
     int rj = (int)sum_lanes<64>((float)rej_acc);
@@ -818,7 +889,10 @@ __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP
     const int64_t i0 = p * 16;
 
     wait_staged();
-    // the panel's X rows straight from the staged block (16 x k, contiguous)
+    // Everything this panel reads from LDS is read before the next panel's
+    // direct-to-LDS loads go out (an LDS read issued after them would wait for
+    // all of them): the X rows, straight from the staged block (16 x k,
+    // contiguous), and the wavefront's table tiles.
     const int rows = (int)min<int64_t>(16, a.m - i0);
     Frag<KP, PREC> xf;
     {
@@ -830,19 +904,19 @@ __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP
         }
         frag_from_f32<KP, PREC>(xf, xv);
     }
+    float4 av[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) av[s] = tile_entries(apan, s, lane, w + NWX * s < nt);
     // no barrier until the next panel: the prefetch overlaps this panel's products
     if (p_next >= 0) stage_panel<KP, TPW>(nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, p_next, w, lane);
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = w + NWX * s;
-        if (t < nt) {
-            const float4 av = apan[s * 64 + lane];
-            const f32x4 zp = zprod<KP, PREC>(yfr[s], xf);
-            float L4[4], G4[4];
-            tile_loss<LK, false>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av, L4, G4);
+        const int t = min(w + NWX * s, nt - 1);
+        const f32x4 zp = zprod<KP, PREC>(yfr[s], xf);
+        float L4[4], G4[4];
+        tile_loss<LK, false>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av[s], L4, G4);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) hacc[s][r] += L4[r];
-        }
+        for (int r = 0; r < 4; ++r) hacc[s][r] += L4[r];
     }
 }
 
