@@ -123,7 +123,6 @@ hipError_t launch_ycheck(const YCheckArgs &a, int kp, int tpw, int prec, int gri
 #undef C_
 }
 
-int pass_waves() { return NWX; }
 
 hipError_t launch_yprox(const YProxArgs &a, int kp, int prec, hipStream_t st)
 {

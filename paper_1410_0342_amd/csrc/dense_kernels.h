@@ -224,12 +224,17 @@ __device__ __forceinline__ void load_panel(float (*xs)[KP], const float *X, int6
     }
 }
 
-// The two passes over the table run four wavefronts per workgroup, one per
-// SIMD, so each wavefront may hold up to 512 registers: its tiles' Y operands
-// stay resident for the whole launch and the column-gradient accumulators
-// live in registers.
-constexpr int NWX = 4;
-constexpr int NTX = NWX * 64;
+// Wavefronts per workgroup of the two passes over the table (xstep_waves,
+// ycheck_waves).  A wavefront's tiles' Y operands stay resident for the whole
+// launch and its column accumulators live in registers.
+template <int KP>
+constexpr int NWX_OF = xstep_waves(KP);
+template <int KP>
+constexpr int NTX_OF = 64 * NWX_OF<KP>;
+template <int KP>
+constexpr int NWY_OF = ycheck_waves(KP);
+template <int KP>
+constexpr int NTY_OF = 64 * NWY_OF<KP>;
 
 // ---------------------------------------------------------------------------
 // panel staging: the next 16-row panel's table tiles, X rows and step sizes
@@ -252,17 +257,17 @@ __device__ __forceinline__ void lds_dma4(const void *src, void *wave_dst)
     __builtin_amdgcn_global_load_lds((glb_void_t *)src, (lds_void_t *)wave_dst, 4, 0, 0);
 }
 
-template <int KP, int TPW>
+template <int KP, int TPW, int NW>
 struct PanelBuf {
-    float4 apan[NWX][TPW * 64];   // wavefront w's tiles: [tile slot][lane]
+    float4 apan[NW][TPW * 64];   // wavefront w's tiles: [tile slot][lane]
     float xrow[16 * KP];         // the panel's X rows, contiguous (16 * k floats)
     float alpha[16];
 };
 
 // Issue the loads of panel p into `pb` (every wavefront issues its own tiles;
 // X rows and step sizes are spread over the wavefronts).
-template <int KP, int TPW>
-__device__ __forceinline__ void stage_panel(PanelBuf<KP, TPW> &pb, const float *Ap, int64_t ldp, int nt,
+template <int KP, int TPW, int NW>
+__device__ __forceinline__ void stage_panel(PanelBuf<KP, TPW, NW> &pb, const float *Ap, int64_t ldp, int nt,
                                             const float *X, int64_t m, int k, const float *alpha, int64_t p,
                                             int w, int lane)
 {
@@ -271,15 +276,15 @@ __device__ __forceinline__ void stage_panel(PanelBuf<KP, TPW> &pb, const float *
     const float *arow = Ap + (i0 + li) * ldp + 4 * g;
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = min(w + NWX * s, nt - 1);
+        const int t = min(w + NW * s, nt - 1);
         lds_dma16(arow + 16 * t, &pb.apan[w][s * 64]);
     }
     const int64_t rows = min<int64_t>(16, m - i0);
     const int nx = (int)(rows * k);            // valid floats of the row block
     const float *xb = X + i0 * k;
-    for (int q = w; q * 64 < nx; q += NWX)
+    for (int q = w; q * 64 < nx; q += NW)
         if (q * 64 + lane < nx) lds_dma4(xb + q * 64 + lane, &pb.xrow[q * 64]);
-    if (alpha && w == NWX - 1 && lane < rows) lds_dma4(alpha + i0 + lane, &pb.alpha[0]);
+    if (alpha && w == NW - 1 && lane < rows) lds_dma4(alpha + i0 + lane, &pb.alpha[0]);
 }
 
 // The lane's four table entries of tile slot s.  A slot past the last tile
@@ -506,25 +511,32 @@ __device__ __forceinline__ void tile_codes(const uint8_t *s_codes, int nt, int8_
 template <int KP>
 constexpr int RS = KP + 4;
 
+// Row stride of the row-objective partials (4 per wavefront, padded so the
+// 64 lanes of a wavefront write to distinct banks).
+template <int KP>
+constexpr int RF = 4 * NWX_OF<KP> + 4;
+
 template <int KP, int TPW, int PREC>
 struct XStepShared {
-    PanelBuf<KP, TPW> buf0, buf1;
+    PanelBuf<KP, TPW, NWX_OF<KP>> buf0, buf1;
     float xs[16][RS<KP>];    // the accepted rows (S6 operand)
     float xp[16][RS<KP>];    // trial rows
     union alignas(16) {
-        float red_g[NWX][16][RS<KP>];     // row-gradient partials (S3 -> S4)
+        float red_g[NWX_OF<KP>][16][RS<KP>];     // row-gradient partials (S3 -> S4)
         struct {
-            float gsc[NWX][16 * GS];      // per-wavefront G transpose tiles (S6)
+            float gsc[NWX_OF<KP>][16 * GS];      // per-wavefront G transpose tiles (S6)
             float xat[KP * GS];           // accepted X transposed ([kc][i]) for S6
         } d;
     } u;
-    float red_f[NWX][4][16];    // row-objective partials per wavefront and lane group
+    // row-objective partials at x (S2) and at the trial rows (S5): row i holds
+    // wavefront w's lane group g at 4w + g, so a row reads them as float4s
+    float red_f[16][RF<KP>], red_fp[16][RF<KP>];
     LossTab lt;                 // per-column loss table (mixed tables only)
-    uint8_t s_codes[16 * NWX * TPW];
-    int8_t s_tcode[NWX * TPW];
-    float s_f[16], s_rx[16], s_rxp[16];
-    float s_blk[NWX];
-    int s_rej[NWX];
+    uint8_t s_codes[16 * NWX_OF<KP> * TPW];
+    int8_t s_tcode[NWX_OF<KP> * TPW];
+    float s_rx[16], s_rxp[16];
+    float s_blk[NWX_OF<KP>];
+    int s_rej[NWX_OF<KP>];
 };
 
 // Reduce-scatter of four column values over a row of sixteen lanes (DPP):
@@ -549,7 +561,7 @@ __device__ __forceinline__ float col_partial(const float (&v)[4], int li)
 // need not wait for them (the compiler drains them at every barrier anyway,
 // and S6 has none).
 template <int KP, int TPW, int PREC, int LK>
-__device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW> *__restrict__ nxt, int64_t p_next,
+__device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ nxt, int64_t p_next,
                                          const float4 *__restrict__ apan, float *__restrict__ gsc,
                                          const LossTab *__restrict__ lt, const uint8_t *__restrict__ s_codes,
                                          const int8_t *__restrict__ s_tcode, const Frag<KP, PREC> (&yfr)[TPW],
@@ -559,10 +571,10 @@ __device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW> *
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     const int nt = (int)(a.ldp / 16);
-    if (p_next >= 0) stage_panel<KP, TPW>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
+    if (p_next >= 0) stage_panel<KP, TPW, NWX_OF<KP>>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = w + NWX * s;
+        const int t = w + NWX_OF<KP> * s;
         // a branch per tile: straight-line tiles raise register pressure past
         // what the resident operands leave
         if (t >= nt) continue;
@@ -584,22 +596,21 @@ __device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW> *
 // One 16-row panel of the fused X half-step.  Five workgroup barriers: the
 // staged panel, the row-gradient partials, the trial rows, the trial
 // objective partials and the accepted rows.  The row steps (S4) and the
-// decisions run on sixteen lanes per row (256 threads = 16 rows x 16 lanes),
-// so their row sums are DPP row reductions.
+// decisions run on the first 256 threads, sixteen lanes per row, so their row
+// sums are DPP row reductions.
 template <int KP, int TPW, int PREC, int LK, int BUF>
 __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, TPW, PREC> &sh, int64_t p,
                                             int64_t p_next, const Frag<KP, PREC> (&yfr)[TPW],
                                             const YtFrag<KP, PREC> (&ytf)[TPW], f32x4 (&dyacc)[TPW][KP / 16],
                                             float (&hacc)[TPW], float &rowreg_acc, int &rej_acc)
 {
-    static_assert(NTX == 256, "row steps map 16 rows x 16 lanes onto the workgroup");
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     constexpr int C = KP / 4;
     const int nt = (int)(a.ldp / 16);
     const int k = a.k;
-    PanelBuf<KP, TPW> &cur = BUF == 0 ? sh.buf0 : sh.buf1;
-    PanelBuf<KP, TPW> &nxt = BUF == 0 ? sh.buf1 : sh.buf0;
+    PanelBuf<KP, TPW, NWX_OF<KP>> &cur = BUF == 0 ? sh.buf0 : sh.buf1;
+    PanelBuf<KP, TPW, NWX_OF<KP>> &nxt = BUF == 0 ? sh.buf1 : sh.buf0;
     const float4 *apan = cur.apan[w];
     const int64_t i0 = p * 16;
     const int rows = (int)min<int64_t>(16, a.m - i0);
@@ -627,7 +638,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     for (int kb = 0; kb < KP / 16; ++kb) dx[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = w + NWX * s;
+        const int t = w + NWX_OF<KP> * s;
         if (t < nt) {
             const float4 av = apan[s * 64 + lane];
             const f32x4 z = zprod<KP, PREC>(yfr[s], xf);
@@ -637,7 +648,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             s3_resident<KP, PREC>(dx, G, ytf[s]);
         }
     }
-    sh.red_f[w][g][li] = fpart;
+    sh.red_f[li][4 * w + g] = fpart;
 #pragma unroll
     for (int kb = 0; kb < KP / 16; ++kb)
 #pragma unroll
@@ -645,19 +656,29 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     __syncthreads();
 
     // ---- S4: prox step and regularizer values ------------------------------------
-    {
-        const float al = rv ? cur.alpha[ri] : 0.0f;
-        float rc = 0.0f, rcp = 0.0f;
+    // every LDS read first (unconditional: the indexes stay inside the arrays),
+    // one wait, then the arithmetic
+    if (threadIdx.x < 256) {
+        constexpr int Q = KP / 16;
+        const float al0 = cur.alpha[ri];
+        float xq[Q], gq[Q];
 #pragma unroll
-        for (int q = 0; q < KP / 16; ++q) {
+        for (int q = 0; q < Q; ++q) {
             const int c = c0 + 16 * q;
+            xq[q] = cur.xrow[ri * k + c];
             float gs = 0.0f;
 #pragma unroll
-            for (int v = 0; v < NWX; ++v) gs += sh.u.red_g[v][ri][c];
-            gs *= GRAD_SCALE<LK>;
+            for (int v = 0; v < NWX_OF<KP>; ++v) gs += sh.u.red_g[v][ri][c];
+            gq[q] = gs * GRAD_SCALE<LK>;
+        }
+        const float al = rv ? al0 : 0.0f;
+        float rc = 0.0f, rcp = 0.0f;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int c = c0 + 16 * q;
             const bool ok = rv && c < k;
-            const float x = ok ? cur.xrow[ri * k + c] : 0.0f;
-            const float xv = ok ? prox_elem(a.rx, al, x - al * gs) : 0.0f;
+            const float x = ok ? xq[q] : 0.0f;
+            const float xv = ok ? prox_elem(a.rx, al, x - al * gq[q]) : 0.0f;
             sh.xp[ri][c] = xv;
             rc += ok ? reg_elem(a.rx, x) : 0.0f;
             rcp += ok ? reg_elem(a.rx, xv) : 0.0f;
@@ -665,11 +686,6 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         rc = row16_sum(rc);
         rcp = row16_sum(rcp);
         if (c0 == 0) {
-            float f = 0.0f;
-#pragma unroll
-            for (int v = 0; v < NWX; ++v)
-                f += (sh.red_f[v][0][ri] + sh.red_f[v][1][ri]) + (sh.red_f[v][2][ri] + sh.red_f[v][3][ri]);
-            sh.s_f[ri] = f + rc;
             sh.s_rx[ri] = rc;
             sh.s_rxp[ri] = rcp;
         }
@@ -682,7 +698,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     float fppart = 0.0f;
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = w + NWX * s;
+        const int t = w + NWX_OF<KP> * s;
         if (t < nt) {
             const float4 av = apan[s * 64 + lane];
             const f32x4 zp = zprod<KP, PREC>(yfr[s], xpf);
@@ -691,30 +707,47 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             fppart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
         }
     }
-    sh.red_f[w][g][li] = fppart;
+    sh.red_fp[li][4 * w + g] = fppart;
     __syncthreads();
 
     // ---- decision per row and the accepted rows ---------------------------------------
-    {
-        float fp = 0.0f;
+    if (threadIdx.x < 256) {
+        constexpr int Q = KP / 16;
+        float4 fa[NWX_OF<KP>], fb[NWX_OF<KP>];
 #pragma unroll
-        for (int v = 0; v < NWX; ++v)
-            fp += (sh.red_f[v][0][ri] + sh.red_f[v][1][ri]) + (sh.red_f[v][2][ri] + sh.red_f[v][3][ri]);
-        fp += sh.s_rxp[ri];
-        const bool acc = rv && fp <= sh.s_f[ri];
+        for (int v = 0; v < NWX_OF<KP>; ++v) {
+            fa[v] = *reinterpret_cast<const float4 *>(&sh.red_f[ri][4 * v]);
+            fb[v] = *reinterpret_cast<const float4 *>(&sh.red_fp[ri][4 * v]);
+        }
+        const float rx = sh.s_rx[ri], rxp = sh.s_rxp[ri], al0 = cur.alpha[ri];
+        float xq[Q], xpq[Q];
 #pragma unroll
-        for (int q = 0; q < KP / 16; ++q) {
+        for (int q = 0; q < Q; ++q) {
+            xq[q] = cur.xrow[ri * k + c0 + 16 * q];
+            xpq[q] = sh.xp[ri][c0 + 16 * q];
+        }
+        // the same sums, in the same order, in every lane of the row
+        float f = 0.0f, fp = 0.0f;
+#pragma unroll
+        for (int v = 0; v < NWX_OF<KP>; ++v) {
+            f += (fa[v].x + fa[v].y) + (fa[v].z + fa[v].w);
+            fp += (fb[v].x + fb[v].y) + (fb[v].z + fb[v].w);
+        }
+        f += rx;
+        fp += rxp;
+        const bool acc = rv && fp <= f;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
             const int c = c0 + 16 * q;
             const bool ok = rv && c < k;
-            const float xa = acc ? sh.xp[ri][c] : (ok ? cur.xrow[ri * k + c] : 0.0f);
+            const float xa = acc ? xpq[q] : (ok ? xq[q] : 0.0f);
             sh.u.d.xat[c * GS + ri] = xa;
             sh.xs[ri][c] = xa;
             if (acc && c < k) a.X[(i0 + ri) * k + c] = xa;
         }
         if (c0 == 0 && rv) {
-            const float al = cur.alpha[ri];
-            a.alpha[i0 + ri] = acc ? al * a.step_up : al * a.step_down;
-            rowreg_acc += acc ? sh.s_rxp[ri] : sh.s_rx[ri];
+            a.alpha[i0 + ri] = acc ? al0 * a.step_up : al0 * a.step_down;
+            rowreg_acc += acc ? rxp : rx;
             rej_acc += acc ? 0 : 1;
         }
     }
@@ -730,7 +763,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
 }
 
 template <int KP, int TPW, int PREC, int LK>
-__global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
+__global__ __launch_bounds__(NTX_OF<KP>, 1) void xstep_kernel(XStepArgs a)
 {
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
@@ -739,16 +772,16 @@ __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
     const int64_t npanels = a.mp / 16;
     const int64_t G = gridDim.x;
 
-    for (int j = threadIdx.x; j < a.ldp; j += NTX) sh.s_codes[j] = a.codes[j];
+    for (int j = threadIdx.x; j < a.ldp; j += NTX_OF<KP>) sh.s_codes[j] = a.codes[j];
     if (threadIdx.x == 0) sh.lt = a.lt;
     __syncthreads();
-    tile_codes(sh.s_codes, nt, sh.s_tcode, NTX);
+    tile_codes(sh.s_codes, nt, sh.s_tcode, NTX_OF<KP>);
     // this wavefront's tiles of Y (fixed during the X half-step), resident in registers
     Frag<KP, PREC> yfr[TPW];
     YtFrag<KP, PREC> ytf[TPW];
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = min(w + NWX * s, nt - 1);
+        const int t = min(w + NWX_OF<KP> * s, nt - 1);
         frag_load_y<KP, PREC>(yfr[s], a.ycur, 16 * t + li, g);
         ytfrag_load<KP, PREC>(ytf[s], a.ycur, a.ldp, 16 * t, li, g);
     }
@@ -764,7 +797,7 @@ __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
     int rej_acc = 0;
 
     if (blockIdx.x < npanels)
-        stage_panel<KP, TPW>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, blockIdx.x, w, lane);
+        stage_panel<KP, TPW, NWX_OF<KP>>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, blockIdx.x, w, lane);
     for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
         const int64_t p1 = p + G, p2 = p + 2 * G;
         xstep_panel<KP, TPW, PREC, LK, 0>(a, sh, p, p1 < npanels ? p1 : -1, yfr, ytf, dyacc, hacc, rowreg_acc,
@@ -778,7 +811,7 @@ __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
     // ---- this workgroup's partials ---------------------------------------------------
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = w + NWX * s;
+        const int t = w + NWX_OF<KP> * s;
         if (t < nt) {
             const int64_t j0 = 16 * t;
 #pragma unroll
@@ -803,7 +836,7 @@ __global__ __launch_bounds__(NTX, 1) void xstep_kernel(XStepArgs a)
         float rsum = 0.0f;
         int jsum = 0;
 #pragma unroll
-        for (int v = 0; v < NWX; ++v) { rsum += sh.s_blk[v]; jsum += sh.s_rej[v]; }
+        for (int v = 0; v < NWX_OF<KP>; ++v) { rsum += sh.s_blk[v]; jsum += sh.s_rej[v]; }
         a.part_rowreg[blockIdx.x] = rsum;
         a.part_rej[blockIdx.x] = jsum;
     }
@@ -869,10 +902,10 @@ __global__ __launch_bounds__(256) void yprox_kernel(YProxArgs a)
 // ---------------------------------------------------------------------------
 template <int KP, int TPW>
 struct YCheckShared {
-    PanelBuf<KP, TPW> buf0, buf1;
+    PanelBuf<KP, TPW, NWY_OF<KP>> buf0, buf1;
     LossTab lt;
-    uint8_t s_codes[16 * NWX * TPW];
-    int8_t s_tcode[NWX * TPW];
+    uint8_t s_codes[16 * NWY_OF<KP> * TPW];
+    int8_t s_tcode[NWY_OF<KP> * TPW];
 };
 
 template <int KP, int TPW, int PREC, int LK, int BUF>
@@ -883,8 +916,8 @@ __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP
     const int li = lane & 15, g = lane >> 4;
     constexpr int C = KP / 4;
     const int nt = (int)(a.ldp / 16);
-    PanelBuf<KP, TPW> &cur = BUF == 0 ? sh.buf0 : sh.buf1;
-    PanelBuf<KP, TPW> &nxt = BUF == 0 ? sh.buf1 : sh.buf0;
+    PanelBuf<KP, TPW, NWY_OF<KP>> &cur = BUF == 0 ? sh.buf0 : sh.buf1;
+    PanelBuf<KP, TPW, NWY_OF<KP>> &nxt = BUF == 0 ? sh.buf1 : sh.buf0;
     const float4 *apan = cur.apan[w];
     const int64_t i0 = p * 16;
 
@@ -906,12 +939,12 @@ __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP
     }
     float4 av[TPW];
 #pragma unroll
-    for (int s = 0; s < TPW; ++s) av[s] = tile_entries(apan, s, lane, w + NWX * s < nt);
+    for (int s = 0; s < TPW; ++s) av[s] = tile_entries(apan, s, lane, w + NWY_OF<KP> * s < nt);
     // no barrier until the next panel: the prefetch overlaps this panel's products
-    if (p_next >= 0) stage_panel<KP, TPW>(nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, p_next, w, lane);
+    if (p_next >= 0) stage_panel<KP, TPW, NWY_OF<KP>>(nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, p_next, w, lane);
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = min(w + NWX * s, nt - 1);
+        const int t = min(w + NWY_OF<KP> * s, nt - 1);
         const f32x4 zp = zprod<KP, PREC>(yfr[s], xf);
         float L4[4], G4[4];
         tile_loss<LK, false>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av[s], L4, G4);
@@ -921,7 +954,7 @@ __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP
 }
 
 template <int KP, int TPW, int PREC, int LK>
-__global__ __launch_bounds__(NTX, 1) void ycheck_kernel(YCheckArgs a)
+__global__ __launch_bounds__(NTY_OF<KP>, 1) void ycheck_kernel(YCheckArgs a)
 {
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
@@ -930,14 +963,14 @@ __global__ __launch_bounds__(NTX, 1) void ycheck_kernel(YCheckArgs a)
     const int64_t npanels = a.mp / 16;
     const int64_t G = gridDim.x;
 
-    for (int j = threadIdx.x; j < a.ldp; j += NTX) sh.s_codes[j] = a.codes[j];
+    for (int j = threadIdx.x; j < a.ldp; j += NTY_OF<KP>) sh.s_codes[j] = a.codes[j];
     if (threadIdx.x == 0) sh.lt = a.lt;
     __syncthreads();
-    tile_codes(sh.s_codes, nt, sh.s_tcode, NTX);
+    tile_codes(sh.s_codes, nt, sh.s_tcode, NTY_OF<KP>);
     Frag<KP, PREC> yfr[TPW];
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = min(w + NWX * s, nt - 1);
+        const int t = min(w + NWY_OF<KP> * s, nt - 1);
         frag_load_y<KP, PREC>(yfr[s], a.yplus, 16 * t + li, g);
     }
     f32x4 hacc[TPW];
@@ -945,7 +978,7 @@ __global__ __launch_bounds__(NTX, 1) void ycheck_kernel(YCheckArgs a)
     for (int s = 0; s < TPW; ++s) hacc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     if (blockIdx.x < npanels)
-        stage_panel<KP, TPW>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, blockIdx.x, w, lane);
+        stage_panel<KP, TPW, NWY_OF<KP>>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, blockIdx.x, w, lane);
     for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
         const int64_t p1 = p + G, p2 = p + 2 * G;
         ycheck_panel<KP, TPW, PREC, LK, 0>(a, sh, p, p1 < npanels ? p1 : -1, yfr, hacc);
@@ -953,7 +986,7 @@ __global__ __launch_bounds__(NTX, 1) void ycheck_kernel(YCheckArgs a)
     }
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = w + NWX * s;
+        const int t = w + NWY_OF<KP> * s;
         if (t < nt) {
             const int64_t j0 = 16 * t;
 #pragma unroll

@@ -32,7 +32,8 @@ namespace glrm {
     default: return hipErrorInvalidValue;                              \
     }
 
-#define GLRM_DISPATCH_TPWX(TV, ...)                                   \
+// Up to 16 tiles per wavefront (the fused row pass at kp <= 32).
+#define GLRM_DISPATCH_TPW16(TV, ...)                                  \
     switch (TV) {                                                     \
     case 1: { constexpr int TPW = 1; __VA_ARGS__; } break;            \
     case 2: { constexpr int TPW = 2; __VA_ARGS__; } break;            \
@@ -41,7 +42,6 @@ namespace glrm {
     case 16: { constexpr int TPW = 16; __VA_ARGS__; } break;          \
     default: return hipErrorInvalidValue;                              \
     }
-
 
 // The quadratic loss (every column) gets its own instances; everything else
 // goes through the per-tile loss selection.
@@ -53,9 +53,9 @@ template <int PREC>
 hipError_t launch_xstep_p(const XStepArgs &a, int kp, int tpw, int grid, hipStream_t st)
 {
     const bool quad = a.lu.kind == L_QUAD;
-    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPWX(tpw, GLRM_DISPATCH_LK(quad,
+    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW16(tpw, GLRM_DISPATCH_LK(quad,
         if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
-        else hipLaunchKernelGGL((xstep_kernel<KP, TPW, PREC, LK>), dim3(grid), dim3(NTX), 0, st, a))));
+        else hipLaunchKernelGGL((xstep_kernel<KP, TPW, PREC, LK>), dim3(grid), dim3(NTX_OF<KP>), 0, st, a))));
     return hipGetLastError();
 }
 
@@ -63,9 +63,8 @@ template <int PREC>
 hipError_t launch_ycheck_p(const YCheckArgs &a, int kp, int tpw, int grid, hipStream_t st)
 {
     const bool quad = a.lu.kind == L_QUAD;
-    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPWX(tpw, GLRM_DISPATCH_LK(quad,
-        if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
-        else hipLaunchKernelGGL((ycheck_kernel<KP, TPW, PREC, LK>), dim3(grid), dim3(NTX), 0, st, a))));
+    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW(tpw, GLRM_DISPATCH_LK(quad,
+        hipLaunchKernelGGL((ycheck_kernel<KP, TPW, PREC, LK>), dim3(grid), dim3(NTY_OF<KP>), 0, st, a))));
     return hipGetLastError();
 }
 

@@ -54,13 +54,20 @@ int tpw_for(int64_t ntiles)
     return 0;
 }
 
-// The same for the two passes of the fit (pass_waves() wavefronts, up to 16
-// tiles each; 8 at kp = 64).
-int tpw_fit(int64_t ntiles, int kp)
+// The same for the two passes of the fit: the fused row pass runs
+// xstep_waves(kp) wavefronts of up to 16 tiles (8 at kp = 64), the trial-column
+// pass ycheck_waves(kp) wavefronts of up to 8 tiles.
+int tpw_xstep(int64_t ntiles, int kp)
 {
-    const int maxt = kp == 64 ? 8 : 16;
     for (int t : {1, 2, 4, 8, 16})
-        if (t <= maxt && (int64_t)pass_waves() * t >= ntiles) return t;
+        if ((kp < 64 || t <= 8) && (int64_t)xstep_waves(kp) * t >= ntiles) return t;
+    return 0;
+}
+
+int tpw_ycheck(int64_t ntiles, int kp)
+{
+    for (int t : {1, 2, 4, 8})
+        if ((int64_t)ycheck_waves(kp) * t >= ntiles) return t;
     return 0;
 }
 
@@ -548,12 +555,13 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
     make_layout(d, L);
     if ((rc = check_ws(L, ws, ws_bytes))) return rc;
     const int prec = o->precision;
-    int tpw = 0;
+    int tpw = 0, tpw_y = 0;
     if (d->layout == GLRM_DENSE) {
-        tpw = tpw_fit(L.ldp / 16, (int)L.kp);
-        if (tpw == 0)
+        tpw = tpw_xstep(L.ldp / 16, (int)L.kp);
+        tpw_y = tpw_ycheck(L.ldp / 16, (int)L.kp);
+        if (tpw == 0 || tpw_y == 0)
             return fail(GLRM_EUNSUPPORTED, "dense fit supports n <= %d for k <= 32 and n <= %d for k > 32; "
-                        "use the COO layout for wider tables", 16 * pass_waves() * 16, 16 * pass_waves() * 8);
+                        "use the COO layout for wider tables", 16 * xstep_waves(32) * 16, 16 * xstep_waves(64) * 8);
     } else {
         if ((rc = coo_fit_supported(d, L.kp, L.cl, prec))) return rc;
     }
@@ -632,7 +640,7 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
             HIP_TRY(launch_yprox(pa, (int)L.kp, prec, st));
             HIP_TRY(timer.stop(st));
             HIP_TRY(timer.start(2, st));
-            HIP_TRY(launch_ycheck(ca, (int)L.kp, tpw, prec, grid, st));
+            HIP_TRY(launch_ycheck(ca, (int)L.kp, tpw_y, prec, grid, st));
             HIP_TRY(timer.stop(st));
             HIP_TRY(timer.start(3, st));
             HIP_TRY(launch_yaccept(aa, (int)L.kp, prec, ya_blocks, st));

@@ -27,6 +27,14 @@ struct LossU {
     float param;
 };
 
+// Wavefronts per workgroup of the two passes over the table (fit), by pass
+// and padded rank kp.  The fused row pass keeps four Y operands and the
+// Y-gradient accumulators per tile resident, so it runs one wavefront per SIMD
+// (up to 512 registers); the trial-column pass holds less and runs two per
+// SIMD while kp <= 32.
+constexpr int xstep_waves(int kp) { return 4; }
+constexpr int ycheck_waves(int kp) { return kp >= 64 ? 4 : 8; }
+
 struct XStepArgs {
     int64_t m, mp, ldp;
     int32_t k;
@@ -149,7 +157,6 @@ struct PackArgs {
 // ---- launchers (dense.hip) ----
 hipError_t launch_xstep(const XStepArgs &a, int kp, int tpw, int prec, int grid, hipStream_t st);
 hipError_t launch_ycheck(const YCheckArgs &a, int kp, int tpw, int prec, int grid, hipStream_t st);
-int pass_waves();   // wavefronts per workgroup of the two table passes
 hipError_t launch_yprox(const YProxArgs &a, int kp, int prec, hipStream_t st);
 hipError_t launch_yaccept(const YAcceptArgs &a, int kp, int prec, int blocks, hipStream_t st);
 int yaccept_blocks(int64_t n, int kp);
