@@ -297,6 +297,15 @@ __device__ __forceinline__ float4 tile_entries(const float4 *apan, int s, int la
     return valid ? v : float4{qnan, qnan, qnan, qnan};
 }
 
+// The lane's four table entries in the layout of X . Y^T products: rows
+// 4g + r of column li of tile slot s.  The staged tile keeps row i's columns
+// 4q .. 4q+3 in lane i + 16q, so the four entries are four words 16 bytes apart.
+__device__ __forceinline__ float4 tile_entries_t(const float4 *apan, int s, int li, int g)
+{
+    const float *b = reinterpret_cast<const float *>(apan) + s * 256 + 64 * (li >> 2) + (li & 3) + 16 * g;
+    return float4{b[0], b[4], b[8], b[12]};
+}
+
 __device__ __forceinline__ void wait_staged()
 {
     __builtin_amdgcn_s_waitcnt(0);
@@ -451,7 +460,9 @@ constexpr float GRAD_SCALE = LK == L_QUAD ? 2.0f : 1.0f;
 // LK >= 0: every column has loss kind LK (compile time).  LK < 0: a tile whose
 // sixteen columns share one loss takes it from a scalar branch on the tile's
 // code; a tile that mixes losses goes entry by entry.
-template <int LK, bool WANT_G>
+// TRANS: the four entries are rows 4g + r of column 16t + li (the layout of
+// X . Y^T products) instead of row li, columns 16t + 4g + r.
+template <int LK, bool WANT_G, bool TRANS = false>
 __device__ __forceinline__ void tile_loss(const LossU &lu, const LossTab &tab, const uint8_t *s_codes,
                                           const int8_t *s_tcode, int t, const f32x4 &z, const float4 &av,
                                           float (&l)[4], float (&g)[4])
@@ -474,8 +485,13 @@ __device__ __forceinline__ void tile_loss(const LossU &lu, const LossTab &tab, c
             }
         } else {
             const int lane = threadIdx.x & 63;
-            const uchar4 c = *reinterpret_cast<const uchar4 *>(s_codes + 16 * t + 4 * (lane >> 4));
-            const int cd[4] = {c.x, c.y, c.z, c.w};
+            int cd[4];
+            if constexpr (TRANS) {
+                cd[0] = cd[1] = cd[2] = cd[3] = s_codes[16 * t + (lane & 15)];
+            } else {
+                const uchar4 c = *reinterpret_cast<const uchar4 *>(s_codes + 16 * t + 4 * (lane >> 4));
+                cd[0] = c.x; cd[1] = c.y; cd[2] = c.z; cd[3] = c.w;
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 float lr = 0.f, gr = 0.f;
@@ -524,7 +540,6 @@ struct XStepShared {
     union alignas(16) {
         float red_g[NWX_OF<KP>][16][RS<KP>];     // row-gradient partials (S3 -> S4)
         struct {
-            float gsc[NWX_OF<KP>][16 * GS];      // per-wavefront G transpose tiles (S6)
             float xat[KP * GS];           // accepted X transposed ([kc][i]) for S6
         } d;
     } u;
@@ -539,30 +554,17 @@ struct XStepShared {
     int s_rej[NWX_OF<KP>];
 };
 
-// Reduce-scatter of four column values over a row of sixteen lanes (DPP):
-// lane li gets column r = 2 (li/8 mod 2) + (li/4 mod 2) summed over itself and
-// its mirror partners (lanes of one quad together hold the whole column).
-__device__ __forceinline__ float col_partial(const float (&v)[4], int li)
-{
-    const bool b8 = li & 8, b4 = li & 4;
-    float k0 = b8 ? v[2] : v[0], k1 = b8 ? v[3] : v[1];
-    const float s0 = b8 ? v[0] : v[2], s1 = b8 ? v[1] : v[3];
-    k0 += dpp_mov<0x140>(s0);   // row_mirror: partner 15 - li
-    k1 += dpp_mov<0x140>(s1);
-    float kk = b4 ? k1 : k0;
-    const float ss = b4 ? k0 : k1;
-    kk += dpp_mov<0x141>(ss);   // row_half_mirror: partner 7 - (li mod 8)
-    return kk;
-}
-
-// S6 of one panel, with the next panel's loads issued first.  The LDS
-// operands come in as restrict pointers so that the compiler can tell the
-// direct-to-LDS loads into the other buffer apart from the reads here and
-// need not wait for them (the compiler drains them at every barrier anyway,
-// and S6 has none).
+// S6 of one panel, with the next panel's loads issued first.  z comes from
+// X . Y^T, so each lane holds rows 4g + r of column li: the loss derivatives
+// are then already the transposed operand of dY += G^T . X, and the column
+// objective of column li is a sum over the lane's four rows (the four lane
+// groups are added once, at the end of the launch).  The LDS operands come in
+// as restrict pointers so that the compiler can tell the direct-to-LDS loads
+// into the other buffer apart from the reads here and need not wait for them
+// (it drains them at every barrier anyway, and S6 has none).
 template <int KP, int TPW, int PREC, int LK>
-__device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ nxt, int64_t p_next,
-                                         const float4 *__restrict__ apan, float *__restrict__ gsc,
+__device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ nxt,
+                                         int64_t p_next, const float4 *__restrict__ apan,
                                          const LossTab *__restrict__ lt, const uint8_t *__restrict__ s_codes,
                                          const int8_t *__restrict__ s_tcode, const Frag<KP, PREC> (&yfr)[TPW],
                                          const XatFrag<KP, PREC> &xa, const Frag<KP, PREC> &xaf,
@@ -571,25 +573,20 @@ __device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, N
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     const int nt = (int)(a.ldp / 16);
-    if (p_next >= 0) stage_panel<KP, TPW, NWX_OF<KP>>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
+    if (p_next >= 0)
+        stage_panel<KP, TPW, NWX_OF<KP>>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
         const int t = w + NWX_OF<KP> * s;
         // a branch per tile: straight-line tiles raise register pressure past
         // what the resident operands leave
         if (t >= nt) continue;
-        const int j0 = 16 * t;
-        const f32x4 zs = zprod<KP, PREC>(yfr[s], xaf);
-        const float4 av = apan[s * 64 + lane];
-        float L4[4], G[4], gT[4];
-        tile_loss<LK, true>(a.lu, *lt, s_codes, s_tcode, t, zs, av, L4, G);
-        // column objective: a reduce-scatter of the lane's four entries over
-        // the row of sixteen lanes leaves lane li with a partial sum of column
-        // 4g + 2 (li/8 mod 2) + (li/4 mod 2); it accumulates in a register
-        // across panels and the quad's four partials are added at the end
-        hacc[s] += col_partial(L4, li);
-        transpose_g(gsc, G, gT, li, g);
-        s6_resident<KP, PREC>(dyacc[s], gT, xa);
+        const f32x4 zt = zprod<KP, PREC>(xaf, yfr[s]);
+        const float4 av = tile_entries_t(apan, s, li, g);
+        float L4[4], G[4];
+        tile_loss<LK, true, true>(a.lu, *lt, s_codes, s_tcode, t, zt, av, L4, G);
+        hacc[s] += (L4[0] + L4[1]) + (L4[2] + L4[3]);
+        s6_resident<KP, PREC>(dyacc[s], G, xa);
     }
 }
 
@@ -758,8 +755,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     xatfrag_load<KP, PREC>(xa, sh.u.d.xat, li, g);
     Frag<KP, PREC> xaf;
     frag_from_f32<KP, PREC>(xaf, &sh.xs[li][g * C]);
-    xstep_s6<KP, TPW, PREC, LK>(a, &nxt, p_next, apan, sh.u.d.gsc[w], &sh.lt, sh.s_codes, sh.s_tcode, yfr, xa, xaf,
-                                dyacc, hacc);
+    xstep_s6<KP, TPW, PREC, LK>(a, &nxt, p_next, apan, &sh.lt, sh.s_codes, sh.s_tcode, yfr, xa, xaf, dyacc, hacc);
 }
 
 template <int KP, int TPW, int PREC, int LK>
@@ -820,11 +816,11 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void xstep_kernel(XStepArgs a)
                 for (int r = 0; r < 4; ++r)
                     a.part_dy[((int64_t)blockIdx.x * a.ldp + j0 + 4 * g + r) * KP + 16 * kb + li] =
                         GRAD_SCALE<LK> * dyacc[s][kb][r];
-            // the quad's four partials of column 4g + 2 (li/8 mod 2) + (li/4 mod 2)
+            // column j0 + li: the four lane groups' partials
             float h = hacc[s];
-            h += dpp_mov<0x4E>(h);   // quad_perm [2,3,0,1]
-            h += dpp_mov<0xB1>(h);   // quad_perm [1,0,3,2]
-            if ((li & 3) == 0) a.part_h[(int64_t)blockIdx.x * a.ldp + j0 + 4 * g + (li >> 2)] = h;
+            h += __shfl_xor(h, 16, 64);
+            h += __shfl_xor(h, 32, 64);
+            if (g == 0) a.part_h[(int64_t)blockIdx.x * a.ldp + j0 + li] = h;
         }
     }
     // row regularizers and rejections live on the first lane of each row's sixteen
