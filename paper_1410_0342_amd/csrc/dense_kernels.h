@@ -575,14 +575,23 @@ __device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, N
     const int nt = (int)(a.ldp / 16);
     if (p_next >= 0)
         stage_panel<KP, TPW, NWX_OF<KP>>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
+    // software pipelined: tile s + 1's entries and product are issued before
+    // tile s's losses (slots past the last tile compute on stale entries and
+    // are skipped), and each tile's work sits behind a uniform branch, since
+    // straight-line tiles raise register pressure past what the resident
+    // operands leave
+    f32x4 zn = zprod<KP, PREC>(xaf, yfr[0]);
+    float4 an = tile_entries_t(apan, 0, li, g);
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
         const int t = w + NWX_OF<KP> * s;
-        // a branch per tile: straight-line tiles raise register pressure past
-        // what the resident operands leave
+        const f32x4 zt = zn;
+        const float4 av = an;
+        if (s + 1 < TPW) {
+            zn = zprod<KP, PREC>(xaf, yfr[s + 1]);
+            an = tile_entries_t(apan, s + 1, li, g);
+        }
         if (t >= nt) continue;
-        const f32x4 zt = zprod<KP, PREC>(xaf, yfr[s]);
-        const float4 av = tile_entries_t(apan, s, li, g);
         float L4[4], G[4];
         tile_loss<LK, true, true>(a.lu, *lt, s_codes, s_tcode, t, zt, av, L4, G);
         hacc[s] += (L4[0] + L4[1]) + (L4[2] + L4[3]);
@@ -633,17 +642,23 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     f32x4 dx[KP / 16];
 #pragma unroll
     for (int kb = 0; kb < KP / 16; ++kb) dx[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // software pipelined as in S6
+    f32x4 zn = zprod<KP, PREC>(yfr[0], xf);
+    float4 an = apan[lane];
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
         const int t = w + NWX_OF<KP> * s;
-        if (t < nt) {
-            const float4 av = apan[s * 64 + lane];
-            const f32x4 z = zprod<KP, PREC>(yfr[s], xf);
-            float L4[4], G[4];
-            tile_loss<LK, true>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, z, av, L4, G);
-            fpart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
-            s3_resident<KP, PREC>(dx, G, ytf[s]);
+        const f32x4 z = zn;
+        const float4 av = an;
+        if (s + 1 < TPW) {
+            zn = zprod<KP, PREC>(yfr[s + 1], xf);
+            an = apan[(s + 1) * 64 + lane];
         }
+        if (t >= nt) continue;
+        float L4[4], G[4];
+        tile_loss<LK, true>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, z, av, L4, G);
+        fpart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
+        s3_resident<KP, PREC>(dx, G, ytf[s]);
     }
     sh.red_f[li][4 * w + g] = fpart;
 #pragma unroll
@@ -693,16 +708,21 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     Frag<KP, PREC> xpf;
     frag_from_f32<KP, PREC>(xpf, &sh.xp[li][g * C]);
     float fppart = 0.0f;
+    f32x4 zn2 = zprod<KP, PREC>(yfr[0], xpf);
+    float4 an2 = apan[lane];
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
         const int t = w + NWX_OF<KP> * s;
-        if (t < nt) {
-            const float4 av = apan[s * 64 + lane];
-            const f32x4 zp = zprod<KP, PREC>(yfr[s], xpf);
-            float L4[4], G4[4];
-            tile_loss<LK, false>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av, L4, G4);
-            fppart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
+        const f32x4 zp = zn2;
+        const float4 av = an2;
+        if (s + 1 < TPW) {
+            zn2 = zprod<KP, PREC>(yfr[s + 1], xpf);
+            an2 = apan[(s + 1) * 64 + lane];
         }
+        if (t >= nt) continue;
+        float L4[4], G4[4];
+        tile_loss<LK, false>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av, L4, G4);
+        fppart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
     }
     sh.red_fp[li][4 * w + g] = fppart;
     __syncthreads();
