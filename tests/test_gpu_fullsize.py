@@ -172,3 +172,24 @@ def test_heterogeneous_gradient_sampled(heterogeneous):
         P = _col_problem(case, j)
         _, gy = P.grad(X0, Y0[j:j + 1])
         np.testing.assert_allclose(dY[j], gy[0], rtol=1e-4, atol=1e-4 * np.abs(gy).max())
+
+
+def test_dense_quadratic_fit_repeatable_on_a_reused_workspace(dense_quadratic):
+    """The benchmark's launch configuration: one prepared workspace serves an
+    FP32 fit, a BF16 fit and the same FP32 fit again.  Nothing a fit leaves in
+    the workspace may reach the next one, so the two FP32 fits agree bit for
+    bit (same start, same sweeps)."""
+    case = dense_quadratic
+    data = g.Data.from_case(case, DEV)
+    g.glrm_prepare(data)
+    outs = []
+    for prec in (g.FP32, g.BF16, g.FP32):
+        X, Y = to_dev(case.X0, DEV), to_dev(case.Y0, DEV)
+        ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
+        ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
+        info = g.glrm_fit(data, X, Y, ax, ay, 10, precision=prec, flags=g.WS_PREPARED)
+        outs.append((X.cpu().numpy(), Y.cpu().numpy(), ax.cpu().numpy(), ay.cpu().numpy(), info["objective"]))
+    a, b = outs[0], outs[2]
+    for u, v in zip(a[:4], b[:4]):
+        assert np.array_equal(u, v)
+    assert a[4] == b[4]
