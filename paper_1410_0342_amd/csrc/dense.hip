@@ -96,6 +96,8 @@ __global__ __launch_bounds__(256) void objective64_kernel(Obj64Args a)
 // ---------------------------------------------------------------------------
 template <int PREC> hipError_t launch_xstep_p(const XStepArgs &, int, int, int, hipStream_t);
 template <int PREC> hipError_t launch_ycheck_p(const YCheckArgs &, int, int, int, hipStream_t);
+template <int PREC> int xstep_blocks_p(int, int, bool);
+template <int PREC> int ycheck_blocks_p(int, int, bool);
 template <int PREC> hipError_t launch_yprox_p(const YProxArgs &, int, hipStream_t);
 template <int PREC> hipError_t launch_yaccept_p(const YAcceptArgs &, int, int, hipStream_t);
 template <int PREC> hipError_t launch_yshadow_p(const YShadowArgs &, int, hipStream_t);
@@ -189,6 +191,26 @@ hipError_t launch_objective64(const Obj64Args &a, int grid, hipStream_t st)
     default: hipLaunchKernelGGL((objective64_kernel<64>), dim3(grid), dim3(256), 0, st, a); break;
     }
     return hipGetLastError();
+}
+
+int xstep_blocks(int kp, int tpw, int prec, bool quad)
+{
+    switch (prec) {
+    case P_FP32: return xstep_blocks_p<P_FP32>(kp, tpw, quad);
+    case P_BF16: return xstep_blocks_p<P_BF16>(kp, tpw, quad);
+    case P_BF16_PLAIN: return xstep_blocks_p<P_BF16_PLAIN>(kp, tpw, quad);
+    default: return 1;
+    }
+}
+
+int ycheck_blocks(int kp, int tpw, int prec, bool quad)
+{
+    switch (prec) {
+    case P_FP32: return ycheck_blocks_p<P_FP32>(kp, tpw, quad);
+    case P_BF16: return ycheck_blocks_p<P_BF16>(kp, tpw, quad);
+    case P_BF16_PLAIN: return ycheck_blocks_p<P_BF16_PLAIN>(kp, tpw, quad);
+    default: return 1;
+    }
 }
 
 }  // namespace glrm

@@ -452,56 +452,83 @@ __device__ __forceinline__ void tile4(int lev, float par, const f32x4 &z, const 
     }
 }
 
+// Losses (and derivatives) of four entries under a per-column loss table.  One
+// copy per variant, called from every tile: inlined per tile, phase and panel
+// buffer, the five loss kinds make the passes far larger than the instruction
+// cache.  tc >= 0: the tile's sixteen columns share loss tc.  tc < 0: codes
+// per entry (cd).
+struct LG4 {
+    f32x4 l, g;
+};
+
+template <bool WANT_G>
+__device__ __attribute__((noinline)) LG4 tile_loss_table(const LossTab *tab, int tc, int4 cd, f32x4 z, float4 av)
+{
+    const float a4[4] = {av.x, av.y, av.z, av.w};
+    float l[4], g[4];
+    if (tc >= 0) {
+        const int kind = __builtin_amdgcn_readfirstlane(tab->kind[tc]);
+        const int lev = __builtin_amdgcn_readfirstlane(tab->levels[tc]);
+        const float par = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, tab->param[tc])));
+        switch (kind) {
+        case L_QUAD: tile4<L_QUAD, WANT_G>(lev, par, z, a4, l, g); break;
+        case L_HUBER: tile4<L_HUBER, WANT_G>(lev, par, z, a4, l, g); break;
+        case L_LOGISTIC: tile4<L_LOGISTIC, WANT_G>(lev, par, z, a4, l, g); break;
+        case L_HINGE: tile4<L_HINGE, WANT_G>(lev, par, z, a4, l, g); break;
+        default: tile4<L_ORDINAL, WANT_G>(lev, par, z, a4, l, g); break;
+        }
+    } else {
+        const int c4[4] = {cd.x, cd.y, cd.z, cd.w};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float lr = 0.f, gr = 0.f;
+            if (a4[r] == a4[r]) {
+                const int q = c4[r];
+                if constexpr (WANT_G) loss_lg(tab->kind[q], tab->levels[q], tab->param[q], z[r], a4[r], lr, gr);
+                else lr = loss_l(tab->kind[q], tab->levels[q], tab->param[q], z[r], a4[r]);
+            }
+            l[r] = lr;
+            g[r] = gr;
+        }
+    }
+    return LG4{f32x4{l[0], l[1], l[2], l[3]}, f32x4{g[0], g[1], g[2], g[3]}};
+}
+
 // Scale of the derivatives tile_loss<LK> returns (see tile4's HALF).
 template <int LK>
 constexpr float GRAD_SCALE = LK == L_QUAD ? 2.0f : 1.0f;
 
 // Losses (and, with WANT_G, derivatives) of the lane's four entries of tile t.
-// LK >= 0: every column has loss kind LK (compile time).  LK < 0: a tile whose
-// sixteen columns share one loss takes it from a scalar branch on the tile's
-// code; a tile that mixes losses goes entry by entry.
-// TRANS: the four entries are rows 4g + r of column 16t + li (the layout of
-// X . Y^T products) instead of row li, columns 16t + 4g + r.
+// LK >= 0: every column has loss kind LK (compile time).  LK < 0: the table
+// (tile_loss_table).  TRANS: the four entries are rows 4g + r of column
+// 16t + li (the layout of X . Y^T products) instead of row li, columns
+// 16t + 4g + r.
 template <int LK, bool WANT_G, bool TRANS = false>
 __device__ __forceinline__ void tile_loss(const LossU &lu, const LossTab &tab, const uint8_t *s_codes,
                                           const int8_t *s_tcode, int t, const f32x4 &z, const float4 &av,
                                           float (&l)[4], float (&g)[4])
 {
-    const float a4[4] = {av.x, av.y, av.z, av.w};
     if constexpr (LK >= 0) {
+        const float a4[4] = {av.x, av.y, av.z, av.w};
         tile4<LK, WANT_G, LK == L_QUAD>(lu.levels, lu.param, z, a4, l, g);
     } else {
         const int tc = __builtin_amdgcn_readfirstlane((int)s_tcode[t]);
-        if (tc >= 0) {
-            const int kind = __builtin_amdgcn_readfirstlane(tab.kind[tc]);
-            const int lev = __builtin_amdgcn_readfirstlane(tab.levels[tc]);
-            const float par = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, tab.param[tc])));
-            switch (kind) {
-            case L_QUAD: tile4<L_QUAD, WANT_G>(lev, par, z, a4, l, g); break;
-            case L_HUBER: tile4<L_HUBER, WANT_G>(lev, par, z, a4, l, g); break;
-            case L_LOGISTIC: tile4<L_LOGISTIC, WANT_G>(lev, par, z, a4, l, g); break;
-            case L_HINGE: tile4<L_HINGE, WANT_G>(lev, par, z, a4, l, g); break;
-            default: tile4<L_ORDINAL, WANT_G>(lev, par, z, a4, l, g); break;
-            }
-        } else {
+        int4 cd = {0, 0, 0, 0};
+        if (tc < 0) {
             const int lane = threadIdx.x & 63;
-            int cd[4];
             if constexpr (TRANS) {
-                cd[0] = cd[1] = cd[2] = cd[3] = s_codes[16 * t + (lane & 15)];
+                const int c = s_codes[16 * t + (lane & 15)];
+                cd = int4{c, c, c, c};
             } else {
                 const uchar4 c = *reinterpret_cast<const uchar4 *>(s_codes + 16 * t + 4 * (lane >> 4));
-                cd[0] = c.x; cd[1] = c.y; cd[2] = c.z; cd[3] = c.w;
+                cd = int4{c.x, c.y, c.z, c.w};
             }
+        }
+        const LG4 r = tile_loss_table<WANT_G>(&tab, tc, cd, z, av);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float lr = 0.f, gr = 0.f;
-                if (a4[r] == a4[r]) {
-                    if constexpr (WANT_G) loss_lg(tab.kind[cd[r]], tab.levels[cd[r]], tab.param[cd[r]], z[r], a4[r], lr, gr);
-                    else lr = loss_l(tab.kind[cd[r]], tab.levels[cd[r]], tab.param[cd[r]], z[r], a4[r]);
-                }
-                l[r] = lr;
-                g[r] = gr;
-            }
+        for (int q = 0; q < 4; ++q) {
+            l[q] = r.l[q];
+            g[q] = r.g[q];
         }
     }
 }

@@ -1,6 +1,8 @@
 // Precision-dependent launchers of the dense kernels.  This file is compiled
 // once per contraction precision with -DGLRM_PREC=<0|1|3> (FP32, split BF16,
 // plain BF16), so the three sets of kernel instances build in parallel.
+#include <type_traits>
+
 #include "dense_kernels.h"
 
 #ifndef GLRM_PREC
@@ -43,6 +45,32 @@ namespace glrm {
     default: return hipErrorInvalidValue;                              \
     }
 
+// Calls f(KP, TPW, LK) as integral constants for the runtime values (TPW up to 16).
+template <typename F>
+static void for_instance(int kp, int tpw, bool quad, F &&f)
+{
+    auto with_lk = [&](auto kpc, auto tpwc) {
+        if (quad) f(kpc, tpwc, std::integral_constant<int, L_QUAD>{});
+        else f(kpc, tpwc, std::integral_constant<int, -1>{});
+    };
+    auto with_tpw = [&](auto kpc) {
+        switch (tpw) {
+        case 1: with_lk(kpc, std::integral_constant<int, 1>{}); break;
+        case 2: with_lk(kpc, std::integral_constant<int, 2>{}); break;
+        case 4: with_lk(kpc, std::integral_constant<int, 4>{}); break;
+        case 8: with_lk(kpc, std::integral_constant<int, 8>{}); break;
+        case 16: with_lk(kpc, std::integral_constant<int, 16>{}); break;
+        default: break;
+        }
+    };
+    switch (kp) {
+    case 16: with_tpw(std::integral_constant<int, 16>{}); break;
+    case 32: with_tpw(std::integral_constant<int, 32>{}); break;
+    case 64: with_tpw(std::integral_constant<int, 64>{}); break;
+    default: break;
+    }
+}
+
 // The quadratic loss (every column) gets its own instances; everything else
 // goes through the per-tile loss selection.
 #define GLRM_DISPATCH_LK(QUAD_ONLY, ...)                              \
@@ -57,6 +85,39 @@ hipError_t launch_xstep_p(const XStepArgs &a, int kp, int tpw, int grid, hipStre
         if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
         else hipLaunchKernelGGL((xstep_kernel<KP, TPW, PREC, LK>), dim3(grid), dim3(NTX_OF<KP>), 0, st, a))));
     return hipGetLastError();
+}
+
+// Workgroups of one instance that fit on a CU at once (registers and LDS).
+template <typename K>
+static int blocks_per_cu(K kernel, int threads)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) return 1;
+    return nb;
+}
+
+template <int PREC>
+int xstep_blocks_p(int kp, int tpw, bool quad)
+{
+    int nb = 1;
+    auto pick = [&](auto kpc, auto tpwc, auto lkc) {
+        constexpr int KP = decltype(kpc)::value, TPW = decltype(tpwc)::value, LK = decltype(lkc)::value;
+        if constexpr (!(KP == 64 && TPW == 16)) nb = blocks_per_cu(xstep_kernel<KP, TPW, PREC, LK>, NTX_OF<KP>);
+    };
+    for_instance(kp, tpw, quad, pick);
+    return nb;
+}
+
+template <int PREC>
+int ycheck_blocks_p(int kp, int tpw, bool quad)
+{
+    int nb = 1;
+    auto pick = [&](auto kpc, auto tpwc, auto lkc) {
+        constexpr int KP = decltype(kpc)::value, TPW = decltype(tpwc)::value, LK = decltype(lkc)::value;
+        if constexpr (TPW <= 8) nb = blocks_per_cu(ycheck_kernel<KP, TPW, PREC, LK>, NTY_OF<KP>);
+    };
+    for_instance(kp, tpw, quad, pick);
+    return nb;
 }
 
 template <int PREC>
@@ -106,6 +167,8 @@ hipError_t launch_lossgrad_p(const LossGradArgs &a, int kp, int tpw, bool want_g
 }
 
 template hipError_t launch_xstep_p<GLRM_PREC>(const XStepArgs &, int, int, int, hipStream_t);
+template int xstep_blocks_p<GLRM_PREC>(int, int, bool);
+template int ycheck_blocks_p<GLRM_PREC>(int, int, bool);
 template hipError_t launch_ycheck_p<GLRM_PREC>(const YCheckArgs &, int, int, int, hipStream_t);
 template hipError_t launch_yprox_p<GLRM_PREC>(const YProxArgs &, int, hipStream_t);
 template hipError_t launch_yaccept_p<GLRM_PREC>(const YAcceptArgs &, int, int, hipStream_t);

@@ -37,7 +37,9 @@ int fail(int code, const char *fmt, ...)
         if (e_ != hipSuccess) return fail(GLRM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int P_MAX = 256;     // workgroups of the persistent dense kernels
+constexpr int P_MAX = 1024;    // workgroups (and partials) of the persistent dense fit passes, at most
+constexpr int64_t P_BYTES = 64ll << 20;  // ... and the Y-gradient partials within this (256 at least)
+constexpr int P_GRAD = 256;    // row chunks of the one-pass loss gradient
 constexpr int NWAVES = 8;      // wavefronts per dense workgroup (matches the kernels)
 constexpr int REG_BLOCKS = 64; // partials of a regularizer sum
 constexpr int OBJ64_BLOCKS = 2048;  // workgroups (and partials) of the FP64 objective
@@ -73,6 +75,7 @@ int tpw_ycheck(int64_t ntiles, int kp)
 
 struct Layout {
     int64_t m, n, k, kp, mp, ldp;
+    int pmax = 0;               // partial slots of the dense fit passes
     size_t total = 0;
     // offsets
     size_t codes, row_count, col_count, Ap;
@@ -135,13 +138,14 @@ bool make_layout(const glrm_data *d, Layout &L)
     L.part_rejc = L.take(sizeof(int32_t) * ya_blocks);
     if (d->layout == GLRM_DENSE) {
         L.Ap = L.take(sizeof(float) * L.mp * ldp);
-        L.part_dy = L.take(sizeof(float) * P_MAX * ldp * kp);
-        L.part_h = L.take(sizeof(float) * P_MAX * ldp);
-        L.part_hp = L.take(sizeof(float) * P_MAX * ldp);
-        L.part_rowreg = L.take(sizeof(float) * P_MAX);
-        L.part_rej = L.take(sizeof(int32_t) * P_MAX);
+        L.pmax = (int)std::clamp<int64_t>(P_BYTES / ((int64_t)sizeof(float) * ldp * kp), 256, P_MAX);
+        L.part_dy = L.take(sizeof(float) * L.pmax * ldp * kp);
+        L.part_h = L.take(sizeof(float) * L.pmax * ldp);
+        L.part_hp = L.take(sizeof(float) * L.pmax * ldp);
+        L.part_rowreg = L.take(sizeof(float) * L.pmax);
+        L.part_rej = L.take(sizeof(int32_t) * L.pmax);
         L.part_dx = L.cb_grad > 1 ? L.take(sizeof(float) * L.cb_grad * m * L.k) : 0;
-        L.part_obj = L.take(sizeof(double) * P_MAX * std::max<int64_t>(L.cb_grad, 1));
+        L.part_obj = L.take(sizeof(double) * P_GRAD * std::max<int64_t>(L.cb_grad, 1));
     } else {
         L.coo = L.take(0);
         coo_layout(d, L.kp, L.cl);
@@ -338,7 +342,7 @@ int dense_lossgrad(const glrm_data *d, const Layout &L, const float *X, const fl
     int rc = write_shadows(L, Y, ws, prec, false, st);
     if (rc != GLRM_OK) return rc;
     const int64_t npanels = L.mp / 16;
-    const int gx = (int)std::min<int64_t>(P_MAX, std::max<int64_t>(1, npanels));
+    const int gx = (int)std::min<int64_t>(P_GRAD, std::max<int64_t>(1, npanels));
     const int gy = (int)L.cb_grad;
     LossGradArgs a;
     a.m = L.m; a.mp = L.mp; a.ldp = L.ldp; a.k = (int32_t)L.k;
@@ -477,7 +481,7 @@ int glrm_objective(const glrm_data *d, const float *X, const float *Y, int preci
         if (d->layout == GLRM_DENSE) {
             if ((rc = dense_lossgrad(d, L, X, Y, precision, nullptr, nullptr, false, ws, st))) return rc;
             po = at<double>(ws, L.part_obj);
-            nparts = (int)(std::min<int64_t>(P_MAX, std::max<int64_t>(1, L.mp / 16)) * L.cb_grad);
+            nparts = (int)(std::min<int64_t>(P_GRAD, std::max<int64_t>(1, L.mp / 16)) * L.cb_grad);
         } else {
             if ((rc = coo_objective(d, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
                                     precision, &po, &nparts, st)))
@@ -509,7 +513,7 @@ int glrm_grad(const glrm_data *d, const float *X, const float *Y, int precision,
     if (d->layout == GLRM_DENSE) {
         if ((rc = dense_lossgrad(d, L, X, Y, precision, dX, dY, true, ws, st))) return rc;
         po = at<double>(ws, L.part_obj);
-        nparts = (int)(std::min<int64_t>(P_MAX, std::max<int64_t>(1, L.mp / 16)) * L.cb_grad);
+        nparts = (int)(std::min<int64_t>(P_GRAD, std::max<int64_t>(1, L.mp / 16)) * L.cb_grad);
     } else {
         if ((rc = coo_grad(d, L.kp, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
                            precision, dX, dY, &po, &nparts, st)))
@@ -583,7 +587,15 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
     if (d->layout == GLRM_DENSE) {
         if ((rc = write_shadows(L, Y, ws, prec, true, st))) return rc;
         const int64_t npanels = L.mp / 16;
-        const int grid = (int)std::min<int64_t>(P_MAX, npanels);
+        // persistent grids: as many workgroups as fit on the device at once
+        int dev = 0, cus = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const bool quad = make_lossu(lt).kind == L_QUAD;
+        const int grid = (int)std::min<int64_t>(
+            {(int64_t)L.pmax, npanels, (int64_t)cus * xstep_blocks((int)L.kp, tpw, prec, quad)});
+        const int grid_y = (int)std::min<int64_t>(
+            {(int64_t)L.pmax, npanels, (int64_t)cus * ycheck_blocks((int)L.kp, tpw_y, prec, quad)});
         XStepArgs xa;
         xa.m = L.m; xa.mp = L.mp; xa.ldp = L.ldp; xa.k = (int32_t)L.k;
         xa.Ap = at<float>(ws, L.Ap);
@@ -618,7 +630,7 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
         ca.part_hp = at<float>(ws, L.part_hp);
 
         YAcceptArgs aa;
-        aa.n = L.n; aa.ldp = L.ldp; aa.k = (int32_t)L.k; aa.P = grid;
+        aa.n = L.n; aa.ldp = L.ldp; aa.k = (int32_t)L.k; aa.P = grid_y;
         aa.part_hp = ca.part_hp; aa.ry_plus = pa.ry_plus; aa.h_old = pa.h_old;
         aa.alpha = alpha_y; aa.step_up = o->step_up; aa.step_down = o->step_down;
         aa.Yplus = pa.Yplus; aa.Y = Y;
@@ -640,7 +652,7 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
             HIP_TRY(launch_yprox(pa, (int)L.kp, prec, st));
             HIP_TRY(timer.stop(st));
             HIP_TRY(timer.start(2, st));
-            HIP_TRY(launch_ycheck(ca, (int)L.kp, tpw_y, prec, grid, st));
+            HIP_TRY(launch_ycheck(ca, (int)L.kp, tpw_y, prec, grid_y, st));
             HIP_TRY(timer.stop(st));
             HIP_TRY(timer.start(3, st));
             HIP_TRY(launch_yaccept(aa, (int)L.kp, prec, ya_blocks, st));

@@ -68,7 +68,32 @@ __device__ __forceinline__ void ordinal_loss(T u, T a, int d, T &l, T &g, bool w
     if (want_g) g = T(n2 - n1);
 }
 
-// Loss value and derivative in u, float, for a loss kind known at compile time.
+// exp(-|t|) with the hardware base-2 exponential (about 1 ulp; it flushes to 0
+// below 2^-126, where the logistic loss and its derivative no longer need it).
+__device__ __forceinline__ float exp_neg_abs(float t)
+{
+    return __builtin_amdgcn_exp2f(-fabsf(t) * 1.4426950408889634f);
+}
+
+// log(1 + e) for e in [0, 1], from log(1 + e) = 2 artanh(s), s = e / (2 + e):
+// s <= 1/3, so the odd series 2 (s + s^3/3 + ... + s^13/13) is within
+// 2 s^15 / (15 (1 - s^2)) of it, below 2e-8 relative.  Exact at e = 0, and
+// accurate for tiny e, where 1 + e rounds to 1.
+__device__ __forceinline__ float log1p_unit(float e)
+{
+    const float s = e * __builtin_amdgcn_rcpf(2.0f + e);
+    const float s2 = s * s;
+    float p = 1.0f / 13.0f;
+    p = p * s2 + 1.0f / 11.0f;
+    p = p * s2 + 1.0f / 9.0f;
+    p = p * s2 + 1.0f / 7.0f;
+    p = p * s2 + 1.0f / 5.0f;
+    p = p * s2 + 1.0f / 3.0f;
+    p = p * s2 + 1.0f;
+    return 2.0f * s * p;
+}
+
+// Loss value and derivative in u, float, for a loss kind known at compile time.// Loss value and derivative in u, float, for a loss kind known at compile time.
 template <int K>
 __device__ __forceinline__ void loss_lg_k(int levels, float param, float u, float a, float &l, float &g)
 {
@@ -83,9 +108,9 @@ __device__ __forceinline__ void loss_lg_k(int levels, float param, float u, floa
     } else if constexpr (K == L_LOGISTIC) {
         // t = -a u;  l = max(t,0) + log1p(exp(-|t|));  dl/du = -a sigmoid(t)
         const float t = -a * u;
-        const float e = __expf(-fabsf(t));
+        const float e = exp_neg_abs(t);
         const float inv = __builtin_amdgcn_rcpf(1.0f + e);
-        l = fmaxf(t, 0.0f) + log1pf(e);
+        l = fmaxf(t, 0.0f) + log1p_unit(e);
         g = -a * (t >= 0.0f ? inv : e * inv);
     } else if constexpr (K == L_HINGE) {
         const float au = a * u;
@@ -107,7 +132,7 @@ __device__ __forceinline__ float loss_l_k(int levels, float param, float u, floa
         return ar <= param ? 0.5f * r * r : param * ar - 0.5f * param * param;
     } else if constexpr (K == L_LOGISTIC) {
         const float t = -a * u;
-        return fmaxf(t, 0.0f) + log1pf(__expf(-fabsf(t)));
+        return fmaxf(t, 0.0f) + log1p_unit(exp_neg_abs(t));
     } else if constexpr (K == L_HINGE) {
         const float au = a * u;
         return au < 1.0f ? 1.0f - au : 0.0f;

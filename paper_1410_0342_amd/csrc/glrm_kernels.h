@@ -157,6 +157,9 @@ struct PackArgs {
 // ---- launchers (dense.hip) ----
 hipError_t launch_xstep(const XStepArgs &a, int kp, int tpw, int prec, int grid, hipStream_t st);
 hipError_t launch_ycheck(const YCheckArgs &a, int kp, int tpw, int prec, int grid, hipStream_t st);
+// Workgroups of the instance the launchers above pick that fit on one CU.
+int xstep_blocks(int kp, int tpw, int prec, bool quad);
+int ycheck_blocks(int kp, int tpw, int prec, bool quad);
 hipError_t launch_yprox(const YProxArgs &a, int kp, int prec, hipStream_t st);
 hipError_t launch_yaccept(const YAcceptArgs &a, int kp, int prec, int blocks, hipStream_t st);
 int yaccept_blocks(int64_t n, int kp);
