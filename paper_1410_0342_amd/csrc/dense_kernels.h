@@ -452,17 +452,18 @@ __device__ __forceinline__ void tile4(int lev, float par, const f32x4 &z, const 
     }
 }
 
-// Losses (and derivatives) of four entries under a per-column loss table.  One
-// copy per variant, called from every tile: inlined per tile, phase and panel
-// buffer, the five loss kinds make the passes far larger than the instruction
-// cache.  tc >= 0: the tile's sixteen columns share loss tc.  tc < 0: codes
-// per entry (cd).
+// Losses (and derivatives) of four entries under a per-column loss table.
+// tc >= 0: the tile's sixteen columns share loss tc.  tc < 0: codes per entry
+// (cd).  Inlined into every tile, phase and panel buffer, the five loss kinds
+// make a pass with 8 or 16 tiles per wavefront 0.2-0.8 MB of code, far beyond
+// the instruction cache; those passes call one shared copy instead
+// (tile_loss_table_call), the smaller ones inline it, which measured faster.
 struct LG4 {
     f32x4 l, g;
 };
 
 template <bool WANT_G>
-__device__ __attribute__((noinline)) LG4 tile_loss_table(const LossTab *tab, int tc, int4 cd, f32x4 z, float4 av)
+__device__ __forceinline__ LG4 tile_loss_table(const LossTab *tab, int tc, int4 cd, f32x4 z, float4 av)
 {
     const float a4[4] = {av.x, av.y, av.z, av.w};
     float l[4], g[4];
@@ -498,12 +499,19 @@ __device__ __attribute__((noinline)) LG4 tile_loss_table(const LossTab *tab, int
 template <int LK>
 constexpr float GRAD_SCALE = LK == L_QUAD ? 2.0f : 1.0f;
 
+template <bool WANT_G>
+__device__ __attribute__((noinline)) LG4 tile_loss_table_call(const LossTab *tab, int tc, int4 cd, f32x4 z,
+                                                              float4 av)
+{
+    return tile_loss_table<WANT_G>(tab, tc, cd, z, av);
+}
+
 // Losses (and, with WANT_G, derivatives) of the lane's four entries of tile t.
 // LK >= 0: every column has loss kind LK (compile time).  LK < 0: the table
 // (tile_loss_table).  TRANS: the four entries are rows 4g + r of column
 // 16t + li (the layout of X . Y^T products) instead of row li, columns
 // 16t + 4g + r.
-template <int LK, bool WANT_G, bool TRANS = false>
+template <int LK, bool WANT_G, bool TRANS = false, int TPW = 1>
 __device__ __forceinline__ void tile_loss(const LossU &lu, const LossTab &tab, const uint8_t *s_codes,
                                           const int8_t *s_tcode, int t, const f32x4 &z, const float4 &av,
                                           float (&l)[4], float (&g)[4])
@@ -524,7 +532,9 @@ __device__ __forceinline__ void tile_loss(const LossU &lu, const LossTab &tab, c
                 cd = int4{c.x, c.y, c.z, c.w};
             }
         }
-        const LG4 r = tile_loss_table<WANT_G>(&tab, tc, cd, z, av);
+        LG4 r;
+        if constexpr (TPW <= 4) r = tile_loss_table<WANT_G>(&tab, tc, cd, z, av);
+        else r = tile_loss_table_call<WANT_G>(&tab, tc, cd, z, av);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             l[q] = r.l[q];
@@ -620,7 +630,7 @@ __device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, N
         }
         if (t >= nt) continue;
         float L4[4], G[4];
-        tile_loss<LK, true, true>(a.lu, *lt, s_codes, s_tcode, t, zt, av, L4, G);
+        tile_loss<LK, true, true, TPW>(a.lu, *lt, s_codes, s_tcode, t, zt, av, L4, G);
         hacc[s] += (L4[0] + L4[1]) + (L4[2] + L4[3]);
         s6_resident<KP, PREC>(dyacc[s], G, xa);
     }
@@ -683,7 +693,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         }
         if (t >= nt) continue;
         float L4[4], G[4];
-        tile_loss<LK, true>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, z, av, L4, G);
+        tile_loss<LK, true, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, z, av, L4, G);
         fpart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
         s3_resident<KP, PREC>(dx, G, ytf[s]);
     }
@@ -748,7 +758,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         }
         if (t >= nt) continue;
         float L4[4], G4[4];
-        tile_loss<LK, false>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av, L4, G4);
+        tile_loss<LK, false, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av, L4, G4);
         fppart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
     }
     sh.red_fp[li][4 * w + g] = fppart;
@@ -990,7 +1000,7 @@ __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP
         const int t = min(w + NWY_OF<KP> * s, nt - 1);
         const f32x4 zp = zprod<KP, PREC>(yfr[s], xf);
         float L4[4], G4[4];
-        tile_loss<LK, false>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av[s], L4, G4);
+        tile_loss<LK, false, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av[s], L4, G4);
 #pragma unroll
         for (int r = 0; r < 4; ++r) hacc[s][r] += L4[r];
     }
