@@ -197,11 +197,17 @@ int coo_check_result(const CooLayout &cl, char *base, hipStream_t st)
 
 // ---- the walks ----------------------------------------------------------------
 
+// Sum over a group of L consecutive lanes (L = 4, 8 or 16) with DPP moves;
+// every lane of the group gets a sum, the group's first lane always in the
+// same order.
 template <int L>
 __device__ __forceinline__ float group_sum(float v)
 {
-#pragma unroll
-    for (int o = L / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    static_assert(L == 4 || L == 8 || L == 16, "entry groups of 4, 8 or 16 lanes");
+    if constexpr (L == 16) v += dpp_mov<0x128>(v);   // row_ror:8
+    if constexpr (L >= 8) v += dpp_mov<0x141>(v);    // row_half_mirror: 7 - (l mod 8)
+    v += dpp_mov<0x4E>(v);                           // quad_perm [2,3,0,1]
+    v += dpp_mov<0xB1>(v);                           // quad_perm [1,0,3,2]
     return v;
 }
 
@@ -248,35 +254,75 @@ struct WalkArgs {
     bool reg_only;           // step: accumulate only r of the decided rows (the other walk counts the loss)
 };
 
+// One entry's loss (and derivative) in the walk.  LK >= 0: every column has
+// loss kind LK (compile time); LK < 0: the code of the entry's column.
+template <int LK>
+__device__ __forceinline__ void walk_lg(const WalkArgs &a, int code, float z, float v, float &l, float &g)
+{
+    if constexpr (LK >= 0) {
+        loss_lg_k<LK>(a.lt.levels[0], a.lt.param[0], z, v, l, g);
+    } else {
+        const int q = a.lt.uniform >= 0 ? a.lt.uniform : code;
+        loss_lg(a.lt.kind[q], a.lt.levels[q], a.lt.param[q], z, v, l, g);
+    }
+}
+
+template <int LK>
+__device__ __forceinline__ float walk_l(const WalkArgs &a, int code, float z, float v)
+{
+    if constexpr (LK >= 0) {
+        return loss_l_k<LK>(a.lt.levels[0], a.lt.param[0], z, v);
+    } else {
+        const int q = a.lt.uniform >= 0 ? a.lt.uniform : code;
+        return loss_l(a.lt.kind[q], a.lt.levels[q], a.lt.param[q], z, v);
+    }
+}
+
 // MODE 0: loss (+ gradient if dU); MODE 1: full half-step; MODE 2: loss in double.
-template <int KP, int MODE>
+// The walk goes through a row's entries in chunks of NS * E: every lane first
+// loads the indices and values of its NS entries, then issues their NS factor
+// gathers, and only then reduces, so each chunk costs two memory round trips.
+template <int KP, int MODE, int LK>
 __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
 {
     constexpr int L = KP / 4;       // lanes per entry
     constexpr int E = 64 / L;       // entries per wavefront step
+    constexpr int NS = 8;           // steps per chunk
     const int lane = threadIdx.x & 63;
     const int slot = lane / L, q = lane % L;
     const int64_t wave = (int64_t)blockIdx.x * CW + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * CW;
     double wsum = 0.0;
     int wrej = 0;
+    const float4 *V4 = reinterpret_cast<const float4 *>(a.Vs);
     for (int64_t i = wave; i < a.rows; i += nwaves) {
         const int32_t beg = a.ptr[i], end = a.ptr[i + 1];
         const float4 x = reinterpret_cast<const float4 *>(a.Us + i * KP)[q];
         const int rowcode = a.codes_by_entry ? 0 : a.codes[i];
         if constexpr (MODE == 2) {
             double acc = 0.0;
-            for (int32_t b = beg; b < end; b += E) {
-                const int32_t e = b + slot;
-                const bool ok = e < end;
-                const int32_t j = ok ? a.idx[e] : 0;
-                const float4 y = ok ? reinterpret_cast<const float4 *>(a.Vs + (int64_t)j * KP)[q] : float4{0, 0, 0, 0};
-                double z = (double)x.x * y.x + (double)x.y * y.y + (double)x.z * y.z + (double)x.w * y.w;
-                z = group_sum64<L>(z);
-                if (ok && q == 0) {
-                    const int code = a.codes_by_entry ? a.codes[j] : rowcode;
-                    const int qq = a.lt.uniform >= 0 ? a.lt.uniform : code;
-                    acc += loss_l64(a.lt.kind[qq], a.lt.levels[qq], (double)a.lt.param[qq], z, (double)a.val[e]);
+            for (int32_t b = beg; b < end; b += NS * E) {
+                int32_t j[NS];
+                float v[NS];
+                float4 y[NS];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int32_t e = b + s * E + slot;
+                    j[s] = e < end ? a.idx[e] : -1;
+                    v[s] = e < end ? a.val[e] : 0.0f;
+                }
+#pragma unroll
+                for (int s = 0; s < NS; ++s) y[s] = j[s] >= 0 ? V4[(int64_t)j[s] * L + q] : float4{0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    double z = (double)x.x * y[s].x + (double)x.y * y[s].y + (double)x.z * y[s].z +
+                               (double)x.w * y[s].w;
+                    z = group_sum64<L>(z);
+                    if (j[s] >= 0 && q == 0) {
+                        const int code = a.codes_by_entry ? a.codes[j[s]] : rowcode;
+                        const int qq = a.lt.uniform >= 0 ? a.lt.uniform : code;
+                        acc += loss_l64(a.lt.kind[qq], a.lt.levels[qq], (double)a.lt.param[qq], z, (double)v[s]);
+                    }
                 }
             }
             wsum += acc;
@@ -284,20 +330,26 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
         }
         float f = 0.0f;
         float4 gacc = {0.f, 0.f, 0.f, 0.f};
-        for (int32_t b = beg; b < end; b += E) {
-            const int32_t e = b + slot;
-            const bool ok = e < end;
-            const int32_t j = ok ? a.idx[e] : 0;
-            const float4 y = ok ? reinterpret_cast<const float4 *>(a.Vs + (int64_t)j * KP)[q] : float4{0, 0, 0, 0};
-            const float z = group_sum<L>(dot4(x, y));
-            float l = 0.f, gr = 0.f;
-            if (ok) {
-                const int code = a.codes_by_entry ? a.codes[j] : rowcode;
-                const int qq = a.lt.uniform >= 0 ? a.lt.uniform : code;
-                loss_lg(a.lt.kind[qq], a.lt.levels[qq], a.lt.param[qq], z, a.val[e], l, gr);
+        for (int32_t b = beg; b < end; b += NS * E) {
+            int32_t j[NS];
+            float v[NS];
+            float4 y[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int32_t e = b + s * E + slot;
+                j[s] = e < end ? a.idx[e] : -1;
+                v[s] = e < end ? a.val[e] : 0.0f;
             }
-            if (q == 0) f += l;
-            gacc.x += gr * y.x; gacc.y += gr * y.y; gacc.z += gr * y.z; gacc.w += gr * y.w;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) y[s] = j[s] >= 0 ? V4[(int64_t)j[s] * L + q] : float4{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const float z = group_sum<L>(dot4(x, y[s]));
+                float l = 0.f, gr = 0.f;
+                if (j[s] >= 0) walk_lg<LK>(a, a.codes_by_entry ? a.codes[j[s]] : rowcode, z, v[s], l, gr);
+                if (q == 0) f += l;
+                gacc.x += gr * y[s].x; gacc.y += gr * y[s].y; gacc.z += gr * y[s].z; gacc.w += gr * y[s].w;
+            }
         }
         gacc.x = across_groups<L>(gacc.x);
         gacc.y = across_groups<L>(gacc.y);
@@ -329,16 +381,22 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
             rcp = group_sum<L>(rcp);
             const float4 xp4 = {xp[0], xp[1], xp[2], xp[3]};
             float fp = 0.0f;
-            for (int32_t b = beg; b < end; b += E) {
-                const int32_t e = b + slot;
-                const bool ok = e < end;
-                const int32_t j = ok ? a.idx[e] : 0;
-                const float4 y = ok ? reinterpret_cast<const float4 *>(a.Vs + (int64_t)j * KP)[q] : float4{0, 0, 0, 0};
-                const float z = group_sum<L>(dot4(xp4, y));
-                if (ok && q == 0) {
-                    const int code = a.codes_by_entry ? a.codes[j] : rowcode;
-                    const int qq = a.lt.uniform >= 0 ? a.lt.uniform : code;
-                    fp += loss_l(a.lt.kind[qq], a.lt.levels[qq], a.lt.param[qq], z, a.val[e]);
+            for (int32_t b = beg; b < end; b += NS * E) {
+                int32_t j[NS];
+                float v[NS];
+                float4 y[NS];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int32_t e = b + s * E + slot;
+                    j[s] = e < end ? a.idx[e] : -1;
+                    v[s] = e < end ? a.val[e] : 0.0f;
+                }
+#pragma unroll
+                for (int s = 0; s < NS; ++s) y[s] = j[s] >= 0 ? V4[(int64_t)j[s] * L + q] : float4{0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const float z = group_sum<L>(dot4(xp4, y[s]));
+                    if (j[s] >= 0 && q == 0) fp += walk_l<LK>(a, a.codes_by_entry ? a.codes[j[s]] : rowcode, z, v[s]);
                 }
             }
             fp = across_groups<L>(group_sum<L>(fp));
@@ -405,16 +463,29 @@ static int walk_grid(int64_t rows)
     return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, COO_MAX_WAVES / CW));
 }
 
-template <int MODE>
-static hipError_t launch_walk(const WalkArgs &a, int kp, int grid, hipStream_t st)
+template <int MODE, int LK>
+static hipError_t launch_walk_lk(const WalkArgs &a, int kp, int grid, hipStream_t st)
 {
     switch (kp) {
-    case 16: hipLaunchKernelGGL((walk_kernel<16, MODE>), dim3(grid), dim3(256), 0, st, a); break;
-    case 32: hipLaunchKernelGGL((walk_kernel<32, MODE>), dim3(grid), dim3(256), 0, st, a); break;
-    case 64: hipLaunchKernelGGL((walk_kernel<64, MODE>), dim3(grid), dim3(256), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((walk_kernel<16, MODE, LK>), dim3(grid), dim3(256), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((walk_kernel<32, MODE, LK>), dim3(grid), dim3(256), 0, st, a); break;
+    case 64: hipLaunchKernelGGL((walk_kernel<64, MODE, LK>), dim3(grid), dim3(256), 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// A table with the quadratic loss everywhere gets its own instances.
+template <int MODE>
+static hipError_t launch_walk(const WalkArgs &a, int kp, int grid, hipStream_t st)
+{
+    if (MODE != 2 && a.lt.uniform >= 0 && a.lt.kind[a.lt.uniform] == L_QUAD) {
+        WalkArgs b = a;
+        b.lt.levels[0] = a.lt.levels[a.lt.uniform];
+        b.lt.param[0] = a.lt.param[a.lt.uniform];
+        return launch_walk_lk<MODE, L_QUAD>(b, kp, grid, st);
+    }
+    return launch_walk_lk<MODE, -1>(a, kp, grid, st);
 }
 
 static WalkArgs row_walk(const glrm_data *d, const CooPtrs &p, const uint8_t *codes, const LossTab &lt)
