@@ -898,27 +898,40 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void xstep_kernel(XStepArgs a)
 // ---------------------------------------------------------------------------
 // Y prox: reduce the partial gradients, step, prox (S7); remember h_j (old)
 // ---------------------------------------------------------------------------
+// A workgroup takes 64 consecutive (column, coordinate) elements; its four
+// wavefronts each sum every fourth of the P partials (so the reads of a
+// wavefront stay coalesced and the grid has n kp / 64 workgroups), and the
+// first wavefront combines the four sums in a fixed order.
+constexpr int YPROX_SPLIT = 4;
+static_assert(YPROX_SPLIT == 4, "the combine below adds four sums");
+
 template <int KP, int PREC>
-__global__ __launch_bounds__(256) void yprox_kernel(YProxArgs a)
+__global__ __launch_bounds__(64 * YPROX_SPLIT) void yprox_kernel(YProxArgs a)
 {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    __shared__ float s_part[YPROX_SPLIT][64];
+    const int el = threadIdx.x & 63, ps = threadIdx.x >> 6;
+    const int64_t t = (int64_t)blockIdx.x * 64 + el;
     const int64_t j = t / KP;
     const int c = (int)(t % KP);
     const bool valid = j < a.n;
-    // fixed-order reduction of the P partials, eight independent running sums
+    // fixed-order reduction of this wavefront's partials, eight running sums
     float gsum = 0.0f;
     if (valid) {
         const float *src = a.part_dy + j * KP + c;
         const int64_t stride = a.ldp * KP;
         float s8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        int p = 0;
-        for (; p + 8 <= a.P; p += 8) {
+        int p = ps;
+        for (; p + 7 * YPROX_SPLIT < a.P; p += 8 * YPROX_SPLIT) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) s8[q] += src[(p + q) * stride];
+            for (int q = 0; q < 8; ++q) s8[q] += src[(int64_t)(p + q * YPROX_SPLIT) * stride];
         }
-        for (; p < a.P; ++p) s8[0] += src[p * stride];
+        for (; p < a.P; p += YPROX_SPLIT) s8[0] += src[(int64_t)p * stride];
         gsum = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
     }
+    s_part[ps][el] = gsum;
+    __syncthreads();
+    if (ps != 0) return;
+    gsum = (s_part[0][el] + s_part[1][el]) + (s_part[2][el] + s_part[3][el]);
     const float y = (valid && c < a.k) ? a.Y[j * a.k + c] : 0.0f;
     const float al = valid ? a.alpha[j] : 0.0f;
     const float yv = (valid && c < a.k) ? prox_elem(a.ry, al, y - al * gsum) : 0.0f;

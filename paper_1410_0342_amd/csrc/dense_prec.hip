@@ -132,8 +132,8 @@ hipError_t launch_ycheck_p(const YCheckArgs &a, int kp, int tpw, int grid, hipSt
 template <int PREC>
 hipError_t launch_yprox_p(const YProxArgs &a, int kp, hipStream_t st)
 {
-    const int blocks = (int)((a.n * (int64_t)kp + 255) / 256);
-    GLRM_DISPATCH_KP(kp, hipLaunchKernelGGL((yprox_kernel<KP, PREC>), dim3(blocks), dim3(256), 0, st, a));
+    const int blocks = (int)((a.n * (int64_t)kp + 63) / 64);
+    GLRM_DISPATCH_KP(kp, hipLaunchKernelGGL((yprox_kernel<KP, PREC>), dim3(blocks), dim3(64 * YPROX_SPLIT), 0, st, a));
     return hipGetLastError();
 }
 
