@@ -215,7 +215,9 @@ class Data:
 def glrm_workspace_size(data):
     size = _L().glrm_workspace_size(ctypes.byref(data.s))
     if size == 0:
-        raise GLRMError(EINVAL, glrm_last_error())
+        # invalid data: glrm_prepare validates first and returns the reason's code
+        rc = _L().glrm_prepare(ctypes.byref(data.s), None, 0, None)
+        raise GLRMError(rc if rc < 0 else EINVAL, glrm_last_error())
     return size
 
 

@@ -164,12 +164,13 @@ int validate_data(const glrm_data *d)
     if (d->m > (int64_t)INT32_MAX || d->n > (int64_t)INT32_MAX) return fail(GLRM_EUNSUPPORTED, "m and n must fit in int32");
     if (d->k < 1) return fail(GLRM_EINVAL, "k must be >= 1 (got %d)", d->k);
     if (d->k > GLRM_MAX_K) return fail(GLRM_EUNSUPPORTED, "k = %d exceeds GLRM_MAX_K = %d", d->k, GLRM_MAX_K);
-    if (!d->A) return fail(GLRM_EINVAL, "A is NULL");
     if (d->layout == GLRM_DENSE) {
+        if (!d->A) return fail(GLRM_EINVAL, "A is NULL");
         if (d->lda < d->n) return fail(GLRM_EINVAL, "lda (%lld) < n (%lld)", (long long)d->lda, (long long)d->n);
     } else if (d->layout == GLRM_COO_ROWSORTED) {
-        if (!d->row || !d->col) return fail(GLRM_EINVAL, "COO row / col is NULL");
         if (d->nnz < 0) return fail(GLRM_EINVAL, "nnz < 0");
+        // an empty observed set needs no arrays
+        if (d->nnz > 0 && (!d->A || !d->row || !d->col)) return fail(GLRM_EINVAL, "COO A / row / col is NULL");
         if (d->nnz > (int64_t)INT32_MAX) return fail(GLRM_EUNSUPPORTED, "nnz must fit in int32 for this build");
     } else {
         return fail(GLRM_EINVAL, "unknown layout %d", d->layout);

@@ -61,7 +61,7 @@ def test_workspace_size_of_a_valid_problem():
     (dict(A=None), "A is NULL"),
     (dict(lda=3), "lda"),
     (dict(layout=7), "unknown layout"),
-    (dict(layout=1, row=None, col=None), "COO row"),
+    (dict(layout=1, row=None, col=None, nnz=5), "COO A / row / col"),
     (dict(losses=[(9, 0, 0.0)]), "unknown kind"),
     (dict(losses=[(1, 0, 0.0)]), "Huber"),
     (dict(losses=[(4, 1, 0.0)]), "ordinal"),
@@ -101,3 +101,10 @@ def test_prox_and_fit_argument_errors():
     o = g._FitOpts(5, g.FP32, 1, 1.0, 1.05, 0.7, 0.0, 0)
     s, keep = _data(n=3000)
     assert g._L().glrm_fit(ctypes.byref(s), P, P, P, P, ctypes.byref(o), None, None, P, 1 << 40, None) == g.EUNSUPPORTED
+
+
+def test_an_empty_coo_needs_no_arrays():
+    """nnz = 0 is a valid (regularizer-only) problem: its arrays may be NULL."""
+    s, keep = _data(layout=1, A=None, row=None, col=None, nnz=0)
+    assert g._L().glrm_workspace_size(ctypes.byref(s)) > 0
+

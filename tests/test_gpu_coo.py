@@ -22,6 +22,9 @@ CASES = [
     dict(m=300, n=45, k=20, seed=4, missing=0.5),
     dict(m=50, n=129, k=40, seed=5, missing=0.6),
     dict(m=33, n=17, k=7, seed=6, empty_row=5, empty_col=3),
+    dict(m=1, n=1, k=1, seed=7, missing=0.0),
+    dict(m=20000, n=40, k=6, seed=10, missing=0.3),
+    dict(m=20, n=10, k=3, seed=11, missing=1.0),        # no entries at all
 ]
 
 

@@ -31,6 +31,11 @@ CASES = [
     dict(m=300, n=45, k=20, seed=4),                    # kp = 32
     dict(m=50, n=129, k=40, seed=5),                    # kp = 64
     dict(m=33, n=17, k=7, seed=6, empty_row=5, empty_col=3),
+    dict(m=1, n=1, k=1, seed=7, missing=0.0),           # one entry, one ragged panel and tile
+    dict(m=40, n=1024, k=20, seed=8),                   # widest fit at kp = 32: every tile slot used
+    dict(m=24, n=512, k=64, seed=9),                    # widest fit at kp = 64
+    dict(m=20000, n=40, k=6, seed=10, missing=0.3),     # narrow and tall: several workgroups per CU
+    dict(m=20, n=10, k=3, seed=11, missing=1.0),        # nothing observed: regularizers only
 ]
 
 
@@ -236,3 +241,20 @@ def test_fit_is_deterministic():
         g.glrm_fit(data, X, Y, ax, ay, 7, precision=g.BF16)
         outs.append((X.cpu().numpy(), Y.cpu().numpy()))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("m,n,k", [(40, 1025, 20), (24, 513, 64), (10, 10, 65)])
+def test_fit_beyond_the_dense_limits_is_reported(m, n, k):
+    """The dense fit keeps a wavefront's tiles resident: n <= 1024 for
+    k <= 32 and n <= 512 for k <= 64; wider tables (and k > 64) are reported
+    as unsupported before any launch, with nothing written."""
+    case = synth.small_mixed(m, n, k, seed=12)
+    data, X, Y, _ = _setup(case)
+    ax = torch.zeros(case.m, dtype=torch.float32, device=DEV)
+    ay = torch.zeros(case.n, dtype=torch.float32, device=DEV)
+    X0 = X.clone()
+    with pytest.raises(g.GLRMError) as err:
+        g.glrm_fit(data, X, Y, ax, ay, 1, precision=g.FP32)
+    assert err.value.code == g.EUNSUPPORTED
+    assert torch.equal(X, X0)
+
