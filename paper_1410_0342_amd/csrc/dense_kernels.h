@@ -269,14 +269,14 @@ struct PanelBuf {
 template <int KP, int TPW, int NW>
 __device__ __forceinline__ void stage_panel(PanelBuf<KP, TPW, NW> &pb, const float *Ap, int64_t ldp, int nt,
                                             const float *X, int64_t m, int k, const float *alpha, int64_t p,
-                                            int w, int lane)
+                                            int w, int lane, int tile0 = 0)
 {
     const int li = lane & 15, g = lane >> 4;
     const int64_t i0 = p * 16;
     const float *arow = Ap + (i0 + li) * ldp + 4 * g;
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = min(w + NW * s, nt - 1);
+        const int t = min(tile0 + w + NW * s, nt - 1);
         lds_dma16(arow + 16 * t, &pb.apan[w][s * 64]);
     }
     const int64_t rows = min<int64_t>(16, m - i0);
@@ -1148,23 +1148,144 @@ __global__ __launch_bounds__(256) void yshadow_kernel(YShadowArgs a)
 // ---------------------------------------------------------------------------
 // objective and gradient (single pass, no decisions)
 // ---------------------------------------------------------------------------
-// grid: x = row chunks, y = column blocks of NW*TPW tiles
-template <int KP, int TPW, int PREC, bool WANT_GRAD>
-__global__ __launch_bounds__(NT, 1) void lossgrad_kernel(LossGradArgs a)
+// grid: x = row chunks (persistent over 16-row panels), y = column blocks of
+// NWX_OF<KP> * TPW tiles.  The structure of the fused row pass without the
+// step: resident Y operands per wavefront, the panel's table tiles and X rows
+// staged in LDS one panel ahead, and a barrier-free tile loop (restrict LDS
+// operands) that the next panel's loads overlap.  A panel's dX partials are
+// combined after the next panel's staging barrier, so each panel needs two
+// barriers and the tile loop none.
+template <int KP, int TPW, int PREC>
+struct GradShared {
+    PanelBuf<KP, TPW, NWX_OF<KP>> buf0, buf1;
+    float red_g[NWX_OF<KP>][16][RS<KP>];            // dX partials of the panel just computed
+    float gsc[NWX_OF<KP>][16 * GS];                 // per-wavefront G transpose tiles
+    LossTab lt;
+    uint8_t s_codes[16 * NWX_OF<KP> * TPW];
+    int8_t s_tcode[NWX_OF<KP> * TPW];
+    double s_obj[NWX_OF<KP>];
+};
+
+template <int KP, int TPW, int PREC, int LK, bool WANT_GRAD>
+__device__ __forceinline__ float grad_tiles(const LossGradArgs &a, PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ nxt,
+                                            int64_t p_next, const PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ cur,
+                                            int rows, int tile0, int nt, float *__restrict__ red_g,
+                                            float *__restrict__ gsc, const LossTab *__restrict__ lt,
+                                            const uint8_t *__restrict__ s_codes, const int8_t *__restrict__ s_tcode,
+                                            const Frag<KP, PREC> (&yfr)[TPW], const YtFrag<KP, PREC> (&ytf)[TPW],
+                                            f32x4 (&dyacc)[TPW][KP / 16])
 {
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     constexpr int C = KP / 4;
-    __shared__ float xs[16][KP];
-    __shared__ __attribute__((aligned(16))) float xat[KP * GS];
-    __shared__ float red_g[NW][16][KP + 1];
-    __shared__ __attribute__((aligned(16))) float gsc_all[NW][16 * GS];
-    __shared__ double s_obj[NW];
-    float *gsc = gsc_all[w];
-    const int64_t ntiles = a.ldp / 16;
-    const int64_t npanels = a.mp / 16;
-    const int64_t tile0 = (int64_t)blockIdx.y * NW * TPW;
+    const int k = a.k;
+    // the panel's X rows straight from the staged block: row li (A operand of
+    // z) and, for S6, rows 4g + q at coordinates 16 kb + li (B operand)
+    Frag<KP, PREC> xf;
+    {
+        float xv[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int c = g * C + q;
+            xv[q] = (li < rows && c < k) ? cur->xrow[li * k + c] : 0.0f;
+        }
+        frag_from_f32<KP, PREC>(xf, xv);
+    }
+    XatFrag<KP, PREC> xa;
+    if constexpr (WANT_GRAD) {
+#pragma unroll
+        for (int kb = 0; kb < KP / 16; ++kb) {
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 4 * g + q, c = 16 * kb + li;
+                v[q] = (i < rows && c < k) ? cur->xrow[i * k + c] : 0.0f;
+            }
+            if constexpr (PREC == P_FP32) xa.f[kb] = float4{v[0], v[1], v[2], v[3]};
+            else xa.b[kb] = pack_bf16x4(v[0], v[1], v[2], v[3]);
+        }
+    }
+    if (p_next >= 0)
+        stage_panel<KP, TPW, NWX_OF<KP>>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, p_next, w, lane, tile0);
+    const float4 *apan = cur->apan[w];
+    float opart = 0.0f;
+    f32x4 dx[KP / 16];
+#pragma unroll
+    for (int kb = 0; kb < KP / 16; ++kb) dx[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4 zn = zprod<KP, PREC>(yfr[0], xf);
+    float4 an = apan[lane];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = tile0 + w + NWX_OF<KP> * s;
+        const f32x4 z = zn;
+        const float4 av = an;
+        if (s + 1 < TPW) {
+            zn = zprod<KP, PREC>(yfr[s + 1], xf);
+            an = apan[(s + 1) * 64 + lane];
+        }
+        if (t >= nt) continue;
+        float L4[4], G[4];
+        tile_loss<LK, WANT_GRAD, false, TPW>(a.lu, *lt, s_codes, s_tcode, t - tile0, z, av, L4, G);
+        opart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
+        if constexpr (WANT_GRAD) {
+            s3_resident<KP, PREC>(dx, G, ytf[s]);
+            float gT[4];
+            transpose_g(gsc + w * 16 * GS, G, gT, li, g);
+            s6_resident<KP, PREC>(dyacc[s], gT, xa);
+        }
+    }
+    if constexpr (WANT_GRAD) {
+#pragma unroll
+        for (int kb = 0; kb < KP / 16; ++kb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red_g[(w * 16 + 4 * g + r) * RS<KP> + 16 * kb + li] = dx[kb][r];
+    }
+    return opart;
+}
 
+// dX rows of panel p from the wavefronts' partials (after a barrier).
+template <int KP, int LK>
+__device__ __forceinline__ void grad_reduce_dx(const LossGradArgs &a, const float (*red_g)[16][RS<KP>], int64_t p)
+{
+    const int64_t i0 = p * 16;
+    for (int t = threadIdx.x; t < 16 * KP; t += NTX_OF<KP>) {
+        const int i = t / KP, c = t % KP;
+        if (i0 + i < a.m && c < a.k) {
+            float s = 0.0f;
+#pragma unroll
+            for (int q = 0; q < NWX_OF<KP>; ++q) s += red_g[q][i][c];
+            s *= GRAD_SCALE<LK>;
+            if (a.part_dx) a.part_dx[((int64_t)blockIdx.y * a.m + i0 + i) * a.k + c] = s;
+            else a.dX[(i0 + i) * a.k + c] = s;
+        }
+    }
+}
+
+template <int KP, int TPW, int PREC, int LK, bool WANT_GRAD>
+__global__ __launch_bounds__(NTX_OF<KP>, 1) void lossgrad_kernel(LossGradArgs a)
+{
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, g = lane >> 4;
+    __shared__ GradShared<KP, TPW, PREC> sh;
+    const int nt = (int)(a.ldp / 16);
+    const int64_t npanels = a.mp / 16;
+    const int64_t G = gridDim.x;
+    const int tile0 = (int)blockIdx.y * NWX_OF<KP> * TPW;
+    const int ntb = min(NWX_OF<KP> * TPW, nt - tile0);   // tiles of this column block
+
+    for (int j = threadIdx.x; j < 16 * NWX_OF<KP> * TPW; j += NTX_OF<KP>)
+        sh.s_codes[j] = a.codes[min(16 * tile0 + j, (int)a.ldp - 1)];
+    if (threadIdx.x == 0) sh.lt = a.lt;
+    __syncthreads();
+    tile_codes(sh.s_codes, ntb, sh.s_tcode, NTX_OF<KP>);
+    Frag<KP, PREC> yfr[TPW];
+    YtFrag<KP, PREC> ytf[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = min(tile0 + w + NWX_OF<KP> * s, nt - 1);
+        frag_load_y<KP, PREC>(yfr[s], a.ycur, 16 * t + li, g);
+        if constexpr (WANT_GRAD) ytfrag_load<KP, PREC>(ytf[s], a.ycur, a.ldp, 16 * t, li, g);
+    }
     f32x4 dyacc[TPW][KP / 16];
 #pragma unroll
     for (int s = 0; s < TPW; ++s)
@@ -1172,93 +1293,51 @@ __global__ __launch_bounds__(NT, 1) void lossgrad_kernel(LossGradArgs a)
         for (int kb = 0; kb < KP / 16; ++kb) dyacc[s][kb] = f32x4{0.f, 0.f, 0.f, 0.f};
     double obj = 0.0;
 
-    for (int64_t p = blockIdx.x; p < npanels; p += gridDim.x) {
-        const int64_t i0 = p * 16;
-        load_panel<KP>(xs, a.X, i0, a.m, a.k);
-        if (WANT_GRAD) {
-            for (int t = threadIdx.x; t < 16 * KP; t += NT) {
-                const int i = t / KP, c = t % KP;
-                xat[c * GS + i] = (i0 + i < a.m && c < a.k) ? a.X[(i0 + i) * a.k + c] : 0.0f;
-            }
-        }
-        __syncthreads();
-        Frag<KP, PREC> xf;
-        frag_from_f32<KP, PREC>(xf, &xs[li][g * C]);
-        f32x4 dx[KP / 16];
+    if (blockIdx.x < npanels)
+        stage_panel<KP, TPW, NWX_OF<KP>>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, blockIdx.x, w, lane,
+                                         tile0);
+    int64_t prev = -1;
+    for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
 #pragma unroll
-        for (int kb = 0; kb < KP / 16; ++kb) dx[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        float opart = 0.0f;
-#pragma unroll
-        for (int s = 0; s < TPW; ++s) {
-            const int64_t t = tile0 + w + NW * s;
-            if (t < ntiles) {
-                const int64_t j0 = 16 * t;
-                const float4 av = *reinterpret_cast<const float4 *>(a.Ap + (i0 + li) * a.ldp + j0 + 4 * g);
-                Frag<KP, PREC> yf;
-                frag_load_y<KP, PREC>(yf, a.ycur, j0 + li, g);
-                const f32x4 z = zprod<KP, PREC>(yf, xf);
-                int cd[4];
-                load_codes(a.codes, j0 + 4 * g, cd);
-                const float avr[4] = {av.x, av.y, av.z, av.w};
-                float G[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float l = 0.f, gr = 0.f;
-                    if (avr[r] == avr[r]) {
-                        if (WANT_GRAD) entry_lg(a.lt, cd[r], z[r], avr[r], l, gr);
-                        else l = entry_l(a.lt, cd[r], z[r], avr[r]);
-                    }
-                    opart += l;
-                    G[r] = gr;
-                }
-                if (WANT_GRAD) {
-                    s3_accum<KP, PREC>(dx, G, a.ycur, a.ldp, j0, li, g);
-                    float gT[4];
-                    transpose_g(gsc, G, gT, li, g);
-                    s6_accum<KP, PREC>(dyacc[s], gT, xat, li, g);
-                }
-            }
-        }
-        obj += (double)opart;
-        if (WANT_GRAD) {
-#pragma unroll
-            for (int kb = 0; kb < KP / 16; ++kb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) red_g[w][4 * g + r][16 * kb + li] = dx[kb][r];
+        for (int b = 0; b < 2; ++b) {
+            const int64_t pc = p + b * G;
+            if (pc >= npanels) break;
+            const int64_t pn = pc + G < npanels ? pc + G : -1;
+            PanelBuf<KP, TPW, NWX_OF<KP>> &cur = b == 0 ? sh.buf0 : sh.buf1;
+            PanelBuf<KP, TPW, NWX_OF<KP>> &nxt = b == 0 ? sh.buf1 : sh.buf0;
+            wait_staged();
+            if (WANT_GRAD && prev >= 0) grad_reduce_dx<KP, LK>(a, sh.red_g, prev);
             __syncthreads();
-            for (int t = threadIdx.x; t < 16 * KP; t += NT) {
-                const int i = t / KP, c = t % KP;
-                if (i0 + i < a.m && c < a.k) {
-                    float s = 0.0f;
-#pragma unroll
-                    for (int q = 0; q < NW; ++q) s += red_g[q][i][c];
-                    if (a.part_dx) a.part_dx[((int64_t)blockIdx.y * a.m + i0 + i) * a.k + c] = s;
-                    else a.dX[(i0 + i) * a.k + c] = s;
-                }
-            }
+            const int rows = (int)min<int64_t>(16, a.m - pc * 16);
+            obj += (double)grad_tiles<KP, TPW, PREC, LK, WANT_GRAD>(a, &nxt, pn, &cur, rows, tile0, nt, &sh.red_g[0][0][0],
+                                                                    &sh.gsc[0][0], &sh.lt, sh.s_codes, sh.s_tcode,
+                                                                    yfr, ytf, dyacc);
+            prev = pc;
         }
-        __syncthreads();
     }
-    if (WANT_GRAD) {
+    __syncthreads();
+    if (WANT_GRAD && prev >= 0) grad_reduce_dx<KP, LK>(a, sh.red_g, prev);
+    if constexpr (WANT_GRAD) {
 #pragma unroll
         for (int s = 0; s < TPW; ++s) {
-            const int64_t t = tile0 + w + NW * s;
-            if (t < ntiles) {
+            const int t = tile0 + w + NWX_OF<KP> * s;
+            if (t < nt && w + NWX_OF<KP> * s < NWX_OF<KP> * TPW) {
                 const int64_t j0 = 16 * t;
 #pragma unroll
                 for (int kb = 0; kb < KP / 16; ++kb)
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        a.part_dy[((int64_t)blockIdx.x * a.ldp + j0 + 4 * g + r) * KP + 16 * kb + li] = dyacc[s][kb][r];
+                        a.part_dy[((int64_t)blockIdx.x * a.ldp + j0 + 4 * g + r) * KP + 16 * kb + li] =
+                            GRAD_SCALE<LK> * dyacc[s][kb][r];
             }
         }
     }
     obj = sum_lanes64<64>(obj);
-    if (lane == 0) s_obj[w] = obj;
+    if (lane == 0) sh.s_obj[w] = obj;
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int q = 0; q < NW; ++q) s += s_obj[q];
+        for (int q = 0; q < NWX_OF<KP>; ++q) s += sh.s_obj[q];
         a.part_obj[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
     }
 }

@@ -155,13 +155,17 @@ hipError_t launch_yshadow_p(const YShadowArgs &a, int kp, hipStream_t st)
 template <int PREC>
 hipError_t launch_lossgrad_p(const LossGradArgs &a, int kp, int tpw, bool want_grad, int gx, int gy, hipStream_t st)
 {
+    const bool quad = a.lu.kind == L_QUAD;
     if (want_grad) {
-        GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW(tpw,
-            if constexpr (KP == 64 && TPW == 8) return hipErrorInvalidValue;
-            else hipLaunchKernelGGL((lossgrad_kernel<KP, TPW, PREC, true>), dim3(gx, gy), dim3(NT), 0, st, a)));
+        GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW16(tpw, GLRM_DISPATCH_LK(quad,
+            if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
+            else hipLaunchKernelGGL((lossgrad_kernel<KP, TPW, PREC, LK, true>), dim3(gx, gy), dim3(NTX_OF<KP>), 0, st,
+                                    a))));
     } else {
-        GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW(tpw,
-            hipLaunchKernelGGL((lossgrad_kernel<KP, TPW, PREC, false>), dim3(gx, gy), dim3(NT), 0, st, a)));
+        GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW16(tpw, GLRM_DISPATCH_LK(quad,
+            if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
+            else hipLaunchKernelGGL((lossgrad_kernel<KP, TPW, PREC, LK, false>), dim3(gx, gy), dim3(NTX_OF<KP>), 0, st,
+                                    a))));
     }
     return hipGetLastError();
 }

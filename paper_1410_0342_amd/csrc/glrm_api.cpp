@@ -40,7 +40,6 @@ int fail(int code, const char *fmt, ...)
 constexpr int P_MAX = 1024;    // workgroups (and partials) of the persistent dense fit passes, at most
 constexpr int64_t P_BYTES = 64ll << 20;  // ... and the Y-gradient partials within this (256 at least)
 constexpr int P_GRAD = 256;    // row chunks of the one-pass loss gradient
-constexpr int NWAVES = 8;      // wavefronts per dense workgroup (matches the kernels)
 constexpr int REG_BLOCKS = 64; // partials of a regularizer sum
 constexpr int OBJ64_BLOCKS = 2048;  // workgroups (and partials) of the FP64 objective
 
@@ -48,15 +47,7 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 int kp_of(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
 
-// Tiles per wavefront needed to cover `ntiles` column tiles in one workgroup.
-int tpw_for(int64_t ntiles)
-{
-    for (int t : {1, 2, 4, 8})
-        if ((int64_t)NWAVES * t >= ntiles) return t;
-    return 0;
-}
-
-// The same for the two passes of the fit: the fused row pass runs
+// Tiles per wavefront of the two passes of the fit: the fused row pass runs
 // xstep_waves(kp) wavefronts of up to 16 tiles (8 at kp = 64), the trial-column
 // pass ycheck_waves(kp) wavefronts of up to 8 tiles.
 int tpw_xstep(int64_t ntiles, int kp)
@@ -106,10 +97,15 @@ bool make_layout(const glrm_data *d, Layout &L)
     L.mp = round_up(d->m, 16);
     L.ldp = round_up(d->n, 16);
     const int64_t ntiles = L.ldp / 16;
-    L.tpw_grad = tpw_for(ntiles);
-    if (L.tpw_grad == 0 || L.tpw_grad > 4) L.tpw_grad = 4;
-    if (L.kp == 64 && L.tpw_grad > 4) L.tpw_grad = 4;
-    L.cb_grad = (ntiles + NWAVES * L.tpw_grad - 1) / (NWAVES * L.tpw_grad);
+    // the gradient pass: xstep_waves(kp) wavefronts of up to 16 tiles (4 at
+    // kp = 64); wider tables take several column blocks
+    {
+        const int tmax = L.kp == 64 ? 4 : 16, nw = xstep_waves((int)L.kp);
+        int t = 1;
+        while (t < tmax && (int64_t)nw * t < ntiles) t *= 2;
+        L.tpw_grad = t;
+        L.cb_grad = (ntiles + nw * t - 1) / (nw * t);
+    }
     const int64_t kp = L.kp, ldp = L.ldp, n = L.n, m = L.m;
     L.codes = L.take(ldp);
     L.row_count = L.take(sizeof(int32_t) * m);
@@ -336,20 +332,30 @@ int objective64(const glrm_data *d, const Layout &L, const float *X, const float
     return GLRM_OK;
 }
 
+// Row chunks of the loss pass.  With the gradient, P_GRAD workgroups in all,
+// so a table cut into several column blocks takes fewer, longer row chunks
+// (and fewer Y-gradient partials to reduce); the objective alone has no
+// partials to spare and keeps P_GRAD row chunks per column block.
+int grad_rows(const Layout &L, bool want_grad)
+{
+    const int64_t per = want_grad ? (P_GRAD + L.cb_grad - 1) / L.cb_grad : P_GRAD;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(per, L.mp / 16));
+}
+
 // Dense loss (+ gradient) pass at fp32 / bf16 precision.
 int dense_lossgrad(const glrm_data *d, const Layout &L, const float *X, const float *Y, int prec, float *dX,
                    float *dY, bool want_grad, void *ws, hipStream_t st)
 {
     int rc = write_shadows(L, Y, ws, prec, false, st);
     if (rc != GLRM_OK) return rc;
-    const int64_t npanels = L.mp / 16;
-    const int gx = (int)std::min<int64_t>(P_GRAD, std::max<int64_t>(1, npanels));
+    const int gx = grad_rows(L, want_grad);
     const int gy = (int)L.cb_grad;
     LossGradArgs a;
     a.m = L.m; a.mp = L.mp; a.ldp = L.ldp; a.k = (int32_t)L.k;
     a.Ap = at<float>(ws, L.Ap);
     a.codes = at<uint8_t>(ws, L.codes);
     a.lt = make_losstab(d);
+    a.lu = make_lossu(a.lt);
     a.X = X;
     a.ycur = shadow(ws, L, false);
     a.dX = dX;
@@ -482,7 +488,7 @@ int glrm_objective(const glrm_data *d, const float *X, const float *Y, int preci
         if (d->layout == GLRM_DENSE) {
             if ((rc = dense_lossgrad(d, L, X, Y, precision, nullptr, nullptr, false, ws, st))) return rc;
             po = at<double>(ws, L.part_obj);
-            nparts = (int)(std::min<int64_t>(P_GRAD, std::max<int64_t>(1, L.mp / 16)) * L.cb_grad);
+            nparts = (int)(grad_rows(L, false) * L.cb_grad);
         } else {
             if ((rc = coo_objective(d, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
                                     precision, &po, &nparts, st)))
@@ -514,7 +520,7 @@ int glrm_grad(const glrm_data *d, const float *X, const float *Y, int precision,
     if (d->layout == GLRM_DENSE) {
         if ((rc = dense_lossgrad(d, L, X, Y, precision, dX, dY, true, ws, st))) return rc;
         po = at<double>(ws, L.part_obj);
-        nparts = (int)(std::min<int64_t>(P_GRAD, std::max<int64_t>(1, L.mp / 16)) * L.cb_grad);
+        nparts = (int)(grad_rows(L, true) * L.cb_grad);
     } else {
         if ((rc = coo_grad(d, L.kp, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
                            precision, dX, dY, &po, &nparts, st)))

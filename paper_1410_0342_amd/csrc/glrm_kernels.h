@@ -119,6 +119,7 @@ struct LossGradArgs {
     const float *Ap;
     const uint8_t *codes;
     LossTab lt;
+    LossU lu;
     const float *X;
     YShadow ycur;
     float *dX;              // m x k, written when part_dx is null
