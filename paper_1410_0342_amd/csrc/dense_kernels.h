@@ -5,15 +5,18 @@
 // columns to a multiple of 16) in which every unobserved entry is a quiet NaN,
 // so one 4-byte load gives both the value and the observation bit.
 //
-// Work decomposition: a workgroup of 8 wavefronts walks 16-row panels.  The
-// panel's columns are cut into 16-wide tiles and tile t belongs to wavefront
-// t mod 8 for the whole launch, so each wavefront can keep per-column
-// accumulators (column objective, Y gradient) in registers across panels.
+// Work decomposition: a persistent workgroup of W wavefronts walks 16-row
+// panels.  The panel's columns are cut into 16-wide tiles and tile t belongs
+// to wavefront t mod W for the whole launch, so each wavefront keeps its
+// tiles' Y operands and its per-column accumulators (column objective, Y
+// gradient) in registers across panels.  The next panel's table tiles travel
+// straight from HBM into LDS while the current one computes.
 //
 // Matrix-core products per 16 x 16 tile (i = row of the panel, j = column):
 //   z     Z^T(16j x 16i) = Y_tile(16j x kp) . X_panel^T        -> lane holds z(i=l%16, j=4(l/16)+r)
 //   S3    dX(16i x 16kc) += G(16i x 16j) . Y_tile(16j x 16kc)   (G straight from the z layout)
-//   S6    dY(16j x 16kc) += G^T(16j x 16i) . X(16i x 16kc)      (G transposed through LDS)
+//   S6    Z(16i x 16j) = X_panel . Y_tile^T                     -> lane holds z(i=4(l/16)+r, j=l%16)
+//         dY(16j x 16kc) += G^T(16j x 16i) . X(16i x 16kc)      (G straight from that layout)
 // The k index each lane feeds is a free choice as long as both operands use
 // the same one: lane group g = l/16 feeds the contiguous run k = g*kp/4 ...
 // (g+1)*kp/4 - 1, which makes every operand load one contiguous vector.
@@ -24,9 +27,7 @@
 
 namespace glrm {
 
-constexpr int NW = 8;            // wavefronts per workgroup
-constexpr int NT = NW * 64;      // threads per workgroup
-constexpr int GS = 20;           // row stride (floats) of the per-wave transpose tile
+constexpr int GS = 20;           // row stride (floats) of the per-wave transpose tiles
 
 // ---------------------------------------------------------------------------
 // operand fragments
@@ -130,55 +131,6 @@ __device__ __forceinline__ f32x4 zprod(const Frag<KP, PREC> &y, const Frag<KP, P
     return acc;
 }
 
-// S3: dX block kb (16 rows x 16 of k) += G(16i x 16j) . Y_tile(16j x 16kc).
-// G[r] = G(i = l%16, j = 4g + r).  Y^T shadow row kc holds y_j for all j.
-template <int KP, int PREC>
-__device__ __forceinline__ void s3_accum(f32x4 (&dx)[KP / 16], const float (&G)[4], const YShadow &ys,
-                                         int64_t ldp, int64_t j0, int li, int g)
-{
-#pragma unroll
-    for (int kb = 0; kb < KP / 16; ++kb) {
-        const int64_t off = (int64_t)(16 * kb + li) * ldp + j0 + 4 * g;
-        if constexpr (PREC == P_FP32) {
-            float4 b = *reinterpret_cast<const float4 *>(ys.t32 + off);
-            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[0], b.x, dx[kb], 0, 0, 0);
-            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[1], b.y, dx[kb], 0, 0, 0);
-            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[2], b.z, dx[kb], 0, 0, 0);
-            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(G[3], b.w, dx[kb], 0, 0, 0);
-        } else {
-            i16x4 av, bv;
-            *reinterpret_cast<uint2 *>(&bv) = *reinterpret_cast<const uint2 *>(ys.tb + off);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) av[s] = bf16_bits(to_bf16(G[s]));
-            dx[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, dx[kb], 0, 0, 0);
-        }
-    }
-}
-
-// S6: dY block (16 j x 16 kc) += G^T(16j x 16i) . X(16i x 16kc).  gT[s] =
-// G(i = 4g + s, j = l%16); xat is the panel's X transposed in LDS ([kc][i]).
-template <int KP, int PREC>
-__device__ __forceinline__ void s6_accum(f32x4 (&dy)[KP / 16], const float (&gT)[4], const float *xat, int li, int g)
-{
-#pragma unroll
-    for (int kb = 0; kb < KP / 16; ++kb) {
-        float4 b = *reinterpret_cast<const float4 *>(xat + (16 * kb + li) * GS + 4 * g);
-        if constexpr (PREC == P_FP32) {
-            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gT[0], b.x, dy[kb], 0, 0, 0);
-            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gT[1], b.y, dy[kb], 0, 0, 0);
-            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gT[2], b.z, dy[kb], 0, 0, 0);
-            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x4f32(gT[3], b.w, dy[kb], 0, 0, 0);
-        } else {
-            i16x4 av, bv;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) av[s] = bf16_bits(to_bf16(gT[s]));
-            bv[0] = bf16_bits(to_bf16(b.x)); bv[1] = bf16_bits(to_bf16(b.y));
-            bv[2] = bf16_bits(to_bf16(b.z)); bv[3] = bf16_bits(to_bf16(b.w));
-            dy[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, dy[kb], 0, 0, 0);
-        }
-    }
-}
-
 // Transpose the wave's 16x16 G tile through LDS.
 __device__ __forceinline__ void transpose_g(float *gsc, const float (&G)[4], float (&gT)[4], int li, int g)
 {
@@ -192,36 +144,6 @@ __device__ __forceinline__ void transpose_g(float *gsc, const float (&G)[4], flo
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Loss codes of the lane's four columns.
-__device__ __forceinline__ void load_codes(const uint8_t *codes, int64_t j, int (&cd)[4])
-{
-    uchar4 c = *reinterpret_cast<const uchar4 *>(codes + j);
-    cd[0] = c.x; cd[1] = c.y; cd[2] = c.z; cd[3] = c.w;
-}
-
-__device__ __forceinline__ void entry_lg(const LossTab &lt, int code, float u, float a, float &l, float &gr)
-{
-    const int q = lt.uniform >= 0 ? lt.uniform : code;
-    loss_lg(lt.kind[q], lt.levels[q], lt.param[q], u, a, l, gr);
-}
-
-__device__ __forceinline__ float entry_l(const LossTab &lt, int code, float u, float a)
-{
-    const int q = lt.uniform >= 0 ? lt.uniform : code;
-    return loss_l(lt.kind[q], lt.levels[q], lt.param[q], u, a);
-}
-
-// Load the 16 x k panel of a factor into LDS as fp32 [16][KP] (zero padded).
-template <int KP>
-__device__ __forceinline__ void load_panel(float (*xs)[KP], const float *X, int64_t i0, int64_t m, int k)
-{
-    for (int t = threadIdx.x; t < 16 * KP; t += NT) {
-        const int i = t / KP, c = t % KP;
-        const int64_t gi = i0 + i;
-        xs[i][c] = (gi < m && c < k) ? X[gi * k + c] : 0.0f;
-    }
 }
 
 // Wavefronts per workgroup of the two passes over the table (xstep_waves,
@@ -388,30 +310,6 @@ __device__ __forceinline__ void s6_resident(f32x4 (&dy)[KP / 16], const float (&
         for (int kb = 0; kb < KP / 16; ++kb)
             dy[kb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, xa.b[kb], dy[kb], 0, 0, 0);
     }
-}
-
-__device__ __forceinline__ void codes_of(const LossU &lu, const uint8_t *s_codes, int j, int (&cd)[4])
-{
-    if (lu.kind >= 0) {
-        cd[0] = cd[1] = cd[2] = cd[3] = 0;
-    } else {
-        uchar4 c = *reinterpret_cast<const uchar4 *>(s_codes + j);
-        cd[0] = c.x; cd[1] = c.y; cd[2] = c.z; cd[3] = c.w;
-    }
-}
-
-// A uniform loss comes from scalar arguments; a per-column table from LDS.
-__device__ __forceinline__ void entry_lg_u(const LossU &lu, const LossTab &tab, int code, float u, float a, float &l,
-                                           float &gr)
-{
-    if (lu.kind >= 0) loss_lg(lu.kind, lu.levels, lu.param, u, a, l, gr);
-    else loss_lg(tab.kind[code], tab.levels[code], tab.param[code], u, a, l, gr);
-}
-
-__device__ __forceinline__ float entry_l_u(const LossU &lu, const LossTab &tab, int code, float u, float a)
-{
-    if (lu.kind >= 0) return loss_l(lu.kind, lu.levels, lu.param, u, a);
-    return loss_l(tab.kind[code], tab.levels[code], tab.param[code], u, a);
 }
 
 // HALF (quadratic loss only): g is half the derivative, z - a; the caller
