@@ -217,6 +217,8 @@ def main():
                 (res["fp32"]["ms_per_step"] * (args.steps + args.warmup)) / (res["bf16"]["ms_per_step"] * sweeps_to)
                 if sweeps_to else None)}
         line["fp32"] = {"value": res["fp32"]["value"], "ms_per_step": res["fp32"]["ms_per_step"]}
+        line["rejected_last_sweep"] = {p: {"rows": res[p]["rows_rejected"], "cols": res[p]["cols_rejected"]}
+                                       for p in ("bf16", "fp32")}
         line["bf16_over_fp32"] = res["bf16"]["value"] / res["fp32"]["value"]
     line["kernel_ms_per_sweep"] = {p: res[p]["kernel_ms"] for p in res}
     if not args.no_cpu_baseline and case.layout == "dense":
