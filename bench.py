@@ -47,6 +47,8 @@ def workload(name):
         return synth.sparse_completion()
     if name == "plain_pca":
         return synth.plain_pca()
+    if name == "autograd":
+        return synth.autograd_point()
     raise SystemExit("unknown workload " + name)
 
 
@@ -99,6 +101,37 @@ def run_gpu(case, precisions, steps, warmup):
     return out
 
 
+def run_grad(case, precisions, steps, warmup):
+    """One step = one objective-and-gradient evaluation (glrm_grad with the
+    objective) at a fixed point: the autograd forward and backward."""
+    import torch
+
+    import paper_1410_0342_amd as g
+
+    dev = torch.device("cuda:0")
+    data = g.Data.from_case(case, dev)
+    g.glrm_prepare(data)
+    X = torch.from_numpy(case.X0).to(dev)
+    Y = torch.from_numpy(case.Y0).to(dev)
+    dX = torch.empty_like(X)
+    dY = torch.empty_like(Y)
+    out = {}
+    for pname in precisions:
+        prec = g.PRECISIONS[pname]
+        for _ in range(max(warmup, 1)):
+            g.glrm_grad(data, X, Y, prec, dX=dX, dY=dY, flags=g.WS_PREPARED)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.glrm_grad(data, X, Y, prec, dX=dX, dY=dY, flags=g.WS_PREPARED)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+        _, _, obj = g.glrm_grad(data, X, Y, prec, dX=dX, dY=dY, want_objective=True, flags=g.WS_PREPARED)
+        out[pname] = dict(ms_per_step=ms, value=case.nnz / (ms * 1e-3), objective=obj)
+        log("%s: %.4f ms per objective and gradient, %.4g entries/s, F = %.10g" % (pname, ms, out[pname]["value"], obj))
+    return out
+
+
 def copy_calibration():
     """A plain device copy of known size (for scaling rocprofv3 byte counters)."""
     import torch
@@ -135,7 +168,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dense_quadratic",
-                    choices=["dense_quadratic", "heterogeneous", "sparse_completion", "plain_pca"])
+                    choices=["dense_quadratic", "heterogeneous", "sparse_completion", "plain_pca", "autograd"])
     ap.add_argument("--precision", default="both", choices=["both", "bf16", "fp32", "bf16_plain"])
     ap.add_argument("--cpu-rows", type=int, default=100000)
     ap.add_argument("--cpu-sweeps", type=int, default=2)
@@ -158,6 +191,29 @@ def main():
         precisions = ["fp32"]
     else:
         precisions = ["bf16", "fp32"] if args.precision == "both" else [args.precision]
+    if args.workload == "autograd":
+        res = run_grad(case, precisions, args.steps, args.warmup)
+        head = precisions[0]
+        r = res[head]
+        m, n, k = case.m, case.n, case.k
+        alg_bytes = 4.0 * m * n + 8.0 * m * k + 8.0 * n * k   # table, X and dX, Y and dY
+        achieved = alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9
+        line = {
+            "metric": "observed entries/s per objective and gradient evaluation",
+            "value": r["value"], "unit": "entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16" if head.startswith("bf16") else "f32", "data": "synthetic",
+            "config": {"workload": case.name, "m": m, "n": n, "k": k, "observed_entries": int(case.nnz),
+                       "layout": "dense", "precision": head},
+            "roofline": {"bound": "hbm", "kernel": "objective and gradient call (all its kernels)",
+                         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": None, "algorithmic_bytes_per_launch": alg_bytes},
+            "objective": {p: res[p]["objective"] for p in res},
+        }
+        if "fp32" in res and head != "fp32":
+            line["fp32"] = {"value": res["fp32"]["value"], "ms_per_step": res["fp32"]["ms_per_step"]}
+        print(json.dumps(line), flush=True)
+        return
     res = run_gpu(case, precisions, args.steps, args.warmup)
     if args.copy_calibration:
         copy_calibration()

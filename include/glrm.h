@@ -107,7 +107,8 @@ typedef struct {
      *        finite.
      * COO:   A holds the nnz observed values (device); row / col are the nnz
      *        0-based indices (device int32), sorted by row then column, no
-     *        duplicates.  mask and lda are ignored. */
+     *        duplicates.  With nnz = 0 the three may be NULL (only the
+     *        regularizers remain).  mask and lda are ignored. */
     const float   *A;
     int64_t        lda;
     const uint8_t *mask;
@@ -202,7 +203,12 @@ typedef struct {
  * arrays updated in place, so a second call resumes the fit.  history
  * (device, max_sweeps doubles, may be NULL) receives F after each sweep as the
  * sweep tracked it.  info_host (host, may be NULL) is filled at the end.
- * Synchronizes `stream`. */
+ * The dense layout keeps a table row's tiles on one workgroup: it fits
+ * n <= 1024 for k <= 32 and n <= 512 for k <= 64 and returns
+ * GLRM_EUNSUPPORTED above (the COO layout has no such limit).  On one device
+ * the results are bitwise reproducible: partial sums are combined in a fixed
+ * order (how many there are follows the device's size).  Synchronizes
+ * `stream`. */
 int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alpha_y,
              const glrm_fit_opts *opts, glrm_fit_info *info_host, double *history,
              void *ws, size_t ws_bytes, void *stream);
