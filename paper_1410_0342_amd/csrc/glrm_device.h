@@ -39,33 +39,22 @@ struct Reg {
 
 // ---- losses ------------------------------------------------------------------
 
-// Ordinal hinge in closed form.  With c = u - 1 the lower hinges (1 - u + a')_+
-// for a' = 1..a-1 are positive exactly for a' > c; with c2 = u + 1 the upper
-// hinges (1 + u - a')_+ for a' = a+1..d are positive exactly for a' < c2.  Each
-// positive run is an arithmetic series.
+// Ordinal hinge in closed form.  The lower hinges (1 - u + a')_+ for
+// a' = 1..a-1 are positive exactly for a' > u - 1, i.e. from lo = max(1, floor u);
+// the upper hinges (1 + u - a')_+ for a' = a+1..d are positive exactly for
+// a' < u + 1, i.e. up to hi = min(d, ceil u).  Each positive run is an
+// arithmetic series; every bound stays in floating point.
 template <typename T>
 __device__ __forceinline__ void ordinal_loss(T u, T a, int d, T &l, T &g, bool want_g)
 {
-    const int ai = (int)a;
-    // lower hinges: a' in [lo, a-1], lo = smallest integer > u - 1, at least 1
-    // only levels 1..d matter, so the integer bounds are taken on clamped values
-    T c = u - T(1);
-    T cc = c < T(-1) ? T(-1) : (c > T(d + 1) ? T(d + 1) : c);
-    int lo = (int)floor(cc) + 1;
-    lo = lo < 1 ? 1 : lo;
-    int n1 = ai - lo;
-    n1 = n1 < 0 ? 0 : n1;
-    // upper hinges: a' in [a+1, hi], hi = largest integer < u + 1, at most d
-    T c2 = u + T(1);
-    T cc2 = c2 < T(0) ? T(0) : (c2 > T(d + 2) ? T(d + 2) : c2);
-    int hi = (int)ceil(cc2) - 1;
-    hi = hi > d ? d : hi;
-    int n2 = hi - ai;
-    n2 = n2 < 0 ? 0 : n2;
-    T s1 = T(n1) * (T(lo + ai - 1) * T(0.5) - c);
-    T s2 = T(n2) * (c2 - T(ai + 1 + hi) * T(0.5));
+    const T lo = fmax(T(1), floor(u));
+    const T hi = fmin(T(d), ceil(u));
+    const T n1 = fmax(T(0), a - lo);     // lower hinges in [lo, a - 1]
+    const T n2 = fmax(T(0), hi - a);     // upper hinges in [a + 1, hi]
+    const T s1 = n1 * ((lo + a - T(1)) * T(0.5) - (u - T(1)));
+    const T s2 = n2 * ((u + T(1)) - (a + T(1) + hi) * T(0.5));
     l = s1 + s2;
-    if (want_g) g = T(n2 - n1);
+    if (want_g) g = n2 - n1;
 }
 
 // exp(-|t|) with the hardware base-2 exponential (about 1 ulp; it flushes to 0
