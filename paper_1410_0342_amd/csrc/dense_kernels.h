@@ -186,27 +186,39 @@ struct PanelBuf {
     float alpha[16];
 };
 
-// Issue the loads of panel p into `pb` (every wavefront issues its own tiles;
-// X rows and step sizes are spread over the wavefronts).
+// Loads of panel p into `pb`: tile slot s of this wavefront ...
 template <int KP, int TPW, int NW>
-__device__ __forceinline__ void stage_panel(PanelBuf<KP, TPW, NW> &pb, const float *Ap, int64_t ldp, int nt,
-                                            const float *X, int64_t m, int k, const float *alpha, int64_t p,
-                                            int w, int lane, int tile0 = 0)
+__device__ __forceinline__ void stage_tile(PanelBuf<KP, TPW, NW> &pb, const float *Ap, int64_t ldp, int nt, int64_t p,
+                                           int w, int lane, int s, int tile0 = 0)
 {
     const int li = lane & 15, g = lane >> 4;
+    const int t = min(tile0 + w + NW * s, nt - 1);
+    lds_dma16(Ap + (p * 16 + li) * ldp + 4 * g + 16 * t, &pb.apan[w][s * 64]);
+}
+
+// ... and the X rows and step sizes (spread over the wavefronts).
+template <int KP, int TPW, int NW>
+__device__ __forceinline__ void stage_rows(PanelBuf<KP, TPW, NW> &pb, const float *X, int64_t m, int k,
+                                           const float *alpha, int64_t p, int w, int lane)
+{
     const int64_t i0 = p * 16;
-    const float *arow = Ap + (i0 + li) * ldp + 4 * g;
-#pragma unroll
-    for (int s = 0; s < TPW; ++s) {
-        const int t = min(tile0 + w + NW * s, nt - 1);
-        lds_dma16(arow + 16 * t, &pb.apan[w][s * 64]);
-    }
     const int64_t rows = min<int64_t>(16, m - i0);
     const int nx = (int)(rows * k);            // valid floats of the row block
     const float *xb = X + i0 * k;
     for (int q = w; q * 64 < nx; q += NW)
         if (q * 64 + lane < nx) lds_dma4(xb + q * 64 + lane, &pb.xrow[q * 64]);
     if (alpha && w == NW - 1 && lane < rows) lds_dma4(alpha + i0 + lane, &pb.alpha[0]);
+}
+
+// All loads of panel p into `pb` (every wavefront issues its own tiles).
+template <int KP, int TPW, int NW>
+__device__ __forceinline__ void stage_panel(PanelBuf<KP, TPW, NW> &pb, const float *Ap, int64_t ldp, int nt,
+                                            const float *X, int64_t m, int k, const float *alpha, int64_t p,
+                                            int w, int lane, int tile0 = 0)
+{
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) stage_tile<KP, TPW, NW>(pb, Ap, ldp, nt, p, w, lane, s, tile0);
+    stage_rows<KP, TPW, NW>(pb, X, m, k, alpha, p, w, lane);
 }
 
 // The lane's four table entries of tile slot s.  A slot past the last tile
@@ -462,22 +474,55 @@ __device__ __forceinline__ void tile_codes(const uint8_t *s_codes, int nt, int8_
 template <int KP>
 constexpr int RS = KP + 4;
 
+// Row stride of the row-gradient partials ([coordinate][row], 16 rows padded
+// to 20 floats: 16-byte aligned, and the S4 reads of 16 coordinates x 4 rows
+// land in distinct banks).
+constexpr int RG = 20;
+
 // Row stride of the row-objective partials (4 per wavefront, padded so the
 // 64 lanes of a wavefront write to distinct banks).
 template <int KP>
 constexpr int RF = 4 * NWX_OF<KP> + 4;
 
-template <int KP, int TPW, int PREC>
-struct XStepShared {
+// Where the row pass issues the next panel's loads.  The bf16 forms spread
+// them over the trial-row loop (S5), so the fetch overlaps S5, the decisions
+// and S6; the FP32 form, whose longer products keep the matrix cores busy in
+// S5, issues them all at the start of S6.
+template <int PREC>
+constexpr bool STAGE_IN_S5 = PREC != P_FP32;
+
+// The row pass's barriers inside a panel: LDS-only where the prefetch is in
+// flight across them (bf16 forms), full otherwise.
+template <int PREC>
+__device__ __forceinline__ void panel_barrier()
+{
+    if constexpr (STAGE_IN_S5<PREC>) lds_barrier();
+    else __syncthreads();
+}
+
+// The two panel buffers of the row pass.  FP32 keeps them in the shared
+// struct and a panel picks its buffer by index.  The bf16 forms, whose
+// prefetch is in flight while the panel reads LDS, keep them as LDS objects
+// of their own and hand them to the panel as restrict pointers: the compiler
+// then knows the loads into one buffer cannot alias the panel's other LDS
+// traffic, and issues no wait for them before those reads.  (With the FP32
+// form's tighter register budget the pointer version spills; the indexed one
+// does not.)
+template <int KP, int TPW, bool INSIDE>
+struct XStepBufs {};
+template <int KP, int TPW>
+struct XStepBufs<KP, TPW, true> {
     PanelBuf<KP, TPW, NWX_OF<KP>> buf0, buf1;
+};
+
+template <int KP, int TPW, int PREC>
+struct XStepShared : XStepBufs<KP, TPW, !STAGE_IN_S5<PREC>> {
     float xs[16][RS<KP>];    // the accepted rows (S6 operand)
     float xp[16][RS<KP>];    // trial rows
-    union alignas(16) {
-        float red_g[NWX_OF<KP>][16][RS<KP>];     // row-gradient partials (S3 -> S4)
-        struct {
-            float xat[KP * GS];           // accepted X transposed ([kc][i]) for S6
-        } d;
-    } u;
+    // row-gradient partials (S3 -> S4), [wavefront][coordinate][row]: a lane's
+    // four rows of one coordinate are one 16-byte write
+    alignas(16) float red_g[NWX_OF<KP>][KP][RG];
+    alignas(16) float xat[KP * GS];                     // accepted X transposed ([kc][i]) for S6
     // row-objective partials at x (S2) and at the trial rows (S5): row i holds
     // wavefront w's lane group g at 4w + g, so a row reads them as float4s
     float red_f[16][RF<KP>], red_fp[16][RF<KP>];
@@ -489,14 +534,22 @@ struct XStepShared {
     int s_rej[NWX_OF<KP>];
 };
 
-// S6 of one panel, with the next panel's loads issued first.  z comes from
+template <int KP, int TPW, int PREC, int BUF>
+__device__ __forceinline__ PanelBuf<KP, TPW, NWX_OF<KP>> &panel_buf(XStepShared<KP, TPW, PREC> &sh,
+                                                                   PanelBuf<KP, TPW, NWX_OF<KP>> *pb0,
+                                                                   PanelBuf<KP, TPW, NWX_OF<KP>> *pb1)
+{
+    if constexpr (STAGE_IN_S5<PREC>) return BUF == 0 ? *pb0 : *pb1;
+    else return BUF == 0 ? sh.buf0 : sh.buf1;
+}
+
+// S6 of one panel.  z comes from
 // X . Y^T, so each lane holds rows 4g + r of column li: the loss derivatives
 // are then already the transposed operand of dY += G^T . X, and the column
 // objective of column li is a sum over the lane's four rows (the four lane
 // groups are added once, at the end of the launch).  The LDS operands come in
 // as restrict pointers so that the compiler can tell the direct-to-LDS loads
-// into the other buffer apart from the reads here and need not wait for them
-// (it drains them at every barrier anyway, and S6 has none).
+// into the other buffer apart from the reads here and need not wait for them.
 template <int KP, int TPW, int PREC, int LK>
 __device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ nxt,
                                          int64_t p_next, const float4 *__restrict__ apan,
@@ -508,8 +561,10 @@ __device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, N
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     const int nt = (int)(a.ldp / 16);
-    if (p_next >= 0)
-        stage_panel<KP, TPW, NWX_OF<KP>>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
+    // (FP32) the next panel's loads, all at once: no product is in flight yet
+    if constexpr (!STAGE_IN_S5<PREC>)
+        if (p_next >= 0)
+            stage_panel<KP, TPW, NWX_OF<KP>>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
     // software pipelined: tile s + 1's entries and product are issued before
     // tile s's losses (slots past the last tile compute on stale entries and
     // are skipped), and each tile's work sits behind a uniform branch, since
@@ -536,11 +591,15 @@ __device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, N
 
 // One 16-row panel of the fused X half-step.  Five workgroup barriers: the
 // staged panel, the row-gradient partials, the trial rows, the trial
-// objective partials and the accepted rows.  The row steps (S4) and the
+// objective partials and the accepted rows.  The next panel's loads go out
+// right after the first, and the other four order LDS traffic only, so the
+// prefetch streams in behind all five phases.  The row steps (S4) and the
 // decisions run on the first 256 threads, sixteen lanes per row, so their row
 // sums are DPP row reductions.
 template <int KP, int TPW, int PREC, int LK, int BUF>
-__device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, TPW, PREC> &sh, int64_t p,
+__device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, TPW, PREC> &__restrict__ sh,
+                                            PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ pb0,
+                                            PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ pb1, int64_t p,
                                             int64_t p_next, const Frag<KP, PREC> (&yfr)[TPW],
                                             const YtFrag<KP, PREC> (&ytf)[TPW], f32x4 (&dyacc)[TPW][KP / 16],
                                             float (&hacc)[TPW], float &rowreg_acc, int &rej_acc)
@@ -550,8 +609,8 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     constexpr int C = KP / 4;
     const int nt = (int)(a.ldp / 16);
     const int k = a.k;
-    PanelBuf<KP, TPW, NWX_OF<KP>> &cur = BUF == 0 ? sh.buf0 : sh.buf1;
-    PanelBuf<KP, TPW, NWX_OF<KP>> &nxt = BUF == 0 ? sh.buf1 : sh.buf0;
+    PanelBuf<KP, TPW, NWX_OF<KP>> &cur = panel_buf<KP, TPW, PREC, BUF>(sh, pb0, pb1);
+    PanelBuf<KP, TPW, NWX_OF<KP>> &nxt = panel_buf<KP, TPW, PREC, 1 - BUF>(sh, pb0, pb1);
     const float4 *apan = cur.apan[w];
     const int64_t i0 = p * 16;
     const int rows = (int)min<int64_t>(16, a.m - i0);
@@ -598,13 +657,16 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     sh.red_f[li][4 * w + g] = fpart;
 #pragma unroll
     for (int kb = 0; kb < KP / 16; ++kb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sh.u.red_g[w][4 * g + r][16 * kb + li] = dx[kb][r];
-    __syncthreads();
+        *reinterpret_cast<f32x4 *>(&sh.red_g[w][16 * kb + li][4 * g]) = dx[kb];
+    panel_barrier<PREC>();
 
     // ---- S4: prox step and regularizer values ------------------------------------
-    // every LDS read first (unconditional: the indexes stay inside the arrays),
-    // one wait, then the arithmetic
+    // (bf16 forms) the next panel's X rows and step sizes go out first; no
+    // matrix-core product is in flight here.  Then every LDS read
+    // (unconditional: the indexes stay inside the arrays), one wait, then the
+    // arithmetic.
+    if constexpr (STAGE_IN_S5<PREC>)
+        if (p_next >= 0) stage_rows<KP, TPW, NWX_OF<KP>>(nxt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
     if (threadIdx.x < 256) {
         constexpr int Q = KP / 16;
         const float al0 = cur.alpha[ri];
@@ -615,7 +677,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             xq[q] = cur.xrow[ri * k + c];
             float gs = 0.0f;
 #pragma unroll
-            for (int v = 0; v < NWX_OF<KP>; ++v) gs += sh.u.red_g[v][ri][c];
+            for (int v = 0; v < NWX_OF<KP>; ++v) gs += sh.red_g[v][c][ri];
             gq[q] = gs * GRAD_SCALE<LK>;
         }
         const float al = rv ? al0 : 0.0f;
@@ -637,12 +699,18 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             sh.s_rxp[ri] = rcp;
         }
     }
-    __syncthreads();
+    panel_barrier<PREC>();
 
     // ---- S5: row objective at the trial rows ---------------------------------------
     Frag<KP, PREC> xpf;
     frag_from_f32<KP, PREC>(xpf, &sh.xp[li][g * C]);
     float fppart = 0.0f;
+    // (bf16 forms) the next panel's tiles are issued one per step of this
+    // loop.  The issue is unconditional (without a next panel it reloads this
+    // panel into the idle buffer): a branch between a matrix-core product and
+    // the read of its result lets the taken path skip the wait states the
+    // read needs.
+    const int64_t p_src = p_next >= 0 ? p_next : p;
     f32x4 zn2 = zprod<KP, PREC>(yfr[0], xpf);
     float4 an2 = apan[lane];
 #pragma unroll
@@ -650,6 +718,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         const int t = w + NWX_OF<KP> * s;
         const f32x4 zp = zn2;
         const float4 av = an2;
+        if constexpr (STAGE_IN_S5<PREC>) stage_tile<KP, TPW, NWX_OF<KP>>(nxt, a.Ap, a.ldp, nt, p_src, w, lane, s);
         if (s + 1 < TPW) {
             zn2 = zprod<KP, PREC>(yfr[s + 1], xpf);
             an2 = apan[(s + 1) * 64 + lane];
@@ -660,7 +729,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         fppart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
     }
     sh.red_fp[li][4 * w + g] = fppart;
-    __syncthreads();
+    panel_barrier<PREC>();
 
     // ---- decision per row and the accepted rows ---------------------------------------
     if (threadIdx.x < 256) {
@@ -693,7 +762,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             const int c = c0 + 16 * q;
             const bool ok = rv && c < k;
             const float xa = acc ? xpq[q] : (ok ? xq[q] : 0.0f);
-            sh.u.d.xat[c * GS + ri] = xa;
+            sh.xat[c * GS + ri] = xa;
             sh.xs[ri][c] = xa;
             if (acc && c < k) a.X[(i0 + ri) * k + c] = xa;
         }
@@ -703,22 +772,33 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             rej_acc += acc ? 0 : 1;
         }
     }
-    __syncthreads();
+    panel_barrier<PREC>();
 
     // ---- S6: column objective and Y gradient from the accepted rows -------------------
     XatFrag<KP, PREC> xa;
-    xatfrag_load<KP, PREC>(xa, sh.u.d.xat, li, g);
+    xatfrag_load<KP, PREC>(xa, sh.xat, li, g);
     Frag<KP, PREC> xaf;
     frag_from_f32<KP, PREC>(xaf, &sh.xs[li][g * C]);
     xstep_s6<KP, TPW, PREC, LK>(a, &nxt, p_next, apan, &sh.lt, sh.s_codes, sh.s_tcode, yfr, xa, xaf, dyacc, hacc);
 }
 
+// Waves per SIMD the row pass is compiled for.  Narrow tables (few tiles per
+// wavefront) run three workgroups per CU, which needs each wavefront within a
+// third of the register file; the rest run one.
+template <int KP, int TPW>
+constexpr int XSTEP_MIN_WAVES = ((KP == 16 && TPW <= 4) || (KP == 32 && TPW <= 2)) ? 3 : 1;
+
 template <int KP, int TPW, int PREC, int LK>
-__global__ __launch_bounds__(NTX_OF<KP>, 1) void xstep_kernel(XStepArgs a)
+__global__ __launch_bounds__(NTX_OF<KP>, (XSTEP_MIN_WAVES<KP, TPW>)) void xstep_kernel(XStepArgs a)
 {
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     __shared__ XStepShared<KP, TPW, PREC> sh;
+    // the bf16 forms' panel buffers (unused, and so not allocated, in FP32)
+    __shared__ PanelBuf<KP, TPW, NWX_OF<KP>> sbuf0;
+    __shared__ PanelBuf<KP, TPW, NWX_OF<KP>> sbuf1;
+    PanelBuf<KP, TPW, NWX_OF<KP>> *pb0 = nullptr, *pb1 = nullptr;
+    if constexpr (STAGE_IN_S5<PREC>) { pb0 = &sbuf0; pb1 = &sbuf1; }
     const int nt = (int)(a.ldp / 16);
     const int64_t npanels = a.mp / 16;
     const int64_t G = gridDim.x;
@@ -748,14 +828,15 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void xstep_kernel(XStepArgs a)
     int rej_acc = 0;
 
     if (blockIdx.x < npanels)
-        stage_panel<KP, TPW, NWX_OF<KP>>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, blockIdx.x, w, lane);
+        stage_panel<KP, TPW, NWX_OF<KP>>(panel_buf<KP, TPW, PREC, 0>(sh, pb0, pb1), a.Ap, a.ldp, nt, a.X, a.m, a.k,
+                                         a.alpha, blockIdx.x, w, lane);
     for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
         const int64_t p1 = p + G, p2 = p + 2 * G;
-        xstep_panel<KP, TPW, PREC, LK, 0>(a, sh, p, p1 < npanels ? p1 : -1, yfr, ytf, dyacc, hacc, rowreg_acc,
-                                          rej_acc);
+        xstep_panel<KP, TPW, PREC, LK, 0>(a, sh, pb0, pb1, p, p1 < npanels ? p1 : -1, yfr, ytf, dyacc, hacc,
+                                          rowreg_acc, rej_acc);
         if (p1 < npanels)
-            xstep_panel<KP, TPW, PREC, LK, 1>(a, sh, p1, p2 < npanels ? p2 : -1, yfr, ytf, dyacc, hacc, rowreg_acc,
-                                              rej_acc);
+            xstep_panel<KP, TPW, PREC, LK, 1>(a, sh, pb0, pb1, p1, p2 < npanels ? p2 : -1, yfr, ytf, dyacc, hacc,
+                                              rowreg_acc, rej_acc);
     }
     __syncthreads();
 

@@ -82,7 +82,7 @@ __device__ __forceinline__ float log1p_unit(float e)
     return 2.0f * s * p;
 }
 
-// Loss value and derivative in u, float, for a loss kind known at compile time.// Loss value and derivative in u, float, for a loss kind known at compile time.
+// Loss value and derivative in u, float, for a loss kind known at compile time.
 template <int K>
 __device__ __forceinline__ void loss_lg_k(int levels, float param, float u, float a, float &l, float &g)
 {
@@ -243,6 +243,21 @@ __device__ __forceinline__ i16x4 pack_bf16x4(float a, float b, float c, float d)
     const bf16x2 p1 = __builtin_convertvector((f32x2){c, d}, bf16x2);
     const uint2 u = {__builtin_bit_cast(uint32_t, p0), __builtin_bit_cast(uint32_t, p1)};
     return __builtin_bit_cast(i16x4, u);
+}
+
+// ---- workgroup barrier for LDS traffic ---------------------------------------
+
+// Barrier that orders LDS accesses only: this wavefront's LDS operations
+// complete (lgkmcnt), then s_barrier.  Outstanding global loads, including
+// direct-to-LDS loads into a buffer that nobody reads before the next full
+// barrier, stay in flight; __syncthreads() would drain them.  The signal
+// fences keep the compiler from moving memory accesses across the barrier.
+__device__ __forceinline__ void lds_barrier()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); vmcnt and expcnt not waited on
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // ---- wavefront reductions ----------------------------------------------------
