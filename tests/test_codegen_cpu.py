@@ -1,0 +1,124 @@
+"""The gfx950 code the library is built from, checked without a GPU.
+
+Every dense kernel instance is compiled to assembly with the library's own
+flags; no taken branch may leave a matrix-core result (or operand) short of
+the wait states the compiler uses on straight-line code, and the bf16 forms
+must not spill registers to scratch.  The checker itself is pinned on small
+hand-written snippets.
+"""
+import concurrent.futures as cf
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+import asm_hazards
+from paper_1410_0342_amd import build as B
+
+HIPCC = B.HIPCC if os.path.exists(B.HIPCC) else shutil.which("hipcc")
+
+
+def test_checker_flags_a_result_read_right_after_a_taken_branch():
+    text = """
+    v_mfma_f32_16x16x4_f32 a[4:7], v6, v58, 0
+    s_cbranch_vccnz .L1
+    v_mov_b32_e32 v1, v2
+.L1:
+    v_accvgpr_read_b32 v61, a7
+    """
+    found, _ = asm_hazards.check(text, {"v_mfma_f32_16x16x4_f32": 10})
+    assert len(found) == 1 and found[0][4] == 1
+
+
+def test_checker_accepts_enough_wait_states_and_unrelated_reads():
+    ok = """
+    v_mfma_f32_16x16x4_f32 a[4:7], v6, v58, 0
+    s_cbranch_vccnz .L1
+    v_mov_b32_e32 v1, v2
+.L1:
+    s_nop 8
+    v_accvgpr_read_b32 v61, a7
+    v_accvgpr_read_b32 v60, a9
+    """
+    found, _ = asm_hazards.check(ok, {"v_mfma_f32_16x16x4_f32": 10})
+    assert found == []
+    other = """
+    v_mfma_f32_16x16x4_f32 a[4:7], v6, v58, 0
+    s_cbranch_vccnz .L1
+.L1:
+    v_accvgpr_read_b32 v60, a9
+    """
+    assert asm_hazards.check(other, {"v_mfma_f32_16x16x4_f32": 10})[0] == []
+
+
+def test_checker_learns_the_straight_line_requirement():
+    text = """
+    v_mfma_f32_16x16x32_bf16 a[0:3], v[2:5], v[6:9], 0
+    s_nop 7
+    v_accvgpr_read_b32 v10, a3
+    v_mfma_f32_16x16x32_bf16 a[0:3], v[2:5], v[6:9], 0
+    s_cbranch_scc1 .L2
+.L2:
+    s_nop 5
+    v_accvgpr_read_b32 v11, a0
+    """
+    found, need = asm_hazards.check(text)
+    assert need["v_mfma_f32_16x16x32_bf16"] == 8
+    assert len(found) == 1 and found[0][4] == 7
+
+
+def test_checker_flags_a_vector_write_feeding_a_product_across_a_branch():
+    text = """
+    v_cvt_pk_bf16_f32 v20, v1, v2
+    s_cbranch_execz .L3
+.L3:
+    v_mfma_f32_16x16x16_bf16 a[0:3], v[20:21], v[22:23], a[0:3]
+    """
+    assert len(asm_hazards.check(text)[0]) == 1
+
+
+def _asm(prec, tmp):
+    out = os.path.join(tmp, "dense_prec%d.s" % prec)
+    cmd = [HIPCC] + B.FLAGS + ["-DGLRM_PREC=%d" % prec, "-x", "hip", "--cuda-device-only", "-S",
+                               os.path.join(B.CSRC, "dense_prec.hip"), "-o", out,
+                               "-Rpass-analysis=kernel-resource-usage"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    return prec, open(out).read(), r.stderr
+
+
+@pytest.fixture(scope="module")
+def dense_asm(tmp_path_factory):
+    if not HIPCC:
+        pytest.skip("hipcc not available")
+    tmp = str(tmp_path_factory.mktemp("asm"))
+    with cf.ThreadPoolExecutor(max_workers=3) as ex:
+        return {p: (text, remarks) for p, text, remarks in ex.map(lambda p: _asm(p, tmp), (0, 1, 3))}
+
+
+@pytest.mark.parametrize("prec", [0, 1, 3])
+def test_no_short_wait_paths_in_the_dense_kernels(dense_asm, prec):
+    found, need = asm_hazards.check(dense_asm[prec][0])
+    assert need, "no straight-line product/read pair found: the checker saw no kernels"
+    assert found == [], found[:5]
+
+
+def _scratch(remarks):
+    out, name = {}, None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name:
+            out[name] = int(m.group(1))
+    return out
+
+
+@pytest.mark.parametrize("prec", [1, 3])
+def test_bf16_forms_do_not_spill(dense_asm, prec):
+    sc = _scratch(dense_asm[prec][1])
+    assert len(sc) > 50
+    assert {k: v for k, v in sc.items() if v} == {}
