@@ -893,6 +893,16 @@ __global__ __launch_bounds__(64 * YPROX_SPLIT) void yprox_kernel(YProxArgs a)
     const int64_t j = t / KP;
     const int c = (int)(t % KP);
     const bool valid = j < a.n;
+    // the first wavefront's own inputs go out first, so that their latency
+    // overlaps the partial loads: y, the step size, and its share of the
+    // column-objective partials (the KP lanes of a column split them; summed
+    // in a fixed order, then a butterfly identical in every lane)
+    float y = 0.0f, al = 0.0f, h = 0.0f;
+    if (ps == 0 && valid) {
+        if (c < a.k) y = a.Y[j * a.k + c];
+        al = a.alpha[j];
+        for (int p = c; p < a.P; p += KP) h += a.part_h[(int64_t)p * a.ldp + j];
+    }
     // fixed-order reduction of this wavefront's partials, eight running sums
     float gsum = 0.0f;
     if (valid) {
@@ -911,8 +921,6 @@ __global__ __launch_bounds__(64 * YPROX_SPLIT) void yprox_kernel(YProxArgs a)
     __syncthreads();
     if (ps != 0) return;
     gsum = (s_part[0][el] + s_part[1][el]) + (s_part[2][el] + s_part[3][el]);
-    const float y = (valid && c < a.k) ? a.Y[j * a.k + c] : 0.0f;
-    const float al = valid ? a.alpha[j] : 0.0f;
     const float yv = (valid && c < a.k) ? prox_elem(a.ry, al, y - al * gsum) : 0.0f;
     if (valid) {
         if (c < a.k) a.Yplus[j * a.k + c] = yv;
@@ -929,11 +937,6 @@ __global__ __launch_bounds__(64 * YPROX_SPLIT) void yprox_kernel(YProxArgs a)
     float rcp = (valid && c < a.k) ? reg_elem(a.ry, yv) : 0.0f;
     rc = sum_lanes<KP>(rc);
     rcp = sum_lanes<KP>(rcp);
-    // column objective: the KP lanes of the column split the partials, then a
-    // butterfly (identical in every lane) combines them
-    float h = 0.0f;
-    if (valid)
-        for (int p = c; p < a.P; p += KP) h += a.part_h[(int64_t)p * a.ldp + j];
     h = sum_lanes<KP>(h);
     if (valid && c == 0) {
         a.h_old[j] = h + rc;
@@ -1058,30 +1061,38 @@ __global__ __launch_bounds__(256) void yaccept_kernel(YAcceptArgs a)
     int acc = 0;
     double Fj = 0.0;
     int rj = 0;
-    float hp = 0.0f;
-    if (valid)
+    // every input goes out before the decision needs it: one round of loads
+    float hp = 0.0f, ryp = 0.0f, h = 0.0f, al = 0.0f, yv = 0.0f;
+    __bf16 yhi = to_bf16(0.0f), ylo = to_bf16(0.0f);
+    if (valid) {
+        ryp = a.ry_plus[j];
+        h = a.h_old[j];
+        if (c == 0) al = a.alpha[j];
+        if (c < a.k) yv = a.Yplus[j * a.k + c];
+        if constexpr (PREC != P_FP32) {
+            yhi = a.yplus.hi[j * KP + c];
+            if constexpr (PREC == P_BF16) ylo = a.yplus.lo[j * KP + c];
+        }
         for (int p = c; p < a.P; p += KP) hp += a.part_hp[(int64_t)p * a.ldp + j];
+    }
     hp = sum_lanes<KP>(hp);   // the same value in every lane of the column
     if (valid) {
-        hp += a.ry_plus[j];
-        const float h = a.h_old[j];
+        hp += ryp;
         acc = hp <= h ? 1 : 0;
         if (c == 0) {
-            const float al = a.alpha[j];
             a.alpha[j] = acc ? al * a.step_up : al * a.step_down;
             Fj = acc ? (double)hp : (double)h;
             rj = acc ? 0 : 1;
         }
         if (acc) {
-            const float yv = c < a.k ? a.Yplus[j * a.k + c] : 0.0f;
             if (c < a.k) a.Y[j * a.k + c] = yv;
             if constexpr (PREC == P_FP32) {
                 a.ycur.f32[j * KP + c] = yv;
                 a.ycur.t32[(int64_t)c * a.ldp + j] = yv;
             } else {
-                a.ycur.hi[j * KP + c] = a.yplus.hi[j * KP + c];
-                if constexpr (PREC == P_BF16) a.ycur.lo[j * KP + c] = a.yplus.lo[j * KP + c];
-                a.ycur.tb[(int64_t)c * a.ldp + j] = a.yplus.hi[j * KP + c];
+                a.ycur.hi[j * KP + c] = yhi;
+                if constexpr (PREC == P_BF16) a.ycur.lo[j * KP + c] = ylo;
+                a.ycur.tb[(int64_t)c * a.ldp + j] = yhi;
             }
         }
     }
