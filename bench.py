@@ -15,6 +15,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,11 +30,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+def _code_only(text):
+    """Source text without comments, trailing blanks and empty lines: what the
+    compiler sees, so comment edits do not invalidate stored counters."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
+
+
+def kernel_source_hash(read=None):
+    """Hash of the code of the dense kernels' sources (comments ignored)."""
     h = hashlib.sha256()
     for f in ("dense_kernels.h", "dense_prec.hip", "glrm_device.h", "glrm_kernels.h"):
-        with open(os.path.join(ROOT, "paper_1410_0342_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        rel = "paper_1410_0342_amd/csrc/" + f
+        if read is None:
+            with open(os.path.join(ROOT, rel)) as fh:
+                text = fh.read()
+        else:
+            text = read(rel)
+        h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
 
 

@@ -162,9 +162,11 @@ constexpr int NTY_OF = 64 * NWY_OF<KP>;
 // panel staging: the next 16-row panel's table tiles, X rows and step sizes
 // travel straight from HBM into an LDS buffer while the current panel
 // computes (global_load_lds: lane l's 16 or 4 bytes land at base + l * size).
-// The two buffers are separate LDS objects and each panel body reads one of
-// them by name, so the compiler never has to wait for the prefetch into the
-// other one before an LDS read.
+// A panel reads only the buffer it computes on.  After a direct-to-LDS load
+// the compiler waits for it before any LDS access it cannot prove unrelated,
+// so the passes either read their tiles before issuing the prefetch
+// (trial-column pass) or hand the buffers over as restrict pointers (row
+// pass).
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void lds_void_t;
 typedef __attribute__((address_space(1))) void glb_void_t;
@@ -547,9 +549,9 @@ __device__ __forceinline__ PanelBuf<KP, TPW, NWX_OF<KP>> &panel_buf(XStepShared<
 // X . Y^T, so each lane holds rows 4g + r of column li: the loss derivatives
 // are then already the transposed operand of dY += G^T . X, and the column
 // objective of column li is a sum over the lane's four rows (the four lane
-// groups are added once, at the end of the launch).  The LDS operands come in
-// as restrict pointers so that the compiler can tell the direct-to-LDS loads
-// into the other buffer apart from the reads here and need not wait for them.
+// groups are added once, at the end of the launch).  The FP32 form issues the
+// next panel's loads here; the LDS operands come in as restrict pointers so
+// that the compiler can tell those loads apart from the reads below.
 template <int KP, int TPW, int PREC, int LK>
 __device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ nxt,
                                          int64_t p_next, const float4 *__restrict__ apan,
