@@ -49,9 +49,9 @@ def straight_line_needs(ins):
     its result (s_nop N then the read), per product opcode: the largest seen."""
     need = {}
     for a, b, c in zip(ins, ins[1:], ins[2:]):
-        if a.startswith('v_mfma') and b.startswith('s_nop') and c.startswith('v_accvgpr_read'):
+        if a.startswith('v_mfma') and b.startswith('s_nop') and c.startswith('v_') and not c.startswith('v_mfma'):
             dst = _regs(a.split()[1])
-            if _regs(c.split()[-1]) & dst:
+            if any(_regs(x) & dst for x in c.split()[2:]):
                 op = a.split()[0]
                 need[op] = max(need.get(op, 0), _waits(b))
     return need
@@ -79,11 +79,16 @@ def short_branch_paths(ins, labels, need, valu_need=2, window=30):
                 for c in range(j0, min(len(ins), j0 + window)):
                     u = ins[c]
                     ops = u.split()[1:]
-                    srcs = ops if u.startswith(('ds_write', 'global_store', 'buffer_store')) else ops[1:]
+                    stores = u.startswith(('ds_write', 'global_store', 'buffer_store'))
+                    srcs = ops if stores else ops[1:]
                     if not u.startswith('v_mfma') and any(_regs(x) & dst for x in srcs):
                         if w < need.get(op, 11):
                             found.append((i, tgt, t, u, w))
                         break
+                    if ops and not stores and u.startswith('v_'):
+                        dst = dst - _regs(ops[0])   # overwritten before any read
+                        if not dst:
+                            break
                     w += _waits(u)
                     if w >= 32 or u.startswith(('s_cbranch', 's_branch', 's_endpgm')):
                         break

@@ -81,7 +81,7 @@ def test_checker_flags_a_vector_write_feeding_a_product_across_a_branch():
 
 def _asm(prec, tmp):
     out = os.path.join(tmp, "dense_prec%d.s" % prec)
-    cmd = [HIPCC] + B.FLAGS + ["-DGLRM_PREC=%d" % prec, "-x", "hip", "--cuda-device-only", "-S",
+    cmd = [HIPCC] + B.FLAGS + B.dense_prec_flags(prec) + ["-x", "hip", "--cuda-device-only", "-S",
                                os.path.join(B.CSRC, "dense_prec.hip"), "-o", out,
                                "-Rpass-analysis=kernel-resource-usage"]
     r = subprocess.run(cmd, capture_output=True, text=True)
