@@ -18,15 +18,23 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-I" + os.path.join(ROOT, "include")]
 
 
-def dense_prec_flags(prec):
-    """Extra flags of the dense instances of one precision.  FP32 keeps
+def dense_prec_flags(prec, lks):
+    """Flags of the dense instances of one precision and loss set (0: the
+    quadratic loss everywhere, 1: a per-column loss table).  FP32 keeps
     matrix-core results and accumulators in VGPRs where they fit: fewer
-    AGPR<->VGPR copies, and its row pass runs 4 % faster; the bf16 forms run
-    slower that way and keep the default."""
-    return ["-DGLRM_PREC=%d" % prec] + (["-mllvm", "-amdgpu-mfma-vgpr-form"] if prec == 0 else [])
+    AGPR<->VGPR copies, and its row pass runs 4 % faster (the bf16 forms run
+    slower that way).  The bf16 forms' quadratic instances use the iterative
+    ILP scheduler: their row pass runs 1.7 % faster, while the loss-table
+    instances run slower with it."""
+    extra = []
+    if prec == 0:
+        extra = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+    elif lks == 0:
+        extra = ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]
+    return ["-DGLRM_PREC=%d" % prec, "-DGLRM_LKS=%d" % lks] + extra
 
 
-SOURCES += [("dense_prec.hip", dense_prec_flags(p), "dense_prec%d" % p) for p in (0, 1, 3)]
+SOURCES += [("dense_prec.hip", dense_prec_flags(p, l), "dense_prec%d_%d" % (p, l)) for p in (0, 1, 3) for l in (0, 1)]
 
 
 def _compile(item):

@@ -94,14 +94,14 @@ __global__ __launch_bounds__(256) void objective64_kernel(Obj64Args a)
 // ---------------------------------------------------------------------------
 // dispatch by precision (instances live in dense_prec.hip)
 // ---------------------------------------------------------------------------
-template <int PREC> hipError_t launch_xstep_p(const XStepArgs &, int, int, int, hipStream_t);
-template <int PREC> hipError_t launch_ycheck_p(const YCheckArgs &, int, int, int, hipStream_t);
-template <int PREC> int xstep_blocks_p(int, int, bool);
-template <int PREC> int ycheck_blocks_p(int, int, bool);
+template <int PREC, int LKS> hipError_t launch_xstep_p(const XStepArgs &, int, int, int, hipStream_t);
+template <int PREC, int LKS> hipError_t launch_ycheck_p(const YCheckArgs &, int, int, int, hipStream_t);
+template <int PREC, int LKS> int xstep_blocks_p(int, int);
+template <int PREC, int LKS> int ycheck_blocks_p(int, int);
 template <int PREC> hipError_t launch_yprox_p(const YProxArgs &, int, hipStream_t);
 template <int PREC> hipError_t launch_yaccept_p(const YAcceptArgs &, int, int, hipStream_t);
 template <int PREC> hipError_t launch_yshadow_p(const YShadowArgs &, int, hipStream_t);
-template <int PREC> hipError_t launch_lossgrad_p(const LossGradArgs &, int, int, bool, int, int, hipStream_t);
+template <int PREC, int LKS> hipError_t launch_lossgrad_p(const LossGradArgs &, int, int, bool, int, int, hipStream_t);
 
 #define GLRM_BY_PREC(PV, CALL)                                      \
     switch (PV) {                                                   \
@@ -111,16 +111,21 @@ template <int PREC> hipError_t launch_lossgrad_p(const LossGradArgs &, int, int,
     default: return hipErrorInvalidValue;                           \
     }
 
+// loss set: 0 = the quadratic loss everywhere, 1 = a per-column loss table
+static int loss_set(const LossU &lu) { return lu.kind == L_QUAD ? 0 : 1; }
+
 hipError_t launch_xstep(const XStepArgs &a, int kp, int tpw, int prec, int grid, hipStream_t st)
 {
-#define C_(P) launch_xstep_p<P>(a, kp, tpw, grid, st)
+    const int lks = loss_set(a.lu);
+#define C_(P) (lks == 0 ? launch_xstep_p<P, 0>(a, kp, tpw, grid, st) : launch_xstep_p<P, 1>(a, kp, tpw, grid, st))
     GLRM_BY_PREC(prec, C_)
 #undef C_
 }
 
 hipError_t launch_ycheck(const YCheckArgs &a, int kp, int tpw, int prec, int grid, hipStream_t st)
 {
-#define C_(P) launch_ycheck_p<P>(a, kp, tpw, grid, st)
+    const int lks = loss_set(a.lu);
+#define C_(P) (lks == 0 ? launch_ycheck_p<P, 0>(a, kp, tpw, grid, st) : launch_ycheck_p<P, 1>(a, kp, tpw, grid, st))
     GLRM_BY_PREC(prec, C_)
 #undef C_
 }
@@ -158,7 +163,9 @@ hipError_t launch_yshadow(const YShadowArgs &a, int kp, int prec, hipStream_t st
 hipError_t launch_lossgrad(const LossGradArgs &a, int kp, int tpw, int prec, bool want_grad, int gx, int gy,
                            hipStream_t st)
 {
-#define C_(P) launch_lossgrad_p<P>(a, kp, tpw, want_grad, gx, gy, st)
+    const int lks = loss_set(a.lu);
+#define C_(P) (lks == 0 ? launch_lossgrad_p<P, 0>(a, kp, tpw, want_grad, gx, gy, st) \
+                        : launch_lossgrad_p<P, 1>(a, kp, tpw, want_grad, gx, gy, st))
     GLRM_BY_PREC(prec, C_)
 #undef C_
 }
@@ -196,9 +203,10 @@ hipError_t launch_objective64(const Obj64Args &a, int grid, hipStream_t st)
 int xstep_blocks(int kp, int tpw, int prec, bool quad)
 {
     switch (prec) {
-    case P_FP32: return xstep_blocks_p<P_FP32>(kp, tpw, quad);
-    case P_BF16: return xstep_blocks_p<P_BF16>(kp, tpw, quad);
-    case P_BF16_PLAIN: return xstep_blocks_p<P_BF16_PLAIN>(kp, tpw, quad);
+    case P_FP32: return quad ? xstep_blocks_p<P_FP32, 0>(kp, tpw) : xstep_blocks_p<P_FP32, 1>(kp, tpw);
+    case P_BF16: return quad ? xstep_blocks_p<P_BF16, 0>(kp, tpw) : xstep_blocks_p<P_BF16, 1>(kp, tpw);
+    case P_BF16_PLAIN:
+        return quad ? xstep_blocks_p<P_BF16_PLAIN, 0>(kp, tpw) : xstep_blocks_p<P_BF16_PLAIN, 1>(kp, tpw);
     default: return 1;
     }
 }
@@ -206,9 +214,10 @@ int xstep_blocks(int kp, int tpw, int prec, bool quad)
 int ycheck_blocks(int kp, int tpw, int prec, bool quad)
 {
     switch (prec) {
-    case P_FP32: return ycheck_blocks_p<P_FP32>(kp, tpw, quad);
-    case P_BF16: return ycheck_blocks_p<P_BF16>(kp, tpw, quad);
-    case P_BF16_PLAIN: return ycheck_blocks_p<P_BF16_PLAIN>(kp, tpw, quad);
+    case P_FP32: return quad ? ycheck_blocks_p<P_FP32, 0>(kp, tpw) : ycheck_blocks_p<P_FP32, 1>(kp, tpw);
+    case P_BF16: return quad ? ycheck_blocks_p<P_BF16, 0>(kp, tpw) : ycheck_blocks_p<P_BF16, 1>(kp, tpw);
+    case P_BF16_PLAIN:
+        return quad ? ycheck_blocks_p<P_BF16_PLAIN, 0>(kp, tpw) : ycheck_blocks_p<P_BF16_PLAIN, 1>(kp, tpw);
     default: return 1;
     }
 }

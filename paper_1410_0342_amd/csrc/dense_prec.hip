@@ -1,12 +1,18 @@
 // Precision-dependent launchers of the dense kernels.  This file is compiled
-// once per contraction precision with -DGLRM_PREC=<0|1|3> (FP32, split BF16,
-// plain BF16), so the three sets of kernel instances build in parallel.
+// once per contraction precision (-DGLRM_PREC=<0|1|3>: FP32, split BF16, plain
+// BF16) and loss set (-DGLRM_LKS=<0|1>: the quadratic loss everywhere, or a
+// per-column loss table), so the instances build in parallel and each set can
+// get its own code-generation flags.  The launchers that do not depend on the
+// loss are built with the loss-table set.
 #include <type_traits>
 
 #include "dense_kernels.h"
 
 #ifndef GLRM_PREC
 #error "compile with -DGLRM_PREC=0, 1 or 3"
+#endif
+#ifndef GLRM_LKS
+#error "compile with -DGLRM_LKS=0 (quadratic) or 1 (loss table)"
 #endif
 
 namespace glrm {
@@ -45,21 +51,22 @@ namespace glrm {
     default: return hipErrorInvalidValue;                              \
     }
 
-// Calls f(KP, TPW, LK) as integral constants for the runtime values (TPW up to 16).
+// The loss instance of a loss set: the quadratic loss (every column) gets its
+// own instances; a loss table goes through the per-tile loss selection.
+template <int LKS>
+constexpr int LK_OF = LKS == 0 ? L_QUAD : -1;
+
+// Calls f(KP, TPW) as integral constants for the runtime values (TPW up to 16).
 template <typename F>
-static void for_instance(int kp, int tpw, bool quad, F &&f)
+static void for_instance(int kp, int tpw, F &&f)
 {
-    auto with_lk = [&](auto kpc, auto tpwc) {
-        if (quad) f(kpc, tpwc, std::integral_constant<int, L_QUAD>{});
-        else f(kpc, tpwc, std::integral_constant<int, -1>{});
-    };
     auto with_tpw = [&](auto kpc) {
         switch (tpw) {
-        case 1: with_lk(kpc, std::integral_constant<int, 1>{}); break;
-        case 2: with_lk(kpc, std::integral_constant<int, 2>{}); break;
-        case 4: with_lk(kpc, std::integral_constant<int, 4>{}); break;
-        case 8: with_lk(kpc, std::integral_constant<int, 8>{}); break;
-        case 16: with_lk(kpc, std::integral_constant<int, 16>{}); break;
+        case 1: f(kpc, std::integral_constant<int, 1>{}); break;
+        case 2: f(kpc, std::integral_constant<int, 2>{}); break;
+        case 4: f(kpc, std::integral_constant<int, 4>{}); break;
+        case 8: f(kpc, std::integral_constant<int, 8>{}); break;
+        case 16: f(kpc, std::integral_constant<int, 16>{}); break;
         default: break;
         }
     };
@@ -71,19 +78,13 @@ static void for_instance(int kp, int tpw, bool quad, F &&f)
     }
 }
 
-// The quadratic loss (every column) gets its own instances; everything else
-// goes through the per-tile loss selection.
-#define GLRM_DISPATCH_LK(QUAD_ONLY, ...)                              \
-    if (QUAD_ONLY) { constexpr int LK = L_QUAD; __VA_ARGS__; }        \
-    else { constexpr int LK = -1; __VA_ARGS__; }
-
-template <int PREC>
+template <int PREC, int LKS>
 hipError_t launch_xstep_p(const XStepArgs &a, int kp, int tpw, int grid, hipStream_t st)
 {
-    const bool quad = a.lu.kind == L_QUAD;
-    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW16(tpw, GLRM_DISPATCH_LK(quad,
+    constexpr int LK = LK_OF<LKS>;
+    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW16(tpw,
         if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
-        else hipLaunchKernelGGL((xstep_kernel<KP, TPW, PREC, LK>), dim3(grid), dim3(NTX_OF<KP>), 0, st, a))));
+        else hipLaunchKernelGGL((xstep_kernel<KP, TPW, PREC, LK>), dim3(grid), dim3(NTX_OF<KP>), 0, st, a)));
     return hipGetLastError();
 }
 
@@ -96,36 +97,38 @@ static int blocks_per_cu(K kernel, int threads)
     return nb;
 }
 
-template <int PREC>
-int xstep_blocks_p(int kp, int tpw, bool quad)
+template <int PREC, int LKS>
+int xstep_blocks_p(int kp, int tpw)
 {
+    constexpr int LK = LK_OF<LKS>;
     int nb = 1;
-    auto pick = [&](auto kpc, auto tpwc, auto lkc) {
-        constexpr int KP = decltype(kpc)::value, TPW = decltype(tpwc)::value, LK = decltype(lkc)::value;
+    auto pick = [&](auto kpc, auto tpwc) {
+        constexpr int KP = decltype(kpc)::value, TPW = decltype(tpwc)::value;
         if constexpr (!(KP == 64 && TPW == 16)) nb = blocks_per_cu(xstep_kernel<KP, TPW, PREC, LK>, NTX_OF<KP>);
     };
-    for_instance(kp, tpw, quad, pick);
+    for_instance(kp, tpw, pick);
     return nb;
 }
 
-template <int PREC>
-int ycheck_blocks_p(int kp, int tpw, bool quad)
+template <int PREC, int LKS>
+int ycheck_blocks_p(int kp, int tpw)
 {
+    constexpr int LK = LK_OF<LKS>;
     int nb = 1;
-    auto pick = [&](auto kpc, auto tpwc, auto lkc) {
-        constexpr int KP = decltype(kpc)::value, TPW = decltype(tpwc)::value, LK = decltype(lkc)::value;
+    auto pick = [&](auto kpc, auto tpwc) {
+        constexpr int KP = decltype(kpc)::value, TPW = decltype(tpwc)::value;
         if constexpr (TPW <= 8) nb = blocks_per_cu(ycheck_kernel<KP, TPW, PREC, LK>, NTY_OF<KP>);
     };
-    for_instance(kp, tpw, quad, pick);
+    for_instance(kp, tpw, pick);
     return nb;
 }
 
-template <int PREC>
+template <int PREC, int LKS>
 hipError_t launch_ycheck_p(const YCheckArgs &a, int kp, int tpw, int grid, hipStream_t st)
 {
-    const bool quad = a.lu.kind == L_QUAD;
-    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW(tpw, GLRM_DISPATCH_LK(quad,
-        hipLaunchKernelGGL((ycheck_kernel<KP, TPW, PREC, LK>), dim3(grid), dim3(NTY_OF<KP>), 0, st, a))));
+    constexpr int LK = LK_OF<LKS>;
+    GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW(tpw,
+        hipLaunchKernelGGL((ycheck_kernel<KP, TPW, PREC, LK>), dim3(grid), dim3(NTY_OF<KP>), 0, st, a)));
     return hipGetLastError();
 }
 
@@ -152,31 +155,34 @@ hipError_t launch_yshadow_p(const YShadowArgs &a, int kp, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int PREC>
+template <int PREC, int LKS>
 hipError_t launch_lossgrad_p(const LossGradArgs &a, int kp, int tpw, bool want_grad, int gx, int gy, hipStream_t st)
 {
-    const bool quad = a.lu.kind == L_QUAD;
+    constexpr int LK = LK_OF<LKS>;
     if (want_grad) {
-        GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW16(tpw, GLRM_DISPATCH_LK(quad,
+        GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW16(tpw,
             if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
             else hipLaunchKernelGGL((lossgrad_kernel<KP, TPW, PREC, LK, true>), dim3(gx, gy), dim3(NTX_OF<KP>), 0, st,
-                                    a))));
+                                    a)));
     } else {
-        GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW16(tpw, GLRM_DISPATCH_LK(quad,
+        GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW16(tpw,
             if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
             else hipLaunchKernelGGL((lossgrad_kernel<KP, TPW, PREC, LK, false>), dim3(gx, gy), dim3(NTX_OF<KP>), 0, st,
-                                    a))));
+                                    a)));
     }
     return hipGetLastError();
 }
 
-template hipError_t launch_xstep_p<GLRM_PREC>(const XStepArgs &, int, int, int, hipStream_t);
-template int xstep_blocks_p<GLRM_PREC>(int, int, bool);
-template int ycheck_blocks_p<GLRM_PREC>(int, int, bool);
-template hipError_t launch_ycheck_p<GLRM_PREC>(const YCheckArgs &, int, int, int, hipStream_t);
+template hipError_t launch_xstep_p<GLRM_PREC, GLRM_LKS>(const XStepArgs &, int, int, int, hipStream_t);
+template int xstep_blocks_p<GLRM_PREC, GLRM_LKS>(int, int);
+template int ycheck_blocks_p<GLRM_PREC, GLRM_LKS>(int, int);
+template hipError_t launch_ycheck_p<GLRM_PREC, GLRM_LKS>(const YCheckArgs &, int, int, int, hipStream_t);
+template hipError_t launch_lossgrad_p<GLRM_PREC, GLRM_LKS>(const LossGradArgs &, int, int, bool, int, int,
+                                                           hipStream_t);
+#if GLRM_LKS == 1
 template hipError_t launch_yprox_p<GLRM_PREC>(const YProxArgs &, int, hipStream_t);
 template hipError_t launch_yaccept_p<GLRM_PREC>(const YAcceptArgs &, int, int, hipStream_t);
 template hipError_t launch_yshadow_p<GLRM_PREC>(const YShadowArgs &, int, hipStream_t);
-template hipError_t launch_lossgrad_p<GLRM_PREC>(const LossGradArgs &, int, int, bool, int, int, hipStream_t);
+#endif
 
 }  // namespace glrm

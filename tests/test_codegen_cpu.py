@@ -79,14 +79,18 @@ def test_checker_flags_a_vector_write_feeding_a_product_across_a_branch():
     assert len(asm_hazards.check(text)[0]) == 1
 
 
-def _asm(prec, tmp):
-    out = os.path.join(tmp, "dense_prec%d.s" % prec)
-    cmd = [HIPCC] + B.FLAGS + B.dense_prec_flags(prec) + ["-x", "hip", "--cuda-device-only", "-S",
+UNITS = [(p, l) for p in (0, 1, 3) for l in (0, 1)]
+
+
+def _asm(unit, tmp):
+    prec, lks = unit
+    out = os.path.join(tmp, "dense_prec%d_%d.s" % unit)
+    cmd = [HIPCC] + B.FLAGS + B.dense_prec_flags(prec, lks) + ["-x", "hip", "--cuda-device-only", "-S",
                                os.path.join(B.CSRC, "dense_prec.hip"), "-o", out,
                                "-Rpass-analysis=kernel-resource-usage"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
-    return prec, open(out).read(), r.stderr
+    return unit, open(out).read(), r.stderr
 
 
 @pytest.fixture(scope="module")
@@ -94,14 +98,25 @@ def dense_asm(tmp_path_factory):
     if not HIPCC:
         pytest.skip("hipcc not available")
     tmp = str(tmp_path_factory.mktemp("asm"))
-    with cf.ThreadPoolExecutor(max_workers=3) as ex:
-        return {p: (text, remarks) for p, text, remarks in ex.map(lambda p: _asm(p, tmp), (0, 1, 3))}
+    with cf.ThreadPoolExecutor(max_workers=6) as ex:
+        return {u: (text, remarks) for u, text, remarks in ex.map(lambda u: _asm(u, tmp), UNITS)}
 
 
-@pytest.mark.parametrize("prec", [0, 1, 3])
-def test_no_short_wait_paths_in_the_dense_kernels(dense_asm, prec):
-    found, need = asm_hazards.check(dense_asm[prec][0])
-    assert need, "no straight-line product/read pair found: the checker saw no kernels"
+@pytest.fixture(scope="module")
+def learned_needs(dense_asm):
+    """The compiler's straight-line wait states, learned over every unit (a
+    unit may lack a sample of some product)."""
+    need = {}
+    for text, _ in dense_asm.values():
+        for op, n in asm_hazards.straight_line_needs(asm_hazards.parse(text)[0]).items():
+            need[op] = max(need.get(op, 0), n)
+    return need
+
+
+@pytest.mark.parametrize("unit", UNITS)
+def test_no_short_wait_paths_in_the_dense_kernels(dense_asm, learned_needs, unit):
+    assert len(learned_needs) >= 3, learned_needs
+    found, _ = asm_hazards.check(dense_asm[unit][0], learned_needs)
     assert found == [], found[:5]
 
 
@@ -117,8 +132,8 @@ def _scratch(remarks):
     return out
 
 
-@pytest.mark.parametrize("prec", [1, 3])
-def test_bf16_forms_do_not_spill(dense_asm, prec):
-    sc = _scratch(dense_asm[prec][1])
-    assert len(sc) > 50
+@pytest.mark.parametrize("unit", [u for u in UNITS if u[0] != 0])
+def test_bf16_forms_do_not_spill(dense_asm, unit):
+    sc = _scratch(dense_asm[unit][1])
+    assert len(sc) > 20
     assert {k: v for k, v in sc.items() if v} == {}
