@@ -39,8 +39,12 @@ def _code_only(text):
 
 
 def kernel_source_hash(read=None):
-    """Hash of the code of the dense kernels' sources (comments ignored)."""
+    """Hash of the code of the dense kernels' sources (comments ignored) and of
+    the compiler flags of the benchmark's instances (include paths left out)."""
+    from paper_1410_0342_amd import build as B
     h = hashlib.sha256()
+    flags = [f for f in B.FLAGS + B.dense_prec_flags(1, 0) if not f.startswith("-I")]
+    h.update(" ".join(flags).encode())
     for f in ("dense_kernels.h", "dense_prec.hip", "glrm_device.h", "glrm_kernels.h"):
         rel = "paper_1410_0342_amd/csrc/" + f
         if read is None:
