@@ -73,6 +73,10 @@ def lib():
         L.oracle_reg_sum.argtypes = [I32, D, P, I64, I32]
         L.oracle_objective.restype = D
         L.oracle_objective.argtypes = [P, P, P, I32, D, I32, D]
+        L.oracle_decode.restype = D
+        L.oracle_decode.argtypes = [P, D]
+        L.oracle_decode_matrix.restype = None
+        L.oracle_decode_matrix.argtypes = [P, P, P, I64, I64, P]
         _lib = L
     return _lib
 
@@ -94,6 +98,32 @@ def loss(kind, u, a, levels=0, param=1.0):
 def dloss(kind, u, a, levels=0, param=1.0):
     L = _Loss(kind, levels, param)
     return lib().oracle_dloss(ctypes.byref(L), float(u), float(a))
+
+
+def decode(kind, u, levels=0, param=1.0):
+    """argmin over the loss's data domain of L(u, a) (Section 5.4)."""
+    L = _Loss(kind, levels, param)
+    return lib().oracle_decode(ctypes.byref(L), float(u))
+
+
+def impute(X, Y, col_loss, losses, A=None, mask=None):
+    """The decoded table a_hat_ij = argmin_a L_j(x_i . y_j, a) (Section 5.4).
+
+    X is m x k, Y is n x k; ``col_loss`` gives each column's index into
+    ``losses`` (None = all 0).  With ``mask`` (m x n bool) the observed entries
+    keep their data A_ij and only the missing ones are decoded.  Returns the
+    float64 products Z = X Y^T (the paper's XY) and the decoded table."""
+    X, Y = _f64(X), _f64(Y)
+    m, n = X.shape[0], Y.shape[0]
+    Z = np.ascontiguousarray(X @ Y.T)
+    code = np.zeros(n, np.uint8) if col_loss is None else np.ascontiguousarray(col_loss, dtype=np.uint8)
+    tab = (_Loss * max(1, len(losses)))(*[_Loss(int(a), int(b), float(c)) for a, b, c in losses])
+    out = np.empty((m, n))
+    lib().oracle_decode_matrix(ctypes.byref(tab), _ptr(code), _ptr(Z), m, n, _ptr(out))
+    if mask is not None:
+        mask = np.asarray(mask, dtype=bool)
+        out[mask] = np.asarray(A, dtype=np.float64)[mask]
+    return Z, out
 
 
 def reg(kind, w, x):

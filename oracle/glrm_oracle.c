@@ -249,3 +249,42 @@ double oracle_objective(const oracle_problem_t *P, const double *X, const double
     return oracle_loss_sum(P, X, Y) + oracle_reg_sum(rx_kind, rx_w, X, P->m, P->k)
          + oracle_reg_sum(ry_kind, ry_w, Y, P->n, P->k);
 }
+
+/* ---- imputation (Section 5.4): the entry of the column's data domain whose
+ * loss at u = x_i . y_j is smallest, a_hat = argmin_a L_j(u, a).  The
+ * quadratic and Huber losses are defined for every real a and are smallest at
+ * a = u, which the paper states as the decoded value for them.  The Boolean
+ * losses range over {-1, +1} and the ordinal hinge over {1..levels}: the
+ * argmin is taken by evaluating the loss at every value of the domain in
+ * increasing order and keeping the first smallest one, so a tie goes to the
+ * smaller value. ------------------------------------------------------------- */
+double oracle_decode(const oracle_loss_t *L, double u)
+{
+    switch (L->kind) {
+    case OR_QUAD:
+    case OR_HUBER:
+        return u;
+    case OR_LOGISTIC:
+    case OR_HINGE:
+        return oracle_loss(L, u, 1.0) < oracle_loss(L, u, -1.0) ? 1.0 : -1.0;
+    case OR_ORDINAL: {
+        double best = 1.0, fbest = oracle_loss(L, u, 1.0);
+        for (int lv = 2; lv <= L->levels; ++lv) {
+            double f = oracle_loss(L, u, (double)lv);
+            if (f < fbest) { fbest = f; best = (double)lv; }
+        }
+        return best;
+    }
+    }
+    return NAN;
+}
+
+/* a_hat for every entry of an m x n matrix of products Z (row-major), column j
+ * decoded with losses[col_code[j]]. */
+void oracle_decode_matrix(const oracle_loss_t *losses, const uint8_t *col_code, const double *Z,
+                          int64_t m, int64_t n, double *out)
+{
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j)
+            out[i * n + j] = oracle_decode(&losses[col_code[j]], Z[i * n + j]);
+}

@@ -327,3 +327,66 @@ def test_global_optimality_certificate_after_convergence():
     X, Y, *_ = P.fit(c.X0, c.Y0, 4000)
     assert cert(X, Y) <= 1.0 + 1e-4
     assert cert(c.X0.astype(np.float64), c.Y0.astype(np.float64)) > 1.0 + 1e-2
+
+
+# ---- imputation decode (Section 5.4) ------------------------------------------
+U_GRID = np.concatenate([np.linspace(-9.3, 9.3, 187), [-2.5, -0.5, 0.5, 1.5, 2.5, 3.5, 6.5, 7.5]])
+
+
+@pytest.mark.parametrize("loss", [(0, 0, 0.0), (1, 0, 1.0), (1, 0, 0.25)])
+def test_decode_real_losses_is_the_product(loss):
+    """Section 5.4: for losses over the reals the decoded entry is x_i . y_j.
+    Checked against a scalar minimiser of L(u, .) as well."""
+    kind, levels, param = loss
+    for u in U_GRID:
+        assert oracle.decode(kind, u, levels, param) == u
+    for u in (-3.7, 0.2, 5.1):
+        r = minimize_scalar(lambda a: oracle.loss(kind, u, a, levels, param), bracket=(u - 2, u + 2), tol=1e-12)
+        assert abs(r.x - u) < 1e-5
+
+
+@pytest.mark.parametrize("kind", [2, 3])
+def test_decode_boolean_losses_is_the_sign(kind):
+    """Section 5.4: for logistic and hinge (MMMF) data the decoded entry is
+    sign(x_i . y_j); at u = 0 both values tie and the smaller is taken."""
+    for u in U_GRID[np.abs(U_GRID) > 1e-9]:
+        assert oracle.decode(kind, u) == np.sign(u)
+    for u in (1e-3, -1e-3, 4e-2):
+        assert oracle.decode(kind, u) == np.sign(u)
+    assert oracle.decode(kind, 0.0) == -1.0
+
+
+@pytest.mark.parametrize("levels", [2, 5, 7])
+def test_decode_ordinal_is_the_nearest_level(levels):
+    """eq. ord-pca decoded by Section 5.4.  Going from level a to a+1 changes
+    the loss by (1 + a - u)_+ - (u - a)_+, which is negative exactly when
+    a < u - 1/2 and zero when a = u - 1/2; so the minimiser is the level
+    nearest to u, clamped to 1..levels, with the lower level at a half-way
+    tie: clamp(ceil(u - 1/2), 1, levels)."""
+    for u in U_GRID:
+        want = min(max(np.ceil(u - 0.5), 1.0), float(levels))
+        assert oracle.decode(4, u, levels) == want, u
+
+
+def test_impute_table_keeps_observed_entries_and_decodes_the_rest():
+    """Section 5.4 on a mixed table: missing entries take the decoded value of
+    their column's loss, observed entries keep A_ij when asked to; with no
+    mask every entry is decoded (the denoised table)."""
+    rng = np.random.default_rng(5)
+    m, n, k = 7, 6, 3
+    X, Y = rng.normal(size=(m, k)), rng.normal(size=(n, k))
+    losses = [(0, 0, 0.0), (3, 0, 0.0), (4, 4, 0.0)]
+    col_loss = np.array([0, 1, 2, 0, 2, 1], np.uint8)
+    A = rng.normal(size=(m, n))
+    mask = rng.random((m, n)) < 0.6
+    Z, full = oracle.impute(X, Y, col_loss, losses)
+    assert np.allclose(Z, np.einsum("ik,jk->ij", X, Y), rtol=0, atol=1e-12)
+    for i in range(m):
+        for j in range(n):
+            u = sum(X[i, l] * Y[j, l] for l in range(k))
+            kind = losses[col_loss[j]][0]
+            want = u if kind == 0 else (np.sign(u) if kind == 3 else min(max(np.ceil(u - 0.5), 1), 4))
+            assert full[i, j] == pytest.approx(want, abs=1e-12)
+    _, part = oracle.impute(X, Y, col_loss, losses, A=A, mask=mask)
+    assert np.array_equal(part[mask], A[mask])
+    assert np.array_equal(part[~mask], full[~mask])
