@@ -68,6 +68,8 @@ def workload(name):
         return synth.plain_pca()
     if name == "autograd":
         return synth.autograd_point()
+    if name == "impute":
+        return synth.heterogeneous()
     raise SystemExit("unknown workload " + name)
 
 
@@ -151,6 +153,41 @@ def run_grad(case, precisions, steps, warmup):
     return out
 
 
+def run_impute(case, steps, warmup):
+    """One step = one decoded table (glrm_impute, Section 5.4) from the case's
+    factors, in each of the two forms; HIP events on the stream the calls run
+    on bracket the timed calls."""
+    import torch
+
+    import paper_1410_0342_amd as g
+
+    dev = torch.device("cuda:0")
+    data = g.Data.from_case(case, dev)
+    g.glrm_prepare(data)
+    X = torch.from_numpy(case.X0).to(dev)
+    Y = torch.from_numpy(case.Y0).to(dev)
+    out = torch.empty((case.m, case.n), dtype=torch.float32, device=dev)
+    m, n, k = case.m, case.n, case.k
+    res = {}
+    for name, mode, alg_bytes in (("all", g.IMPUTE_ALL, 4.0 * m * n + 4.0 * (m + n) * k),
+                                  ("missing", g.IMPUTE_MISSING, 9.0 * m * n + 4.0 * (m + n) * k)):
+        for _ in range(max(warmup, 1)):
+            g.glrm_impute(data, X, Y, mode=mode, out=out, flags=g.WS_PREPARED)
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(st)
+        for _ in range(steps):
+            g.glrm_impute(data, X, Y, mode=mode, out=out, flags=g.WS_PREPARED)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / max(steps, 1)
+        gbs = alg_bytes / (ms * 1e-3) / 1e9
+        res[name] = dict(ms_per_step=ms, value=m * n / (ms * 1e-3), achieved=gbs, alg_bytes=alg_bytes)
+        log("impute %s: %.4f ms per table, %.4g entries/s, %.0f GB/s algorithmic" % (name, ms, m * n / (ms * 1e-3), gbs))
+    return res
+
+
 def copy_calibration():
     """A plain device copy of known size (for scaling rocprofv3 byte counters)."""
     import torch
@@ -187,7 +224,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dense_quadratic",
-                    choices=["dense_quadratic", "heterogeneous", "sparse_completion", "plain_pca", "autograd"])
+                    choices=["dense_quadratic", "heterogeneous", "sparse_completion", "plain_pca", "autograd",
+                             "impute"])
     ap.add_argument("--precision", default="both", choices=["both", "bf16", "fp32", "bf16_plain"])
     ap.add_argument("--cpu-rows", type=int, default=100000)
     ap.add_argument("--cpu-sweeps", type=int, default=2)
@@ -210,6 +248,26 @@ def main():
         precisions = ["fp32"]
     else:
         precisions = ["bf16", "fp32"] if args.precision == "both" else [args.precision]
+    if args.workload == "impute":
+        res = run_impute(case, args.steps, args.warmup)
+        r = res["all"]
+        line = {
+            "metric": "table entries decoded/s (Section 5.4 imputation from fitted factors)",
+            "value": r["value"], "unit": "entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "impute_" + case.name, "m": case.m, "n": case.n, "k": case.k,
+                       "layout": "dense", "mode": "all"},
+            "roofline": {"bound": "hbm", "kernel": "impute (every entry)", "achieved": r["achieved"],
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS,
+                         "traffic": None, "algorithmic_bytes_per_launch": r["alg_bytes"]},
+            "missing_only": {"value": res["missing"]["value"], "ms_per_step": res["missing"]["ms_per_step"],
+                             "achieved_GBs": res["missing"]["achieved"],
+                             "frac": res["missing"]["achieved"] / HBM_PEAK_GBS,
+                             "algorithmic_bytes_per_launch": res["missing"]["alg_bytes"]},
+        }
+        print(json.dumps(line), flush=True)
+        return
     if args.workload == "autograd":
         res = run_grad(case, precisions, args.steps, args.warmup)
         head = precisions[0]

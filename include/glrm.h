@@ -213,6 +213,30 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
              const glrm_fit_opts *opts, glrm_fit_info *info_host, double *history,
              void *ws, size_t ws_bytes, void *stream);
 
+/* Imputation modes. */
+#define GLRM_IMPUTE_ALL     0  /* decode every entry: the denoised table (end of Section 5.4) */
+#define GLRM_IMPUTE_MISSING 1  /* observed entries keep A_ij; only the missing ones are decoded */
+
+/* The decoded table of Section 5.4, Ahat_ij = argmin over the data domain of
+ * L_j(x_i . y_j, a):
+ *   QUADRATIC, HUBER   x_i . y_j (losses over the reals are smallest at a = u)
+ *   LOGISTIC, HINGE    +1 if x_i . y_j > 0, else -1 (at 0 both values tie and
+ *                      the smaller is taken)
+ *   ORDINAL            the level nearest to x_i . y_j, clamped to 1..levels (a
+ *                      half-way tie takes the lower level)
+ * x_i . y_j is a float32 fused multiply-add chain over l = 0..k-1, so an entry
+ * within rounding of a tie may decode to either neighbour.  X and Y must be
+ * finite.  Ahat is m x n row-major with leading dimension ldh >= n (device);
+ * all m x n entries are written, the padding beyond n is not.  With
+ * GLRM_IMPUTE_MISSING the observed entries receive A_ij instead (dense: mask
+ * != 0, or every entry when mask is NULL; COO: the nnz listed entries).
+ * Reads the per-column loss codes from `ws` (glrm_workspace_size() bytes):
+ * without GLRM_WS_PREPARED in `flags` it uploads them first and waits for that
+ * small copy, and a COO list in GLRM_IMPUTE_MISSING mode is prepared (and its
+ * indices validated) in full.  Otherwise asynchronous on `stream`. */
+int glrm_impute(const glrm_data *d, const float *X, const float *Y, int32_t mode, float *Ahat, int64_t ldh,
+                void *ws, size_t ws_bytes, unsigned flags, void *stream);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char *glrm_last_error(void);
 

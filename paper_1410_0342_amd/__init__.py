@@ -15,7 +15,7 @@ import numpy as np
 __all__ = [
     "GLRMError", "Data", "glrm_workspace_size", "glrm_prepare", "glrm_objective", "glrm_grad", "glrm_prox",
     "glrm_fit", "glrm_last_error", "library_path", "FP32", "BF16", "FP64", "BF16_PLAIN", "DENSE", "COO_ROWSORTED",
-    "WS_PREPARED", "TIME_KERNELS",
+    "WS_PREPARED", "TIME_KERNELS", "glrm_impute", "IMPUTE_ALL", "IMPUTE_MISSING",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,6 +25,7 @@ FP32, BF16, FP64, BF16_PLAIN = 0, 1, 2, 3
 DENSE, COO_ROWSORTED = 0, 1
 WS_PREPARED = 1
 TIME_KERNELS = 2
+IMPUTE_ALL, IMPUTE_MISSING = 0, 1
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp64": FP64, "bf16_plain": BF16_PLAIN}
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
@@ -93,6 +94,8 @@ def _L():
         L.glrm_fit.restype = ctypes.c_int
         L.glrm_fit.argtypes = [D, P, P, P, P, ctypes.POINTER(_FitOpts), ctypes.POINTER(_FitInfo), P, P,
                                ctypes.c_size_t, P]
+        L.glrm_impute.restype = ctypes.c_int
+        L.glrm_impute.argtypes = [D, P, P, ctypes.c_int32, P, ctypes.c_int64, P, ctypes.c_size_t, ctypes.c_uint, P]
         L.glrm_last_error.restype = ctypes.c_char_p
         L.glrm_last_error.argtypes = []
         L.glrm_version.restype = ctypes.c_char_p
@@ -289,3 +292,22 @@ def glrm_fit(data, X, Y, alpha_x, alpha_y, max_sweeps, precision=BF16, init_alph
     return dict(sweeps=info.sweeps, objective=info.objective, objective_fp32=info.objective_fp32,
                 rows_rejected=info.rows_rejected, cols_rejected=info.cols_rejected,
                 kernel_ms=list(info.kernel_ms), kernel_calls=list(info.kernel_calls))
+
+
+def glrm_impute(data, X, Y, mode=IMPUTE_ALL, out=None, flags=0, stream=None):
+    """The decoded table of Section 5.4 (m x n float32): every entry, or with
+    ``mode=IMPUTE_MISSING`` only the missing ones (observed entries keep A).
+    ``out`` may be a row-strided m x n float32 view (stride (ldh, 1))."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((data.m, data.n), dtype=torch.float32, device=X.device)
+    if not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.float32:
+        raise TypeError("out must be a float32 GPU tensor")
+    if out.dim() != 2 or tuple(out.shape) != (data.m, data.n) or out.stride(1) != 1 or out.stride(0) < data.n:
+        raise ValueError("out must be m x n with stride (ldh >= n, 1)")
+    ws, wsb = data.workspace()
+    _check(_L().glrm_impute(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
+                            _dev_ptr(Y, torch.float32, "Y", data.n * data.k), int(mode),
+                            ctypes.c_void_p(out.data_ptr()), int(out.stride(0)), ws, wsb, int(flags),
+                            _stream(stream)))
+    return out

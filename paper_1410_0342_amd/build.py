@@ -11,7 +11,8 @@ LIB = os.path.join(HERE, "libglrm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # (source, extra flags, object name): dense_prec.hip is built once per precision
 SOURCES = [("glrm_api.cpp", [], "glrm_api"), ("common.hip", [], "common"), ("dense.hip", [], "dense"),
-           ("coo.hip", [], "coo")]
+           ("coo.hip", [], "coo"),
+           ("impute.hip", [], "impute")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-mllvm", "-pragma-unroll-threshold=1000000",

@@ -13,6 +13,7 @@
 #include "../../include/glrm.h"
 #include "glrm_kernels.h"
 #include "coo.h"
+#include "impute.h"
 
 using namespace glrm;
 
@@ -250,16 +251,25 @@ int check_ws(const Layout &L, void *ws, size_t ws_bytes)
     return GLRM_OK;
 }
 
-int prepare(const glrm_data *d, const Layout &L, void *ws, hipStream_t st)
+// Per-column loss codes: host -> workspace.  Padding columns repeat the last
+// column's code, so the last tile keeps one loss.  Without a code list every
+// column gets code 0.  The caller keeps `codes` alive until the copy is done.
+int upload_codes(const glrm_data *d, const Layout &L, void *ws, std::string &codes, hipStream_t st)
 {
-    // loss codes: host -> workspace (padded columns get code 0)
-    // padding columns repeat the last column's code, so the last tile keeps one loss
-    std::string codes((size_t)L.ldp, '\0');
+    codes.assign((size_t)L.ldp, '\0');
     if (d->col_loss) {
         memcpy(&codes[0], d->col_loss, (size_t)d->n);
         for (int64_t j = d->n; j < L.ldp; ++j) codes[(size_t)j] = (char)d->col_loss[d->n - 1];
     }
     HIP_TRY(hipMemcpyAsync(at<uint8_t>(ws, L.codes), codes.data(), (size_t)L.ldp, hipMemcpyHostToDevice, st));
+    return GLRM_OK;
+}
+
+int prepare(const glrm_data *d, const Layout &L, void *ws, hipStream_t st)
+{
+    std::string codes;
+    int rc0 = upload_codes(d, L, ws, codes, st);
+    if (rc0) return rc0;
     if (d->layout == GLRM_DENSE) {
         HIP_TRY(launch_fill_i32(at<int32_t>(ws, L.col_count), L.n, 0, st));
         PackArgs p;
@@ -533,6 +543,50 @@ int glrm_grad(const glrm_data *d, const float *X, const float *Y, int precision,
         HIP_TRY(hipMemcpyAsync(obj_host, res, sizeof(double), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
+    return GLRM_OK;
+}
+
+int glrm_impute(const glrm_data *d, const float *X, const float *Y, int32_t mode, float *Ahat, int64_t ldh, void *ws,
+                size_t ws_bytes, unsigned flags, void *stream)
+{
+    g_err.clear();
+    int rc = validate_data(d);
+    if (rc) return rc;
+    if (!X || !Y || !Ahat) return fail(GLRM_EINVAL, "X, Y and Ahat must not be NULL");
+    if (mode != GLRM_IMPUTE_ALL && mode != GLRM_IMPUTE_MISSING) return fail(GLRM_EINVAL, "unknown imputation mode %d", mode);
+    if (ldh < d->n) return fail(GLRM_EINVAL, "ldh (%lld) < n (%lld)", (long long)ldh, (long long)d->n);
+    Layout L;
+    make_layout(d, L);
+    if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    // the pass needs only the loss codes; a COO list that is about to be
+    // written into the output is validated by the full preparation
+    if (!(flags & GLRM_WS_PREPARED)) {
+        if (d->layout == GLRM_COO_ROWSORTED && mode == GLRM_IMPUTE_MISSING) {
+            if ((rc = prepare(d, L, ws, st))) return rc;
+        } else {
+            std::string codes;
+            if ((rc = upload_codes(d, L, ws, codes, st))) return rc;
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+    }
+    const bool dense_keep = d->layout == GLRM_DENSE && mode == GLRM_IMPUTE_MISSING;
+    if (dense_keep && !d->mask) {
+        // every entry is observed: the table itself
+        HIP_TRY(hipMemcpy2DAsync(Ahat, (size_t)ldh * sizeof(float), d->A, (size_t)d->lda * sizeof(float),
+                                 (size_t)d->n * sizeof(float), (size_t)d->m, hipMemcpyDeviceToDevice, st));
+        return GLRM_OK;
+    }
+    ImputeArgs a;
+    a.m = d->m; a.n = d->n; a.ldh = ldh; a.lda = dense_keep ? d->lda : 0;
+    a.k = d->k;
+    a.rows_per_block = impute_rows_per_block(d->m, d->n);
+    a.keep_observed = dense_keep ? 1 : 0;
+    a.codes = at<uint8_t>(ws, L.codes);
+    a.lt = make_losstab(d);
+    HIP_TRY(launch_impute(a, X, Y, dense_keep ? d->A : nullptr, dense_keep ? d->mask : nullptr, Ahat, st));
+    if (d->layout == GLRM_COO_ROWSORTED && mode == GLRM_IMPUTE_MISSING)
+        HIP_TRY(launch_scatter_observed(d->nnz, d->m, d->n, ldh, d->row, d->col, d->A, Ahat, st));
     return GLRM_OK;
 }
 

@@ -1,0 +1,168 @@
+// Imputation (Section 5.4): every entry of the table decoded from the fitted
+// factors, a_hat_ij = argmin over the column's data domain of L_j(x_i . y_j, a).
+//
+// The pass is bound by its m x n store.  Each lane owns one column j and keeps
+// y_j in registers; a workgroup walks a chunk of rows, and every row's x_i is
+// the same for the whole wavefront, so it comes in through scalar loads and
+// feeds the lanes' multiply-adds as a scalar operand.  Stores are one row's 64
+// consecutive columns per wavefront instruction.
+#include <algorithm>
+#include <utility>
+
+#include "glrm_device.h"
+#include "impute.h"
+
+namespace glrm {
+
+// The decoded value for the three domains: real (quadratic, Huber: the product
+// itself), Boolean (logistic, hinge: +1 above zero, -1 otherwise, so a tie at
+// zero takes the smaller value) and ordinal (the nearest level, clamped to
+// 1..levels, a half-way tie taking the lower one: stepping from level a to a+1
+// lowers the ordinal hinge only while a < u - 1/2).  u - 0.5f is exact wherever
+// the clamp does not decide the result.
+__device__ __forceinline__ float decode_entry(float u, int kind, float levels)
+{
+    const float boolean = u > 0.0f ? 1.0f : -1.0f;
+    const float ordinal = fminf(fmaxf(ceilf(u - 0.5f), 1.0f), levels);
+    return kind <= L_HUBER ? u : (kind <= L_HINGE ? boolean : ordinal);
+}
+
+// Rows of the table loaded ahead in the missing-only form (clamped to the
+// chunk, so the loads past its end repeat its last row and stay in bounds).
+template <int RB>
+__device__ __forceinline__ void load_rows(const float *__restrict__ A, const uint8_t *__restrict__ mask, int64_t lda,
+                                          int64_t ib, int64_t i1, int64_t jc, float (&av)[RB], uint8_t (&obs)[RB])
+{
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const int64_t o = (ib + r < i1 ? ib + r : i1 - 1) * lda + jc;
+        obs[r] = mask[o];
+        av[r] = A[o];
+    }
+}
+
+// KEEP: observed entries (mask != 0) keep A_ij (the missing-only form).
+template <int K, bool KEEP>
+__global__ __launch_bounds__(256) void impute_kernel(ImputeArgs a, const float *__restrict__ X,
+                                                     const float *__restrict__ Y, const float *__restrict__ A,
+                                                     const uint8_t *__restrict__ mask, float *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t ncb = (a.n + 255) >> 8;
+    const int64_t cb = blockIdx.x % ncb, chunk = blockIdx.x / ncb;
+    const int64_t j = cb * 256 + w * 64 + lane;
+    const bool live = j < a.n;
+    const int64_t jc = live ? j : a.n - 1;
+
+    float y[K];
+#pragma unroll
+    for (int l = 0; l < K; ++l) y[l] = Y[jc * K + l];
+    // this column's loss, picked from the table by its code
+    const int code = a.codes[jc];
+    int kind = a.lt.kind[0];
+    float levels = (float)a.lt.levels[0];
+#pragma unroll
+    for (int q = 1; q < MAX_LOSSES; ++q)
+        if (code == q) {
+            kind = a.lt.kind[q];
+            levels = (float)a.lt.levels[q];
+        }
+    // Stores and loads share one completion counter, so a wait for y_j inside
+    // the row loop would also wait for every store issued before it: wait once
+    // here.  The missing-only form loads the table one batch of rows ahead, so
+    // its wait for a batch leaves the stores issued since in flight.
+    __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
+#pragma unroll
+    for (int l = 0; l < K; ++l) asm volatile("" : "+v"(y[l]));   // y_j is in registers from here on
+    constexpr int RB = 4;
+    const int64_t i0 = chunk * a.rows_per_block;
+    const int64_t i1 = i0 + a.rows_per_block < a.m ? i0 + a.rows_per_block : a.m;
+    float av[RB], avn[RB];
+    uint8_t obs[RB], obsn[RB];
+    if constexpr (KEEP) load_rows<RB>(A, mask, a.lda, i0, i1, jc, av, obs);
+    for (int64_t ib = i0; ib < i1; ib += RB) {
+        if constexpr (KEEP) load_rows<RB>(A, mask, a.lda, ib + RB, i1, jc, avn, obsn);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int64_t i = ib + r;
+            if (i >= i1) break;
+            const float *xr = X + i * K;
+            float u = 0.0f;
+#pragma unroll
+            for (int l = 0; l < K; ++l) u = __builtin_fmaf(xr[l], y[l], u);
+            float v = decode_entry(u, kind, levels);
+            if constexpr (KEEP) v = obs[r] != 0 ? av[r] : v;
+            if (live) out[i * a.ldh + j] = v;
+        }
+        if constexpr (KEEP) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                av[r] = avn[r];
+                obs[r] = obsn[r];
+            }
+        }
+    }
+}
+
+// Observed entries of a row-sorted COO list written over the decoded table.
+// Indices outside the table are skipped (the host validates them beforehand).
+__global__ __launch_bounds__(256) void scatter_observed_kernel(int64_t nnz, int64_t m, int64_t n, int64_t ldh,
+                                                               const int32_t *__restrict__ row,
+                                                               const int32_t *__restrict__ col,
+                                                               const float *__restrict__ val, float *__restrict__ out)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nnz) return;
+    const int64_t r = row[e], c = col[e];
+    if (r >= 0 && r < m && c >= 0 && c < n) out[r * ldh + c] = val[e];
+}
+
+int impute_rows_per_block(int64_t m, int64_t n)
+{
+    // about eight workgroups per CU over the whole table, at least 16 rows each
+    const int64_t ncb = (n + 255) / 256;
+    const int64_t chunks = std::max<int64_t>(1, (IMPUTE_TARGET_BLOCKS + ncb - 1) / ncb);
+    return (int)std::max<int64_t>(16, (m + chunks - 1) / chunks);
+}
+
+// One instance per rank, so a row of X is a fixed run of scalar loads.
+template <int K>
+static hipError_t launch_k(const ImputeArgs &a, const float *X, const float *Y, const float *A, const uint8_t *mask,
+                           float *out, hipStream_t st)
+{
+    const int64_t ncb = (a.n + 255) / 256, chunks = (a.m + a.rows_per_block - 1) / a.rows_per_block;
+    if (a.keep_observed)
+        hipLaunchKernelGGL((impute_kernel<K, true>), dim3((unsigned)(ncb * chunks)), dim3(256), 0, st, a, X, Y, A,
+                           mask, out);
+    else
+        hipLaunchKernelGGL((impute_kernel<K, false>), dim3((unsigned)(ncb * chunks)), dim3(256), 0, st, a, X, Y, A,
+                           mask, out);
+    return hipGetLastError();
+}
+
+template <int... Ks>
+static hipError_t launch_rank(const ImputeArgs &a, const float *X, const float *Y, const float *A,
+                              const uint8_t *mask, float *out, hipStream_t st, std::integer_sequence<int, Ks...>)
+{
+    hipError_t e = hipErrorInvalidValue;
+    ((a.k == Ks + 1 ? (e = launch_k<Ks + 1>(a, X, Y, A, mask, out, st), 0) : 0), ...);
+    return e;
+}
+
+hipError_t launch_impute(const ImputeArgs &a, const float *X, const float *Y, const float *A, const uint8_t *mask,
+                         float *out, hipStream_t st)
+{
+    return launch_rank(a, X, Y, A, mask, out, st, std::make_integer_sequence<int, IMPUTE_MAX_K>{});
+}
+
+hipError_t launch_scatter_observed(int64_t nnz, int64_t m, int64_t n, int64_t ldh, const int32_t *row,
+                                   const int32_t *col, const float *val, float *out, hipStream_t st)
+{
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_observed_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, nnz, m, n,
+                       ldh, row, col, val, out);
+    return hipGetLastError();
+}
+
+}  // namespace glrm

@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(g.library_path())
     names = _declared()
     assert {"glrm_objective", "glrm_grad", "glrm_prox", "glrm_fit", "glrm_workspace_size", "glrm_prepare",
-            "glrm_last_error"} <= set(names)
+            "glrm_impute", "glrm_last_error"} <= set(names)
     for name in names:
         assert hasattr(lib, name), name
 
@@ -108,3 +108,18 @@ def test_an_empty_coo_needs_no_arrays():
     s, keep = _data(layout=1, A=None, row=None, col=None, nnz=0)
     assert g._L().glrm_workspace_size(ctypes.byref(s)) > 0
 
+
+
+def test_impute_argument_errors():
+    s, keep = _data()
+    P = ctypes.c_void_p(0x1000)
+    L = g._L()
+    assert L.glrm_impute(ctypes.byref(s), P, P, 0, None, 8, P, 1 << 40, 0, None) == g.EINVAL
+    assert "NULL" in g.glrm_last_error()
+    assert L.glrm_impute(ctypes.byref(s), P, P, 2, P, 8, P, 1 << 40, 0, None) == g.EINVAL
+    assert "mode" in g.glrm_last_error()
+    assert L.glrm_impute(ctypes.byref(s), P, P, 0, P, 7, P, 1 << 40, 0, None) == g.EINVAL
+    assert "ldh" in g.glrm_last_error()
+    assert L.glrm_impute(ctypes.byref(s), P, P, 0, P, 8, P, 16, 0, None) == g.ENOMEM
+    bad, keep2 = _data(losses=[(7, 0, 0.0)])
+    assert L.glrm_impute(ctypes.byref(bad), P, P, 0, P, 8, P, 1 << 40, 0, None) == g.EINVAL
