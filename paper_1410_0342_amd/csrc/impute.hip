@@ -4,8 +4,16 @@
 // The pass is bound by its m x n store.  Each lane owns one column j and keeps
 // y_j in registers; a workgroup walks a chunk of rows, and every row's x_i is
 // the same for the whole wavefront, so it comes in through scalar loads and
-// feeds the lanes' multiply-adds as a scalar operand.  Stores are one row's 64
-// consecutive columns per wavefront instruction.
+// feeds the lanes' multiply-adds as a scalar operand.
+//
+// Stores: HBM takes whole 128-byte lines far faster than parts of lines, and a
+// row of 4n bytes starts on a line boundary only when 4n is a multiple of 128.
+// A contiguous table of at most 256 columns whose rows are not line-aligned is
+// one workgroup wide, so the workgroup stages SB rows in LDS and stores their
+// flat range with line-aligned wavefront stores; other tables store each row's
+// 64 columns per wavefront directly.  The every-entry form stores non-temporally (the table is
+// not read back here); the missing-only form measured faster with plain
+// stores.
 #include <algorithm>
 #include <utility>
 
@@ -41,12 +49,31 @@ __device__ __forceinline__ void load_rows(const float *__restrict__ A, const uin
     }
 }
 
+constexpr int SB = 16;   // rows staged per flat store
+
+// The staged rows of the flat form (SB rows of at most 256 columns).
+__device__ __forceinline__ float *stage_tile()
+{
+    __shared__ float tile[SB * 256];
+    return tile;
+}
+
+template <bool NT>
+__device__ __forceinline__ void store_entry(float *p, float v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // KEEP: observed entries (mask != 0) keep A_ij (the missing-only form).
-template <int K, bool KEEP>
+// FLAT: the table is contiguous (ldh == n) and n <= 256: rows go through LDS
+// and out as one flat, line-aligned range per SB rows.
+template <int K, bool KEEP, bool FLAT>
 __global__ __launch_bounds__(256) void impute_kernel(ImputeArgs a, const float *__restrict__ X,
                                                      const float *__restrict__ Y, const float *__restrict__ A,
                                                      const uint8_t *__restrict__ mask, float *__restrict__ out)
 {
+    constexpr bool NT = !KEEP;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t ncb = (a.n + 255) >> 8;
@@ -71,7 +98,8 @@ __global__ __launch_bounds__(256) void impute_kernel(ImputeArgs a, const float *
     // Stores and loads share one completion counter, so a wait for y_j inside
     // the row loop would also wait for every store issued before it: wait once
     // here.  The missing-only form loads the table one batch of rows ahead, so
-    // its wait for a batch leaves the stores issued since in flight.
+    // its wait for a batch leaves the stores issued since in flight; the
+    // barriers around the staged rows wait on LDS only, for the same reason.
     __builtin_amdgcn_s_waitcnt(0x0f70);   // vmcnt(0)
 #pragma unroll
     for (int l = 0; l < K; ++l) asm volatile("" : "+v"(y[l]));   // y_j is in registers from here on
@@ -81,26 +109,42 @@ __global__ __launch_bounds__(256) void impute_kernel(ImputeArgs a, const float *
     float av[RB], avn[RB];
     uint8_t obs[RB], obsn[RB];
     if constexpr (KEEP) load_rows<RB>(A, mask, a.lda, i0, i1, jc, av, obs);
-    for (int64_t ib = i0; ib < i1; ib += RB) {
-        if constexpr (KEEP) load_rows<RB>(A, mask, a.lda, ib + RB, i1, jc, avn, obsn);
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const int64_t i = ib + r;
-            if (i >= i1) break;
-            const float *xr = X + i * K;
-            float u = 0.0f;
-#pragma unroll
-            for (int l = 0; l < K; ++l) u = __builtin_fmaf(xr[l], y[l], u);
-            float v = decode_entry(u, kind, levels);
-            if constexpr (KEEP) v = obs[r] != 0 ? av[r] : v;
-            if (live) out[i * a.ldh + j] = v;
-        }
-        if constexpr (KEEP) {
+    for (int64_t sb = i0; sb < i1; sb += SB) {
+        const int64_t se = sb + SB < i1 ? sb + SB : i1;
+        for (int64_t ib = sb; ib < se; ib += RB) {
+            if constexpr (KEEP) load_rows<RB>(A, mask, a.lda, ib + RB, i1, jc, avn, obsn);
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                av[r] = avn[r];
-                obs[r] = obsn[r];
+                const int64_t i = ib + r;
+                if (i >= se) break;
+                const float *xr = X + i * K;
+                float u = 0.0f;
+#pragma unroll
+                for (int l = 0; l < K; ++l) u = __builtin_fmaf(xr[l], y[l], u);
+                float v = decode_entry(u, kind, levels);
+                if constexpr (KEEP) v = obs[r] != 0 ? av[r] : v;
+                if constexpr (FLAT) {
+                    if (live) stage_tile()[(i - sb) * a.n + j] = v;
+                } else {
+                    if (live) store_entry<NT>(&out[i * a.ldh + j], v);
+                }
             }
+            if constexpr (KEEP) {
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    av[r] = avn[r];
+                    obs[r] = obsn[r];
+                }
+            }
+        }
+        if constexpr (FLAT) {
+            // the staged rows are out[sb * n, se * n): store it from the line
+            // that holds its first entry, 256 consecutive entries per pass
+            lds_barrier();
+            const int64_t f0 = sb * a.n, f1 = se * a.n;
+            for (int64_t t = (f0 & ~(int64_t)31) + threadIdx.x; t < f1; t += 256)
+                if (t >= f0) store_entry<NT>(&out[t], stage_tile()[t - f0]);
+            lds_barrier();
         }
     }
 }
@@ -132,12 +176,17 @@ static hipError_t launch_k(const ImputeArgs &a, const float *X, const float *Y, 
                            float *out, hipStream_t st)
 {
     const int64_t ncb = (a.n + 255) / 256, chunks = (a.m + a.rows_per_block - 1) / a.rows_per_block;
-    if (a.keep_observed)
-        hipLaunchKernelGGL((impute_kernel<K, true>), dim3((unsigned)(ncb * chunks)), dim3(256), 0, st, a, X, Y, A,
-                           mask, out);
-    else
-        hipLaunchKernelGGL((impute_kernel<K, false>), dim3((unsigned)(ncb * chunks)), dim3(256), 0, st, a, X, Y, A,
-                           mask, out);
+    const dim3 grid((unsigned)(ncb * chunks));
+    // staged only where rows do not start on line boundaries: aligned rows
+    // measured faster stored directly
+    const bool flat = a.ldh == a.n && a.n <= 256 && (a.n % 32) != 0;
+    if (a.keep_observed) {
+        if (flat) hipLaunchKernelGGL((impute_kernel<K, true, true>), grid, dim3(256), 0, st, a, X, Y, A, mask, out);
+        else hipLaunchKernelGGL((impute_kernel<K, true, false>), grid, dim3(256), 0, st, a, X, Y, A, mask, out);
+    } else {
+        if (flat) hipLaunchKernelGGL((impute_kernel<K, false, true>), grid, dim3(256), 0, st, a, X, Y, A, mask, out);
+        else hipLaunchKernelGGL((impute_kernel<K, false, false>), grid, dim3(256), 0, st, a, X, Y, A, mask, out);
+    }
     return hipGetLastError();
 }
 
