@@ -116,7 +116,26 @@ def run_gpu(case, precisions, steps, warmup):
         kinfo = g.glrm_fit(data, X.clone(), Y.clone(), ax.clone(), ay.clone(), kt_sweeps, precision=prec,
                            init_alpha=False, flags=g.WS_PREPARED | g.TIME_KERNELS)
         torch.cuda.synchronize()
+        # Spread of the per-sweep time: each sample is the extra time of a
+        # 25-sweep fit over a 5-sweep fit, divided by 20, which cancels a fit
+        # call's fixed cost (set-up, final FP64 objective, synchronization).
+        # HIP events on the stream the fits run on; the timed state is untouched.
+        Xs, Ys, axs, ays = X.clone(), Y.clone(), ax.clone(), ay.clone()
+        st = torch.cuda.current_stream()
+
+        def fit_ms(sweeps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            g.glrm_fit(data, Xs, Ys, axs, ays, sweeps, precision=prec, init_alpha=False, flags=g.WS_PREPARED)
+            e1.record(st)
+            e1.synchronize()
+            return e0.elapsed_time(e1)
+
+        per = [(fit_ms(25) - fit_ms(5)) / 20.0 for _ in range(10)]
+        pct = np.percentile(np.array(per), [10, 50, 90])
+        del Xs, Ys, axs, ays
         out[pname] = dict(ms_per_step=ms, value=nnz / (ms * 1e-3), objective=info["objective"],
+                          sweep_ms_p10_p50_p90=[float(v) for v in pct],
                           objective_tracked=info["objective_fp32"], rows_rejected=info["rows_rejected"],
                           cols_rejected=info["cols_rejected"],
                           kernel_ms=[v / kt_sweeps for v in kinfo["kernel_ms"]],
@@ -375,6 +394,7 @@ def main():
                                        for p in ("bf16", "fp32")}
         line["bf16_over_fp32"] = res["bf16"]["value"] / res["fp32"]["value"]
     line["kernel_ms_per_sweep"] = {p: res[p]["kernel_ms"] for p in res}
+    line["sweep_ms_p10_p50_p90"] = {p: res[p]["sweep_ms_p10_p50_p90"] for p in res}
     if not args.no_cpu_baseline and case.layout == "dense":
         rows = min(args.cpu_rows, case.m)
         line["cpu_baseline"] = cpu_baseline(case, rows, args.cpu_sweeps)
