@@ -188,14 +188,31 @@ struct PanelBuf {
     float alpha[16];
 };
 
-// Loads of panel p into `pb`: tile slot s of this wavefront ...
-template <int KP, int TPW, int NW>
+// Where a tile's entries sit in its 1 KB slot.  Lane l = li + 16g reads row
+// li's columns 4g .. 4g+3 as one 16-byte word (the plain read), and in S6 the
+// rows 4g .. 4g+3 of column li (the transposed read).  Row i's columns
+// 4q .. 4q+3 are staged in word 16q + ((i + q) & 15): each quarter-wave's plain
+// reads then fall on 16 distinct words, and each 4-byte step of the transposed
+// read on 64 distinct banks (stored in order, row i's words sat in one bank
+// group per q, a 4-way conflict).
+__device__ __forceinline__ int tile_word(int row, int q) { return 16 * q + ((row + q) & 15); }
+
+// The staged word of lane l's plain read.  Only the row pass reads its tiles
+// transposed, so only it stages them in this order (SWZ); the other passes
+// keep row i's block q in word i + 16q, which they read in lane order.
+template <bool SWZ>
+__device__ __forceinline__ int tile_slot(int lane) { return SWZ ? tile_word(lane & 15, lane >> 4) : lane; }
+
+// Loads of panel p into `pb`: tile slot s of this wavefront (lane l fills
+// word l, with the row whose block g belongs there) ...
+template <int KP, int TPW, int NW, bool SWZ = false>
 __device__ __forceinline__ void stage_tile(PanelBuf<KP, TPW, NW> &pb, const float *Ap, int64_t ldp, int nt, int64_t p,
                                            int w, int lane, int s, int tile0 = 0)
 {
     const int li = lane & 15, g = lane >> 4;
+    const int row = SWZ ? (li - g) & 15 : li;   // tile_word(row, g) == lane under SWZ
     const int t = min(tile0 + w + NW * s, nt - 1);
-    lds_dma16(Ap + (p * 16 + li) * ldp + 4 * g + 16 * t, &pb.apan[w][s * 64]);
+    lds_dma16(Ap + (p * 16 + row) * ldp + 4 * g + 16 * t, &pb.apan[w][s * 64]);
 }
 
 // ... and the X rows and step sizes (spread over the wavefronts).
@@ -213,13 +230,13 @@ __device__ __forceinline__ void stage_rows(PanelBuf<KP, TPW, NW> &pb, const floa
 }
 
 // All loads of panel p into `pb` (every wavefront issues its own tiles).
-template <int KP, int TPW, int NW>
+template <int KP, int TPW, int NW, bool SWZ = false>
 __device__ __forceinline__ void stage_panel(PanelBuf<KP, TPW, NW> &pb, const float *Ap, int64_t ldp, int nt,
                                             const float *X, int64_t m, int k, const float *alpha, int64_t p,
                                             int w, int lane, int tile0 = 0)
 {
 #pragma unroll
-    for (int s = 0; s < TPW; ++s) stage_tile<KP, TPW, NW>(pb, Ap, ldp, nt, p, w, lane, s, tile0);
+    for (int s = 0; s < TPW; ++s) stage_tile<KP, TPW, NW, SWZ>(pb, Ap, ldp, nt, p, w, lane, s, tile0);
     stage_rows<KP, TPW, NW>(pb, X, m, k, alpha, p, w, lane);
 }
 
@@ -234,12 +251,14 @@ __device__ __forceinline__ float4 tile_entries(const float4 *apan, int s, int la
 }
 
 // The lane's four table entries in the layout of X . Y^T products: rows
-// 4g + r of column li of tile slot s.  The staged tile keeps row i's columns
-// 4q .. 4q+3 in lane i + 16q, so the four entries are four words 16 bytes apart.
+// 4g + r of column li of tile slot s (row 4g + r's block li >> 2, entry li & 3),
+// in the row pass's staging order.
 __device__ __forceinline__ float4 tile_entries_t(const float4 *apan, int s, int li, int g)
 {
-    const float *b = reinterpret_cast<const float *>(apan) + s * 256 + 64 * (li >> 2) + (li & 3) + 16 * g;
-    return float4{b[0], b[4], b[8], b[12]};
+    const int q = li >> 2;
+    const float *b = reinterpret_cast<const float *>(apan) + s * 256 + (li & 3);
+    return float4{b[4 * tile_word(4 * g + 0, q)], b[4 * tile_word(4 * g + 1, q)], b[4 * tile_word(4 * g + 2, q)],
+                  b[4 * tile_word(4 * g + 3, q)]};
 }
 
 __device__ __forceinline__ void wait_staged()
@@ -566,7 +585,7 @@ __device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, N
     // (FP32) the next panel's loads, all at once: no product is in flight yet
     if constexpr (!STAGE_IN_S5<PREC>)
         if (p_next >= 0)
-            stage_panel<KP, TPW, NWX_OF<KP>>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
+            stage_panel<KP, TPW, NWX_OF<KP>, true>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
     // software pipelined: tile s + 1's entries and product are issued before
     // tile s's losses (slots past the last tile compute on stale entries and
     // are skipped), and each tile's work sits behind a uniform branch, since
@@ -640,7 +659,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     for (int kb = 0; kb < KP / 16; ++kb) dx[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
     // software pipelined as in S6
     f32x4 zn = zprod<KP, PREC>(yfr[0], xf);
-    float4 an = apan[lane];
+    float4 an = apan[tile_slot<true>(lane)];
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
         const int t = w + NWX_OF<KP> * s;
@@ -648,7 +667,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         const float4 av = an;
         if (s + 1 < TPW) {
             zn = zprod<KP, PREC>(yfr[s + 1], xf);
-            an = apan[(s + 1) * 64 + lane];
+            an = apan[(s + 1) * 64 + tile_slot<true>(lane)];
         }
         if (t >= nt) continue;
         float L4[4], G[4];
@@ -714,16 +733,16 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     // read needs.
     const int64_t p_src = p_next >= 0 ? p_next : p;
     f32x4 zn2 = zprod<KP, PREC>(yfr[0], xpf);
-    float4 an2 = apan[lane];
+    float4 an2 = apan[tile_slot<true>(lane)];
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
         const int t = w + NWX_OF<KP> * s;
         const f32x4 zp = zn2;
         const float4 av = an2;
-        if constexpr (STAGE_IN_S5<PREC>) stage_tile<KP, TPW, NWX_OF<KP>>(nxt, a.Ap, a.ldp, nt, p_src, w, lane, s);
+        if constexpr (STAGE_IN_S5<PREC>) stage_tile<KP, TPW, NWX_OF<KP>, true>(nxt, a.Ap, a.ldp, nt, p_src, w, lane, s);
         if (s + 1 < TPW) {
             zn2 = zprod<KP, PREC>(yfr[s + 1], xpf);
-            an2 = apan[(s + 1) * 64 + lane];
+            an2 = apan[(s + 1) * 64 + tile_slot<true>(lane)];
         }
         if (t >= nt) continue;
         float L4[4], G4[4];
@@ -830,7 +849,7 @@ __global__ __launch_bounds__(NTX_OF<KP>, (XSTEP_MIN_WAVES<KP, TPW>)) void xstep_
     int rej_acc = 0;
 
     if (blockIdx.x < npanels)
-        stage_panel<KP, TPW, NWX_OF<KP>>(panel_buf<KP, TPW, PREC, 0>(sh, pb0, pb1), a.Ap, a.ldp, nt, a.X, a.m, a.k,
+        stage_panel<KP, TPW, NWX_OF<KP>, true>(panel_buf<KP, TPW, PREC, 0>(sh, pb0, pb1), a.Ap, a.ldp, nt, a.X, a.m, a.k,
                                          a.alpha, blockIdx.x, w, lane);
     for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
         const int64_t p1 = p + G, p2 = p + 2 * G;
