@@ -979,7 +979,8 @@ struct YCheckShared {
 
 template <int KP, int TPW, int PREC, int LK, int BUF>
 __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP, TPW> &sh, int64_t p,
-                                             int64_t p_next, const Frag<KP, PREC> (&yfr)[TPW], f32x4 (&hacc)[TPW])
+                                             int64_t p_next, int tile0, const Frag<KP, PREC> (&yfr)[TPW],
+                                             f32x4 (&hacc)[TPW])
 {
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
@@ -1008,15 +1009,17 @@ __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP
     }
     float4 av[TPW];
 #pragma unroll
-    for (int s = 0; s < TPW; ++s) av[s] = tile_entries(apan, s, lane, w + NWY_OF<KP> * s < nt);
+    for (int s = 0; s < TPW; ++s) av[s] = tile_entries(apan, s, lane, tile0 + w + NWY_OF<KP> * s < nt);
     // no barrier until the next panel: the prefetch overlaps this panel's products
-    if (p_next >= 0) stage_panel<KP, TPW, NWY_OF<KP>>(nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, p_next, w, lane);
+    if (p_next >= 0)
+        stage_panel<KP, TPW, NWY_OF<KP>>(nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, p_next, w, lane, tile0);
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = min(w + NWY_OF<KP> * s, nt - 1);
+        // the loss codes are staged per column block: index them by the tile's place in it
+        const int tl = min(tile0 + w + NWY_OF<KP> * s, nt - 1) - tile0;
         const f32x4 zp = zprod<KP, PREC>(yfr[s], xf);
         float L4[4], G4[4];
-        tile_loss<LK, false, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av[s], L4, G4);
+        tile_loss<LK, false, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, tl, zp, av[s], L4, G4);
 #pragma unroll
         for (int r = 0; r < 4; ++r) hacc[s][r] += L4[r];
     }
@@ -1030,38 +1033,45 @@ __global__ __launch_bounds__(NTY_OF<KP>, 1) void ycheck_kernel(YCheckArgs a)
     __shared__ YCheckShared<KP, TPW> sh;
     const int nt = (int)(a.ldp / 16);
     const int64_t npanels = a.mp / 16;
-    const int64_t G = gridDim.x;
+    // workgroup b takes column block b % ncb of the panels b / ncb, b / ncb + G, ...
+    const int64_t G = gridDim.x / a.ncb;
+    const int cb = (int)(blockIdx.x % a.ncb);
+    const int64_t b0 = blockIdx.x / a.ncb;
+    const int tile0 = cb * NWY_OF<KP> * TPW;
 
-    for (int j = threadIdx.x; j < a.ldp; j += NTY_OF<KP>) sh.s_codes[j] = a.codes[j];
+    // the loss codes of this workgroup's column block (columns past the table
+    // repeat its last code, as the padding columns do)
+    for (int j = threadIdx.x; j < 16 * NWY_OF<KP> * TPW; j += NTY_OF<KP>)
+        sh.s_codes[j] = a.codes[min<int64_t>(16 * (int64_t)tile0 + j, a.ldp - 1)];
     if (threadIdx.x == 0) sh.lt = a.lt;
     __syncthreads();
-    tile_codes(sh.s_codes, nt, sh.s_tcode, NTY_OF<KP>);
+    tile_codes(sh.s_codes, NWY_OF<KP> * TPW, sh.s_tcode, NTY_OF<KP>);
     Frag<KP, PREC> yfr[TPW];
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = min(w + NWY_OF<KP> * s, nt - 1);
+        const int t = min(tile0 + w + NWY_OF<KP> * s, nt - 1);
         frag_load_y<KP, PREC>(yfr[s], a.yplus, 16 * t + li, g);
     }
     f32x4 hacc[TPW];
 #pragma unroll
     for (int s = 0; s < TPW; ++s) hacc[s] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    if (blockIdx.x < npanels)
-        stage_panel<KP, TPW, NWY_OF<KP>>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, blockIdx.x, w, lane);
-    for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
+    if (b0 < npanels)
+        stage_panel<KP, TPW, NWY_OF<KP>>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, b0, w, lane, tile0);
+    for (int64_t p = b0; p < npanels; p += 2 * G) {
         const int64_t p1 = p + G, p2 = p + 2 * G;
-        ycheck_panel<KP, TPW, PREC, LK, 0>(a, sh, p, p1 < npanels ? p1 : -1, yfr, hacc);
-        if (p1 < npanels) ycheck_panel<KP, TPW, PREC, LK, 1>(a, sh, p1, p2 < npanels ? p2 : -1, yfr, hacc);
+        ycheck_panel<KP, TPW, PREC, LK, 0>(a, sh, p, p1 < npanels ? p1 : -1, tile0, yfr, hacc);
+        if (p1 < npanels) ycheck_panel<KP, TPW, PREC, LK, 1>(a, sh, p1, p2 < npanels ? p2 : -1, tile0, yfr, hacc);
     }
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = w + NWY_OF<KP> * s;
+        const int t = tile0 + w + NWY_OF<KP> * s;
         if (t < nt) {
             const int64_t j0 = 16 * t;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 float h = sum_lanes<16>(hacc[s][r]);
-                if (li == 0) a.part_hp[(int64_t)blockIdx.x * a.ldp + j0 + 4 * g + r] = h;
+                if (li == 0) a.part_hp[b0 * a.ldp + j0 + 4 * g + r] = h;
             }
         }
     }

@@ -655,8 +655,16 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
         const bool quad = make_lossu(lt).kind == L_QUAD;
         const int grid = (int)std::min<int64_t>(
             {(int64_t)L.pmax, npanels, (int64_t)cus * xstep_blocks((int)L.kp, tpw, prec, quad)});
-        const int grid_y = (int)std::min<int64_t>(
-            {(int64_t)L.pmax, npanels, (int64_t)cus * ycheck_blocks((int)L.kp, tpw_y, prec, quad)});
+        // A table wider than 4 tiles per wavefront runs the trial-column pass
+        // in column blocks of 4 tiles per wavefront, so two workgroups fit on
+        // a CU; the partial rows stay one per panel stream.
+        int ncb_y = 1;
+        if (tpw_y > 4) {
+            tpw_y = 4;
+            ncb_y = (int)((L.ldp / 16 + 4 * ycheck_waves((int)L.kp) - 1) / (4 * ycheck_waves((int)L.kp)));
+        }
+        const int grid_y = ncb_y * (int)std::min<int64_t>(
+            {(int64_t)L.pmax, npanels, (int64_t)cus * ycheck_blocks((int)L.kp, tpw_y, prec, quad) / ncb_y});
         XStepArgs xa;
         xa.m = L.m; xa.mp = L.mp; xa.ldp = L.ldp; xa.k = (int32_t)L.k;
         xa.Ap = at<float>(ws, L.Ap);
@@ -689,9 +697,10 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
         ca.Ap = xa.Ap; ca.codes = xa.codes; ca.lt = lt; ca.lu = xa.lu; ca.X = X;
         ca.yplus = pa.yplus;
         ca.part_hp = at<float>(ws, L.part_hp);
+        ca.ncb = ncb_y;
 
         YAcceptArgs aa;
-        aa.n = L.n; aa.ldp = L.ldp; aa.k = (int32_t)L.k; aa.P = grid_y;
+        aa.n = L.n; aa.ldp = L.ldp; aa.k = (int32_t)L.k; aa.P = grid_y / ncb_y;
         aa.part_hp = ca.part_hp; aa.ry_plus = pa.ry_plus; aa.h_old = pa.h_old;
         aa.alpha = alpha_y; aa.step_up = o->step_up; aa.step_down = o->step_down;
         aa.Yplus = pa.Yplus; aa.Y = Y;

@@ -76,6 +76,7 @@ struct YCheckArgs {
     const float *X;
     YShadow yplus;
     float *part_hp;         // P x ldp
+    int32_t ncb;            // column blocks per panel (workgroups b with b % ncb == c take block c)
 };
 
 struct YAcceptArgs {
