@@ -8,10 +8,11 @@
 //
 // Stores: HBM takes whole 128-byte lines far faster than parts of lines, and a
 // row of 4n bytes starts on a line boundary only when 4n is a multiple of 128.
-// A contiguous table of at most 256 columns whose rows are not line-aligned is
-// one workgroup wide, so the workgroup stages SB rows in LDS and stores their
-// flat range with line-aligned wavefront stores; other tables store each row's
-// 64 columns per wavefront directly.  The every-entry form stores non-temporally (the table is
+// A contiguous table of at most 1024 columns whose rows are not line-aligned
+// runs one workgroup per row width (4 wavefronts up to 256 columns, 16 up to
+// 1024), so the workgroup stages SB rows in LDS and stores their flat range
+// with line-aligned wavefront stores; other tables store each row's 64 columns
+// per wavefront directly, in workgroups of 256 columns.  The every-entry form stores non-temporally (the table is
 // not read back here); the missing-only form measured faster with plain
 // stores.
 #include <algorithm>
@@ -51,10 +52,11 @@ __device__ __forceinline__ void load_rows(const float *__restrict__ A, const uin
 
 constexpr int SB = 16;   // rows staged per flat store
 
-// The staged rows of the flat form (SB rows of at most 256 columns).
+// The staged rows of the flat form (SB rows of at most W columns).
+template <int W>
 __device__ __forceinline__ float *stage_tile()
 {
-    __shared__ float tile[SB * 256];
+    __shared__ float tile[SB * W];
     return tile;
 }
 
@@ -66,17 +68,21 @@ __device__ __forceinline__ void store_entry(float *p, float v)
 }
 
 // KEEP: observed entries (mask != 0) keep A_ij (the missing-only form).
-// FLAT: the table is contiguous (ldh == n) and n <= 256: rows go through LDS
-// and out as one flat, line-aligned range per SB rows.
-template <int K, bool KEEP, bool FLAT>
-__global__ __launch_bounds__(256) void impute_kernel(ImputeArgs a, const float *__restrict__ X,
+// FW: 0 for direct stores (workgroups of 256 columns); otherwise the table is
+// contiguous (ldh == n) with n <= 64 FW, a workgroup of FW wavefronts spans a
+// row, and rows go through LDS and out as one flat, line-aligned range per SB
+// rows.
+template <int K, bool KEEP, int FW>
+__global__ __launch_bounds__(FW == 0 ? 256 : 64 * FW) void impute_kernel(ImputeArgs a, const float *__restrict__ X,
                                                      const float *__restrict__ Y, const float *__restrict__ A,
                                                      const uint8_t *__restrict__ mask, float *__restrict__ out)
 {
     constexpr bool NT = !KEEP;
+    constexpr bool FLAT = FW != 0;
+    constexpr int TB = FLAT ? 64 * FW : 256;   // threads per workgroup
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t ncb = (a.n + 255) >> 8;
+    const int64_t ncb = FLAT ? 1 : (a.n + 255) >> 8;
     const int64_t cb = blockIdx.x % ncb, chunk = blockIdx.x / ncb;
     const int64_t j = cb * 256 + w * 64 + lane;
     const bool live = j < a.n;
@@ -124,7 +130,7 @@ __global__ __launch_bounds__(256) void impute_kernel(ImputeArgs a, const float *
                 float v = decode_entry(u, kind, levels);
                 if constexpr (KEEP) v = obs[r] != 0 ? av[r] : v;
                 if constexpr (FLAT) {
-                    if (live) stage_tile()[(i - sb) * a.n + j] = v;
+                    if (live) stage_tile<TB>()[(i - sb) * a.n + j] = v;
                 } else {
                     if (live) store_entry<NT>(&out[i * a.ldh + j], v);
                 }
@@ -139,11 +145,11 @@ __global__ __launch_bounds__(256) void impute_kernel(ImputeArgs a, const float *
         }
         if constexpr (FLAT) {
             // the staged rows are out[sb * n, se * n): store it from the line
-            // that holds its first entry, 256 consecutive entries per pass
+            // that holds its first entry, TB consecutive entries per pass
             lds_barrier();
             const int64_t f0 = sb * a.n, f1 = se * a.n;
-            for (int64_t t = (f0 & ~(int64_t)31) + threadIdx.x; t < f1; t += 256)
-                if (t >= f0) store_entry<NT>(&out[t], stage_tile()[t - f0]);
+            for (int64_t t = (f0 & ~(int64_t)31) + threadIdx.x; t < f1; t += TB)
+                if (t >= f0) store_entry<NT>(&out[t], stage_tile<TB>()[t - f0]);
             lds_barrier();
         }
     }
@@ -162,12 +168,34 @@ __global__ __launch_bounds__(256) void scatter_observed_kernel(int64_t nnz, int6
     if (r >= 0 && r < m && c >= 0 && c < n) out[r * ldh + c] = val[e];
 }
 
+// The launch form: staged only where rows do not start on line boundaries
+// (aligned rows measured faster stored directly), and only while one
+// workgroup spans a row.
+static int flat_waves(const ImputeArgs &a)
+{
+    if (a.ldh != a.n || (a.n % 32) == 0 || a.n > 1024) return 0;
+    return a.n <= 256 ? 4 : 16;
+}
+
 int impute_rows_per_block(int64_t m, int64_t n)
 {
-    // about eight workgroups per CU over the whole table, at least 16 rows each
+    // about eight 256-thread workgroups per CU over the whole table (as many
+    // threads with the wider ones), at least 16 rows each
     const int64_t ncb = (n + 255) / 256;
     const int64_t chunks = std::max<int64_t>(1, (IMPUTE_TARGET_BLOCKS + ncb - 1) / ncb);
     return (int)std::max<int64_t>(16, (m + chunks - 1) / chunks);
+}
+
+template <int K, bool KEEP, int FW>
+static void launch_form(const ImputeArgs &a, const float *X, const float *Y, const float *A, const uint8_t *mask,
+                        float *out, hipStream_t st)
+{
+    // a staged workgroup spans all of a row's 256-column blocks, so a chunk of
+    // rows is one workgroup of as many threads
+    const int64_t ncb = FW == 0 ? (a.n + 255) / 256 : 1;
+    const int64_t chunks = (a.m + a.rows_per_block - 1) / a.rows_per_block;
+    hipLaunchKernelGGL((impute_kernel<K, KEEP, FW>), dim3((unsigned)(ncb * chunks)), dim3(FW == 0 ? 256 : 64 * FW), 0,
+                       st, a, X, Y, A, mask, out);
 }
 
 // One instance per rank, so a row of X is a fixed run of scalar loads.
@@ -175,17 +203,15 @@ template <int K>
 static hipError_t launch_k(const ImputeArgs &a, const float *X, const float *Y, const float *A, const uint8_t *mask,
                            float *out, hipStream_t st)
 {
-    const int64_t ncb = (a.n + 255) / 256, chunks = (a.m + a.rows_per_block - 1) / a.rows_per_block;
-    const dim3 grid((unsigned)(ncb * chunks));
-    // staged only where rows do not start on line boundaries: aligned rows
-    // measured faster stored directly
-    const bool flat = a.ldh == a.n && a.n <= 256 && (a.n % 32) != 0;
+    const int fw = flat_waves(a);
     if (a.keep_observed) {
-        if (flat) hipLaunchKernelGGL((impute_kernel<K, true, true>), grid, dim3(256), 0, st, a, X, Y, A, mask, out);
-        else hipLaunchKernelGGL((impute_kernel<K, true, false>), grid, dim3(256), 0, st, a, X, Y, A, mask, out);
+        if (fw == 4) launch_form<K, true, 4>(a, X, Y, A, mask, out, st);
+        else if (fw == 16) launch_form<K, true, 16>(a, X, Y, A, mask, out, st);
+        else launch_form<K, true, 0>(a, X, Y, A, mask, out, st);
     } else {
-        if (flat) hipLaunchKernelGGL((impute_kernel<K, false, true>), grid, dim3(256), 0, st, a, X, Y, A, mask, out);
-        else hipLaunchKernelGGL((impute_kernel<K, false, false>), grid, dim3(256), 0, st, a, X, Y, A, mask, out);
+        if (fw == 4) launch_form<K, false, 4>(a, X, Y, A, mask, out, st);
+        else if (fw == 16) launch_form<K, false, 16>(a, X, Y, A, mask, out, st);
+        else launch_form<K, false, 0>(a, X, Y, A, mask, out, st);
     }
     return hipGetLastError();
 }
