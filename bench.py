@@ -240,9 +240,16 @@ def cpu_baseline(case, rows, sweeps):
     for _ in range(sweeps):
         P.sweep(X, Y, ax, ay)
     dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), cpu)
+    except OSError:
+        pass
     return dict(value=P.nnz * sweeps / dt, unit="entries/s", cores=1, kind="oracle",
                 sample="first %d of %d rows (%d observed entries), %d sweep(s) of the FP64 oracle, "
-                       "single thread, %.1f s" % (rows, case.m, P.nnz, sweeps, dt))
+                       "single thread, %.1f s" % (rows, case.m, P.nnz, sweeps, dt),
+                cpu=cpu, host_cpus=os.cpu_count())
 
 
 def main():

@@ -82,6 +82,7 @@ CASES = [
     dict(m=130, n=517, k=20, seed=4),       # three column blocks, rank of the benchmark
     dict(m=77, n=64, k=64, seed=5),         # largest rank
     dict(m=1000, n=40, k=33, seed=6),       # many rows per workgroup, odd rank
+    dict(m=50, n=1000, k=64, seed=10),      # unaligned rows of a 16-wavefront workgroup, largest rank
 ]
 
 
