@@ -12,9 +12,9 @@
 // runs one workgroup per row width (4 wavefronts up to 256 columns, 16 up to
 // 1024), so the workgroup stages SB rows in LDS and stores their flat range
 // with line-aligned wavefront stores; other tables store each row's 64 columns
-// per wavefront directly, in workgroups of 256 columns.  The every-entry form stores non-temporally (the table is
-// not read back here); the missing-only form measured faster with plain
-// stores.
+// per wavefront directly, in workgroups of 256 columns.  The every-entry form
+// stores non-temporally (the table is not read back here); the missing-only
+// form measured faster with plain stores.
 #include <algorithm>
 #include <utility>
 
