@@ -505,39 +505,18 @@ constexpr int RG = 20;
 template <int KP>
 constexpr int RF = 4 * NWX_OF<KP> + 4;
 
-// Where the row pass issues the next panel's loads.  The bf16 forms spread
-// them over the trial-row loop (S5), so the fetch overlaps S5, the decisions
-// and S6; the FP32 form, whose longer products keep the matrix cores busy in
-// S5, issues them all at the start of S6.
-template <int PREC>
-constexpr bool STAGE_IN_S5 = PREC != P_FP32;
-
-// The row pass's barriers inside a panel: LDS-only where the prefetch is in
-// flight across them (bf16 forms), full otherwise.
-template <int PREC>
-__device__ __forceinline__ void panel_barrier()
-{
-    if constexpr (STAGE_IN_S5<PREC>) lds_barrier();
-    else __syncthreads();
-}
-
-// The two panel buffers of the row pass.  FP32 keeps them in the shared
-// struct and a panel picks its buffer by index.  The bf16 forms, whose
-// prefetch is in flight while the panel reads LDS, keep them as LDS objects
-// of their own and hand them to the panel as restrict pointers: the compiler
-// then knows the loads into one buffer cannot alias the panel's other LDS
-// traffic, and issues no wait for them before those reads.  (With the FP32
-// form's tighter register budget the pointer version spills; the indexed one
-// does not.)
-template <int KP, int TPW, bool INSIDE>
-struct XStepBufs {};
-template <int KP, int TPW>
-struct XStepBufs<KP, TPW, true> {
-    PanelBuf<KP, TPW, NWX_OF<KP>> buf0, buf1;
-};
-
+// Where the row pass issues the next panel's loads: the X rows and step sizes
+// at the start of S4, the tiles one per step of the trial-row loop (S5), so
+// the fetch overlaps S5, the decisions and S6.  Its barriers inside a panel
+// therefore wait on LDS only (lds_barrier).  The two panel buffers are LDS
+// objects of their own, handed to the panel as restrict pointers: the
+// compiler then knows the loads into one buffer cannot alias the panel's other
+// LDS traffic, and issues no wait for them before those reads.  (The FP32 form
+// once issued all its loads at the start of S6 instead; once S6's transposed
+// reads no longer waited for the prefetch, this placement measured 5 % faster
+// for it too.)
 template <int KP, int TPW, int PREC>
-struct XStepShared : XStepBufs<KP, TPW, !STAGE_IN_S5<PREC>> {
+struct XStepShared {
     float xs[16][RS<KP>];    // the accepted rows (S6 operand)
     float xp[16][RS<KP>];    // trial rows
     // row-gradient partials (S3 -> S4), [wavefront][coordinate][row]: a lane's
@@ -555,25 +534,15 @@ struct XStepShared : XStepBufs<KP, TPW, !STAGE_IN_S5<PREC>> {
     int s_rej[NWX_OF<KP>];
 };
 
-template <int KP, int TPW, int PREC, int BUF>
-__device__ __forceinline__ PanelBuf<KP, TPW, NWX_OF<KP>> &panel_buf(XStepShared<KP, TPW, PREC> &sh,
-                                                                   PanelBuf<KP, TPW, NWX_OF<KP>> *pb0,
-                                                                   PanelBuf<KP, TPW, NWX_OF<KP>> *pb1)
-{
-    if constexpr (STAGE_IN_S5<PREC>) return BUF == 0 ? *pb0 : *pb1;
-    else return BUF == 0 ? sh.buf0 : sh.buf1;
-}
-
 // S6 of one panel.  z comes from
 // X . Y^T, so each lane holds rows 4g + r of column li: the loss derivatives
 // are then already the transposed operand of dY += G^T . X, and the column
 // objective of column li is a sum over the lane's four rows (the four lane
-// groups are added once, at the end of the launch).  The FP32 form issues the
-// next panel's loads here; the LDS operands come in as restrict pointers so
-// that the compiler can tell those loads apart from the reads below.
+// groups are added once, at the end of the launch).  The LDS operands come in
+// as restrict pointers so that the compiler can tell the next panel's loads,
+// in flight, apart from the reads below.
 template <int KP, int TPW, int PREC, int LK>
-__device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ nxt,
-                                         int64_t p_next, const float4 *__restrict__ apan,
+__device__ __forceinline__ void xstep_s6(const XStepArgs &a, const float4 *__restrict__ apan,
                                          const LossTab *__restrict__ lt, const uint8_t *__restrict__ s_codes,
                                          const int8_t *__restrict__ s_tcode, const Frag<KP, PREC> (&yfr)[TPW],
                                          const XatFrag<KP, PREC> &xa, const Frag<KP, PREC> &xaf,
@@ -582,10 +551,6 @@ __device__ __forceinline__ void xstep_s6(const XStepArgs &a, PanelBuf<KP, TPW, N
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     const int nt = (int)(a.ldp / 16);
-    // (FP32) the next panel's loads, all at once: no product is in flight yet
-    if constexpr (!STAGE_IN_S5<PREC>)
-        if (p_next >= 0)
-            stage_panel<KP, TPW, NWX_OF<KP>, true>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
     // software pipelined: tile s + 1's entries and product are issued before
     // tile s's losses (slots past the last tile compute on stale entries and
     // are skipped), and each tile's work sits behind a uniform branch, since
@@ -630,8 +595,8 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     constexpr int C = KP / 4;
     const int nt = (int)(a.ldp / 16);
     const int k = a.k;
-    PanelBuf<KP, TPW, NWX_OF<KP>> &cur = panel_buf<KP, TPW, PREC, BUF>(sh, pb0, pb1);
-    PanelBuf<KP, TPW, NWX_OF<KP>> &nxt = panel_buf<KP, TPW, PREC, 1 - BUF>(sh, pb0, pb1);
+    PanelBuf<KP, TPW, NWX_OF<KP>> &cur = BUF == 0 ? *pb0 : *pb1;
+    PanelBuf<KP, TPW, NWX_OF<KP>> &nxt = BUF == 0 ? *pb1 : *pb0;
     const float4 *apan = cur.apan[w];
     const int64_t i0 = p * 16;
     const int rows = (int)min<int64_t>(16, a.m - i0);
@@ -679,15 +644,13 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
 #pragma unroll
     for (int kb = 0; kb < KP / 16; ++kb)
         *reinterpret_cast<f32x4 *>(&sh.red_g[w][16 * kb + li][4 * g]) = dx[kb];
-    panel_barrier<PREC>();
+    lds_barrier();
 
     // ---- S4: prox step and regularizer values ------------------------------------
-    // (bf16 forms) the next panel's X rows and step sizes go out first; no
-    // matrix-core product is in flight here.  Then every LDS read
-    // (unconditional: the indexes stay inside the arrays), one wait, then the
-    // arithmetic.
-    if constexpr (STAGE_IN_S5<PREC>)
-        if (p_next >= 0) stage_rows<KP, TPW, NWX_OF<KP>>(nxt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
+    // the next panel's X rows and step sizes go out first; no matrix-core
+    // product is in flight here.  Then every LDS read (unconditional: the
+    // indexes stay inside the arrays), one wait, then the arithmetic.
+    if (p_next >= 0) stage_rows<KP, TPW, NWX_OF<KP>>(nxt, a.X, a.m, a.k, a.alpha, p_next, w, lane);
     if (threadIdx.x < 256) {
         constexpr int Q = KP / 16;
         const float al0 = cur.alpha[ri];
@@ -720,14 +683,13 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             sh.s_rxp[ri] = rcp;
         }
     }
-    panel_barrier<PREC>();
+    lds_barrier();
 
     // ---- S5: row objective at the trial rows ---------------------------------------
     Frag<KP, PREC> xpf;
     frag_from_f32<KP, PREC>(xpf, &sh.xp[li][g * C]);
     float fppart = 0.0f;
-    // (bf16 forms) the next panel's tiles are issued one per step of this
-    // loop.  The issue is unconditional (without a next panel it reloads this
+    // the next panel's tiles are issued one per step of this loop.  The issue is unconditional (without a next panel it reloads this
     // panel into the idle buffer): a branch between a matrix-core product and
     // the read of its result lets the taken path skip the wait states the
     // read needs.
@@ -739,7 +701,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         const int t = w + NWX_OF<KP> * s;
         const f32x4 zp = zn2;
         const float4 av = an2;
-        if constexpr (STAGE_IN_S5<PREC>) stage_tile<KP, TPW, NWX_OF<KP>, true>(nxt, a.Ap, a.ldp, nt, p_src, w, lane, s);
+        stage_tile<KP, TPW, NWX_OF<KP>, true>(nxt, a.Ap, a.ldp, nt, p_src, w, lane, s);
         if (s + 1 < TPW) {
             zn2 = zprod<KP, PREC>(yfr[s + 1], xpf);
             an2 = apan[(s + 1) * 64 + tile_slot<true>(lane)];
@@ -750,7 +712,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         fppart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
     }
     sh.red_fp[li][4 * w + g] = fppart;
-    panel_barrier<PREC>();
+    lds_barrier();
 
     // ---- decision per row and the accepted rows ---------------------------------------
     if (threadIdx.x < 256) {
@@ -793,14 +755,14 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             rej_acc += acc ? 0 : 1;
         }
     }
-    panel_barrier<PREC>();
+    lds_barrier();
 
     // ---- S6: column objective and Y gradient from the accepted rows -------------------
     XatFrag<KP, PREC> xa;
     xatfrag_load<KP, PREC>(xa, sh.xat, li, g);
     Frag<KP, PREC> xaf;
     frag_from_f32<KP, PREC>(xaf, &sh.xs[li][g * C]);
-    xstep_s6<KP, TPW, PREC, LK>(a, &nxt, p_next, apan, &sh.lt, sh.s_codes, sh.s_tcode, yfr, xa, xaf, dyacc, hacc);
+    xstep_s6<KP, TPW, PREC, LK>(a, apan, &sh.lt, sh.s_codes, sh.s_tcode, yfr, xa, xaf, dyacc, hacc);
 }
 
 // Waves per SIMD the row pass is compiled for.  Narrow tables (few tiles per
@@ -815,11 +777,10 @@ __global__ __launch_bounds__(NTX_OF<KP>, (XSTEP_MIN_WAVES<KP, TPW>)) void xstep_
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     __shared__ XStepShared<KP, TPW, PREC> sh;
-    // the bf16 forms' panel buffers (unused, and so not allocated, in FP32)
+    // the panel buffers, LDS objects of their own
     __shared__ PanelBuf<KP, TPW, NWX_OF<KP>> sbuf0;
     __shared__ PanelBuf<KP, TPW, NWX_OF<KP>> sbuf1;
-    PanelBuf<KP, TPW, NWX_OF<KP>> *pb0 = nullptr, *pb1 = nullptr;
-    if constexpr (STAGE_IN_S5<PREC>) { pb0 = &sbuf0; pb1 = &sbuf1; }
+    PanelBuf<KP, TPW, NWX_OF<KP>> *const pb0 = &sbuf0, *const pb1 = &sbuf1;
     const int nt = (int)(a.ldp / 16);
     const int64_t npanels = a.mp / 16;
     const int64_t G = gridDim.x;
@@ -849,7 +810,7 @@ __global__ __launch_bounds__(NTX_OF<KP>, (XSTEP_MIN_WAVES<KP, TPW>)) void xstep_
     int rej_acc = 0;
 
     if (blockIdx.x < npanels)
-        stage_panel<KP, TPW, NWX_OF<KP>, true>(panel_buf<KP, TPW, PREC, 0>(sh, pb0, pb1), a.Ap, a.ldp, nt, a.X, a.m, a.k,
+        stage_panel<KP, TPW, NWX_OF<KP>, true>(*pb0, a.Ap, a.ldp, nt, a.X, a.m, a.k,
                                          a.alpha, blockIdx.x, w, lane);
     for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
         const int64_t p1 = p + G, p2 = p + 2 * G;
