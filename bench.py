@@ -270,7 +270,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the GLRM sweep here is built and measured on a single MI355X "
-              "(the multi-GPU row sharding is a design in DESIGN.md, not built); run with --gpus 1",
+              "(the multi-GPU row sharding is designed, not built); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
