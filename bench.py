@@ -24,7 +24,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "xstep_counters_dense_quadratic.txt")
-IMPUTE_COUNTERS = os.path.join(ROOT, "profiles", "impute_counters_heterogeneous.txt")
+IMPUTE_COUNTERS = {"impute": os.path.join(ROOT, "profiles", "impute_counters_heterogeneous.txt"),
+                   "impute_dense": os.path.join(ROOT, "profiles", "impute_counters_dense_quadratic.txt")}
 
 
 def log(*a):
@@ -77,6 +78,8 @@ def workload(name):
         return synth.autograd_point()
     if name == "impute":
         return synth.heterogeneous()
+    if name == "impute_dense":
+        return synth.dense_quadratic()
     raise SystemExit("unknown workload " + name)
 
 
@@ -259,7 +262,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dense_quadratic",
                     choices=["dense_quadratic", "heterogeneous", "sparse_completion", "plain_pca", "autograd",
-                             "impute"])
+                             "impute", "impute_dense"])
     ap.add_argument("--precision", default="both", choices=["both", "bf16", "fp32", "bf16_plain"])
     ap.add_argument("--cpu-rows", type=int, default=100000)
     ap.add_argument("--cpu-sweeps", type=int, default=2)
@@ -282,15 +285,16 @@ def main():
         precisions = ["fp32"]
     else:
         precisions = ["bf16", "fp32"] if args.precision == "both" else [args.precision]
-    if args.workload == "impute":
+    if args.workload in ("impute", "impute_dense"):
         res = run_impute(case, args.steps, args.warmup)
         if args.copy_calibration:
             copy_calibration()
         r = res["all"]
         traffic = {}
-        if os.path.exists(IMPUTE_COUNTERS):
+        counters = IMPUTE_COUNTERS[args.workload]
+        if os.path.exists(counters):
             try:
-                pc = dict(l.split(":", 1) for l in open(IMPUTE_COUNTERS).read().splitlines() if ":" in l)
+                pc = dict(l.split(":", 1) for l in open(counters).read().splitlines() if ":" in l)
                 pc = {k.strip(): v.strip() for k, v in pc.items()}
                 if pc.get("kernel_source_hash") == kernel_source_hash(unit="impute") and case.name in pc.get("kernel", ""):
                     traffic = {"all": float(pc["traffic_bytes_per_launch_all"]),
