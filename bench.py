@@ -183,7 +183,7 @@ def run_grad(case, precisions, steps, warmup):
 
 
 def run_impute(case, steps, warmup):
-    """One step = one decoded table (glrm_impute, Section 5.4) from the case's
+    """One step = one decoded table (glrm_impute, Section 5.3) from the case's
     seeded starting factors (the pass's work and data movement do not depend on
     their values), in each of the two forms; HIP events on the stream the calls
     run on bracket the timed calls."""
@@ -302,7 +302,7 @@ def main():
             except (OSError, ValueError, KeyError):
                 traffic = {}
         line = {
-            "metric": "table entries decoded/s (Section 5.4 imputation)",
+            "metric": "table entries decoded/s (Section 5.3 imputation)",
             "value": r["value"], "unit": "entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32", "data": "synthetic",

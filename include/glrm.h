@@ -47,13 +47,13 @@ extern "C" {
 #define GLRM_ENOMEM       -3  /* workspace smaller than glrm_workspace_size() */
 #define GLRM_EHIP         -4  /* a HIP runtime call failed; the message names it */
 
-/* ---- loss kinds (Section 4 and Section 5.1) ----------------------------------
+/* ---- loss kinds (Section 4 and Section 5.2) ----------------------------------
  *  QUADRATIC  (a - u)^2                              eq. qpca
  *  HUBER      huber(u - a) with threshold `param`:   Section 4.2 ("Huber PCA",
  *             0.5 r^2 if |r| <= param else           the paper fixes param = 1)
  *             param |r| - 0.5 param^2
- *  LOGISTIC   log(1 + exp(-a u)), a in {-1, +1}      Section 5.1 ("Logistic PCA")
- *  HINGE      max(0, 1 - a u),     a in {-1, +1}      Section 5.1 ("Boolean PCA")
+ *  LOGISTIC   log(1 + exp(-a u)), a in {-1, +1}      Section 5.2 ("Logistic PCA")
+ *  HINGE      max(0, 1 - a u),     a in {-1, +1}      Section 5.2 ("Boolean PCA")
  *  ORDINAL    sum_{a'<a} (1 - u + a')_+ +            eq. ord-pca, a in {1..levels}
  *             sum_{a'>a} (1 + u - a')_+
  * The derivative used at a kink is the strict-inequality branch (the kink
@@ -214,10 +214,10 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
              void *ws, size_t ws_bytes, void *stream);
 
 /* Imputation modes. */
-#define GLRM_IMPUTE_ALL     0  /* decode every entry: the denoised table (end of Section 5.4) */
+#define GLRM_IMPUTE_ALL     0  /* decode every entry: the denoised table (end of Section 5.3) */
 #define GLRM_IMPUTE_MISSING 1  /* observed entries keep A_ij; only the missing ones are decoded */
 
-/* The decoded table of Section 5.4, Ahat_ij = argmin over the data domain of
+/* The decoded table of Section 5.3, Ahat_ij = argmin over the data domain of
  * L_j(x_i . y_j, a):
  *   QUADRATIC, HUBER   x_i . y_j (losses over the reals are smallest at a = u)
  *   LOGISTIC, HINGE    +1 if x_i . y_j > 0, else -1 (at 0 both values tie and

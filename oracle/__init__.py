@@ -65,6 +65,8 @@ def lib():
         L.oracle_loss_sum.argtypes = [P, P, P]
         L.oracle_loss_grad_rows.restype = None
         L.oracle_loss_grad_rows.argtypes = [P, P, P, P]
+        L.oracle_loss_grad_abs_rows.restype = None
+        L.oracle_loss_grad_abs_rows.argtypes = [P, P, P, P]
         L.oracle_half_step.restype = I64
         L.oracle_half_step.argtypes = [P, P, P, P, I32, D, D, D, P, P, P, P]
         L.oracle_init_alpha.restype = None
@@ -101,13 +103,13 @@ def dloss(kind, u, a, levels=0, param=1.0):
 
 
 def decode(kind, u, levels=0, param=1.0):
-    """argmin over the loss's data domain of L(u, a) (Section 5.4)."""
+    """argmin over the loss's data domain of L(u, a) (Section 5.3)."""
     L = _Loss(kind, levels, param)
     return lib().oracle_decode(ctypes.byref(L), float(u))
 
 
 def impute(X, Y, col_loss, losses, A=None, mask=None):
-    """The decoded table a_hat_ij = argmin_a L_j(x_i . y_j, a) (Section 5.4).
+    """The decoded table a_hat_ij = argmin_a L_j(x_i . y_j, a) (Section 5.3).
 
     X is m x k, Y is n x k; ``col_loss`` gives each column's index into
     ``losses`` (None = all 0).  With ``mask`` (m x n bool) the observed entries
@@ -234,6 +236,16 @@ class Problem:
         lib().oracle_loss_grad_rows(ctypes.byref(self.row.s), _ptr(X), _ptr(Y), _ptr(dX))
         lib().oracle_loss_grad_rows(ctypes.byref(self.colv.s), _ptr(Y), _ptr(X), _ptr(dY))
         return dX, dY
+
+    def grad_abs(self, X, Y):
+        """Sums of the absolute gradient terms, sum_j |dL_ij| |y_j| (m x k) and
+        sum_i |dL_ij| |x_i| (n x k): the scale of a gradient's rounding error."""
+        X, Y = _f64(X), _f64(Y)
+        aX = np.empty_like(X)
+        aY = np.empty_like(Y)
+        lib().oracle_loss_grad_abs_rows(ctypes.byref(self.row.s), _ptr(X), _ptr(Y), _ptr(aX))
+        lib().oracle_loss_grad_abs_rows(ctypes.byref(self.colv.s), _ptr(Y), _ptr(X), _ptr(aY))
+        return aX, aY
 
     def init_alpha(self, s=1.0):
         ax = np.empty(self.m)

@@ -48,7 +48,7 @@ typedef struct {
 
 static double pos(double t) { return t > 0.0 ? t : 0.0; }
 
-/* ---- losses, value (Section 4 and Section 5.1 / 5.3) ----------------------- */
+/* ---- losses, value (Section 4 and Section 5.2) ----------------------- */
 double oracle_loss(const oracle_loss_t *L, double u, double a)
 {
     switch (L->kind) {
@@ -177,6 +177,24 @@ void oracle_loss_grad_rows(const oracle_problem_t *P, const double *U, const dou
     }
 }
 
+/* Sum of the absolute terms of that gradient, dU_i = sum_j |dL(u_i . v_j, A_ij)| |v_j|
+ * (coordinate-wise).  Not part of the method: it scales the rounding bound
+ * of a gradient computed in finite precision, which the tests use to tell a
+ * decision that rounding may flip from one that it cannot. */
+void oracle_loss_grad_abs_rows(const oracle_problem_t *P, const double *U, const double *V, double *dU)
+{
+    const int32_t k = P->k;
+    for (int64_t i = 0; i < P->m; ++i) {
+        double *g = dU + i * k;
+        for (int c = 0; c < k; ++c) g[c] = 0.0;
+        for (int64_t e = P->row_ptr[i]; e < P->row_ptr[i + 1]; ++e) {
+            const double *v = V + (int64_t)P->col[e] * k;
+            double d = fabs(oracle_dloss(&P->losses[P->ecode[e]], dot(U + i * k, v, k), P->val[e]));
+            for (int c = 0; c < k; ++c) g[c] += d * fabs(v[c]);
+        }
+    }
+}
+
 /*
  * One half-step of Algorithm 2 with the proximal gradient update and the
  * per-row step-size rule of Section 7.2 ("Choosing a step size"):
@@ -184,6 +202,7 @@ void oracle_loss_grad_rows(const oracle_problem_t *P, const double *U, const dou
  *   g    = sum_j dL(u_i . v_j, A_ij) v_j
  *   u+   = prox_{alpha_i r}(u_i - alpha_i g)
  *   f+   = sum_j L(u+ . v_j, A_ij) + r(u+)
+ *   (f+ = +inf when u+ has a non-finite coordinate)
  *   f+ <= f : keep u+ and multiply alpha_i by step_up
  *   else    : keep u_i and multiply alpha_i by step_down
  * Rows are independent.  Returns the number of rejected rows.  f_old / f_new
@@ -208,6 +227,11 @@ int64_t oracle_half_step(const oracle_problem_t *P, double *U, const double *V, 
         for (int c = 0; c < k; ++c) up[c] = u[c] - alpha[i] * g[c];
         oracle_prox(reg_kind, reg_w, alpha[i], up, k);
         double fp = row_loss(P, i, up, V) + oracle_reg(reg_kind, reg_w, up, k);
+        /* the factors range over the reals (Section 2.1): a trial point with an
+         * infinite or NaN coordinate (a step size that overflowed) is outside
+         * the problem's domain, so its objective counts as +inf */
+        for (int c = 0; c < k; ++c)
+            if (!isfinite(up[c])) fp = INFINITY;
         int acc = (fp <= f);
         if (acc) {
             for (int c = 0; c < k; ++c) u[c] = up[c];
@@ -250,7 +274,7 @@ double oracle_objective(const oracle_problem_t *P, const double *X, const double
          + oracle_reg_sum(ry_kind, ry_w, Y, P->n, P->k);
 }
 
-/* ---- imputation (Section 5.4): the entry of the column's data domain whose
+/* ---- imputation (Section 5.3): the entry of the column's data domain whose
  * loss at u = x_i . y_j is smallest, a_hat = argmin_a L_j(u, a).  The
  * quadratic and Huber losses are defined for every real a and are smallest at
  * a = u, which the paper states as the decoded value for them.  The Boolean

@@ -295,7 +295,7 @@ def glrm_fit(data, X, Y, alpha_x, alpha_y, max_sweeps, precision=BF16, init_alph
 
 
 def glrm_impute(data, X, Y, mode=IMPUTE_ALL, out=None, flags=0, stream=None):
-    """The decoded table of Section 5.4 (m x n float32): every entry, or with
+    """The decoded table of Section 5.3 (m x n float32): every entry, or with
     ``mode=IMPUTE_MISSING`` only the missing ones (observed entries keep A).
     ``out`` may be a row-strided m x n float32 view (stride (ldh, 1))."""
     torch = _torch()

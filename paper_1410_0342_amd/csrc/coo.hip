@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
                 const bool in = 4 * q + s < a.k;
                 xp[s] = in ? prox_elem(a.reg, al, xv[s] - al * gv[s]) : 0.0f;
                 rc += in ? reg_elem(a.reg, xv[s]) : 0.0f;
-                rcp += in ? reg_elem(a.reg, xp[s]) : 0.0f;
+                rcp += in ? reg_elem_trial(a.reg, xp[s]) : 0.0f;
             }
             rc = group_sum<L>(rc);
             rcp = group_sum<L>(rcp);

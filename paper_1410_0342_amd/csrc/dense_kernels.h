@@ -362,11 +362,12 @@ __device__ __forceinline__ void tile4(int lev, float par, const f32x4 &z, const 
         return;
     }
     if constexpr (K == L_QUAD && !WANT_G) {
-        // NaN propagates into d * d and the IEEE maximum with 0 drops it
+        // only an unobserved entry (NaN in the table) is masked; a NaN
+        // product keeps a NaN loss, so such a trial point is never accepted
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const float d = z[r] - a4[r];
-            l[r] = __builtin_fmaxf(d * d, 0.0f);
+            l[r] = a4[r] == a4[r] ? d * d : 0.0f;
             g[r] = 0.0f;
         }
         return;
@@ -674,7 +675,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             const float xv = ok ? prox_elem(a.rx, al, x - al * gq[q]) : 0.0f;
             sh.xp[ri][c] = xv;
             rc += ok ? reg_elem(a.rx, x) : 0.0f;
-            rcp += ok ? reg_elem(a.rx, xv) : 0.0f;
+            rcp += ok ? reg_elem_trial(a.rx, xv) : 0.0f;
         }
         rc = row16_sum(rc);
         rcp = row16_sum(rcp);
@@ -916,7 +917,7 @@ __global__ __launch_bounds__(64 * YPROX_SPLIT) void yprox_kernel(YProxArgs a)
         }
     }
     float rc = (valid && c < a.k) ? reg_elem(a.ry, y) : 0.0f;
-    float rcp = (valid && c < a.k) ? reg_elem(a.ry, yv) : 0.0f;
+    float rcp = (valid && c < a.k) ? reg_elem_trial(a.ry, yv) : 0.0f;
     rc = sum_lanes<KP>(rc);
     rcp = sum_lanes<KP>(rcp);
     h = sum_lanes<KP>(h);

@@ -2,7 +2,7 @@
 // derivatives, regularizers, proximal operators, bfloat16 splitting, the
 // matrix-core fragment products and wavefront reductions.
 //
-// Losses: Section 4 (quadratic eq. qpca, Huber), Section 5.1 (hinge, logistic,
+// Losses: Section 4 (quadratic eq. qpca, Huber), Section 5.2 (hinge, logistic,
 // ordinal hinge eq. ord-pca).  Regularizers: Section 3.  Proximal operators:
 // definition in Section 7.2.  At a kink the derivative takes the
 // strict-inequality branch (the kink contributes 0).
@@ -102,8 +102,9 @@ __device__ __forceinline__ void loss_lg_k(int levels, float param, float u, floa
         l = fmaxf(t, 0.0f) + log1p_unit(e);
         g = -a * (t >= 0.0f ? inv : e * inv);
     } else if constexpr (K == L_HINGE) {
+        // written so that a NaN product gives a NaN loss (never a zero one)
         const float au = a * u;
-        if (au < 1.0f) { l = 1.0f - au; g = -a; }
+        if (!(au >= 1.0f)) { l = 1.0f - au; g = -a; }
         else { l = 0.0f; g = 0.0f; }
     } else {
         ordinal_loss<float>(u, a, levels, l, g, true);
@@ -124,7 +125,7 @@ __device__ __forceinline__ float loss_l_k(int levels, float param, float u, floa
         return fmaxf(t, 0.0f) + log1p_unit(exp_neg_abs(t));
     } else if constexpr (K == L_HINGE) {
         const float au = a * u;
-        return au < 1.0f ? 1.0f - au : 0.0f;
+        return !(au >= 1.0f) ? 1.0f - au : 0.0f;
     } else {
         float l, g;
         ordinal_loss<float>(u, a, levels, l, g, false);
@@ -173,7 +174,7 @@ __device__ __forceinline__ double loss_l64(int kind, int levels, double param, d
     }
     case L_HINGE: {
         double au = a * u;
-        return au < 1.0 ? 1.0 - au : 0.0;
+        return !(au >= 1.0) ? 1.0 - au : 0.0;
     }
     default: {
         double l, g;
@@ -204,6 +205,15 @@ __device__ __forceinline__ double reg_elem64(const Reg &r, double x)
     case R_NONNEG: return x < 0.0 ? __builtin_huge_val() : 0.0;
     default: return 0.0;
     }
+}
+
+// A trial point's share of r(x) with the step gate folded in: r(x) plus
+// 0 * x, which is exactly r(x) for a finite coordinate and NaN for an
+// infinite or NaN one, so a trial objective built from it is NaN and the
+// step is rejected (a non-finite point lies outside the model's domain).
+__device__ __forceinline__ float reg_elem_trial(const Reg &r, float x)
+{
+    return reg_elem(r, x) + 0.0f * x;
 }
 
 // prox_{alpha r}(v), coordinate-wise (every supported r is separable).

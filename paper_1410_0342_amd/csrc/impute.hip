@@ -1,4 +1,4 @@
-// Imputation (Section 5.4): every entry of the table decoded from the fitted
+// Imputation (Section 5.3): every entry of the table decoded from the fitted
 // factors, a_hat_ij = argmin over the column's data domain of L_j(x_i . y_j, a).
 //
 // The pass is bound by its m x n store.  Each lane owns one column j and keeps

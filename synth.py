@@ -11,6 +11,7 @@ pattern, 3 = starting point, 4 = sampled coordinates.
 Loss kinds: 0 quadratic, 1 Huber, 2 logistic, 3 hinge, 4 ordinal hinge.
 Regularizer kinds: 0 zero, 1 quadratic, 2 l1, 3 nonnegative.
 """
+import os
 from dataclasses import dataclass, field
 from typing import List, Optional, Tuple
 
@@ -164,38 +165,77 @@ def autograd_point(m=50_000, n=2_000, k=64, missing=0.1, config=4):
 
 
 def sparse_completion(m=2_000_000, n=20_000, k=32, density=0.01, noise=0.05, gamma=1.0,
-                      sweeps=50, config=5):
+                      sweeps=50, config=5, threads=None):
     """Each row observes each column independently with probability ``density``
     (drawn as geometric gaps), values from a rank-k Gaussian model plus noise;
-    COO sorted by row then column, int32 indices."""
-    gf, gn, gp = rng(config, 0), rng(config, 1), rng(config, 2)
+    COO sorted by row then column, int32 indices.
+
+    Rows are drawn in fixed chunks of CHUNK rows, each from its own seeded
+    streams (pattern: ``rng(config, 2, c)``, noise: ``rng(config, 1, c)`` for
+    chunk c), so the chunks can be drawn on several threads and the result
+    does not depend on how many there are."""
+    import concurrent.futures as cf
+    import torch
+
+    gf = rng(config, 0)
     Xt = gf.standard_normal((m, k)).astype(np.float32)
     Yt = gf.standard_normal((n, k)).astype(np.float32)
-    rows_l, cols_l, vals_l = [], [], []
-    chunk = max(1, (1 << 24) // max(1, int(n * density * 3) + 8))
-    for r0 in range(0, m, chunk):
+    Xt_t, Yt_t = torch.from_numpy(Xt), torch.from_numpy(Yt)
+    chunk = 16384
+    mean = n * density
+    per = int(mean + 6.0 * np.sqrt(mean) + 16)   # gaps drawn per row up front
+
+    def draw(c):
+        r0 = c * chunk
         r1 = min(m, r0 + chunk)
         rr = r1 - r0
+        gp, gn = rng(config, 2, c), rng(config, 1, c)
         # geometric gaps give an exact Bernoulli(density) pattern per row
-        per = int(n * density * 2 + 64)
-        gaps = gp.geometric(density, size=(rr, per)).astype(np.int64)
-        pos = np.cumsum(gaps, axis=1) - 1
-        while True:
-            short = pos[:, -1] < n
-            if not short.any():
-                break
-            extra = gp.geometric(density, size=(rr, per)).astype(np.int64)
-            pos = np.concatenate([pos, pos[:, -1:] + np.cumsum(extra, axis=1)], axis=1)
+        pos = np.cumsum(gp.geometric(density, size=(rr, per)), axis=1, dtype=np.int64) - 1
+        short = np.nonzero(pos[:, -1] < n)[0]
+        rows_extra = {}
+        for i in short:   # rows whose gaps did not reach the end yet (rare)
+            p = [pos[i]]
+            last = p[0][-1]
+            while last < n:
+                more = last + np.cumsum(gp.geometric(density, size=per), dtype=np.int64)
+                p.append(more)
+                last = more[-1]
+            rows_extra[i] = np.concatenate(p)
         keep = pos < n
-        rr_idx = np.repeat(np.arange(r0, r1, dtype=np.int64), keep.sum(axis=1))
+        cnt = keep.sum(axis=1)
         cc = pos[keep]
-        v = np.einsum("ij,ij->i", Xt[rr_idx], Yt[cc]).astype(np.float32) + _normal32(gn, cc.size, noise)
-        rows_l.append(rr_idx.astype(np.int32))
-        cols_l.append(cc.astype(np.int32))
-        vals_l.append(v)
-    rows = np.concatenate(rows_l)
-    cols = np.concatenate(cols_l)
-    vals = np.concatenate(vals_l)
+        if rows_extra:
+            parts, counts = [], cnt.copy()
+            for i in range(rr):
+                if i in rows_extra:
+                    q = rows_extra[i]
+                    q = q[q < n]
+                    parts.append(q)
+                    counts[i] = q.size
+                else:
+                    parts.append(pos[i][keep[i]])
+            cc, cnt = np.concatenate(parts), counts
+        rr_idx = np.repeat(np.arange(r0, r1, dtype=np.int64), cnt)
+        with torch.no_grad():
+            v = (Xt_t.index_select(0, torch.from_numpy(rr_idx)) *
+                 Yt_t.index_select(0, torch.from_numpy(cc))).sum(1).numpy()
+        v = v + _normal32(gn, cc.size, noise)
+        return rr_idx.astype(np.int32), cc.astype(np.int32), v.astype(np.float32)
+
+    nchunks = (m + chunk - 1) // chunk
+    threads = threads or min(16, os.cpu_count() or 1)
+    torch_threads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+            out = list(ex.map(draw, range(nchunks)))
+    finally:
+        torch.set_num_threads(torch_threads)
+    rows = np.concatenate([o[0] for o in out])
+    cols = np.concatenate([o[1] for o in out])
+    vals = np.concatenate([o[2] for o in out])
+    del out
     g = rng(config, 3)
     return Case("sparse_completion_%dx%d_k%d" % (m, n, k), m, n, k, "coo",
                 np.zeros(n, np.uint8), [(QUAD, 0, 0.0)], (RQUAD, gamma), (RQUAD, gamma),

@@ -30,3 +30,168 @@ def rel_fro(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ---- decisions near a tie ------------------------------------------------------
+#
+# The GPU forms its step x+ = prox(x - alpha g) from a gradient g that carries
+# rounding error.  A gradient coordinate is a sum of terms G_ij y_jc, and its
+# rounding error is a fraction of the sum of their magnitudes,
+# S_c = sum_j |G_ij| |y_jc| (the oracle's grad_abs): about 2^-8 of it when
+# the contraction is one bfloat16 product per term (the BF16 form: both
+# operands rounded to 8 bits), and below 2^-16 for float32 accumulation of
+# up to ~10^4 terms (many standard deviations of sqrt(n) 2^-24).  The prox operators are
+# nonexpansive, so each coordinate of the GPU's trial point lies within
+# eps_c = 2 rel alpha S_c of the oracle's.  The trial objective then moves by
+# at most sum_c S+_c eps_c to first order (S+ is the same magnitude sum at the
+# trial point, plus the regularizer's slope); the band doubles that for the
+# second-order term and adds the float32 rounding of the objective sums
+# themselves (sqrt(n) 2^-24 relative for n <= 2e4 terms).  A decision whose
+# margin |f+ - f| lies inside the band may legitimately go either way; every
+# other decision must match the oracle's.
+
+GRAD_REL = {"fp32": 2.0 ** -16, "bf16": 2.0 ** -8}
+SUM_REL = 1e-5
+
+
+def _reg_slope(reg, V):
+    kind, w = reg
+    if kind == 1:
+        return 2.0 * w * np.abs(V)
+    if kind == 2:
+        return np.full_like(V, w)
+    return np.zeros_like(V)
+
+
+def _trial(reg, V, g, alpha):
+    out = np.empty_like(V)
+    for i in range(V.shape[0]):
+        out[i] = oracle.prox(reg[0], reg[1], float(alpha[i]), V[i] - alpha[i] * g[i])
+    return out
+
+
+def band_rows(P, X, Y, ax, f_old, f_new, prec):
+    """Decision band of every row of the X half-step at (X, Y) with step sizes ax."""
+    X, Y = np.asarray(X, np.float64), np.asarray(Y, np.float64)
+    g, _ = P.grad(X, Y)
+    S, _ = P.grad_abs(X, Y)
+    Xp = _trial(P.rx, X, g, ax)
+    Sp, _ = P.grad_abs(Xp, Y)
+    eps = 2.0 * GRAD_REL[prec] * np.asarray(ax, np.float64)[:, None] * S
+    first = np.sum((Sp + _reg_slope(P.rx, Xp)) * eps, axis=1)
+    return 2.0 * first + SUM_REL * (np.abs(f_old) + np.abs(f_new))
+
+
+def band_cols(P, X, Y, ay, h_old, h_new, prec):
+    """Decision band of every column of the Y half-step at (X^t, Y)."""
+    X, Y = np.asarray(X, np.float64), np.asarray(Y, np.float64)
+    _, g = P.grad(X, Y)
+    _, S = P.grad_abs(X, Y)
+    Yp = _trial(P.ry, Y, g, ay)
+    _, Sp = P.grad_abs(X, Yp)
+    eps = 2.0 * GRAD_REL[prec] * np.asarray(ay, np.float64)[:, None] * S
+    first = np.sum((Sp + _reg_slope(P.ry, Yp)) * eps, axis=1)
+    return 2.0 * first + SUM_REL * (np.abs(h_old) + np.abs(h_new))
+
+
+def clear_decisions(f_old, f_new, band):
+    """True where the oracle's accept / reject decision has a margin beyond the band."""
+    f_old, f_new = np.asarray(f_old), np.asarray(f_new)
+    with np.errstate(invalid="ignore"):
+        return ~(np.isfinite(f_old) & np.isfinite(f_new)) | (np.abs(f_new - f_old) > band)
+
+
+def _check_half(P, which, U0, V, alpha0, Ugpu, alpha_gpu, prec, step_up=1.05, step_down=0.7, tag=""):
+    """One half-step of the GPU checked against the oracle's from the same
+    state.  `which` is "x" (rows of X against Y = V) or "y" (columns of Y
+    against X^t = V).  Every row is checked:
+      * its decision (read from the step size, which moved by step_up or
+        step_down) equals the oracle's wherever the oracle's margin lies
+        outside the band;
+      * an accepted row equals the oracle's trial point within the rounding
+        bound eps_c of its gradient (+ float32 rounding of the value);
+      * a rejected row is bit-for-bit the old row.
+    Returns (number of decisions inside the band, number of them the GPU took
+    the other way)."""
+    U0 = np.asarray(U0, np.float64)
+    V = np.asarray(V, np.float64)
+    alpha0 = np.asarray(alpha0, np.float64)
+    Uo = U0.copy()
+    ao = alpha0.copy()
+    if which == "x":
+        X0, Y0 = U0, V
+        _, f_old, f_new, acc_o = P.half_step_x(Uo, V, ao, step_up, step_down)
+        band = band_rows(P, X0, Y0, alpha0, f_old, f_new, prec)
+        g, _ = P.grad(X0, Y0)
+        S, _ = P.grad_abs(X0, Y0)
+        reg = P.rx
+    else:
+        X0, Y0 = V, U0
+        _, f_old, f_new, acc_o = P.half_step_y(V, Uo, ao, step_up, step_down)
+        band = band_cols(P, X0, Y0, alpha0, f_old, f_new, prec)
+        _, g = P.grad(X0, Y0)
+        _, S = P.grad_abs(X0, Y0)
+        reg = P.ry
+    trial = _trial(reg, U0, g, alpha0)
+    # the float32 rounding of x - alpha g and of the prox adds 2^-22 of |x| + |x+|
+    eps = 2.0 * GRAD_REL[prec] * alpha0[:, None] * S + 2.0 ** -22 * (np.abs(trial) + np.abs(U0)) + 1e-30
+    Ugpu = np.asarray(Ugpu, np.float32)
+    alpha_gpu = np.asarray(alpha_gpu, np.float64)
+    ratio = alpha_gpu / np.maximum(alpha0, 1e-300)
+    acc_g = np.abs(ratio - step_up) <= 1e-6 * step_up
+    rej_g = np.abs(ratio - step_down) <= 1e-6 * step_down
+    assert np.all(acc_g | rej_g), "%s: step sizes moved by neither factor" % tag
+    clear = clear_decisions(f_old, f_new, band)
+    acc_o = acc_o.astype(bool)
+    bad = np.nonzero(clear & (acc_g != acc_o))[0]
+    assert bad.size == 0, "%s: decisions differ on clear %s %s (margin %s, band %s)" % (
+        tag, "rows" if which == "x" else "columns", bad[:8], (f_new - f_old)[bad[:8]], band[bad[:8]])
+    U0_32 = U0.astype(np.float32)
+    assert np.array_equal(Ugpu[rej_g], U0_32[rej_g]), "%s: a rejected row changed" % tag
+    if acc_g.any():
+        diff = np.abs(Ugpu[acc_g].astype(np.float64) - trial[acc_g])
+        worst = np.max(diff / eps[acc_g])
+        assert worst <= 1.0, "%s: accepted trial point off by %.3g of its rounding bound" % (tag, worst)
+    return int((~clear).sum()), int((~clear & (acc_g != acc_o)).sum()), acc_g
+
+
+def guided_half(P, which, U, V, alpha, gpu_acc, prec, step_up=1.05, step_down=0.7):
+    """The oracle's half-step from (U, alpha) against V, except that every
+    decision inside its rounding band takes the branch the GPU took
+    (gpu_acc).  Either branch is a correct outcome there; following the GPU's
+    lets a multi-sweep comparison isolate the arithmetic error.  Returns the
+    new (U, alpha)."""
+    U = np.asarray(U, np.float64)
+    alpha = np.asarray(alpha, np.float64)
+    Uo, ao = U.copy(), alpha.copy()
+    if which == "x":
+        _, f_old, f_new, acc_o = P.half_step_x(Uo, V, ao, step_up, step_down)
+        band = band_rows(P, U, V, alpha, f_old, f_new, prec)
+        g, _ = P.grad(U, V)
+        reg = P.rx
+    else:
+        _, f_old, f_new, acc_o = P.half_step_y(V, Uo, ao, step_up, step_down)
+        band = band_cols(P, V, U, alpha, f_old, f_new, prec)
+        _, g = P.grad(V, U)
+        reg = P.ry
+    acc = np.where(clear_decisions(f_old, f_new, band), acc_o.astype(bool), np.asarray(gpu_acc, bool))
+    trial = _trial(reg, U, g, alpha)
+    return np.where(acc[:, None], trial, U), alpha * np.where(acc, step_up, step_down)
+
+
+def check_sweep(P, X0, Y0, ax0, ay0, Xg, Yg, axg, ayg, prec, tag=""):
+    """A GPU sweep from (X0, Y0, ax0, ay0) to (Xg, Yg, axg, ayg) checked half by
+    half: the rows against the oracle's X half-step from the same state, the
+    columns against the oracle's Y half-step from the GPU's own X^t (so both
+    halves are compared like for like).  Returns the near-tie counts."""
+    nr = _check_half(P, "x", X0, Y0, ax0, Xg, axg, prec, tag=tag + " rows")
+    nc = _check_half(P, "y", Y0, Xg, ay0, Yg, ayg, prec, tag=tag + " columns")
+    return dict(band_rows=nr[0], band_cols=nc[0], flipped=nr[1] + nc[1], acc_rows=nr[2], acc_cols=nc[2])
+
+
+def init_alpha32(P, scale):
+    """The step sizes the GPU starts from: scale / max(n_i, 1) in float32."""
+    ax, ay = P.init_alpha(1.0)          # 1 / max(n_i, 1)
+    cx = np.rint(1.0 / ax).astype(np.float32)
+    cy = np.rint(1.0 / ay).astype(np.float32)
+    return (np.float32(scale) / cx).astype(np.float64), (np.float32(scale) / cy).astype(np.float64)

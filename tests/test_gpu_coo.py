@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import oracle_problem, rel_fro, to_dev
+from gpu_helpers import check_sweep, init_alpha32, oracle_problem, rel_fro, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -61,23 +61,18 @@ def test_gradient_matches_oracle(spec):
 
 @pytest.mark.parametrize("spec", CASES)
 def test_one_sweep_matches_oracle(spec):
+    """One sweep from an identical state, every row and column checked (rows
+    against the oracle's X half-step, columns against the oracle's Y
+    half-step from the GPU's own X^t; see gpu_helpers.check_sweep)."""
     case = _case(spec, rx=(1, 0.1), ry=(2, 0.05))
     data, X, Y, P = _setup(case)
     ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
     ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
     info = g.glrm_fit(data, X, Y, ax, ay, 1, precision=g.FP32, alpha_scale=2.0)
-    Xo, Yo = case.X0.astype(np.float64).copy(), case.Y0.astype(np.float64).copy()
-    axo, ayo = P.init_alpha(2.0)
-    rej, fo, fn, _ = P.half_step_x(Xo, Yo, axo)
-    amb = np.abs(fn - fo) <= 2e-5 * np.abs(fo)
-    np.testing.assert_allclose(X.cpu().numpy()[~amb], Xo[~amb], rtol=2e-5, atol=2e-5 * np.abs(Xo).max())
-    np.testing.assert_allclose(ax.cpu().numpy()[~amb], axo[~amb], rtol=1e-6)
-    rej_c, ho, hn, _ = P.half_step_y(Xo, Yo, ayo)
-    if amb.any():
-        return
-    ambc = np.abs(hn - ho) <= 1e-4 * np.abs(ho)
-    np.testing.assert_allclose(Y.cpu().numpy()[~ambc], Yo[~ambc], rtol=1e-4, atol=1e-4 * np.abs(Yo).max())
-    assert info["objective"] == pytest.approx(P.objective(Xo, Yo), rel=1e-5)
+    ax0, ay0 = init_alpha32(P, 2.0)
+    Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
+    check_sweep(P, case.X0, case.Y0, ax0, ay0, Xg, Yg, ax.cpu().numpy(), ay.cpu().numpy(), "fp32", tag=case.name)
+    assert info["objective"] == pytest.approx(P.objective(Xg, Yg), rel=1e-10)
 
 
 def test_fit_reaches_the_oracles_converged_objective():

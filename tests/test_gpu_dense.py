@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import oracle_problem, rel_fro, to_dev
+from gpu_helpers import check_sweep, guided_half, init_alpha32, oracle_problem, rel_fro, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -71,15 +71,29 @@ def test_objective_matches_oracle(spec, prec, tol):
     assert abs(got - ref) <= tol * abs(ref)
 
 
+def _coord_err(got, ref):
+    """Largest per-coordinate error, scaled by max(|ref|, RMS of ref)."""
+    ref = np.asarray(ref, np.float64)
+    rms = np.sqrt(np.mean(ref ** 2)) if ref.size else 0.0
+    return float(np.max(np.abs(np.asarray(got, np.float64) - ref) / np.maximum(np.abs(ref), max(rms, 1e-300))))
+
+
 @pytest.mark.parametrize("spec", CASES)
-@pytest.mark.parametrize("prec,tol", [(g.FP32, 1e-4), (g.BF16, 2e-2)])
-def test_gradient_matches_oracle(spec, prec, tol):
+@pytest.mark.parametrize("prec,tol,ctol", [(g.FP32, 1e-4, 1e-4), (g.BF16, 2e-2, 5e-2)])
+def test_gradient_matches_oracle(spec, prec, tol, ctol):
+    """Frobenius error and per-coordinate error (scale max(|ref|, RMS)) of both
+    gradients.  BF16: each term of a gradient coordinate is one bfloat16
+    product, 2^-8 relative, so a coordinate whose terms cancel carries up to
+    2^-8 of the sum of their magnitudes; 5e-2 of the RMS covers it."""
     case = _case(spec)
     data, X, Y, P = _setup(case)
     dXr, dYr = P.grad(case.X0, case.Y0)
     dX, dY, obj = g.glrm_grad(data, X, Y, prec, want_objective=True)
-    assert rel_fro(dX.cpu().numpy(), dXr) <= tol
-    assert rel_fro(dY.cpu().numpy(), dYr) <= tol
+    dX, dY = dX.cpu().numpy(), dY.cpu().numpy()
+    assert rel_fro(dX, dXr) <= tol
+    assert rel_fro(dY, dYr) <= tol
+    assert _coord_err(dX, dXr) <= ctol
+    assert _coord_err(dY, dYr) <= ctol
     assert obj == pytest.approx(P.objective(case.X0, case.Y0), rel=1e-5 if prec == g.FP32 else 1e-3)
 
 
@@ -131,49 +145,83 @@ def test_hand_worked_sweeps_on_the_gpu():
             assert info["cols_rejected"] == exp["cols_rejected"], tag
 
 
-def _ambiguous(fo, fn, rel=2e-5):
-    return np.abs(fn - fo) <= rel * np.maximum(np.abs(fo), 1e-30)
+PNAME = {g.FP32: "fp32", g.BF16: "bf16"}
 
 
 @pytest.mark.parametrize("spec", CASES)
 @pytest.mark.parametrize("prec", [g.FP32, g.BF16])
 def test_one_sweep_matches_oracle(spec, prec):
-    """One sweep from an identical state.  Rows and columns whose accept /
-    reject decision the oracle takes by a clear margin must match; ambiguous
-    ones are excluded.  FP32: element-wise.  BF16: the gradient contractions
-    use one bfloat16 product, so the step x+ - x carries a relative error of
-    order 2^-8; it is compared as a step, in Frobenius norm."""
+    """One sweep from an identical state, every row and column checked: the
+    rows against the oracle's X half-step, the columns against the oracle's Y
+    half-step taken from the GPU's own X^t.  A decision whose margin lies
+    outside its rounding band matches the oracle's; one inside it is either
+    an accepted step equal to the oracle's trial point within the gradient's
+    rounding bound, or a rejected step that left the row untouched (the band
+    and bounds are derived in gpu_helpers)."""
     case = _case(spec, rx=(1, 0.1), ry=(2, 0.05))
     data, X, Y, P = _setup(case)
     ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
     ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
     info = g.glrm_fit(data, X, Y, ax, ay, 1, precision=prec, init_alpha=True, alpha_scale=2.0)
-    X0, Y0 = case.X0.astype(np.float64), case.Y0.astype(np.float64)
-    Xo, Yo = X0.copy(), Y0.copy()
-    axo, ayo = P.init_alpha(2.0)
-    rej, fo, fn, accx = P.half_step_x(Xo, Yo, axo)
-    amb_r = _ambiguous(fo, fn, 2e-5 if prec == g.FP32 else 2e-2)
-    ok_r = ~amb_r
-    Xg = X.cpu().numpy()
-    np.testing.assert_allclose(ax.cpu().numpy()[ok_r], axo[ok_r], rtol=1e-6)
+    ax0, ay0 = init_alpha32(P, 2.0)
+    Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
+    check_sweep(P, case.X0, case.Y0, ax0, ay0, Xg, Yg, ax.cpu().numpy(), ay.cpu().numpy(), PNAME[prec],
+                tag=case.name)
+    # the reported objective is F at the state the GPU reached (FP64 recompute)
+    assert info["objective"] == pytest.approx(P.objective(Xg, Yg), rel=1e-10)
+
+
+NONSMOOTH = [
+    # hinge and ordinal columns, l1 on X, nonnegative Y
+    dict(m=90, n=40, k=5, seed=71, kinds=(3, 4), rx=(2, 0.05), ry=(3, 0.0)),
+    # every loss kind, nonnegative X from a nonnegative start, l1 on Y
+    dict(m=120, n=33, k=4, seed=72, x_nonneg=True, rx=(3, 0.0), ry=(2, 0.1)),
+    # ordinal only, l1 on both, a wider table (several tiles, kp = 16)
+    dict(m=70, n=150, k=9, seed=73, kinds=(4,), rx=(2, 0.02), ry=(2, 0.02)),
+]
+
+
+@pytest.mark.parametrize("spec", NONSMOOTH)
+@pytest.mark.parametrize("prec", [g.FP32, g.BF16])
+def test_three_sweeps_nonsmooth_match_oracle(spec, prec):
+    """Three sweeps on hinge / ordinal losses with l1 and nonnegative
+    regularizers.  Each GPU sweep is checked against the oracle's sweep from
+    the GPU's previous state (every row and column, as in the one-sweep
+    test).  After three sweeps the GPU's objective equals, within the
+    precision's tolerance, that of the oracle's three sweeps from the common
+    start in which each decision inside its rounding band took the GPU's
+    branch (either branch is correct there).  FP32 takes no decision inside
+    the band, so there the oracle's own trajectory is compared; for BF16 the
+    gap to the unguided trajectory is reported with the count of band
+    decisions."""
+    sp = dict(spec)
+    case = synth.small_mixed(sp.pop("m"), sp.pop("n"), sp.pop("k"), **sp)
+    data, X, Y, P = _setup(case)
+    ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
+    ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
+    Xp, Yp = case.X0.copy(), case.Y0.copy()
+    axp, ayp = init_alpha32(P, 1.0)
+    Xo, Yo, axo, ayo = case.X0.astype(np.float64), case.Y0.astype(np.float64), axp.copy(), ayp.copy()
+    band = flipped = 0
+    pn = PNAME[prec]
+    for t in range(3):
+        info = g.glrm_fit(data, X, Y, ax, ay, 1, precision=prec, init_alpha=(t == 0))
+        Xg, Yg, axg, ayg = X.cpu().numpy(), Y.cpu().numpy(), ax.cpu().numpy(), ay.cpu().numpy()
+        r = check_sweep(P, Xp, Yp, axp, ayp, Xg, Yg, axg, ayg, pn, tag="%s sweep %d" % (case.name, t + 1))
+        band += r["band_rows"] + r["band_cols"]
+        flipped += r["flipped"]
+        Xo, axo = guided_half(P, "x", Xo, Yo, axo, r["acc_rows"], pn)
+        Yo, ayo = guided_half(P, "y", Yo, Xo, ayo, r["acc_cols"], pn)
+        Xp, Yp, axp, ayp = Xg, Yg, axg.astype(np.float64), ayg.astype(np.float64)
+    *_, href, _ = P.fit(case.X0, case.Y0, 3)
+    F_guided = P.objective(Xo, Yo)
+    print("%s %s: %d decisions in the band, %d took the other branch; F gpu %.10g, guided oracle %.10g, "
+          "oracle %.10g" % (case.name, pn, band, flipped, info["objective"], F_guided, href[-1]))
+    tol = 1e-5 if prec == g.FP32 else 1e-3
+    assert info["objective"] == pytest.approx(F_guided, rel=tol)
     if prec == g.FP32:
-        np.testing.assert_allclose(Xg[ok_r], Xo[ok_r], rtol=2e-5, atol=2e-5 * np.abs(Xo).max())
-    else:
-        assert rel_fro((Xg - X0)[ok_r], (Xo - X0)[ok_r]) <= 2e-2
-    rej_c, ho, hn, accy = P.half_step_y(Xo, Yo, ayo)
-    if amb_r.any():
-        return  # the GPU's X^t differs in an ambiguous row: columns no longer like for like
-    ok_c = ~_ambiguous(ho, hn, 1e-4 if prec == g.FP32 else 2e-2)
-    Yg = Y.cpu().numpy()
-    np.testing.assert_allclose(ay.cpu().numpy()[ok_c], ayo[ok_c], rtol=1e-6)
-    if prec == g.FP32:
-        np.testing.assert_allclose(Yg[ok_c], Yo[ok_c], rtol=1e-4, atol=1e-4 * np.abs(Yo).max())
-    else:
-        assert rel_fro((Yg - Y0)[ok_c], (Yo - Y0)[ok_c]) <= 5e-2
-    if prec == g.FP32:
-        assert info["objective"] == pytest.approx(P.objective(Xo, Yo), rel=1e-5)
-    # the reported objective is F at the state the GPU reached
-    assert info["objective"] == pytest.approx(P.objective(X.cpu().numpy(), Yg), rel=1e-10)
+        assert band == 0
+        assert info["objective"] == pytest.approx(href[-1], rel=tol)
 
 
 @pytest.mark.parametrize("prec,tol", [(g.FP32, 1e-5), (g.BF16, 1e-4)])
@@ -258,3 +306,30 @@ def test_fit_beyond_the_dense_limits_is_reported(m, n, k):
     assert err.value.code == g.EUNSUPPORTED
     assert torch.equal(X, X0)
 
+
+
+@pytest.mark.parametrize("layout", ["dense", "coo"])
+@pytest.mark.parametrize("prec", [g.FP32, g.BF16])
+def test_overflowing_step_sizes_leave_the_factors_finite(layout, prec):
+    """Step sizes that overflow float32 (alpha_scale 3e38, zero regularizers,
+    an unobserved row and column whose gradient is exactly 0): a trial point
+    with an infinite or NaN coordinate, or whose products overflow, is never
+    accepted, so X and Y stay finite and every observed row and column keeps
+    its start, as in the oracle; the objective equals the oracle's."""
+    if layout == "coo" and prec == g.BF16:
+        pytest.skip("the COO layout's BF16 form is covered by the sparse tests")
+    case = synth.small_mixed(60, 30, 4, seed=81, missing=0.3, layout=layout, rx=(0, 0.0), ry=(0, 0.0),
+                             empty_row=3, empty_col=7)
+    data = g.Data.from_case(case, DEV)
+    X, Y = to_dev(case.X0, DEV), to_dev(case.Y0, DEV)
+    P = oracle_problem(case)
+    ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
+    ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
+    info = g.glrm_fit(data, X, Y, ax, ay, 4, precision=prec, alpha_scale=3.0e38)
+    Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
+    assert np.all(np.isfinite(Xg)) and np.all(np.isfinite(Yg))
+    *_, href, _ = P.fit(case.X0, case.Y0, 4, alpha_scale=3.0e38)
+    assert np.isfinite(info["objective"])
+    assert info["objective"] == pytest.approx(href[-1], rel=1e-9)
+    np.testing.assert_array_equal(Xg, case.X0)
+    np.testing.assert_array_equal(Yg, case.Y0)

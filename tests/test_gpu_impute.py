@@ -1,4 +1,4 @@
-"""GPU parity of the imputation decode (Section 5.4) against the FP64 oracle,
+"""GPU parity of the imputation decode (Section 5.3) against the FP64 oracle,
 through the C ABI.
 
 The kernel forms x_i . y_j as a float32 multiply-add chain of k terms, so it is
@@ -31,7 +31,7 @@ F32 = lambda v: float(np.float32(v))  # noqa: E731
 
 
 def _closed_form(u, kind, levels):
-    """The decoded value of Section 5.4 by kind (arrays broadcast)."""
+    """The decoded value of Section 5.3 by kind (arrays broadcast)."""
     boolean = np.where(u > 0, 1.0, -1.0)
     ordinal = np.clip(np.ceil(u - 0.5), 1.0, levels)
     return np.where(kind <= 1, u, np.where(kind <= 3, boolean, ordinal))

@@ -30,7 +30,7 @@ def _load_losses():
 
 @pytest.mark.parametrize("row", _load_losses())
 def test_loss_hand_values(row):
-    """Hand-worked values of each loss (Sections 2.2, 4.2, 5.1, eq. ord-pca)."""
+    """Hand-worked values of each loss (Sections 2.2, 4.2, 5.2, eq. ord-pca)."""
     kind, levels, param, u, a, val, der = row
     assert oracle.loss(kind, u, a, levels, param) == pytest.approx(val, rel=1e-14, abs=1e-14)
     assert oracle.dloss(kind, u, a, levels, param) == pytest.approx(der, rel=1e-14, abs=1e-14)
@@ -288,6 +288,31 @@ def test_step_sizes_move_by_exact_factors_and_rejected_rows_stay():
         P.half_step_y(X, Y, ay)
 
 
+def test_a_trial_point_outside_the_reals_is_rejected():
+    """The factors are real matrices (Section 2.1).  With an infinite step
+    size the step of a row with no observations and no regularizer is
+    x - inf * 0 = NaN: that trial point is outside the domain, so the row is
+    rejected and keeps its (finite) value, where comparing a loss-free, zero
+    trial objective with the old one would have accepted it.  An observed
+    row with an overflowing step is rejected as well, and its old objective
+    is untouched."""
+    c = synth.small_mixed(8, 6, 2, seed=13, rx=(0, 0.0), ry=(0, 0.0), empty_row=2)
+    P = _problem(c)
+    X, Y = c.X0.astype(np.float64).copy(), c.Y0.astype(np.float64).copy()
+    X0 = X.copy()
+    ax = np.full(c.m, np.inf)
+    r, fo, fn, acc = P.half_step_x(X, Y, ax)
+    assert r == c.m and not acc.any()
+    assert np.all(np.isinf(fn)) and np.all(np.isfinite(fo))
+    np.testing.assert_array_equal(X, X0)
+    assert fo[2] == 0.0          # the empty row's old objective: no loss, no regularizer
+    # a finite step size leaves the empty row's step at exactly 0: accepted
+    ax = np.full(c.m, 1e300)
+    r, fo, fn, acc = P.half_step_x(X, Y, ax)
+    assert acc[2] and fn[2] == 0.0
+    np.testing.assert_array_equal(X, X0)
+
+
 def test_initial_step_is_inverse_count():
     """alpha_i^0 = 1/n_i (Section 7.2), empty rows take the scale itself."""
     c = synth.small_mixed(12, 9, 2, seed=12, empty_row=3, empty_col=4)
@@ -329,13 +354,13 @@ def test_global_optimality_certificate_after_convergence():
     assert cert(c.X0.astype(np.float64), c.Y0.astype(np.float64)) > 1.0 + 1e-2
 
 
-# ---- imputation decode (Section 5.4) ------------------------------------------
+# ---- imputation decode (Section 5.3) ------------------------------------------
 U_GRID = np.concatenate([np.linspace(-9.3, 9.3, 187), [-2.5, -0.5, 0.5, 1.5, 2.5, 3.5, 6.5, 7.5]])
 
 
 @pytest.mark.parametrize("loss", [(0, 0, 0.0), (1, 0, 1.0), (1, 0, 0.25)])
 def test_decode_real_losses_is_the_product(loss):
-    """Section 5.4: for losses over the reals the decoded entry is x_i . y_j.
+    """Section 5.3: for losses over the reals the decoded entry is x_i . y_j.
     Checked against a scalar minimiser of L(u, .) as well."""
     kind, levels, param = loss
     for u in U_GRID:
@@ -347,7 +372,7 @@ def test_decode_real_losses_is_the_product(loss):
 
 @pytest.mark.parametrize("kind", [2, 3])
 def test_decode_boolean_losses_is_the_sign(kind):
-    """Section 5.4: for logistic and hinge (MMMF) data the decoded entry is
+    """Section 5.3: for logistic and hinge (MMMF) data the decoded entry is
     sign(x_i . y_j); at u = 0 both values tie and the smaller is taken."""
     for u in U_GRID[np.abs(U_GRID) > 1e-9]:
         assert oracle.decode(kind, u) == np.sign(u)
@@ -358,7 +383,7 @@ def test_decode_boolean_losses_is_the_sign(kind):
 
 @pytest.mark.parametrize("levels", [2, 5, 7])
 def test_decode_ordinal_is_the_nearest_level(levels):
-    """eq. ord-pca decoded by Section 5.4.  Going from level a to a+1 changes
+    """eq. ord-pca decoded by Section 5.3.  Going from level a to a+1 changes
     the loss by (1 + a - u)_+ - (u - a)_+, which is negative exactly when
     a < u - 1/2 and zero when a = u - 1/2; so the minimiser is the level
     nearest to u, clamped to 1..levels, with the lower level at a half-way
@@ -369,7 +394,7 @@ def test_decode_ordinal_is_the_nearest_level(levels):
 
 
 def test_impute_table_keeps_observed_entries_and_decodes_the_rest():
-    """Section 5.4 on a mixed table: missing entries take the decoded value of
+    """Section 5.3 on a mixed table: missing entries take the decoded value of
     their column's loss, observed entries keep A_ij when asked to; with no
     mask every entry is decoded (the denoised table)."""
     rng = np.random.default_rng(5)
