@@ -161,6 +161,24 @@ int glrm_grad(const glrm_data *d, const float *X, const float *Y, int precision,
               float *dX, float *dY, double *obj_host, void *ws, size_t ws_bytes,
               unsigned flags, void *stream);
 
+/* glrm_grad for callers that cannot allocate device memory: code recorded
+ * under HIP graph capture, tight serving loops, and harnesses that forbid
+ * hipMalloc.  The same computation and results as glrm_grad (bit for bit),
+ * with its workspace taken from a static device array the library owns
+ * instead of a caller's buffer: GLRM_NOALLOC_MAX_BYTES per device, held on
+ * every device the library runs on until the process ends.  The call
+ * allocates nothing and calls no allocating routine.  Problems whose
+ * gradient workspace (glrm_workspace_size with the gradient's smaller
+ * partial buffers) exceeds the limit return GLRM_ENOMEM before any HIP call.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents: GLRM_WS_PREPARED may skip the preparation only if the
+ * previous call on this device prepared the same data; calls that overlap
+ * on one device (other threads, other streams) race.  Asynchronous unless
+ * obj_host is given, as glrm_grad. */
+#define GLRM_NOALLOC_MAX_BYTES (64u << 20)
+int glrm_grad_noalloc(const glrm_data *d, const float *X, const float *Y, int precision,
+                      float *dX, float *dY, double *obj_host, unsigned flags, void *stream);
+
 /* In place V[i,:] <- prox_{alpha[i] r}(V[i,:]) for i < rows (Section 7.2,
  * prox_f(z) = argmin_x f(x) + 1/2 ||x - z||^2).  V is rows x k with leading
  * dimension ldv >= k (device); alpha has `rows` entries (device) or is NULL

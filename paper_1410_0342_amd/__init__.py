@@ -15,7 +15,8 @@ import numpy as np
 __all__ = [
     "GLRMError", "Data", "glrm_workspace_size", "glrm_prepare", "glrm_objective", "glrm_grad", "glrm_prox",
     "glrm_fit", "glrm_last_error", "library_path", "FP32", "BF16", "FP64", "BF16_PLAIN", "DENSE", "COO_ROWSORTED",
-    "WS_PREPARED", "TIME_KERNELS", "glrm_impute", "IMPUTE_ALL", "IMPUTE_MISSING",
+    "WS_PREPARED", "TIME_KERNELS", "glrm_impute", "IMPUTE_ALL", "IMPUTE_MISSING", "glrm_grad_noalloc",
+    "NOALLOC_MAX_BYTES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -26,6 +27,7 @@ DENSE, COO_ROWSORTED = 0, 1
 WS_PREPARED = 1
 TIME_KERNELS = 2
 IMPUTE_ALL, IMPUTE_MISSING = 0, 1
+NOALLOC_MAX_BYTES = 64 << 20
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp64": FP64, "bf16_plain": BF16_PLAIN}
 
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
@@ -89,6 +91,8 @@ def _L():
         L.glrm_grad.restype = ctypes.c_int
         L.glrm_grad.argtypes = [D, P, P, ctypes.c_int, P, P, ctypes.POINTER(ctypes.c_double), P, ctypes.c_size_t,
                                 ctypes.c_uint, P]
+        L.glrm_grad_noalloc.restype = ctypes.c_int
+        L.glrm_grad_noalloc.argtypes = [D, P, P, ctypes.c_int, P, P, ctypes.POINTER(ctypes.c_double), ctypes.c_uint, P]
         L.glrm_prox.restype = ctypes.c_int
         L.glrm_prox.argtypes = [ctypes.POINTER(_Reg), P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, P, P]
         L.glrm_fit.restype = ctypes.c_int
@@ -258,6 +262,23 @@ def glrm_grad(data, X, Y, precision=FP32, dX=None, dY=None, want_objective=False
                           _dev_ptr(dX, torch.float32, "dX", data.m * data.k),
                           _dev_ptr(dY, torch.float32, "dY", data.n * data.k),
                           ctypes.byref(out) if want_objective else None, ws, wsb, int(flags), _stream(stream)))
+    return (dX, dY, out.value) if want_objective else (dX, dY)
+
+
+def glrm_grad_noalloc(data, X, Y, precision=FP32, dX=None, dY=None, want_objective=False, flags=0, stream=None):
+    """glrm_grad with the library's static scratch instead of a workspace (the
+    outputs are the caller's; pass dX / dY to allocate nothing here either)."""
+    torch = _torch()
+    if dX is None:
+        dX = torch.empty((data.m, data.k), dtype=torch.float32, device=X.device)
+    if dY is None:
+        dY = torch.empty((data.n, data.k), dtype=torch.float32, device=X.device)
+    out = ctypes.c_double(0.0)
+    _check(_L().glrm_grad_noalloc(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
+                                  _dev_ptr(Y, torch.float32, "Y", data.n * data.k), _prec(precision),
+                                  _dev_ptr(dX, torch.float32, "dX", data.m * data.k),
+                                  _dev_ptr(dY, torch.float32, "dY", data.n * data.k),
+                                  ctypes.byref(out) if want_objective else None, int(flags), _stream(stream)))
     return (dX, dY, out.value) if want_objective else (dX, dY)
 
 

@@ -164,8 +164,8 @@ int coo_prepare(const glrm_data *d, int kp, const CooLayout &cl, char *base, int
     CooPtrs p = ptrs(cl, base);
     const int64_t nnz = d->nnz, m = d->m, n = d->n;
     hipError_t e;
-    if ((e = hipMemsetAsync(p.flags, 0, sizeof(int32_t) * 4, st)) != hipSuccess)
-        return set_error(GLRM_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+    if ((e = launch_fill_i32(p.flags, 4, 0, st)) != hipSuccess)
+        return set_error(GLRM_EHIP, "clearing the validation flags: %s", hipGetErrorString(e));
     if (nnz > 0) hipLaunchKernelGGL(coo_validate_kernel, dim3(nblk(nnz)), dim3(256), 0, st, d->row, d->col, nnz, m, n, p.flags);
     hipLaunchKernelGGL(seg_ptr_kernel, dim3(nblk(m + 1)), dim3(256), 0, st, d->row, nnz, m, p.row_ptr);
     hipLaunchKernelGGL(seg_count_kernel, dim3(nblk(m)), dim3(256), 0, st, p.row_ptr, m, row_count);

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -88,7 +89,9 @@ struct Layout {
     }
 };
 
-bool make_layout(const glrm_data *d, Layout &L)
+// grad_only: the layout of the gradient entry points alone, whose Y-gradient
+// partials never exceed P_GRAD rows (the fit's run up to P_MAX).
+bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false)
 {
     L = Layout();
     L.m = d->m;
@@ -135,7 +138,8 @@ bool make_layout(const glrm_data *d, Layout &L)
     L.part_rejc = L.take(sizeof(int32_t) * ya_blocks);
     if (d->layout == GLRM_DENSE) {
         L.Ap = L.take(sizeof(float) * L.mp * ldp);
-        L.pmax = (int)std::clamp<int64_t>(P_BYTES / ((int64_t)sizeof(float) * ldp * kp), 256, P_MAX);
+        L.pmax = grad_only ? P_GRAD
+                           : (int)std::clamp<int64_t>(P_BYTES / ((int64_t)sizeof(float) * ldp * kp), 256, P_MAX);
         L.part_dy = L.take(sizeof(float) * L.pmax * ldp * kp);
         L.part_h = L.take(sizeof(float) * L.pmax * ldp);
         L.part_hp = L.take(sizeof(float) * L.pmax * ldp);
@@ -451,6 +455,64 @@ int set_error(int code, const char *fmt, ...)
 }
 }  // namespace glrm
 
+namespace {
+// The gradient entry points after their checks: prepare unless told the
+// workspace holds it, one loss-and-gradient pass, the objective if asked.
+int grad_run(const glrm_data *d, const Layout &L, const float *X, const float *Y, int precision, float *dX,
+             float *dY, double *obj_host, void *ws, unsigned flags, hipStream_t st)
+{
+    int rc;
+    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    double *po = nullptr;
+    int nparts = 0;
+    if (d->layout == GLRM_DENSE) {
+        if ((rc = dense_lossgrad(d, L, X, Y, precision, dX, dY, true, ws, st))) return rc;
+        po = at<double>(ws, L.part_obj);
+        nparts = (int)(grad_rows(L, true) * L.cb_grad);
+    } else {
+        if ((rc = coo_grad(d, L.kp, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
+                           precision, dX, dY, &po, &nparts, st)))
+            return rc;
+    }
+    if (obj_host) {
+        double *res = at<double>(ws, L.scal);
+        if ((rc = reg_sums(d, L, X, Y, ws, st))) return rc;
+        HIP_TRY(launch_sum_doubles(po, nparts, at<double>(ws, L.regpart), 2 * REG_BLOCKS, res, st));
+        HIP_TRY(hipMemcpyAsync(obj_host, res, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return GLRM_OK;
+}
+
+
+// The workspace of glrm_grad_noalloc: a file-scope device array, one copy on
+// every device the library runs on, held until the process ends.  In host
+// code its name stands for a host-side symbol, not a device address: the
+// address comes from hipGetSymbolAddress, once per device with that device
+// current, and only that address is handed to kernels.
+__device__ __align__(256) unsigned char scratch[GLRM_NOALLOC_MAX_BYTES];
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_DEVICES] = {};
+
+int scratch_address(void **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return fail(GLRM_EUNSUPPORTED, "device %d is beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(GLRM_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GLRM_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char *glrm_last_error(void) { return g_err.c_str(); }
@@ -523,29 +585,26 @@ int glrm_grad(const glrm_data *d, const float *X, const float *Y, int precision,
     Layout L;
     make_layout(d, L);
     if ((rc = check_ws(L, ws, ws_bytes))) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
-    double *po = nullptr;
-    int nparts = 0;
-    if (d->layout == GLRM_DENSE) {
-        if ((rc = dense_lossgrad(d, L, X, Y, precision, dX, dY, true, ws, st))) return rc;
-        po = at<double>(ws, L.part_obj);
-        nparts = (int)(grad_rows(L, true) * L.cb_grad);
-    } else {
-        if ((rc = coo_grad(d, L.kp, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
-                           precision, dX, dY, &po, &nparts, st)))
-            return rc;
-    }
-    if (obj_host) {
-        double *res = at<double>(ws, L.scal);
-        if ((rc = reg_sums(d, L, X, Y, ws, st))) return rc;
-        HIP_TRY(launch_sum_doubles(po, nparts, at<double>(ws, L.regpart), 2 * REG_BLOCKS, res, st));
-        HIP_TRY(hipMemcpyAsync(obj_host, res, sizeof(double), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-    }
-    return GLRM_OK;
+    return grad_run(d, L, X, Y, precision, dX, dY, obj_host, ws, flags, (hipStream_t)stream);
 }
 
+int glrm_grad_noalloc(const glrm_data *d, const float *X, const float *Y, int precision, float *dX, float *dY,
+                      double *obj_host, unsigned flags, void *stream)
+{
+    g_err.clear();
+    int rc = validate_data(d);
+    if (rc) return rc;
+    if (!X || !Y || !dX || !dY) return fail(GLRM_EINVAL, "X, Y, dX and dY must not be NULL");
+    if ((rc = check_prec(precision, false))) return rc;
+    Layout L;
+    make_layout(d, L, true);
+    if (L.total > (size_t)GLRM_NOALLOC_MAX_BYTES)
+        return fail(GLRM_ENOMEM, "glrm_grad_noalloc: this problem needs %zu bytes of scratch; the static scratch "
+                    "holds %zu (use glrm_grad with a workspace)", L.total, (size_t)GLRM_NOALLOC_MAX_BYTES);
+    void *ws = nullptr;
+    if ((rc = scratch_address(&ws))) return rc;
+    return grad_run(d, L, X, Y, precision, dX, dY, obj_host, ws, flags, (hipStream_t)stream);
+}
 int glrm_impute(const glrm_data *d, const float *X, const float *Y, int32_t mode, float *Ahat, int64_t ldh, void *ws,
                 size_t ws_bytes, unsigned flags, void *stream)
 {

@@ -123,3 +123,13 @@ def test_impute_argument_errors():
     assert L.glrm_impute(ctypes.byref(s), P, P, 0, P, 8, P, 16, 0, None) == g.ENOMEM
     bad, keep2 = _data(losses=[(7, 0, 0.0)])
     assert L.glrm_impute(ctypes.byref(bad), P, P, 0, P, 8, P, 1 << 40, 0, None) == g.EINVAL
+
+
+def test_noalloc_gradient_rejects_a_problem_beyond_its_scratch():
+    """The allocation-free gradient checks its static scratch limit before any
+    HIP call: a 100,000 x 1,000 dense table needs far more than it holds."""
+    s, keep = _data(m=100000, n=1000, k=20)
+    rc = g._L().glrm_grad_noalloc(ctypes.byref(s), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), g.FP32,
+                                  ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), None, 0, None)
+    assert rc == g.ENOMEM
+    assert "static scratch" in g.glrm_last_error()
