@@ -179,6 +179,37 @@ int glrm_grad(const glrm_data *d, const float *X, const float *Y, int precision,
 int glrm_grad_noalloc(const glrm_data *d, const float *X, const float *Y, int precision,
                       float *dX, float *dY, double *obj_host, unsigned flags, void *stream);
 
+/* Bytes of device workspace for the linear-algebra entry points
+ * (glrm_certificate with block = 1, glrm_init_svd with block = the sketch
+ * width it reports): glrm_workspace_size plus a region for an entry-wise
+ * matrix in the table's layout and vector blocks of `block` columns.
+ * 1 <= block <= 96.  The prepared part sits at the same offsets as in
+ * glrm_workspace_size's layout. */
+size_t glrm_linalg_workspace_size(const glrm_data *d, int32_t block);
+
+typedef struct {
+    double  norm;       /* the estimate of ||G / gamma + U V^T||_2 after `iters` iterations */
+    double  norm_prev;  /* the estimate one iteration earlier (convergence check) */
+    int32_t rank;       /* rank of X Y^T (singular values above 1e-6 of the largest) */
+    int32_t iters;      /* power iterations run */
+} glrm_cert_info;
+
+/* The global-optimality certificate of Section 7.6.  For a loss L(XY) that is
+ * convex in XY and the quadratic regularizer w ||.||^2 on both factors (the
+ * factored problem of Section 7.6 with gamma = 2 w), (X, Y) is globally
+ * optimal if ||G / gamma + U V^T||_2 <= 1, where G is the matrix of loss
+ * derivatives dL_j(x_i . y_j, A_ij) on the observed set (0 elsewhere; at a
+ * kink the derivative the fit uses) and X Y^T = U S V^T is the thin SVD.  U V^T
+ * is formed as X P Y^T with a k x k matrix P from the two Gram matrices
+ * (host, double); the spectral norm is estimated by `iters` power
+ * iterations on M^T M from a fixed start vector (SplitMix64 hash of the
+ * index), so info->norm increases toward the norm from below and
+ * info->norm_prev shows how far it still moves.  Requires rx and ry both
+ * GLRM_REG_QUADRATIC with the same weight > 0 (GLRM_EINVAL otherwise).  ws is
+ * glrm_linalg_workspace_size(d, 1) bytes; synchronizes `stream`. */
+int glrm_certificate(const glrm_data *d, const float *X, const float *Y, int32_t iters, glrm_cert_info *info,
+                     void *ws, size_t ws_bytes, unsigned flags, void *stream);
+
 /* In place V[i,:] <- prox_{alpha[i] r}(V[i,:]) for i < rows (Section 7.2,
  * prox_f(z) = argmin_x f(x) + 1/2 ||x - z||^2).  V is rows x k with leading
  * dimension ldv >= k (device); alpha has `rows` entries (device) or is NULL

@@ -65,6 +65,8 @@ def lib():
         L.oracle_loss_sum.argtypes = [P, P, P]
         L.oracle_loss_grad_rows.restype = None
         L.oracle_loss_grad_rows.argtypes = [P, P, P, P]
+        L.oracle_dloss_entries.restype = None
+        L.oracle_dloss_entries.argtypes = [P, P, P, P]
         L.oracle_loss_grad_abs_rows.restype = None
         L.oracle_loss_grad_abs_rows.argtypes = [P, P, P, P]
         L.oracle_half_step.restype = I64
@@ -246,6 +248,32 @@ class Problem:
         lib().oracle_loss_grad_abs_rows(ctypes.byref(self.row.s), _ptr(X), _ptr(Y), _ptr(aX))
         lib().oracle_loss_grad_abs_rows(ctypes.byref(self.colv.s), _ptr(Y), _ptr(X), _ptr(aY))
         return aX, aY
+
+    def grad_matrix(self, X, Y):
+        """The m x n matrix G of loss derivatives dL_j(x_i . y_j, A_ij) on the
+        observed set, 0 elsewhere (dense; small problems)."""
+        X, Y = _f64(X), _f64(Y)
+        g = np.empty(self.nnz)
+        lib().oracle_dloss_entries(ctypes.byref(self.row.s), _ptr(X), _ptr(Y), _ptr(g))
+        G = np.zeros((self.m, self.n))
+        rows = np.repeat(np.arange(self.m), np.diff(self.row.row_ptr))
+        G[rows, self.row.col] = g
+        return G
+
+    def certificate(self, X, Y, rtol=1e-6):
+        """Section 7.6: ||G / gamma + U V^T||_2 with X Y^T = U S V^T (singular
+        values above rtol times the largest) and gamma = 2 w for the
+        regularizer w ||.||^2 on both factors (the factored problem carries
+        gamma / 2).  At most 1 certifies (X, Y) globally optimal.  Returns
+        (norm, rank)."""
+        if self.rx[0] != 1 or self.ry[0] != 1 or self.rx[1] != self.ry[1] or not self.rx[1] > 0:
+            raise ValueError("the certificate needs the quadratic regularizer with one weight on both factors")
+        X, Y = _f64(X), _f64(Y)
+        gamma = 2.0 * self.rx[1]
+        U, s, Vt = np.linalg.svd(X @ Y.T, full_matrices=False)
+        r = int(np.sum(s > rtol * s[0])) if s.size and s[0] > 0 else 0
+        M = self.grad_matrix(X, Y) / gamma + U[:, :r] @ Vt[:r]
+        return float(np.linalg.norm(M, 2)), r
 
     def init_alpha(self, s=1.0):
         ax = np.empty(self.m)

@@ -177,6 +177,16 @@ void oracle_loss_grad_rows(const oracle_problem_t *P, const double *U, const dou
     }
 }
 
+/* The loss derivative of every observed entry, dL(u_i . v_j, A_ij), in the
+ * order of the list (the matrix G of Section 7.6 on the observed set). */
+void oracle_dloss_entries(const oracle_problem_t *P, const double *U, const double *V, double *out)
+{
+    const int32_t k = P->k;
+    for (int64_t i = 0; i < P->m; ++i)
+        for (int64_t e = P->row_ptr[i]; e < P->row_ptr[i + 1]; ++e)
+            out[e] = oracle_dloss(&P->losses[P->ecode[e]], dot(U + i * k, V + (int64_t)P->col[e] * k, k), P->val[e]);
+}
+
 /* Sum of the absolute terms of that gradient, dU_i = sum_j |dL(u_i . v_j, A_ij)| |v_j|
  * (coordinate-wise).  Not part of the method: it scales the rounding bound
  * of a gradient computed in finite precision, which the tests use to tell a

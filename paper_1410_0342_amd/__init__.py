@@ -16,7 +16,7 @@ __all__ = [
     "GLRMError", "Data", "glrm_workspace_size", "glrm_prepare", "glrm_objective", "glrm_grad", "glrm_prox",
     "glrm_fit", "glrm_last_error", "library_path", "FP32", "BF16", "FP64", "BF16_PLAIN", "DENSE", "COO_ROWSORTED",
     "WS_PREPARED", "TIME_KERNELS", "glrm_impute", "IMPUTE_ALL", "IMPUTE_MISSING", "glrm_grad_noalloc",
-    "NOALLOC_MAX_BYTES",
+    "NOALLOC_MAX_BYTES", "glrm_certificate", "glrm_linalg_workspace_size",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -67,6 +67,11 @@ class _FitInfo(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double * 4), ("kernel_calls", ctypes.c_int32 * 4)]
 
 
+class _CertInfo(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_double), ("norm_prev", ctypes.c_double), ("rank", ctypes.c_int32),
+                ("iters", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -93,6 +98,11 @@ def _L():
                                 ctypes.c_uint, P]
         L.glrm_grad_noalloc.restype = ctypes.c_int
         L.glrm_grad_noalloc.argtypes = [D, P, P, ctypes.c_int, P, P, ctypes.POINTER(ctypes.c_double), ctypes.c_uint, P]
+        L.glrm_linalg_workspace_size.restype = ctypes.c_size_t
+        L.glrm_linalg_workspace_size.argtypes = [D, ctypes.c_int32]
+        L.glrm_certificate.restype = ctypes.c_int
+        L.glrm_certificate.argtypes = [D, P, P, ctypes.c_int32, ctypes.POINTER(_CertInfo), P, ctypes.c_size_t,
+                                       ctypes.c_uint, P]
         L.glrm_prox.restype = ctypes.c_int
         L.glrm_prox.argtypes = [ctypes.POINTER(_Reg), P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, P, P]
         L.glrm_fit.restype = ctypes.c_int
@@ -207,10 +217,12 @@ class Data:
                     layout=self.layout, lda=self.s.lda if self.layout == DENSE else None, col_loss=self.col_loss,
                     losses=self.losses, rx=rx, ry=ry)
 
-    def workspace(self):
-        """Device workspace of glrm_workspace_size() bytes, 256-byte aligned, cached."""
+    def workspace(self, size=None):
+        """Device workspace of at least glrm_workspace_size() (or `size`) bytes,
+        256-byte aligned, cached.  Growing it starts a new buffer, whose
+        prepared part must be rebuilt (call glrm_prepare again)."""
         torch = _torch()
-        size = glrm_workspace_size(self)
+        size = max(glrm_workspace_size(self), size or 0)
         if self._ws is None or self._ws[1] < size:
             buf = torch.empty(size + 256, dtype=torch.uint8, device=self.device)
             off = (-buf.data_ptr()) % 256
@@ -280,6 +292,25 @@ def glrm_grad_noalloc(data, X, Y, precision=FP32, dX=None, dY=None, want_objecti
                                   _dev_ptr(dY, torch.float32, "dY", data.n * data.k),
                                   ctypes.byref(out) if want_objective else None, int(flags), _stream(stream)))
     return (dX, dY, out.value) if want_objective else (dX, dY)
+
+
+def glrm_linalg_workspace_size(data, block):
+    size = _L().glrm_linalg_workspace_size(ctypes.byref(data.s), int(block))
+    if size == 0:
+        raise GLRMError(EINVAL, glrm_last_error())
+    return size
+
+
+def glrm_certificate(data, X, Y, iters=500, flags=0, stream=None):
+    """The global-optimality certificate of Section 7.6: an estimate of
+    ||G / gamma + U V^T||_2 by power iteration (<= 1 certifies (X, Y))."""
+    torch = _torch()
+    ws, wsb = data.workspace(glrm_linalg_workspace_size(data, 1))
+    info = _CertInfo()
+    _check(_L().glrm_certificate(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
+                                 _dev_ptr(Y, torch.float32, "Y", data.n * data.k), int(iters), ctypes.byref(info),
+                                 ws, wsb, int(flags), _stream(stream)))
+    return dict(norm=info.norm, norm_prev=info.norm_prev, rank=info.rank, iters=info.iters)
 
 
 def glrm_prox(reg, V, alpha=None, stream=None):

@@ -28,11 +28,18 @@ struct CooLayout {
     size_t sort_tmp = 0, sort_tmp_bytes = 0;
     size_t flags = 0;      // int32 [4] validation result
     size_t part = 0, part_bytes = 0;  // double partials of the objective
-    size_t xs = 0;         // shadows of X for the column pass (m x kp, bf16 hi / lo)
-    size_t ys = 0;         // shadows of Y for the row pass (n x kp, bf16 hi / lo)
-    size_t yplus = 0;      // float [n x k] trial columns
-    size_t hcol = 0;       // float [n] column objectives
+    size_t xs = 0;         // padded copy of X (m x kp, fp32), updated in place by the row walk
+    size_t ys = 0;         // padded copy of Y (n x kp, fp32), updated in place by the column walk
 };
+
+// The parts of the COO region other passes read: the row pointers, the
+// column-grouped copy and the permutation that made it.
+struct CooView {
+    const int32_t *row_ptr, *col_ptr, *csc_row;
+    const float *csc_val;
+};
+CooView coo_view(const CooLayout &cl, char *base);
+const int32_t *coo_perm(const CooLayout &cl, char *base);
 
 void coo_layout(const glrm_data *d, int kp, CooLayout &cl);
 int coo_prepare(const glrm_data *d, int kp, const CooLayout &cl, char *base, int32_t *row_count, int32_t *col_count,

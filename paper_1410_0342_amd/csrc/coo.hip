@@ -54,8 +54,6 @@ void coo_layout(const glrm_data *d, int kp, CooLayout &cl)
     cl.part = take(cl.part_bytes);
     cl.xs = take(sizeof(float) * d->m * kp);
     cl.ys = take(sizeof(float) * d->n * kp);
-    cl.yplus = 0;
-    cl.hcol = 0;
 }
 
 struct CooPtrs {
@@ -87,6 +85,15 @@ static CooPtrs ptrs(const CooLayout &cl, char *b)
     p.ys = (float *)(b + cl.ys);
     return p;
 }
+
+CooView coo_view(const CooLayout &cl, char *base)
+{
+    CooPtrs p = ptrs(cl, base);
+    return CooView{p.row_ptr, p.col_ptr, p.csc_row, p.csc_val};
+}
+
+// perm_out[p] is the row-order position of the p-th entry of the column-grouped copy
+const int32_t *coo_perm(const CooLayout &cl, char *base) { return ptrs(cl, base).perm_out; }
 
 // ---- set-up kernels ------------------------------------------------------------
 

@@ -15,6 +15,8 @@
 #include "glrm_kernels.h"
 #include "coo.h"
 #include "impute.h"
+#include "linalg.h"
+#include "smallmat.h"
 
 using namespace glrm;
 
@@ -44,6 +46,7 @@ constexpr int64_t P_BYTES = 64ll << 20;  // ... and the Y-gradient partials with
 constexpr int P_GRAD = 256;    // row chunks of the one-pass loss gradient
 constexpr int REG_BLOCKS = 64; // partials of a regularizer sum
 constexpr int OBJ64_BLOCKS = 2048;  // workgroups (and partials) of the FP64 objective
+constexpr int AUX_SMALL = 16 * LA_MAXB * LA_MAXB;  // doubles of small matrices in the linear-algebra region
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -80,6 +83,13 @@ struct Layout {
     CooLayout cl;
     int64_t cb_grad;       // column blocks of the gradient kernel
     int tpw_grad;
+    // linear-algebra region (certificate, SVD initialization), when requested
+    int aux_b = 0;                       // vector block width
+    size_t aux_V = 0, aux_V2 = 0;        // entry-wise matrix (dense: mp x ldp; COO: row and column order)
+    size_t aux_m1 = 0, aux_m2 = 0;       // m x aux_b doubles
+    size_t aux_n1 = 0, aux_n2 = 0;       // n x aux_b doubles
+    size_t aux_part = 0;                 // partial sums
+    size_t aux_small = 0;                // AUX_SMALL doubles of small matrices
 
     size_t take(size_t bytes)
     {
@@ -91,7 +101,7 @@ struct Layout {
 
 // grad_only: the layout of the gradient entry points alone, whose Y-gradient
 // partials never exceed P_GRAD rows (the fit's run up to P_MAX).
-bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false)
+bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false, int aux_b = 0)
 {
     L = Layout();
     L.m = d->m;
@@ -151,6 +161,25 @@ bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false)
         L.coo = L.take(0);
         coo_layout(d, L.kp, L.cl);
         L.coo = L.take(L.cl.total);
+    }
+    if (aux_b > 0) {
+        const int64_t b = aux_b;
+        L.aux_b = aux_b;
+        if (d->layout == GLRM_DENSE) {
+            L.aux_V = L.take(sizeof(float) * L.mp * ldp);
+        } else {
+            L.aux_V = L.take(sizeof(float) * std::max<int64_t>(d->nnz, 1));
+            L.aux_V2 = L.take(sizeof(float) * std::max<int64_t>(d->nnz, 1));
+        }
+        L.aux_m1 = L.take(sizeof(double) * m * b);
+        L.aux_m2 = L.take(sizeof(double) * m * b);
+        L.aux_n1 = L.take(sizeof(double) * n * b);
+        L.aux_n2 = L.take(sizeof(double) * n * b);
+        const int64_t kb = std::max<int64_t>(kp, b);
+        const int64_t parts = std::max<int64_t>({(int64_t)LA_TCHUNKS * n * b,
+                                                 (int64_t)tall_tmul_blocks(std::max(m, n)) * kb * kb, 256});
+        L.aux_part = L.take(sizeof(double) * parts);
+        L.aux_small = L.take(sizeof(double) * AUX_SMALL);
     }
     return true;
 }
@@ -511,6 +540,60 @@ int scratch_address(void **out)
     *out = g_scratch_ptr[dev];
     return GLRM_OK;
 }
+// The entry-wise matrix of the loss derivatives at (X, Y) in the aux region:
+// dense, in the padded table's layout; COO, per entry in row order (aux_V) and
+// in the column-grouped order (aux_V2).
+int grad_matrix(const glrm_data *d, const Layout &L, const float *X, const float *Y, void *ws, hipStream_t st)
+{
+    EntryArgs ea;
+    memset(&ea, 0, sizeof ea);
+    ea.m = L.m; ea.n = L.n; ea.mp = L.mp; ea.ldp = L.ldp; ea.k = (int32_t)L.k;
+    ea.Ap = d->layout == GLRM_DENSE ? at<float>(ws, L.Ap) : nullptr;
+    ea.codes = at<uint8_t>(ws, L.codes);
+    ea.lt = make_losstab(d);
+    ea.X = X; ea.Y = Y;
+    if (d->layout == GLRM_DENSE) {
+        HIP_TRY(launch_dense_grad_matrix(ea, at<float>(ws, L.aux_V), st));
+    } else {
+        HIP_TRY(launch_coo_grad_values(ea, d->row, d->col, d->A, d->nnz, at<float>(ws, L.aux_V), st));
+        HIP_TRY(launch_permute(coo_perm(L.cl, at<char>(ws, L.coo)), at<float>(ws, L.aux_V), d->nnz,
+                               at<float>(ws, L.aux_V2), st));
+    }
+    return GLRM_OK;
+}
+
+// out (m x b) = alpha V B, or out (n x b) = alpha V^T B (transposed)
+int apply_matrix(const glrm_data *d, const Layout &L, void *ws, bool transposed, const double *B, int32_t b,
+                 double alpha, double *out, hipStream_t st)
+{
+    if (d->layout == GLRM_DENSE) {
+        if (!transposed) HIP_TRY(launch_dense_apply(at<float>(ws, L.aux_V), L.m, L.n, L.ldp, B, b, alpha, out, st));
+        else HIP_TRY(launch_dense_apply_t(at<float>(ws, L.aux_V), L.m, L.n, L.ldp, B, b, alpha,
+                                          at<double>(ws, L.aux_part), out, st));
+    } else {
+        const CooView cv = coo_view(L.cl, at<char>(ws, L.coo));
+        if (!transposed) HIP_TRY(launch_seg_apply(cv.row_ptr, d->col, at<float>(ws, L.aux_V), L.m, B, b, alpha, out, st));
+        else HIP_TRY(launch_seg_apply(cv.col_ptr, cv.csc_row, at<float>(ws, L.aux_V2), L.n, B, b, alpha, out, st));
+    }
+    return GLRM_OK;
+}
+
+// Gram matrices of both factors, to the host.
+int gram_pair(const Layout &L, const float *X, const float *Y, void *ws, std::vector<double> &Gx,
+              std::vector<double> &Gy, hipStream_t st)
+{
+    const int k = (int)L.k;
+    double *part = at<double>(ws, L.aux_part), *sm = at<double>(ws, L.aux_small);
+    HIP_TRY(launch_gram_f(X, L.m, k, part, sm, st));
+    HIP_TRY(launch_gram_f(Y, L.n, k, part, sm + k * k, st));
+    Gx.assign((size_t)k * k, 0.0);
+    Gy.assign((size_t)k * k, 0.0);
+    HIP_TRY(hipMemcpyAsync(Gx.data(), sm, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(Gy.data(), sm + k * k, sizeof(double) * k * k, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GLRM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -605,6 +688,81 @@ int glrm_grad_noalloc(const glrm_data *d, const float *X, const float *Y, int pr
     if ((rc = scratch_address(&ws))) return rc;
     return grad_run(d, L, X, Y, precision, dX, dY, obj_host, ws, flags, (hipStream_t)stream);
 }
+size_t glrm_linalg_workspace_size(const glrm_data *d, int32_t block)
+{
+    if (validate_data(d) != GLRM_OK) return 0;
+    if (block < 1 || block > LA_MAXB) {
+        fail(GLRM_EINVAL, "block must be in 1..%d", LA_MAXB);
+        return 0;
+    }
+    Layout L;
+    make_layout(d, L, false, block);
+    return L.total;
+}
+
+int glrm_certificate(const glrm_data *d, const float *X, const float *Y, int32_t iters, glrm_cert_info *info,
+                     void *ws, size_t ws_bytes, unsigned flags, void *stream)
+{
+    g_err.clear();
+    int rc = validate_data(d);
+    if (rc) return rc;
+    if (!X || !Y || !info) return fail(GLRM_EINVAL, "X, Y and info must not be NULL");
+    if (iters < 1 || iters > 1000000) return fail(GLRM_EINVAL, "iters must be in 1..1e6");
+    if (d->rx.kind != GLRM_REG_QUADRATIC || d->ry.kind != GLRM_REG_QUADRATIC || d->rx.weight != d->ry.weight ||
+        !(d->rx.weight > 0.0f))
+        return fail(GLRM_EINVAL, "the certificate needs the quadratic regularizer with one weight > 0 on both factors");
+    Layout L;
+    make_layout(d, L, false, 1);
+    if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    const int k = (int)L.k;
+    // weight w on ||x||^2 is the factored problem's gamma / 2
+    const double inv_gamma = 1.0 / (2.0 * (double)d->rx.weight);
+    if ((rc = grad_matrix(d, L, X, Y, ws, st))) return rc;
+    std::vector<double> Gx, Gy;
+    if ((rc = gram_pair(L, X, Y, ws, Gx, Gy, st))) return rc;
+    std::vector<double> P((size_t)k * k), Pt((size_t)k * k), sv(k);
+    const int rank = glrm_host::polar_map(k, Gx.data(), Gy.data(), 1e-6, P.data(), sv.data());
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) Pt[j * k + i] = P[i * k + j];
+    double *sm = at<double>(ws, L.aux_small);
+    double *Pd = sm, *Ptd = sm + k * k, *tv = sm + 2 * k * k, *sv_d = tv + LA_MAXB, *nrm = sv_d + LA_MAXB;
+    double *est = nrm + 4;
+    HIP_TRY(hipMemcpyAsync(Pd, P.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(Ptd, Pt.data(), sizeof(double) * k * k, hipMemcpyHostToDevice, st));
+    double *part = at<double>(ws, L.aux_part);
+    double *u = at<double>(ws, L.aux_m1), *v = at<double>(ws, L.aux_n1), *w = at<double>(ws, L.aux_n2);
+    HIP_TRY(launch_start_vector(v, L.n, 0x14100342ull, st));
+    HIP_TRY(launch_sumsq(v, L.n, part, nrm, st));
+    HIP_TRY(launch_normalize(v, L.n, nrm, nullptr, 0, st));
+    for (int it = 0; it < iters; ++it) {
+        // u = M v = G v / gamma + X P Y^T v
+        if ((rc = apply_matrix(d, L, ws, false, v, 1, inv_gamma, u, st))) return rc;
+        HIP_TRY(launch_tall_tmul_f(Y, L.n, k, k, v, 1, part, tv, st));
+        HIP_TRY(launch_tall_mul_d(Pd, k, k, k, tv, 1, 1.0, 0.0, sv_d, st));
+        HIP_TRY(launch_tall_mul_f(X, L.m, k, k, sv_d, 1, 1.0, 1.0, u, st));
+        HIP_TRY(launch_sumsq(u, L.m, part, nrm, st));
+        HIP_TRY(launch_normalize(nullptr, 0, nrm, est, it & 1, st));
+        // w = M^T u = G^T u / gamma + Y P^T X^T u, then v = w / ||w||
+        if ((rc = apply_matrix(d, L, ws, true, u, 1, inv_gamma, w, st))) return rc;
+        HIP_TRY(launch_tall_tmul_f(X, L.m, k, k, u, 1, part, tv, st));
+        HIP_TRY(launch_tall_mul_d(Ptd, k, k, k, tv, 1, 1.0, 0.0, sv_d, st));
+        HIP_TRY(launch_tall_mul_f(Y, L.n, k, k, sv_d, 1, 1.0, 1.0, w, st));
+        HIP_TRY(launch_sumsq(w, L.n, part, nrm + 1, st));
+        HIP_TRY(launch_normalize(w, L.n, nrm + 1, nullptr, 0, st));
+        std::swap(v, w);
+    }
+    double e2[2] = {0.0, 0.0};
+    HIP_TRY(hipMemcpyAsync(e2, est, sizeof e2, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    info->norm = e2[(iters - 1) & 1];
+    info->norm_prev = iters > 1 ? e2[iters & 1] : NAN;
+    info->rank = rank;
+    info->iters = iters;
+    return GLRM_OK;
+}
+
 int glrm_impute(const glrm_data *d, const float *X, const float *Y, int32_t mode, float *Ahat, int64_t ldh, void *ws,
                 size_t ws_bytes, unsigned flags, void *stream)
 {

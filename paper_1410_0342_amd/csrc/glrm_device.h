@@ -184,6 +184,26 @@ __device__ __forceinline__ double loss_l64(int kind, int levels, double param, d
     }
 }
 
+// Double precision loss derivative, with the same choice at each kink as the
+// float form (the strict-inequality branch).
+__device__ __forceinline__ double loss_g64(int kind, int levels, double param, double u, double a)
+{
+    switch (kind) {
+    case L_QUAD: return 2.0 * (u - a);
+    case L_HUBER: {
+        const double r = u - a;
+        return fabs(r) <= param ? r : (r > 0.0 ? param : -param);
+    }
+    case L_LOGISTIC: return -a / (1.0 + exp(a * u));
+    case L_HINGE: return !(a * u >= 1.0) ? -a : 0.0;
+    default: {
+        double l, g;
+        ordinal_loss<double>(u, a, levels, l, g, true);
+        return g;
+    }
+    }
+}
+
 // ---- regularizers -------------------------------------------------------------
 
 // One coordinate's share of r(x) (the sum over coordinates is r).

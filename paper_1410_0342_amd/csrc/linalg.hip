@@ -1,0 +1,453 @@
+// Kernels of the linear algebra around the fit (declared in linalg.h): the
+// matrices defined entry by entry on the observed set, their products with
+// blocks of vectors, tall-skinny products with the factors, and vector
+// reductions.  Everything is summed in double and in a fixed order, so each
+// result is reproducible.  None of this is on the sweep's hot path: these
+// serve the certificate of Section 7.6 (a few hundred matrix-vector pairs)
+// and the randomized SVD of Section 7.5 (a few block products).
+#include <algorithm>
+
+#include "glrm_kernels.h"
+#include "linalg.h"
+
+namespace glrm {
+
+static unsigned nblk(int64_t n, int per = 256) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
+
+// ---- entry-wise matrices -------------------------------------------------------
+
+// One workgroup per padded table row; x_i staged in LDS, z = x_i . y_j and the
+// derivative in double (the branch at a kink is taken on the double product).
+__global__ __launch_bounds__(256) void dense_grad_matrix_kernel(EntryArgs a, float *V)
+{
+    __shared__ float sx[GLRM_MAXK_DEV];
+    const int64_t i = blockIdx.x;
+    if (threadIdx.x < a.k) sx[threadIdx.x] = i < a.m ? a.X[i * a.k + threadIdx.x] : 0.0f;
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < a.ldp; j += 256) {
+        float out = 0.0f;
+        const float av = a.Ap[i * a.ldp + j];
+        if (i < a.m && j < a.n && av == av) {
+            double z = 0.0;
+            for (int l = 0; l < a.k; ++l) z += (double)sx[l] * (double)a.Y[j * a.k + l];
+            const int q = a.lt.uniform >= 0 ? a.lt.uniform : a.codes[j];
+            const double gv = loss_g64(a.lt.kind[q], a.lt.levels[q], (double)a.lt.param[q], z, (double)av);
+            out = (float)(a.colw ? gv * (double)a.colw[j] : gv);
+        }
+        V[i * a.ldp + j] = out;
+    }
+}
+
+hipError_t launch_dense_grad_matrix(const EntryArgs &a, float *V, hipStream_t st)
+{
+    hipLaunchKernelGGL(dense_grad_matrix_kernel, dim3((unsigned)a.mp), dim3(256), 0, st, a, V);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void dense_scaled_matrix_kernel(EntryArgs a, float *V)
+{
+    const int64_t i = blockIdx.x;
+    for (int64_t j = threadIdx.x; j < a.ldp; j += 256) {
+        const float av = a.Ap[i * a.ldp + j];
+        V[i * a.ldp + j] = (i < a.m && j < a.n && av == av) ? a.cs[j] * (av - a.mu[j]) : 0.0f;
+    }
+}
+
+hipError_t launch_dense_scaled_matrix(const EntryArgs &a, float *V, hipStream_t st)
+{
+    hipLaunchKernelGGL(dense_scaled_matrix_kernel, dim3((unsigned)a.mp), dim3(256), 0, st, a, V);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void coo_grad_values_kernel(EntryArgs a, const int32_t *row, const int32_t *col,
+                                                              const float *A, int64_t nnz, float *out)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nnz) return;
+    const int64_t i = row[e], j = col[e];
+    double z = 0.0;
+    for (int l = 0; l < a.k; ++l) z += (double)a.X[i * a.k + l] * (double)a.Y[j * a.k + l];
+    const int q = a.lt.uniform >= 0 ? a.lt.uniform : a.codes[j];
+    const double gv = loss_g64(a.lt.kind[q], a.lt.levels[q], (double)a.lt.param[q], z, (double)A[e]);
+    out[e] = (float)(a.colw ? gv * (double)a.colw[j] : gv);
+}
+
+hipError_t launch_coo_grad_values(const EntryArgs &a, const int32_t *row, const int32_t *col, const float *A,
+                                  int64_t nnz, float *out, hipStream_t st)
+{
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(coo_grad_values_kernel, dim3(nblk(nnz)), dim3(256), 0, st, a, row, col, A, nnz, out);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void coo_scaled_values_kernel(EntryArgs a, const int32_t *col, const float *A,
+                                                                int64_t nnz, float *out)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nnz) return;
+    const int64_t j = col[e];
+    out[e] = a.cs[j] * (A[e] - a.mu[j]);
+}
+
+hipError_t launch_coo_scaled_values(const EntryArgs &a, const int32_t *col, const float *A, int64_t nnz, float *out,
+                                    hipStream_t st)
+{
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(coo_scaled_values_kernel, dim3(nblk(nnz)), dim3(256), 0, st, a, col, A, nnz, out);
+    return hipGetLastError();
+}
+
+__global__ void permute_kernel(const int32_t *perm, const float *in, int64_t nnz, float *out)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < nnz) out[p] = in[perm[p]];
+}
+
+hipError_t launch_permute(const int32_t *perm, const float *in, int64_t nnz, float *out, hipStream_t st)
+{
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(permute_kernel, dim3(nblk(nnz)), dim3(256), 0, st, perm, in, nnz, out);
+    return hipGetLastError();
+}
+
+// ---- the table's matrix times a block of vectors -----------------------------------
+
+constexpr int LA_Q = LA_MAXB / 16;   // outputs per thread along the block
+
+// out (m x b) = alpha V B.  A workgroup owns 16 rows; 64-column slices of V and
+// of B go through LDS; thread (r, cl) accumulates row r's outputs cl + 16 q.
+__global__ __launch_bounds__(256) void dense_apply_kernel(const float *V, int64_t m, int64_t n, int64_t ldp,
+                                                          const double *B, int32_t b, double alpha, double *out)
+{
+    __shared__ float sV[16][65];
+    __shared__ double sB[64][LA_MAXB + 1];
+    const int t = threadIdx.x, r = t >> 4, cl = t & 15;
+    const int64_t i0 = (int64_t)blockIdx.x * 16;
+    double acc[LA_Q];
+#pragma unroll
+    for (int q = 0; q < LA_Q; ++q) acc[q] = 0.0;
+    for (int64_t j0 = 0; j0 < n; j0 += 64) {
+        for (int e = t; e < 16 * 64; e += 256) {
+            const int rr = e >> 6, jj = e & 63;
+            const int64_t i = i0 + rr, j = j0 + jj;
+            sV[rr][jj] = (i < m && j < n) ? V[i * ldp + j] : 0.0f;
+        }
+        for (int e = t; e < 64 * b; e += 256) {
+            const int jj = e / b, c = e % b;
+            const int64_t j = j0 + jj;
+            sB[jj][c] = j < n ? B[j * b + c] : 0.0;
+        }
+        __syncthreads();
+        const int jn = (int)min<int64_t>(64, n - j0);
+        for (int jj = 0; jj < jn; ++jj) {
+            const double v = (double)sV[r][jj];
+#pragma unroll
+            for (int q = 0; q < LA_Q; ++q) {
+                const int c = cl + 16 * q;
+                if (c < b) acc[q] += v * sB[jj][c];
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t i = i0 + r;
+    if (i < m) {
+#pragma unroll
+        for (int q = 0; q < LA_Q; ++q) {
+            const int c = cl + 16 * q;
+            if (c < b) out[i * b + c] = alpha * acc[q];
+        }
+    }
+}
+
+hipError_t launch_dense_apply(const float *V, int64_t m, int64_t n, int64_t ldp, const double *B, int32_t b,
+                              double alpha, double *out, hipStream_t st)
+{
+    if (b < 1 || b > LA_MAXB) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(dense_apply_kernel, dim3(nblk(m, 16)), dim3(256), 0, st, V, m, n, ldp, B, b, alpha, out);
+    return hipGetLastError();
+}
+
+// Partials of V^T Q: workgroup (column block of 16, row chunk); rows go through
+// LDS in slices of 64.
+__global__ __launch_bounds__(256) void dense_apply_t_kernel(const float *V, int64_t m, int64_t n, int64_t ldp,
+                                                            const double *Q, int32_t b, int64_t per, double *part)
+{
+    __shared__ float sV[64][17];
+    __shared__ double sQ[64][LA_MAXB + 1];
+    const int t = threadIdx.x, jj = t >> 4, cl = t & 15;
+    const int64_t j0 = (int64_t)blockIdx.x * 16;
+    const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min<int64_t>(m, r0 + per);
+    double acc[LA_Q];
+#pragma unroll
+    for (int q = 0; q < LA_Q; ++q) acc[q] = 0.0;
+    for (int64_t i0 = r0; i0 < r1; i0 += 64) {
+        for (int e = t; e < 64 * 16; e += 256) {
+            const int ii = e >> 4, c = e & 15;
+            const int64_t i = i0 + ii, j = j0 + c;
+            sV[ii][c] = (i < r1 && j < n) ? V[i * ldp + j] : 0.0f;
+        }
+        for (int e = t; e < 64 * b; e += 256) {
+            const int ii = e / b, c = e % b;
+            const int64_t i = i0 + ii;
+            sQ[ii][c] = i < r1 ? Q[i * b + c] : 0.0;
+        }
+        __syncthreads();
+        const int in_ = (int)min<int64_t>(64, r1 - i0);
+        for (int ii = 0; ii < in_; ++ii) {
+            const double v = (double)sV[ii][jj];
+#pragma unroll
+            for (int q = 0; q < LA_Q; ++q) {
+                const int c = cl + 16 * q;
+                if (c < b) acc[q] += v * sQ[ii][c];
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t j = j0 + jj;
+    if (j < n) {
+#pragma unroll
+        for (int q = 0; q < LA_Q; ++q) {
+            const int c = cl + 16 * q;
+            if (c < b) part[((int64_t)blockIdx.y * n + j) * b + c] = acc[q];
+        }
+    }
+}
+
+// out[e] = alpha * sum_p part[p][e] over p = 0..np-1, in that order.
+__global__ void reduce_parts_kernel(const double *part, int32_t np, int64_t len, double alpha, double *out)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= len) return;
+    double s = 0.0;
+    for (int p = 0; p < np; ++p) s += part[(int64_t)p * len + e];
+    out[e] = alpha * s;
+}
+
+int dense_apply_t_chunks(int64_t m, int64_t n)
+{
+    const int64_t cblocks = (n + 15) / 16;
+    const int64_t want = std::max<int64_t>(1, 2048 / cblocks);
+    return (int)std::min<int64_t>({want, (int64_t)LA_TCHUNKS, std::max<int64_t>(1, (m + 63) / 64)});
+}
+
+hipError_t launch_dense_apply_t(const float *V, int64_t m, int64_t n, int64_t ldp, const double *Q, int32_t b,
+                                double alpha, double *part, double *out, hipStream_t st)
+{
+    if (b < 1 || b > LA_MAXB) return hipErrorInvalidValue;
+    const int ch = dense_apply_t_chunks(m, n);
+    const int64_t per = (m + ch - 1) / ch;
+    hipLaunchKernelGGL(dense_apply_t_kernel, dim3(nblk(n, 16), ch), dim3(256), 0, st, V, m, n, ldp, Q, b, per,
+                       part);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(n * b)), dim3(256), 0, st, part, ch, n * b, alpha, out);
+    return hipGetLastError();
+}
+
+// One wavefront per segment (row of the row view, or column of the column
+// view).  Narrow blocks: lanes take every 64th entry and the lanes' sums are
+// combined by a butterfly; wide blocks: lanes take output columns.
+__global__ __launch_bounds__(256) void seg_apply_kernel(const int32_t *ptr, const int32_t *idx, const float *val,
+                                                        int64_t rows, const double *B, int32_t b, double alpha,
+                                                        double *out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= rows) return;
+    const int32_t beg = ptr[r], end = ptr[r + 1];
+    if (b <= 4) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int32_t e = beg + lane; e < end; e += 64) {
+            const double v = (double)val[e];
+            const int64_t j = idx[e];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (c < b) acc[c] += v * B[j * b + c];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double s = acc[c];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+            if (c < b && lane == 0) out[r * b + c] = alpha * s;
+        }
+    } else {
+        for (int c0 = 0; c0 < b; c0 += 64) {
+            const int c = c0 + lane;
+            double acc = 0.0;
+            for (int32_t e = beg; e < end; ++e)
+                if (c < b) acc += (double)val[e] * B[(int64_t)idx[e] * b + c];
+            if (c < b) out[r * b + c] = alpha * acc;
+        }
+    }
+}
+
+hipError_t launch_seg_apply(const int32_t *ptr, const int32_t *idx, const float *val, int64_t rows, const double *B,
+                            int32_t b, double alpha, double *out, hipStream_t st)
+{
+    if (b < 1 || b > LA_MAXB) return hipErrorInvalidValue;
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(seg_apply_kernel, dim3(nblk(rows, 4)), dim3(256), 0, st, ptr, idx, val, rows, B, b, alpha,
+                       out);
+    return hipGetLastError();
+}
+
+// ---- tall-skinny products ----------------------------------------------------------
+
+constexpr int TALL_ROWS = 1024;     // rows per workgroup of U^T B
+
+int tall_tmul_blocks(int64_t rows) { return (int)std::min<int64_t>(4096, std::max<int64_t>(1, (rows + TALL_ROWS - 1) / TALL_ROWS)); }
+
+// part[blk][l b + c] = sum over the workgroup's rows of U[i, l] B[i, c]
+template <typename TU, typename TB>
+__global__ __launch_bounds__(256) void tall_tmul_kernel(const TU *U, int64_t rows, int32_t k, int64_t ldu,
+                                                        const TB *B, int64_t ldb, int32_t b, int64_t per,
+                                                        double *part)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min<int64_t>(rows, i0 + per);
+    const int np = k * b;
+    for (int p0 = 0; p0 < np; p0 += 256) {
+        const int p = p0 + threadIdx.x;
+        if (p < np) {
+            const int l = p / b, c = p % b;
+            double acc = 0.0;
+            for (int64_t i = i0; i < i1; ++i) acc += (double)U[i * ldu + l] * (double)B[i * ldb + c];
+            part[(int64_t)blockIdx.x * np + p] = acc;
+        }
+    }
+}
+
+template <typename TU, typename TB>
+static hipError_t tall_tmul(const TU *U, int64_t rows, int32_t k, int64_t ldu, const TB *B, int64_t ldb, int32_t b,
+                            double *part, double *out, hipStream_t st)
+{
+    const int nb = tall_tmul_blocks(rows);
+    const int64_t per = (rows + nb - 1) / nb;
+    hipLaunchKernelGGL((tall_tmul_kernel<TU, TB>), dim3(nb), dim3(256), 0, st, U, rows, k, ldu, B, ldb, b, per, part);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk((int64_t)k * b)), dim3(256), 0, st, part, nb, (int64_t)k * b,
+                       1.0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_tall_tmul_f(const float *U, int64_t rows, int32_t k, int64_t ldu, const double *B, int32_t b,
+                              double *part, double *out, hipStream_t st)
+{
+    return tall_tmul<float, double>(U, rows, k, ldu, B, b, b, part, out, st);
+}
+
+hipError_t launch_tall_tmul_d(const double *U, int64_t rows, int32_t k, int64_t ldu, const double *B, int32_t b,
+                              double *part, double *out, hipStream_t st)
+{
+    return tall_tmul<double, double>(U, rows, k, ldu, B, b, b, part, out, st);
+}
+
+hipError_t launch_gram_f(const float *U, int64_t rows, int32_t k, double *part, double *out, hipStream_t st)
+{
+    return tall_tmul<float, float>(U, rows, k, k, U, k, k, part, out, st);
+}
+
+template <typename TU>
+__global__ void tall_mul_kernel(const TU *U, int64_t rows, int32_t k, int64_t ldu, const double *S, int32_t b,
+                                double alpha, double beta, double *out)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= rows * b) return;
+    const int64_t i = t / b;
+    const int c = (int)(t % b);
+    double acc = 0.0;
+    for (int l = 0; l < k; ++l) acc += (double)U[i * ldu + l] * S[l * b + c];
+    out[t] = (beta == 0.0 ? 0.0 : beta * out[t]) + alpha * acc;
+}
+
+hipError_t launch_tall_mul_f(const float *U, int64_t rows, int32_t k, int64_t ldu, const double *S, int32_t b,
+                             double alpha, double beta, double *out, hipStream_t st)
+{
+    if (rows * b <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tall_mul_kernel<float>, dim3(nblk(rows * b)), dim3(256), 0, st, U, rows, k, ldu, S, b, alpha,
+                       beta, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_tall_mul_d(const double *U, int64_t rows, int32_t k, int64_t ldu, const double *S, int32_t b,
+                             double alpha, double beta, double *out, hipStream_t st)
+{
+    if (rows * b <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tall_mul_kernel<double>, dim3(nblk(rows * b)), dim3(256), 0, st, U, rows, k, ldu, S, b, alpha,
+                       beta, out);
+    return hipGetLastError();
+}
+
+// ---- vectors -------------------------------------------------------------------------
+
+constexpr int SUMSQ_BLOCKS = 256;
+
+__global__ __launch_bounds__(256) void sumsq_kernel(const double *v, int64_t len, double *part)
+{
+    __shared__ double s[4];
+    double acc = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256)
+        acc += v[t] * v[t];
+    acc = sum_lanes64<64>(acc);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
+}
+
+hipError_t launch_sumsq(const double *v, int64_t len, double *part, double *nrm2, hipStream_t st)
+{
+    hipLaunchKernelGGL(sumsq_kernel, dim3(SUMSQ_BLOCKS), dim3(256), 0, st, v, len, part);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, st, part, SUMSQ_BLOCKS, (int64_t)1, 1.0, nrm2);
+    return hipGetLastError();
+}
+
+__global__ void normalize_kernel(double *v, int64_t len, const double *nrm2, double *est, int32_t slot)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const double nv = sqrt(*nrm2);
+    if (t == 0 && est) est[slot] = nv;
+    if (v && t < len && nv > 0.0) v[t] /= nv;
+}
+
+hipError_t launch_normalize(double *v, int64_t len, const double *nrm2, double *est, int32_t slot, hipStream_t st)
+{
+    hipLaunchKernelGGL(normalize_kernel, dim3(nblk(std::max<int64_t>(len, 1))), dim3(256), 0, st, v, len, nrm2, est,
+                       slot);
+    return hipGetLastError();
+}
+
+__global__ void start_vector_kernel(double *v, int64_t len, uint64_t seed)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= len) return;
+    // SplitMix64 (Steele, Lea, Flood 2014) of the counter seed + t
+    uint64_t z = seed + (uint64_t)t * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    v[t] = 1.0 + (double)(z >> 11) * 0x1.0p-53;
+}
+
+hipError_t launch_start_vector(double *v, int64_t len, uint64_t seed, hipStream_t st)
+{
+    if (len <= 0) return hipSuccess;
+    hipLaunchKernelGGL(start_vector_kernel, dim3(nblk(len)), dim3(256), 0, st, v, len, seed);
+    return hipGetLastError();
+}
+
+__global__ void to_float_kernel(const double *src, int64_t rows, int32_t b, int32_t cols, float *dst, int64_t ldd,
+                                int32_t col0)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= rows * cols) return;
+    const int64_t i = t / cols;
+    const int c = (int)(t % cols);
+    dst[i * ldd + col0 + c] = (float)src[i * b + c];
+}
+
+hipError_t launch_to_float(const double *src, int64_t rows, int32_t b, int32_t cols, float *dst, int64_t ldd,
+                           int32_t col0, hipStream_t st)
+{
+    if (rows * cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(to_float_kernel, dim3(nblk(rows * cols)), dim3(256), 0, st, src, rows, b, cols, dst, ldd, col0);
+    return hipGetLastError();
+}
+
+}  // namespace glrm

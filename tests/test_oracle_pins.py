@@ -332,26 +332,45 @@ def test_dense_and_coo_forms_agree():
     assert Pd.objective(X, Y) == Pc.objective(X, Y)
 
 
+def test_certificate_at_zero_is_the_scaled_top_singular_value():
+    """Section 7.6 at X = Y = 0: U V^T vanishes (rank 0) and, for the quadratic
+    loss on a fully observed table, G = 2 (0 - A), so the certificate is
+    2 sigma_1(A) / gamma with gamma = 2 w (numpy's SVD of A)."""
+    c = synth.plain_pca(m=30, n=20, k=3)
+    w = 0.7
+    P = oracle.Problem.from_dense(c.A, None, c.k, c.col_loss, c.losses, (1, w), (1, w))
+    val, r = P.certificate(np.zeros((c.m, c.k)), np.zeros((c.n, c.k)))
+    s = np.linalg.svd(c.A.astype(np.float64), compute_uv=False)
+    assert r == 0
+    assert val == pytest.approx(2.0 * s[0] / (2.0 * w), rel=1e-12)
+
+
+def test_certificate_at_the_quadratic_pca_optimum_is_the_next_singular_value():
+    """Quadratic loss, full table, w ||.||^2 on both factors: the global optimum
+    (Section 2.2, Appendix A) is X = U_k diag(sqrt(s_i - w)), Y = V_k diag(
+    sqrt(s_i - w)).  Then G / (2w) = (Z - A) / w cancels U_k V_k^T and leaves
+    -sum_{i>k} (s_i / w) u_i v_i^T, so the certificate equals s_{k+1} / w:
+    <= 1 exactly when s_{k+1} <= w."""
+    c = synth.plain_pca(m=40, n=25, k=4)
+    A = c.A.astype(np.float64)
+    U, s, Vt = np.linalg.svd(A, full_matrices=False)
+    for w in (0.5 * (s[c.k - 1] + s[c.k]), 0.5 * s[c.k]):
+        X = U[:, :c.k] * np.sqrt(s[:c.k] - w)
+        Y = Vt[:c.k].T * np.sqrt(s[:c.k] - w)
+        P = oracle.Problem.from_dense(c.A, None, c.k, c.col_loss, c.losses, (1, w), (1, w))
+        val, r = P.certificate(X, Y)
+        assert r == c.k
+        assert val == pytest.approx(s[c.k] / w, rel=1e-9)
+
+
 def test_global_optimality_certificate_after_convergence():
     """Convex loss + quadratic regularizer with missing entries (Section 7.6):
-    at a global optimum ||G / gamma' + U V^T||_2 <= 1, where gamma' = 2 gamma
-    because the regularizer here is gamma ||x||^2 (the factored problem of
-    Section 7.6 carries gamma'/2), G is the loss gradient matrix (zero off
-    Omega) and XY = U S V^T.  The converged fit must satisfy it; an
-    unconverged start must not."""
+    the converged fit certifies (norm <= 1); the random start does not."""
     c = synth.dense_quadratic(m=40, n=30, k=4, missing=0.3, gamma=2.0, config=12)
     P = _problem(c)
-
-    def cert(X, Y):
-        Z = X @ Y.T
-        G = np.where(c.mask.astype(bool), 2.0 * (Z - c.A.astype(np.float64)), 0.0)
-        U, s, Vt = np.linalg.svd(Z, full_matrices=False)
-        r = int(np.sum(s > 1e-8 * s[0]))
-        return np.linalg.norm(G / (2 * 2.0) + U[:, :r] @ Vt[:r], 2)
-
     X, Y, *_ = P.fit(c.X0, c.Y0, 4000)
-    assert cert(X, Y) <= 1.0 + 1e-4
-    assert cert(c.X0.astype(np.float64), c.Y0.astype(np.float64)) > 1.0 + 1e-2
+    assert P.certificate(X, Y)[0] <= 1.0 + 1e-4
+    assert P.certificate(c.X0, c.Y0)[0] > 1.0 + 1e-2
 
 
 # ---- imputation decode (Section 5.3) ------------------------------------------
