@@ -121,6 +121,16 @@ typedef struct {
     int32_t          n_losses;/* 1 .. GLRM_MAX_LOSSES */
     glrm_reg rx;              /* r on the rows of X */
     glrm_reg ry;              /* rt on the columns of the paper's Y */
+    /* Offset (Section 3.3): 1 = coordinate 0 of every x_i is the constant 1 and
+     * coordinate 0 of every y_j a free, unpenalized column offset, so the model
+     * is x_i . y_j = mu_j + (the other k - 1 coordinates); r and rt apply to
+     * coordinates 1..k-1 only, and an x_i whose coordinate 0 is not 1 is
+     * infeasible (r = +inf; the prox sets it to 1).  0 = no offset. */
+    int32_t offset;
+    /* Per-column loss weights (device, n floats, finite and >= 0; NULL = all 1):
+     * column j's loss becomes col_weight[j] * L_j, e.g. 1 / sigma_j^2 for the
+     * scaled losses of Section 4.3 (glrm_column_scaling). */
+    const float *col_weight;
 } glrm_data;
 
 /* Flags for the compute entry points. */
@@ -210,12 +220,51 @@ typedef struct {
 int glrm_certificate(const glrm_data *d, const float *X, const float *Y, int32_t iters, glrm_cert_info *info,
                      void *ws, size_t ws_bytes, unsigned flags, void *stream);
 
+/* Automatic loss scaling of Section 4.3: for every column j,
+ *     mu_j     = argmin_mu sum_{i:(i,j) in Omega} L_j(mu, A_ij)
+ *     sigma2_j = sum_{i:(i,j) in Omega} L_j(mu_j, A_ij) / (n_j - 1)
+ * (the mean and the sample variance for the quadratic loss).  mu_j is the
+ * minimizer over [min_i A_ij - 1, max_i A_ij + 1], found by 64 bisection
+ * steps on the sign of the derivative sum in double (one pass over the data
+ * each); where the minimizer is not unique (hinge, ordinal hinge) it is one of
+ * them, and a logistic column with one label only gets the bracket's end.
+ * sigma2_j = 1 for a column with fewer than two entries or a zero minimum;
+ * mu_j = 0 for an empty column.  mu and sigma2 are n floats (device).  ws is
+ * glrm_linalg_workspace_size(d, 1) bytes; asynchronous except for
+ * preparation. */
+int glrm_column_scaling(const glrm_data *d, float *mu, float *sigma2, void *ws, size_t ws_bytes, unsigned flags,
+                        void *stream);
+
+/* SVD initialization of Section 7.5.  The standardized table
+ *     At_ij = m / (sigma_j m_j) (A_ij - mu_j)  on Omega, 0 elsewhere
+ * (m_j = observations in column j; mu = NULL is 0, sigma2 = NULL is 1) is
+ * sketched by the randomized range finder of Halko, Martinsson and Tropp
+ * (2011): Q = orth(At Omega) from the caller's test matrix omega (n x l floats,
+ * device, e.g. i.i.d. N(0, 1); l >= k', at most 96), power_iters rounds of
+ * Q = orth(At orth(At^T Q)), then the SVD of Q^T At from its l x l Gram matrix
+ * (host, double).  With the top k' singular triples (U, S, V):
+ *     X = U S^1/2,   Y = diag(sigma) V S^1/2   (Y stored n x k, row j = y_j)
+ * where k' = k, or k - 1 with d->offset, in which case coordinate 0 holds the
+ * offset: x_i0 = 1 and y_j0 = mu_j (mu required).  Triples with singular value
+ * below 1e-6 of the largest (a table of lower rank) leave their coordinates 0.
+ * sv_host (host, k' doubles, may be NULL) receives the singular values.  ws is
+ * glrm_linalg_workspace_size(d, l) bytes; synchronizes `stream`. */
+int glrm_init_svd(const glrm_data *d, const float *mu, const float *sigma2, const float *omega, int32_t l,
+                  int32_t power_iters, float *X, float *Y, double *sv_host, void *ws, size_t ws_bytes,
+                  unsigned flags, void *stream);
+
 /* In place V[i,:] <- prox_{alpha[i] r}(V[i,:]) for i < rows (Section 7.2,
  * prox_f(z) = argmin_x f(x) + 1/2 ||x - z||^2).  V is rows x k with leading
  * dimension ldv >= k (device); alpha has `rows` entries (device) or is NULL
  * for alpha = 1.  Asynchronous. */
 int glrm_prox(const glrm_reg *reg, float *V, int64_t rows, int32_t k, int64_t ldv,
               const float *alpha, void *stream);
+
+/* Update rules of the fit (Section 7.2). */
+#define GLRM_UPDATE_PROXGRAD 0  /* one proximal gradient step per row and column */
+#define GLRM_UPDATE_PROXPROX 1  /* prox-prox: x <- prox_{alpha r}(prox_{alpha f}(x)), `inner` times per
+                                   half-step with the Gram data of Section 7.3 cached; quadratic losses,
+                                   dense layout, FP32 (the k x k solves in FP64) */
 
 typedef struct {
     int32_t max_sweeps;   /* sweeps to run, >= 0 */
@@ -228,6 +277,8 @@ typedef struct {
     double  tol;          /* > 0: stop once (F_prev - F) <= tol * |F_prev| after a sweep
                              (reads F back to the host every sweep); 0: run max_sweeps */
     uint32_t flags;       /* GLRM_WS_PREPARED | GLRM_TIME_KERNELS */
+    int32_t update;       /* GLRM_UPDATE_PROXGRAD (0) or GLRM_UPDATE_PROXPROX */
+    int32_t inner;        /* prox-prox: updates per half-step with the cached factorization (>= 1) */
 } glrm_fit_opts;
 
 typedef struct {
@@ -244,6 +295,12 @@ typedef struct {
     int32_t kernel_calls[4];
 } glrm_fit_info;
 
+/* Bytes of workspace glrm_fit needs with these options: glrm_workspace_size
+ * for the proximal gradient update; with GLRM_UPDATE_PROXPROX also a
+ * transposed copy of the table, every row's and column's Gram data and the
+ * trial factors.  0 if the problem is invalid. */
+size_t glrm_fit_workspace_size(const glrm_data *d, const glrm_fit_opts *opts);
+
 /* Run Algorithm 2 (Section 7.2): per sweep, every row takes one proximal
  * gradient step against Y^{t-1} and keeps it only if its row objective did not
  * increase; then every column does the same against the updated X^t
@@ -254,7 +311,16 @@ typedef struct {
  * sweep tracked it.  info_host (host, may be NULL) is filled at the end.
  * The dense layout keeps a table row's tiles on one workgroup: it fits
  * n <= 1024 for k <= 32 and n <= 512 for k <= 64 and returns
- * GLRM_EUNSUPPORTED above (the COO layout has no such limit).  On one device
+ * GLRM_EUNSUPPORTED above (the COO layout has no such limit).
+ *
+ * With opts->update = GLRM_UPDATE_PROXPROX (Section 7.2, "Prox-prox method";
+ * Section 7.3) every row i instead forms G_i = sum_j w_j y_j y_j^T and
+ * b_i = sum_j w_j A_ij y_j over its observed entries, factors
+ * G_i + I / (2 alpha_i) (Cholesky, double) and applies
+ *     x <- prox_{alpha r}((G_i + I / (2 alpha))^-1 (b_i + x / (2 alpha)))
+ * opts->inner times, then keeps the result under the same step rule; the
+ * columns do the same against X^t.  ws must hold glrm_fit_workspace_size()
+ * bytes.  On one device
  * the results are bitwise reproducible: partial sums are combined in a fixed
  * order (how many there are follows the device's size).  Synchronizes
  * `stream`. */

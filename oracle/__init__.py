@@ -40,7 +40,7 @@ class _Loss(ctypes.Structure):
 class _Problem(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int32),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p),
-                ("ecode", ctypes.c_void_p), ("losses", ctypes.c_void_p)]
+                ("ecode", ctypes.c_void_p), ("losses", ctypes.c_void_p), ("ew", ctypes.c_void_p)]
 
 
 _lib = None
@@ -58,25 +58,33 @@ def lib():
         L.oracle_dloss.restype = D
         L.oracle_dloss.argtypes = [P, D, D]
         L.oracle_reg.restype = D
-        L.oracle_reg.argtypes = [I32, D, P, I32]
+        L.oracle_reg.argtypes = [I32, D, I32, P, I32]
         L.oracle_prox.restype = None
-        L.oracle_prox.argtypes = [I32, D, D, P, I32]
+        L.oracle_prox.argtypes = [I32, D, I32, D, P, I32]
         L.oracle_loss_sum.restype = D
         L.oracle_loss_sum.argtypes = [P, P, P]
         L.oracle_loss_grad_rows.restype = None
         L.oracle_loss_grad_rows.argtypes = [P, P, P, P]
         L.oracle_dloss_entries.restype = None
         L.oracle_dloss_entries.argtypes = [P, P, P, P]
+        L.oracle_loss_grad_sq_rows.restype = None
+        L.oracle_loss_grad_sq_rows.argtypes = [P, P, P, P]
         L.oracle_loss_grad_abs_rows.restype = None
         L.oracle_loss_grad_abs_rows.argtypes = [P, P, P, P]
         L.oracle_half_step.restype = I64
-        L.oracle_half_step.argtypes = [P, P, P, P, I32, D, D, D, P, P, P, P]
+        L.oracle_half_step.argtypes = [P, P, P, P, I32, D, I32, D, D, P, P, P, P]
+        L.oracle_half_step_proxprox.restype = I64
+        L.oracle_half_step_proxprox.argtypes = [P, P, P, P, I32, D, I32, I32, D, D, P, P, P, P, P]
         L.oracle_init_alpha.restype = None
         L.oracle_init_alpha.argtypes = [P, D, P]
         L.oracle_reg_sum.restype = D
-        L.oracle_reg_sum.argtypes = [I32, D, P, I64, I32]
+        L.oracle_reg_sum.argtypes = [I32, D, I32, P, I64, I32]
         L.oracle_objective.restype = D
-        L.oracle_objective.argtypes = [P, P, P, I32, D, I32, D]
+        L.oracle_objective.argtypes = [P, P, P, I32, D, I32, D, I32]
+        L.oracle_column_scaling.restype = None
+        L.oracle_column_scaling.argtypes = [P, P, P]
+        L.oracle_column_loss_at.restype = None
+        L.oracle_column_loss_at.argtypes = [P, P, P]
         L.oracle_decode.restype = D
         L.oracle_decode.argtypes = [P, D]
         L.oracle_decode_matrix.restype = None
@@ -130,29 +138,32 @@ def impute(X, Y, col_loss, losses, A=None, mask=None):
     return Z, out
 
 
-def reg(kind, w, x):
+def reg(kind, w, x, offset=0):
+    """r(x); offset 1 / 2 applies the offset of Section 3.3 to coordinate 0
+    (held at 1 / free and unpenalized)."""
     x = _f64(x).ravel()
-    return lib().oracle_reg(kind, float(w), _ptr(x), x.size)
+    return lib().oracle_reg(kind, float(w), int(offset), _ptr(x), x.size)
 
 
-def prox(kind, w, alpha, v):
+def prox(kind, w, alpha, v, offset=0):
     v = _f64(v).ravel().copy()
-    lib().oracle_prox(kind, float(w), float(alpha), _ptr(v), v.size)
+    lib().oracle_prox(kind, float(w), int(offset), float(alpha), _ptr(v), v.size)
     return v
 
 
 class _View:
     """One row-compressed list of observed entries (kept alive with its arrays)."""
 
-    def __init__(self, m, n, k, row_ptr, col, val, ecode, loss_arr):
+    def __init__(self, m, n, k, row_ptr, col, val, ecode, loss_arr, ew=None):
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
         self.col = np.ascontiguousarray(col, dtype=np.int32)
         self.val = _f64(val)
         self.ecode = np.ascontiguousarray(ecode, dtype=np.uint8)
+        self.ew = None if ew is None else _f64(ew)
         self._loss_arr = loss_arr
         self.s = _Problem(m, n, k, self.row_ptr.ctypes.data, self.col.ctypes.data,
                           self.val.ctypes.data, self.ecode.ctypes.data,
-                          ctypes.addressof(loss_arr))
+                          ctypes.addressof(loss_arr), None if self.ew is None else self.ew.ctypes.data)
         self.m, self.n = m, n
 
 
@@ -165,11 +176,16 @@ class Problem:
     ``(kind, levels, param)``; ``rx`` / ``ry`` are ``(kind, weight)``.
     """
 
-    def __init__(self, m, n, k, rows, cols, vals, col_loss, losses, rx, ry, col_order=None, row_sorted=False):
+    def __init__(self, m, n, k, rows, cols, vals, col_loss, losses, rx, ry, col_order=None, row_sorted=False,
+                 offset=False, col_weight=None):
         """rows / cols / vals list the observed entries.  ``row_sorted`` says they
         are already ordered by (row, column); ``col_order`` optionally gives the
-        permutation that orders them by (column, row)."""
+        permutation that orders them by (column, row).  ``offset`` makes
+        coordinate 0 the model's offset (Section 3.3: x_i0 = 1, y_j0 free and
+        unpenalized); ``col_weight`` (n) scales column j's loss (Section 4.3)."""
         self.m, self.n, self.k = int(m), int(n), int(k)
+        self.offset = bool(offset)
+        self.col_weight = None if col_weight is None else np.asarray(col_weight, np.float64)
         self.rx, self.ry = (int(rx[0]), float(rx[1])), (int(ry[0]), float(ry[1]))
         self.losses = list(losses)
         self._loss_arr = (_Loss * max(1, len(losses)))(*[_Loss(int(a), int(b), float(c)) for a, b, c in losses])
@@ -177,22 +193,25 @@ class Problem:
         cols = np.asarray(cols, dtype=np.int64)
         vals = np.asarray(vals, dtype=np.float64)
         ecode = np.asarray(col_loss, dtype=np.uint8)[cols]
+        ew = None if self.col_weight is None else self.col_weight[cols]
         # row view: entries ordered by (row, column)
         o = None if row_sorted else np.lexsort((cols, rows))
         pick = (lambda a: a) if o is None else (lambda a: a[o])
         rp = np.zeros(self.m + 1, dtype=np.int64)
         np.add.at(rp, rows + 1, 1) if rows.size < (1 << 22) else rp.__setitem__(
             slice(1, None), np.bincount(rows, minlength=self.m))
-        self.row = _View(self.m, self.n, self.k, np.cumsum(rp), pick(cols), pick(vals), pick(ecode), self._loss_arr)
+        self.row = _View(self.m, self.n, self.k, np.cumsum(rp), pick(cols), pick(vals), pick(ecode), self._loss_arr,
+                         None if ew is None else pick(ew))
         # transposed view for the column half-step: ordered by (column, row)
         o = np.lexsort((rows, cols)) if col_order is None else col_order
         cp = np.zeros(self.n + 1, dtype=np.int64)
         cp[1:] = np.bincount(cols, minlength=self.n)
-        self.colv = _View(self.n, self.m, self.k, np.cumsum(cp), rows[o], vals[o], ecode[o], self._loss_arr)
+        self.colv = _View(self.n, self.m, self.k, np.cumsum(cp), rows[o], vals[o], ecode[o], self._loss_arr,
+                          None if ew is None else ew[o])
         self.nnz = int(rows.size)
 
     @classmethod
-    def from_dense(cls, A, mask, k, col_loss, losses, rx, ry):
+    def from_dense(cls, A, mask, k, col_loss, losses, rx, ry, offset=False, col_weight=None):
         A = np.asarray(A)
         m, n = A.shape
         if mask is None:
@@ -210,21 +229,23 @@ class Problem:
             cj, ci = np.nonzero(mask.T)
             order = rank[ci, cj]
             del rank
-        return cls(m, n, k, rows, cols, A[rows, cols], col_loss, losses, rx, ry, col_order=order, row_sorted=True)
+        return cls(m, n, k, rows, cols, A[rows, cols], col_loss, losses, rx, ry, col_order=order, row_sorted=True,
+                   offset=offset, col_weight=col_weight)
 
     @classmethod
-    def from_coo(cls, m, n, k, rows, cols, vals, col_loss, losses, rx, ry):
+    def from_coo(cls, m, n, k, rows, cols, vals, col_loss, losses, rx, ry, offset=False, col_weight=None):
         rows = np.asarray(rows, dtype=np.int64)
         cols = np.asarray(cols, dtype=np.int64)
         row_sorted = bool(rows.size < 2 or np.all((rows[1:] > rows[:-1]) | ((rows[1:] == rows[:-1]) & (cols[1:] > cols[:-1]))))
         order = np.argsort(cols, kind="stable") if row_sorted else None
-        return cls(m, n, k, rows, cols, vals, col_loss, losses, rx, ry, col_order=order, row_sorted=row_sorted)
+        return cls(m, n, k, rows, cols, vals, col_loss, losses, rx, ry, col_order=order, row_sorted=row_sorted,
+                   offset=offset, col_weight=col_weight)
 
     # ---- the method ----------------------------------------------------------
     def objective(self, X, Y):
         X, Y = _f64(X), _f64(Y)
         return lib().oracle_objective(ctypes.byref(self.row.s), _ptr(X), _ptr(Y),
-                                      self.rx[0], self.rx[1], self.ry[0], self.ry[1])
+                                      self.rx[0], self.rx[1], self.ry[0], self.ry[1], 1 if self.offset else 0)
 
     def loss_sum(self, X, Y):
         X, Y = _f64(X), _f64(Y)
@@ -275,6 +296,67 @@ class Problem:
         M = self.grad_matrix(X, Y) / gamma + U[:, :r] @ Vt[:r]
         return float(np.linalg.norm(M, 2)), r
 
+    def column_scaling(self):
+        """Section 4.3: (mu, sigma2) per column, from the unweighted losses."""
+        mu, s2 = np.empty(self.n), np.empty(self.n)
+        lib().oracle_column_scaling(ctypes.byref(self.colv_plain().s), _ptr(mu), _ptr(s2))
+        return mu, s2
+
+    def column_loss_at(self, mu):
+        """sum over column j's observed entries of L_j(mu_j, A_ij), per column."""
+        mu = _f64(mu)
+        out = np.empty(self.n)
+        lib().oracle_column_loss_at(ctypes.byref(self.colv_plain().s), _ptr(mu), _ptr(out))
+        return out
+
+    def colv_plain(self):
+        """The column view without loss weights."""
+        v = self.colv
+        return _View(v.m, v.n, self.k, v.row_ptr, v.col, v.val, v.ecode, self._loss_arr)
+
+    def dense_values(self):
+        """The observed entries as a dense m x n array and the observation mask."""
+        A = np.zeros((self.m, self.n))
+        M = np.zeros((self.m, self.n), bool)
+        rows = np.repeat(np.arange(self.m), np.diff(self.row.row_ptr))
+        A[rows, self.row.col] = self.row.val
+        M[rows, self.row.col] = True
+        return A, M
+
+    def init_svd(self, mu, sigma2, k):
+        """Section 7.5: the exact top-k' SVD of the standardized table
+        At_ij = m / (sigma_j m_j) (A_ij - mu_j) on the observed set (0
+        elsewhere), X = U S^1/2, Y = diag(sigma) V S^1/2, with k' = k - 1 and
+        the offset in coordinate 0 (x_i0 = 1, y_j0 = mu_j) when this problem
+        has one.  Returns X, Y and the singular values."""
+        A, M = self.dense_values()
+        mu = np.asarray(mu, np.float64)
+        sig = np.sqrt(np.asarray(sigma2, np.float64))
+        cnt = M.sum(axis=0)
+        scale = np.where(cnt > 0, self.m / (sig * np.maximum(cnt, 1)), 0.0)
+        At = np.where(M, (A - mu[None, :]) * scale[None, :], 0.0)
+        off = 1 if self.offset else 0
+        ks = k - off
+        U, s, Vt = np.linalg.svd(At, full_matrices=False)
+        X = np.zeros((self.m, k))
+        Y = np.zeros((self.n, k))
+        if off:
+            X[:, 0] = 1.0
+            Y[:, 0] = mu
+        r = min(ks, int(np.sum(s > 1e-6 * s[0])) if s.size and s[0] > 0 else 0)
+        X[:, off:off + r] = U[:, :r] * np.sqrt(s[:r])
+        Y[:, off:off + r] = sig[:, None] * (Vt[:r].T * np.sqrt(s[:r]))
+        return X, Y, s[:ks]
+
+    def grad_rss(self, X, Y):
+        """Root of the sums of the squared gradient terms (m x k, n x k)."""
+        X, Y = _f64(X), _f64(Y)
+        aX = np.empty_like(X)
+        aY = np.empty_like(Y)
+        lib().oracle_loss_grad_sq_rows(ctypes.byref(self.row.s), _ptr(X), _ptr(Y), _ptr(aX))
+        lib().oracle_loss_grad_sq_rows(ctypes.byref(self.colv.s), _ptr(Y), _ptr(X), _ptr(aY))
+        return np.sqrt(aX), np.sqrt(aY)
+
     def init_alpha(self, s=1.0):
         ax = np.empty(self.m)
         ay = np.empty(self.n)
@@ -287,7 +369,7 @@ class Problem:
         fo, fn, acc = np.empty(self.m), np.empty(self.m), np.empty(self.m, dtype=np.uint8)
         scr = np.empty(2 * self.k)
         rej = lib().oracle_half_step(ctypes.byref(self.row.s), _ptr(X), _ptr(Y), _ptr(ax),
-                                     self.rx[0], self.rx[1], float(step_up), float(step_down),
+                                     self.rx[0], self.rx[1], 1 if self.offset else 0, float(step_up), float(step_down),
                                      _ptr(fo), _ptr(fn), _ptr(acc), _ptr(scr))
         return rej, fo, fn, acc
 
@@ -296,9 +378,42 @@ class Problem:
         fo, fn, acc = np.empty(self.n), np.empty(self.n), np.empty(self.n, dtype=np.uint8)
         scr = np.empty(2 * self.k)
         rej = lib().oracle_half_step(ctypes.byref(self.colv.s), _ptr(Y), _ptr(X), _ptr(ay),
-                                     self.ry[0], self.ry[1], float(step_up), float(step_down),
+                                     self.ry[0], self.ry[1], 2 if self.offset else 0, float(step_up), float(step_down),
                                      _ptr(fo), _ptr(fn), _ptr(acc), _ptr(scr))
         return rej, fo, fn, acc
+
+    def half_step_x_pp(self, X, Y, ax, inner=1, step_up=1.05, step_down=0.7, trial=None):
+        """X half-step with the prox-prox update of Sections 7.2-7.3 (quadratic
+        losses); in place, returns (rejected, f_old, f_new, accepted).  ``trial``
+        (m x k float64) receives every row's trial point."""
+        fo, fn, acc = np.empty(self.m), np.empty(self.m), np.empty(self.m, dtype=np.uint8)
+        scr = np.empty(2 * self.k * self.k + 3 * self.k)
+        rej = lib().oracle_half_step_proxprox(ctypes.byref(self.row.s), _ptr(X), _ptr(Y), _ptr(ax), self.rx[0],
+                                              self.rx[1], 1 if self.offset else 0, int(inner), float(step_up),
+                                              float(step_down), _ptr(fo), _ptr(fn), _ptr(acc),
+                                              None if trial is None else _ptr(trial), _ptr(scr))
+        return rej, fo, fn, acc
+
+    def half_step_y_pp(self, X, Y, ay, inner=1, step_up=1.05, step_down=0.7, trial=None):
+        """The same for the columns (the transposed problem)."""
+        fo, fn, acc = np.empty(self.n), np.empty(self.n), np.empty(self.n, dtype=np.uint8)
+        scr = np.empty(2 * self.k * self.k + 3 * self.k)
+        rej = lib().oracle_half_step_proxprox(ctypes.byref(self.colv.s), _ptr(Y), _ptr(X), _ptr(ay), self.ry[0],
+                                              self.ry[1], 2 if self.offset else 0, int(inner), float(step_up),
+                                              float(step_down), _ptr(fo), _ptr(fn), _ptr(acc),
+                                              None if trial is None else _ptr(trial), _ptr(scr))
+        return rej, fo, fn, acc
+
+    def fit_pp(self, X0, Y0, sweeps, inner=1, alpha_scale=1.0):
+        """Algorithm 2 with the prox-prox update; returns X, Y, ax, ay, history."""
+        X, Y = _f64(X0).copy(), _f64(Y0).copy()
+        ax, ay = self.init_alpha(alpha_scale)
+        hist = []
+        for _ in range(int(sweeps)):
+            self.half_step_x_pp(X, Y, ax, inner)
+            self.half_step_y_pp(X, Y, ay, inner)
+            hist.append(self.objective(X, Y))
+        return X, Y, ax, ay, np.array(hist)
 
     def sweep(self, X, Y, ax, ay, step_up=1.05, step_down=0.7):
         """One iteration t of Algorithm 2 (Gauss-Seidel: the Y half-step sees X^t).

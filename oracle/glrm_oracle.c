@@ -44,7 +44,11 @@ typedef struct {
     const double *val;            /* nnz, A_ij */
     const uint8_t *ecode;         /* nnz, loss of the entry (its column's loss) */
     const oracle_loss_t *losses;  /* table */
+    const double *ew;             /* nnz, weight of the entry's loss (its column's), or NULL for 1 */
 } oracle_problem_t;
+
+/* the weight of entry e: the scaled losses L_ij / sigma_j^2 of eq. sgpca (Section 4.3) */
+static double ew(const oracle_problem_t *P, int64_t e) { return P->ew ? P->ew[e] : 1.0; }
 
 static double pos(double t) { return t > 0.0 ? t : 0.0; }
 
@@ -105,24 +109,36 @@ double oracle_dloss(const oracle_loss_t *L, double u, double a)
 }
 
 /* ---- regularizers (Section 3) and their proximal operators (Section 7.2,
- * prox_f(z) = argmin_x f(x) + 1/2 ||x - z||^2) ------------------------------ */
-double oracle_reg(int32_t kind, double w, const double *x, int32_t k)
+ * prox_f(z) = argmin_x f(x) + 1/2 ||x - z||^2).  `offset` applies the offset
+ * of Section 3.3 to coordinate 0: 1 = r'(x) = r(x_2..) plus the indicator of
+ * x_1 = 1 (the rows of X), 2 = rt'(y) = rt(y_2..) (the columns of Y); 0 = none. */
+double oracle_reg(int32_t kind, double w, int32_t offset, const double *x, int32_t k)
 {
     double s = 0.0;
+    int c0 = 0;
+    if (offset) {
+        if (offset == 1 && x[0] != 1.0) return INFINITY;
+        c0 = 1;
+    }
     switch (kind) {
     case OR_RZERO: return 0.0;
-    case OR_RQUAD: for (int c = 0; c < k; ++c) s += x[c] * x[c]; return w * s;
-    case OR_RL1:   for (int c = 0; c < k; ++c) s += fabs(x[c]); return w * s;
+    case OR_RQUAD: for (int c = c0; c < k; ++c) s += x[c] * x[c]; return w * s;
+    case OR_RL1:   for (int c = c0; c < k; ++c) s += fabs(x[c]); return w * s;
     case OR_RNONNEG:
-        for (int c = 0; c < k; ++c) if (x[c] < 0.0) return INFINITY;
+        for (int c = c0; c < k; ++c) if (x[c] < 0.0) return INFINITY;
         return 0.0;
     }
     return NAN;
 }
 
-void oracle_prox(int32_t kind, double w, double alpha, double *v, int32_t k)
+void oracle_prox(int32_t kind, double w, int32_t offset, double alpha, double *v, int32_t k)
 {
-    for (int c = 0; c < k; ++c) {
+    int c0 = 0;
+    if (offset) {
+        if (offset == 1) v[0] = 1.0;   /* projection onto {x_1 = 1} */
+        c0 = 1;                         /* offset 2: unpenalized, unchanged */
+    }
+    for (int c = c0; c < k; ++c) {
         switch (kind) {
         case OR_RZERO: break;
         case OR_RQUAD: v[c] = v[c] / (1.0 + 2.0 * alpha * w); break;
@@ -148,7 +164,7 @@ static double row_loss(const oracle_problem_t *P, int64_t i, const double *u, co
 {
     double f = 0.0;
     for (int64_t e = P->row_ptr[i]; e < P->row_ptr[i + 1]; ++e)
-        f += oracle_loss(&P->losses[P->ecode[e]], dot(u, V + (int64_t)P->col[e] * P->k, P->k), P->val[e]);
+        f += ew(P, e) * oracle_loss(&P->losses[P->ecode[e]], dot(u, V + (int64_t)P->col[e] * P->k, P->k), P->val[e]);
     return f;
 }
 
@@ -171,7 +187,7 @@ void oracle_loss_grad_rows(const oracle_problem_t *P, const double *U, const dou
         for (int c = 0; c < k; ++c) g[c] = 0.0;
         for (int64_t e = P->row_ptr[i]; e < P->row_ptr[i + 1]; ++e) {
             const double *v = V + (int64_t)P->col[e] * k;
-            double d = oracle_dloss(&P->losses[P->ecode[e]], dot(U + i * k, v, k), P->val[e]);
+            double d = ew(P, e) * oracle_dloss(&P->losses[P->ecode[e]], dot(U + i * k, v, k), P->val[e]);
             for (int c = 0; c < k; ++c) g[c] += d * v[c];
         }
     }
@@ -184,7 +200,7 @@ void oracle_dloss_entries(const oracle_problem_t *P, const double *U, const doub
     const int32_t k = P->k;
     for (int64_t i = 0; i < P->m; ++i)
         for (int64_t e = P->row_ptr[i]; e < P->row_ptr[i + 1]; ++e)
-            out[e] = oracle_dloss(&P->losses[P->ecode[e]], dot(U + i * k, V + (int64_t)P->col[e] * k, k), P->val[e]);
+            out[e] = ew(P, e) * oracle_dloss(&P->losses[P->ecode[e]], dot(U + i * k, V + (int64_t)P->col[e] * k, k), P->val[e]);
 }
 
 /* Sum of the absolute terms of that gradient, dU_i = sum_j |dL(u_i . v_j, A_ij)| |v_j|
@@ -199,8 +215,25 @@ void oracle_loss_grad_abs_rows(const oracle_problem_t *P, const double *U, const
         for (int c = 0; c < k; ++c) g[c] = 0.0;
         for (int64_t e = P->row_ptr[i]; e < P->row_ptr[i + 1]; ++e) {
             const double *v = V + (int64_t)P->col[e] * k;
-            double d = fabs(oracle_dloss(&P->losses[P->ecode[e]], dot(U + i * k, v, k), P->val[e]));
+            double d = ew(P, e) * fabs(oracle_dloss(&P->losses[P->ecode[e]], dot(U + i * k, v, k), P->val[e]));
             for (int c = 0; c < k; ++c) g[c] += d * fabs(v[c]);
+        }
+    }
+}
+
+/* Sum of the squared terms of that gradient, dU_i = sum_j (dL(u_i . v_j, A_ij) v_j)^2
+ * (coordinate-wise): independent rounding errors of the terms add in
+ * quadrature, so its square root scales their typical sum.  Test use only. */
+void oracle_loss_grad_sq_rows(const oracle_problem_t *P, const double *U, const double *V, double *dU)
+{
+    const int32_t k = P->k;
+    for (int64_t i = 0; i < P->m; ++i) {
+        double *g = dU + i * k;
+        for (int c = 0; c < k; ++c) g[c] = 0.0;
+        for (int64_t e = P->row_ptr[i]; e < P->row_ptr[i + 1]; ++e) {
+            const double *v = V + (int64_t)P->col[e] * k;
+            double d = ew(P, e) * oracle_dloss(&P->losses[P->ecode[e]], dot(U + i * k, v, k), P->val[e]);
+            for (int c = 0; c < k; ++c) g[c] += (d * v[c]) * (d * v[c]);
         }
     }
 }
@@ -219,7 +252,7 @@ void oracle_loss_grad_abs_rows(const oracle_problem_t *P, const double *U, const
  * (length m) receive f and f+ when not NULL; accepted receives the decision.
  */
 int64_t oracle_half_step(const oracle_problem_t *P, double *U, const double *V, double *alpha,
-                         int32_t reg_kind, double reg_w, double step_up, double step_down,
+                         int32_t reg_kind, double reg_w, int32_t reg_offset, double step_up, double step_down,
                          double *f_old, double *f_new, uint8_t *accepted, double *scratch_2k)
 {
     const int32_t k = P->k;
@@ -227,16 +260,16 @@ int64_t oracle_half_step(const oracle_problem_t *P, double *U, const double *V, 
     int64_t rejected = 0;
     for (int64_t i = 0; i < P->m; ++i) {
         double *u = U + i * k;
-        double f = row_loss(P, i, u, V) + oracle_reg(reg_kind, reg_w, u, k);
+        double f = row_loss(P, i, u, V) + oracle_reg(reg_kind, reg_w, reg_offset, u, k);
         for (int c = 0; c < k; ++c) g[c] = 0.0;
         for (int64_t e = P->row_ptr[i]; e < P->row_ptr[i + 1]; ++e) {
             const double *v = V + (int64_t)P->col[e] * k;
-            double d = oracle_dloss(&P->losses[P->ecode[e]], dot(u, v, k), P->val[e]);
+            double d = ew(P, e) * oracle_dloss(&P->losses[P->ecode[e]], dot(u, v, k), P->val[e]);
             for (int c = 0; c < k; ++c) g[c] += d * v[c];
         }
         for (int c = 0; c < k; ++c) up[c] = u[c] - alpha[i] * g[c];
-        oracle_prox(reg_kind, reg_w, alpha[i], up, k);
-        double fp = row_loss(P, i, up, V) + oracle_reg(reg_kind, reg_w, up, k);
+        oracle_prox(reg_kind, reg_w, reg_offset, alpha[i], up, k);
+        double fp = row_loss(P, i, up, V) + oracle_reg(reg_kind, reg_w, reg_offset, up, k);
         /* the factors range over the reals (Section 2.1): a trial point with an
          * infinite or NaN coordinate (a step size that overflowed) is outside
          * the problem's domain, so its objective counts as +inf */
@@ -245,6 +278,92 @@ int64_t oracle_half_step(const oracle_problem_t *P, double *U, const double *V, 
         int acc = (fp <= f);
         if (acc) {
             for (int c = 0; c < k; ++c) u[c] = up[c];
+            alpha[i] *= step_up;
+        } else {
+            alpha[i] *= step_down;
+            ++rejected;
+        }
+        if (f_old) f_old[i] = f;
+        if (f_new) f_new[i] = fp;
+        if (accepted) accepted[i] = (uint8_t)acc;
+    }
+    return rejected;
+}
+
+/* ---- the prox-prox update for quadratic losses (Sections 7.2 and 7.3) -------
+ * For f_i(x) = sum_j w_j (A_ij - x . v_j)^2 over row i's observed entries, with
+ * G_i = sum_j w_j v_j v_j^T and b_i = sum_j w_j A_ij v_j:
+ *     prox_{alpha f_i}(x) = argmin_z f_i(z) + 1/(2 alpha) ||z - x||^2
+ *                         = (G_i + I / (2 alpha))^-1 (b_i + x / (2 alpha)),
+ * and the update is x <- prox_{alpha r}(prox_{alpha f_i}(x)), applied `inner`
+ * times with Y fixed (the factorization is the same each time).  The step
+ * rule is the one of the gradient step: keep the result only if the row
+ * objective did not increase, and move alpha_i by step_up / step_down.
+ * (The paper prints (G + I/alpha)^-1 (A Y^T + X/alpha); the factors 2 above
+ * follow from the loss (A - u)^2 and the prox's 1/2 ||.||^2.) */
+static void cholesky_solve(int k, double *M, double *rhs)
+{
+    /* M (k x k, row-major, SPD) = L L^T in place (lower), then rhs <- M^-1 rhs */
+    for (int j = 0; j < k; ++j) {
+        double d = M[j * k + j];
+        for (int l = 0; l < j; ++l) d -= M[j * k + l] * M[j * k + l];
+        d = sqrt(d);
+        M[j * k + j] = d;
+        for (int i = j + 1; i < k; ++i) {
+            double s = M[i * k + j];
+            for (int l = 0; l < j; ++l) s -= M[i * k + l] * M[j * k + l];
+            M[i * k + j] = s / d;
+        }
+    }
+    for (int j = 0; j < k; ++j) {       /* L y = rhs */
+        double s = rhs[j];
+        for (int l = 0; l < j; ++l) s -= M[j * k + l] * rhs[l];
+        rhs[j] = s / M[j * k + j];
+    }
+    for (int j = k - 1; j >= 0; --j) {  /* L^T x = y */
+        double s = rhs[j];
+        for (int l = j + 1; l < k; ++l) s -= M[l * k + j] * rhs[l];
+        rhs[j] = s / M[j * k + j];
+    }
+}
+
+int64_t oracle_half_step_proxprox(const oracle_problem_t *P, double *U, const double *V, double *alpha,
+                                  int32_t reg_kind, double reg_w, int32_t reg_offset, int32_t inner,
+                                  double step_up, double step_down, double *f_old, double *f_new,
+                                  uint8_t *accepted, double *trial, double *scratch)
+{
+    const int32_t k = P->k;
+    double *G = scratch, *M = G + k * k, *b = M + k * k, *x = b + k, *rhs = x + k;
+    int64_t rejected = 0;
+    for (int64_t i = 0; i < P->m; ++i) {
+        double *u = U + i * k;
+        for (int c = 0; c < k * k; ++c) G[c] = 0.0;
+        for (int c = 0; c < k; ++c) b[c] = 0.0;
+        for (int64_t e = P->row_ptr[i]; e < P->row_ptr[i + 1]; ++e) {
+            const double *v = V + (int64_t)P->col[e] * k, w = ew(P, e);
+            for (int r = 0; r < k; ++r) {
+                b[r] += w * P->val[e] * v[r];
+                for (int c = 0; c < k; ++c) G[r * k + c] += w * v[r] * v[c];
+            }
+        }
+        const double h = 1.0 / (2.0 * alpha[i]);
+        for (int c = 0; c < k; ++c) x[c] = u[c];
+        for (int q = 0; q < inner; ++q) {
+            for (int c = 0; c < k * k; ++c) M[c] = G[c];
+            for (int c = 0; c < k; ++c) { M[c * k + c] += h; rhs[c] = b[c] + h * x[c]; }
+            cholesky_solve(k, M, rhs);
+            for (int c = 0; c < k; ++c) x[c] = rhs[c];
+            oracle_prox(reg_kind, reg_w, reg_offset, alpha[i], x, k);
+        }
+        const double f = row_loss(P, i, u, V) + oracle_reg(reg_kind, reg_w, reg_offset, u, k);
+        double fp = row_loss(P, i, x, V) + oracle_reg(reg_kind, reg_w, reg_offset, x, k);
+        for (int c = 0; c < k; ++c)
+            if (!isfinite(x[c])) fp = INFINITY;
+        const int acc = (fp <= f);
+        if (trial)
+            for (int c = 0; c < k; ++c) trial[i * k + c] = x[c];
+        if (acc) {
+            for (int c = 0; c < k; ++c) u[c] = x[c];
             alpha[i] *= step_up;
         } else {
             alpha[i] *= step_down;
@@ -268,20 +387,73 @@ void oracle_init_alpha(const oracle_problem_t *P, double s, double *alpha)
 }
 
 /* Sum of r over the rows of U (the regularizer terms of eq. gpca). */
-double oracle_reg_sum(int32_t kind, double w, const double *U, int64_t rows, int32_t k)
+double oracle_reg_sum(int32_t kind, double w, int32_t offset, const double *U, int64_t rows, int32_t k)
 {
     double s = 0.0;
-    for (int64_t i = 0; i < rows; ++i) s += oracle_reg(kind, w, U + i * k, k);
+    for (int64_t i = 0; i < rows; ++i) s += oracle_reg(kind, w, offset, U + i * k, k);
     return s;
 }
 
 /* The full objective of eq. gpca: loss over the observed entries plus both
  * regularizer sums.  P is the row view (U = X, V = Y). */
 double oracle_objective(const oracle_problem_t *P, const double *X, const double *Y,
-                        int32_t rx_kind, double rx_w, int32_t ry_kind, double ry_w)
+                        int32_t rx_kind, double rx_w, int32_t ry_kind, double ry_w, int32_t offset)
 {
-    return oracle_loss_sum(P, X, Y) + oracle_reg_sum(rx_kind, rx_w, X, P->m, P->k)
-         + oracle_reg_sum(ry_kind, ry_w, Y, P->n, P->k);
+    return oracle_loss_sum(P, X, Y) + oracle_reg_sum(rx_kind, rx_w, offset ? 1 : 0, X, P->m, P->k)
+         + oracle_reg_sum(ry_kind, ry_w, offset ? 2 : 0, Y, P->n, P->k);
+}
+
+/* ---- automatic loss scaling (Section 4.3) ----------------------------------
+ * On the column view (each "row" is a column of A): for column j,
+ *   mu_j     = argmin over mu of f(mu) = sum_e L_j(mu, A_ej)
+ *   sigma2_j = f(mu_j) / (n_j - 1).
+ * f is convex, so its minimizers are where the subgradient sum changes sign:
+ * bisection on the sign of sum_e dL_j(mu, A_ej) over [min A - 1, max A + 1]
+ * (which holds a minimizer of every loss here), 200 halvings, to double
+ * rounding.  Readings: an empty column takes mu = 0; sigma2 = 1 when n_j < 2
+ * or f(mu_j) = 0 (nothing to scale by). */
+static double col_loss_at(const oracle_problem_t *C, int64_t j, double mu)
+{
+    double f = 0.0;
+    for (int64_t e = C->row_ptr[j]; e < C->row_ptr[j + 1]; ++e)
+        f += oracle_loss(&C->losses[C->ecode[e]], mu, C->val[e]);
+    return f;
+}
+
+static double col_dloss_at(const oracle_problem_t *C, int64_t j, double mu)
+{
+    double g = 0.0;
+    for (int64_t e = C->row_ptr[j]; e < C->row_ptr[j + 1]; ++e)
+        g += oracle_dloss(&C->losses[C->ecode[e]], mu, C->val[e]);
+    return g;
+}
+
+void oracle_column_loss_at(const oracle_problem_t *C, const double *mu, double *out)
+{
+    for (int64_t j = 0; j < C->m; ++j) out[j] = col_loss_at(C, j, mu[j]);
+}
+
+void oracle_column_scaling(const oracle_problem_t *C, double *mu, double *sigma2)
+{
+    for (int64_t j = 0; j < C->m; ++j) {
+        const int64_t nj = C->row_ptr[j + 1] - C->row_ptr[j];
+        if (nj == 0) { mu[j] = 0.0; sigma2[j] = 1.0; continue; }
+        double lo = INFINITY, hi = -INFINITY;
+        for (int64_t e = C->row_ptr[j]; e < C->row_ptr[j + 1]; ++e) {
+            if (C->val[e] < lo) lo = C->val[e];
+            if (C->val[e] > hi) hi = C->val[e];
+        }
+        lo -= 1.0;
+        hi += 1.0;
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (col_dloss_at(C, j, mid) < 0.0) lo = mid;   /* f still decreasing: the minimum lies above */
+            else hi = mid;
+        }
+        mu[j] = 0.5 * (lo + hi);
+        const double S = col_loss_at(C, j, mu[j]);
+        sigma2[j] = (nj >= 2 && S > 0.0) ? S / (double)(nj - 1) : 1.0;
+    }
 }
 
 /* ---- imputation (Section 5.3): the entry of the column's data domain whose

@@ -16,7 +16,8 @@ __all__ = [
     "GLRMError", "Data", "glrm_workspace_size", "glrm_prepare", "glrm_objective", "glrm_grad", "glrm_prox",
     "glrm_fit", "glrm_last_error", "library_path", "FP32", "BF16", "FP64", "BF16_PLAIN", "DENSE", "COO_ROWSORTED",
     "WS_PREPARED", "TIME_KERNELS", "glrm_impute", "IMPUTE_ALL", "IMPUTE_MISSING", "glrm_grad_noalloc",
-    "NOALLOC_MAX_BYTES", "glrm_certificate", "glrm_linalg_workspace_size",
+    "NOALLOC_MAX_BYTES", "glrm_certificate", "glrm_linalg_workspace_size", "glrm_column_scaling",
+    "glrm_init_svd", "fit_standardized", "UPDATE_PROXGRAD", "UPDATE_PROXPROX",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -27,6 +28,7 @@ DENSE, COO_ROWSORTED = 0, 1
 WS_PREPARED = 1
 TIME_KERNELS = 2
 IMPUTE_ALL, IMPUTE_MISSING = 0, 1
+UPDATE_PROXGRAD, UPDATE_PROXPROX = 0, 1
 NOALLOC_MAX_BYTES = 64 << 20
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp64": FP64, "bf16_plain": BF16_PLAIN}
 
@@ -52,13 +54,14 @@ class _Data(ctypes.Structure):
                 ("A", ctypes.c_void_p), ("lda", ctypes.c_int64), ("mask", ctypes.c_void_p),
                 ("row", ctypes.c_void_p), ("col", ctypes.c_void_p), ("nnz", ctypes.c_int64),
                 ("col_loss", ctypes.c_void_p), ("losses", ctypes.c_void_p), ("n_losses", ctypes.c_int32),
-                ("rx", _Reg), ("ry", _Reg)]
+                ("rx", _Reg), ("ry", _Reg), ("offset", ctypes.c_int32), ("col_weight", ctypes.c_void_p)]
 
 
 class _FitOpts(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("precision", ctypes.c_int32), ("init_alpha", ctypes.c_int32),
                 ("alpha_scale", ctypes.c_float), ("step_up", ctypes.c_float), ("step_down", ctypes.c_float),
-                ("tol", ctypes.c_double), ("flags", ctypes.c_uint32)]
+                ("tol", ctypes.c_double), ("flags", ctypes.c_uint32), ("update", ctypes.c_int32),
+                ("inner", ctypes.c_int32)]
 
 
 class _FitInfo(ctypes.Structure):
@@ -103,6 +106,13 @@ def _L():
         L.glrm_certificate.restype = ctypes.c_int
         L.glrm_certificate.argtypes = [D, P, P, ctypes.c_int32, ctypes.POINTER(_CertInfo), P, ctypes.c_size_t,
                                        ctypes.c_uint, P]
+        L.glrm_column_scaling.restype = ctypes.c_int
+        L.glrm_column_scaling.argtypes = [D, P, P, P, ctypes.c_size_t, ctypes.c_uint, P]
+        L.glrm_init_svd.restype = ctypes.c_int
+        L.glrm_init_svd.argtypes = [D, P, P, P, ctypes.c_int32, ctypes.c_int32, P, P,
+                                    ctypes.POINTER(ctypes.c_double), P, ctypes.c_size_t, ctypes.c_uint, P]
+        L.glrm_fit_workspace_size.restype = ctypes.c_size_t
+        L.glrm_fit_workspace_size.argtypes = [D, ctypes.POINTER(_FitOpts)]
         L.glrm_prox.restype = ctypes.c_int
         L.glrm_prox.argtypes = [ctypes.POINTER(_Reg), P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, P, P]
         L.glrm_fit.restype = ctypes.c_int
@@ -166,7 +176,7 @@ class Data:
     """
 
     def __init__(self, m, n, k, *, A, mask=None, row=None, col=None, layout=DENSE, lda=None, col_loss=None,
-                 losses=((0, 0, 0.0),), rx=(0, 0.0), ry=(0, 0.0)):
+                 losses=((0, 0, 0.0),), rx=(0, 0.0), ry=(0, 0.0), offset=False, col_weight=None):
         torch = _torch()
         self.m, self.n, self.k, self.layout = int(m), int(n), int(k), int(layout)
         self.A, self.mask, self.row, self.col = A, mask, row, col
@@ -192,6 +202,10 @@ class Data:
         s.n_losses = len(self.losses)
         s.rx = _Reg(*self.rx)
         s.ry = _Reg(*self.ry)
+        self.offset = bool(offset)
+        self.col_weight = col_weight
+        s.offset = 1 if offset else 0
+        s.col_weight = _dev_ptr(col_weight, torch.float32, "col_weight", self.n) if col_weight is not None else None
         self.s = s
         self._ws = None
         self.device = A.device
@@ -213,19 +227,31 @@ class Data:
 
     def with_regs(self, rx, ry):
         """Same data and losses with other regularizers (shares the tensors)."""
-        return Data(self.m, self.n, self.k, A=self.A, mask=self.mask, row=self.row, col=self.col,
+        return self.variant(rx=rx, ry=ry)
+
+    def variant(self, **kw):
+        """The same data with some of k, rx, ry, offset, col_weight replaced
+        (shares the tensors)."""
+        args = dict(k=self.k, rx=self.rx, ry=self.ry, offset=self.offset, col_weight=self.col_weight)
+        args.update(kw)
+        return Data(self.m, self.n, args["k"], A=self.A, mask=self.mask, row=self.row, col=self.col,
                     layout=self.layout, lda=self.s.lda if self.layout == DENSE else None, col_loss=self.col_loss,
-                    losses=self.losses, rx=rx, ry=ry)
+                    losses=self.losses, rx=args["rx"], ry=args["ry"], offset=args["offset"],
+                    col_weight=args["col_weight"])
 
     def workspace(self, size=None):
         """Device workspace of at least glrm_workspace_size() (or `size`) bytes,
-        256-byte aligned, cached.  Growing it starts a new buffer, whose
-        prepared part must be rebuilt (call glrm_prepare again)."""
+        256-byte aligned, cached.  Growing it copies the old contents over, so a
+        prepared part stays valid (every layout extends the basic one)."""
         torch = _torch()
         size = max(glrm_workspace_size(self), size or 0)
         if self._ws is None or self._ws[1] < size:
             buf = torch.empty(size + 256, dtype=torch.uint8, device=self.device)
             off = (-buf.data_ptr()) % 256
+            if self._ws is not None:
+                # every larger layout keeps the smaller one as its prefix: carry the prepared part over
+                old, osize, ooff = self._ws
+                buf[off:off + osize].copy_(old[ooff:ooff + osize])
             self._ws = (buf, size, off)
         buf, size, off = self._ws
         return ctypes.c_void_p(buf.data_ptr() + off), size
@@ -313,6 +339,63 @@ def glrm_certificate(data, X, Y, iters=500, flags=0, stream=None):
     return dict(norm=info.norm, norm_prev=info.norm_prev, rank=info.rank, iters=info.iters)
 
 
+def glrm_column_scaling(data, mu=None, sigma2=None, flags=0, stream=None):
+    """mu_j and sigma_j^2 of every column (Section 4.3); two float32 GPU tensors."""
+    torch = _torch()
+    if mu is None:
+        mu = torch.empty(data.n, dtype=torch.float32, device=data.device)
+    if sigma2 is None:
+        sigma2 = torch.empty(data.n, dtype=torch.float32, device=data.device)
+    ws, wsb = data.workspace(glrm_linalg_workspace_size(data, 1))
+    _check(_L().glrm_column_scaling(ctypes.byref(data.s), _dev_ptr(mu, torch.float32, "mu", data.n),
+                                    _dev_ptr(sigma2, torch.float32, "sigma2", data.n), ws, wsb, int(flags),
+                                    _stream(stream)))
+    return mu, sigma2
+
+
+def glrm_init_svd(data, omega, mu=None, sigma2=None, power_iters=2, X=None, Y=None, flags=0, stream=None):
+    """X (m x k), Y (n x k) from the top singular triples of the standardized
+    table (Section 7.5); omega is the caller's n x l float32 test matrix.
+    Returns X, Y and the singular values."""
+    torch = _torch()
+    l = int(omega.shape[1]) if omega is not None else 1
+    if X is None:
+        X = torch.empty((data.m, data.k), dtype=torch.float32, device=data.device)
+    if Y is None:
+        Y = torch.empty((data.n, data.k), dtype=torch.float32, device=data.device)
+    ks = data.k - (1 if data.offset else 0)
+    sv = (ctypes.c_double * max(ks, 1))()
+    ws, wsb = data.workspace(glrm_linalg_workspace_size(data, l))
+    _check(_L().glrm_init_svd(ctypes.byref(data.s), _dev_ptr(mu, torch.float32, "mu", data.n) if mu is not None else None,
+                              _dev_ptr(sigma2, torch.float32, "sigma2", data.n) if sigma2 is not None else None,
+                              _dev_ptr(omega, torch.float32, "omega", data.n * l) if omega is not None else None,
+                              l, int(power_iters), _dev_ptr(X, torch.float32, "X", data.m * data.k),
+                              _dev_ptr(Y, torch.float32, "Y", data.n * data.k), sv, ws, wsb, int(flags),
+                              _stream(stream)))
+    return X, Y, np.array(sv[:ks])
+
+
+def fit_standardized(data, k, sweeps, omega=None, oversample=10, power_iters=2, precision=BF16, seed=0, **fit_kw):
+    """The fit as the paper's implementation runs it by default (Section 9.1):
+    an offset in the model (Section 3.3) and losses scaled by 1 / sigma_j^2
+    around mu_j (Section 4.3), started from the SVD initialization of
+    Section 7.5.  ``k`` counts the offset coordinate.  ``omega`` (n x l,
+    float32) defaults to i.i.d. N(0, 1) drawn by torch from ``seed``.  Returns
+    (X, Y, info, mu, sigma2, model) with ``model`` the scaled, offset Data."""
+    torch = _torch()
+    mu, sigma2 = glrm_column_scaling(data)
+    model = data.variant(k=int(k), offset=True, col_weight=1.0 / sigma2)
+    if omega is None:
+        gen = torch.Generator(device="cpu").manual_seed(int(seed))
+        l = min(max(int(k) - 1 + int(oversample), 1), 96)
+        omega = torch.randn((data.n, l), generator=gen, dtype=torch.float32).to(data.device)
+    X, Y, sv = glrm_init_svd(model, omega, mu=mu, sigma2=sigma2, power_iters=power_iters)
+    ax = torch.empty(data.m, dtype=torch.float32, device=data.device)
+    ay = torch.empty(data.n, dtype=torch.float32, device=data.device)
+    info = glrm_fit(model, X, Y, ax, ay, sweeps, precision=precision, **fit_kw)
+    return X, Y, info, mu, sigma2, model
+
+
 def glrm_prox(reg, V, alpha=None, stream=None):
     """In place V[i] <- prox_{alpha_i r}(V[i]) for a rows x k float32 tensor."""
     torch = _torch()
@@ -325,16 +408,20 @@ def glrm_prox(reg, V, alpha=None, stream=None):
 
 
 def glrm_fit(data, X, Y, alpha_x, alpha_y, max_sweeps, precision=BF16, init_alpha=True, alpha_scale=1.0,
-             step_up=1.05, step_down=0.7, tol=0.0, history=None, flags=0, stream=None):
+             step_up=1.05, step_down=0.7, tol=0.0, history=None, flags=0, stream=None, update=UPDATE_PROXGRAD,
+             inner=1):
     """Run Algorithm 2 in place on X, Y, alpha_x, alpha_y; returns the info dict.
 
     ``history`` (optional float64 GPU tensor of max_sweeps entries) receives F
-    after each sweep."""
+    after each sweep.  ``update=UPDATE_PROXPROX`` takes the prox-prox update
+    (quadratic losses, dense layout, FP32) with ``inner`` updates per
+    half-step."""
     torch = _torch()
     o = _FitOpts(int(max_sweeps), _prec(precision), 1 if init_alpha else 0, float(alpha_scale), float(step_up),
-                 float(step_down), float(tol), int(flags))
+                 float(step_down), float(tol), int(flags), int(update), int(inner))
     info = _FitInfo()
-    ws, wsb = data.workspace()
+    size = _L().glrm_fit_workspace_size(ctypes.byref(data.s), ctypes.byref(o))
+    ws, wsb = data.workspace(size)
     _check(_L().glrm_fit(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
                          _dev_ptr(Y, torch.float32, "Y", data.n * data.k),
                          _dev_ptr(alpha_x, torch.float32, "alpha_x", data.m),

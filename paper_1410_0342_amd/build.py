@@ -12,7 +12,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # (source, extra flags, object name): dense_prec.hip is built once per precision
 SOURCES = [("glrm_api.cpp", [], "glrm_api"), ("common.hip", [], "common"), ("dense.hip", [], "dense"),
            ("coo.hip", [], "coo"),
-           ("impute.hip", [], "impute"), ("linalg.hip", [], "linalg"), ("smallmat.cpp", [], "smallmat")]
+           ("impute.hip", [], "impute"), ("linalg.hip", [], "linalg"), ("smallmat.cpp", [], "smallmat"),
+           ("proxprox.hip", [], "proxprox")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-mllvm", "-pragma-unroll-threshold=1000000",

@@ -72,7 +72,7 @@ __global__ void prox_kernel(Reg r, float *V, int64_t rows, int32_t k, int64_t ld
     const int64_t i = t / k;
     const int c = (int)(t % k);
     const float al = alpha ? alpha[i] : 1.0f;
-    V[i * ldv + c] = prox_elem(r, al, V[i * ldv + c]);
+    V[i * ldv + c] = prox_elem(r, al, V[i * ldv + c], c);
 }
 
 hipError_t launch_prox(Reg r, float *V, int64_t rows, int32_t k, int64_t ldv, const float *alpha, hipStream_t st)
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void regsum_kernel(Reg r, const float *V, int6
     double acc = 0.0;
     const int64_t total = rows * k;
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256)
-        acc += reg_elem64(r, (double)V[t]);
+        acc += reg_elem64(r, (double)V[t], (int)(t % k));
     acc = sum_lanes64<64>(acc);
     if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
     __syncthreads();
@@ -124,6 +124,19 @@ __global__ __launch_bounds__(256) void sum_doubles_kernel(const double *a, int32
 hipError_t launch_sum_doubles(const double *a, int32_t na, const double *b, int32_t nb, double *out, hipStream_t st)
 {
     hipLaunchKernelGGL(sum_doubles_kernel, dim3(1), dim3(256), 0, st, a, na, b, nb, out);
+    return hipGetLastError();
+}
+
+// dst[j] = src[j] for j < n (1 without src), 1 for the padding columns up to ldp.
+__global__ void pad_weights_kernel(const float *src, int64_t n, int64_t ldp, float *dst)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < ldp) dst[j] = (src && j < n) ? src[j] : 1.0f;
+}
+
+hipError_t launch_pad_weights(const float *src, int64_t n, int64_t ldp, float *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(pad_weights_kernel, dim3((unsigned)((ldp + 255) / 256)), dim3(256), 0, st, src, n, ldp, dst);
     return hipGetLastError();
 }
 

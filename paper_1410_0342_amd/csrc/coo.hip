@@ -263,25 +263,32 @@ struct WalkArgs {
 
 // One entry's loss (and derivative) in the walk.  LK >= 0: every column has
 // loss kind LK (compile time); LK < 0: the code of the entry's column.
+// wcol: the entry's column of A (its loss weight, when the table has weights).
 template <int LK>
-__device__ __forceinline__ void walk_lg(const WalkArgs &a, int code, float z, float v, float &l, float &g)
+__device__ __forceinline__ void walk_lg(const WalkArgs &a, int code, int wcol, float z, float v, float &l, float &g)
 {
     if constexpr (LK >= 0) {
         loss_lg_k<LK>(a.lt.levels[0], a.lt.param[0], z, v, l, g);
     } else {
         const int q = a.lt.uniform >= 0 ? a.lt.uniform : code;
         loss_lg(a.lt.kind[q], a.lt.levels[q], a.lt.param[q], z, v, l, g);
+        if (a.lt.colw) {
+            const float w = a.lt.colw[wcol];
+            l *= w;
+            g *= w;
+        }
     }
 }
 
 template <int LK>
-__device__ __forceinline__ float walk_l(const WalkArgs &a, int code, float z, float v)
+__device__ __forceinline__ float walk_l(const WalkArgs &a, int code, int wcol, float z, float v)
 {
     if constexpr (LK >= 0) {
         return loss_l_k<LK>(a.lt.levels[0], a.lt.param[0], z, v);
     } else {
         const int q = a.lt.uniform >= 0 ? a.lt.uniform : code;
-        return loss_l(a.lt.kind[q], a.lt.levels[q], a.lt.param[q], z, v);
+        const float l = loss_l(a.lt.kind[q], a.lt.levels[q], a.lt.param[q], z, v);
+        return a.lt.colw ? l * a.lt.colw[wcol] : l;
     }
 }
 
@@ -328,7 +335,8 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
                     if (j[s] >= 0 && q == 0) {
                         const int code = a.codes_by_entry ? a.codes[j[s]] : rowcode;
                         const int qq = a.lt.uniform >= 0 ? a.lt.uniform : code;
-                        acc += loss_l64(a.lt.kind[qq], a.lt.levels[qq], (double)a.lt.param[qq], z, (double)v[s]);
+                        const double wv = a.lt.colw ? (double)a.lt.colw[a.codes_by_entry ? j[s] : (int)i] : 1.0;
+                        acc += wv * loss_l64(a.lt.kind[qq], a.lt.levels[qq], (double)a.lt.param[qq], z, (double)v[s]);
                     }
                 }
             }
@@ -353,7 +361,9 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
             for (int s = 0; s < NS; ++s) {
                 const float z = group_sum<L>(dot4(x, y[s]));
                 float l = 0.f, gr = 0.f;
-                if (j[s] >= 0) walk_lg<LK>(a, a.codes_by_entry ? a.codes[j[s]] : rowcode, z, v[s], l, gr);
+                if (j[s] >= 0)
+                    walk_lg<LK>(a, a.codes_by_entry ? a.codes[j[s]] : rowcode, a.codes_by_entry ? j[s] : (int)i, z,
+                                v[s], l, gr);
                 if (q == 0) f += l;
                 gacc.x += gr * y[s].x; gacc.y += gr * y[s].y; gacc.z += gr * y[s].z; gacc.w += gr * y[s].w;
             }
@@ -380,9 +390,9 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const bool in = 4 * q + s < a.k;
-                xp[s] = in ? prox_elem(a.reg, al, xv[s] - al * gv[s]) : 0.0f;
-                rc += in ? reg_elem(a.reg, xv[s]) : 0.0f;
-                rcp += in ? reg_elem_trial(a.reg, xp[s]) : 0.0f;
+                xp[s] = in ? prox_elem(a.reg, al, xv[s] - al * gv[s], 4 * q + s) : 0.0f;
+                rc += in ? reg_elem(a.reg, xv[s], 4 * q + s) : 0.0f;
+                rcp += in ? reg_elem_trial(a.reg, xp[s], 4 * q + s) : 0.0f;
             }
             rc = group_sum<L>(rc);
             rcp = group_sum<L>(rcp);
@@ -403,7 +413,9 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     const float z = group_sum<L>(dot4(xp4, y[s]));
-                    if (j[s] >= 0 && q == 0) fp += walk_l<LK>(a, a.codes_by_entry ? a.codes[j[s]] : rowcode, z, v[s]);
+                    if (j[s] >= 0 && q == 0)
+                        fp += walk_l<LK>(a, a.codes_by_entry ? a.codes[j[s]] : rowcode, a.codes_by_entry ? j[s] : (int)i,
+                                         z, v[s]);
                 }
             }
             fp = across_groups<L>(group_sum<L>(fp));
@@ -590,11 +602,11 @@ int coo_fit(const glrm_data *d, int kp, const CooLayout &cl, char *base, const u
     int rc = pad_factors(d, kp, p, X, Y, st);
     if (rc) return rc;
     WalkArgs ra = row_walk(d, p, codes, lt);
-    ra.reg = Reg{d->rx.kind, d->rx.weight};
+    ra.reg = Reg{d->rx.kind, d->rx.weight, d->offset ? 1 : 0};
     ra.U = X; ra.alpha = alpha_x; ra.step_up = o->step_up; ra.step_down = o->step_down;
     ra.part_obj = p.partA; ra.part_rej = p.ipartA; ra.reg_only = true;
     WalkArgs ca = col_walk(d, p, codes, lt);
-    ca.reg = Reg{d->ry.kind, d->ry.weight};
+    ca.reg = Reg{d->ry.kind, d->ry.weight, d->offset ? 2 : 0};
     ca.U = Y; ca.alpha = alpha_y; ca.step_up = o->step_up; ca.step_down = o->step_down;
     ca.part_obj = p.partB; ca.part_rej = p.ipartB;
     const int grid_r = walk_grid(d->m), grid_c = walk_grid(d->n);

@@ -73,6 +73,7 @@ __global__ __launch_bounds__(256) void objective64_kernel(Obj64Args a)
             const int q = a.lt.uniform >= 0 ? a.lt.uniform : a.codes[j];
             const int kind = a.lt.kind[q], lev = a.lt.levels[q];
             const double par = (double)a.lt.param[q];
+            const double wj = a.lt.colw ? (double)a.lt.colw[j] : 1.0;
 #pragma unroll
             for (int ii = 0; ii < 16; ++ii) {
                 const float av = avs[ii];
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(256) void objective64_kernel(Obj64Args a)
                     double z = 0.0;
 #pragma unroll
                     for (int c = 0; c < KP; ++c) z += xsd[ii][c] * y[c];
-                    acc += loss_l64(kind, lev, par, z, (double)av);
+                    acc += wj * loss_l64(kind, lev, par, z, (double)av);
                 }
             }
         }

@@ -443,10 +443,15 @@ __device__ __attribute__((noinline)) LG4 tile_loss_table_call(const LossTab *tab
 // (tile_loss_table).  TRANS: the four entries are rows 4g + r of column
 // 16t + li (the layout of X . Y^T products) instead of row li, columns
 // 16t + 4g + r.
+//
+// Under a per-column loss table each entry's loss and derivative are scaled
+// by its column's weight (tab.colw, padded to the table's width, all 1 unless
+// the caller gave weights); tw is the tile's index in the whole table (t may
+// count within a column block).
 template <int LK, bool WANT_G, bool TRANS = false, int TPW = 1>
 __device__ __forceinline__ void tile_loss(const LossU &lu, const LossTab &tab, const uint8_t *s_codes,
                                           const int8_t *s_tcode, int t, const f32x4 &z, const float4 &av,
-                                          float (&l)[4], float (&g)[4])
+                                          float (&l)[4], float (&g)[4], int tw = -1)
 {
     if constexpr (LK >= 0) {
         const float a4[4] = {av.x, av.y, av.z, av.w};
@@ -471,6 +476,23 @@ __device__ __forceinline__ void tile_loss(const LossU &lu, const LossTab &tab, c
         for (int q = 0; q < 4; ++q) {
             l[q] = r.l[q];
             g[q] = r.g[q];
+        }
+        // unconditional (the weights are all 1 without a caller's weights): a
+        // branch here would sit between a matrix-core product and its read
+        const int lane = threadIdx.x & 63;
+        const int tt = tw >= 0 ? tw : t;
+        float w[4];
+        if constexpr (TRANS) {
+            const float wc = tab.colw[16 * tt + (lane & 15)];
+            w[0] = w[1] = w[2] = w[3] = wc;
+        } else {
+            const float4 w4 = *reinterpret_cast<const float4 *>(tab.colw + 16 * tt + 4 * (lane >> 4));
+            w[0] = w4.x; w[1] = w4.y; w[2] = w4.z; w[3] = w4.w;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            l[q] *= w[q];
+            g[q] *= w[q];
         }
     }
 }
@@ -672,10 +694,10 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
             const int c = c0 + 16 * q;
             const bool ok = rv && c < k;
             const float x = ok ? xq[q] : 0.0f;
-            const float xv = ok ? prox_elem(a.rx, al, x - al * gq[q]) : 0.0f;
+            const float xv = ok ? prox_elem(a.rx, al, x - al * gq[q], c) : 0.0f;
             sh.xp[ri][c] = xv;
-            rc += ok ? reg_elem(a.rx, x) : 0.0f;
-            rcp += ok ? reg_elem_trial(a.rx, xv) : 0.0f;
+            rc += ok ? reg_elem(a.rx, x, c) : 0.0f;
+            rcp += ok ? reg_elem_trial(a.rx, xv, c) : 0.0f;
         }
         rc = row16_sum(rc);
         rcp = row16_sum(rcp);
@@ -904,7 +926,7 @@ __global__ __launch_bounds__(64 * YPROX_SPLIT) void yprox_kernel(YProxArgs a)
     __syncthreads();
     if (ps != 0) return;
     gsum = (s_part[0][el] + s_part[1][el]) + (s_part[2][el] + s_part[3][el]);
-    const float yv = (valid && c < a.k) ? prox_elem(a.ry, al, y - al * gsum) : 0.0f;
+    const float yv = (valid && c < a.k) ? prox_elem(a.ry, al, y - al * gsum, c) : 0.0f;
     if (valid) {
         if (c < a.k) a.Yplus[j * a.k + c] = yv;
         if constexpr (PREC == P_FP32) {
@@ -916,8 +938,8 @@ __global__ __launch_bounds__(64 * YPROX_SPLIT) void yprox_kernel(YProxArgs a)
             a.yplus.lo[j * KP + c] = lo;
         }
     }
-    float rc = (valid && c < a.k) ? reg_elem(a.ry, y) : 0.0f;
-    float rcp = (valid && c < a.k) ? reg_elem_trial(a.ry, yv) : 0.0f;
+    float rc = (valid && c < a.k) ? reg_elem(a.ry, y, c) : 0.0f;
+    float rcp = (valid && c < a.k) ? reg_elem_trial(a.ry, yv, c) : 0.0f;
     rc = sum_lanes<KP>(rc);
     rcp = sum_lanes<KP>(rcp);
     h = sum_lanes<KP>(h);
@@ -981,7 +1003,7 @@ __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP
         const int tl = min(tile0 + w + NWY_OF<KP> * s, nt - 1) - tile0;
         const f32x4 zp = zprod<KP, PREC>(yfr[s], xf);
         float L4[4], G4[4];
-        tile_loss<LK, false, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, tl, zp, av[s], L4, G4);
+        tile_loss<LK, false, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, tl, zp, av[s], L4, G4, tile0 + tl);
 #pragma unroll
         for (int r = 0; r < 4; ++r) hacc[s][r] += L4[r];
     }
@@ -1208,7 +1230,7 @@ __device__ __forceinline__ float grad_tiles(const LossGradArgs &a, PanelBuf<KP, 
         }
         if (t >= nt) continue;
         float L4[4], G[4];
-        tile_loss<LK, WANT_GRAD, false, TPW>(a.lu, *lt, s_codes, s_tcode, t - tile0, z, av, L4, G);
+        tile_loss<LK, WANT_GRAD, false, TPW>(a.lu, *lt, s_codes, s_tcode, t - tile0, z, av, L4, G, t);
         opart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
         if constexpr (WANT_GRAD) {
             s3_resident<KP, PREC>(dx, G, ytf[s]);

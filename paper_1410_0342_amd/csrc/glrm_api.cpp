@@ -16,6 +16,7 @@
 #include "coo.h"
 #include "impute.h"
 #include "linalg.h"
+#include "proxprox.h"
 #include "smallmat.h"
 
 using namespace glrm;
@@ -74,7 +75,7 @@ struct Layout {
     int pmax = 0;               // partial slots of the dense fit passes
     size_t total = 0;
     // offsets
-    size_t codes, row_count, col_count, Ap;
+    size_t codes, colw, row_count, col_count, Ap;
     size_t part_dy, part_h, part_hp, part_rowreg, part_rej, part_dx, part_obj;
     size_t ycur_f32, ycur_t32, ycur_hi, ycur_lo, ycur_tb;
     size_t yp_f32, yp_t32, yp_hi, yp_lo, yp_tb;
@@ -90,6 +91,12 @@ struct Layout {
     size_t aux_n1 = 0, aux_n2 = 0;       // n x aux_b doubles
     size_t aux_part = 0;                 // partial sums
     size_t aux_small = 0;                // AUX_SMALL doubles of small matrices
+    size_t aux_cols = 0;                 // 8 n doubles of per-column state
+    // prox-prox region (dense fits with the prox-prox update)
+    bool pp = false;
+    int pp_gsz = 0;
+    size_t pp_At = 0, pp_gram = 0, pp_gpart = 0, pp_trial = 0, pp_fpart = 0;
+    size_t pp_objx = 0, pp_objy = 0, pp_rejx = 0, pp_rejy = 0;
 
     size_t take(size_t bytes)
     {
@@ -101,7 +108,7 @@ struct Layout {
 
 // grad_only: the layout of the gradient entry points alone, whose Y-gradient
 // partials never exceed P_GRAD rows (the fit's run up to P_MAX).
-bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false, int aux_b = 0)
+bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false, int aux_b = 0, bool proxprox = false)
 {
     L = Layout();
     L.m = d->m;
@@ -122,6 +129,7 @@ bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false, int aux_
     }
     const int64_t kp = L.kp, ldp = L.ldp, n = L.n, m = L.m;
     L.codes = L.take(ldp);
+    L.colw = L.take(sizeof(float) * ldp);
     L.row_count = L.take(sizeof(int32_t) * m);
     L.col_count = L.take(sizeof(int32_t) * n);
     L.stats = L.take(sizeof(double) * 8);
@@ -180,6 +188,21 @@ bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false, int aux_
                                                  (int64_t)tall_tmul_blocks(std::max(m, n)) * kb * kb, 256});
         L.aux_part = L.take(sizeof(double) * parts);
         L.aux_small = L.take(sizeof(double) * AUX_SMALL);
+        L.aux_cols = L.take(sizeof(double) * 8 * n);
+    }
+    if (proxprox && d->layout == GLRM_DENSE) {
+        const int64_t rmax = std::max(m, n);
+        L.pp = true;
+        L.pp_gsz = pp_gram_floats((int)kp);
+        L.pp_At = L.take(sizeof(float) * ldp * L.mp);
+        L.pp_gram = L.take(sizeof(float) * rmax * L.pp_gsz);
+        L.pp_gpart = L.take(sizeof(float) * PP_SPLITS_MAX * n * L.pp_gsz);
+        L.pp_trial = L.take(sizeof(float) * rmax * L.k);
+        L.pp_fpart = L.take(sizeof(float) * 2 * std::max<int64_t>(m, (int64_t)PP_SPLITS_MAX * n));
+        L.pp_objx = L.take(sizeof(double) * m);
+        L.pp_objy = L.take(sizeof(double) * n);
+        L.pp_rejx = L.take(sizeof(int32_t) * m);
+        L.pp_rejy = L.take(sizeof(int32_t) * n);
     }
     return true;
 }
@@ -220,6 +243,7 @@ int validate_data(const glrm_data *d)
         for (int64_t j = 0; j < d->n; ++j)
             if (d->col_loss[j] >= d->n_losses) return fail(GLRM_EINVAL, "col_loss[%lld] = %d >= n_losses", (long long)j, d->col_loss[j]);
     }
+    if (d->offset != 0 && d->offset != 1) return fail(GLRM_EINVAL, "offset must be 0 or 1 (got %d)", d->offset);
     for (const glrm_reg *r : {&d->rx, &d->ry}) {
         if (r->kind < GLRM_REG_ZERO || r->kind > GLRM_REG_NONNEG) return fail(GLRM_EINVAL, "unknown regularizer kind %d", r->kind);
         if (!(r->weight >= 0.0f) || !std::isfinite(r->weight)) return fail(GLRM_EINVAL, "regularizer weight must be finite and >= 0");
@@ -227,7 +251,10 @@ int validate_data(const glrm_data *d)
     return GLRM_OK;
 }
 
-LossTab make_losstab(const glrm_data *d)
+// The loss table as the kernels take it.  With per-column weights the table
+// points at the workspace's padded copy of them (written by prepare) and is
+// never treated as uniform, so the weighted per-column path runs.
+LossTab make_losstab(const glrm_data *d, const Layout &L, void *ws)
 {
     LossTab t;
     memset(&t, 0, sizeof t);
@@ -245,10 +272,16 @@ LossTab make_losstab(const glrm_data *d)
             if (d->col_loss[j] != u) { u = -1; break; }
         t.uniform = u;
     }
+    t.colw = at<float>(ws, L.colw);   // all 1 unless the caller gave weights
+    if (d->col_weight) t.uniform = -1;
     return t;
 }
 
-Reg make_reg(const glrm_reg &r) { return Reg{r.kind, r.weight}; }
+Reg make_reg(const glrm_reg &r, int32_t offset = 0) { return Reg{r.kind, r.weight, offset}; }
+// The regularizers of the rows of X and of the columns of Y; with the offset
+// (Section 3.3) coordinate 0 is the constant 1 in X and a free offset in Y.
+Reg reg_x(const glrm_data *d) { return make_reg(d->rx, d->offset ? 1 : 0); }
+Reg reg_y(const glrm_data *d) { return make_reg(d->ry, d->offset ? 2 : 0); }
 
 LossU make_lossu(const LossTab &t)
 {
@@ -303,6 +336,7 @@ int prepare(const glrm_data *d, const Layout &L, void *ws, hipStream_t st)
     std::string codes;
     int rc0 = upload_codes(d, L, ws, codes, st);
     if (rc0) return rc0;
+    HIP_TRY(launch_pad_weights(d->col_weight, L.n, L.ldp, at<float>(ws, L.colw), st));
     if (d->layout == GLRM_DENSE) {
         HIP_TRY(launch_fill_i32(at<int32_t>(ws, L.col_count), L.n, 0, st));
         PackArgs p;
@@ -340,8 +374,8 @@ int write_shadows(const Layout &L, const float *Y, void *ws, int prec, bool clea
 int reg_sums(const glrm_data *d, const Layout &L, const float *X, const float *Y, void *ws, hipStream_t st)
 {
     double *rp = at<double>(ws, L.regpart);
-    HIP_TRY(launch_regsum(make_reg(d->rx), X, L.m, (int32_t)L.k, rp, REG_BLOCKS, st));
-    HIP_TRY(launch_regsum(make_reg(d->ry), Y, L.n, (int32_t)L.k, rp + REG_BLOCKS, REG_BLOCKS, st));
+    HIP_TRY(launch_regsum(reg_x(d), X, L.m, (int32_t)L.k, rp, REG_BLOCKS, st));
+    HIP_TRY(launch_regsum(reg_y(d), Y, L.n, (int32_t)L.k, rp + REG_BLOCKS, REG_BLOCKS, st));
     return GLRM_OK;
 }
 
@@ -355,14 +389,14 @@ int objective64(const glrm_data *d, const Layout &L, const float *X, const float
         a.m = L.m; a.n = L.n; a.mp = L.mp; a.ldp = L.ldp; a.k = (int32_t)L.k;
         a.Ap = at<float>(ws, L.Ap);
         a.codes = at<uint8_t>(ws, L.codes);
-        a.lt = make_losstab(d);
+        a.lt = make_losstab(d, L, ws);
         a.X = X; a.Y = Y;
         a.part_obj = po;
         const int64_t tiles = (L.mp / 16) * ((L.ldp + 255) / 256);
         nparts = (int)std::min<int64_t>(OBJ64_BLOCKS, std::max<int64_t>(1, tiles));
         HIP_TRY(launch_objective64(a, nparts, st));
     } else {
-        int rc = coo_objective(d, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
+        int rc = coo_objective(d, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d, L, ws), X, Y,
                                GLRM_FP64, &po, &nparts, st);
         if (rc != GLRM_OK) return rc;
     }
@@ -397,7 +431,7 @@ int dense_lossgrad(const glrm_data *d, const Layout &L, const float *X, const fl
     a.m = L.m; a.mp = L.mp; a.ldp = L.ldp; a.k = (int32_t)L.k;
     a.Ap = at<float>(ws, L.Ap);
     a.codes = at<uint8_t>(ws, L.codes);
-    a.lt = make_losstab(d);
+    a.lt = make_losstab(d, L, ws);
     a.lu = make_lossu(a.lt);
     a.X = X;
     a.ycur = shadow(ws, L, false);
@@ -499,7 +533,7 @@ int grad_run(const glrm_data *d, const Layout &L, const float *X, const float *Y
         po = at<double>(ws, L.part_obj);
         nparts = (int)(grad_rows(L, true) * L.cb_grad);
     } else {
-        if ((rc = coo_grad(d, L.kp, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
+        if ((rc = coo_grad(d, L.kp, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d, L, ws), X, Y,
                            precision, dX, dY, &po, &nparts, st)))
             return rc;
     }
@@ -550,7 +584,8 @@ int grad_matrix(const glrm_data *d, const Layout &L, const float *X, const float
     ea.m = L.m; ea.n = L.n; ea.mp = L.mp; ea.ldp = L.ldp; ea.k = (int32_t)L.k;
     ea.Ap = d->layout == GLRM_DENSE ? at<float>(ws, L.Ap) : nullptr;
     ea.codes = at<uint8_t>(ws, L.codes);
-    ea.lt = make_losstab(d);
+    ea.lt = make_losstab(d, L, ws);
+    ea.colw = ea.lt.colw;
     ea.X = X; ea.Y = Y;
     if (d->layout == GLRM_DENSE) {
         HIP_TRY(launch_dense_grad_matrix(ea, at<float>(ws, L.aux_V), st));
@@ -594,6 +629,38 @@ int gram_pair(const Layout &L, const float *X, const float *Y, void *ws, std::ve
     return GLRM_OK;
 }
 
+// Orthonormal basis of the columns of Q (rows x b, double) into Qo: with
+// Q^T Q = E diag(l) E^T, Qo = Q E_r diag(l_r)^-1/2 over the eigenvalues above
+// 1e-12 of the largest (a column space of rank r <= b); done twice, as in
+// CholeskyQR2, so the second pass repairs the rounding of the first.  Returns
+// r through *r; the basis ends in *Q (the buffers swap).
+int orthonormalize(const Layout &L, void *ws, double **Q, double **Qo, int64_t rows, int *b, hipStream_t st)
+{
+    double *part = at<double>(ws, L.aux_part), *sm = at<double>(ws, L.aux_small);
+    for (int pass = 0; pass < 2; ++pass) {
+        const int bb = *b;
+        if (bb == 0) return GLRM_OK;
+        HIP_TRY(launch_tall_tmul_d(*Q, rows, bb, bb, *Q, bb, part, sm, st));
+        std::vector<double> G((size_t)bb * bb), w(bb), E((size_t)bb * bb);
+        HIP_TRY(hipMemcpyAsync(G.data(), sm, sizeof(double) * bb * bb, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        glrm_host::sym_eig(bb, G.data(), w.data(), E.data());
+        int r = 0;
+        while (r < bb && w[r] > 1e-12 * std::max(w[0], 0.0) && w[r] > 0.0) ++r;
+        std::vector<double> T((size_t)bb * std::max(r, 1));
+        for (int a = 0; a < bb; ++a)
+            for (int c = 0; c < r; ++c) T[a * r + c] = E[a * bb + c] / std::sqrt(w[c]);
+        if (r > 0) {
+            HIP_TRY(hipMemcpyAsync(sm, T.data(), sizeof(double) * bb * r, hipMemcpyHostToDevice, st));
+            HIP_TRY(launch_tall_mul_d(*Q, rows, bb, bb, sm, r, 1.0, 0.0, *Qo, st));
+            HIP_TRY(hipStreamSynchronize(st));   // T lives on this host stack
+        }
+        std::swap(*Q, *Qo);
+        *b = r;
+    }
+    return GLRM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -607,6 +674,14 @@ size_t glrm_workspace_size(const glrm_data *d)
     if (validate_data(d) != GLRM_OK) return 0;
     Layout L;
     make_layout(d, L);
+    return L.total;
+}
+
+size_t glrm_fit_workspace_size(const glrm_data *d, const glrm_fit_opts *o)
+{
+    if (validate_data(d) != GLRM_OK) return 0;
+    Layout L;
+    make_layout(d, L, false, 0, o && o->update == GLRM_UPDATE_PROXPROX);
     return L.total;
 }
 
@@ -645,7 +720,7 @@ int glrm_objective(const glrm_data *d, const float *X, const float *Y, int preci
             po = at<double>(ws, L.part_obj);
             nparts = (int)(grad_rows(L, false) * L.cb_grad);
         } else {
-            if ((rc = coo_objective(d, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d), X, Y,
+            if ((rc = coo_objective(d, L.cl, at<char>(ws, L.coo), at<uint8_t>(ws, L.codes), make_losstab(d, L, ws), X, Y,
                                     precision, &po, &nparts, st)))
                 return rc;
         }
@@ -763,6 +838,145 @@ int glrm_certificate(const glrm_data *d, const float *X, const float *Y, int32_t
     return GLRM_OK;
 }
 
+int glrm_column_scaling(const glrm_data *d, float *mu, float *sigma2, void *ws, size_t ws_bytes, unsigned flags,
+                        void *stream)
+{
+    g_err.clear();
+    int rc = validate_data(d);
+    if (rc) return rc;
+    if (!mu || !sigma2) return fail(GLRM_EINVAL, "mu and sigma2 must not be NULL");
+    Layout L;
+    make_layout(d, L, false, 1);
+    if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    const bool coo = d->layout != GLRM_DENSE;
+    ColArgs a;
+    memset(&a, 0, sizeof a);
+    a.m = L.m; a.n = L.n; a.mp = L.mp; a.ldp = L.ldp;
+    if (coo) {
+        const CooView cv = coo_view(L.cl, at<char>(ws, L.coo));
+        a.col_ptr = cv.col_ptr;
+        a.csc_val = cv.csc_val;
+    } else {
+        a.Ap = at<float>(ws, L.Ap);
+    }
+    a.codes = at<uint8_t>(ws, L.codes);
+    a.lt = make_losstab(d, L, ws);
+    double *lo = at<double>(ws, L.aux_cols), *hi = lo + L.n, *mid = hi + L.n, *out = mid + L.n;
+    a.mid = mid;
+    double *part = at<double>(ws, L.aux_part);
+    const int32_t *count = at<int32_t>(ws, L.col_count);
+    HIP_TRY(launch_col_pass(a, 0, coo, part, out, st));
+    HIP_TRY(launch_bracket(lo, hi, mid, out, count, L.n, true, st));
+    // bisection on the sign of the derivative sum: the bracket [min a - 1,
+    // max a + 1] holds a minimizer of every loss here, and 64 halvings take it
+    // to double rounding
+    for (int it = 0; it < 64; ++it) {
+        HIP_TRY(launch_col_pass(a, 1, coo, part, out, st));
+        HIP_TRY(launch_bracket(lo, hi, mid, out, count, L.n, false, st));
+    }
+    HIP_TRY(launch_col_pass(a, 2, coo, part, out, st));
+    HIP_TRY(launch_scaling_finish(mid, out, count, L.n, mu, sigma2, st));
+    return GLRM_OK;
+}
+
+int glrm_init_svd(const glrm_data *d, const float *mu, const float *sigma2, const float *omega, int32_t l,
+                  int32_t power_iters, float *X, float *Y, double *sv_host, void *ws, size_t ws_bytes,
+                  unsigned flags, void *stream)
+{
+    g_err.clear();
+    int rc = validate_data(d);
+    if (rc) return rc;
+    const int k = d->k, off = d->offset ? 1 : 0, ks = k - off;
+    if (!X || !Y) return fail(GLRM_EINVAL, "X and Y must not be NULL");
+    if (off && !mu) return fail(GLRM_EINVAL, "the offset row needs the column means mu");
+    if (ks > 0 && !omega) return fail(GLRM_EINVAL, "omega (the n x l test matrix) must not be NULL");
+    if (l < ks || l < 1 || l > LA_MAXB) return fail(GLRM_EINVAL, "l must be in max(k', 1)..%d (k' = %d)", LA_MAXB, ks);
+    if (power_iters < 0 || power_iters > 32) return fail(GLRM_EINVAL, "power_iters must be in 0..32");
+    Layout L;
+    make_layout(d, L, false, l);
+    if ((rc = check_ws(L, ws, ws_bytes))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    const int64_t m = L.m, n = L.n;
+    const int32_t *count = at<int32_t>(ws, L.col_count);
+    float *cs = at<float>(ws, L.aux_cols), *mu0 = cs + n;
+    HIP_TRY(launch_svd_scales(mu, sigma2, count, m, n, cs, mu0, st));
+    for (int c = 0; c < k; ++c) {
+        HIP_TRY(launch_fill_column(X, m, k, c, c < off ? 1.0f : 0.0f, nullptr, st));
+        HIP_TRY(launch_fill_column(Y, n, k, c, 0.0f, c < off ? mu0 : nullptr, st));
+    }
+    std::vector<double> svals(std::max(ks, 1), 0.0);
+    if (ks > 0) {
+        // the standardized table of Section 7.5 in the aux region
+        EntryArgs ea;
+        memset(&ea, 0, sizeof ea);
+        ea.m = m; ea.n = n; ea.mp = L.mp; ea.ldp = L.ldp; ea.k = k;
+        ea.Ap = d->layout == GLRM_DENSE ? at<float>(ws, L.Ap) : nullptr;
+        ea.mu = mu0; ea.cs = cs;
+        if (d->layout == GLRM_DENSE) {
+            HIP_TRY(launch_dense_scaled_matrix(ea, at<float>(ws, L.aux_V), st));
+        } else {
+            HIP_TRY(launch_coo_scaled_values(ea, d->col, d->A, d->nnz, at<float>(ws, L.aux_V), st));
+            HIP_TRY(launch_permute(coo_perm(L.cl, at<char>(ws, L.coo)), at<float>(ws, L.aux_V), d->nnz,
+                                   at<float>(ws, L.aux_V2), st));
+        }
+        double *Qa = at<double>(ws, L.aux_m1), *Qb = at<double>(ws, L.aux_m2);
+        double *Za = at<double>(ws, L.aux_n1), *Zb = at<double>(ws, L.aux_n2);
+        double *sm = at<double>(ws, L.aux_small);
+        // randomized range finder (Halko, Martinsson, Tropp 2011): Q = orth(A~ Omega),
+        // then power_iters rounds of Q = orth(A~ orth(A~^T Q))
+        int b = l;
+        HIP_TRY(launch_to_double(omega, n * (int64_t)l, Za, st));
+        if ((rc = apply_matrix(d, L, ws, false, Za, b, 1.0, Qa, st))) return rc;
+        if ((rc = orthonormalize(L, ws, &Qa, &Qb, m, &b, st))) return rc;
+        for (int it = 0; it < power_iters && b > 0; ++it) {
+            if ((rc = apply_matrix(d, L, ws, true, Qa, b, 1.0, Za, st))) return rc;
+            if ((rc = orthonormalize(L, ws, &Za, &Zb, n, &b, st))) return rc;
+            if (b == 0) break;
+            if ((rc = apply_matrix(d, L, ws, false, Za, b, 1.0, Qa, st))) return rc;
+            if ((rc = orthonormalize(L, ws, &Qa, &Qb, m, &b, st))) return rc;
+        }
+        if (b > 0) {
+            // B = Q^T A~ (kept transposed, n x b); B B^T = U_B diag(s^2) U_B^T
+            if ((rc = apply_matrix(d, L, ws, true, Qa, b, 1.0, Za, st))) return rc;
+            double *part = at<double>(ws, L.aux_part);
+            HIP_TRY(launch_tall_tmul_d(Za, n, b, b, Za, b, part, sm, st));
+            std::vector<double> C((size_t)b * b), s2(b), U((size_t)b * b);
+            HIP_TRY(hipMemcpyAsync(C.data(), sm, sizeof(double) * b * b, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            glrm_host::sym_eig(b, C.data(), s2.data(), U.data());
+            const double smax = std::sqrt(std::max(s2[0], 0.0));
+            int r = 0;
+            while (r < ks && r < b && s2[r] > 0.0 && std::sqrt(s2[r]) > 1e-6 * smax) ++r;
+            if (r > 0) {
+                // X = Q U_B,r diag(s^1/2);  Y = diag(sigma) B^T U_B,r diag(s^-1/2) (= V diag(s^1/2))
+                std::vector<double> S1((size_t)b * r), S2((size_t)b * r);
+                for (int a = 0; a < b; ++a)
+                    for (int t = 0; t < r; ++t) {
+                        const double sv = std::sqrt(s2[t]);
+                        S1[a * r + t] = U[a * b + t] * std::sqrt(sv);
+                        S2[a * r + t] = U[a * b + t] / std::sqrt(sv);
+                    }
+                for (int t = 0; t < r; ++t) svals[t] = std::sqrt(s2[t]);
+                double *S1d = sm, *S2d = sm + (size_t)b * r;
+                HIP_TRY(hipMemcpyAsync(S1d, S1.data(), sizeof(double) * b * r, hipMemcpyHostToDevice, st));
+                HIP_TRY(hipMemcpyAsync(S2d, S2.data(), sizeof(double) * b * r, hipMemcpyHostToDevice, st));
+                HIP_TRY(launch_tall_mul_d(Qa, m, b, b, S1d, r, 1.0, 0.0, Qb, st));
+                HIP_TRY(launch_tall_mul_d(Za, n, b, b, S2d, r, 1.0, 0.0, Zb, st));
+                HIP_TRY(launch_to_float_scaled(Qb, m, r, r, nullptr, X, k, off, st));
+                HIP_TRY(launch_to_float_scaled(Zb, n, r, r, sigma2, Y, k, off, st));
+                HIP_TRY(hipStreamSynchronize(st));   // S1, S2 live on this host stack
+            }
+        }
+    }
+    if (sv_host)
+        for (int t = 0; t < ks; ++t) sv_host[t] = svals[t];
+    HIP_TRY(hipStreamSynchronize(st));
+    return GLRM_OK;
+}
+
 int glrm_impute(const glrm_data *d, const float *X, const float *Y, int32_t mode, float *Ahat, int64_t ldh, void *ws,
                 size_t ws_bytes, unsigned flags, void *stream)
 {
@@ -784,6 +998,7 @@ int glrm_impute(const glrm_data *d, const float *X, const float *Y, int32_t mode
         } else {
             std::string codes;
             if ((rc = upload_codes(d, L, ws, codes, st))) return rc;
+            HIP_TRY(launch_pad_weights(d->col_weight, L.n, L.ldp, at<float>(ws, L.colw), st));
             HIP_TRY(hipStreamSynchronize(st));
         }
     }
@@ -800,7 +1015,7 @@ int glrm_impute(const glrm_data *d, const float *X, const float *Y, int32_t mode
     a.rows_per_block = impute_rows_per_block(d->m, d->n);
     a.keep_observed = dense_keep ? 1 : 0;
     a.codes = at<uint8_t>(ws, L.codes);
-    a.lt = make_losstab(d);
+    a.lt = make_losstab(d, L, ws);
     HIP_TRY(launch_impute(a, X, Y, dense_keep ? d->A : nullptr, dense_keep ? d->mask : nullptr, Ahat, st));
     if (d->layout == GLRM_COO_ROWSORTED && mode == GLRM_IMPUTE_MISSING)
         HIP_TRY(launch_scatter_observed(d->nnz, d->m, d->n, ldh, d->row, d->col, d->A, Ahat, st));
@@ -833,12 +1048,28 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
     if (o->init_alpha && !(o->alpha_scale > 0.0f && std::isfinite(o->alpha_scale)))
         return fail(GLRM_EINVAL, "alpha_scale must be finite and > 0");
     if (!(o->tol >= 0.0)) return fail(GLRM_EINVAL, "tol must be >= 0");
+    if (o->update != GLRM_UPDATE_PROXGRAD && o->update != GLRM_UPDATE_PROXPROX)
+        return fail(GLRM_EINVAL, "unknown update rule %d", o->update);
+    const bool proxprox = o->update == GLRM_UPDATE_PROXPROX;
+    if (proxprox) {
+        if (d->layout != GLRM_DENSE) return fail(GLRM_EUNSUPPORTED, "the prox-prox update is built for the dense layout");
+        if (o->precision != GLRM_FP32) return fail(GLRM_EUNSUPPORTED, "the prox-prox update computes in FP32 (and FP64 for the solves)");
+        if (o->inner < 1 || o->inner > 10000) return fail(GLRM_EINVAL, "inner must be in 1..10000");
+        for (int64_t j = 0; j < d->n; ++j) {
+            const int q = d->col_loss ? d->col_loss[j] : 0;
+            if (d->losses[q].kind != GLRM_LOSS_QUADRATIC)
+                return fail(GLRM_EUNSUPPORTED, "the prox-prox update needs the quadratic loss on every column (column %lld)",
+                            (long long)j);
+        }
+    }
     Layout L;
-    make_layout(d, L);
+    make_layout(d, L, false, 0, proxprox);
     if ((rc = check_ws(L, ws, ws_bytes))) return rc;
     const int prec = o->precision;
     int tpw = 0, tpw_y = 0;
-    if (d->layout == GLRM_DENSE) {
+    if (proxprox) {
+        // no pass-shape limits: the Gram, solve and check passes take any width
+    } else if (d->layout == GLRM_DENSE) {
         tpw = tpw_xstep(L.ldp / 16, (int)L.kp);
         tpw_y = tpw_ycheck(L.ldp / 16, (int)L.kp);
         if (tpw == 0 || tpw_y == 0)
@@ -856,13 +1087,59 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
         HIP_TRY(launch_init_alpha(at<int32_t>(ws, L.row_count), L.m, o->alpha_scale, alpha_x, st));
         HIP_TRY(launch_init_alpha(at<int32_t>(ws, L.col_count), L.n, o->alpha_scale, alpha_y, st));
     }
-    const LossTab lt = make_losstab(d);
+    const LossTab lt = make_losstab(d, L, ws);
     double *stats = at<double>(ws, L.stats);
     long long *istats = at<long long>(ws, L.istats);
     int sweeps = 0;
     double F_prev = NAN;
 
-    if (d->layout == GLRM_DENSE) {
+    if (proxprox) {
+        // the transposed table serves the column half-step as rows
+        HIP_TRY(launch_transpose(at<float>(ws, L.Ap), L.mp, L.ldp, at<float>(ws, L.pp_At), st));
+        PPArgs px;
+        memset(&px, 0, sizeof px);
+        px.rows = L.m; px.cols = L.n; px.ldt = L.ldp; px.k = (int32_t)L.k; px.kp = (int32_t)L.kp;
+        px.T = at<float>(ws, L.Ap);
+        px.wcol = at<float>(ws, L.colw);
+        px.wrow = nullptr;
+        px.U = X; px.V = Y; px.alpha = alpha_x; px.reg = reg_x(d);
+        px.inner = o->inner; px.step_up = o->step_up; px.step_down = o->step_down;
+        px.gram = at<float>(ws, L.pp_gram); px.gpart = at<float>(ws, L.pp_gpart); px.splits = 1;
+        px.trial = at<float>(ws, L.pp_trial); px.fpart = at<float>(ws, L.pp_fpart);
+        px.rowobj = at<double>(ws, L.pp_objx); px.obj_with_loss = 0; px.rej = at<int32_t>(ws, L.pp_rejx);
+        PPArgs py = px;
+        py.rows = L.n; py.cols = L.m; py.ldt = L.mp;
+        py.T = at<float>(ws, L.pp_At);
+        py.wcol = nullptr;
+        py.wrow = at<float>(ws, L.colw);
+        py.U = Y; py.V = X; py.alpha = alpha_y; py.reg = reg_y(d);
+        py.splits = (int32_t)std::min<int64_t>(PP_SPLITS_MAX, std::max<int64_t>(1, L.m / 1024));
+        py.rowobj = at<double>(ws, L.pp_objy); py.obj_with_loss = 1; py.rej = at<int32_t>(ws, L.pp_rejy);
+        for (int t = 0; t < o->max_sweeps; ++t) {
+            HIP_TRY(timer.start(0, st));
+            HIP_TRY(launch_pp_gram(px, st));
+            HIP_TRY(launch_pp_solve(px, st));
+            HIP_TRY(launch_pp_check(px, st));
+            HIP_TRY(timer.stop(st));
+            HIP_TRY(timer.start(2, st));
+            HIP_TRY(launch_pp_gram(py, st));
+            HIP_TRY(launch_pp_solve(py, st));
+            HIP_TRY(launch_pp_check(py, st));
+            HIP_TRY(timer.stop(st));
+            HIP_TRY(timer.start(3, st));
+            HIP_TRY(launch_pp_finalize(px.rowobj, px.rej, L.m, py.rowobj, py.rej, L.n, nullptr, stats, istats, history,
+                                       t, st));
+            HIP_TRY(timer.stop(st));
+            sweeps = t + 1;
+            if (o->tol > 0.0) {
+                double F;
+                HIP_TRY(hipMemcpyAsync(&F, stats, sizeof(double), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                if (t > 0 && (F_prev - F) <= o->tol * std::fabs(F_prev)) break;
+                F_prev = F;
+            }
+        }
+    } else if (d->layout == GLRM_DENSE) {
         if ((rc = write_shadows(L, Y, ws, prec, true, st))) return rc;
         const int64_t npanels = L.mp / 16;
         // persistent grids: as many workgroups as fit on the device at once
@@ -888,7 +1165,7 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
         xa.codes = at<uint8_t>(ws, L.codes);
         xa.lt = lt;
         xa.lu = make_lossu(lt);
-        xa.rx = make_reg(d->rx);
+        xa.rx = reg_x(d);
         xa.X = X;
         xa.alpha = alpha_x;
         xa.step_up = o->step_up; xa.step_down = o->step_down;
@@ -901,7 +1178,7 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
         YProxArgs pa;
         pa.n = L.n; pa.ldp = L.ldp; pa.k = (int32_t)L.k; pa.P = grid;
         pa.part_dy = xa.part_dy; pa.part_h = xa.part_h;
-        pa.ry = make_reg(d->ry);
+        pa.ry = reg_y(d);
         pa.Y = Y; pa.alpha = alpha_y;
         pa.Yplus = at<float>(ws, L.Yplus);
         pa.yplus = shadow(ws, L, true);

@@ -29,12 +29,17 @@ struct LossTab {
     int32_t levels[MAX_LOSSES];
     float param[MAX_LOSSES];
     int32_t n;
-    int32_t uniform;   // >= 0: every column uses losses[uniform]; -1: mixed
+    int32_t uniform;   // >= 0: every column uses losses[uniform] with weight 1; -1: per-column table
+    const float *colw; // per-column loss weights (padded to the table's width), or null for 1
 };
 
+// A regularizer; `offset` marks coordinate 0 as the model's offset
+// (Section 3.3): 1 = held at the constant 1 (the rows of X), 2 = free and
+// unpenalized (the columns of Y); 0 = no offset.
 struct Reg {
     int32_t kind;
     float w;
+    int32_t offset;
 };
 
 // ---- losses ------------------------------------------------------------------
@@ -206,9 +211,12 @@ __device__ __forceinline__ double loss_g64(int kind, int levels, double param, d
 
 // ---- regularizers -------------------------------------------------------------
 
-// One coordinate's share of r(x) (the sum over coordinates is r).
-__device__ __forceinline__ float reg_elem(const Reg &r, float x)
+// One coordinate's share of r(x) (the sum over coordinates is r); c is the
+// coordinate.  With an offset, coordinate 0 carries no penalty, and on the
+// rows of X only x_0 = 1 is feasible.
+__device__ __forceinline__ float reg_elem(const Reg &r, float x, int c)
 {
+    if (c == 0 && r.offset) return (r.offset == 1 && x != 1.0f) ? __builtin_huge_valf() : 0.0f;
     switch (r.kind) {
     case R_QUAD: return r.w * x * x;
     case R_L1: return r.w * fabsf(x);
@@ -217,8 +225,9 @@ __device__ __forceinline__ float reg_elem(const Reg &r, float x)
     }
 }
 
-__device__ __forceinline__ double reg_elem64(const Reg &r, double x)
+__device__ __forceinline__ double reg_elem64(const Reg &r, double x, int c)
 {
+    if (c == 0 && r.offset) return (r.offset == 1 && x != 1.0) ? __builtin_huge_val() : 0.0;
     switch (r.kind) {
     case R_QUAD: return (double)r.w * x * x;
     case R_L1: return (double)r.w * fabs(x);
@@ -231,14 +240,16 @@ __device__ __forceinline__ double reg_elem64(const Reg &r, double x)
 // 0 * x, which is exactly r(x) for a finite coordinate and NaN for an
 // infinite or NaN one, so a trial objective built from it is NaN and the
 // step is rejected (a non-finite point lies outside the model's domain).
-__device__ __forceinline__ float reg_elem_trial(const Reg &r, float x)
+__device__ __forceinline__ float reg_elem_trial(const Reg &r, float x, int c)
 {
-    return reg_elem(r, x) + 0.0f * x;
+    return reg_elem(r, x, c) + 0.0f * x;
 }
 
-// prox_{alpha r}(v), coordinate-wise (every supported r is separable).
-__device__ __forceinline__ float prox_elem(const Reg &r, float alpha, float v)
+// prox_{alpha r}(v), coordinate-wise (every supported r is separable); the
+// offset coordinate is projected onto 1 (X) or left as it is (Y).
+__device__ __forceinline__ float prox_elem(const Reg &r, float alpha, float v, int c)
 {
+    if (c == 0 && r.offset) return r.offset == 1 ? 1.0f : v;
     switch (r.kind) {
     case R_QUAD: return v / (1.0f + 2.0f * alpha * r.w);
     case R_L1: {

@@ -76,5 +76,41 @@ hipError_t launch_start_vector(double *v, int64_t len, uint64_t seed, hipStream_
 hipError_t launch_to_float(const double *src, int64_t rows, int32_t b, int32_t cols, float *dst, int64_t ldd,
                            int32_t col0, hipStream_t st);
 
+// ---- per-column sums for the loss scaling of Section 4.3 ----------------------
+// MODE 0: min and max of the observed entries; 1: sum of dL_j(mid_j, a);
+// 2: sum of L_j(mid_j, a).  Dense: partials over row chunks (part: R x 2 x n
+// doubles) then a fixed-order reduction into out (2 x n); COO: one wavefront
+// per column of the column-grouped copy, straight into out.
+struct ColArgs {
+    int64_t m, n, mp, ldp;
+    const float *Ap;            // dense table (NaN = unobserved)
+    const int32_t *col_ptr;     // COO column view
+    const float *csc_val;
+    const uint8_t *codes;
+    LossTab lt;
+    const double *mid;          // n: the point of modes 1 and 2
+};
+int col_pass_chunks(int64_t m);
+hipError_t launch_col_pass(const ColArgs &a, int mode, bool coo, double *part, double *out, hipStream_t st);
+// lo, hi (n): the bracket; mid = (lo + hi) / 2.  init: lo = min - 1, hi = max + 1
+// from out (mode 0); step: the half whose end keeps the derivative's sign change.
+hipError_t launch_bracket(double *lo, double *hi, double *mid, const double *out, const int32_t *count, int64_t n,
+                          bool init, hipStream_t st);
+// mu_j = mid_j (0 for an empty column); sigma2_j = S_j / (n_j - 1), or 1 when
+// n_j < 2 or S_j <= 0 (S_j = out[j], mode 2).
+hipError_t launch_scaling_finish(const double *mid, const double *out, const int32_t *count, int64_t n, float *mu,
+                                 float *sigma2, hipStream_t st);
+// cs_j = m / (sigma_j m_j) (0 for an empty column), mu0_j = mu_j or 0 (Section 7.5).
+hipError_t launch_svd_scales(const float *mu, const float *sigma2, const int32_t *count, int64_t m, int64_t n,
+                             float *cs, float *mu0, hipStream_t st);
+// dst[i ldd + col0 + c] = src[i b + c] * (rowscale ? sqrt(rowscale[i]) : 1), c < cols
+hipError_t launch_to_float_scaled(const double *src, int64_t rows, int32_t b, int32_t cols, const float *rowscale,
+                                  float *dst, int64_t ldd, int32_t col0, hipStream_t st);
+// dst[i ldd + col] = value (value_vec ? value_vec[i] : value)
+hipError_t launch_fill_column(float *dst, int64_t rows, int64_t ldd, int32_t col, float value,
+                              const float *value_vec, hipStream_t st);
+// double copy of a float block: dst (rows x b) = src (rows x b)
+hipError_t launch_to_double(const float *src, int64_t len, double *dst, hipStream_t st);
+
 }  // namespace glrm
 

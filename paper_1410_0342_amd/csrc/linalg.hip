@@ -450,4 +450,210 @@ hipError_t launch_to_float(const double *src, int64_t rows, int32_t b, int32_t c
     return hipGetLastError();
 }
 
+// ---- per-column sums (loss scaling) ------------------------------------------------
+
+constexpr int COL_CHUNKS = 32;
+
+int col_pass_chunks(int64_t m) { return (int)std::min<int64_t>(COL_CHUNKS, std::max<int64_t>(1, (m + 255) / 256)); }
+
+template <int MODE>
+__device__ __forceinline__ void col_term(const ColArgs &a, int64_t j, float av, double &s0, double &s1)
+{
+    if constexpr (MODE == 0) {
+        s0 = fmin(s0, (double)av);
+        s1 = fmax(s1, (double)av);
+    } else {
+        const int q = a.lt.uniform >= 0 ? a.lt.uniform : a.codes[j];
+        const double mu = a.mid[j];
+        if constexpr (MODE == 1) s0 += loss_g64(a.lt.kind[q], a.lt.levels[q], (double)a.lt.param[q], mu, (double)av);
+        else s0 += loss_l64(a.lt.kind[q], a.lt.levels[q], (double)a.lt.param[q], mu, (double)av);
+    }
+}
+
+// thread per column, rows of chunk blockIdx.y (coalesced across the threads)
+template <int MODE>
+__global__ __launch_bounds__(256) void col_pass_dense_kernel(ColArgs a, int64_t per, double *part)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= a.n) return;
+    const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min<int64_t>(a.m, r0 + per);
+    double s0 = MODE == 0 ? __builtin_huge_val() : 0.0, s1 = MODE == 0 ? -__builtin_huge_val() : 0.0;
+    for (int64_t i = r0; i < r1; ++i) {
+        const float av = a.Ap[i * a.ldp + j];
+        if (av == av) col_term<MODE>(a, j, av, s0, s1);
+    }
+    part[((int64_t)blockIdx.y * 2) * a.n + j] = s0;
+    part[((int64_t)blockIdx.y * 2 + 1) * a.n + j] = s1;
+}
+
+template <int MODE>
+__global__ void col_reduce_kernel(const double *part, int32_t R, int64_t n, double *out)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    double s0 = MODE == 0 ? __builtin_huge_val() : 0.0, s1 = MODE == 0 ? -__builtin_huge_val() : 0.0;
+    for (int r = 0; r < R; ++r) {
+        const double p0 = part[((int64_t)r * 2) * n + j], p1 = part[((int64_t)r * 2 + 1) * n + j];
+        if constexpr (MODE == 0) { s0 = fmin(s0, p0); s1 = fmax(s1, p1); }
+        else s0 += p0;
+    }
+    out[j] = s0;
+    out[n + j] = s1;
+}
+
+// one wavefront per column of the column-grouped copy
+template <int MODE>
+__global__ __launch_bounds__(256) void col_pass_coo_kernel(ColArgs a, double *out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= a.n) return;
+    double s0 = MODE == 0 ? __builtin_huge_val() : 0.0, s1 = MODE == 0 ? -__builtin_huge_val() : 0.0;
+    for (int32_t e = a.col_ptr[j] + lane; e < a.col_ptr[j + 1]; e += 64) col_term<MODE>(a, j, a.csc_val[e], s0, s1);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const double t0 = __shfl_xor(s0, o, 64), t1 = __shfl_xor(s1, o, 64);
+        if constexpr (MODE == 0) { s0 = fmin(s0, t0); s1 = fmax(s1, t1); }
+        else { s0 += t0; s1 += t1; }
+    }
+    if (lane == 0) {
+        out[j] = s0;
+        out[a.n + j] = s1;
+    }
+}
+
+template <int MODE>
+static hipError_t col_pass(const ColArgs &a, bool coo, double *part, double *out, hipStream_t st)
+{
+    if (coo) {
+        hipLaunchKernelGGL(col_pass_coo_kernel<MODE>, dim3(nblk(a.n, 4)), dim3(256), 0, st, a, out);
+    } else {
+        const int R = col_pass_chunks(a.m);
+        const int64_t per = (a.m + R - 1) / R;
+        hipLaunchKernelGGL(col_pass_dense_kernel<MODE>, dim3(nblk(a.n), R), dim3(256), 0, st, a, per, part);
+        hipLaunchKernelGGL(col_reduce_kernel<MODE>, dim3(nblk(a.n)), dim3(256), 0, st, part, R, a.n, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_col_pass(const ColArgs &a, int mode, bool coo, double *part, double *out, hipStream_t st)
+{
+    switch (mode) {
+    case 0: return col_pass<0>(a, coo, part, out, st);
+    case 1: return col_pass<1>(a, coo, part, out, st);
+    default: return col_pass<2>(a, coo, part, out, st);
+    }
+}
+
+__global__ void bracket_kernel(double *lo, double *hi, double *mid, const double *out, const int32_t *count, int64_t n,
+                               bool init)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    if (init) {
+        if (count[j] > 0) {
+            lo[j] = out[j] - 1.0;
+            hi[j] = out[n + j] + 1.0;
+        } else {
+            lo[j] = hi[j] = 0.0;
+        }
+    } else {
+        // a negative derivative at mid: the minimum lies above it
+        if (out[j] < 0.0) lo[j] = mid[j];
+        else hi[j] = mid[j];
+    }
+    mid[j] = 0.5 * (lo[j] + hi[j]);
+}
+
+hipError_t launch_bracket(double *lo, double *hi, double *mid, const double *out, const int32_t *count, int64_t n,
+                          bool init, hipStream_t st)
+{
+    hipLaunchKernelGGL(bracket_kernel, dim3(nblk(n)), dim3(256), 0, st, lo, hi, mid, out, count, n, init);
+    return hipGetLastError();
+}
+
+__global__ void scaling_finish_kernel(const double *mid, const double *out, const int32_t *count, int64_t n, float *mu,
+                                      float *sigma2)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const int c = count[j];
+    mu[j] = c > 0 ? (float)mid[j] : 0.0f;
+    const double S = out[j];
+    sigma2[j] = (c >= 2 && S > 0.0) ? (float)(S / (double)(c - 1)) : 1.0f;
+}
+
+hipError_t launch_scaling_finish(const double *mid, const double *out, const int32_t *count, int64_t n, float *mu,
+                                 float *sigma2, hipStream_t st)
+{
+    hipLaunchKernelGGL(scaling_finish_kernel, dim3(nblk(n)), dim3(256), 0, st, mid, out, count, n, mu, sigma2);
+    return hipGetLastError();
+}
+
+__global__ void svd_scales_kernel(const float *mu, const float *sigma2, const int32_t *count, int64_t m, int64_t n,
+                                  float *cs, float *mu0)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const int c = count[j];
+    const double sig = sigma2 ? sqrt((double)sigma2[j]) : 1.0;
+    cs[j] = (c > 0 && sig > 0.0) ? (float)((double)m / (sig * (double)c)) : 0.0f;
+    mu0[j] = mu ? mu[j] : 0.0f;
+}
+
+hipError_t launch_svd_scales(const float *mu, const float *sigma2, const int32_t *count, int64_t m, int64_t n,
+                             float *cs, float *mu0, hipStream_t st)
+{
+    hipLaunchKernelGGL(svd_scales_kernel, dim3(nblk(n)), dim3(256), 0, st, mu, sigma2, count, m, n, cs, mu0);
+    return hipGetLastError();
+}
+
+__global__ void to_float_scaled_kernel(const double *src, int64_t rows, int32_t b, int32_t cols,
+                                       const float *rowscale, float *dst, int64_t ldd, int32_t col0)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= rows * cols) return;
+    const int64_t i = t / cols;
+    const int c = (int)(t % cols);
+    const double sc = rowscale ? sqrt((double)rowscale[i]) : 1.0;
+    dst[i * ldd + col0 + c] = (float)(src[i * b + c] * sc);
+}
+
+hipError_t launch_to_float_scaled(const double *src, int64_t rows, int32_t b, int32_t cols, const float *rowscale,
+                                  float *dst, int64_t ldd, int32_t col0, hipStream_t st)
+{
+    if (rows * cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(to_float_scaled_kernel, dim3(nblk(rows * cols)), dim3(256), 0, st, src, rows, b, cols, rowscale,
+                       dst, ldd, col0);
+    return hipGetLastError();
+}
+
+__global__ void fill_column_kernel(float *dst, int64_t rows, int64_t ldd, int32_t col, float value,
+                                   const float *value_vec)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < rows) dst[i * ldd + col] = value_vec ? value_vec[i] : value;
+}
+
+hipError_t launch_fill_column(float *dst, int64_t rows, int64_t ldd, int32_t col, float value,
+                              const float *value_vec, hipStream_t st)
+{
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_column_kernel, dim3(nblk(rows)), dim3(256), 0, st, dst, rows, ldd, col, value, value_vec);
+    return hipGetLastError();
+}
+
+__global__ void to_double_kernel(const float *src, int64_t len, double *dst)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < len) dst[t] = (double)src[t];
+}
+
+hipError_t launch_to_double(const float *src, int64_t len, double *dst, hipStream_t st)
+{
+    if (len <= 0) return hipSuccess;
+    hipLaunchKernelGGL(to_double_kernel, dim3(nblk(len)), dim3(256), 0, st, src, len, dst);
+    return hipGetLastError();
+}
+
 }  // namespace glrm

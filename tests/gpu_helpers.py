@@ -35,7 +35,7 @@ def rel_fro(a, b):
 # ---- decisions near a tie ------------------------------------------------------
 #
 # The GPU forms its step x+ = prox(x - alpha g) from a gradient g that carries
-# rounding error.  A gradient coordinate is a sum of terms G_ij y_jc, and its
+# rounding error (bound: grad_eps below).  A gradient coordinate is a sum of terms G_ij y_jc, and its
 # rounding error is a fraction of the sum of their magnitudes,
 # S_c = sum_j |G_ij| |y_jc| (the oracle's grad_abs): about 2^-8 of it when
 # the contraction is one bfloat16 product per term (the BF16 form: both
@@ -50,35 +50,66 @@ def rel_fro(a, b):
 # margin |f+ - f| lies inside the band may legitimately go either way; every
 # other decision must match the oracle's.
 
-GRAD_REL = {"fp32": 2.0 ** -16, "bf16": 2.0 ** -8}
+GRAD_REL = {"fp32": 0.0, "bf16": 2.0 ** -8}
 SUM_REL = 1e-5
+# Two sources.  (1) The products: in BF16 each term's operands are rounded to
+# 8 bits (worst case 2^-8 of S_c above, all errors of one sign).  Rounding
+# errors of independent terms add in quadrature instead: rounded to nearest,
+# each operand's error is uniform within 2^-9 relative, so the sum's error
+# has a standard deviation of about 0.82 2^-9 of the root of the squared terms
+# R_c, and 2^-6 R_c is six of them; the smaller bound is taken.  FP32
+# products are exact to 2^-24, below (2).  (2) The float32 accumulation: the
+# kernels add runs of at most about 2^10 terms in sequence (a workgroup's rows
+# or a wavefront's chunk) before fixed-order reductions of the partials, so
+# the accumulated error stays below 2^10 2^-24 = 2^-14 of S_c.
+RSS_REL = {"fp32": None, "bf16": 2.0 ** -6}
+ACC_REL = 2.0 ** -14
 
 
-def _reg_slope(reg, V):
+def grad_eps(P, which, X, Y, alpha, prec):
+    """Per-coordinate bound on |x+_gpu - x+_oracle| from the gradient's rounding."""
+    S = P.grad_abs(X, Y)[0 if which == "x" else 1]
+    bound = GRAD_REL[prec] * S
+    if RSS_REL[prec] is not None:
+        R = P.grad_rss(X, Y)[0 if which == "x" else 1]
+        bound = np.minimum(bound, RSS_REL[prec] * R)
+    return 2.0 * np.asarray(alpha, np.float64)[:, None] * (bound + ACC_REL * S)
+
+
+def _reg_slope(reg, V, offset=0):
     kind, w = reg
     if kind == 1:
-        return 2.0 * w * np.abs(V)
-    if kind == 2:
-        return np.full_like(V, w)
-    return np.zeros_like(V)
+        out = 2.0 * w * np.abs(V)
+    elif kind == 2:
+        out = np.full_like(V, w)
+    else:
+        out = np.zeros_like(V)
+    if offset:
+        out[:, 0] = 0.0      # the offset coordinate carries no penalty
+    return out
 
 
-def _trial(reg, V, g, alpha):
+def _trial(reg, V, g, alpha, offset=0):
     out = np.empty_like(V)
     for i in range(V.shape[0]):
-        out[i] = oracle.prox(reg[0], reg[1], float(alpha[i]), V[i] - alpha[i] * g[i])
+        out[i] = oracle.prox(reg[0], reg[1], float(alpha[i]), V[i] - alpha[i] * g[i], offset)
     return out
+
+
+def _offsets(P):
+    """Offset codes of the X and Y regularizers (Section 3.3)."""
+    return (1, 2) if getattr(P, "offset", False) else (0, 0)
 
 
 def band_rows(P, X, Y, ax, f_old, f_new, prec):
     """Decision band of every row of the X half-step at (X, Y) with step sizes ax."""
     X, Y = np.asarray(X, np.float64), np.asarray(Y, np.float64)
     g, _ = P.grad(X, Y)
-    S, _ = P.grad_abs(X, Y)
-    Xp = _trial(P.rx, X, g, ax)
+    ox = _offsets(P)[0]
+    Xp = _trial(P.rx, X, g, ax, ox)
     Sp, _ = P.grad_abs(Xp, Y)
-    eps = 2.0 * GRAD_REL[prec] * np.asarray(ax, np.float64)[:, None] * S
-    first = np.sum((Sp + _reg_slope(P.rx, Xp)) * eps, axis=1)
+    eps = grad_eps(P, "x", X, Y, ax, prec)
+    first = np.sum((Sp + _reg_slope(P.rx, Xp, ox)) * eps, axis=1)
     return 2.0 * first + SUM_REL * (np.abs(f_old) + np.abs(f_new))
 
 
@@ -86,11 +117,11 @@ def band_cols(P, X, Y, ay, h_old, h_new, prec):
     """Decision band of every column of the Y half-step at (X^t, Y)."""
     X, Y = np.asarray(X, np.float64), np.asarray(Y, np.float64)
     _, g = P.grad(X, Y)
-    _, S = P.grad_abs(X, Y)
-    Yp = _trial(P.ry, Y, g, ay)
+    oy = _offsets(P)[1]
+    Yp = _trial(P.ry, Y, g, ay, oy)
     _, Sp = P.grad_abs(X, Yp)
-    eps = 2.0 * GRAD_REL[prec] * np.asarray(ay, np.float64)[:, None] * S
-    first = np.sum((Sp + _reg_slope(P.ry, Yp)) * eps, axis=1)
+    eps = grad_eps(P, "y", X, Y, ay, prec)
+    first = np.sum((Sp + _reg_slope(P.ry, Yp, oy)) * eps, axis=1)
     return 2.0 * first + SUM_REL * (np.abs(h_old) + np.abs(h_new))
 
 
@@ -123,18 +154,16 @@ def _check_half(P, which, U0, V, alpha0, Ugpu, alpha_gpu, prec, step_up=1.05, st
         _, f_old, f_new, acc_o = P.half_step_x(Uo, V, ao, step_up, step_down)
         band = band_rows(P, X0, Y0, alpha0, f_old, f_new, prec)
         g, _ = P.grad(X0, Y0)
-        S, _ = P.grad_abs(X0, Y0)
-        reg = P.rx
+        reg, off = P.rx, _offsets(P)[0]
     else:
         X0, Y0 = V, U0
         _, f_old, f_new, acc_o = P.half_step_y(V, Uo, ao, step_up, step_down)
         band = band_cols(P, X0, Y0, alpha0, f_old, f_new, prec)
         _, g = P.grad(X0, Y0)
-        _, S = P.grad_abs(X0, Y0)
-        reg = P.ry
-    trial = _trial(reg, U0, g, alpha0)
+        reg, off = P.ry, _offsets(P)[1]
+    trial = _trial(reg, U0, g, alpha0, off)
     # the float32 rounding of x - alpha g and of the prox adds 2^-22 of |x| + |x+|
-    eps = 2.0 * GRAD_REL[prec] * alpha0[:, None] * S + 2.0 ** -22 * (np.abs(trial) + np.abs(U0)) + 1e-30
+    eps = grad_eps(P, which, X0, Y0, alpha0, prec) + 2.0 ** -22 * (np.abs(trial) + np.abs(U0)) + 1e-30
     Ugpu = np.asarray(Ugpu, np.float32)
     alpha_gpu = np.asarray(alpha_gpu, np.float64)
     ratio = alpha_gpu / np.maximum(alpha0, 1e-300)
@@ -168,14 +197,14 @@ def guided_half(P, which, U, V, alpha, gpu_acc, prec, step_up=1.05, step_down=0.
         _, f_old, f_new, acc_o = P.half_step_x(Uo, V, ao, step_up, step_down)
         band = band_rows(P, U, V, alpha, f_old, f_new, prec)
         g, _ = P.grad(U, V)
-        reg = P.rx
+        reg, off = P.rx, _offsets(P)[0]
     else:
         _, f_old, f_new, acc_o = P.half_step_y(V, Uo, ao, step_up, step_down)
         band = band_cols(P, V, U, alpha, f_old, f_new, prec)
         _, g = P.grad(V, U)
-        reg = P.ry
+        reg, off = P.ry, _offsets(P)[1]
     acc = np.where(clear_decisions(f_old, f_new, band), acc_o.astype(bool), np.asarray(gpu_acc, bool))
-    trial = _trial(reg, U, g, alpha)
+    trial = _trial(reg, U, g, alpha, off)
     return np.where(acc[:, None], trial, U), alpha * np.where(acc, step_up, step_down)
 
 

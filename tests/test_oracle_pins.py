@@ -434,3 +434,164 @@ def test_impute_table_keeps_observed_entries_and_decodes_the_rest():
     _, part = oracle.impute(X, Y, col_loss, losses, A=A, mask=mask)
     assert np.array_equal(part[mask], A[mask])
     assert np.array_equal(part[~mask], full[~mask])
+
+
+# ---- automatic loss scaling (Section 4.3) ------------------------------------------
+
+def _scaling_case(kinds, seed, m=300, n=12, missing=0.2, levels=5):
+    c = synth.small_mixed(m, n, 3, seed=seed, missing=missing, kinds=kinds, levels=levels)
+    return c, _problem(c)
+
+
+def test_scaling_of_quadratic_columns_is_mean_and_sample_variance():
+    """Section 2.6 / 4.3: for (u - a)^2, mu_j is the mean and sigma_j^2 the
+    sample variance of the observed entries (numpy)."""
+    c, P = _scaling_case((0,), 21)
+    mu, s2 = P.column_scaling()
+    for j in range(c.n):
+        a = c.A[c.mask[:, j].astype(bool), j].astype(np.float64)
+        assert mu[j] == pytest.approx(a.mean(), abs=1e-12 * (1 + abs(a).max()))
+        assert s2[j] == pytest.approx(a.var(ddof=1), rel=1e-10)
+
+
+def test_scaling_of_logistic_columns_is_the_log_odds():
+    """For log(1 + exp(-a u)) the minimizer is log(p / (1 - p)), p the share of
+    +1 labels (set the derivative sum to zero)."""
+    c, P = _scaling_case((2,), 22)
+    mu, s2 = P.column_scaling()
+    for j in range(c.n):
+        a = c.A[c.mask[:, j].astype(bool), j].astype(np.float64)
+        p = np.mean(a > 0)
+        want = np.log(p / (1 - p))
+        assert abs(want) < 2.0
+        assert mu[j] == pytest.approx(want, abs=1e-12)
+        f = np.sum(np.log1p(np.exp(-a * want)))
+        assert s2[j] == pytest.approx(f / (a.size - 1), rel=1e-10)
+
+
+def test_scaling_of_huber_columns_matches_a_scalar_minimizer():
+    c, P = _scaling_case((1,), 23)
+    mu, s2 = P.column_scaling()
+    for j in range(c.n):
+        a = c.A[c.mask[:, j].astype(bool), j].astype(np.float64)
+        f = lambda u: sum(oracle.loss(1, u, x, 0, 1.0) for x in a)  # noqa: E731
+        r = minimize_scalar(f, bounds=(a.min() - 1, a.max() + 1), method="bounded", options={"xatol": 1e-10})
+        assert mu[j] == pytest.approx(r.x, abs=1e-6)
+        assert s2[j] * (a.size - 1) == pytest.approx(r.fun, rel=1e-9)
+
+
+@pytest.mark.parametrize("kind", [3, 4])
+def test_scaling_of_piecewise_linear_columns_reaches_the_minimum(kind):
+    """Hinge and ordinal hinge: sum_i L(mu, a_i) is convex and piecewise linear
+    with kinks at integers (a' +- 1 for integer levels, +-1 for the Boolean
+    labels), so its minimum over the bracket is attained at an integer or a
+    bracket end: brute force over those candidates."""
+    c, P = _scaling_case((kind,), 24 + kind)
+    mu, s2 = P.column_scaling()
+    vals = P.column_loss_at(mu)
+    for j in range(c.n):
+        a = c.A[c.mask[:, j].astype(bool), j].astype(np.float64)
+        lo, hi = a.min() - 1, a.max() + 1
+        cand = np.concatenate([[lo, hi], np.arange(np.ceil(lo), np.floor(hi) + 1)])
+        best = min(sum(oracle.loss(kind, u, x, 5) for x in a) for u in cand)
+        assert vals[j] == pytest.approx(best, rel=1e-12, abs=1e-12)
+        assert s2[j] * (a.size - 1) == pytest.approx(best, rel=1e-12)
+
+
+def test_scaling_readings_for_degenerate_columns():
+    """An empty column: mu = 0, sigma^2 = 1; one entry: sigma^2 = 1; a constant
+    quadratic column: zero minimum, sigma^2 = 1."""
+    A = np.array([[1.0, 3.0, 2.0], [1.0, 0.0, 5.0], [1.0, 0.0, -1.0]])
+    mask = np.array([[1, 1, 0], [1, 0, 0], [1, 0, 0]], bool)
+    P = oracle.Problem.from_dense(A, mask, 1, np.zeros(3, np.uint8), [(0, 0, 0.0)], (0, 0.0), (0, 0.0))
+    mu, s2 = P.column_scaling()
+    assert mu[0] == pytest.approx(1.0) and s2[0] == 1.0
+    assert mu[1] == pytest.approx(3.0) and s2[1] == 1.0
+    assert mu[2] == 0.0 and s2[2] == 1.0
+
+
+def test_svd_initialization_of_a_full_quadratic_table_is_its_best_rank_k_fit():
+    """Section 7.5 on a fully observed quadratic table: At = (A - mu) / sigma,
+    so X Y^T = U_k S_k V_k^T diag(sigma) is the Eckart-Young approximation of
+    the standardized table, scaled back, plus the offset mu (numpy SVD of the
+    standardized table)."""
+    c = synth.plain_pca(m=60, n=15, k=4)
+    P = oracle.Problem.from_dense(c.A, None, 5, c.col_loss, c.losses, (1, 0.1), (1, 0.1), offset=True)
+    mu, s2 = P.column_scaling()
+    A = c.A.astype(np.float64)
+    np.testing.assert_allclose(mu, A.mean(0), atol=1e-12 * np.abs(A).max())
+    X, Y, s = P.init_svd(mu, s2, 5)
+    Z = (A - A.mean(0)) / A.std(0, ddof=1)
+    U, sv, Vt = np.linalg.svd(Z, full_matrices=False)
+    want = (U[:, :4] * sv[:4]) @ Vt[:4] * A.std(0, ddof=1) + A.mean(0)
+    np.testing.assert_allclose(X @ Y.T, want, atol=1e-9 * np.abs(want).max())
+    np.testing.assert_allclose(s, sv[:4], rtol=1e-12)
+    assert np.all(X[:, 0] == 1.0) and np.allclose(Y[:, 0], mu)
+
+
+def test_offset_regularizer_holds_the_constant_and_frees_the_offset():
+    """Section 3.3: r'(x) = r(x_2..) + indicator(x_1 = 1) and rt'(y) = rt(y_2..);
+    their proxes set x_1 = 1 and leave y_1 alone."""
+    x = np.array([1.0, 2.0, -3.0])
+    assert oracle.reg(1, 0.5, x, offset=1) == pytest.approx(0.5 * 13.0)
+    assert oracle.reg(1, 0.5, np.array([0.9, 2.0, -3.0]), offset=1) == np.inf
+    assert oracle.reg(1, 0.5, np.array([7.0, 2.0, -3.0]), offset=2) == pytest.approx(0.5 * 13.0)
+    np.testing.assert_allclose(oracle.prox(1, 0.5, 2.0, np.array([4.0, 2.0, -3.0]), offset=1), [1.0, 2.0 / 3.0, -1.0])
+    np.testing.assert_allclose(oracle.prox(2, 0.5, 2.0, np.array([4.0, 2.0, -3.0]), offset=2), [4.0, 1.0, -2.0])
+
+
+# ---- prox-prox update for quadratic losses (Sections 7.2, 7.3) ---------------------
+
+def _pp_case(rx=(0, 0.0), missing=0.3, seed=41):
+    c = synth.small_mixed(50, 30, 4, seed=seed, missing=missing, kinds=(0,), rx=rx, ry=rx)
+    return c, _problem(c)
+
+
+def test_proxprox_with_a_huge_step_is_exact_least_squares():
+    """alpha -> infinity, r = 0: prox_{alpha f}(x) -> argmin f, the row's least
+    squares solution over its observed entries (numpy lstsq): the exact
+    alternating-minimization update of Algorithm 1 (Section 7.1)."""
+    c, P = _pp_case()
+    X, Y = c.X0.astype(np.float64).copy(), c.Y0.astype(np.float64)
+    ax = np.full(c.m, 1e15)
+    P.half_step_x_pp(X, Y, ax)
+    for i in range(c.m):
+        obs = c.mask[i].astype(bool)
+        want = np.linalg.lstsq(Y[obs], c.A[i, obs].astype(np.float64), rcond=None)[0]
+        np.testing.assert_allclose(X[i], want, rtol=1e-8, atol=1e-9)
+
+
+def test_proxprox_fixed_point_under_the_quadratic_regularizer():
+    """Repeating the update with r = g ||x||^2 converges to its fixed point
+    x = prox_r(prox_f(x)), which solves (G (1 + 2 alpha g) + g I) x = b
+    (G, b the row's Gram matrix and A Y^T row; numpy solve) -- not the
+    minimizer (G + g I)^-1 b unless alpha -> 0."""
+    g_ = 0.3
+    c, P = _pp_case(rx=(1, g_))
+    X, Y = c.X0.astype(np.float64).copy(), c.Y0.astype(np.float64)
+    alpha = 0.05
+    ax = np.full(c.m, alpha)
+    P.half_step_x_pp(X, Y, ax, inner=400)
+    for i in range(0, c.m, 7):
+        obs = c.mask[i].astype(bool)
+        G = Y[obs].T @ Y[obs]
+        b = Y[obs].T @ c.A[i, obs].astype(np.float64)
+        want = np.linalg.solve(G * (1 + 2 * alpha * g_) + g_ * np.eye(c.k), b)
+        np.testing.assert_allclose(X[i], want, rtol=1e-9, atol=1e-11)
+
+
+def test_proxprox_agrees_with_the_gradient_step_to_second_order():
+    """prox_{alpha f}(x) = x - alpha grad f(x) + O(alpha^2): the gap between the
+    prox-prox and the proximal gradient trial points shrinks fourfold when
+    alpha halves (r = 0)."""
+    c, P = _pp_case()
+    X0, Y = c.X0.astype(np.float64), c.Y0.astype(np.float64)
+    g, _ = P.grad(X0, Y)
+    gaps = []
+    for alpha in (1e-3, 5e-4, 2.5e-4):
+        X = X0.copy()
+        ax = np.full(c.m, alpha)
+        _, fo, fn, acc = P.half_step_x_pp(X, Y, ax)
+        assert acc.all()
+        gaps.append(np.linalg.norm(X - (X0 - alpha * g)))
+    assert 3.6 < gaps[0] / gaps[1] < 4.4 and 3.6 < gaps[1] / gaps[2] < 4.4
