@@ -35,35 +35,45 @@ def rel_fro(a, b):
 # ---- decisions near a tie ------------------------------------------------------
 #
 # The GPU forms its step x+ = prox(x - alpha g) from a gradient g that carries
-# rounding error (bound: grad_eps below).  A gradient coordinate is a sum of terms G_ij y_jc, and its
-# rounding error is a fraction of the sum of their magnitudes,
-# S_c = sum_j |G_ij| |y_jc| (the oracle's grad_abs): about 2^-8 of it when
-# the contraction is one bfloat16 product per term (the BF16 form: both
-# operands rounded to 8 bits), and below 2^-16 for float32 accumulation of
-# up to ~10^4 terms (many standard deviations of sqrt(n) 2^-24).  The prox operators are
-# nonexpansive, so each coordinate of the GPU's trial point lies within
-# eps_c = 2 rel alpha S_c of the oracle's.  The trial objective then moves by
-# at most sum_c S+_c eps_c to first order (S+ is the same magnitude sum at the
-# trial point, plus the regularizer's slope); the band doubles that for the
-# second-order term and adds the float32 rounding of the objective sums
-# themselves (sqrt(n) 2^-24 relative for n <= 2e4 terms).  A decision whose
-# margin |f+ - f| lies inside the band may legitimately go either way; every
-# other decision must match the oracle's.
+# rounding error (bound: grad_eps below).  A gradient coordinate is a sum of
+# terms G_ij y_jc; its error is bounded by the three sources listed below, in
+# units of the sum of their magnitudes S_c = sum_j |G_ij| |y_jc| (the oracle's
+# grad_abs) and of their root sum of squares R_c (grad_rss).  The prox
+# operators are nonexpansive, so each coordinate of the GPU's trial point lies
+# within eps_c = 2 alpha (that bound) of the oracle's.  The trial objective
+# then moves by at most sum_c S+_c eps_c to first order (S+ is the same
+# magnitude sum at the trial point, plus the regularizer's slope); the band
+# doubles that for the second-order term and adds the float32 rounding of the
+# objective sums themselves (sqrt(n) 2^-24 relative for n <= 2e4 terms).  A
+# decision whose margin |f+ - f| lies inside the band may legitimately go
+# either way; every other decision must match the oracle's.
 
 GRAD_REL = {"fp32": 0.0, "bf16": 2.0 ** -8}
 SUM_REL = 1e-5
-# Two sources.  (1) The products: in BF16 each term's operands are rounded to
-# 8 bits (worst case 2^-8 of S_c above, all errors of one sign).  Rounding
-# errors of independent terms add in quadrature instead: rounded to nearest,
-# each operand's error is uniform within 2^-9 relative, so the sum's error
-# has a standard deviation of about 0.82 2^-9 of the root of the squared terms
-# R_c, and 2^-6 R_c is six of them; the smaller bound is taken.  FP32
-# products are exact to 2^-24, below (2).  (2) The float32 accumulation: the
+# Three sources.  (1) The derivative operand: the BF16 form rounds every
+# G_ij to bfloat16 (round to nearest even).  These errors are not independent:
+# a derivative that saturates (the logistic one near +-1)
+# piles up just below a power of two and always rounds the same way.  So
+# their sum E_c = sum_j (bf16(G_ij) - G_ij) v_jc is computed exactly from the
+# oracle's derivatives.  (2) The factor operand, also rounded to bfloat16:
+# worst case 2^-8 of S_c (all errors of one sign); factor values spread over
+# many units in the last place, so their rounding errors are independent and
+# uniform within half a unit, 2^-8 relative at most: the sum's standard
+# deviation is at most 2^-8 / sqrt(3) of the root of the squared terms R_c,
+# and 2^-6 R_c is about seven of them; the smaller bound is taken.  FP32
+# products are exact to 2^-24, below (3).  (3) The float32 accumulation: the
 # kernels add runs of at most about 2^10 terms in sequence (a workgroup's rows
 # or a wavefront's chunk) before fixed-order reductions of the partials, so
 # the accumulated error stays below 2^10 2^-24 = 2^-14 of S_c.
 RSS_REL = {"fp32": None, "bf16": 2.0 ** -6}
 ACC_REL = 2.0 ** -14
+
+
+def bf16_round(a):
+    """float64 -> float32 -> bfloat16 (round to nearest even) -> float64."""
+    b = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    r = ((b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
 
 
 def grad_eps(P, which, X, Y, alpha, prec):
@@ -73,6 +83,10 @@ def grad_eps(P, which, X, Y, alpha, prec):
     if RSS_REL[prec] is not None:
         R = P.grad_rss(X, Y)[0 if which == "x" else 1]
         bound = np.minimum(bound, RSS_REL[prec] * R)
+        G = P.grad_matrix(X, Y)
+        dG = bf16_round(G) - G
+        X64, Y64 = np.asarray(X, np.float64), np.asarray(Y, np.float64)
+        bound = bound + np.abs(dG @ Y64 if which == "x" else dG.T @ X64)
     return 2.0 * np.asarray(alpha, np.float64)[:, None] * (bound + ACC_REL * S)
 
 
