@@ -13,7 +13,9 @@ column half-step (Section 7.2 defines the Y update as the X update with the
 roles of X and Y swapped and every matrix argument transposed).
 
 Loss kinds: 0 quadratic, 1 Huber(delta = param), 2 logistic, 3 hinge,
-4 ordinal hinge over 1..levels.  Regularizer kinds: 0 zero, 1 quadratic
+4 ordinal hinge over 1..levels; the multi-dimensional losses of Section 6
+(``MDProblem``): 5 categorical one-vs-all over labels 1..levels, 6
+multi-dimensional ordinal over levels 1..levels.  Regularizer kinds: 0 zero, 1 quadratic
 w*||x||^2, 2 l1 w*||x||_1, 3 nonnegative indicator.
 """
 import ctypes
@@ -89,6 +91,26 @@ def lib():
         L.oracle_decode.argtypes = [P, D]
         L.oracle_decode_matrix.restype = None
         L.oracle_decode_matrix.argtypes = [P, P, P, I64, I64, P]
+        L.oracle_md_dim.restype = I32
+        L.oracle_md_dim.argtypes = [I32, I32]
+        L.oracle_md_loss.restype = D
+        L.oracle_md_loss.argtypes = [I32, I32, D, P, D]
+        L.oracle_md_dloss.restype = None
+        L.oracle_md_dloss.argtypes = [I32, I32, D, P, D, P]
+        L.oracle_md_decode.restype = D
+        L.oracle_md_decode.argtypes = [I32, I32, D, P]
+        L.oracle_md_objective.restype = D
+        L.oracle_md_objective.argtypes = [P, I64, P, P, I32, D, I32, D, I32]
+        L.oracle_md_grad.restype = None
+        L.oracle_md_grad.argtypes = [P, I64, P, P, P, P]
+        L.oracle_md_init_alpha.restype = None
+        L.oracle_md_init_alpha.argtypes = [P, P, I64, D, P, P]
+        L.oracle_md_half_step_x.restype = I64
+        L.oracle_md_half_step_x.argtypes = [P, P, P, P, I32, D, I32, D, D, P, P, P]
+        L.oracle_md_half_step_y.restype = I64
+        L.oracle_md_half_step_y.argtypes = [P, P, P, P, I32, D, I32, D, D, P, P, P, P]
+        L.oracle_md_impute.restype = None
+        L.oracle_md_impute.argtypes = [P, I64, P, P, P]
         _lib = L
     return _lib
 
@@ -439,3 +461,133 @@ class Problem:
             hist.append(self.objective(X, Y))
             rej.append((d["rows_rejected"], d["cols_rejected"]))
         return X, Y, ax, ay, np.array(hist), rej
+
+
+# ---- multi-dimensional losses (Section 6) -----------------------------------
+CATEGORICAL, MORDINAL = 5, 6
+
+
+def md_dim(kind, levels):
+    """Embedding dimension d_j of a feature with this loss."""
+    return lib().oracle_md_dim(int(kind), int(levels))
+
+
+def md_loss(kind, u, a, levels=0, param=1.0):
+    u = _f64(np.atleast_1d(u))
+    return lib().oracle_md_loss(int(kind), int(levels), float(param), _ptr(u), float(a))
+
+
+def md_dloss(kind, u, a, levels=0, param=1.0):
+    u = _f64(np.atleast_1d(u))
+    g = np.empty(max(1, md_dim(kind, levels)))
+    lib().oracle_md_dloss(int(kind), int(levels), float(param), _ptr(u), float(a), _ptr(g))
+    return g
+
+
+def md_decode(kind, u, levels=0, param=1.0):
+    u = _f64(np.atleast_1d(u))
+    return lib().oracle_md_decode(int(kind), int(levels), float(param), _ptr(u))
+
+
+class _MD(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("k", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("other", ctypes.c_void_p), ("val", ctypes.c_void_p), ("fkind", ctypes.c_void_p),
+                ("flev", ctypes.c_void_p), ("fpar", ctypes.c_void_p), ("fw", ctypes.c_void_p),
+                ("fcol", ctypes.c_void_p)]
+
+
+class MDProblem:
+    """A table of features under the losses of eq. mpca: dense A (m x nf)
+    with a mask (1 = observed), one loss (kind, levels, param) per feature,
+    the regularizers r on the rows of X and rt on the columns of each Y_j.
+    Y is stored d x k, d = sum_j d_j: feature j owns rows fcol[j] .. fcol[j+1]-1
+    (the columns of the paper's block Y_j).  ``weight`` scales each feature's
+    loss; ``offset`` is the offset coordinate 0 of Section 3.3."""
+
+    def __init__(self, A, mask, k, feat_losses, rx, ry, offset=False, weight=None):
+        A = np.asarray(A)
+        self.m, self.nf = A.shape
+        self.k = int(k)
+        self.rx, self.ry = (int(rx[0]), float(rx[1])), (int(ry[0]), float(ry[1]))
+        self.offset = bool(offset)
+        self.fkind = np.array([int(l[0]) for l in feat_losses], np.int32)
+        self.flev = np.array([int(l[1]) for l in feat_losses], np.int32)
+        self.fpar = np.array([float(l[2]) for l in feat_losses], np.float64)
+        self.fw = None if weight is None else _f64(weight)
+        dims = np.array([md_dim(a, b) for a, b in zip(self.fkind, self.flev)], np.int64)
+        self.dims = dims
+        self.fcol = np.concatenate([[0], np.cumsum(dims)]).astype(np.int64)
+        self.d = int(self.fcol[-1])
+        obs = np.asarray(mask) != 0 if mask is not None else np.ones(A.shape, bool)
+        ri, rj = np.nonzero(obs)                       # row-major: sorted by row
+        self._keep = []
+        self.row = self._view(self.m, ri, rj, A[ri, rj])
+        order = np.lexsort((ri, rj))                   # sorted by feature, then row
+        self.feat = self._view(self.nf, rj[order], ri[order], A[ri[order], rj[order]])
+        self.nnz = int(ri.size)
+
+    def _view(self, rows, key, other, val):
+        ptr = np.zeros(rows + 1, np.int64)
+        np.add.at(ptr, key + 1, 1)
+        ptr = np.cumsum(ptr).astype(np.int64)
+        oth = np.ascontiguousarray(other, np.int32)
+        v = _f64(val)
+        self._keep += [ptr, oth, v, self.fkind, self.flev, self.fpar, self.fcol]
+        if self.fw is not None:
+            self._keep.append(self.fw)
+        return _MD(rows, self.k, _ptr(ptr).value, _ptr(oth).value, _ptr(v).value, _ptr(self.fkind).value,
+                   _ptr(self.flev).value, _ptr(self.fpar).value,
+                   None if self.fw is None else _ptr(self.fw).value, _ptr(self.fcol).value)
+
+    def objective(self, X, Y):
+        X, Y = _f64(X), _f64(Y)
+        return lib().oracle_md_objective(ctypes.byref(self.row), self.nf, _ptr(X), _ptr(Y), self.rx[0], self.rx[1],
+                                         self.ry[0], self.ry[1], 1 if self.offset else 0)
+
+    def grad(self, X, Y):
+        """Loss-part gradients (dX m x k, dY d x k)."""
+        X, Y = _f64(X), _f64(Y)
+        dX, dY = np.empty_like(X), np.empty_like(Y)
+        lib().oracle_md_grad(ctypes.byref(self.row), self.nf, _ptr(X), _ptr(Y), _ptr(dX), _ptr(dY))
+        return dX, dY
+
+    def init_alpha(self, s=1.0):
+        """(per row, per feature) initial step sizes."""
+        ax, af = np.empty(self.m), np.empty(self.nf)
+        lib().oracle_md_init_alpha(ctypes.byref(self.row), ctypes.byref(self.feat), self.nf, float(s), _ptr(ax),
+                                   _ptr(af))
+        return ax, af
+
+    def half_step_x(self, X, Y, ax, step_up=1.05, step_down=0.7):
+        fo, fn, acc = np.empty(self.m), np.empty(self.m), np.empty(self.m, dtype=np.uint8)
+        rej = lib().oracle_md_half_step_x(ctypes.byref(self.row), _ptr(X), _ptr(Y), _ptr(ax), self.rx[0], self.rx[1],
+                                          1 if self.offset else 0, float(step_up), float(step_down), _ptr(fo),
+                                          _ptr(fn), _ptr(acc))
+        return rej, fo, fn, acc
+
+    def half_step_y(self, X, Y, af, step_up=1.05, step_down=0.7):
+        """Block step of every feature (af: one step size per feature)."""
+        fo, fn, acc = np.empty(self.nf), np.empty(self.nf), np.empty(self.nf, dtype=np.uint8)
+        scr = np.empty(2 * 1024 * self.k)
+        rej = lib().oracle_md_half_step_y(ctypes.byref(self.feat), _ptr(Y), _ptr(X), _ptr(af), self.ry[0],
+                                          self.ry[1], 2 if self.offset else 0, float(step_up), float(step_down),
+                                          _ptr(fo), _ptr(fn), _ptr(acc), _ptr(scr))
+        return rej, fo, fn, acc
+
+    def fit(self, X0, Y0, sweeps, alpha_scale=1.0, step_up=1.05, step_down=0.7):
+        """Algorithm 2; returns X, Y, ax, af, history."""
+        X, Y = _f64(X0).copy(), _f64(Y0).copy()
+        ax, af = self.init_alpha(alpha_scale)
+        hist = []
+        for _ in range(int(sweeps)):
+            self.half_step_x(X, Y, ax, step_up, step_down)
+            self.half_step_y(X, Y, af, step_up, step_down)
+            hist.append(self.objective(X, Y))
+        return X, Y, ax, af, np.array(hist)
+
+    def impute(self, X, Y):
+        """Section 5.3 for every entry (m x nf): argmin over the feature's values."""
+        X, Y = _f64(X), _f64(Y)
+        out = np.empty((self.m, self.nf))
+        lib().oracle_md_impute(ctypes.byref(self.row), self.nf, _ptr(X), _ptr(Y), _ptr(out))
+        return out

@@ -494,3 +494,282 @@ void oracle_decode_matrix(const oracle_loss_t *losses, const uint8_t *col_code, 
         for (int64_t j = 0; j < n; ++j)
             out[i * n + j] = oracle_decode(&losses[col_code[j]], Z[i * n + j]);
 }
+
+/* ---- multi-dimensional losses (Section 6) ------------------------------------
+ * Feature j of the table has embedding dimension d_j and owns rows
+ * fcol[j] .. fcol[j+1]-1 of Y (stored d x k: those rows are the columns of
+ * the paper's block Y_j), so u = x_i Y_j has d_j entries (eq. mpca).
+ *   categorical, labels 1..d (one-vs-all, Section 6.1), d_j = d:
+ *       L(u, a) = (1 - u_a)_+ + sum_{a' != a} (1 + u_a')_+
+ *   multi-dimensional ordinal, levels 1..d (eq. ord-mpca), d_j = d - 1:
+ *       L(u, a) = sum_{l=1}^{d-1} (1 - s_l(a) u_l)_+,  s_l(a) = +1 if a > l, else -1
+ *   (the paper prints the factor as the indicator of a > l; it is read as
+ *   this sign, the form under which each term is the SVM that separates the
+ *   levels up to l from those above, which is how the paper describes it)
+ * Every other kind is the scalar loss of u_0 (d_j = 1).  Feature j's loss is
+ * scaled by fw[j] (NULL = 1).  At a kink the derivative takes the
+ * strict-inequality branch, as everywhere in this file.  The regularizers
+ * r on the rows of X and rt on the columns of every Y_j are the ones of
+ * eq. gpca; r~_j(Y_j) is rt summed over the block's columns. */
+enum { OR_CATEGORICAL = 5, OR_MORDINAL = 6 };
+#define OR_MD_MAXD 1024
+
+typedef struct {
+    int64_t rows;                 /* rows of the view: rows of A (row view) or features (feature view) */
+    int32_t k;
+    const int64_t *row_ptr;       /* rows + 1 */
+    const int32_t *other;         /* per entry: its feature (row view) or its row of A (feature view) */
+    const double *val;            /* per entry: A_ij */
+    const int32_t *fkind, *flev;  /* per feature */
+    const double *fpar, *fw;      /* per feature (fw may be NULL) */
+    const int64_t *fcol;          /* features + 1 */
+} oracle_md_t;
+
+int32_t oracle_md_dim(int32_t kind, int32_t lev)
+{
+    return kind == OR_CATEGORICAL ? lev : (kind == OR_MORDINAL ? lev - 1 : 1);
+}
+
+double oracle_md_loss(int32_t kind, int32_t lev, double par, const double *u, double a)
+{
+    if (kind == OR_CATEGORICAL) {
+        double s = 0.0;
+        for (int l = 1; l <= lev; ++l) s += (l == (int)a) ? pos(1.0 - u[l - 1]) : pos(1.0 + u[l - 1]);
+        return s;
+    }
+    if (kind == OR_MORDINAL) {
+        double s = 0.0;
+        for (int l = 1; l <= lev - 1; ++l) s += pos(1.0 - (a > (double)l ? 1.0 : -1.0) * u[l - 1]);
+        return s;
+    }
+    oracle_loss_t L = {kind, lev, par};
+    return oracle_loss(&L, u[0], a);
+}
+
+void oracle_md_dloss(int32_t kind, int32_t lev, double par, const double *u, double a, double *g)
+{
+    if (kind == OR_CATEGORICAL) {
+        for (int l = 1; l <= lev; ++l)
+            g[l - 1] = (l == (int)a) ? (1.0 - u[l - 1] > 0.0 ? -1.0 : 0.0) : (1.0 + u[l - 1] > 0.0 ? 1.0 : 0.0);
+        return;
+    }
+    if (kind == OR_MORDINAL) {
+        for (int l = 1; l <= lev - 1; ++l) {
+            const double sg = a > (double)l ? 1.0 : -1.0;
+            g[l - 1] = 1.0 - sg * u[l - 1] > 0.0 ? -sg : 0.0;
+        }
+        return;
+    }
+    oracle_loss_t L = {kind, lev, par};
+    g[0] = oracle_dloss(&L, u[0], a);
+}
+
+/* Section 5.3 for a block: argmin over the feature's values of L(u, a),
+ * by enumeration of the labels (the first of equal minima). */
+double oracle_md_decode(int32_t kind, int32_t lev, double par, const double *u)
+{
+    if (kind == OR_CATEGORICAL || kind == OR_MORDINAL) {
+        double best = 1.0, fbest = oracle_md_loss(kind, lev, par, u, 1.0);
+        for (int a = 2; a <= lev; ++a) {
+            const double f = oracle_md_loss(kind, lev, par, u, (double)a);
+            if (f < fbest) { fbest = f; best = a; }
+        }
+        return best;
+    }
+    oracle_loss_t L = {kind, lev, par};
+    return oracle_decode(&L, u[0]);
+}
+
+static int md_d(const oracle_md_t *P, int64_t j) { return oracle_md_dim(P->fkind[j], P->flev[j]); }
+static double md_w(const oracle_md_t *P, int64_t j) { return P->fw ? P->fw[j] : 1.0; }
+
+/* loss of one entry: feature j, value a, row x, block B (d_j rows of k) */
+static double md_entry_loss(const oracle_md_t *P, int64_t j, const double *x, const double *B, double a, double *u)
+{
+    const int d = md_d(P, j);
+    for (int l = 0; l < d; ++l) u[l] = dot(x, B + (int64_t)l * P->k, P->k);
+    return md_w(P, j) * oracle_md_loss(P->fkind[j], P->flev[j], P->fpar[j], u, a);
+}
+
+/* its derivatives with respect to u (scaled by the weight) */
+static void md_entry_dloss(const oracle_md_t *P, int64_t j, const double *x, const double *B, double a, double *u,
+                           double *g)
+{
+    const int d = md_d(P, j);
+    for (int l = 0; l < d; ++l) u[l] = dot(x, B + (int64_t)l * P->k, P->k);
+    oracle_md_dloss(P->fkind[j], P->flev[j], P->fpar[j], u, a, g);
+    for (int l = 0; l < d; ++l) g[l] *= md_w(P, j);
+}
+
+/* losses of row i (row view) at x against Y */
+static double md_row_loss(const oracle_md_t *R, int64_t i, const double *x, const double *Y, double *u)
+{
+    double f = 0.0;
+    for (int64_t e = R->row_ptr[i]; e < R->row_ptr[i + 1]; ++e) {
+        const int32_t j = R->other[e];
+        f += md_entry_loss(R, j, x, Y + R->fcol[j] * R->k, R->val[e], u);
+    }
+    return f;
+}
+
+/* losses of feature j (feature view) with block B against X */
+static double md_feat_loss(const oracle_md_t *F, int64_t j, const double *B, const double *X, double *u)
+{
+    double f = 0.0;
+    for (int64_t e = F->row_ptr[j]; e < F->row_ptr[j + 1]; ++e)
+        f += md_entry_loss(F, j, X + (int64_t)F->other[e] * F->k, B, F->val[e], u);
+    return f;
+}
+
+static double md_block_reg(int32_t kind, double w, int32_t offset, const double *B, int d, int32_t k)
+{
+    double r = 0.0;
+    for (int l = 0; l < d; ++l) r += oracle_reg(kind, w, offset, B + (int64_t)l * k, k);
+    return r;
+}
+
+/* the objective of eq. mpca, from the row view; nf features */
+double oracle_md_objective(const oracle_md_t *R, int64_t nf, const double *X, const double *Y, int32_t rx_kind,
+                           double rx_w, int32_t ry_kind, double ry_w, int32_t offset)
+{
+    double u[OR_MD_MAXD];
+    double f = 0.0;
+    for (int64_t i = 0; i < R->rows; ++i)
+        f += md_row_loss(R, i, X + i * R->k, Y, u) + oracle_reg(rx_kind, rx_w, offset ? 1 : 0, X + i * R->k, R->k);
+    f += oracle_reg_sum(ry_kind, ry_w, offset ? 2 : 0, Y, R->fcol[nf], R->k);
+    return f;
+}
+
+/* loss-part gradients from the row view: dX_i = sum_j (dL/du) Y_j^T and
+ * the rows of dY of block j, sum_i x_i^T (dL/du) */
+void oracle_md_grad(const oracle_md_t *R, int64_t nf, const double *X, const double *Y, double *dX, double *dY)
+{
+    const int k = R->k;
+    double u[OR_MD_MAXD], g[OR_MD_MAXD];
+    for (int64_t t = 0; t < R->rows * k; ++t) dX[t] = 0.0;
+    for (int64_t t = 0; t < R->fcol[nf] * k; ++t) dY[t] = 0.0;
+    for (int64_t i = 0; i < R->rows; ++i)
+        for (int64_t e = R->row_ptr[i]; e < R->row_ptr[i + 1]; ++e) {
+            const int32_t j = R->other[e];
+            md_entry_dloss(R, j, X + i * k, Y + R->fcol[j] * k, R->val[e], u, g);
+            for (int l = 0; l < md_d(R, j); ++l) {
+                const double *y = Y + (R->fcol[j] + l) * k;
+                double *dy = dY + (R->fcol[j] + l) * k;
+                for (int c = 0; c < k; ++c) {
+                    dX[i * k + c] += g[l] * y[c];
+                    dy[c] += g[l] * X[i * k + c];
+                }
+            }
+        }
+}
+
+/* Initial step sizes of Algorithm 2: s over the entries of each row's loss
+ * terms (a feature of dimension d_j counts d_j) and s / n_j per feature. */
+void oracle_md_init_alpha(const oracle_md_t *R, const oracle_md_t *F, int64_t nf, double s, double *ax, double *af)
+{
+    for (int64_t i = 0; i < R->rows; ++i) {
+        int64_t c = 0;
+        for (int64_t e = R->row_ptr[i]; e < R->row_ptr[i + 1]; ++e) c += md_d(R, R->other[e]);
+        ax[i] = s / (double)(c > 0 ? c : 1);
+    }
+    for (int64_t j = 0; j < nf; ++j) {
+        const int64_t c = F->row_ptr[j + 1] - F->row_ptr[j];
+        af[j] = s / (double)(c > 0 ? c : 1);
+    }
+}
+
+/* X half-step of Algorithm 2 (proximal gradient step and step rule of
+ * Section 7.2) on the row view, in place. */
+int64_t oracle_md_half_step_x(const oracle_md_t *R, double *X, const double *Y, double *alpha, int32_t reg_kind,
+                              double reg_w, int32_t offset, double step_up, double step_down, double *f_old,
+                              double *f_new, uint8_t *accepted)
+{
+    const int k = R->k;
+    double u[OR_MD_MAXD], g[OR_MD_MAXD], gx[64], xp[64];
+    int64_t rejected = 0;
+    for (int64_t i = 0; i < R->rows; ++i) {
+        double *x = X + i * k;
+        const double f = md_row_loss(R, i, x, Y, u) + oracle_reg(reg_kind, reg_w, offset, x, k);
+        for (int c = 0; c < k; ++c) gx[c] = 0.0;
+        for (int64_t e = R->row_ptr[i]; e < R->row_ptr[i + 1]; ++e) {
+            const int32_t j = R->other[e];
+            md_entry_dloss(R, j, x, Y + R->fcol[j] * k, R->val[e], u, g);
+            for (int l = 0; l < md_d(R, j); ++l)
+                for (int c = 0; c < k; ++c) gx[c] += g[l] * Y[(R->fcol[j] + l) * k + c];
+        }
+        for (int c = 0; c < k; ++c) xp[c] = x[c] - alpha[i] * gx[c];
+        oracle_prox(reg_kind, reg_w, offset, alpha[i], xp, k);
+        double fp = md_row_loss(R, i, xp, Y, u) + oracle_reg(reg_kind, reg_w, offset, xp, k);
+        for (int c = 0; c < k; ++c)
+            if (!isfinite(xp[c])) fp = INFINITY;
+        const int acc = fp <= f;
+        if (acc) {
+            for (int c = 0; c < k; ++c) x[c] = xp[c];
+            alpha[i] *= step_up;
+        } else {
+            alpha[i] *= step_down;
+            ++rejected;
+        }
+        if (f_old) f_old[i] = f;
+        if (f_new) f_new[i] = fp;
+        if (accepted) accepted[i] = (uint8_t)acc;
+    }
+    return rejected;
+}
+
+/* Y half-step on the feature view: the block Y_j of feature j takes one
+ * proximal gradient step with the feature's one step size and is kept or
+ * rejected whole (the column update of Algorithm 2, with Y_j in the place of
+ * y_j).  scratch: 2 * OR_MD_MAXD * k doubles. */
+int64_t oracle_md_half_step_y(const oracle_md_t *F, double *Y, const double *X, double *alpha, int32_t reg_kind,
+                              double reg_w, int32_t offset, double step_up, double step_down, double *f_old,
+                              double *f_new, uint8_t *accepted, double *scratch)
+{
+    const int k = F->k;
+    double u[OR_MD_MAXD], g[OR_MD_MAXD];
+    double *gb = scratch, *bp = scratch + OR_MD_MAXD * k;
+    int64_t rejected = 0;
+    for (int64_t j = 0; j < F->rows; ++j) {
+        const int d = md_d(F, j);
+        double *B = Y + F->fcol[j] * k;
+        const double f = md_feat_loss(F, j, B, X, u) + md_block_reg(reg_kind, reg_w, offset, B, d, k);
+        for (int t = 0; t < d * k; ++t) gb[t] = 0.0;
+        for (int64_t e = F->row_ptr[j]; e < F->row_ptr[j + 1]; ++e) {
+            const double *x = X + (int64_t)F->other[e] * k;
+            md_entry_dloss(F, j, x, B, F->val[e], u, g);
+            for (int l = 0; l < d; ++l)
+                for (int c = 0; c < k; ++c) gb[l * k + c] += g[l] * x[c];
+        }
+        for (int l = 0; l < d; ++l) {
+            for (int c = 0; c < k; ++c) bp[l * k + c] = B[l * k + c] - alpha[j] * gb[l * k + c];
+            oracle_prox(reg_kind, reg_w, offset, alpha[j], bp + l * k, k);
+        }
+        double fp = md_feat_loss(F, j, bp, X, u) + md_block_reg(reg_kind, reg_w, offset, bp, d, k);
+        for (int t = 0; t < d * k; ++t)
+            if (!isfinite(bp[t])) fp = INFINITY;
+        const int acc = fp <= f;
+        if (acc) {
+            for (int t = 0; t < d * k; ++t) B[t] = bp[t];
+            alpha[j] *= step_up;
+        } else {
+            alpha[j] *= step_down;
+            ++rejected;
+        }
+        if (f_old) f_old[j] = f;
+        if (f_new) f_new[j] = fp;
+        if (accepted) accepted[j] = (uint8_t)acc;
+    }
+    return rejected;
+}
+
+/* Imputation (Section 5.3) of every entry: out is rows x nf */
+void oracle_md_impute(const oracle_md_t *R, int64_t nf, const double *X, const double *Y, double *out)
+{
+    const int k = R->k;
+    double u[OR_MD_MAXD];
+    for (int64_t i = 0; i < R->rows; ++i)
+        for (int64_t j = 0; j < nf; ++j) {
+            for (int l = 0; l < md_d(R, j); ++l) u[l] = dot(X + i * k, Y + (R->fcol[j] + l) * k, k);
+            out[i * nf + j] = oracle_md_decode(R->fkind[j], R->flev[j], R->fpar[j], u);
+        }
+}
