@@ -56,10 +56,22 @@ extern "C" {
  *  HINGE      max(0, 1 - a u),     a in {-1, +1}      Section 5.2 ("Boolean PCA")
  *  ORDINAL    sum_{a'<a} (1 - u + a')_+ +            eq. ord-pca, a in {1..levels}
  *             sum_{a'>a} (1 + u - a')_+
+ * Multi-dimensional losses (Section 6, eq. mpca): the column is a feature of
+ * embedding dimension d_j, modelled by the block of d_j rows of Y (the
+ * columns of the paper's Y_j) and u = x_i Y_j:
+ *  CATEGORICAL  (1 - u_a)_+ + sum_{a' != a} (1 + u_a')_+    Section 6.1 (one-vs-all),
+ *               labels a in {1..levels}, d_j = levels
+ *  MORDINAL     sum_{l=1}^{levels-1} (1 - s_l u_l)_+,       eq. ord-mpca, levels a in
+ *               s_l = +1 if a > l, else -1                  {1..levels}, d_j = levels - 1
+ * (eq. ord-mpca prints the factor as the indicator of a > l; it is taken as
+ * this sign, so that each term is the SVM separating the levels up to l from
+ * those above, as the paper describes the model.)  A value that is no label
+ * counts as matching none (CATEGORICAL: every term (1 + u_a')_+).
  * The derivative used at a kink is the strict-inequality branch (the kink
  * contributes 0); Section 7.2 allows any subgradient. */
 enum { GLRM_LOSS_QUADRATIC = 0, GLRM_LOSS_HUBER = 1, GLRM_LOSS_LOGISTIC = 2,
-       GLRM_LOSS_HINGE = 3, GLRM_LOSS_ORDINAL = 4 };
+       GLRM_LOSS_HINGE = 3, GLRM_LOSS_ORDINAL = 4, GLRM_LOSS_CATEGORICAL = 5,
+       GLRM_LOSS_MORDINAL = 6 };
 
 /* ---- regularizer kinds (Section 3) and their proxes (Section 7.2) -------------
  *  ZERO       0                                  prox: v
@@ -84,10 +96,12 @@ enum { GLRM_FP32 = 0, GLRM_BF16 = 1, GLRM_FP64 = 2, GLRM_BF16_PLAIN = 3 };
 
 #define GLRM_MAX_LOSSES 16
 #define GLRM_MAX_K 64
+#define GLRM_MAX_LEVELS 1024   /* labels / levels of a multi-dimensional loss */
 
 typedef struct {
     int32_t kind;    /* GLRM_LOSS_* */
-    int32_t levels;  /* ORDINAL: number of levels d >= 2, data in 1..d; else ignored */
+    int32_t levels;  /* ORDINAL: number of levels d >= 2, data in 1..d; CATEGORICAL,
+                        MORDINAL: 2..GLRM_MAX_LEVELS labels / levels; else ignored */
     float   param;   /* HUBER: threshold > 0; else ignored */
 } glrm_loss;
 
@@ -132,6 +146,26 @@ typedef struct {
      * scaled losses of Section 4.3 (glrm_column_scaling). */
     const float *col_weight;
 } glrm_data;
+
+/* Multi-dimensional losses (Section 6).  When some column's loss is
+ * CATEGORICAL or MORDINAL, Y has d = glrm_embed_dim(d) rows instead of n:
+ * column j of A owns the next d_j rows (d_j = 1 for the scalar losses, in
+ * column order), and every entry point that takes Y, dY or alpha_y takes
+ * d rows or entries.  Both losses are sums of hinge losses over their d_j
+ * embedded columns (the separability Section 6.1 notes for one-vs-all), so
+ * the passes run on the embedded table of +-1 values; glrm_fit decides each
+ * column's block as a whole (one step-size rule per block Y_j: the block's
+ * trial objective against its current one), and its step sizes move
+ * together (keep them equal within a block when resuming; init_alpha
+ * does).  The row of X counts the d_j embedded entries of each observed
+ * value in n_i; a block's columns count n_j.  Built for the dense layout;
+ * the COO layout, glrm_column_scaling and glrm_init_svd return
+ * GLRM_EUNSUPPORTED for such problems, and glrm_fit's prox-prox update does
+ * (its losses are quadratic). */
+
+/* d = sum_j d_j (n when every loss is scalar); -1 for an invalid problem or a
+ * multi-dimensional loss outside the dense layout (glrm_last_error() says why). */
+int64_t glrm_embed_dim(const glrm_data *d);
 
 /* Flags for the compute entry points. */
 #define GLRM_WS_PREPARED 1u   /* `ws` already holds what glrm_prepare() builds for this
@@ -342,7 +376,11 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
  * x_i . y_j is a float32 fused multiply-add chain over l = 0..k-1, so an entry
  * within rounding of a tie may decode to either neighbour.  X and Y must be
  * finite.  Ahat is m x n row-major with leading dimension ldh >= n (device);
- * all m x n entries are written, the padding beyond n is not.  With
+ * all m x n entries are written, the padding beyond n is not.  A column
+ * under a multi-dimensional loss decodes its block u = x_i Y_j (float32
+ * fused multiply-add chains): CATEGORICAL the label of the largest u_l (the
+ * argmin of the one-vs-all loss; the first of equal ones), MORDINAL the level
+ * of least loss (the lowest of equal ones); Ahat stays m x n.  With
  * GLRM_IMPUTE_MISSING the observed entries receive A_ij instead (dense: mask
  * != 0, or every entry when mask is NULL; COO: the nnz listed entries).
  * Reads the per-column loss codes from `ws` (glrm_workspace_size() bytes):

@@ -17,7 +17,8 @@ __all__ = [
     "glrm_fit", "glrm_last_error", "library_path", "FP32", "BF16", "FP64", "BF16_PLAIN", "DENSE", "COO_ROWSORTED",
     "WS_PREPARED", "TIME_KERNELS", "glrm_impute", "IMPUTE_ALL", "IMPUTE_MISSING", "glrm_grad_noalloc",
     "NOALLOC_MAX_BYTES", "glrm_certificate", "glrm_linalg_workspace_size", "glrm_column_scaling",
-    "glrm_init_svd", "fit_standardized", "UPDATE_PROXGRAD", "UPDATE_PROXPROX",
+    "glrm_init_svd", "fit_standardized", "UPDATE_PROXGRAD", "UPDATE_PROXPROX", "glrm_embed_dim",
+    "LOSS_CATEGORICAL", "LOSS_MORDINAL",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,6 +29,7 @@ DENSE, COO_ROWSORTED = 0, 1
 WS_PREPARED = 1
 TIME_KERNELS = 2
 IMPUTE_ALL, IMPUTE_MISSING = 0, 1
+LOSS_QUADRATIC, LOSS_HUBER, LOSS_LOGISTIC, LOSS_HINGE, LOSS_ORDINAL, LOSS_CATEGORICAL, LOSS_MORDINAL = range(7)
 UPDATE_PROXGRAD, UPDATE_PROXPROX = 0, 1
 NOALLOC_MAX_BYTES = 64 << 20
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp64": FP64, "bf16_plain": BF16_PLAIN}
@@ -91,6 +93,8 @@ def _L():
         P, D = ctypes.c_void_p, ctypes.POINTER(_Data)
         L.glrm_workspace_size.restype = ctypes.c_size_t
         L.glrm_workspace_size.argtypes = [D]
+        L.glrm_embed_dim.restype = ctypes.c_int64
+        L.glrm_embed_dim.argtypes = [D]
         L.glrm_prepare.restype = ctypes.c_int
         L.glrm_prepare.argtypes = [D, P, ctypes.c_size_t, P]
         L.glrm_objective.restype = ctypes.c_int
@@ -209,6 +213,9 @@ class Data:
         self.s = s
         self._ws = None
         self.device = A.device
+        # rows of Y: n, or the embedded width with multi-dimensional losses
+        d = int(_L().glrm_embed_dim(ctypes.byref(s)))
+        self.d = d if d > 0 else self.n
 
     @classmethod
     def from_case(cls, case, device="cuda"):
@@ -266,6 +273,14 @@ def glrm_workspace_size(data):
     return size
 
 
+def glrm_embed_dim(data):
+    """Rows of Y for this problem: n, or sum_j d_j with multi-dimensional losses."""
+    d = int(_L().glrm_embed_dim(ctypes.byref(data.s)))
+    if d < 0:
+        raise GLRMError(EINVAL, glrm_last_error())
+    return d
+
+
 def glrm_prepare(data, stream=None):
     ws, wsb = data.workspace()
     _check(_L().glrm_prepare(ctypes.byref(data.s), ws, wsb, _stream(stream)))
@@ -281,7 +296,7 @@ def glrm_objective(data, X, Y, precision=FP32, flags=0, stream=None):
     ws, wsb = data.workspace()
     out = ctypes.c_double(0.0)
     _check(_L().glrm_objective(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
-                               _dev_ptr(Y, torch.float32, "Y", data.n * data.k), _prec(precision),
+                               _dev_ptr(Y, torch.float32, "Y", data.d * data.k), _prec(precision),
                                ctypes.byref(out), ws, wsb, int(flags), _stream(stream)))
     return out.value
 
@@ -292,13 +307,13 @@ def glrm_grad(data, X, Y, precision=FP32, dX=None, dY=None, want_objective=False
     if dX is None:
         dX = torch.empty((data.m, data.k), dtype=torch.float32, device=X.device)
     if dY is None:
-        dY = torch.empty((data.n, data.k), dtype=torch.float32, device=X.device)
+        dY = torch.empty((data.d, data.k), dtype=torch.float32, device=X.device)
     ws, wsb = data.workspace()
     out = ctypes.c_double(0.0)
     _check(_L().glrm_grad(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
-                          _dev_ptr(Y, torch.float32, "Y", data.n * data.k), _prec(precision),
+                          _dev_ptr(Y, torch.float32, "Y", data.d * data.k), _prec(precision),
                           _dev_ptr(dX, torch.float32, "dX", data.m * data.k),
-                          _dev_ptr(dY, torch.float32, "dY", data.n * data.k),
+                          _dev_ptr(dY, torch.float32, "dY", data.d * data.k),
                           ctypes.byref(out) if want_objective else None, ws, wsb, int(flags), _stream(stream)))
     return (dX, dY, out.value) if want_objective else (dX, dY)
 
@@ -310,12 +325,12 @@ def glrm_grad_noalloc(data, X, Y, precision=FP32, dX=None, dY=None, want_objecti
     if dX is None:
         dX = torch.empty((data.m, data.k), dtype=torch.float32, device=X.device)
     if dY is None:
-        dY = torch.empty((data.n, data.k), dtype=torch.float32, device=X.device)
+        dY = torch.empty((data.d, data.k), dtype=torch.float32, device=X.device)
     out = ctypes.c_double(0.0)
     _check(_L().glrm_grad_noalloc(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
-                                  _dev_ptr(Y, torch.float32, "Y", data.n * data.k), _prec(precision),
+                                  _dev_ptr(Y, torch.float32, "Y", data.d * data.k), _prec(precision),
                                   _dev_ptr(dX, torch.float32, "dX", data.m * data.k),
-                                  _dev_ptr(dY, torch.float32, "dY", data.n * data.k),
+                                  _dev_ptr(dY, torch.float32, "dY", data.d * data.k),
                                   ctypes.byref(out) if want_objective else None, int(flags), _stream(stream)))
     return (dX, dY, out.value) if want_objective else (dX, dY)
 
@@ -334,7 +349,7 @@ def glrm_certificate(data, X, Y, iters=500, flags=0, stream=None):
     ws, wsb = data.workspace(glrm_linalg_workspace_size(data, 1))
     info = _CertInfo()
     _check(_L().glrm_certificate(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
-                                 _dev_ptr(Y, torch.float32, "Y", data.n * data.k), int(iters), ctypes.byref(info),
+                                 _dev_ptr(Y, torch.float32, "Y", data.d * data.k), int(iters), ctypes.byref(info),
                                  ws, wsb, int(flags), _stream(stream)))
     return dict(norm=info.norm, norm_prev=info.norm_prev, rank=info.rank, iters=info.iters)
 
@@ -370,7 +385,7 @@ def glrm_init_svd(data, omega, mu=None, sigma2=None, power_iters=2, X=None, Y=No
                               _dev_ptr(sigma2, torch.float32, "sigma2", data.n) if sigma2 is not None else None,
                               _dev_ptr(omega, torch.float32, "omega", data.n * l) if omega is not None else None,
                               l, int(power_iters), _dev_ptr(X, torch.float32, "X", data.m * data.k),
-                              _dev_ptr(Y, torch.float32, "Y", data.n * data.k), sv, ws, wsb, int(flags),
+                              _dev_ptr(Y, torch.float32, "Y", data.d * data.k), sv, ws, wsb, int(flags),
                               _stream(stream)))
     return X, Y, np.array(sv[:ks])
 
@@ -423,9 +438,9 @@ def glrm_fit(data, X, Y, alpha_x, alpha_y, max_sweeps, precision=BF16, init_alph
     size = _L().glrm_fit_workspace_size(ctypes.byref(data.s), ctypes.byref(o))
     ws, wsb = data.workspace(size)
     _check(_L().glrm_fit(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
-                         _dev_ptr(Y, torch.float32, "Y", data.n * data.k),
+                         _dev_ptr(Y, torch.float32, "Y", data.d * data.k),
                          _dev_ptr(alpha_x, torch.float32, "alpha_x", data.m),
-                         _dev_ptr(alpha_y, torch.float32, "alpha_y", data.n), ctypes.byref(o), ctypes.byref(info),
+                         _dev_ptr(alpha_y, torch.float32, "alpha_y", data.d), ctypes.byref(o), ctypes.byref(info),
                          _dev_ptr(history, torch.float64, "history") if history is not None else None,
                          ws, wsb, _stream(stream)))
     return dict(sweeps=info.sweeps, objective=info.objective, objective_fp32=info.objective_fp32,
@@ -446,7 +461,7 @@ def glrm_impute(data, X, Y, mode=IMPUTE_ALL, out=None, flags=0, stream=None):
         raise ValueError("out must be m x n with stride (ldh >= n, 1)")
     ws, wsb = data.workspace()
     _check(_L().glrm_impute(ctypes.byref(data.s), _dev_ptr(X, torch.float32, "X", data.m * data.k),
-                            _dev_ptr(Y, torch.float32, "Y", data.n * data.k), int(mode),
+                            _dev_ptr(Y, torch.float32, "Y", data.d * data.k), int(mode),
                             ctypes.c_void_p(out.data_ptr()), int(out.stride(0)), ws, wsb, int(flags),
                             _stream(stream)))
     return out

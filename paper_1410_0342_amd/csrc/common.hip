@@ -7,6 +7,18 @@
 
 namespace glrm {
 
+// Packed column j of row i: whether it is observed, and its value.
+__device__ __forceinline__ bool pack_entry(const PackArgs &a, int64_t i, int64_t j, float &v)
+{
+    const int64_t s = a.emb.src ? a.emb.src[j] : j;
+    if (a.mask && a.mask[i * a.lda + s] == 0) return false;
+    const float x = a.A[i * a.lda + s];
+    if (!a.emb.src || a.emb.kind[j] == EMB_COPY) v = x;
+    else if (a.emb.kind[j] == EMB_EQ) v = x == (float)a.emb.thr[j] ? 1.0f : -1.0f;
+    else v = x > (float)a.emb.thr[j] ? 1.0f : -1.0f;
+    return true;
+}
+
 // One workgroup per 16 rows of the padded table.  Unobserved and padding
 // entries become quiet NaN.  Row counts are exact block sums; column counts
 // are integer atomics (order-free, so deterministic).
@@ -20,10 +32,7 @@ __global__ __launch_bounds__(256) void pack_dense_kernel(PackArgs a)
         int cnt = 0;
         for (int64_t j = threadIdx.x; j < a.ldp; j += 256) {
             float v = qnan;
-            if (i < a.m && j < a.n) {
-                const bool obs = a.mask ? (a.mask[i * a.lda + j] != 0) : true;
-                if (obs) { v = a.A[i * a.lda + j]; ++cnt; }
-            }
+            if (i < a.m && j < a.n && pack_entry(a, i, j, v)) ++cnt;
             a.Ap[i * a.ldp + j] = v;
         }
         cnt = (int)sum_lanes<64>((float)cnt);
@@ -36,7 +45,7 @@ __global__ __launch_bounds__(256) void pack_dense_kernel(PackArgs a)
         int cnt = 0;
         for (int ii = 0; ii < 16; ++ii) {
             const int64_t i = i0 + ii;
-            if (i < a.m) cnt += a.mask ? (a.mask[i * a.lda + j] != 0) : 1;
+            if (i < a.m) cnt += a.mask ? (a.mask[i * a.lda + (a.emb.src ? a.emb.src[j] : j)] != 0) : 1;
         }
         if (cnt) atomicAdd(&a.col_count[j], cnt);
     }
@@ -127,16 +136,19 @@ hipError_t launch_sum_doubles(const double *a, int32_t na, const double *b, int3
     return hipGetLastError();
 }
 
-// dst[j] = src[j] for j < n (1 without src), 1 for the padding columns up to ldp.
-__global__ void pad_weights_kernel(const float *src, int64_t n, int64_t ldp, float *dst)
+// dst[j] = src[map[j]] (src[j] without a map; 1 without src) for j < n, 1 for
+// the padding columns up to ldp.
+__global__ void pad_weights_kernel(const float *src, const int32_t *map, int64_t n, int64_t ldp, float *dst)
 {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j < ldp) dst[j] = (src && j < n) ? src[j] : 1.0f;
+    if (j < ldp) dst[j] = (src && j < n) ? src[map ? map[j] : j] : 1.0f;
 }
 
-hipError_t launch_pad_weights(const float *src, int64_t n, int64_t ldp, float *dst, hipStream_t st)
+hipError_t launch_pad_weights(const float *src, const int32_t *map, int64_t n, int64_t ldp, float *dst,
+                              hipStream_t st)
 {
-    hipLaunchKernelGGL(pad_weights_kernel, dim3((unsigned)((ldp + 255) / 256)), dim3(256), 0, st, src, n, ldp, dst);
+    hipLaunchKernelGGL(pad_weights_kernel, dim3((unsigned)((ldp + 255) / 256)), dim3(256), 0, st, src, map, n, ldp,
+                       dst);
     return hipGetLastError();
 }
 

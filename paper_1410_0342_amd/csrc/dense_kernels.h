@@ -1091,13 +1091,30 @@ __global__ __launch_bounds__(256) void yaccept_kernel(YAcceptArgs a)
         for (int p = c; p < a.P; p += KP) hp += a.part_hp[(int64_t)p * a.ldp + j];
     }
     hp = sum_lanes<KP>(hp);   // the same value in every lane of the column
+    if (a.phase == 1) {
+        if (valid && c == 0) a.hpc[j] = hp + ryp;
+        return;
+    }
     if (valid) {
         hp += ryp;
-        acc = hp <= h ? 1 : 0;
+        bool lead = true;     // the lane that counts the decision
+        if (a.phase == 2) {
+            // the block's sums, in column order (the same in every column of it)
+            const int32_t b0 = a.blk0[j], b1 = a.blk1[j];
+            float hb = 0.0f, hpb = 0.0f;
+            for (int32_t e = b0; e < b1; ++e) {
+                hb += a.h_old[e];
+                hpb += a.hpc[e];
+            }
+            acc = hpb <= hb ? 1 : 0;
+            lead = j == b0;
+        } else {
+            acc = hp <= h ? 1 : 0;
+        }
         if (c == 0) {
             a.alpha[j] = acc ? al * a.step_up : al * a.step_down;
             Fj = acc ? (double)hp : (double)h;
-            rj = acc ? 0 : 1;
+            rj = (acc || !lead) ? 0 : 1;
         }
         if (acc) {
             if (c < a.k) a.Y[j * a.k + c] = yv;

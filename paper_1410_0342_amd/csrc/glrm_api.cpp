@@ -76,6 +76,8 @@ struct Layout {
     size_t total = 0;
     // offsets
     size_t codes, colw, row_count, col_count, Ap;
+    size_t emb_src, emb_thr, emb_kind, blk0, blk1, hpc;   // embedded columns (Section 6)
+    size_t feat;                                          // per column of A: block start, kind, levels
     size_t part_dy, part_h, part_hp, part_rowreg, part_rej, part_dx, part_obj;
     size_t ycur_f32, ycur_t32, ycur_hi, ycur_lo, ycur_tb;
     size_t yp_f32, yp_t32, yp_hi, yp_lo, yp_tb;
@@ -130,6 +132,13 @@ bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false, int aux_
     const int64_t kp = L.kp, ldp = L.ldp, n = L.n, m = L.m;
     L.codes = L.take(ldp);
     L.colw = L.take(sizeof(float) * ldp);
+    L.emb_src = L.take(sizeof(int32_t) * ldp);
+    L.emb_thr = L.take(sizeof(int32_t) * ldp);
+    L.emb_kind = L.take(ldp);
+    L.blk0 = L.take(sizeof(int32_t) * ldp);
+    L.blk1 = L.take(sizeof(int32_t) * ldp);
+    L.hpc = L.take(sizeof(float) * ldp);
+    L.feat = L.take(sizeof(int32_t) * 3 * ldp);
     L.row_count = L.take(sizeof(int32_t) * m);
     L.col_count = L.take(sizeof(int32_t) * n);
     L.stats = L.take(sizeof(double) * 8);
@@ -233,11 +242,13 @@ int validate_data(const glrm_data *d)
     if (!d->losses) return fail(GLRM_EINVAL, "losses is NULL");
     for (int q = 0; q < d->n_losses; ++q) {
         const glrm_loss &l = d->losses[q];
-        if (l.kind < GLRM_LOSS_QUADRATIC || l.kind > GLRM_LOSS_ORDINAL) return fail(GLRM_EINVAL, "loss %d: unknown kind %d", q, l.kind);
+        if (l.kind < GLRM_LOSS_QUADRATIC || l.kind > GLRM_LOSS_MORDINAL) return fail(GLRM_EINVAL, "loss %d: unknown kind %d", q, l.kind);
         if (l.kind == GLRM_LOSS_HUBER && !(l.param > 0.0f && std::isfinite(l.param)))
             return fail(GLRM_EINVAL, "loss %d: Huber threshold must be finite and > 0", q);
         if (l.kind == GLRM_LOSS_ORDINAL && (l.levels < 2 || l.levels > 1000000))
             return fail(GLRM_EINVAL, "loss %d: ordinal levels must be in 2..1e6", q);
+        if ((l.kind == GLRM_LOSS_CATEGORICAL || l.kind == GLRM_LOSS_MORDINAL) && (l.levels < 2 || l.levels > GLRM_MAX_LEVELS))
+            return fail(GLRM_EINVAL, "loss %d: a multi-dimensional loss needs 2..%d levels", q, GLRM_MAX_LEVELS);
     }
     if (d->col_loss) {
         for (int64_t j = 0; j < d->n; ++j)
@@ -249,6 +260,113 @@ int validate_data(const glrm_data *d)
         if (!(r->weight >= 0.0f) || !std::isfinite(r->weight)) return fail(GLRM_EINVAL, "regularizer weight must be finite and >= 0");
     }
     return GLRM_OK;
+}
+
+// ---- multi-dimensional losses (Section 6) ----------------------------------
+// A column of A under the categorical or multi-dimensional ordinal loss with
+// d levels is a feature of embedding dimension d or d - 1.  Both losses are
+// sums of hinge losses (1 - s u_l)_+ over their embedded columns with a sign
+// s = +-1 fixed by the value (one-vs-all: s = +1 on the value's own label;
+// ordinal: s = +1 on the thresholds below the value), so every pass runs
+// unchanged on the embedded table of +-1 entries under the hinge loss, and
+// only the column step decides per block (one decision for the block Y_j).
+struct Embed {
+    bool active = false;
+    glrm_data e;                        // the problem over the embedded columns
+    std::vector<uint8_t> codes;         // loss code per embedded column
+    std::vector<glrm_loss> losses;      // the caller's table (+ a hinge entry)
+    std::vector<int32_t> src, thr, blk0, blk1;
+    std::vector<uint8_t> kind;
+};
+
+bool is_md(int kind) { return kind == GLRM_LOSS_CATEGORICAL || kind == GLRM_LOSS_MORDINAL; }
+
+int md_dim(const glrm_loss &l)
+{
+    return l.kind == GLRM_LOSS_CATEGORICAL ? l.levels : (l.kind == GLRM_LOSS_MORDINAL ? l.levels - 1 : 1);
+}
+
+// Validates d and points *out at the problem the passes run on: d itself, or
+// its embedding in E.
+int embed(const glrm_data *d, Embed &E, const glrm_data **out)
+{
+    int rc = validate_data(d);
+    if (rc) return rc;
+    *out = d;
+    E.active = false;
+    bool any = false;
+    int64_t total = 0;
+    for (int64_t j = 0; j < d->n; ++j) {
+        const glrm_loss &l = d->losses[d->col_loss ? d->col_loss[j] : 0];
+        any = any || is_md(l.kind);
+        total += md_dim(l);
+    }
+    if (!any) return GLRM_OK;
+    if (d->layout != GLRM_DENSE) return fail(GLRM_EUNSUPPORTED, "multi-dimensional losses are built for the dense layout");
+    if (total > (int64_t)INT32_MAX) return fail(GLRM_EUNSUPPORTED, "the embedded table must have < 2^31 columns");
+    E.losses.assign(d->losses, d->losses + d->n_losses);
+    int hinge = -1;
+    for (int q = 0; q < d->n_losses && hinge < 0; ++q)
+        if (d->losses[q].kind == GLRM_LOSS_HINGE) hinge = q;
+    if (hinge < 0) {
+        if (d->n_losses >= GLRM_MAX_LOSSES)
+            return fail(GLRM_EUNSUPPORTED, "multi-dimensional losses need a free loss slot (n_losses < %d) or a hinge entry",
+                        GLRM_MAX_LOSSES);
+        hinge = d->n_losses;
+        E.losses.push_back(glrm_loss{GLRM_LOSS_HINGE, 0, 0.0f});
+    }
+    E.codes.clear(); E.src.clear(); E.thr.clear(); E.kind.clear(); E.blk0.clear(); E.blk1.clear();
+    for (int64_t j = 0; j < d->n; ++j) {
+        const int q = d->col_loss ? d->col_loss[j] : 0;
+        const glrm_loss &l = d->losses[q];
+        const int dj = md_dim(l);
+        const int32_t b0 = (int32_t)E.src.size();
+        for (int t = 0; t < dj; ++t) {
+            E.src.push_back((int32_t)j);
+            E.blk0.push_back(b0);
+            E.blk1.push_back(b0 + dj);
+            if (l.kind == GLRM_LOSS_CATEGORICAL) {          // label t + 1 against the rest
+                E.codes.push_back((uint8_t)hinge); E.kind.push_back(EMB_EQ); E.thr.push_back(t + 1);
+            } else if (l.kind == GLRM_LOSS_MORDINAL) {      // levels above t + 1 against the rest
+                E.codes.push_back((uint8_t)hinge); E.kind.push_back(EMB_GT); E.thr.push_back(t + 1);
+            } else {
+                E.codes.push_back((uint8_t)q); E.kind.push_back(EMB_COPY); E.thr.push_back(0);
+            }
+        }
+    }
+    E.e = *d;
+    E.e.n = total;
+    E.e.col_loss = E.codes.data();
+    E.e.losses = E.losses.data();
+    E.e.n_losses = (int32_t)E.losses.size();
+    E.active = true;
+    *out = &E.e;
+    return GLRM_OK;
+}
+
+// Uploads the embedding map (padding columns repeat the last column, as the
+// codes do); the caller synchronizes before the vectors go.
+int upload_embed(const Embed &E, const Layout &L, void *ws, std::vector<int32_t> (&pad)[4], std::vector<uint8_t> &kpad,
+                 hipStream_t st)
+{
+    const std::vector<int32_t> *v[4] = {&E.src, &E.thr, &E.blk0, &E.blk1};
+    const size_t off[4] = {L.emb_src, L.emb_thr, L.blk0, L.blk1};
+    for (int q = 0; q < 4; ++q) {
+        pad[q] = *v[q];
+        pad[q].resize((size_t)L.ldp, v[q]->back());
+        HIP_TRY(hipMemcpyAsync(at<int32_t>(ws, off[q]), pad[q].data(), sizeof(int32_t) * L.ldp, hipMemcpyHostToDevice,
+                               st));
+    }
+    kpad = E.kind;
+    kpad.resize((size_t)L.ldp, E.kind.back());
+    HIP_TRY(hipMemcpyAsync(at<uint8_t>(ws, L.emb_kind), kpad.data(), (size_t)L.ldp, hipMemcpyHostToDevice, st));
+    return GLRM_OK;
+}
+
+EmbedMap embed_map(const Embed &E, const Layout &L, void *ws)
+{
+    if (!E.active) return EmbedMap{nullptr, nullptr, nullptr};
+    return EmbedMap{at<int32_t>(ws, L.emb_src), at<int32_t>(ws, L.emb_thr), at<uint8_t>(ws, L.emb_kind)};
 }
 
 // The loss table as the kernels take it.  With per-column weights the table
@@ -331,17 +449,22 @@ int upload_codes(const glrm_data *d, const Layout &L, void *ws, std::string &cod
     return GLRM_OK;
 }
 
-int prepare(const glrm_data *d, const Layout &L, void *ws, hipStream_t st)
+int prepare(const glrm_data *d, const Layout &L, void *ws, hipStream_t st, const Embed &E)
 {
     std::string codes;
     int rc0 = upload_codes(d, L, ws, codes, st);
     if (rc0) return rc0;
-    HIP_TRY(launch_pad_weights(d->col_weight, L.n, L.ldp, at<float>(ws, L.colw), st));
+    std::vector<int32_t> pad[4];
+    std::vector<uint8_t> kpad;
+    if (E.active && (rc0 = upload_embed(E, L, ws, pad, kpad, st))) return rc0;
+    const EmbedMap em = embed_map(E, L, ws);
+    HIP_TRY(launch_pad_weights(d->col_weight, em.src, L.n, L.ldp, at<float>(ws, L.colw), st));
     if (d->layout == GLRM_DENSE) {
         HIP_TRY(launch_fill_i32(at<int32_t>(ws, L.col_count), L.n, 0, st));
         PackArgs p;
         p.m = L.m; p.n = L.n; p.lda = d->lda; p.mp = L.mp; p.ldp = L.ldp;
         p.A = d->A; p.mask = d->mask;
+        p.emb = em;
         p.Ap = at<float>(ws, L.Ap);
         p.row_count = at<int32_t>(ws, L.row_count);
         p.col_count = at<int32_t>(ws, L.col_count);
@@ -351,7 +474,7 @@ int prepare(const glrm_data *d, const Layout &L, void *ws, hipStream_t st)
                              at<int32_t>(ws, L.col_count), st);
         if (rc != GLRM_OK) return rc;
     }
-    // the host string must outlive the copy
+    // the host vectors must outlive the copies
     HIP_TRY(hipStreamSynchronize(st));
     if (d->layout != GLRM_DENSE) {
         int bad = coo_check_result(L.cl, at<char>(ws, L.coo), st);
@@ -522,10 +645,10 @@ namespace {
 // The gradient entry points after their checks: prepare unless told the
 // workspace holds it, one loss-and-gradient pass, the objective if asked.
 int grad_run(const glrm_data *d, const Layout &L, const float *X, const float *Y, int precision, float *dX,
-             float *dY, double *obj_host, void *ws, unsigned flags, hipStream_t st)
+             float *dY, double *obj_host, void *ws, unsigned flags, hipStream_t st, const Embed &E)
 {
     int rc;
-    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st, E))) return rc;
     double *po = nullptr;
     int nparts = 0;
     if (d->layout == GLRM_DENSE) {
@@ -669,38 +792,54 @@ const char *glrm_last_error(void) { return g_err.c_str(); }
 
 const char *glrm_version(void) { return "glrm-gfx950 0.1"; }
 
-size_t glrm_workspace_size(const glrm_data *d)
+size_t glrm_workspace_size(const glrm_data *d0)
 {
-    if (validate_data(d) != GLRM_OK) return 0;
+    Embed E;
+    const glrm_data *d = nullptr;
+    if (embed(d0, E, &d) != GLRM_OK) return 0;
     Layout L;
     make_layout(d, L);
     return L.total;
 }
 
-size_t glrm_fit_workspace_size(const glrm_data *d, const glrm_fit_opts *o)
+int64_t glrm_embed_dim(const glrm_data *d0)
 {
-    if (validate_data(d) != GLRM_OK) return 0;
+    Embed E;
+    const glrm_data *d = nullptr;
+    if (embed(d0, E, &d) != GLRM_OK) return -1;
+    return d->n;
+}
+
+size_t glrm_fit_workspace_size(const glrm_data *d0, const glrm_fit_opts *o)
+{
+    Embed E;
+    const glrm_data *d = nullptr;
+    if (embed(d0, E, &d) != GLRM_OK) return 0;
     Layout L;
     make_layout(d, L, false, 0, o && o->update == GLRM_UPDATE_PROXPROX);
     return L.total;
 }
 
-int glrm_prepare(const glrm_data *d, void *ws, size_t ws_bytes, void *stream)
+int glrm_prepare(const glrm_data *d0, void *ws, size_t ws_bytes, void *stream)
 {
     g_err.clear();
-    int rc = validate_data(d);
+    Embed E;
+    const glrm_data *d = nullptr;
+    int rc = embed(d0, E, &d);
     if (rc) return rc;
     Layout L;
     make_layout(d, L);
     if ((rc = check_ws(L, ws, ws_bytes))) return rc;
-    return prepare(d, L, ws, (hipStream_t)stream);
+    return prepare(d, L, ws, (hipStream_t)stream, E);
 }
 
-int glrm_objective(const glrm_data *d, const float *X, const float *Y, int precision, double *obj_host, void *ws,
+int glrm_objective(const glrm_data *d0, const float *X, const float *Y, int precision, double *obj_host, void *ws,
                    size_t ws_bytes, unsigned flags, void *stream)
 {
     g_err.clear();
-    int rc = validate_data(d);
+    Embed E;
+    const glrm_data *d = nullptr;
+    int rc = embed(d0, E, &d);
     if (rc) return rc;
     if (!X || !Y || !obj_host) return fail(GLRM_EINVAL, "X, Y and obj_host must not be NULL");
     if ((rc = check_prec(precision, true))) return rc;
@@ -708,7 +847,7 @@ int glrm_objective(const glrm_data *d, const float *X, const float *Y, int preci
     make_layout(d, L);
     if ((rc = check_ws(L, ws, ws_bytes))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st, E))) return rc;
     double *res = at<double>(ws, L.scal);
     if (precision == GLRM_FP64) {
         if ((rc = objective64(d, L, X, Y, ws, res, st))) return rc;
@@ -732,25 +871,29 @@ int glrm_objective(const glrm_data *d, const float *X, const float *Y, int preci
     return GLRM_OK;
 }
 
-int glrm_grad(const glrm_data *d, const float *X, const float *Y, int precision, float *dX, float *dY,
+int glrm_grad(const glrm_data *d0, const float *X, const float *Y, int precision, float *dX, float *dY,
               double *obj_host, void *ws, size_t ws_bytes, unsigned flags, void *stream)
 {
     g_err.clear();
-    int rc = validate_data(d);
+    Embed E;
+    const glrm_data *d = nullptr;
+    int rc = embed(d0, E, &d);
     if (rc) return rc;
     if (!X || !Y || !dX || !dY) return fail(GLRM_EINVAL, "X, Y, dX and dY must not be NULL");
     if ((rc = check_prec(precision, false))) return rc;
     Layout L;
     make_layout(d, L);
     if ((rc = check_ws(L, ws, ws_bytes))) return rc;
-    return grad_run(d, L, X, Y, precision, dX, dY, obj_host, ws, flags, (hipStream_t)stream);
+    return grad_run(d, L, X, Y, precision, dX, dY, obj_host, ws, flags, (hipStream_t)stream, E);
 }
 
-int glrm_grad_noalloc(const glrm_data *d, const float *X, const float *Y, int precision, float *dX, float *dY,
+int glrm_grad_noalloc(const glrm_data *d0, const float *X, const float *Y, int precision, float *dX, float *dY,
                       double *obj_host, unsigned flags, void *stream)
 {
     g_err.clear();
-    int rc = validate_data(d);
+    Embed E;
+    const glrm_data *d = nullptr;
+    int rc = embed(d0, E, &d);
     if (rc) return rc;
     if (!X || !Y || !dX || !dY) return fail(GLRM_EINVAL, "X, Y, dX and dY must not be NULL");
     if ((rc = check_prec(precision, false))) return rc;
@@ -761,11 +904,13 @@ int glrm_grad_noalloc(const glrm_data *d, const float *X, const float *Y, int pr
                     "holds %zu (use glrm_grad with a workspace)", L.total, (size_t)GLRM_NOALLOC_MAX_BYTES);
     void *ws = nullptr;
     if ((rc = scratch_address(&ws))) return rc;
-    return grad_run(d, L, X, Y, precision, dX, dY, obj_host, ws, flags, (hipStream_t)stream);
+    return grad_run(d, L, X, Y, precision, dX, dY, obj_host, ws, flags, (hipStream_t)stream, E);
 }
-size_t glrm_linalg_workspace_size(const glrm_data *d, int32_t block)
+size_t glrm_linalg_workspace_size(const glrm_data *d0, int32_t block)
 {
-    if (validate_data(d) != GLRM_OK) return 0;
+    Embed E;
+    const glrm_data *d = nullptr;
+    if (embed(d0, E, &d) != GLRM_OK) return 0;
     if (block < 1 || block > LA_MAXB) {
         fail(GLRM_EINVAL, "block must be in 1..%d", LA_MAXB);
         return 0;
@@ -775,11 +920,13 @@ size_t glrm_linalg_workspace_size(const glrm_data *d, int32_t block)
     return L.total;
 }
 
-int glrm_certificate(const glrm_data *d, const float *X, const float *Y, int32_t iters, glrm_cert_info *info,
+int glrm_certificate(const glrm_data *d0, const float *X, const float *Y, int32_t iters, glrm_cert_info *info,
                      void *ws, size_t ws_bytes, unsigned flags, void *stream)
 {
     g_err.clear();
-    int rc = validate_data(d);
+    Embed E;
+    const glrm_data *d = nullptr;
+    int rc = embed(d0, E, &d);
     if (rc) return rc;
     if (!X || !Y || !info) return fail(GLRM_EINVAL, "X, Y and info must not be NULL");
     if (iters < 1 || iters > 1000000) return fail(GLRM_EINVAL, "iters must be in 1..1e6");
@@ -790,7 +937,7 @@ int glrm_certificate(const glrm_data *d, const float *X, const float *Y, int32_t
     make_layout(d, L, false, 1);
     if ((rc = check_ws(L, ws, ws_bytes))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st, E))) return rc;
     const int k = (int)L.k;
     // weight w on ||x||^2 is the factored problem's gamma / 2
     const double inv_gamma = 1.0 / (2.0 * (double)d->rx.weight);
@@ -838,18 +985,21 @@ int glrm_certificate(const glrm_data *d, const float *X, const float *Y, int32_t
     return GLRM_OK;
 }
 
-int glrm_column_scaling(const glrm_data *d, float *mu, float *sigma2, void *ws, size_t ws_bytes, unsigned flags,
+int glrm_column_scaling(const glrm_data *d0, float *mu, float *sigma2, void *ws, size_t ws_bytes, unsigned flags,
                         void *stream)
 {
     g_err.clear();
-    int rc = validate_data(d);
+    Embed E;
+    const glrm_data *d = nullptr;
+    int rc = embed(d0, E, &d);
     if (rc) return rc;
+    if (E.active) return fail(GLRM_EUNSUPPORTED, "column scaling is built for scalar losses only");
     if (!mu || !sigma2) return fail(GLRM_EINVAL, "mu and sigma2 must not be NULL");
     Layout L;
     make_layout(d, L, false, 1);
     if ((rc = check_ws(L, ws, ws_bytes))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st, E))) return rc;
     const bool coo = d->layout != GLRM_DENSE;
     ColArgs a;
     memset(&a, 0, sizeof a);
@@ -881,13 +1031,16 @@ int glrm_column_scaling(const glrm_data *d, float *mu, float *sigma2, void *ws, 
     return GLRM_OK;
 }
 
-int glrm_init_svd(const glrm_data *d, const float *mu, const float *sigma2, const float *omega, int32_t l,
+int glrm_init_svd(const glrm_data *d0, const float *mu, const float *sigma2, const float *omega, int32_t l,
                   int32_t power_iters, float *X, float *Y, double *sv_host, void *ws, size_t ws_bytes,
                   unsigned flags, void *stream)
 {
     g_err.clear();
-    int rc = validate_data(d);
+    Embed E;
+    const glrm_data *d = nullptr;
+    int rc = embed(d0, E, &d);
     if (rc) return rc;
+    if (E.active) return fail(GLRM_EUNSUPPORTED, "the SVD initialization is built for scalar losses only");
     const int k = d->k, off = d->offset ? 1 : 0, ks = k - off;
     if (!X || !Y) return fail(GLRM_EINVAL, "X and Y must not be NULL");
     if (off && !mu) return fail(GLRM_EINVAL, "the offset row needs the column means mu");
@@ -898,7 +1051,7 @@ int glrm_init_svd(const glrm_data *d, const float *mu, const float *sigma2, cons
     make_layout(d, L, false, l);
     if ((rc = check_ws(L, ws, ws_bytes))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    if (!(flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st, E))) return rc;
     const int64_t m = L.m, n = L.n;
     const int32_t *count = at<int32_t>(ws, L.col_count);
     float *cs = at<float>(ws, L.aux_cols), *mu0 = cs + n;
@@ -977,28 +1130,56 @@ int glrm_init_svd(const glrm_data *d, const float *mu, const float *sigma2, cons
     return GLRM_OK;
 }
 
-int glrm_impute(const glrm_data *d, const float *X, const float *Y, int32_t mode, float *Ahat, int64_t ldh, void *ws,
+int glrm_impute(const glrm_data *d0, const float *X, const float *Y, int32_t mode, float *Ahat, int64_t ldh, void *ws,
                 size_t ws_bytes, unsigned flags, void *stream)
 {
     g_err.clear();
-    int rc = validate_data(d);
+    Embed E;
+    const glrm_data *d = nullptr;
+    int rc = embed(d0, E, &d);
     if (rc) return rc;
     if (!X || !Y || !Ahat) return fail(GLRM_EINVAL, "X, Y and Ahat must not be NULL");
     if (mode != GLRM_IMPUTE_ALL && mode != GLRM_IMPUTE_MISSING) return fail(GLRM_EINVAL, "unknown imputation mode %d", mode);
-    if (ldh < d->n) return fail(GLRM_EINVAL, "ldh (%lld) < n (%lld)", (long long)ldh, (long long)d->n);
+    if (ldh < d0->n) return fail(GLRM_EINVAL, "ldh (%lld) < n (%lld)", (long long)ldh, (long long)d0->n);
     Layout L;
     make_layout(d, L);
     if ((rc = check_ws(L, ws, ws_bytes))) return rc;
     hipStream_t st = (hipStream_t)stream;
+    if (E.active) {
+        // feature by feature: the block's first row of Y, the loss kind and levels
+        std::vector<int32_t> info(3 * (size_t)d0->n);
+        for (int64_t j = 0, c = 0; j < d0->n; ++j) {
+            const glrm_loss &l = d0->losses[d0->col_loss ? d0->col_loss[j] : 0];
+            info[(size_t)j] = (int32_t)c;
+            info[(size_t)(d0->n + j)] = l.kind;
+            info[(size_t)(2 * d0->n + j)] = l.levels;
+            c += md_dim(l);
+        }
+        int32_t *fi = at<int32_t>(ws, L.feat);
+        HIP_TRY(hipMemcpyAsync(fi, info.data(), sizeof(int32_t) * info.size(), hipMemcpyHostToDevice, st));
+        ImputeMDArgs a;
+        a.m = d0->m; a.nf = d0->n; a.ldh = ldh; a.lda = d0->lda; a.k = d0->k;
+        a.keep_observed = (mode == GLRM_IMPUTE_MISSING && d0->mask) ? 1 : 0;
+        a.fcol = fi; a.fkind = fi + d0->n; a.flev = fi + 2 * d0->n;
+        if (mode == GLRM_IMPUTE_MISSING && !d0->mask) {
+            HIP_TRY(hipMemcpy2DAsync(Ahat, (size_t)ldh * sizeof(float), d0->A, (size_t)d0->lda * sizeof(float),
+                                     (size_t)d0->n * sizeof(float), (size_t)d0->m, hipMemcpyDeviceToDevice, st));
+        } else {
+            HIP_TRY(launch_impute_md(a, X, Y, d0->A, d0->mask, Ahat, st));
+        }
+        // the host vector must outlive the copy
+        HIP_TRY(hipStreamSynchronize(st));
+        return GLRM_OK;
+    }
     // the pass needs only the loss codes; a COO list that is about to be
     // written into the output is validated by the full preparation
     if (!(flags & GLRM_WS_PREPARED)) {
         if (d->layout == GLRM_COO_ROWSORTED && mode == GLRM_IMPUTE_MISSING) {
-            if ((rc = prepare(d, L, ws, st))) return rc;
+            if ((rc = prepare(d, L, ws, st, E))) return rc;
         } else {
             std::string codes;
             if ((rc = upload_codes(d, L, ws, codes, st))) return rc;
-            HIP_TRY(launch_pad_weights(d->col_weight, L.n, L.ldp, at<float>(ws, L.colw), st));
+            HIP_TRY(launch_pad_weights(d->col_weight, nullptr, L.n, L.ldp, at<float>(ws, L.colw), st));
             HIP_TRY(hipStreamSynchronize(st));
         }
     }
@@ -1034,11 +1215,13 @@ int glrm_prox(const glrm_reg *reg, float *V, int64_t rows, int32_t k, int64_t ld
     return GLRM_OK;
 }
 
-int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alpha_y, const glrm_fit_opts *o,
+int glrm_fit(const glrm_data *d0, float *X, float *Y, float *alpha_x, float *alpha_y, const glrm_fit_opts *o,
              glrm_fit_info *info, double *history, void *ws, size_t ws_bytes, void *stream)
 {
     g_err.clear();
-    int rc = validate_data(d);
+    Embed E;
+    const glrm_data *d = nullptr;
+    int rc = embed(d0, E, &d);
     if (rc) return rc;
     if (!X || !Y || !alpha_x || !alpha_y || !o) return fail(GLRM_EINVAL, "X, Y, alpha_x, alpha_y and opts must not be NULL");
     if (o->max_sweeps < 0) return fail(GLRM_EINVAL, "max_sweeps < 0");
@@ -1082,7 +1265,7 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
     if (info) memset(info, 0, sizeof *info);
     KernelTimer timer;
     if ((rc = timer.init((o->flags & GLRM_TIME_KERNELS) != 0, (size_t)o->max_sweeps * 4))) return rc;
-    if (!(o->flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st))) return rc;
+    if (!(o->flags & GLRM_WS_PREPARED) && (rc = prepare(d, L, ws, st, E))) return rc;
     if (o->init_alpha) {
         HIP_TRY(launch_init_alpha(at<int32_t>(ws, L.row_count), L.m, o->alpha_scale, alpha_x, st));
         HIP_TRY(launch_init_alpha(at<int32_t>(ws, L.col_count), L.n, o->alpha_scale, alpha_y, st));
@@ -1201,6 +1384,12 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
         aa.yplus = pa.yplus; aa.ycur = xa.ycur;
         aa.part_F = at<double>(ws, L.part_F);
         aa.part_rejc = at<int32_t>(ws, L.part_rejc);
+        aa.phase = E.active ? 2 : 0;
+        aa.hpc = at<float>(ws, L.hpc);
+        aa.blk0 = E.active ? at<int32_t>(ws, L.blk0) : nullptr;
+        aa.blk1 = E.active ? at<int32_t>(ws, L.blk1) : nullptr;
+        YAcceptArgs aa1 = aa;
+        aa1.phase = 1;
         const int ya_blocks = yaccept_blocks(L.n, (int)L.kp);
 
         FinalizeArgs fa;
@@ -1219,6 +1408,7 @@ int glrm_fit(const glrm_data *d, float *X, float *Y, float *alpha_x, float *alph
             HIP_TRY(launch_ycheck(ca, (int)L.kp, tpw_y, prec, grid_y, st));
             HIP_TRY(timer.stop(st));
             HIP_TRY(timer.start(3, st));
+            if (E.active) HIP_TRY(launch_yaccept(aa1, (int)L.kp, prec, ya_blocks, st));
             HIP_TRY(launch_yaccept(aa, (int)L.kp, prec, ya_blocks, st));
             fa.sweep = t;
             HIP_TRY(launch_finalize(fa, st));

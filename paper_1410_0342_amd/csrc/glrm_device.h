@@ -17,7 +17,7 @@ typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) short i16x4;
 
-enum { L_QUAD = 0, L_HUBER = 1, L_LOGISTIC = 2, L_HINGE = 3, L_ORDINAL = 4 };
+enum { L_QUAD = 0, L_HUBER = 1, L_LOGISTIC = 2, L_HINGE = 3, L_ORDINAL = 4, L_CATEGORICAL = 5, L_MORDINAL = 6 };
 enum { R_ZERO = 0, R_QUAD = 1, R_L1 = 2, R_NONNEG = 3 };
 enum { P_FP32 = 0, P_BF16 = 1, P_FP64 = 2, P_BF16_PLAIN = 3 };
 

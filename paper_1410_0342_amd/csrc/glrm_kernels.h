@@ -79,9 +79,16 @@ struct YCheckArgs {
     int32_t ncb;            // column blocks per panel (workgroups b with b % ncb == c take block c)
 };
 
+// Block decisions (multi-dimensional losses, Section 6): the columns
+// blk0[j] .. blk1[j]-1 of a block share one decision on the sums of their
+// objectives.  They take two launches: phase 1 stores every column's trial
+// objective in hpc, phase 2 decides; phase 0 decides per column in one.
 struct YAcceptArgs {
     int64_t n, ldp;
     int32_t k, P;
+    int32_t phase;
+    float *hpc;
+    const int32_t *blk0, *blk1;
     const float *part_hp;
     const float *ry_plus, *h_old;
     float *alpha;
@@ -147,6 +154,17 @@ struct Obj64Args {
     double *part_obj;
 };
 
+// Columns of a table embedded for multi-dimensional losses (Section 6): packed
+// column j reads column emb_src[j] of A and, by emb_kind[j], copies the value
+// (EMB_COPY) or encodes +1 / -1 for value == emb_thr[j] (EMB_EQ, the
+// categorical one-vs-all columns) or value > emb_thr[j] (EMB_GT, the
+// multi-dimensional ordinal thresholds).
+enum { EMB_COPY = 0, EMB_EQ = 1, EMB_GT = 2 };
+struct EmbedMap {
+    const int32_t *src, *thr;   // null: no embedding (column j is column j of A)
+    const uint8_t *kind;
+};
+
 struct PackArgs {
     int64_t m, n, lda, mp, ldp;
     const float *A;
@@ -154,6 +172,7 @@ struct PackArgs {
     float *Ap;
     int32_t *row_count;     // m (zeroed by the kernel itself)
     int32_t *col_count;     // n (zeroed beforehand)
+    EmbedMap emb;
 };
 
 // ---- launchers (dense.hip) ----
@@ -180,6 +199,6 @@ hipError_t launch_prox(Reg r, float *V, int64_t rows, int32_t k, int64_t ldv, co
 hipError_t launch_regsum(Reg r, const float *V, int64_t rows, int32_t k, double *part, int blocks, hipStream_t st);
 hipError_t launch_sum_doubles(const double *a, int32_t na, const double *b, int32_t nb, double *out, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t len, int32_t v, hipStream_t st);
-hipError_t launch_pad_weights(const float *src, int64_t n, int64_t ldp, float *dst, hipStream_t st);
+hipError_t launch_pad_weights(const float *src, const int32_t *map, int64_t n, int64_t ldp, float *dst, hipStream_t st);
 
 }  // namespace glrm

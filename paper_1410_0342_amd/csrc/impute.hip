@@ -231,6 +231,72 @@ hipError_t launch_impute(const ImputeArgs &a, const float *X, const float *Y, co
     return launch_rank(a, X, Y, A, mask, out, st, std::make_integer_sequence<int, IMPUTE_MAX_K>{});
 }
 
+// ---- tables with multi-dimensional losses (Section 6) ------------------------
+// One thread per entry (i, j) of the table: u_l = x_i . (row fcol[j] + l of
+// Y), each a float32 fused multiply-add chain over the rank, and the value
+// that minimizes the feature's loss (Section 5.3):
+//   categorical   the label of the largest u_l (the first of equal ones): the
+//                 one-vs-all loss is the largest part of the sum minus a
+//                 strictly decreasing function of u_a, so its argmin is the argmax
+//   ordinal       the level a minimizing sum_{l < a-1} (1 - u_l)_+ +
+//                 sum_{l >= a-1} (1 + u_l)_+; from a to a + 1 the sum changes by
+//                 (1 - u_{a-1})_+ - (1 + u_{a-1})_+, so a running sum of those
+//                 steps ranks the levels (the first of equal minima)
+//   other kinds   the scalar rules of decode_entry
+__global__ __launch_bounds__(256) void impute_md_kernel(ImputeMDArgs a, const float *__restrict__ X,
+                                                        const float *__restrict__ Y, const float *__restrict__ A,
+                                                        const uint8_t *__restrict__ mask, float *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= a.m * a.nf) return;
+    const int64_t i = t / a.nf, j = t - i * a.nf;
+    if (a.keep_observed && mask[i * a.lda + j] != 0) {
+        out[i * a.ldh + j] = A[i * a.lda + j];
+        return;
+    }
+    const float *x = X + i * a.k;
+    const int kind = a.fkind[j], lev = a.flev[j];
+    const float *y0 = Y + (int64_t)a.fcol[j] * a.k;
+    auto dot = [&](int l) {
+        const float *y = y0 + (int64_t)l * a.k;
+        float u = 0.0f;
+        for (int c = 0; c < a.k; ++c) u = __builtin_fmaf(x[c], y[c], u);
+        return u;
+    };
+    float v;
+    if (kind == L_CATEGORICAL) {
+        int best = 0;
+        float bu = dot(0);
+        for (int l = 1; l < lev; ++l) {
+            const float u = dot(l);
+            if (u > bu) { bu = u; best = l; }
+        }
+        v = (float)(best + 1);
+    } else if (kind == L_MORDINAL) {
+        int best = 1;
+        float D = 0.0f, bD = 0.0f;
+        for (int l = 0; l < lev - 1; ++l) {
+            const float u = dot(l);
+            D += fmaxf(1.0f - u, 0.0f) - fmaxf(1.0f + u, 0.0f);
+            if (D < bD) { bD = D; best = l + 2; }
+        }
+        v = (float)best;
+    } else {
+        v = decode_entry(dot(0), kind, (float)lev);
+    }
+    out[i * a.ldh + j] = v;
+}
+
+hipError_t launch_impute_md(const ImputeMDArgs &a, const float *X, const float *Y, const float *A, const uint8_t *mask,
+                            float *out, hipStream_t st)
+{
+    const int64_t total = a.m * a.nf;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(impute_md_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, X, Y, A, mask,
+                       out);
+    return hipGetLastError();
+}
+
 hipError_t launch_scatter_observed(int64_t nnz, int64_t m, int64_t n, int64_t ldh, const int32_t *row,
                                    const int32_t *col, const float *val, float *out, hipStream_t st)
 {

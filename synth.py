@@ -8,7 +8,9 @@ Random streams: ``numpy.random.default_rng([14100342, config, stream])`` with
 stream 0 = hidden factors, 1 = noise / outliers / flips, 2 = observation
 pattern, 3 = starting point, 4 = sampled coordinates.
 
-Loss kinds: 0 quadratic, 1 Huber, 2 logistic, 3 hinge, 4 ordinal hinge.
+Loss kinds: 0 quadratic, 1 Huber, 2 logistic, 3 hinge, 4 ordinal hinge,
+5 categorical one-vs-all, 6 multi-dimensional ordinal (Section 6; a column
+under one of these owns levels resp. levels - 1 rows of Y0).
 Regularizer kinds: 0 zero, 1 quadratic, 2 l1, 3 nonnegative.
 """
 import os
@@ -19,7 +21,7 @@ import numpy as np
 
 SEED = 14100342
 
-QUAD, HUBER, LOGISTIC, HINGE, ORDINAL = 0, 1, 2, 3, 4
+QUAD, HUBER, LOGISTIC, HINGE, ORDINAL, CATEGORICAL, MORDINAL = 0, 1, 2, 3, 4, 5, 6
 RZERO, RQUAD, RL1, RNONNEG = 0, 1, 2, 3
 
 
@@ -241,6 +243,74 @@ def sparse_completion(m=2_000_000, n=20_000, k=32, density=0.01, noise=0.05, gam
                 np.zeros(n, np.uint8), [(QUAD, 0, 0.0)], (RQUAD, gamma), (RQUAD, gamma),
                 _normal32(g, (m, k)), _normal32(g, (n, k)), rows=rows, cols=cols, vals=vals,
                 sweeps=sweeps)
+
+
+# ---- a census-shaped table (Section 6.3) ----------------------------------------
+
+def _y_rows(kind, levels):
+    """Rows of Y a column takes (its embedding dimension)."""
+    return levels if kind == CATEGORICAL else (levels - 1 if kind == MORDINAL else 1)
+
+
+def census_like(m=3_132_796, k=10, missing=0.1, gamma=0.1, config=6, mordinal=False, offset=True):
+    """A stand-in for the survey table of the paper's heterogeneous example:
+    m responses to 21 questions of the four types its table lists (5 real, 9
+    Boolean, 3 ordinal, 4 categorical), fitted at rank 10 with Huber, hinge,
+    ordinal hinge and one-vs-all losses and gamma = 0.1.  The label and level
+    counts (categorical 8, 50, 4, 5; ordinal 12, 8, 7) are this generator's
+    choices.  Values come from a hidden rank-k Gaussian model: real columns
+    are the latent plus N(0, 0.1^2) noise with 5% Laplace(0, 10) outliers,
+    Boolean ones its sign with 5% flips, ordinal ones equal-width bins of the
+    standardized latent over [-3, 3], categorical ones the argmax over the
+    labels of latent scores plus Gumbel noise.  10% of entries are missing
+    uniformly.  With ``mordinal`` the ordinal columns take the
+    multi-dimensional ordinal loss instead.  With ``offset`` coordinate 0 of
+    X0 is 1 (Section 3.3)."""
+    kinds = ([(HUBER, 0)] * 5 + [(HINGE, 0)] * 9 + [(MORDINAL if mordinal else ORDINAL, lv) for lv in (12, 8, 7)]
+             + [(CATEGORICAL, lv) for lv in (8, 50, 4, 5)])
+    # interleave the types the way a survey mixes them (fixed order)
+    order = [15, 17, 0, 5, 6, 1, 2, 3, 4, 7, 8, 9, 14, 16, 18, 10, 11, 12, 19, 13, 20]
+    kinds = [kinds[i] for i in order]
+    n = len(kinds)
+    losses, col_loss = [], np.empty(n, np.uint8)
+    for j, (kd, lv) in enumerate(kinds):
+        entry = (kd, lv, 1.0 if kd == HUBER else 0.0)
+        if entry not in losses:
+            losses.append(entry)
+        col_loss[j] = losses.index(entry)
+    gf, gn = rng(config, 0), rng(config, 1)
+    Xt = gf.standard_normal((m, k)).astype(np.float32)
+    W = [gf.standard_normal((k, lv if kd == CATEGORICAL else 1)).astype(np.float32) / np.float32(np.sqrt(k))
+         for kd, lv in kinds]
+    A = np.empty((m, n), dtype=np.float32)
+    chunk = 1 << 16
+    edges = {lv: np.linspace(-3.0, 3.0, lv + 1)[1:-1].astype(np.float32) for kd, lv in kinds if kd in (ORDINAL, MORDINAL)}
+    for r0 in range(0, m, chunk):
+        r1 = min(m, r0 + chunk)
+        xt = Xt[r0:r1]
+        rr = r1 - r0
+        for j, (kd, lv) in enumerate(kinds):
+            z = xt @ W[j]
+            if kd == HUBER:
+                out = gn.random(rr, dtype=np.float32) < 0.05
+                A[r0:r1, j] = z[:, 0] + 0.1 * gn.standard_normal(rr, dtype=np.float32) + np.where(
+                    out, gn.laplace(0.0, 10.0, rr), 0.0).astype(np.float32)
+            elif kd == HINGE:
+                b = np.where(z[:, 0] >= 0, 1.0, -1.0).astype(np.float32)
+                A[r0:r1, j] = np.where(gn.random(rr, dtype=np.float32) < 0.05, -b, b)
+            elif kd in (ORDINAL, MORDINAL):
+                A[r0:r1, j] = (np.searchsorted(edges[lv], z[:, 0], side="right") + 1).astype(np.float32)
+            else:
+                A[r0:r1, j] = (np.argmax(z + gn.gumbel(size=z.shape).astype(np.float32), axis=1) + 1).astype(np.float32)
+    mask = _bernoulli_mask(rng(config, 2), m, n, 1.0 - missing)
+    d = sum(_y_rows(kd, lv) for kd, lv in kinds)
+    g = rng(config, 3)
+    X0 = _normal32(g, (m, k))
+    if offset:
+        X0[:, 0] = 1.0
+    return Case("census_like_%dx%d_k%d%s" % (m, n, k, "_mordinal" if mordinal else ""), m, n, k, "dense", col_loss,
+                losses, (RQUAD, gamma), (RQUAD, gamma), X0, _normal32(g, (d, k)), A=A, mask=mask,
+                notes=dict(d=d, offset=offset))
 
 
 # ---- small mixed cases for tests -----------------------------------------------

@@ -36,7 +36,7 @@ def rel_fro(a, b):
 #
 # The GPU forms its step x+ = prox(x - alpha g) from a gradient g that carries
 # rounding error (bound: grad_eps below).  A gradient coordinate is a sum of
-# terms G_ij y_jc; its error is bounded by the three sources listed below, in
+# terms G_ij y_jc; its error is bounded by the four sources listed below, in
 # units of the sum of their magnitudes S_c = sum_j |G_ij| |y_jc| (the oracle's
 # grad_abs) and of their root sum of squares R_c (grad_rss).  The prox
 # operators are nonexpansive, so each coordinate of the GPU's trial point lies
@@ -50,7 +50,7 @@ def rel_fro(a, b):
 
 GRAD_REL = {"fp32": 0.0, "bf16": 2.0 ** -8}
 SUM_REL = 1e-5
-# Three sources.  (1) The derivative operand: the BF16 form rounds every
+# Four sources.  (1) The derivative operand: the BF16 form rounds every
 # G_ij to bfloat16 (round to nearest even).  These errors are not independent:
 # a derivative that saturates (the logistic one near +-1)
 # piles up just below a power of two and always rounds the same way.  So
@@ -61,12 +61,22 @@ SUM_REL = 1e-5
 # uniform within half a unit, 2^-8 relative at most: the sum's standard
 # deviation is at most 2^-8 / sqrt(3) of the root of the squared terms R_c,
 # and 2^-6 R_c is about seven of them; the smaller bound is taken.  FP32
-# products are exact to 2^-24, below (3).  (3) The float32 accumulation: the
+# products are exact to 2^-24, below (3).  (3) The float32 accumulation: a sum
+# of N terms added in sequence errs by at most (N - 1) 2^-24 of S_c, and the
 # kernels add runs of at most about 2^10 terms in sequence (a workgroup's rows
 # or a wavefront's chunk) before fixed-order reductions of the partials, so
-# the accumulated error stays below 2^10 2^-24 = 2^-14 of S_c.
+# the accumulated error stays below min(N, 2^10) 2^-24 of S_c, N the row's
+# (column's) observed count; a float32 product's own rounding adds 2^-24.
+# (4) The rounding of z = x . y itself, |z_gpu - z| <= z_rel sum_c |x_c||y_c|
+# (FP32: k float32 products and their sum, (k + 1) 2^-24; BF16: three
+# bfloat16 products per coordinate, whose dropped lo*lo term and rounded lo
+# parts leave about 3 2^-18, and the float32 sums, under 2^-14 in all).  A smooth loss passes it on to G scaled by its curvature
+# (quadratic 2, Huber 1, logistic 1/4); a kinked loss (hinge, ordinal hinge)
+# passes nothing on, except where a kink lies within that distance of z: there
+# the derivative may take either side, a step of 1 per term that kinks there.
 RSS_REL = {"fp32": None, "bf16": 2.0 ** -6}
-ACC_REL = 2.0 ** -14
+ACC_RUN = 2 ** 10
+CURVATURE = {0: 2.0, 1: 1.0, 2: 0.25, 3: 0.0, 4: 0.0}
 
 
 def bf16_round(a):
@@ -74,6 +84,52 @@ def bf16_round(a):
     b = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
     r = ((b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
     return r.view(np.float32).astype(np.float64)
+
+
+def acc_rel(P, which):
+    """Source (3) per row (which = "x") or column: (min(N, 2^10) + 1) 2^-24."""
+    a = P.init_alpha(1.0)[0 if which == "x" else 1]      # 1 / max(N, 1)
+    return (np.minimum(np.rint(1.0 / a), ACC_RUN) + 1.0) * 2.0 ** -24
+
+
+def _kink_steps(kind, levels, a, u, dz):
+    """Size of the derivative's jumps within dz of u (0 where there are none)."""
+    out = np.zeros_like(u)
+    h = kind == 3                                   # hinge: kink at u = a (a = +-1)
+    out[h] = (np.abs(u[h] - a[h]) <= dz[h]).astype(np.float64)
+    o = kind == 4                                   # ordinal hinge: kinks at 2..a and a..levels-1
+    if o.any():
+        uo, ao, lo, do = u[o], a[o], levels[o].astype(np.float64), dz[o]
+        t = np.clip(np.rint(uo), 1.0, lo)           # the nearest integer in range
+        is_kink = ((t >= 2) & (t <= ao)) | ((t >= ao) & (t <= lo - 1))
+        steps = np.where((t == ao) & (ao >= 2) & (ao <= lo - 1), 2.0, 1.0)
+        out[o] = np.where(is_kink & (np.abs(uo - t) <= do), steps, 0.0)
+    return out
+
+
+def z_terms(P, which, X, Y, prec):
+    """Source (4) per coordinate: sum over the row's (column's) observed
+    entries of w (curvature dz + kink steps) |v_c|."""
+    view = P.row if which == "x" else P.colv
+    U, V = (np.asarray(X, np.float64), np.asarray(Y, np.float64))
+    if which != "x":
+        U, V = V, U
+    rows = np.repeat(np.arange(view.m), np.diff(view.row_ptr))
+    other = view.col.astype(np.int64)
+    Ur, Vo = U[rows], V[other]
+    u = np.einsum("ij,ij->i", Ur, Vo)
+    z_rel = (U.shape[1] + 1) * 2.0 ** -24 if prec == "fp32" else 2.0 ** -14
+    dz = z_rel * np.einsum("ij,ij->i", np.abs(Ur), np.abs(Vo))
+    kinds = np.array([l[0] for l in P.losses], np.int64)[view.ecode]
+    levels = np.array([l[1] for l in P.losses], np.int64)[view.ecode]
+    curv = np.array([CURVATURE[int(l[0])] for l in P.losses])[view.ecode]
+    term = curv * dz + _kink_steps(kinds, levels, view.val, u, dz)
+    if view.ew is not None:
+        term = term * view.ew
+    out = np.zeros((view.m, U.shape[1]))
+    for c in range(U.shape[1]):
+        out[:, c] = np.bincount(rows, weights=term * np.abs(Vo[:, c]), minlength=view.m)
+    return out
 
 
 def grad_eps(P, which, X, Y, alpha, prec):
@@ -87,7 +143,8 @@ def grad_eps(P, which, X, Y, alpha, prec):
         dG = bf16_round(G) - G
         X64, Y64 = np.asarray(X, np.float64), np.asarray(Y, np.float64)
         bound = bound + np.abs(dG @ Y64 if which == "x" else dG.T @ X64)
-    return 2.0 * np.asarray(alpha, np.float64)[:, None] * (bound + ACC_REL * S)
+    bound = bound + acc_rel(P, which)[:, None] * S + z_terms(P, which, X, Y, prec)
+    return 2.0 * np.asarray(alpha, np.float64)[:, None] * bound
 
 
 def _reg_slope(reg, V, offset=0):
@@ -178,22 +235,46 @@ def _check_half(P, which, U0, V, alpha0, Ugpu, alpha_gpu, prec, step_up=1.05, st
     trial = _trial(reg, U0, g, alpha0, off)
     # the float32 rounding of x - alpha g and of the prox adds 2^-22 of |x| + |x+|
     eps = grad_eps(P, which, X0, Y0, alpha0, prec) + 2.0 ** -22 * (np.abs(trial) + np.abs(U0)) + 1e-30
+    return compare_half(tag, "rows" if which == "x" else "columns", U0, Ugpu, alpha0, alpha_gpu, acc_o, f_old, f_new,
+                        band, trial, eps, step_up, step_down)
+
+
+def compare_half(tag, what, U0, Ugpu, alpha0, alpha_gpu, acc_o, f_old, f_new, band, trial, eps, step_up=1.05,
+                 step_down=0.7, blocks=None):
+    """The checks of one half-step, given the oracle's outcome: decisions
+    (read from the GPU's step sizes) equal wherever the oracle's margin
+    clears the band; rejected rows bit-for-bit unchanged; accepted rows within
+    eps of the oracle's trial point.  With ``blocks`` (the first row of each
+    block, then the end) the rows move in blocks: acc_o, f_old, f_new and band
+    are per block, and every row of a block must take the block's decision.
+    Returns (decisions inside the band, of them taken the other way, GPU
+    decisions)."""
+    U0 = np.asarray(U0, np.float64)
+    alpha0 = np.asarray(alpha0, np.float64)
     Ugpu = np.asarray(Ugpu, np.float32)
     alpha_gpu = np.asarray(alpha_gpu, np.float64)
     ratio = alpha_gpu / np.maximum(alpha0, 1e-300)
     acc_g = np.abs(ratio - step_up) <= 1e-6 * step_up
     rej_g = np.abs(ratio - step_down) <= 1e-6 * step_down
     assert np.all(acc_g | rej_g), "%s: step sizes moved by neither factor" % tag
+    acc_r = acc_g
+    if blocks is not None:
+        blocks = np.asarray(blocks)
+        sizes = np.diff(blocks)
+        cnt = np.add.reduceat(acc_g.astype(np.int64), blocks[:-1])
+        assert np.all((cnt == 0) | (cnt == sizes)), "%s: a block's columns took different decisions" % tag
+        acc_g = cnt == sizes
     clear = clear_decisions(f_old, f_new, band)
-    acc_o = acc_o.astype(bool)
+    acc_o = np.asarray(acc_o).astype(bool)
     bad = np.nonzero(clear & (acc_g != acc_o))[0]
     assert bad.size == 0, "%s: decisions differ on clear %s %s (margin %s, band %s)" % (
-        tag, "rows" if which == "x" else "columns", bad[:8], (f_new - f_old)[bad[:8]], band[bad[:8]])
+        tag, what, bad[:8], (np.asarray(f_new) - np.asarray(f_old))[bad[:8]], np.asarray(band)[bad[:8]])
     U0_32 = U0.astype(np.float32)
-    assert np.array_equal(Ugpu[rej_g], U0_32[rej_g]), "%s: a rejected row changed" % tag
-    if acc_g.any():
-        diff = np.abs(Ugpu[acc_g].astype(np.float64) - trial[acc_g])
-        worst = np.max(diff / eps[acc_g])
+    rej_r = ~acc_r
+    assert np.array_equal(Ugpu[rej_r], U0_32[rej_r]), "%s: a rejected row changed" % tag
+    if acc_r.any():
+        diff = np.abs(Ugpu[acc_r].astype(np.float64) - trial[acc_r])
+        worst = np.max(diff / eps[acc_r])
         assert worst <= 1.0, "%s: accepted trial point off by %.3g of its rounding bound" % (tag, worst)
     return int((~clear).sum()), int((~clear & (acc_g != acc_o)).sum()), acc_g
 

