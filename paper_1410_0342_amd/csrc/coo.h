@@ -30,6 +30,16 @@ struct CooLayout {
     size_t part = 0, part_bytes = 0;  // double partials of the objective
     size_t xs = 0;         // padded copy of X (m x kp, fp32), updated in place by the row walk
     size_t ys = 0;         // padded copy of Y (n x kp, fp32), updated in place by the column walk
+    // Row-blocked column-grouped copy for the column step: entries ordered by
+    // (row block, column, row), rows in blocks of 2^rb_shift, with segment
+    // pointers per (row block, column).  blk = false: not built (too many
+    // segments or columns for it); the column step then walks whole columns.
+    bool blk = false;
+    int rb_shift = 0;
+    int64_t nb = 0;        // row blocks
+    size_t bkey = 0, bperm = 0, brow = 0, bval = 0, seg = 0;
+    size_t bpart0 = 0, bpart1 = 0;     // per-XCD partials of the two column passes
+    size_t yplus = 0, hold = 0, rplus = 0;
 };
 
 // The parts of the COO region other passes read: the row pointers, the

@@ -25,6 +25,31 @@ namespace glrm {
 
 constexpr int CW = 4;              // wavefronts per workgroup
 constexpr int COO_MAX_WAVES = 8192;
+// The row-blocked column step: NX partial sets (one per XCD: workgroup w
+// runs on XCD w mod 8 and takes the row blocks rb = w mod 8 (mod 8)), each
+// wave owning at most CB_JW(kp) columns, CB_GMIN..CB_GMAX workgroups per XCD,
+// and row blocks of about 1 MB of the padded float32 X.
+constexpr int NX = 8;
+#ifndef GLRM_CB_NS
+#define GLRM_CB_NS 4
+#endif
+#ifndef GLRM_CB_GMIN
+#define GLRM_CB_GMIN 128
+#endif
+constexpr int CB_NS = GLRM_CB_NS;
+constexpr int CB_GMIN = GLRM_CB_GMIN, CB_GMAX = 256;
+constexpr int64_t CB_MAX_SEGMENTS = int64_t(1) << 28;
+static int cb_jw_max(int kp) { return kp == 64 ? 32 : 64; }
+#ifndef GLRM_CB_RB_ADJ
+#define GLRM_CB_RB_ADJ 0
+#endif
+static int cb_rb_shift(int kp) { return (kp == 16 ? 14 : (kp == 32 ? 13 : 12)) - GLRM_CB_RB_ADJ; }
+static int bits_for(int64_t v)
+{
+    int b = 1;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
 
 static int64_t rup(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -43,12 +68,34 @@ void coo_layout(const glrm_data *d, int kp, CooLayout &cl)
     cl.perm_out = take(sizeof(int32_t) * nnz);
     cl.keys_out = take(sizeof(int32_t) * nnz);
     size_t tb = 0;
-    int bits = 1;
-    while ((int64_t(1) << bits) < d->n) ++bits;
     hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const int *)nullptr, (int *)nullptr, (const int *)nullptr,
-                                       (int *)nullptr, (int)nnz, 0, bits, (hipStream_t)0);
+                                       (int *)nullptr, (int)nnz, 0, bits_for(d->n), (hipStream_t)0);
+    // the row-blocked copy
+    cl.rb_shift = cb_rb_shift(kp);
+    cl.nb = (d->m + (int64_t(1) << cl.rb_shift) - 1) >> cl.rb_shift;
+    const int64_t nseg = cl.nb * d->n;
+    // packed entries: column in 16 bits
+    cl.blk = d->nnz > 0 && nseg < CB_MAX_SEGMENTS && d->n <= std::min<int64_t>(65536, (int64_t)cb_jw_max(kp) * CW * CB_GMAX);
+    if (cl.blk) {
+        size_t tb2 = 0;
+        hipcub::DeviceRadixSort::SortPairs(nullptr, tb2, (const int *)nullptr, (int *)nullptr, (const int *)nullptr,
+                                           (int *)nullptr, (int)nnz, 0, bits_for(nseg), (hipStream_t)0);
+        tb = std::max(tb, tb2);
+    }
     cl.sort_tmp_bytes = tb;
     cl.sort_tmp = take(tb);
+    if (cl.blk) {
+        cl.bkey = take(sizeof(int32_t) * nnz);
+        cl.bperm = take(sizeof(int32_t) * nnz);
+        cl.brow = take(sizeof(int32_t) * nnz);
+        cl.bval = take(sizeof(float) * nnz);
+        cl.seg = take(sizeof(int32_t) * (nseg + 1));
+        cl.bpart0 = take(sizeof(float) * NX * d->n * (kp + 1));
+        cl.bpart1 = take(sizeof(float) * NX * d->n);
+        cl.yplus = take(sizeof(float) * d->n * kp);
+        cl.hold = take(sizeof(float) * d->n);
+        cl.rplus = take(sizeof(float) * d->n);
+    }
     cl.flags = take(sizeof(int32_t) * 4);
     cl.part_bytes = (sizeof(double) * 2 + sizeof(int32_t) * 2) * COO_MAX_WAVES;
     cl.part = take(cl.part_bytes);
@@ -59,6 +106,8 @@ void coo_layout(const glrm_data *d, int kp, CooLayout &cl)
 struct CooPtrs {
     int32_t *row_ptr, *col_ptr, *csc_row, *perm_in, *perm_out, *keys_out, *flags;
     float *csc_val, *xs, *ys;
+    int32_t *bkey, *bperm, *brow, *seg;
+    float *bval, *bpart0, *bpart1, *yplus, *hold, *rplus;
     double *partA, *partB;
     int32_t *ipartA, *ipartB;
     void *sort_tmp;
@@ -83,6 +132,16 @@ static CooPtrs ptrs(const CooLayout &cl, char *b)
     p.ipartB = p.ipartA + COO_MAX_WAVES;
     p.xs = (float *)(b + cl.xs);
     p.ys = (float *)(b + cl.ys);
+    p.bkey = (int32_t *)(b + cl.bkey);
+    p.bperm = (int32_t *)(b + cl.bperm);
+    p.brow = (int32_t *)(b + cl.brow);
+    p.bval = (float *)(b + cl.bval);
+    p.seg = (int32_t *)(b + cl.seg);
+    p.bpart0 = (float *)(b + cl.bpart0);
+    p.bpart1 = (float *)(b + cl.bpart1);
+    p.yplus = (float *)(b + cl.yplus);
+    p.hold = (float *)(b + cl.hold);
+    p.rplus = (float *)(b + cl.rplus);
     return p;
 }
 
@@ -152,6 +211,25 @@ __global__ void gather_csc_kernel(const int32_t *perm, const int32_t *row, const
     }
 }
 
+// The row-blocked copy: value and packed (column << 16 | row within its block).
+__global__ void gather_blk_kernel(const int32_t *perm, const int32_t *row, const int32_t *col, const float *val,
+                                  int64_t nnz, int shift, uint32_t *packed, float *bval)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < nnz) {
+        const int32_t e = perm[p];
+        packed[p] = ((uint32_t)col[e] << 16) | ((uint32_t)row[e] & ((1u << shift) - 1));
+        bval[p] = val[e];
+    }
+}
+
+// Key of an entry in the row-blocked order: (row block, column).
+__global__ void blk_key_kernel(const int32_t *row, const int32_t *col, int64_t nnz, int64_t n, int shift, int32_t *key)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < nnz) key[e] = (int32_t)((int64_t)(row[e] >> shift) * n + col[e]);
+}
+
 // Padded copy of a factor: dst (rows x kp) from src (rows x k).
 __global__ void pad_factor_kernel(const float *src, int64_t rows, int32_t k, int32_t kp, float *dst)
 {
@@ -189,6 +267,20 @@ int coo_prepare(const glrm_data *d, int kp, const CooLayout &cl, char *base, int
     }
     hipLaunchKernelGGL(seg_ptr_kernel, dim3(nblk(n + 1)), dim3(256), 0, st, p.keys_out, nnz, n, p.col_ptr);
     hipLaunchKernelGGL(seg_count_kernel, dim3(nblk(n)), dim3(256), 0, st, p.col_ptr, n, col_count);
+    if (cl.blk) {
+        // (row block, column) keys of the row-sorted list; a stable sort keeps
+        // each segment's rows in order
+        const int64_t nseg = cl.nb * n;
+        hipLaunchKernelGGL(blk_key_kernel, dim3(nblk(nnz)), dim3(256), 0, st, d->row, d->col, nnz, n, cl.rb_shift,
+                           p.bkey);
+        size_t tb = cl.sort_tmp_bytes;
+        e = hipcub::DeviceRadixSort::SortPairs(p.sort_tmp, tb, p.bkey, p.keys_out, p.perm_in, p.bperm, (int)nnz, 0,
+                                               bits_for(nseg), st);
+        if (e != hipSuccess) return set_error(GLRM_EHIP, "radix sort (row blocks): %s", hipGetErrorString(e));
+        hipLaunchKernelGGL(gather_blk_kernel, dim3(nblk(nnz)), dim3(256), 0, st, p.bperm, d->row, d->col, d->A, nnz,
+                           cl.rb_shift, reinterpret_cast<uint32_t *>(p.brow), p.bval);
+        hipLaunchKernelGGL(seg_ptr_kernel, dim3(nblk(nseg + 1)), dim3(256), 0, st, p.keys_out, nnz, nseg, p.seg);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return set_error(GLRM_EHIP, "COO set-up launch: %s", hipGetErrorString(e));
     return GLRM_OK;
 }
@@ -240,6 +332,65 @@ __device__ __forceinline__ float dot4(const float4 &a, const float4 &b)
     return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
 }
 
+// A lane's C consecutive coordinates of a factor row (C = 4 or 8).
+template <int C>
+struct Part {
+    float4 v[C / 4];
+};
+
+template <int KP, int C>
+__device__ __forceinline__ Part<C> load_part(const float4 *__restrict__ F4, int64_t row, int q)
+{
+    Part<C> r;
+#pragma unroll
+    for (int u = 0; u < C / 4; ++u) r.v[u] = F4[row * (KP / 4) + q * (C / 4) + u];
+    return r;
+}
+
+template <int C>
+__device__ __forceinline__ float dot_part(const Part<C> &a, const Part<C> &b)
+{
+    float s = dot4(a.v[0], b.v[0]);
+#pragma unroll
+    for (int u = 1; u < C / 4; ++u) s += dot4(a.v[u], b.v[u]);
+    return s;
+}
+
+template <int C>
+__device__ __forceinline__ void axpy_part(Part<C> &acc, float g, const Part<C> &x)
+{
+#pragma unroll
+    for (int u = 0; u < C / 4; ++u) {
+        acc.v[u].x += g * x.v[u].x; acc.v[u].y += g * x.v[u].y;
+        acc.v[u].z += g * x.v[u].z; acc.v[u].w += g * x.v[u].w;
+    }
+}
+
+// Coordinates per lane in the row-blocked column passes: 8 (groups of KP / 8
+// lanes per entry, fewer lanes repeating the loss and the butterfly), 4 at
+// KP = 16.
+template <int KP>
+constexpr int cb_c() { return KP == 16 ? 4 : 8; }
+
+// Indices and values of the chunk at b of a segment [first, end): entries
+// b + s E + slot for the steps s the chunk has (a uniform early exit; the
+// caller runs exactly as many).  An entry past the segment's end repeats the
+// segment's first one, so every load and gather stays in bounds, and the
+// caller masks it out.
+template <int NS, int E, typename T>
+__device__ __forceinline__ void chunk_load(const T *__restrict__ idx, const float *__restrict__ val, int32_t b,
+                                           int32_t end, int32_t first, int slot, T (&i)[NS], float (&v)[NS])
+{
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (b + s * E >= end) break;
+        const int32_t e = b + s * E + slot;
+        const int32_t ee = e < end ? e : first;
+        i[s] = idx[ee];
+        v[s] = val[ee];
+    }
+}
+
 struct WalkArgs {
     int64_t rows;            // rows of the walked view (m for the row walk, n for the column walk)
     int32_t k;
@@ -265,15 +416,15 @@ struct WalkArgs {
 // loss kind LK (compile time); LK < 0: the code of the entry's column.
 // wcol: the entry's column of A (its loss weight, when the table has weights).
 template <int LK>
-__device__ __forceinline__ void walk_lg(const WalkArgs &a, int code, int wcol, float z, float v, float &l, float &g)
+__device__ __forceinline__ void walk_lg(const LossTab &lt, int code, int wcol, float z, float v, float &l, float &g)
 {
     if constexpr (LK >= 0) {
-        loss_lg_k<LK>(a.lt.levels[0], a.lt.param[0], z, v, l, g);
+        loss_lg_k<LK>(lt.levels[0], lt.param[0], z, v, l, g);
     } else {
-        const int q = a.lt.uniform >= 0 ? a.lt.uniform : code;
-        loss_lg(a.lt.kind[q], a.lt.levels[q], a.lt.param[q], z, v, l, g);
-        if (a.lt.colw) {
-            const float w = a.lt.colw[wcol];
+        const int q = lt.uniform >= 0 ? lt.uniform : code;
+        loss_lg(lt.kind[q], lt.levels[q], lt.param[q], z, v, l, g);
+        if (lt.colw) {
+            const float w = lt.colw[wcol];
             l *= w;
             g *= w;
         }
@@ -281,27 +432,29 @@ __device__ __forceinline__ void walk_lg(const WalkArgs &a, int code, int wcol, f
 }
 
 template <int LK>
-__device__ __forceinline__ float walk_l(const WalkArgs &a, int code, int wcol, float z, float v)
+__device__ __forceinline__ float walk_l(const LossTab &lt, int code, int wcol, float z, float v)
 {
     if constexpr (LK >= 0) {
-        return loss_l_k<LK>(a.lt.levels[0], a.lt.param[0], z, v);
+        return loss_l_k<LK>(lt.levels[0], lt.param[0], z, v);
     } else {
-        const int q = a.lt.uniform >= 0 ? a.lt.uniform : code;
-        const float l = loss_l(a.lt.kind[q], a.lt.levels[q], a.lt.param[q], z, v);
-        return a.lt.colw ? l * a.lt.colw[wcol] : l;
+        const int q = lt.uniform >= 0 ? lt.uniform : code;
+        const float l = loss_l(lt.kind[q], lt.levels[q], lt.param[q], z, v);
+        return lt.colw ? l * lt.colw[wcol] : l;
     }
 }
 
 // MODE 0: loss (+ gradient if dU); MODE 1: full half-step; MODE 2: loss in double.
-// The walk goes through a row's entries in chunks of NS * E: every lane first
-// loads the indices and values of its NS entries, then issues their NS factor
-// gathers, and only then reduces, so each chunk costs two memory round trips.
+// A wave owns one row at a time; groups of L = KP / C lanes share an entry,
+// each lane holding C coordinates, so a factor row is one coalesced gather
+// and z = x_i . y_j a short butterfly over the group.  The walk goes through
+// a row's entries in chunks of up to NS steps of E entries: every lane first
+// loads the indices and values of its entries, then issues their factor
+// gathers, and only then reduces (a row's last chunk runs only the steps it
+// has; entries past the row's end repeat its first entry and are masked).
 template <int KP, int MODE, int LK>
 __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
 {
-    constexpr int L = KP / 4;       // lanes per entry
-    constexpr int E = 64 / L;       // entries per wavefront step
-    constexpr int NS = 8;           // steps per chunk
+    constexpr int C = cb_c<KP>(), L = KP / C, E = 64 / L, NS = CB_NS;
     const int lane = threadIdx.x & 63;
     const int slot = lane / L, q = lane % L;
     const int64_t wave = (int64_t)blockIdx.x * CW + (threadIdx.x >> 6);
@@ -309,32 +462,35 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
     double wsum = 0.0;
     int wrej = 0;
     const float4 *V4 = reinterpret_cast<const float4 *>(a.Vs);
+    const float4 *U4 = reinterpret_cast<const float4 *>(a.Us);
+    auto code_of = [&](int32_t j, int rowcode) { return a.codes_by_entry ? (int)a.codes[j] : rowcode; };
     for (int64_t i = wave; i < a.rows; i += nwaves) {
         const int32_t beg = a.ptr[i], end = a.ptr[i + 1];
-        const float4 x = reinterpret_cast<const float4 *>(a.Us + i * KP)[q];
+        const Part<C> x = load_part<KP, C>(U4, i, q);
         const int rowcode = a.codes_by_entry ? 0 : a.codes[i];
         if constexpr (MODE == 2) {
             double acc = 0.0;
             for (int32_t b = beg; b < end; b += NS * E) {
                 int32_t j[NS];
                 float v[NS];
-                float4 y[NS];
+                Part<C> y[NS];
+                chunk_load<NS, E>(a.idx, a.val, b, end, beg, slot, j, v);
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    const int32_t e = b + s * E + slot;
-                    j[s] = e < end ? a.idx[e] : -1;
-                    v[s] = e < end ? a.val[e] : 0.0f;
+                    if (b + s * E >= end) break;
+                    y[s] = load_part<KP, C>(V4, j[s], q);
                 }
 #pragma unroll
-                for (int s = 0; s < NS; ++s) y[s] = j[s] >= 0 ? V4[(int64_t)j[s] * L + q] : float4{0, 0, 0, 0};
-#pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    double z = (double)x.x * y[s].x + (double)x.y * y[s].y + (double)x.z * y[s].z +
-                               (double)x.w * y[s].w;
+                    if (b + s * E >= end) break;
+                    double z = 0.0;
+#pragma unroll
+                    for (int u = 0; u < C / 4; ++u)
+                        z += (double)x.v[u].x * y[s].v[u].x + (double)x.v[u].y * y[s].v[u].y +
+                             (double)x.v[u].z * y[s].v[u].z + (double)x.v[u].w * y[s].v[u].w;
                     z = group_sum64<L>(z);
-                    if (j[s] >= 0 && q == 0) {
-                        const int code = a.codes_by_entry ? a.codes[j[s]] : rowcode;
-                        const int qq = a.lt.uniform >= 0 ? a.lt.uniform : code;
+                    if (b + s * E + slot < end && q == 0) {
+                        const int qq = a.lt.uniform >= 0 ? a.lt.uniform : code_of(j[s], rowcode);
                         const double wv = a.lt.colw ? (double)a.lt.colw[a.codes_by_entry ? j[s] : (int)i] : 1.0;
                         acc += wv * loss_l64(a.lt.kind[qq], a.lt.levels[qq], (double)a.lt.param[qq], z, (double)v[s]);
                     }
@@ -344,88 +500,104 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
             continue;
         }
         float f = 0.0f;
-        float4 gacc = {0.f, 0.f, 0.f, 0.f};
+        Part<C> gacc = {};
         for (int32_t b = beg; b < end; b += NS * E) {
             int32_t j[NS];
             float v[NS];
-            float4 y[NS];
+            Part<C> y[NS];
+            chunk_load<NS, E>(a.idx, a.val, b, end, beg, slot, j, v);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const int32_t e = b + s * E + slot;
-                j[s] = e < end ? a.idx[e] : -1;
-                v[s] = e < end ? a.val[e] : 0.0f;
+                if (b + s * E >= end) break;
+                y[s] = load_part<KP, C>(V4, j[s], q);
             }
 #pragma unroll
-            for (int s = 0; s < NS; ++s) y[s] = j[s] >= 0 ? V4[(int64_t)j[s] * L + q] : float4{0, 0, 0, 0};
-#pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const float z = group_sum<L>(dot4(x, y[s]));
-                float l = 0.f, gr = 0.f;
-                if (j[s] >= 0)
-                    walk_lg<LK>(a, a.codes_by_entry ? a.codes[j[s]] : rowcode, a.codes_by_entry ? j[s] : (int)i, z,
-                                v[s], l, gr);
-                if (q == 0) f += l;
-                gacc.x += gr * y[s].x; gacc.y += gr * y[s].y; gacc.z += gr * y[s].z; gacc.w += gr * y[s].w;
+                if (b + s * E >= end) break;
+                const bool ok = b + s * E + slot < end;
+                const float z = group_sum<L>(dot_part<C>(x, y[s]));
+                float l, gr;
+                walk_lg<LK>(a.lt, code_of(j[s], rowcode), a.codes_by_entry ? j[s] : (int)i, z, v[s], l, gr);
+                f += (ok && q == 0) ? l : 0.0f;
+                axpy_part<C>(gacc, ok ? gr : 0.0f, y[s]);
             }
         }
-        gacc.x = across_groups<L>(gacc.x);
-        gacc.y = across_groups<L>(gacc.y);
-        gacc.z = across_groups<L>(gacc.z);
-        gacc.w = across_groups<L>(gacc.w);
+#pragma unroll
+        for (int u = 0; u < C / 4; ++u) {
+            gacc.v[u].x = across_groups<L>(gacc.v[u].x);
+            gacc.v[u].y = across_groups<L>(gacc.v[u].y);
+            gacc.v[u].z = across_groups<L>(gacc.v[u].z);
+            gacc.v[u].w = across_groups<L>(gacc.v[u].w);
+        }
         f = across_groups<L>(group_sum<L>(f));   // only q == 0 lanes were nonzero
         if constexpr (MODE == 0) {
             wsum += (double)f;
             if (a.dU && slot == 0) {
-                const float gv[4] = {gacc.x, gacc.y, gacc.z, gacc.w};
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    if (4 * q + s < a.k) a.dU[i * a.k + 4 * q + s] = gv[s];
+                for (int u = 0; u < C / 4; ++u) {
+                    const float gv[4] = {gacc.v[u].x, gacc.v[u].y, gacc.v[u].z, gacc.v[u].w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int c = C * q + 4 * u + t;
+                        if (c < a.k) a.dU[i * a.k + c] = gv[t];
+                    }
+                }
             }
         } else {
             const float al = a.alpha[i];
-            const float xv[4] = {x.x, x.y, x.z, x.w};
-            const float gv[4] = {gacc.x, gacc.y, gacc.z, gacc.w};
-            float xp[4];
+            Part<C> xp;
             float rc = 0.f, rcp = 0.f;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const bool in = 4 * q + s < a.k;
-                xp[s] = in ? prox_elem(a.reg, al, xv[s] - al * gv[s], 4 * q + s) : 0.0f;
-                rc += in ? reg_elem(a.reg, xv[s], 4 * q + s) : 0.0f;
-                rcp += in ? reg_elem_trial(a.reg, xp[s], 4 * q + s) : 0.0f;
+            for (int u = 0; u < C / 4; ++u) {
+                const float xv[4] = {x.v[u].x, x.v[u].y, x.v[u].z, x.v[u].w};
+                const float gv[4] = {gacc.v[u].x, gacc.v[u].y, gacc.v[u].z, gacc.v[u].w};
+                float pv[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int c = C * q + 4 * u + t;
+                    const bool in = c < a.k;
+                    pv[t] = in ? prox_elem(a.reg, al, xv[t] - al * gv[t], c) : 0.0f;
+                    rc += in ? reg_elem(a.reg, xv[t], c) : 0.0f;
+                    rcp += in ? reg_elem_trial(a.reg, pv[t], c) : 0.0f;
+                }
+                xp.v[u] = float4{pv[0], pv[1], pv[2], pv[3]};
             }
             rc = group_sum<L>(rc);
             rcp = group_sum<L>(rcp);
-            const float4 xp4 = {xp[0], xp[1], xp[2], xp[3]};
             float fp = 0.0f;
             for (int32_t b = beg; b < end; b += NS * E) {
                 int32_t j[NS];
                 float v[NS];
-                float4 y[NS];
+                Part<C> y[NS];
+                chunk_load<NS, E>(a.idx, a.val, b, end, beg, slot, j, v);
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    const int32_t e = b + s * E + slot;
-                    j[s] = e < end ? a.idx[e] : -1;
-                    v[s] = e < end ? a.val[e] : 0.0f;
+                    if (b + s * E >= end) break;
+                    y[s] = load_part<KP, C>(V4, j[s], q);
                 }
 #pragma unroll
-                for (int s = 0; s < NS; ++s) y[s] = j[s] >= 0 ? V4[(int64_t)j[s] * L + q] : float4{0, 0, 0, 0};
-#pragma unroll
                 for (int s = 0; s < NS; ++s) {
-                    const float z = group_sum<L>(dot4(xp4, y[s]));
-                    if (j[s] >= 0 && q == 0)
-                        fp += walk_l<LK>(a, a.codes_by_entry ? a.codes[j[s]] : rowcode, a.codes_by_entry ? j[s] : (int)i,
-                                         z, v[s]);
+                    if (b + s * E >= end) break;
+                    const bool ok = b + s * E + slot < end;
+                    const float z = group_sum<L>(dot_part<C>(xp, y[s]));
+                    const float l = walk_l<LK>(a.lt, code_of(j[s], rowcode), a.codes_by_entry ? j[s] : (int)i, z, v[s]);
+                    fp += (ok && q == 0) ? l : 0.0f;
                 }
             }
             fp = across_groups<L>(group_sum<L>(fp));
             const float F0 = f + rc, F1 = fp + rcp;
             const bool acc = F1 <= F0;
             if (acc && slot == 0) {
-                reinterpret_cast<float4 *>(a.Us + i * KP)[q] = xp4;
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    if (4 * q + s < a.k) a.U[i * a.k + 4 * q + s] = xp[s];
+                for (int u = 0; u < C / 4; ++u) {
+                    reinterpret_cast<float4 *>(a.Us + i * KP)[q * (C / 4) + u] = xp.v[u];
+                    const float pv[4] = {xp.v[u].x, xp.v[u].y, xp.v[u].z, xp.v[u].w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int c = C * q + 4 * u + t;
+                        if (c < a.k) a.U[i * a.k + c] = pv[t];
+                    }
+                }
             }
             if (lane == 0) {
                 a.alpha[i] = acc ? al * a.step_up : al * a.step_down;
@@ -471,6 +643,275 @@ __global__ __launch_bounds__(256) void coo_finalize_kernel(const double *colF, c
         istats[0] = sr[0];
         istats[1] = sc[0];
         if (history) history[sweep] = sF[0];
+    }
+}
+
+// ---- the column step on the row-blocked copy ----------------------------------
+//
+// A column's entries sit in segments, one per row block.  The workgroups of
+// one XCD take that XCD's row blocks in order and, within a block, every
+// wave the segments of its own columns, so all waves of an XCD gather x_i
+// from the same ~1 MB block of X at about the same time: the gathers hit the
+// XCD's L2 instead of going out to memory.  A wave accumulates its columns
+// across row blocks in LDS (each lane only its own slots) and writes one
+// partial per column and XCD; the NX partials are summed in a fixed order.
+struct ColBlkArgs {
+    int64_t n, nb;
+    int32_t k, jw;          // jw: columns per wave at most (wave w owns w, w + V, ...)
+    int32_t rb_shift;       // rows per block: 2^rb_shift
+    const int32_t *seg;     // nb * n + 1 segment pointers
+    const uint32_t *row;    // nnz, row-blocked order: column << 16 | row within its block
+    const float *val;
+    const uint8_t *codes;   // per column of A
+    LossTab lt;
+    const float *Xs;        // m x kp
+    const float *Ys;        // n x kp: y (pass 0) or the trial y+ (pass 1)
+    float *part;            // pass 0: NX x n x (kp + 1) (gradient, loss); pass 1: NX x n (trial loss)
+};
+
+// PASS 0: loss-part gradient and loss of every column at Ys; PASS 1: loss at Ys.
+// Per row block a wave first reads its segments' pointers (one per lane),
+// then walks its segments as one stream of chunks of up to NS * E entries
+// (a segment's last chunk runs only the steps it has), the indices and
+// values of the next chunk loading while the current chunk's rows are
+// gathered and used.  A segment's sums go into its column's LDS slots
+// (lane groups reduced first; each lane adds only its own slots).
+template <int KP, int PASS, int LK>
+__global__ __launch_bounds__(256) void colblk_kernel(ColBlkArgs a)
+{
+    constexpr int C = cb_c<KP>(), L = KP / C, E = 64 / L, NS = CB_NS;
+    constexpr int W = PASS == 0 ? KP + 1 : 1;
+    extern __shared__ float cb_lds[];
+    const int lane = threadIdx.x & 63, slot = lane / L, q = lane % L;
+    const int xcd = (int)(blockIdx.x % NX);
+    const int64_t V = (int64_t)(gridDim.x / NX) * CW;
+    const int64_t wv = (int64_t)(blockIdx.x / NX) * CW + (threadIdx.x >> 6);
+    float *acc = cb_lds + (size_t)(threadIdx.x >> 6) * a.jw * W;
+    const bool owner = PASS == 0 ? slot == 0 : lane == 0;     // lanes holding accumulator slots
+    for (int jl = 0; jl < a.jw; ++jl) {
+        if (PASS == 0 && owner) {
+#pragma unroll
+            for (int t = 0; t < C; ++t) acc[jl * W + C * q + t] = 0.0f;
+        }
+        if (lane == 0) acc[jl * W + W - 1] = 0.0f;
+    }
+    // columns of this wave: j = wv + jl * V, jl < jc (<= 64, one per lane)
+    const int jc = wv < a.n ? (int)((a.n - wv + V - 1) / V) : 0;
+    const float4 *X4 = reinterpret_cast<const float4 *>(a.Xs);
+    const float4 *Y4 = reinterpret_cast<const float4 *>(a.Ys);
+    const uint32_t rmask = (1u << a.rb_shift) - 1;
+    for (int64_t rb = xcd; rb < a.nb; rb += NX) {
+        int32_t pb = 0, pe = 0;
+        if (lane < jc) {
+            const int64_t o = rb * a.n + wv + (int64_t)lane * V;
+            pb = a.seg[o];
+            pe = a.seg[o + 1];
+        }
+        const int64_t rbase = rb << a.rb_shift;
+        // the first non-empty segment at or after jl
+        auto next_seg = [&](int jl) {
+            while (jl < jc && __builtin_amdgcn_readlane(pb, jl) == __builtin_amdgcn_readlane(pe, jl)) ++jl;
+            return jl;
+        };
+        int jl = next_seg(0);
+        if (jl >= jc) continue;
+        int32_t first = __builtin_amdgcn_readlane(pb, jl), b = first, end = __builtin_amdgcn_readlane(pe, jl);
+        uint32_t i[NS];
+        float v[NS];
+        chunk_load<NS, E>(a.row, a.val, b, end, first, slot, i, v);
+        Part<C> y = load_part<KP, C>(Y4, wv + (int64_t)jl * V, q);
+        float f = 0.0f;
+        Part<C> g = {};
+        while (true) {
+            Part<C> x[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (b + s * E >= end) break;
+                x[s] = load_part<KP, C>(X4, rbase + (i[s] & rmask), q);
+            }
+            // the next chunk: the rest of this segment, else the next non-empty one
+            int jl2 = jl;
+            int32_t b2 = b + NS * E, end2 = end, first2 = first;
+            if (b2 >= end) {
+                jl2 = next_seg(jl + 1);
+                if (jl2 < jc) {
+                    b2 = first2 = __builtin_amdgcn_readlane(pb, jl2);
+                    end2 = __builtin_amdgcn_readlane(pe, jl2);
+                }
+            }
+            uint32_t i2[NS];
+            float v2[NS];
+            Part<C> y2 = y;
+            if (jl2 < jc) {
+                chunk_load<NS, E>(a.row, a.val, b2, end2, first2, slot, i2, v2);
+                if (jl2 != jl) y2 = load_part<KP, C>(Y4, wv + (int64_t)jl2 * V, q);
+            }
+            const int64_t j = wv + (int64_t)jl * V;
+            const int code = a.codes[j];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (b + s * E >= end) break;
+                const bool ok = b + s * E + slot < end;
+                const float z = group_sum<L>(dot_part<C>(x[s], y));
+                if constexpr (PASS == 0) {
+                    float l, gr;
+                    walk_lg<LK>(a.lt, code, (int)j, z, v[s], l, gr);
+                    f += (ok && q == 0) ? l : 0.0f;
+                    axpy_part<C>(g, ok ? gr : 0.0f, x[s]);
+                } else {
+                    const float l = walk_l<LK>(a.lt, code, (int)j, z, v[s]);
+                    f += (ok && q == 0) ? l : 0.0f;
+                }
+            }
+            if (jl2 != jl) {
+                // the segment is done: into the column's accumulator
+                f = across_groups<L>(group_sum<L>(f));   // only q == 0 lanes were nonzero
+                if constexpr (PASS == 0) {
+#pragma unroll
+                    for (int u = 0; u < C / 4; ++u) {
+                        float4 &gv = g.v[u];
+                        gv.x = across_groups<L>(gv.x);
+                        gv.y = across_groups<L>(gv.y);
+                        gv.z = across_groups<L>(gv.z);
+                        gv.w = across_groups<L>(gv.w);
+                        if (owner) {
+                            float *d = acc + jl * W + C * q + 4 * u;
+                            d[0] += gv.x; d[1] += gv.y; d[2] += gv.z; d[3] += gv.w;
+                        }
+                    }
+                    g = Part<C>{};
+                }
+                if (lane == 0) acc[jl * W + W - 1] += f;
+                f = 0.0f;
+            }
+            if (jl2 >= jc) break;
+            jl = jl2;
+            b = b2;
+            end = end2;
+            first = first2;
+            y = y2;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                i[s] = i2[s];
+                v[s] = v2[s];
+            }
+        }
+    }
+    int jl = 0;
+    for (int64_t j = wv; j < a.n; j += V, ++jl) {
+        float *dst = a.part + ((int64_t)xcd * a.n + j) * W;
+        if (PASS == 0 && owner) {
+#pragma unroll
+            for (int t = 0; t < C; ++t) dst[C * q + t] = acc[jl * W + C * q + t];
+        }
+        if (lane == 0) dst[W - 1] = acc[jl * W + W - 1];
+    }
+}
+
+struct ColStepArgs {
+    int64_t n;
+    int32_t k;
+    const float *part0;     // NX x n x (kp + 1)
+    const float *part1;     // NX x n
+    const float *Yin;       // n x k (current columns)
+    float *alpha;
+    Reg reg;
+    float step_up, step_down;
+    float *yplus;           // n x kp: the trial columns
+    float *hold, *rplus;    // n: objective of the current column (loss + rt), rt of the trial column
+    float *dY;              // gradient mode: n x k output (then no step is taken)
+    float *Y;               // decide: n x k, updated
+    float *ys;              // decide: n x kp padded copy, updated
+    double *partF;          // decide: per block, decided column objectives
+    int32_t *partR;         // decide: per block, rejected columns
+};
+
+// The sum of the NX partials (fixed order), then either the gradient out
+// (dY) or the proximal gradient step of every column: the trial y+, the
+// current column's objective and rt(y+).
+template <int KP>
+__global__ __launch_bounds__(256) void colblk_step_kernel(ColStepArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = t / KP;
+    const int c = (int)(t % KP);
+    const bool valid = j < a.n;
+    float g = 0.0f, fo = 0.0f;
+    if (valid) {
+#pragma unroll
+        for (int x = 0; x < NX; ++x) g += a.part0[((int64_t)x * a.n + j) * (KP + 1) + c];
+        if (c == 0) {
+#pragma unroll
+            for (int x = 0; x < NX; ++x) fo += a.part0[((int64_t)x * a.n + j) * (KP + 1) + KP];
+        }
+    }
+    if (a.dY) {
+        if (valid && c < a.k) a.dY[j * a.k + c] = g;
+        return;
+    }
+    float y = 0.0f, al = 0.0f;
+    if (valid) {
+        al = a.alpha[j];
+        if (c < a.k) y = a.Yin[j * a.k + c];
+    }
+    const bool in = valid && c < a.k;
+    const float yp = in ? prox_elem(a.reg, al, y - al * g, c) : 0.0f;
+    float ro = in ? reg_elem(a.reg, y, c) : 0.0f;
+    float rp = in ? reg_elem_trial(a.reg, yp, c) : 0.0f;
+    ro = sum_lanes<KP>(ro);
+    rp = sum_lanes<KP>(rp);
+    if (valid) {
+        a.yplus[j * KP + c] = yp;
+        if (c == 0) {
+            a.hold[j] = fo + ro;
+            a.rplus[j] = rp;
+        }
+    }
+}
+
+// The step rule of every column: the trial objective (NX partials in a fixed
+// order + rt(y+)) against the current one; accepted columns take y+.
+template <int KP>
+__global__ __launch_bounds__(256) void colblk_decide_kernel(ColStepArgs a)
+{
+    __shared__ double s_F[4];
+    __shared__ int s_r[4];
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = t / KP;
+    const int c = (int)(t % KP);
+    const bool valid = j < a.n;
+    float fp = 0.0f;
+    if (valid && c == 0) {
+#pragma unroll
+        for (int x = 0; x < NX; ++x) fp += a.part1[(int64_t)x * a.n + j];
+    }
+    fp = sum_lanes<KP>(fp);   // the same value in every lane of the column
+    double Fj = 0.0;
+    int rj = 0;
+    if (valid) {
+        fp += a.rplus[j];
+        const float ho = a.hold[j];
+        const bool acc = fp <= ho;
+        if (acc) {
+            const float yp = a.yplus[j * KP + c];
+            a.ys[j * KP + c] = yp;
+            if (c < a.k) a.Y[j * a.k + c] = yp;
+        }
+        if (c == 0) {
+            const float al = a.alpha[j];
+            a.alpha[j] = acc ? al * a.step_up : al * a.step_down;
+            Fj = acc ? (double)fp : (double)ho;
+            rj = acc ? 0 : 1;
+        }
+    }
+    Fj = sum_lanes64<64>(Fj);
+    rj = (int)sum_lanes<64>((float)rj);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { s_F[w] = Fj; s_r[w] = rj; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.partF[blockIdx.x] = s_F[0] + s_F[1] + s_F[2] + s_F[3];
+        a.partR[blockIdx.x] = s_r[0] + s_r[1] + s_r[2] + s_r[3];
     }
 }
 
@@ -531,6 +972,82 @@ static WalkArgs col_walk(const glrm_data *d, const CooPtrs &p, const uint8_t *co
     return a;
 }
 
+// Launch shape of the row-blocked column passes: workgroups per XCD and the
+// columns each wave owns.
+struct ColBlkShape {
+    int g, jw;
+};
+
+static ColBlkShape colblk_shape(int64_t n, int kp)
+{
+    const int64_t need = (n + (int64_t)cb_jw_max(kp) * CW - 1) / ((int64_t)cb_jw_max(kp) * CW);
+    const int g = (int)std::min<int64_t>(CB_GMAX, std::max<int64_t>(CB_GMIN, need));
+    const int jw = (int)std::max<int64_t>(1, (n + (int64_t)g * CW - 1) / ((int64_t)g * CW));
+    return ColBlkShape{g, jw};
+}
+
+template <int PASS, int LK>
+static hipError_t launch_colblk_lk(const ColBlkArgs &a, int kp, const ColBlkShape &sh, hipStream_t st)
+{
+    const size_t lds = sizeof(float) * CW * sh.jw * (PASS == 0 ? kp + 1 : 1);
+    const dim3 grid((unsigned)(NX * sh.g));
+    switch (kp) {
+    case 16: hipLaunchKernelGGL((colblk_kernel<16, PASS, LK>), grid, dim3(256), lds, st, a); break;
+    case 32: hipLaunchKernelGGL((colblk_kernel<32, PASS, LK>), grid, dim3(256), lds, st, a); break;
+    case 64: hipLaunchKernelGGL((colblk_kernel<64, PASS, LK>), grid, dim3(256), lds, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int PASS>
+static hipError_t launch_colblk(const ColBlkArgs &a, int kp, const ColBlkShape &sh, hipStream_t st)
+{
+    if (a.lt.uniform >= 0 && a.lt.kind[a.lt.uniform] == L_QUAD) {
+        ColBlkArgs b = a;
+        b.lt.levels[0] = a.lt.levels[a.lt.uniform];
+        b.lt.param[0] = a.lt.param[a.lt.uniform];
+        return launch_colblk_lk<PASS, L_QUAD>(b, kp, sh, st);
+    }
+    return launch_colblk_lk<PASS, -1>(a, kp, sh, st);
+}
+
+template <int DECIDE>
+static hipError_t launch_colstep(const ColStepArgs &a, int kp, hipStream_t st)
+{
+    const dim3 grid(nblk(a.n * kp));
+    switch (kp) {
+    case 16:
+        if (DECIDE) hipLaunchKernelGGL(colblk_decide_kernel<16>, grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(colblk_step_kernel<16>, grid, dim3(256), 0, st, a);
+        break;
+    case 32:
+        if (DECIDE) hipLaunchKernelGGL(colblk_decide_kernel<32>, grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(colblk_step_kernel<32>, grid, dim3(256), 0, st, a);
+        break;
+    case 64:
+        if (DECIDE) hipLaunchKernelGGL(colblk_decide_kernel<64>, grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL(colblk_step_kernel<64>, grid, dim3(256), 0, st, a);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static ColBlkArgs colblk_args(const glrm_data *d, const CooLayout &cl, const CooPtrs &p, const uint8_t *codes,
+                              const LossTab &lt, int kp)
+{
+    ColBlkArgs a;
+    memset(&a, 0, sizeof a);
+    a.n = d->n; a.nb = cl.nb; a.k = d->k;
+    a.jw = colblk_shape(d->n, kp).jw;
+    a.seg = p.seg; a.row = reinterpret_cast<const uint32_t *>(p.brow); a.val = p.bval;
+    a.rb_shift = cl.rb_shift;
+    a.codes = codes; a.lt = lt;
+    a.Xs = p.xs;
+    return a;
+}
+
 static int pad_factors(const glrm_data *d, int kp, const CooPtrs &p, const float *X, const float *Y, hipStream_t st)
 {
     hipLaunchKernelGGL(pad_factor_kernel, dim3(nblk(d->m * kp)), dim3(256), 0, st, X, d->m, d->k, kp, p.xs);
@@ -577,10 +1094,21 @@ int coo_grad(const glrm_data *d, int kp, const CooLayout &cl, char *base, const 
     const int grid = walk_grid(d->m);
     hipError_t e = launch_walk<0>(a, kp, grid, st);
     if (e != hipSuccess) return set_error(GLRM_EHIP, "COO gradient (rows): %s", hipGetErrorString(e));
-    WalkArgs b = col_walk(d, p, codes, lt);
-    b.dU = dY;
-    b.part_obj = p.partB;
-    e = launch_walk<0>(b, kp, walk_grid(d->n), st);
+    if (cl.blk) {
+        ColBlkArgs b = colblk_args(d, cl, p, codes, lt, kp);
+        b.Ys = p.ys;
+        b.part = p.bpart0;
+        e = launch_colblk<0>(b, kp, colblk_shape(d->n, kp), st);
+        ColStepArgs s;
+        memset(&s, 0, sizeof s);
+        s.n = d->n; s.k = d->k; s.part0 = p.bpart0; s.dY = dY;
+        if (e == hipSuccess) e = launch_colstep<0>(s, kp, st);
+    } else {
+        WalkArgs b = col_walk(d, p, codes, lt);
+        b.dU = dY;
+        b.part_obj = p.partB;
+        e = launch_walk<0>(b, kp, walk_grid(d->n), st);
+    }
     if (e != hipSuccess) return set_error(GLRM_EHIP, "COO gradient (columns): %s", hipGetErrorString(e));
     *parts = p.partA;
     *nparts = grid * CW;
@@ -610,6 +1138,22 @@ int coo_fit(const glrm_data *d, int kp, const CooLayout &cl, char *base, const u
     ca.U = Y; ca.alpha = alpha_y; ca.step_up = o->step_up; ca.step_down = o->step_down;
     ca.part_obj = p.partB; ca.part_rej = p.ipartB;
     const int grid_r = walk_grid(d->m), grid_c = walk_grid(d->n);
+    // the row-blocked column step: gradient pass, step, trial pass, decision
+    const ColBlkShape sh = colblk_shape(d->n, kp);
+    ColBlkArgs c0, c1;
+    ColStepArgs cs;
+    memset(&cs, 0, sizeof cs);
+    if (cl.blk) {
+        c0 = colblk_args(d, cl, p, codes, lt, kp);
+        c0.Ys = p.ys; c0.part = p.bpart0;
+        c1 = c0;
+        c1.Ys = p.yplus; c1.part = p.bpart1;
+        cs.n = d->n; cs.k = d->k; cs.part0 = p.bpart0; cs.part1 = p.bpart1;
+        cs.Yin = Y; cs.alpha = alpha_y; cs.reg = ca.reg; cs.step_up = o->step_up; cs.step_down = o->step_down;
+        cs.yplus = p.yplus; cs.hold = p.hold; cs.rplus = p.rplus;
+        cs.Y = Y; cs.ys = p.ys; cs.partF = p.partB; cs.partR = p.ipartB;
+    }
+    const int ncolparts = cl.blk ? (int)nblk(d->n * kp) : grid_c * CW;
     double F_prev = NAN;
     *sweeps = 0;
     for (int t = 0; t < o->max_sweeps; ++t) {
@@ -617,12 +1161,19 @@ int coo_fit(const glrm_data *d, int kp, const CooLayout &cl, char *base, const u
         if (e == hipSuccess) e = launch_walk<1>(ra, kp, grid_r, st);
         if (e == hipSuccess) e = tstop();
         if (e == hipSuccess) e = tstart(1);
-        if (e == hipSuccess) e = launch_walk<1>(ca, kp, grid_c, st);
+        if (cl.blk) {
+            if (e == hipSuccess) e = launch_colblk<0>(c0, kp, sh, st);
+            if (e == hipSuccess) e = launch_colstep<0>(cs, kp, st);
+            if (e == hipSuccess) e = launch_colblk<1>(c1, kp, sh, st);
+            if (e == hipSuccess) e = launch_colstep<1>(cs, kp, st);
+        } else {
+            if (e == hipSuccess) e = launch_walk<1>(ca, kp, grid_c, st);
+        }
         if (e == hipSuccess) e = tstop();
         if (e == hipSuccess) e = tstart(3);
         if (e != hipSuccess) return set_error(GLRM_EHIP, "COO sweep: %s", hipGetErrorString(e));
         // F = decided column objectives (loss + rt) + r of the decided rows
-        hipLaunchKernelGGL(coo_finalize_kernel, dim3(1), dim3(256), 0, st, p.partB, p.ipartB, grid_c * CW, p.partA,
+        hipLaunchKernelGGL(coo_finalize_kernel, dim3(1), dim3(256), 0, st, p.partB, p.ipartB, ncolparts, p.partA,
                            p.ipartA, grid_r * CW, stats, istats, history, t);
         if ((e = tstop()) != hipSuccess) return set_error(GLRM_EHIP, "COO timing: %s", hipGetErrorString(e));
         if ((e = hipGetLastError()) != hipSuccess) return set_error(GLRM_EHIP, "COO finalize: %s", hipGetErrorString(e));

@@ -25,6 +25,11 @@ CASES = [
     dict(m=1, n=1, k=1, seed=7, missing=0.0),
     dict(m=20000, n=40, k=6, seed=10, missing=0.3),
     dict(m=20, n=10, k=3, seed=11, missing=1.0),        # no entries at all
+    # the row-blocked column step: blocks of 2^14 / 2^13 / 2^12 rows at kp = 16 / 32 / 64
+    dict(m=60000, n=90, k=20, seed=12, missing=0.97),   # kp = 32: 8 row blocks, one per partial set
+    dict(m=70000, n=30, k=40, seed=13, missing=0.95),   # kp = 64: 18 row blocks, 2-3 per partial set
+    dict(m=9000, n=1500, k=10, seed=14, missing=0.99),  # several columns per wave
+    dict(m=20000, n=1100, k=24, seed=15, missing=0.995),  # both
 ]
 
 
@@ -134,3 +139,22 @@ def test_bf16_is_reported_unsupported_for_coo():
     with pytest.raises(g.GLRMError) as ei:
         g.glrm_objective(data, X, Y, g.BF16)
     assert ei.value.code == g.EUNSUPPORTED
+
+
+def test_fit_is_bitwise_repeatable():
+    """Two fits from the same state give the same bits: every partial sum of
+    both walks (and of the row-blocked column passes) is combined in a fixed
+    order."""
+    case = _case(dict(m=60000, n=90, k=20, seed=12, missing=0.97))
+    data = g.Data.from_case(case, DEV)
+    g.glrm_prepare(data)
+    out = []
+    for _ in range(2):
+        X, Y = to_dev(case.X0, DEV), to_dev(case.Y0, DEV)
+        ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
+        ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
+        info = g.glrm_fit(data, X, Y, ax, ay, 4, precision=g.FP32, flags=g.WS_PREPARED)
+        out.append((X.cpu().numpy(), Y.cpu().numpy(), info["objective_fp32"]))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
