@@ -30,6 +30,8 @@ struct CooLayout {
     size_t part = 0, part_bytes = 0;  // double partials of the objective
     size_t xs = 0;         // padded copy of X (m x kp, fp32), updated in place by the row walk
     size_t ys = 0;         // padded copy of Y (n x kp, fp32), updated in place by the column walk
+    size_t xsb = 0, ysb = 0;   // bfloat16 copies of xs and ys (the BF16 fit's trial passes)
+    size_t zc = 0;         // per entry (row-blocked order): z kept between the BF16 column passes
     // Row-blocked column-grouped copy for the column step: entries ordered by
     // (row block, column, row), rows in blocks of 2^rb_shift, with segment
     // pointers per (row block, column).  blk = false: not built (too many

@@ -101,11 +101,15 @@ void coo_layout(const glrm_data *d, int kp, CooLayout &cl)
     cl.part = take(cl.part_bytes);
     cl.xs = take(sizeof(float) * d->m * kp);
     cl.ys = take(sizeof(float) * d->n * kp);
+    cl.xsb = take(2 * d->m * kp);
+    cl.ysb = take(2 * d->n * kp);
+    if (cl.blk) cl.zc = take(sizeof(float) * nnz);
 }
 
 struct CooPtrs {
     int32_t *row_ptr, *col_ptr, *csc_row, *perm_in, *perm_out, *keys_out, *flags;
-    float *csc_val, *xs, *ys;
+    float *csc_val, *xs, *ys, *zc;
+    __bf16 *xsb, *ysb;
     int32_t *bkey, *bperm, *brow, *seg;
     float *bval, *bpart0, *bpart1, *yplus, *hold, *rplus;
     double *partA, *partB;
@@ -132,6 +136,9 @@ static CooPtrs ptrs(const CooLayout &cl, char *b)
     p.ipartB = p.ipartA + COO_MAX_WAVES;
     p.xs = (float *)(b + cl.xs);
     p.ys = (float *)(b + cl.ys);
+    p.xsb = (__bf16 *)(b + cl.xsb);
+    p.ysb = (__bf16 *)(b + cl.ysb);
+    p.zc = (float *)(b + cl.zc);
     p.bkey = (int32_t *)(b + cl.bkey);
     p.bperm = (int32_t *)(b + cl.bperm);
     p.brow = (int32_t *)(b + cl.brow);
@@ -230,14 +237,17 @@ __global__ void blk_key_kernel(const int32_t *row, const int32_t *col, int64_t n
     if (e < nnz) key[e] = (int32_t)((int64_t)(row[e] >> shift) * n + col[e]);
 }
 
-// Padded copy of a factor: dst (rows x kp) from src (rows x k).
-__global__ void pad_factor_kernel(const float *src, int64_t rows, int32_t k, int32_t kp, float *dst)
+// Padded copies of a factor: dst (rows x kp) from src (rows x k), and its
+// bfloat16 rounding (round to nearest even).
+__global__ void pad_factor_kernel(const float *src, int64_t rows, int32_t k, int32_t kp, float *dst, __bf16 *dstb)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= rows * kp) return;
     const int64_t i = t / kp;
     const int c = (int)(t % kp);
-    dst[t] = c < k ? src[i * k + c] : 0.0f;
+    const float v = c < k ? src[i * k + c] : 0.0f;
+    dst[t] = v;
+    dstb[t] = (__bf16)v;
 }
 
 static unsigned nblk(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + 255) / 256); }
@@ -366,6 +376,76 @@ __device__ __forceinline__ void axpy_part(Part<C> &acc, float g, const Part<C> &
     }
 }
 
+// The bfloat16 copy of a lane's C coordinates (C / 2 packed pairs).
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2_t;
+typedef __attribute__((ext_vector_type(2))) float f32x2_t;
+
+template <int C>
+struct PartB {
+    uint32_t w[C / 2];
+};
+
+template <int KP, int C>
+__device__ __forceinline__ PartB<C> load_partb(const __bf16 *__restrict__ F, int64_t row, int q)
+{
+    PartB<C> r;
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(F + row * KP + (int64_t)q * C);
+    if constexpr (C == 8) {
+        const uint4 u = *reinterpret_cast<const uint4 *>(p);
+        r.w[0] = u.x; r.w[1] = u.y; r.w[2] = u.z; r.w[3] = u.w;
+    } else {
+        const uint2 u = *reinterpret_cast<const uint2 *>(p);
+        r.w[0] = u.x; r.w[1] = u.y;
+    }
+    return r;
+}
+
+// A step d in bfloat16 pairs (round to nearest even).
+template <int C>
+__device__ __forceinline__ PartB<C> to_partb(const Part<C> &d)
+{
+    PartB<C> r;
+#pragma unroll
+    for (int u = 0; u < C / 4; ++u) {
+        const bf16x2_t a = __builtin_convertvector((f32x2_t){d.v[u].x, d.v[u].y}, bf16x2_t);
+        const bf16x2_t b = __builtin_convertvector((f32x2_t){d.v[u].z, d.v[u].w}, bf16x2_t);
+        r.w[2 * u] = __builtin_bit_cast(uint32_t, a);
+        r.w[2 * u + 1] = __builtin_bit_cast(uint32_t, b);
+    }
+    return r;
+}
+
+// sum over the lane's coordinates of d_c v_c, both in bfloat16, float32 sums
+template <int C>
+__device__ __forceinline__ float dot_partb(const PartB<C> &d, const PartB<C> &v)
+{
+    float s = 0.0f;
+#pragma unroll
+    for (int p = 0; p < C / 2; ++p)
+        s = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, d.w[p]), __builtin_bit_cast(bf16x2_t, v.w[p]),
+                                            s, false);
+    return s;
+}
+
+template <int C>
+__device__ __forceinline__ Part<C> sub_part(const Part<C> &a, const Part<C> &b)
+{
+    Part<C> r;
+#pragma unroll
+    for (int u = 0; u < C / 4; ++u)
+        r.v[u] = float4{a.v[u].x - b.v[u].x, a.v[u].y - b.v[u].y, a.v[u].z - b.v[u].z, a.v[u].w - b.v[u].w};
+    return r;
+}
+
+template <int KP, int C>
+__device__ __forceinline__ void store_partb(__bf16 *F, int64_t row, int q, const Part<C> &x)
+{
+    const PartB<C> b = to_partb<C>(x);
+    uint32_t *p = reinterpret_cast<uint32_t *>(F + row * KP + (int64_t)q * C);
+#pragma unroll
+    for (int t = 0; t < C / 2; ++t) p[t] = b.w[t];
+}
+
 // Coordinates per lane in the row-blocked column passes: 8 (groups of KP / 8
 // lanes per entry, fewer lanes repeating the loss and the butterfly), 4 at
 // KP = 16.
@@ -410,7 +490,14 @@ struct WalkArgs {
     double *part_obj;        // per wave: objective part (lossgrad) / decided row objectives (step)
     int32_t *part_rej;       // per wave: rejected rows (step)
     bool reg_only;           // step: accumulate only r of the decided rows (the other walk counts the loss)
+    // the bfloat16 trial (MODE 3): bf16 copies of both padded factors
+    const __bf16 *Vsb;
+    __bf16 *Usb;
 };
+
+// The bfloat16 trial keeps a row's products z_ij in LDS between the two
+// passes when the row has at most ZMAX entries.
+constexpr int ZMAX = 512;
 
 // One entry's loss (and derivative) in the walk.  LK >= 0: every column has
 // loss kind LK (compile time); LK < 0: the code of the entry's column.
@@ -443,8 +530,11 @@ __device__ __forceinline__ float walk_l(const LossTab &lt, int code, int wcol, f
     }
 }
 
-// MODE 0: loss (+ gradient if dU); MODE 1: full half-step; MODE 2: loss in double.
-// A wave owns one row at a time; groups of L = KP / C lanes share an entry,
+// MODE 0: loss (+ gradient if dU); MODE 1: full half-step; MODE 2: loss in
+// double; MODE 3: the half-step with the bfloat16 trial: the first pass keeps
+// every z_ij = x_i . y_j, and the trial products are z_ij + (x+ - x) . y_j with
+// the step and y_j in bfloat16 (two coordinates per dot2 instruction), so the
+// second pass gathers half the bytes.  A wave owns one row at a time; groups of L = KP / C lanes share an entry,
 // each lane holding C coordinates, so a factor row is one coalesced gather
 // and z = x_i . y_j a short butterfly over the group.  The walk goes through
 // a row's entries in chunks of up to NS steps of E entries: every lane first
@@ -464,6 +554,9 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
     const float4 *V4 = reinterpret_cast<const float4 *>(a.Vs);
     const float4 *U4 = reinterpret_cast<const float4 *>(a.Us);
     auto code_of = [&](int32_t j, int rowcode) { return a.codes_by_entry ? (int)a.codes[j] : rowcode; };
+    constexpr bool BT = MODE == 3;
+    __shared__ float zbuf[BT ? CW : 1][BT ? ZMAX : 1];
+    float *zrow = zbuf[BT ? (threadIdx.x >> 6) : 0];
     for (int64_t i = wave; i < a.rows; i += nwaves) {
         const int32_t beg = a.ptr[i], end = a.ptr[i + 1];
         const Part<C> x = load_part<KP, C>(U4, i, q);
@@ -501,6 +594,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
         }
         float f = 0.0f;
         Part<C> gacc = {};
+        const bool keep_z = BT && end - beg <= ZMAX;
         for (int32_t b = beg; b < end; b += NS * E) {
             int32_t j[NS];
             float v[NS];
@@ -516,6 +610,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
                 if (b + s * E >= end) break;
                 const bool ok = b + s * E + slot < end;
                 const float z = group_sum<L>(dot_part<C>(x, y[s]));
+                if (BT && keep_z && ok && q == 0) zrow[b - beg + s * E + slot] = z;
                 float l, gr;
                 walk_lg<LK>(a.lt, code_of(j[s], rowcode), a.codes_by_entry ? j[s] : (int)i, z, v[s], l, gr);
                 f += (ok && q == 0) ? l : 0.0f;
@@ -565,6 +660,39 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
             rc = group_sum<L>(rc);
             rcp = group_sum<L>(rcp);
             float fp = 0.0f;
+            if (BT && keep_z) {
+                // z held in LDS (written by lanes q == 0 of each group, read by all of it)
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const PartB<C> db = to_partb<C>(sub_part<C>(xp, x));
+                const __bf16 *Vb = a.Vsb;
+                for (int32_t b = beg; b < end; b += NS * E) {
+                    int32_t j[NS];
+                    float v[NS];
+                    PartB<C> yb[NS];
+                    chunk_load<NS, E>(a.idx, a.val, b, end, beg, slot, j, v);
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        if (b + s * E >= end) break;
+                        yb[s] = load_partb<KP, C>(Vb, j[s], q);
+                    }
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        if (b + s * E >= end) break;
+                        const int32_t e = b - beg + s * E + slot;
+                        const bool ok = e < end - beg;
+                        const float z0 = zrow[ok ? e : 0];
+                        const float z = z0 + group_sum<L>(dot_partb<C>(db, yb[s]));
+                        const float l = walk_l<LK>(a.lt, code_of(j[s], rowcode), a.codes_by_entry ? j[s] : (int)i, z, v[s]);
+                        fp += (ok && q == 0) ? l : 0.0f;
+                    }
+                }
+                // the next row's products may not overwrite these before every lane has read them
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else
             for (int32_t b = beg; b < end; b += NS * E) {
                 int32_t j[NS];
                 float v[NS];
@@ -588,6 +716,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
             const float F0 = f + rc, F1 = fp + rcp;
             const bool acc = F1 <= F0;
             if (acc && slot == 0) {
+                if constexpr (BT) store_partb<KP, C>(a.Usb, i, q, xp);
 #pragma unroll
                 for (int u = 0; u < C / 4; ++u) {
                     reinterpret_cast<float4 *>(a.Us + i * KP)[q * (C / 4) + u] = xp.v[u];
@@ -610,7 +739,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
     if constexpr (MODE == 2) wsum = sum_lanes64<64>(wsum);  // lanes with q == 0 hold the parts
     if (lane == 0) {
         a.part_obj[wave] = wsum;
-        if (MODE == 1) a.part_rej[wave] = wrej;
+        if (MODE == 1 || MODE == 3) a.part_rej[wave] = wrej;
     }
 }
 
@@ -665,11 +794,18 @@ struct ColBlkArgs {
     const uint8_t *codes;   // per column of A
     LossTab lt;
     const float *Xs;        // m x kp
-    const float *Ys;        // n x kp: y (pass 0) or the trial y+ (pass 1)
-    float *part;            // pass 0: NX x n x (kp + 1) (gradient, loss); pass 1: NX x n (trial loss)
+    const float *Ys;        // n x kp: y (passes 0, 2) or the trial y+ (passes 1, 3)
+    float *part;            // passes 0, 2: NX x n x (kp + 1) (gradient, loss); 1, 3: NX x n (trial loss)
+    // the bfloat16 trial: pass 2 keeps z of every entry (row-blocked order),
+    // pass 3 forms z + (y+ - y) . x_i from it with the bf16 copy of X
+    float *zc;
+    const __bf16 *Xsb;
+    const float *Ycur;      // n x kp: y (pass 3)
 };
 
 // PASS 0: loss-part gradient and loss of every column at Ys; PASS 1: loss at Ys.
+// PASS 2: PASS 0 that also keeps every entry's z; PASS 3: PASS 1 from those z
+// and the bfloat16 copy of X (the bf16 trial).
 // Per row block a wave first reads its segments' pointers (one per lane),
 // then walks its segments as one stream of chunks of up to NS * E entries
 // (a segment's last chunk runs only the steps it has), the indices and
@@ -680,16 +816,17 @@ template <int KP, int PASS, int LK>
 __global__ __launch_bounds__(256) void colblk_kernel(ColBlkArgs a)
 {
     constexpr int C = cb_c<KP>(), L = KP / C, E = 64 / L, NS = CB_NS;
-    constexpr int W = PASS == 0 ? KP + 1 : 1;
+    constexpr bool GRAD = PASS == 0 || PASS == 2, BT = PASS == 3;
+    constexpr int W = GRAD ? KP + 1 : 1;
     extern __shared__ float cb_lds[];
     const int lane = threadIdx.x & 63, slot = lane / L, q = lane % L;
     const int xcd = (int)(blockIdx.x % NX);
     const int64_t V = (int64_t)(gridDim.x / NX) * CW;
     const int64_t wv = (int64_t)(blockIdx.x / NX) * CW + (threadIdx.x >> 6);
     float *acc = cb_lds + (size_t)(threadIdx.x >> 6) * a.jw * W;
-    const bool owner = PASS == 0 ? slot == 0 : lane == 0;     // lanes holding accumulator slots
+    const bool owner = GRAD ? slot == 0 : lane == 0;     // lanes holding accumulator slots
     for (int jl = 0; jl < a.jw; ++jl) {
-        if (PASS == 0 && owner) {
+        if (GRAD && owner) {
 #pragma unroll
             for (int t = 0; t < C; ++t) acc[jl * W + C * q + t] = 0.0f;
         }
@@ -717,17 +854,26 @@ __global__ __launch_bounds__(256) void colblk_kernel(ColBlkArgs a)
         if (jl >= jc) continue;
         int32_t first = __builtin_amdgcn_readlane(pb, jl), b = first, end = __builtin_amdgcn_readlane(pe, jl);
         uint32_t i[NS];
-        float v[NS];
-        chunk_load<NS, E>(a.row, a.val, b, end, first, slot, i, v);
+        float v[NS], zv[NS];
+        auto load_c = [&](int32_t b0, int32_t e0, int32_t f0, uint32_t (&ii)[NS], float (&vv)[NS], float (&zz)[NS]) {
+            chunk_load<NS, E>(a.row, a.val, b0, e0, f0, slot, ii, vv);
+            if constexpr (BT) chunk_load<NS, E>(a.row, a.zc, b0, e0, f0, slot, ii, zz);
+        };
+        load_c(b, end, first, i, v, zv);
         Part<C> y = load_part<KP, C>(Y4, wv + (int64_t)jl * V, q);
+        // the step of the column (bf16 trial)
+        PartB<C> db = {};
+        if constexpr (BT) db = to_partb<C>(sub_part<C>(y, load_part<KP, C>(reinterpret_cast<const float4 *>(a.Ycur), wv + (int64_t)jl * V, q)));
         float f = 0.0f;
         Part<C> g = {};
         while (true) {
             Part<C> x[NS];
+            PartB<C> xb[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 if (b + s * E >= end) break;
-                x[s] = load_part<KP, C>(X4, rbase + (i[s] & rmask), q);
+                if constexpr (BT) xb[s] = load_partb<KP, C>(a.Xsb, rbase + (i[s] & rmask), q);
+                else x[s] = load_part<KP, C>(X4, rbase + (i[s] & rmask), q);
             }
             // the next chunk: the rest of this segment, else the next non-empty one
             int jl2 = jl;
@@ -740,11 +886,17 @@ __global__ __launch_bounds__(256) void colblk_kernel(ColBlkArgs a)
                 }
             }
             uint32_t i2[NS];
-            float v2[NS];
+            float v2[NS], zv2[NS];
             Part<C> y2 = y;
+            PartB<C> db2 = db;
             if (jl2 < jc) {
-                chunk_load<NS, E>(a.row, a.val, b2, end2, first2, slot, i2, v2);
-                if (jl2 != jl) y2 = load_part<KP, C>(Y4, wv + (int64_t)jl2 * V, q);
+                load_c(b2, end2, first2, i2, v2, zv2);
+                if (jl2 != jl) {
+                    y2 = load_part<KP, C>(Y4, wv + (int64_t)jl2 * V, q);
+                    if constexpr (BT)
+                        db2 = to_partb<C>(sub_part<C>(
+                            y2, load_part<KP, C>(reinterpret_cast<const float4 *>(a.Ycur), wv + (int64_t)jl2 * V, q)));
+                }
             }
             const int64_t j = wv + (int64_t)jl * V;
             const int code = a.codes[j];
@@ -752,8 +904,17 @@ __global__ __launch_bounds__(256) void colblk_kernel(ColBlkArgs a)
             for (int s = 0; s < NS; ++s) {
                 if (b + s * E >= end) break;
                 const bool ok = b + s * E + slot < end;
+                if constexpr (BT) {
+                    const float z = zv[s] + group_sum<L>(dot_partb<C>(db, xb[s]));
+                    const float l = walk_l<LK>(a.lt, code, (int)j, z, v[s]);
+                    f += (ok && q == 0) ? l : 0.0f;
+                    continue;
+                }
                 const float z = group_sum<L>(dot_part<C>(x[s], y));
-                if constexpr (PASS == 0) {
+                if constexpr (PASS == 2) {
+                    if (ok && q == 0) a.zc[b + s * E + slot] = z;
+                }
+                if constexpr (GRAD) {
                     float l, gr;
                     walk_lg<LK>(a.lt, code, (int)j, z, v[s], l, gr);
                     f += (ok && q == 0) ? l : 0.0f;
@@ -766,7 +927,7 @@ __global__ __launch_bounds__(256) void colblk_kernel(ColBlkArgs a)
             if (jl2 != jl) {
                 // the segment is done: into the column's accumulator
                 f = across_groups<L>(group_sum<L>(f));   // only q == 0 lanes were nonzero
-                if constexpr (PASS == 0) {
+                if constexpr (GRAD) {
 #pragma unroll
                     for (int u = 0; u < C / 4; ++u) {
                         float4 &gv = g.v[u];
@@ -790,17 +951,19 @@ __global__ __launch_bounds__(256) void colblk_kernel(ColBlkArgs a)
             end = end2;
             first = first2;
             y = y2;
+            db = db2;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 i[s] = i2[s];
                 v[s] = v2[s];
+                zv[s] = zv2[s];
             }
         }
     }
     int jl = 0;
     for (int64_t j = wv; j < a.n; j += V, ++jl) {
         float *dst = a.part + ((int64_t)xcd * a.n + j) * W;
-        if (PASS == 0 && owner) {
+        if (GRAD && owner) {
 #pragma unroll
             for (int t = 0; t < C; ++t) dst[C * q + t] = acc[jl * W + C * q + t];
         }
@@ -822,6 +985,7 @@ struct ColStepArgs {
     float *dY;              // gradient mode: n x k output (then no step is taken)
     float *Y;               // decide: n x k, updated
     float *ys;              // decide: n x kp padded copy, updated
+    __bf16 *ysb;            // decide: its bfloat16 copy, updated
     double *partF;          // decide: per block, decided column objectives
     int32_t *partR;         // decide: per block, rejected columns
 };
@@ -895,6 +1059,7 @@ __global__ __launch_bounds__(256) void colblk_decide_kernel(ColStepArgs a)
         if (acc) {
             const float yp = a.yplus[j * KP + c];
             a.ys[j * KP + c] = yp;
+            a.ysb[j * KP + c] = (__bf16)yp;
             if (c < a.k) a.Y[j * a.k + c] = yp;
         }
         if (c == 0) {
@@ -989,7 +1154,7 @@ static ColBlkShape colblk_shape(int64_t n, int kp)
 template <int PASS, int LK>
 static hipError_t launch_colblk_lk(const ColBlkArgs &a, int kp, const ColBlkShape &sh, hipStream_t st)
 {
-    const size_t lds = sizeof(float) * CW * sh.jw * (PASS == 0 ? kp + 1 : 1);
+    const size_t lds = sizeof(float) * CW * sh.jw * (PASS == 0 || PASS == 2 ? kp + 1 : 1);
     const dim3 grid((unsigned)(NX * sh.g));
     switch (kp) {
     case 16: hipLaunchKernelGGL((colblk_kernel<16, PASS, LK>), grid, dim3(256), lds, st, a); break;
@@ -1050,17 +1215,20 @@ static ColBlkArgs colblk_args(const glrm_data *d, const CooLayout &cl, const Coo
 
 static int pad_factors(const glrm_data *d, int kp, const CooPtrs &p, const float *X, const float *Y, hipStream_t st)
 {
-    hipLaunchKernelGGL(pad_factor_kernel, dim3(nblk(d->m * kp)), dim3(256), 0, st, X, d->m, d->k, kp, p.xs);
-    hipLaunchKernelGGL(pad_factor_kernel, dim3(nblk(d->n * kp)), dim3(256), 0, st, Y, d->n, d->k, kp, p.ys);
+    hipLaunchKernelGGL(pad_factor_kernel, dim3(nblk(d->m * kp)), dim3(256), 0, st, X, d->m, d->k, kp, p.xs, p.xsb);
+    hipLaunchKernelGGL(pad_factor_kernel, dim3(nblk(d->n * kp)), dim3(256), 0, st, Y, d->n, d->k, kp, p.ys, p.ysb);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? GLRM_OK : set_error(GLRM_EHIP, "pad factors: %s", hipGetErrorString(e));
 }
 
+// The COO layout's precisions: FP32; FP64 for the objective; BF16, whose
+// trial passes take z + (x+ - x) . y with the step and the gathered factor
+// in bfloat16 (objective and gradient calls compute as FP32).
 static int coo_prec_ok(int prec)
 {
-    if (prec == GLRM_FP32 || prec == GLRM_FP64) return GLRM_OK;
-    return set_error(GLRM_EUNSUPPORTED, "the COO layout computes in FP32 (and FP64 for the objective); "
-                     "bfloat16 precisions are built for the dense layout only");
+    if (prec == GLRM_FP32 || prec == GLRM_FP64 || prec == GLRM_BF16) return GLRM_OK;
+    return set_error(GLRM_EUNSUPPORTED, "the COO layout computes in FP32 or BF16 (and FP64 for the objective); "
+                     "BF16_PLAIN is built for the dense layout only");
 }
 
 int coo_objective(const glrm_data *d, const CooLayout &cl, char *base, const uint8_t *codes, const LossTab &lt,
@@ -1073,7 +1241,7 @@ int coo_objective(const glrm_data *d, const CooLayout &cl, char *base, const uin
     WalkArgs a = row_walk(d, p, codes, lt);
     a.part_obj = p.partA;
     const int grid = walk_grid(d->m);
-    hipError_t e = prec == GLRM_FP64 ? launch_walk<2>(a, cl.kp, grid, st) : launch_walk<0>(a, cl.kp, grid, st);
+    hipError_t e = prec == GLRM_FP64 ? launch_walk<2>(a, cl.kp, grid, st) : launch_walk<0>(a, cl.kp, grid, st);  // BF16: as FP32
     if (e != hipSuccess) return set_error(GLRM_EHIP, "COO objective: %s", hipGetErrorString(e));
     *parts = p.partA;
     *nparts = grid * CW;
@@ -1133,10 +1301,13 @@ int coo_fit(const glrm_data *d, int kp, const CooLayout &cl, char *base, const u
     ra.reg = Reg{d->rx.kind, d->rx.weight, d->offset ? 1 : 0};
     ra.U = X; ra.alpha = alpha_x; ra.step_up = o->step_up; ra.step_down = o->step_down;
     ra.part_obj = p.partA; ra.part_rej = p.ipartA; ra.reg_only = true;
+    ra.Vsb = p.ysb; ra.Usb = p.xsb;
     WalkArgs ca = col_walk(d, p, codes, lt);
     ca.reg = Reg{d->ry.kind, d->ry.weight, d->offset ? 2 : 0};
     ca.U = Y; ca.alpha = alpha_y; ca.step_up = o->step_up; ca.step_down = o->step_down;
     ca.part_obj = p.partB; ca.part_rej = p.ipartB;
+    ca.Vsb = p.xsb; ca.Usb = p.ysb;
+    const bool bt = o->precision == GLRM_BF16;   // the bfloat16 trial passes
     const int grid_r = walk_grid(d->m), grid_c = walk_grid(d->n);
     // the row-blocked column step: gradient pass, step, trial pass, decision
     const ColBlkShape sh = colblk_shape(d->n, kp);
@@ -1146,28 +1317,29 @@ int coo_fit(const glrm_data *d, int kp, const CooLayout &cl, char *base, const u
     if (cl.blk) {
         c0 = colblk_args(d, cl, p, codes, lt, kp);
         c0.Ys = p.ys; c0.part = p.bpart0;
+        c0.zc = p.zc; c0.Xsb = p.xsb; c0.Ycur = p.ys;
         c1 = c0;
         c1.Ys = p.yplus; c1.part = p.bpart1;
         cs.n = d->n; cs.k = d->k; cs.part0 = p.bpart0; cs.part1 = p.bpart1;
         cs.Yin = Y; cs.alpha = alpha_y; cs.reg = ca.reg; cs.step_up = o->step_up; cs.step_down = o->step_down;
         cs.yplus = p.yplus; cs.hold = p.hold; cs.rplus = p.rplus;
-        cs.Y = Y; cs.ys = p.ys; cs.partF = p.partB; cs.partR = p.ipartB;
+        cs.Y = Y; cs.ys = p.ys; cs.ysb = p.ysb; cs.partF = p.partB; cs.partR = p.ipartB;
     }
     const int ncolparts = cl.blk ? (int)nblk(d->n * kp) : grid_c * CW;
     double F_prev = NAN;
     *sweeps = 0;
     for (int t = 0; t < o->max_sweeps; ++t) {
         hipError_t e = tstart(0);
-        if (e == hipSuccess) e = launch_walk<1>(ra, kp, grid_r, st);
+        if (e == hipSuccess) e = bt ? launch_walk<3>(ra, kp, grid_r, st) : launch_walk<1>(ra, kp, grid_r, st);
         if (e == hipSuccess) e = tstop();
         if (e == hipSuccess) e = tstart(1);
         if (cl.blk) {
-            if (e == hipSuccess) e = launch_colblk<0>(c0, kp, sh, st);
+            if (e == hipSuccess) e = bt ? launch_colblk<2>(c0, kp, sh, st) : launch_colblk<0>(c0, kp, sh, st);
             if (e == hipSuccess) e = launch_colstep<0>(cs, kp, st);
-            if (e == hipSuccess) e = launch_colblk<1>(c1, kp, sh, st);
+            if (e == hipSuccess) e = bt ? launch_colblk<3>(c1, kp, sh, st) : launch_colblk<1>(c1, kp, sh, st);
             if (e == hipSuccess) e = launch_colstep<1>(cs, kp, st);
         } else {
-            if (e == hipSuccess) e = launch_walk<1>(ca, kp, grid_c, st);
+            if (e == hipSuccess) e = bt ? launch_walk<3>(ca, kp, grid_c, st) : launch_walk<1>(ca, kp, grid_c, st);
         }
         if (e == hipSuccess) e = tstop();
         if (e == hipSuccess) e = tstart(3);

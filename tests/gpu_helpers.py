@@ -48,7 +48,7 @@ def rel_fro(a, b):
 # decision whose margin |f+ - f| lies inside the band may legitimately go
 # either way; every other decision must match the oracle's.
 
-GRAD_REL = {"fp32": 0.0, "bf16": 2.0 ** -8}
+GRAD_REL = {"fp32": 0.0, "bf16": 2.0 ** -8, "coo_bf16": 0.0}
 SUM_REL = 1e-5
 # Four sources.  (1) The derivative operand: the BF16 form rounds every
 # G_ij to bfloat16 (round to nearest even).  These errors are not independent:
@@ -74,7 +74,7 @@ SUM_REL = 1e-5
 # (quadratic 2, Huber 1, logistic 1/4); a kinked loss (hinge, ordinal hinge)
 # passes nothing on, except where a kink lies within that distance of z: there
 # the derivative may take either side, a step of 1 per term that kinks there.
-RSS_REL = {"fp32": None, "bf16": 2.0 ** -6}
+RSS_REL = {"fp32": None, "bf16": 2.0 ** -6, "coo_bf16": None}
 ACC_RUN = 2 ** 10
 CURVATURE = {0: 2.0, 1: 1.0, 2: 0.25, 3: 0.0, 4: 0.0}
 
@@ -118,7 +118,7 @@ def z_terms(P, which, X, Y, prec):
     other = view.col.astype(np.int64)
     Ur, Vo = U[rows], V[other]
     u = np.einsum("ij,ij->i", Ur, Vo)
-    z_rel = (U.shape[1] + 1) * 2.0 ** -24 if prec == "fp32" else 2.0 ** -14
+    z_rel = (U.shape[1] + 1) * 2.0 ** -24 if prec in ("fp32", "coo_bf16") else 2.0 ** -14
     dz = z_rel * np.einsum("ij,ij->i", np.abs(Ur), np.abs(Vo))
     kinds = np.array([l[0] for l in P.losses], np.int64)[view.ecode]
     levels = np.array([l[1] for l in P.losses], np.int64)[view.ecode]
@@ -172,6 +172,33 @@ def _offsets(P):
     return (1, 2) if getattr(P, "offset", False) else (0, 0)
 
 
+# The sparse layout's BF16 form computes the gradient and the trial point as
+# FP32 does ("coo_bf16" takes the FP32 bounds above), but evaluates the trial
+# objective from z_ij + d . v_j with the step d = u+ - u and the gathered row
+# v_j both in bfloat16: each trial product errs by at most 2^-8 sum_c |d_c| |v_jc|
+# (two roundings of 2^-9), which moves the trial objective by at most
+# (|G(z+)| + a kink's step + curvature / 2 times that) times that error, entry by entry.
+def trial_bf16_terms(P, which, U0, Ut, V):
+    """Per row (which = "x") or column: the bound on the trial objective's
+    error in the sparse BF16 form."""
+    view = P.row if which == "x" else P.colv
+    U0, Ut, V = (np.asarray(a, np.float64) for a in (U0, Ut, V))
+    rows = np.repeat(np.arange(view.m), np.diff(view.row_ptr))
+    other = view.col.astype(np.int64)
+    D = np.abs(Ut - U0)
+    dz = 2.0 ** -8 * np.einsum("ij,ij->i", D[rows], np.abs(V[other]))
+    u = np.einsum("ij,ij->i", Ut[rows], V[other])
+    G = P.grad_matrix(Ut, V) if which == "x" else P.grad_matrix(V, Ut).T
+    kinds = np.array([l[0] for l in P.losses], np.int64)[view.ecode]
+    levels = np.array([l[1] for l in P.losses], np.int64)[view.ecode]
+    curv = np.array([CURVATURE[int(l[0])] for l in P.losses])[view.ecode]
+    slope = np.abs(G[rows, other]) + _kink_steps(kinds, levels, view.val, u, dz) + 0.5 * curv * dz
+    term = slope * dz
+    if view.ew is not None:
+        term = term * view.ew
+    return np.bincount(rows, weights=term, minlength=view.m)
+
+
 def band_rows(P, X, Y, ax, f_old, f_new, prec):
     """Decision band of every row of the X half-step at (X, Y) with step sizes ax."""
     X, Y = np.asarray(X, np.float64), np.asarray(Y, np.float64)
@@ -181,6 +208,8 @@ def band_rows(P, X, Y, ax, f_old, f_new, prec):
     Sp, _ = P.grad_abs(Xp, Y)
     eps = grad_eps(P, "x", X, Y, ax, prec)
     first = np.sum((Sp + _reg_slope(P.rx, Xp, ox)) * eps, axis=1)
+    if prec == "coo_bf16":
+        first = first + trial_bf16_terms(P, "x", X, Xp, Y)
     return 2.0 * first + SUM_REL * (np.abs(f_old) + np.abs(f_new))
 
 
@@ -193,6 +222,8 @@ def band_cols(P, X, Y, ay, h_old, h_new, prec):
     _, Sp = P.grad_abs(X, Yp)
     eps = grad_eps(P, "y", X, Y, ay, prec)
     first = np.sum((Sp + _reg_slope(P.ry, Yp, oy)) * eps, axis=1)
+    if prec == "coo_bf16":
+        first = first + trial_bf16_terms(P, "y", Y, Yp, X)
     return 2.0 * first + SUM_REL * (np.abs(h_old) + np.abs(h_new))
 
 

@@ -65,18 +65,24 @@ def test_gradient_matches_oracle(spec):
 
 
 @pytest.mark.parametrize("spec", CASES)
-def test_one_sweep_matches_oracle(spec):
+@pytest.mark.parametrize("prec", [g.FP32, g.BF16])
+def test_one_sweep_matches_oracle(spec, prec):
     """One sweep from an identical state, every row and column checked (rows
     against the oracle's X half-step, columns against the oracle's Y
-    half-step from the GPU's own X^t; see gpu_helpers.check_sweep)."""
+    half-step from the GPU's own X^t; see gpu_helpers.check_sweep).  BF16:
+    the same trial points, decided on trial objectives from bfloat16 step
+    products (the band carries their rounding)."""
     case = _case(spec, rx=(1, 0.1), ry=(2, 0.05))
     data, X, Y, P = _setup(case)
     ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
     ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
-    info = g.glrm_fit(data, X, Y, ax, ay, 1, precision=g.FP32, alpha_scale=2.0)
+    info = g.glrm_fit(data, X, Y, ax, ay, 1, precision=prec, alpha_scale=2.0)
     ax0, ay0 = init_alpha32(P, 2.0)
     Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
-    check_sweep(P, case.X0, case.Y0, ax0, ay0, Xg, Yg, ax.cpu().numpy(), ay.cpu().numpy(), "fp32", tag=case.name)
+    pname = "fp32" if prec == g.FP32 else "coo_bf16"
+    r = check_sweep(P, case.X0, case.Y0, ax0, ay0, Xg, Yg, ax.cpu().numpy(), ay.cpu().numpy(), pname, tag=case.name)
+    print("%s %s: decisions inside the rounding band: %d rows, %d columns"
+          % (case.name, pname, r["band_rows"], r["band_cols"]))
     assert info["objective"] == pytest.approx(P.objective(Xg, Yg), rel=1e-10)
 
 
@@ -133,12 +139,32 @@ def test_invalid_coo_is_rejected(bad):
     assert ei.value.code == g.EINVAL
 
 
-def test_bf16_is_reported_unsupported_for_coo():
+def test_bf16_plain_is_reported_unsupported_for_coo():
     case = _case(CASES[0])
     data, X, Y, P = _setup(case)
     with pytest.raises(g.GLRMError) as ei:
-        g.glrm_objective(data, X, Y, g.BF16)
+        g.glrm_objective(data, X, Y, g.BF16_PLAIN)
     assert ei.value.code == g.EUNSUPPORTED
+    # BF16 objective and gradient calls compute as FP32
+    assert g.glrm_objective(data, X, Y, g.BF16) == g.glrm_objective(data, X, Y, g.FP32)
+
+
+@pytest.mark.parametrize("spec", [CASES[7], CASES[9], CASES[12]])
+def test_bf16_three_sweeps_checked_sweep_by_sweep(spec):
+    """Three BF16 sweeps, each checked against the oracle from the GPU's
+    state before it."""
+    case = _case(spec, rx=(1, 0.1), ry=(1, 0.1))
+    data, X, Y, P = _setup(case)
+    g.glrm_prepare(data)
+    ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
+    ay = torch.empty(case.n, dtype=torch.float32, device=DEV)
+    Xp, Yp = case.X0.copy(), case.Y0.copy()
+    axp, ayp = init_alpha32(P, 1.0)
+    for t in range(3):
+        g.glrm_fit(data, X, Y, ax, ay, 1, precision=g.BF16, init_alpha=(t == 0), flags=g.WS_PREPARED)
+        Xg, Yg, axg, ayg = X.cpu().numpy(), Y.cpu().numpy(), ax.cpu().numpy(), ay.cpu().numpy()
+        check_sweep(P, Xp, Yp, axp, ayp, Xg, Yg, axg, ayg, "coo_bf16", tag="%s sweep %d" % (case.name, t + 1))
+        Xp, Yp, axp, ayp = Xg, Yg, axg.astype(np.float64), ayg.astype(np.float64)
 
 
 def test_fit_is_bitwise_repeatable():

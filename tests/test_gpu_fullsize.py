@@ -216,7 +216,10 @@ def _coo_row_problem(case, i):
                                    (case.rx[0], F32(case.rx[1])), (0, 0.0))
 
 
-@pytest.mark.parametrize("prec", [g.FP32])
+SPARSE_PNAME = {g.FP32: "fp32", g.BF16: "coo_bf16"}
+
+
+@pytest.mark.parametrize("prec", [g.FP32, g.BF16])
 def test_sparse_completion_one_sweep_sampled(sparse_completion, prec):
     """One sweep of the 4e8-entry COO fit, in the benchmark's launch
     configuration (prepared workspace, one fit call): 300 sampled rows and 40
@@ -235,7 +238,7 @@ def test_sparse_completion_one_sweep_sampled(sparse_completion, prec):
     near = [0, 0]
     for i in synth.sample_indices(5, 300, case.m):
         P = _coo_row_problem(case, i)
-        r = _check_half(P, "x", X0[i:i + 1], Y0, _alpha32([P.nnz]), Xg[i:i + 1], axg[i:i + 1], PNAME[prec],
+        r = _check_half(P, "x", X0[i:i + 1], Y0, _alpha32([P.nnz]), Xg[i:i + 1], axg[i:i + 1], SPARSE_PNAME[prec],
                         tag="row %d" % i)
         near[0] += r[0]
     cols = synth.sample_indices(5, 40, case.n, 1)
@@ -245,9 +248,9 @@ def test_sparse_completion_one_sweep_sampled(sparse_completion, prec):
         P = oracle.Problem.from_coo(case.m, 1, case.k, case.rows[e], np.zeros(e.size, np.int64), case.vals[e],
                                     case.col_loss[j:j + 1], _coo_losses(case), (0, 0.0),
                                     (case.ry[0], F32(case.ry[1])))
-        r = _check_half(P, "y", Y0[j:j + 1], Xg, _alpha32([e.size]), Yg[j:j + 1], ayg[j:j + 1], PNAME[prec],
+        r = _check_half(P, "y", Y0[j:j + 1], Xg, _alpha32([e.size]), Yg[j:j + 1], ayg[j:j + 1], SPARSE_PNAME[prec],
                         tag="column %d" % j)
         near[1] += r[0]
     print("%s %s: decisions inside the rounding band: %d of 300 rows, %d of 40 columns"
-          % (case.name, PNAME[prec], near[0], near[1]))
+          % (case.name, SPARSE_PNAME[prec], near[0], near[1]))
     assert np.isfinite(info["objective"])
