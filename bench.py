@@ -23,9 +23,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "xstep_counters_dense_quadratic.txt")
 IMPUTE_COUNTERS = {"impute": os.path.join(ROOT, "profiles", "impute_counters_heterogeneous.txt"),
                    "impute_dense": os.path.join(ROOT, "profiles", "impute_counters_dense_quadratic.txt")}
+# HBM bytes per launch of each workload's dominant kernel, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs scaled by a plain copy's reading; a line is used
+# only while the kernel's sources and flags hash to what they were then.
+HBM_COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.txt")
+
+# The dominant kernel of each sweep workload, its sources (for the hash) and
+# its algorithmic bytes per launch (one read of every observed entry's data:
+# dense 4 B value + 1 B mask per table entry, COO 4 + 4 B indices + 4 B value
+# per entry; plus reading and writing the walked factor and its step sizes).
+DOMINANT = {
+    "dense": dict(kernel="xstep_kernel", desc="xstep (fused row pass)",
+                  files=("dense_kernels.h", "dense_prec.hip", "glrm_device.h", "glrm_kernels.h"),
+                  bytes=lambda c: 5.0 * c.m * c.n + 8.0 * c.m * c.k + 8.0 * c.m),
+    "coo": dict(kernel="walk_kernel", desc="walk_kernel (row walk: gradient, step, trial, decision)",
+                files=("coo.hip", "coo.h", "glrm_device.h"),
+                bytes=lambda c: 12.0 * c.nnz + 8.0 * c.m * c.k + 8.0 * c.m),
+    "grad": dict(kernel="lossgrad_kernel", desc="lossgrad (objective and both gradients, one pass)",
+                 files=("dense_kernels.h", "dense_prec.hip", "glrm_device.h", "glrm_kernels.h"),
+                 bytes=lambda c: 5.0 * c.m * c.n + 8.0 * c.m * c.k + 8.0 * c.n * c.k),
+}
 
 
 def log(*a):
@@ -40,13 +59,17 @@ def _code_only(text):
     return "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
 
 
-def kernel_source_hash(read=None, unit="dense"):
+def kernel_source_hash(read=None, unit="dense", files=None, prec_flags=None):
     """Hash of the code of a kernel's sources (comments ignored) and of the
     compiler flags it is built with (include paths left out).  ``unit`` is
-    "dense" (the benchmark's split-BF16 instances) or "impute"."""
+    "dense" (the benchmark's split-BF16 instances) or "impute"; or give the
+    ``files`` (and the dense precision's flags, ``prec_flags`` = (prec, lks))."""
     from paper_1410_0342_amd import build as B
     h = hashlib.sha256()
-    if unit == "impute":
+    if files is not None:
+        extra = B.dense_prec_flags(*prec_flags) if prec_flags else []
+        flags = [f for f in B.FLAGS + extra if not f.startswith("-I")]
+    elif unit == "impute":
         flags = [f for f in B.FLAGS if not f.startswith("-I")]
         files = ("impute.hip", "impute.h", "glrm_device.h")
     else:
@@ -62,6 +85,30 @@ def kernel_source_hash(read=None, unit="dense"):
             text = read(rel)
         h.update(_code_only(text).encode())
     return h.hexdigest()[:16]
+
+
+def _prec_flags(kind, pname, case):
+    """(precision, loss set) of the dense instances a run uses, for the hash."""
+    if kind == "coo":
+        return None
+    p = {"fp32": 0, "bf16": 1, "bf16_plain": 3}[pname]
+    lks = 0 if (case.col_loss is None or len(case.losses) == 1) and case.losses[0][0] == 0 else 1
+    return (p, lks)
+
+
+def counter_traffic(kind, workload_name, pname, case):
+    """HBM bytes per launch of the dominant kernel (fetched + written), if the
+    committed counters match the current sources; else None."""
+    d = DOMINANT[kind]
+    if not os.path.exists(HBM_COUNTERS):
+        return None
+    h = kernel_source_hash(files=d["files"], prec_flags=_prec_flags(kind, pname, case))
+    for line in open(HBM_COUNTERS).read().splitlines():
+        f = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
+        if (f.get("kernel") == d["kernel"] and f.get("workload") == workload_name and f.get("precision") == pname
+                and f.get("hash") == h):
+            return float(f["fetch_bytes"]) + float(f["write_bytes"])
+    return None
 
 
 def workload(name):
@@ -229,19 +276,36 @@ def copy_calibration():
     log("copy calibration: 5 copies of %d bytes" % (src.numel() * 4))
 
 
-def cpu_baseline(case, rows, sweeps):
-    """The FP64 oracle on the first `rows` rows of the same workload."""
+def _sub_problem(case, rows):
+    """The oracle's problem on the first `rows` rows of the workload."""
     import numpy as np
 
     import oracle
+    if case.layout == "coo":
+        hi = int(np.searchsorted(case.rows, rows))
+        return oracle.Problem.from_coo(rows, case.n, case.k, case.rows[:hi], case.cols[:hi], case.vals[:hi],
+                                       case.col_loss, case.losses, case.rx, case.ry)
     sub_mask = None if case.mask is None else case.mask[:rows]
-    P = oracle.Problem.from_dense(case.A[:rows], sub_mask, case.k, case.col_loss, case.losses, case.rx, case.ry)
+    return oracle.Problem.from_dense(case.A[:rows], sub_mask, case.k, case.col_loss, case.losses, case.rx, case.ry)
+
+
+def cpu_baseline(case, rows, sweeps, grad_only=False):
+    """The FP64 oracle (as it stands, one thread) on the first `rows` rows of
+    the same workload: `sweeps` sweeps of Algorithm 2, or with ``grad_only``
+    that many objective-and-gradient evaluations."""
+    import numpy as np
+
+    P = _sub_problem(case, rows)
     X = case.X0[:rows].astype(np.float64).copy()
     Y = case.Y0.astype(np.float64).copy()
     ax, ay = P.init_alpha(1.0)
     t0 = time.perf_counter()
     for _ in range(sweeps):
-        P.sweep(X, Y, ax, ay)
+        if grad_only:
+            P.objective(X, Y)
+            P.grad(X, Y)
+        else:
+            P.sweep(X, Y, ax, ay)
     dt = time.perf_counter() - t0
     cpu = "unknown"
     try:
@@ -249,9 +313,10 @@ def cpu_baseline(case, rows, sweeps):
             cpu = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), cpu)
     except OSError:
         pass
+    what = "objective-and-gradient evaluation(s)" if grad_only else "sweep(s)"
     return dict(value=P.nnz * sweeps / dt, unit="entries/s", cores=1, kind="oracle",
-                sample="first %d of %d rows (%d observed entries), %d sweep(s) of the FP64 oracle, "
-                       "single thread, %.1f s" % (rows, case.m, P.nnz, sweeps, dt),
+                sample="first %d of %d rows (%d observed entries), %d %s of the FP64 oracle, "
+                       "single thread, %.1f s" % (rows, case.m, P.nnz, sweeps, what, dt),
                 cpu=cpu, host_cpus=os.cpu_count())
 
 
@@ -282,7 +347,8 @@ def main():
     log("workload %s: m=%d n=%d k=%d observed=%d (generated in %.1f s)"
         % (case.name, case.m, case.n, case.k, case.nnz, time.perf_counter() - t0))
     if case.layout == "coo":
-        precisions = ["fp32"]
+        # the sparse walks: FP32 (the faster form there) heads the line, BF16 beside it
+        precisions = ["fp32", "bf16"] if args.precision == "both" else [args.precision]
     else:
         precisions = ["bf16", "fp32"] if args.precision == "both" else [args.precision]
     if args.workload in ("impute", "impute_dense"):
@@ -324,7 +390,7 @@ def main():
         head = precisions[0]
         r = res[head]
         m, n, k = case.m, case.n, case.k
-        alg_bytes = 4.0 * m * n + 8.0 * m * k + 8.0 * n * k   # table, X and dX, Y and dY
+        alg_bytes = DOMINANT["grad"]["bytes"](case)   # table and mask, X and dX, Y and dY
         achieved = alg_bytes / (r["ms_per_step"] * 1e-3) / 1e9
         line = {
             "metric": "observed entries/s per objective and gradient evaluation",
@@ -333,13 +399,17 @@ def main():
             "dtype": "bf16" if head.startswith("bf16") else "f32", "data": "synthetic",
             "config": {"workload": case.name, "m": m, "n": n, "k": k, "observed_entries": int(case.nnz),
                        "layout": "dense", "precision": head},
-            "roofline": {"bound": "hbm", "kernel": "objective and gradient call (all its kernels)",
+            "roofline": {"bound": "hbm", "kernel": "objective and gradient call (one lossgrad pass + reductions)",
                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": None, "algorithmic_bytes_per_launch": alg_bytes},
+                         "traffic": counter_traffic("grad", args.workload, head, case),
+                         "algorithmic_bytes_per_launch": alg_bytes},
             "objective": {p: res[p]["objective"] for p in res},
         }
         if "fp32" in res and head != "fp32":
             line["fp32"] = {"value": res["fp32"]["value"], "ms_per_step": res["fp32"]["ms_per_step"]}
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = cpu_baseline(case, min(args.cpu_rows // 10, case.m), args.cpu_sweeps,
+                                                grad_only=True)
         print(json.dumps(line), flush=True)
         return
     res = run_gpu(case, precisions, args.steps, args.warmup)
@@ -349,23 +419,13 @@ def main():
     head = precisions[0]
     r = res[head]
     m, n, k = case.m, case.n, case.k
-    # dominant kernel: the fused row pass (kernel kind 0)
+    kind = "dense" if case.layout == "dense" else "coo"
+    dom = DOMINANT[kind]
+    # dominant kernel: the row pass (kernel kind 0), timed with HIP events on the fit's stream
     calls = max(r["kernel_calls"][0], 1)
     avg_ms = r["kernel_ms"][0] / calls
-    if case.layout == "dense":
-        alg_bytes = 4.0 * m * n + 8.0 * m * k + 8.0 * m
-    else:
-        alg_bytes = 12.0 * case.nnz + 8.0 * m * k + 8.0 * m
+    alg_bytes = dom["bytes"](case)
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(PROFILE_COUNTERS) and args.workload == "dense_quadratic":
-        try:
-            pc = dict(l.split(":", 1) for l in open(PROFILE_COUNTERS).read().splitlines() if ":" in l)
-            pc = {k.strip(): v.strip() for k, v in pc.items()}
-            if pc.get("kernel_source_hash") == kernel_source_hash() and pc.get("precision") == head:
-                traffic = float(pc["traffic_bytes_per_launch"])
-        except (OSError, ValueError, KeyError):
-            traffic = None
     line = {
         "metric": "observed entries/s per prox-grad sweep, bf16-MFMA vs fp32 at equal objective",
         "value": r["value"],
@@ -382,34 +442,70 @@ def main():
         "config": {"workload": case.name, "m": m, "n": n, "k": k, "observed_entries": case.nnz,
                    "layout": case.layout, "precision": head,
                    "sweeps_timed": args.steps, "sweeps_total": args.steps + args.warmup},
-        "roofline": {"bound": "hbm", "kernel": "xstep (fused row pass)", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": dom["desc"], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": alg_bytes},
+                     "traffic": counter_traffic(kind, args.workload, head, case), "avg_launch_ms": avg_ms,
+                     "algorithmic_bytes_per_launch": alg_bytes},
         "objective": {p: res[p]["objective"] for p in res},
     }
-    if "bf16" in res and "fp32" in res:
-        fb, ff = res["bf16"]["objective"], res["fp32"]["objective"]
-        hb = res["bf16"]["history"]
-        # sweeps the BF16 fit needs to reach the FP32 fit's final objective (within 1e-3)
+    if len(res) == 2:
+        other = precisions[1]
+        # equal objective: both forms from the same seeded start for at least
+        # CMP_SWEEPS sweeps (the timed run's own count when it is longer)
+        cmp_sweeps = max(args.steps + args.warmup, 200 if kind == "dense" else 50)
+        if cmp_sweeps == args.steps + args.warmup:
+            hist = {p: res[p]["history"] for p in res}
+            fin = {p: res[p]["objective"] for p in res}
+            offset = args.warmup
+        else:
+            hist, fin = compare_fits(case, precisions, cmp_sweeps)
+            offset = 0
+        fb, ff = fin.get("bf16"), fin.get("fp32")
+        hb = hist["bf16"]
         reach = [i for i, v in enumerate(hb) if v <= ff * (1 + 1e-3)]
-        sweeps_to = (reach[0] + 1 + args.warmup) if reach else None
+        sweeps_to = (reach[0] + 1 + offset) if reach else None
         line["equal_objective"] = {
-            "bf16": fb, "fp32": ff, "rel_diff": (fb - ff) / abs(ff),
+            "sweeps": cmp_sweeps, "bf16": fb, "fp32": ff, "rel_diff": (fb - ff) / abs(ff),
             "bf16_no_worse_within_1e-3": fb <= ff * (1 + 1e-3),
-            "bf16_sweeps_to_fp32_objective": sweeps_to, "fp32_sweeps": args.steps + args.warmup,
+            "bf16_sweeps_to_fp32_objective": sweeps_to,
             "time_to_equal_objective_speedup": (
-                (res["fp32"]["ms_per_step"] * (args.steps + args.warmup)) / (res["bf16"]["ms_per_step"] * sweeps_to)
+                (res["fp32"]["ms_per_step"] * cmp_sweeps) / (res["bf16"]["ms_per_step"] * sweeps_to)
                 if sweeps_to else None)}
-        line["fp32"] = {"value": res["fp32"]["value"], "ms_per_step": res["fp32"]["ms_per_step"]}
+        line[other] = {"value": res[other]["value"], "ms_per_step": res[other]["ms_per_step"]}
         line["rejected_last_sweep"] = {p: {"rows": res[p]["rows_rejected"], "cols": res[p]["cols_rejected"]}
-                                       for p in ("bf16", "fp32")}
+                                       for p in res}
         line["bf16_over_fp32"] = res["bf16"]["value"] / res["fp32"]["value"]
     line["kernel_ms_per_sweep"] = {p: res[p]["kernel_ms"] for p in res}
     line["sweep_ms_p10_p50_p90"] = {p: res[p]["sweep_ms_p10_p50_p90"] for p in res}
-    if not args.no_cpu_baseline and case.layout == "dense":
+    if not args.no_cpu_baseline:
         rows = min(args.cpu_rows, case.m)
         line["cpu_baseline"] = cpu_baseline(case, rows, args.cpu_sweeps)
     print(json.dumps(line), flush=True)
+
+
+def compare_fits(case, precisions, sweeps):
+    """Both forms from the seeded start for `sweeps` sweeps (untimed):
+    per-sweep objective histories and the final FP64 objectives."""
+    import torch
+
+    import paper_1410_0342_amd as g
+
+    dev = torch.device("cuda:0")
+    data = g.Data.from_case(case, dev)
+    g.glrm_prepare(data)
+    hist, fin = {}, {}
+    for pname in precisions:
+        X = torch.from_numpy(case.X0).to(dev)
+        Y = torch.from_numpy(case.Y0).to(dev)
+        ax = torch.empty(case.m, dtype=torch.float32, device=dev)
+        ay = torch.empty(case.n, dtype=torch.float32, device=dev)
+        h = torch.zeros(sweeps, dtype=torch.float64, device=dev)
+        info = g.glrm_fit(data, X, Y, ax, ay, sweeps, precision=g.PRECISIONS[pname], init_alpha=True,
+                          flags=g.WS_PREPARED, history=h)
+        hist[pname] = h.cpu().numpy()
+        fin[pname] = info["objective"]
+        log("equal-objective run, %s: F after %d sweeps = %.10g" % (pname, sweeps, info["objective"]))
+    return hist, fin
 
 
 if __name__ == "__main__":

@@ -51,6 +51,10 @@ constexpr int AUX_SMALL = 16 * LA_MAXB * LA_MAXB;  // doubles of small matrices 
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+#ifndef GLRM_GRAD_TMAX64
+#define GLRM_GRAD_TMAX64 4
+#endif
+
 int kp_of(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
 
 // Tiles per wavefront of the two passes of the fit: the fused row pass runs
@@ -123,7 +127,7 @@ bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false, int aux_
     // the gradient pass: xstep_waves(kp) wavefronts of up to 16 tiles (4 at
     // kp = 64); wider tables take several column blocks
     {
-        const int tmax = L.kp == 64 ? 4 : 16, nw = xstep_waves((int)L.kp);
+        const int tmax = L.kp == 64 ? GLRM_GRAD_TMAX64 : 16, nw = xstep_waves((int)L.kp);
         int t = 1;
         while (t < tmax && (int64_t)nw * t < ntiles) t *= 2;
         L.tpw_grad = t;
