@@ -127,7 +127,88 @@ def workload(name):
         return synth.heterogeneous()
     if name == "impute_dense":
         return synth.dense_quadratic()
+    if name in ("proxprox", "linalg"):
+        return synth.dense_quadratic()
+    if name == "census":
+        return synth.census_like()
     raise SystemExit("unknown workload " + name)
+
+
+def run_adjacent(name, case, steps, warmup):
+    """The adjacent steps on full-size workloads, timed with HIP events on
+    the stream the calls run on.  proxprox: sweeps of the prox-prox update
+    (FP32, one inner solve) beside prox-grad FP32 from the same start;
+    linalg: column scaling, SVD initialization and the certificate on the
+    dense quadratic table; census: sweeps of the multi-dimensional-loss fit."""
+    import numpy as np
+    import torch
+
+    import paper_1410_0342_amd as g
+
+    dev = torch.device("cuda:0")
+    data = g.Data.from_case(case, dev)
+    if case.notes.get("offset"):
+        data = data.variant(offset=True)
+    g.glrm_prepare(data)
+    st = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    if name == "linalg":
+        mu, s2 = g.glrm_column_scaling(data)
+        out["column_scaling_ms"] = timed(lambda: g.glrm_column_scaling(data, mu, s2, flags=g.WS_PREPARED), 3)
+        k = case.k
+        gen = torch.Generator().manual_seed(0)
+        omega = torch.randn((case.n, k + 10), generator=gen, dtype=torch.float32).to(dev)
+        res = {}
+
+        def init():
+            res["X"], res["Y"], res["sv"] = g.glrm_init_svd(data, omega, mu, s2, power_iters=2, flags=g.WS_PREPARED)
+        out["init_svd_ms"] = timed(init, 3)
+        cdata = data.with_regs((1, 0.1), (1, 0.1))
+        g.glrm_prepare(cdata)
+        cert = {}
+
+        def certify():
+            cert["info"] = g.glrm_certificate(cdata, res["X"], res["Y"], iters=100, flags=g.WS_PREPARED)
+        out["certificate_100_iters_ms"] = timed(certify, 3)
+        out["certificate_norm"] = cert["info"]["norm"]
+        out["top_singular_values"] = [float(v) for v in np.asarray(res["sv"])[:3]]
+        for kname, v in out.items():
+            if kname.endswith("_ms"):
+                log("%s: %.3f ms" % (kname, v))
+        return out
+    precs = {"proxprox": [("proxprox_fp32", g.FP32, g.UPDATE_PROXPROX), ("proxgrad_fp32", g.FP32, g.UPDATE_PROXGRAD)],
+             "census": [("bf16", g.BF16, g.UPDATE_PROXGRAD), ("fp32", g.FP32, g.UPDATE_PROXGRAD)]}[name]
+    for tag, prec, upd in precs:
+        X = torch.from_numpy(case.X0).to(dev)
+        Y = torch.from_numpy(case.Y0).to(dev)
+        ax = torch.empty(case.m, dtype=torch.float32, device=dev)
+        ay = torch.empty(data.d, dtype=torch.float32, device=dev)
+        g.glrm_fit(data, X, Y, ax, ay, warmup, precision=prec, init_alpha=True, flags=g.WS_PREPARED, update=upd)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        info = g.glrm_fit(data, X, Y, ax, ay, steps, precision=prec, init_alpha=False, flags=g.WS_PREPARED,
+                          update=upd)
+        e1.record(st)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / max(steps, 1)
+        out[tag] = dict(ms_per_step=ms, value=case.nnz / (ms * 1e-3), objective=info["objective"],
+                        rows_rejected=info["rows_rejected"], cols_rejected=info["cols_rejected"])
+        log("%s: %.4f ms/sweep, %.4g entries/s, F after %d sweeps = %.10g"
+            % (tag, ms, out[tag]["value"], steps + warmup, info["objective"]))
+    return out
 
 
 def run_gpu(case, precisions, steps, warmup):
@@ -320,6 +401,27 @@ def cpu_baseline(case, rows, sweeps, grad_only=False):
                 cpu=cpu, host_cpus=os.cpu_count())
 
 
+def census_cpu_baseline(case, rows, sweeps):
+    """The feature-level FP64 oracle (one thread) on the first `rows` rows."""
+    import numpy as np
+
+    import oracle
+    feats = [tuple(case.losses[int(c)]) for c in case.col_loss]
+    M = oracle.MDProblem(case.A[:rows], case.mask[:rows], case.k, feats, case.rx, case.ry,
+                         offset=bool(case.notes.get("offset")))
+    X = case.X0[:rows].astype(np.float64).copy()
+    Y = case.Y0.astype(np.float64).copy()
+    ax, af = M.init_alpha(1.0)
+    t0 = time.perf_counter()
+    for _ in range(sweeps):
+        M.half_step_x(X, Y, ax)
+        M.half_step_y(X, Y, af)
+    dt = time.perf_counter() - t0
+    return dict(value=M.nnz * sweeps / dt, unit="entries/s", cores=1, kind="oracle",
+                sample="first %d of %d rows (%d observed values), %d sweep(s) of the feature-level FP64 oracle, "
+                       "single thread, %.1f s" % (rows, case.m, M.nnz, sweeps, dt))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,7 +429,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dense_quadratic",
                     choices=["dense_quadratic", "heterogeneous", "sparse_completion", "plain_pca", "autograd",
-                             "impute", "impute_dense"])
+                             "impute", "impute_dense", "proxprox", "linalg", "census"])
     ap.add_argument("--precision", default="both", choices=["both", "bf16", "fp32", "bf16_plain"])
     ap.add_argument("--cpu-rows", type=int, default=100000)
     ap.add_argument("--cpu-sweeps", type=int, default=2)
@@ -351,6 +453,27 @@ def main():
         precisions = ["fp32", "bf16"] if args.precision == "both" else [args.precision]
     else:
         precisions = ["bf16", "fp32"] if args.precision == "both" else [args.precision]
+    if args.workload in ("proxprox", "linalg", "census"):
+        res = run_adjacent(args.workload, case, args.steps, args.warmup)
+        if args.workload == "linalg":
+            line = {"metric": "time per call of the linear-algebra steps (Sections 4.3, 7.5, 7.6)",
+                    "value": res["init_svd_ms"], "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+                    "steps": 3, "warmup": 1, "data": "synthetic", "dtype": "f32/f64",
+                    "config": {"workload": "linalg_" + case.name, "m": case.m, "n": case.n, "k": case.k}}
+            line.update(res)
+        else:
+            head = next(iter(res))
+            line = {"metric": "observed entries/s per sweep", "value": res[head]["value"], "unit": "entries/s",
+                    "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                    "ms_per_step": res[head]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                    "vs_baseline": None, "dtype": "bf16" if head == "bf16" else "f32", "data": "synthetic",
+                    "config": {"workload": args.workload + "_" + case.name, "m": case.m, "n": case.n, "k": case.k,
+                               "observed_entries": int(case.nnz), "precision": head}}
+            line.update(res)
+            if not args.no_cpu_baseline and args.workload == "census":
+                line["cpu_baseline"] = census_cpu_baseline(case, min(args.cpu_rows * 10, case.m), args.cpu_sweeps)
+        print(json.dumps(line), flush=True)
+        return
     if args.workload in ("impute", "impute_dense"):
         res = run_impute(case, args.steps, args.warmup)
         if args.copy_calibration:
