@@ -43,7 +43,7 @@ extern "C" {
 /* ---- return codes ----------------------------------------------------------- */
 #define GLRM_OK            0
 #define GLRM_EINVAL       -1  /* null pointer, bad size, bad kind, unsorted / out-of-range COO, bad loss code */
-#define GLRM_EUNSUPPORTED -2  /* valid request outside what is built (e.g. k > 64, dense fit with n > 1024) */
+#define GLRM_EUNSUPPORTED -2  /* valid request outside what is built (e.g. k > 64, layout or loss combination not built) */
 #define GLRM_ENOMEM       -3  /* workspace smaller than glrm_workspace_size() */
 #define GLRM_EHIP         -4  /* a HIP runtime call failed; the message names it */
 
@@ -343,9 +343,11 @@ size_t glrm_fit_workspace_size(const glrm_data *d, const glrm_fit_opts *opts);
  * arrays updated in place, so a second call resumes the fit.  history
  * (device, max_sweeps doubles, may be NULL) receives F after each sweep as the
  * sweep tracked it.  info_host (host, may be NULL) is filled at the end.
- * The dense layout keeps a table row's tiles on one workgroup: it fits
- * n <= 1024 for k <= 32 and n <= 512 for k <= 64 and returns
- * GLRM_EUNSUPPORTED above (the COO layout has no such limit).
+ * The dense layout takes any width.  Up to n = 1024 for k <= 32 and
+ * n = 512 for k <= 64 one fused pass does the row half-step (a table row's
+ * tiles stay on one workgroup); wider tables take it in column blocks, in
+ * three passes over the table with the row steps and decisions between them
+ * (the same arithmetic, with row sums over the blocks in block order).
  *
  * With opts->update = GLRM_UPDATE_PROXPROX (Section 7.2, "Prox-prox method";
  * Section 7.3) every row i instead forms G_i = sum_j w_j y_j y_j^T and

@@ -34,6 +34,93 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a)
     }
 }
 
+// S4 of the row half-step in column blocks: each row's gradient and loss sum
+// over the column blocks (in block order), the prox step to the trial row and
+// the regularizer at both.  Sixteen lanes per row, coordinates c0 + 16 q.
+__global__ __launch_bounds__(256) void xwide_step_kernel(XWideRowArgs a)
+{
+    const int ri = threadIdx.x >> 4, c0 = threadIdx.x & 15;
+    const int64_t i = (int64_t)blockIdx.x * 16 + ri;
+    const bool rv = i < a.m;
+    const float al = rv ? a.alpha[i] : 0.0f;
+    float rc = 0.0f, rcp = 0.0f;
+#pragma unroll
+    for (int q = 0; q < GLRM_MAXK_DEV / 16; ++q) {
+        const int c = c0 + 16 * q;
+        const bool ok = rv && c < a.k;
+        float gs = 0.0f, x = 0.0f;
+        if (ok) {
+            for (int b = 0; b < a.ncb; ++b) gs += a.part_dx[((int64_t)b * a.m + i) * a.k + c];
+            x = a.X[i * a.k + c];
+        }
+        const float xv = ok ? prox_elem(a.rx, al, x - al * gs, c) : 0.0f;
+        if (ok) a.Xp[i * a.k + c] = xv;
+        rc += ok ? reg_elem(a.rx, x, c) : 0.0f;
+        rcp += ok ? reg_elem_trial(a.rx, xv, c) : 0.0f;
+    }
+    rc = row16_sum(rc);
+    rcp = row16_sum(rcp);
+    if (c0 == 0 && rv) {
+        float f = 0.0f;
+        for (int b = 0; b < a.ncb; ++b) f += a.part_f[(int64_t)b * a.mp + i];
+        a.rsum[i] = f;
+        a.rsum[a.mp + i] = rc;
+        a.rsum[2 * a.mp + i] = rcp;
+    }
+}
+
+// The step rule of the rows (S5): keep the trial row if its objective (loss
+// sum over the column blocks, in block order, plus r) does not exceed the
+// old one; step sizes move by step_up / step_down.  A fixed grid of 16-row
+// panels, so the per-workgroup sums of the decided rows' regularizers and of
+// the rejections come in a fixed number and order.
+__global__ __launch_bounds__(256) void xwide_decide_kernel(XWideRowArgs a)
+{
+    __shared__ float s_r[4];
+    __shared__ int s_j[4];
+    const int ri = threadIdx.x >> 4, c0 = threadIdx.x & 15;
+    float rr = 0.0f;
+    int rj = 0;
+    for (int64_t p = blockIdx.x; p * 16 < a.m; p += gridDim.x) {
+        const int64_t i = p * 16 + ri;
+        const bool rv = i < a.m;
+        bool acc = false;
+        float rx = 0.0f, rxp = 0.0f;
+        if (rv) {
+            float fp = 0.0f;
+            for (int b = 0; b < a.ncb; ++b) fp += a.part_fp[(int64_t)b * a.mp + i];
+            rx = a.rsum[a.mp + i];
+            rxp = a.rsum[2 * a.mp + i];
+            const float f = a.rsum[i] + rx;
+            fp += rxp;
+            acc = fp <= f;
+        }
+#pragma unroll
+        for (int q = 0; q < GLRM_MAXK_DEV / 16; ++q) {
+            const int c = c0 + 16 * q;
+            if (acc && c < a.k) a.X[i * a.k + c] = a.Xp[i * a.k + c];
+        }
+        if (c0 == 0 && rv) {
+            const float al = a.alpha[i];
+            a.alpha[i] = acc ? al * a.step_up : al * a.step_down;
+            rr += acc ? rxp : rx;
+            rj += acc ? 0 : 1;
+        }
+    }
+    rr = sum_lanes<64>(rr);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) rj += __shfl_xor(rj, o, 64);
+    if ((threadIdx.x & 63) == 0) {
+        s_r[threadIdx.x >> 6] = rr;
+        s_j[threadIdx.x >> 6] = rj;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.part_rowreg[blockIdx.x] = ((s_r[0] + s_r[1]) + s_r[2]) + s_r[3];
+        a.part_rej[blockIdx.x] = s_j[0] + s_j[1] + s_j[2] + s_j[3];
+    }
+}
+
 __global__ __launch_bounds__(256) void reduce_dx_kernel(ReduceArgs a)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -103,6 +190,7 @@ template <int PREC> hipError_t launch_yprox_p(const YProxArgs &, int, hipStream_
 template <int PREC> hipError_t launch_yaccept_p(const YAcceptArgs &, int, int, hipStream_t);
 template <int PREC> hipError_t launch_yshadow_p(const YShadowArgs &, int, hipStream_t);
 template <int PREC, int LKS> hipError_t launch_lossgrad_p(const LossGradArgs &, int, int, bool, int, int, hipStream_t);
+template <int PREC, int LKS> hipError_t launch_xwide_p(const XWideArgs &, int, int, int, int, int, hipStream_t);
 
 #define GLRM_BY_PREC(PV, CALL)                                      \
     switch (PV) {                                                   \
@@ -169,6 +257,28 @@ hipError_t launch_lossgrad(const LossGradArgs &a, int kp, int tpw, int prec, boo
                         : launch_lossgrad_p<P, 1>(a, kp, tpw, want_grad, gx, gy, st))
     GLRM_BY_PREC(prec, C_)
 #undef C_
+}
+
+hipError_t launch_xwide(const XWideArgs &a, int mode, int kp, int tpw, int prec, int gx, int gy, hipStream_t st)
+{
+    const int lks = loss_set(a.lu);
+#define C_(P) (lks == 0 ? launch_xwide_p<P, 0>(a, mode, kp, tpw, gx, gy, st) \
+                        : launch_xwide_p<P, 1>(a, mode, kp, tpw, gx, gy, st))
+    GLRM_BY_PREC(prec, C_)
+#undef C_
+}
+
+hipError_t launch_xwide_step(const XWideRowArgs &a, hipStream_t st)
+{
+    const int blocks = (int)((a.m + 15) / 16);
+    hipLaunchKernelGGL(xwide_step_kernel, dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_xwide_decide(const XWideRowArgs &a, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(xwide_decide_kernel, dim3(grid), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_dy(const ReduceArgs &a, int kp, hipStream_t st)

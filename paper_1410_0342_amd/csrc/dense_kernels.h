@@ -1364,6 +1364,213 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void lossgrad_kernel(LossGradArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// the row half-step in column blocks (tables wider than the fused row pass
+// holds, whose wavefronts keep every tile of a row's Y operands resident)
+// ---------------------------------------------------------------------------
+// Three passes over the table on a grid of row chunks x column blocks of
+// NWX_OF<KP> * TPW tiles, as the gradient pass:
+//   MODE 0  at X: each row's loss sum and gradient over the block (S1-S3)
+//   MODE 1  at the trial rows X+: each row's loss sum over the block (S5)
+//   MODE 2  at the decided rows: each column's loss sum and Y-gradient
+//           partial over the workgroup's rows (S6)
+// with the row steps (S4) and the decisions between them, in dense.hip.  The
+// sums over column blocks are taken there, in block order.
+template <int KP, int TPW, int PREC>
+struct WideShared {
+    float red_g[NWX_OF<KP>][16][RS<KP>];   // MODE 0: dX partials of the panel
+    float red_f[NWX_OF<KP>][16];           // MODE 0, 1: row loss partials of the panel
+    LossTab lt;
+    uint8_t s_codes[16 * NWX_OF<KP> * TPW];
+    int8_t s_tcode[NWX_OF<KP> * TPW];
+};
+
+template <int KP, int TPW, int PREC, int LK, int MODE>
+__device__ __forceinline__ void xwide_tiles(const XWideArgs &a, PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ nxt,
+                                            int64_t p_next, const PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ cur,
+                                            int rows, int tile0, int nt, float *__restrict__ red_g,
+                                            float *__restrict__ red_f, const LossTab *__restrict__ lt,
+                                            const uint8_t *__restrict__ s_codes, const int8_t *__restrict__ s_tcode,
+                                            const Frag<KP, PREC> (&yfr)[TPW], const YtFrag<KP, PREC> (&ytf)[TPW],
+                                            f32x4 (&dyacc)[TPW][KP / 16], float (&hacc)[TPW])
+{
+    constexpr bool SWZ = MODE == 2;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, g = lane >> 4;
+    constexpr int C = KP / 4;
+    const int k = a.k;
+    // row li's coordinates g C .. g C + C - 1: the A operand of z in MODE 2,
+    // the B operand otherwise
+    Frag<KP, PREC> xf;
+    {
+        float xv[C];
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int c = g * C + q;
+            xv[q] = (li < rows && c < k) ? cur->xrow[li * k + c] : 0.0f;
+        }
+        frag_from_f32<KP, PREC>(xf, xv);
+    }
+    XatFrag<KP, PREC> xa;   // MODE 2: rows 4g + q at coordinates 16 kb + li (B operand of dY)
+    if constexpr (MODE == 2) {
+#pragma unroll
+        for (int kb = 0; kb < KP / 16; ++kb) {
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 4 * g + q, c = 16 * kb + li;
+                v[q] = (i < rows && c < k) ? cur->xrow[i * k + c] : 0.0f;
+            }
+            if constexpr (PREC == P_FP32) xa.f[kb] = float4{v[0], v[1], v[2], v[3]};
+            else xa.b[kb] = pack_bf16x4(v[0], v[1], v[2], v[3]);
+        }
+    }
+    if (p_next >= 0)
+        stage_panel<KP, TPW, NWX_OF<KP>, SWZ>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, p_next, w, lane, tile0);
+    const float4 *apan = cur->apan[w];
+    float opart = 0.0f;
+    f32x4 dx[KP / 16];
+#pragma unroll
+    for (int kb = 0; kb < KP / 16; ++kb) dx[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // software pipelined as the fused row pass
+    f32x4 zn = MODE == 2 ? zprod<KP, PREC>(xf, yfr[0]) : zprod<KP, PREC>(yfr[0], xf);
+    float4 an = MODE == 2 ? tile_entries_t(apan, 0, li, g) : apan[lane];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = tile0 + w + NWX_OF<KP> * s;
+        const f32x4 z = zn;
+        const float4 av = an;
+        if (s + 1 < TPW) {
+            zn = MODE == 2 ? zprod<KP, PREC>(xf, yfr[s + 1]) : zprod<KP, PREC>(yfr[s + 1], xf);
+            an = MODE == 2 ? tile_entries_t(apan, s + 1, li, g) : apan[(s + 1) * 64 + lane];
+        }
+        if (t >= nt) continue;
+        float L4[4], G[4];
+        tile_loss<LK, MODE != 1, MODE == 2, TPW>(a.lu, *lt, s_codes, s_tcode, t - tile0, z, av, L4, G, t);
+        const float l4 = (L4[0] + L4[1]) + (L4[2] + L4[3]);
+        if constexpr (MODE == 2) {
+            hacc[s] += l4;
+            s6_resident<KP, PREC>(dyacc[s], G, xa);
+        } else {
+            opart += l4;
+            if constexpr (MODE == 0) s3_resident<KP, PREC>(dx, G, ytf[s]);
+        }
+    }
+    if constexpr (MODE != 2) {
+        // row li: the four lane groups' partials (the same sum in every lane)
+        opart += __shfl_xor(opart, 16, 64);
+        opart += __shfl_xor(opart, 32, 64);
+        if (g == 0) red_f[w * 16 + li] = opart;
+    }
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int kb = 0; kb < KP / 16; ++kb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red_g[(w * 16 + 4 * g + r) * RS<KP> + 16 * kb + li] = dx[kb][r];
+    }
+}
+
+template <int KP, int TPW, int PREC, int LK, int MODE>
+__global__ __launch_bounds__(NTX_OF<KP>, 1) void xwide_kernel(XWideArgs a)
+{
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, g = lane >> 4;
+    constexpr bool SWZ = MODE == 2;
+    __shared__ WideShared<KP, TPW, PREC> sh;
+    // the panel buffers, LDS objects of their own (as in the fused row pass)
+    __shared__ PanelBuf<KP, TPW, NWX_OF<KP>> sbuf0;
+    __shared__ PanelBuf<KP, TPW, NWX_OF<KP>> sbuf1;
+    const int nt = (int)(a.ldp / 16);
+    const int64_t npanels = a.mp / 16;
+    const int64_t G = gridDim.x;
+    const int cb = (int)blockIdx.y;
+    const int tile0 = cb * NWX_OF<KP> * TPW;
+    const int ntb = min(NWX_OF<KP> * TPW, nt - tile0);   // tiles of this column block
+
+    for (int j = threadIdx.x; j < 16 * NWX_OF<KP> * TPW; j += NTX_OF<KP>)
+        sh.s_codes[j] = a.codes[min<int64_t>(16 * (int64_t)tile0 + j, a.ldp - 1)];
+    if (threadIdx.x == 0) sh.lt = a.lt;
+    __syncthreads();
+    tile_codes(sh.s_codes, ntb, sh.s_tcode, NTX_OF<KP>);
+    Frag<KP, PREC> yfr[TPW];
+    YtFrag<KP, PREC> ytf[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        const int t = min(tile0 + w + NWX_OF<KP> * s, nt - 1);
+        frag_load_y<KP, PREC>(yfr[s], a.ycur, 16 * t + li, g);
+        if constexpr (MODE == 0) ytfrag_load<KP, PREC>(ytf[s], a.ycur, a.ldp, 16 * t, li, g);
+    }
+    f32x4 dyacc[TPW][KP / 16];
+    float hacc[TPW];
+#pragma unroll
+    for (int s = 0; s < TPW; ++s) {
+        hacc[s] = 0.0f;
+#pragma unroll
+        for (int kb = 0; kb < KP / 16; ++kb) dyacc[s][kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+
+    if (blockIdx.x < npanels)
+        stage_panel<KP, TPW, NWX_OF<KP>, SWZ>(sbuf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, blockIdx.x, w, lane,
+                                              tile0);
+    for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t pc = p + b * G;
+            if (pc >= npanels) break;
+            const int64_t pn = pc + G < npanels ? pc + G : -1;
+            PanelBuf<KP, TPW, NWX_OF<KP>> &cur = b == 0 ? sbuf0 : sbuf1;
+            PanelBuf<KP, TPW, NWX_OF<KP>> &nxt = b == 0 ? sbuf1 : sbuf0;
+            wait_staged();
+            const int64_t i0 = pc * 16;
+            const int rows = (int)min<int64_t>(16, a.m - i0);
+            xwide_tiles<KP, TPW, PREC, LK, MODE>(a, &nxt, pn, &cur, rows, tile0, nt, &sh.red_g[0][0][0],
+                                                 &sh.red_f[0][0], &sh.lt, sh.s_codes, sh.s_tcode, yfr, ytf, dyacc,
+                                                 hacc);
+            if constexpr (MODE != 2) {
+                // the panel's rows: the wavefronts' partials in wavefront order
+                lds_barrier();
+                if (threadIdx.x < 16 && threadIdx.x < rows) {
+                    float f = 0.0f;
+#pragma unroll
+                    for (int v = 0; v < NWX_OF<KP>; ++v) f += sh.red_f[v][threadIdx.x];
+                    a.part_f[(int64_t)cb * a.mp + i0 + threadIdx.x] = f;
+                }
+                if constexpr (MODE == 0) {
+                    for (int t = threadIdx.x; t < 16 * KP; t += NTX_OF<KP>) {
+                        const int i = t / KP, c = t % KP;
+                        if (i < rows && c < a.k) {
+                            float s = 0.0f;
+#pragma unroll
+                            for (int v = 0; v < NWX_OF<KP>; ++v) s += sh.red_g[v][i][c];
+                            a.part_dx[((int64_t)cb * a.m + i0 + i) * a.k + c] = GRAD_SCALE<LK> * s;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (MODE == 2) {
+#pragma unroll
+        for (int s = 0; s < TPW; ++s) {
+            const int t = tile0 + w + NWX_OF<KP> * s;
+            if (t < nt) {
+                const int64_t j0 = 16 * t;
+#pragma unroll
+                for (int kb = 0; kb < KP / 16; ++kb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        a.part_dy[((int64_t)blockIdx.x * a.ldp + j0 + 4 * g + r) * KP + 16 * kb + li] =
+                            GRAD_SCALE<LK> * dyacc[s][kb][r];
+                // column j0 + li: the four lane groups' partials
+                float h = hacc[s];
+                h += __shfl_xor(h, 16, 64);
+                h += __shfl_xor(h, 32, 64);
+                if (g == 0) a.part_h[(int64_t)blockIdx.x * a.ldp + j0 + li] = h;
+            }
+        }
+    }
+}
+
 // dY = sum over row chunks of the partials; dX = sum over column blocks.
 template <int KP>
 __global__ __launch_bounds__(256) void reduce_dy_kernel(ReduceArgs a)

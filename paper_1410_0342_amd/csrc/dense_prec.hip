@@ -173,6 +173,30 @@ hipError_t launch_lossgrad_p(const LossGradArgs &a, int kp, int tpw, bool want_g
     return hipGetLastError();
 }
 
+// The column-blocked row half-step: 16 tiles per wavefront at kp <= 32, 4 at
+// kp = 64 (the gradient pass's widest instances, which tables too wide for
+// the fused row pass always take).
+template <int PREC, int LKS>
+hipError_t launch_xwide_p(const XWideArgs &a, int mode, int kp, int tpw, int gx, int gy, hipStream_t st)
+{
+    constexpr int LK = LK_OF<LKS>;
+    auto go = [&](auto kpc, auto tpwc) -> hipError_t {
+        constexpr int KP = decltype(kpc)::value, TPW = decltype(tpwc)::value;
+        switch (mode) {
+        case 0: hipLaunchKernelGGL((xwide_kernel<KP, TPW, PREC, LK, 0>), dim3(gx, gy), dim3(NTX_OF<KP>), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((xwide_kernel<KP, TPW, PREC, LK, 1>), dim3(gx, gy), dim3(NTX_OF<KP>), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((xwide_kernel<KP, TPW, PREC, LK, 2>), dim3(gx, gy), dim3(NTX_OF<KP>), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    };
+    if (kp == 16 && tpw == 16) return go(std::integral_constant<int, 16>{}, std::integral_constant<int, 16>{});
+    if (kp == 32 && tpw == 16) return go(std::integral_constant<int, 32>{}, std::integral_constant<int, 16>{});
+    if (kp == 64 && tpw == 4) return go(std::integral_constant<int, 64>{}, std::integral_constant<int, 4>{});
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_xwide_p<GLRM_PREC, GLRM_LKS>(const XWideArgs &, int, int, int, int, int, hipStream_t);
 template hipError_t launch_xstep_p<GLRM_PREC, GLRM_LKS>(const XStepArgs &, int, int, int, hipStream_t);
 template int xstep_blocks_p<GLRM_PREC, GLRM_LKS>(int, int);
 template int ycheck_blocks_p<GLRM_PREC, GLRM_LKS>(int, int);

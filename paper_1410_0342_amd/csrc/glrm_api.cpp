@@ -90,6 +90,12 @@ struct Layout {
     CooLayout cl;
     int64_t cb_grad;       // column blocks of the gradient kernel
     int tpw_grad;
+    // dense fits wider than the fused row pass takes: the row half-step in
+    // column blocks (tiles per wavefront, blocks, per-block row sums, trial rows)
+    bool wide = false;
+    int wide_tpw = 0;
+    int64_t wide_ncb = 0;
+    size_t wd_f = 0, wd_fp = 0, wd_xp = 0, wd_rsum = 0;
     // linear-algebra region (certificate, SVD initialization), when requested
     int aux_b = 0;                       // vector block width
     size_t aux_V = 0, aux_V2 = 0;        // entry-wise matrix (dense: mp x ldp; COO: row and column order)
@@ -134,6 +140,12 @@ bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false, int aux_
         L.cb_grad = (ntiles + nw * t - 1) / (nw * t);
     }
     const int64_t kp = L.kp, ldp = L.ldp, n = L.n, m = L.m;
+    if (d->layout == GLRM_DENSE && !grad_only && !proxprox && tpw_xstep(ntiles, (int)kp) == 0) {
+        L.wide = true;
+        L.wide_tpw = kp == 64 ? 4 : 16;
+        const int64_t per = (int64_t)xstep_waves((int)kp) * L.wide_tpw;
+        L.wide_ncb = (ntiles + per - 1) / per;
+    }
     L.codes = L.take(ldp);
     L.colw = L.take(sizeof(float) * ldp);
     L.emb_src = L.take(sizeof(int32_t) * ldp);
@@ -176,7 +188,14 @@ bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false, int aux_
         L.part_hp = L.take(sizeof(float) * L.pmax * ldp);
         L.part_rowreg = L.take(sizeof(float) * L.pmax);
         L.part_rej = L.take(sizeof(int32_t) * L.pmax);
-        L.part_dx = L.cb_grad > 1 ? L.take(sizeof(float) * L.cb_grad * m * L.k) : 0;
+        const int64_t cbx = std::max<int64_t>(L.cb_grad > 1 ? L.cb_grad : 0, L.wide_ncb);
+        L.part_dx = cbx > 0 ? L.take(sizeof(float) * cbx * m * L.k) : 0;
+        if (L.wide) {
+            L.wd_f = L.take(sizeof(float) * L.wide_ncb * L.mp);
+            L.wd_fp = L.take(sizeof(float) * L.wide_ncb * L.mp);
+            L.wd_xp = L.take(sizeof(float) * m * L.k);
+            L.wd_rsum = L.take(sizeof(float) * 3 * L.mp);
+        }
         L.part_obj = L.take(sizeof(double) * P_GRAD * std::max<int64_t>(L.cb_grad, 1));
     } else {
         L.coo = L.take(0);
@@ -1257,11 +1276,9 @@ int glrm_fit(const glrm_data *d0, float *X, float *Y, float *alpha_x, float *alp
     if (proxprox) {
         // no pass-shape limits: the Gram, solve and check passes take any width
     } else if (d->layout == GLRM_DENSE) {
+        // tpw == 0: too wide for the fused row pass, which then runs in column blocks
         tpw = tpw_xstep(L.ldp / 16, (int)L.kp);
         tpw_y = tpw_ycheck(L.ldp / 16, (int)L.kp);
-        if (tpw == 0 || tpw_y == 0)
-            return fail(GLRM_EUNSUPPORTED, "dense fit supports n <= %d for k <= 32 and n <= %d for k > 32; "
-                        "use the COO layout for wider tables", 16 * xstep_waves(32) * 16, 16 * xstep_waves(64) * 8);
     } else {
         if ((rc = coo_fit_supported(d, L.kp, L.cl, prec))) return rc;
     }
@@ -1334,18 +1351,28 @@ int glrm_fit(const glrm_data *d0, float *X, float *Y, float *alpha_x, float *alp
         HIP_TRY(hipGetDevice(&dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         const bool quad = make_lossu(lt).kind == L_QUAD;
-        const int grid = (int)std::min<int64_t>(
-            {(int64_t)L.pmax, npanels, (int64_t)cus * xstep_blocks((int)L.kp, tpw, prec, quad)});
+        const bool wide = L.wide;
+        // the row half-step in column blocks: row chunks of the two row-sum
+        // passes, of the column pass (its Y-gradient partials, P_GRAD in
+        // all) and of the decisions
+        const int ncb_w = (int)L.wide_ncb;
+        const int gx_rows = (int)std::min<int64_t>(P_GRAD, npanels);
+        const int gx_cols = wide ? (int)std::max<int64_t>(1, std::min<int64_t>(npanels, (P_GRAD + ncb_w - 1) / ncb_w))
+                                 : 0;
+        const int grid_dec = (int)std::min<int64_t>(L.pmax, npanels);
+        const int grid = wide ? gx_cols
+                              : (int)std::min<int64_t>({(int64_t)L.pmax, npanels,
+                                                        (int64_t)cus * xstep_blocks((int)L.kp, tpw, prec, quad)});
         // A table wider than 4 tiles per wavefront runs the trial-column pass
         // in column blocks of 4 tiles per wavefront, so two workgroups fit on
         // a CU; the partial rows stay one per panel stream.
         int ncb_y = 1;
-        if (tpw_y > 4) {
+        if (tpw_y > 4 || tpw_y == 0) {
             tpw_y = 4;
             ncb_y = (int)((L.ldp / 16 + 4 * ycheck_waves((int)L.kp) - 1) / (4 * ycheck_waves((int)L.kp)));
         }
-        const int grid_y = ncb_y * (int)std::min<int64_t>(
-            {(int64_t)L.pmax, npanels, (int64_t)cus * ycheck_blocks((int)L.kp, tpw_y, prec, quad) / ncb_y});
+        const int grid_y = ncb_y * (int)std::max<int64_t>(1, std::min<int64_t>(
+            {(int64_t)L.pmax, npanels, (int64_t)cus * ycheck_blocks((int)L.kp, tpw_y, prec, quad) / ncb_y}));
         XStepArgs xa;
         xa.m = L.m; xa.mp = L.mp; xa.ldp = L.ldp; xa.k = (int32_t)L.k;
         xa.Ap = at<float>(ws, L.Ap);
@@ -1361,6 +1388,30 @@ int glrm_fit(const glrm_data *d0, float *X, float *Y, float *alpha_x, float *alp
         xa.part_h = at<float>(ws, L.part_h);
         xa.part_rowreg = at<float>(ws, L.part_rowreg);
         xa.part_rej = at<int32_t>(ws, L.part_rej);
+
+        XWideArgs wa0;
+        memset(&wa0, 0, sizeof wa0);
+        wa0.m = L.m; wa0.mp = L.mp; wa0.ldp = L.ldp; wa0.k = (int32_t)L.k;
+        wa0.Ap = xa.Ap; wa0.codes = xa.codes; wa0.lt = lt; wa0.lu = xa.lu;
+        wa0.X = X; wa0.ycur = xa.ycur;
+        wa0.part_f = wide ? at<float>(ws, L.wd_f) : nullptr;
+        wa0.part_dx = wide ? at<float>(ws, L.part_dx) : nullptr;
+        XWideArgs wa1 = wa0;
+        wa1.X = wide ? at<float>(ws, L.wd_xp) : nullptr;
+        wa1.part_f = wide ? at<float>(ws, L.wd_fp) : nullptr;
+        wa1.part_dx = nullptr;
+        XWideArgs wa2 = wa0;
+        wa2.part_f = nullptr; wa2.part_dx = nullptr;
+        wa2.part_dy = xa.part_dy; wa2.part_h = xa.part_h;
+        XWideRowArgs ra;
+        memset(&ra, 0, sizeof ra);
+        ra.m = L.m; ra.mp = L.mp; ra.k = (int32_t)L.k; ra.ncb = ncb_w;
+        ra.rx = xa.rx; ra.X = X; ra.alpha = alpha_x;
+        ra.part_f = wa0.part_f; ra.part_fp = wa1.part_f; ra.part_dx = wa0.part_dx;
+        ra.Xp = wide ? at<float>(ws, L.wd_xp) : nullptr;
+        ra.rsum = wide ? at<float>(ws, L.wd_rsum) : nullptr;
+        ra.step_up = o->step_up; ra.step_down = o->step_down;
+        ra.part_rowreg = xa.part_rowreg; ra.part_rej = xa.part_rej;
 
         YProxArgs pa;
         pa.n = L.n; pa.ldp = L.ldp; pa.k = (int32_t)L.k; pa.P = grid;
@@ -1398,12 +1449,20 @@ int glrm_fit(const glrm_data *d0, float *X, float *Y, float *alpha_x, float *alp
 
         FinalizeArgs fa;
         fa.part_F = aa.part_F; fa.part_rejc = aa.part_rejc; fa.n_colparts = ya_blocks;
-        fa.part_rowreg = xa.part_rowreg; fa.part_rej = xa.part_rej; fa.n_rowparts = grid;
+        fa.part_rowreg = xa.part_rowreg; fa.part_rej = xa.part_rej; fa.n_rowparts = wide ? grid_dec : grid;
         fa.stats = stats; fa.istats = istats; fa.history = history;
 
         for (int t = 0; t < o->max_sweeps; ++t) {
             HIP_TRY(timer.start(0, st));
-            HIP_TRY(launch_xstep(xa, (int)L.kp, tpw, prec, grid, st));
+            if (wide) {
+                HIP_TRY(launch_xwide(wa0, 0, (int)L.kp, L.wide_tpw, prec, gx_rows, ncb_w, st));
+                HIP_TRY(launch_xwide_step(ra, st));
+                HIP_TRY(launch_xwide(wa1, 1, (int)L.kp, L.wide_tpw, prec, gx_rows, ncb_w, st));
+                HIP_TRY(launch_xwide_decide(ra, grid_dec, st));
+                HIP_TRY(launch_xwide(wa2, 2, (int)L.kp, L.wide_tpw, prec, gx_cols, ncb_w, st));
+            } else {
+                HIP_TRY(launch_xstep(xa, (int)L.kp, tpw, prec, grid, st));
+            }
             HIP_TRY(timer.stop(st));
             HIP_TRY(timer.start(1, st));
             HIP_TRY(launch_yprox(pa, (int)L.kp, prec, st));

@@ -136,6 +136,40 @@ struct LossGradArgs {
     double *part_obj;       // P * CB
 };
 
+// The row half-step in column blocks (tables wider than the fused row pass
+// takes): the passes over the table ...
+struct XWideArgs {
+    int64_t m, mp, ldp;
+    int32_t k;
+    const float *Ap;
+    const uint8_t *codes;
+    LossTab lt;
+    LossU lu;
+    const float *X;         // the rows the pass evaluates, m x k
+    YShadow ycur;
+    float *part_f;          // CB x mp: row loss sums per column block (modes 0, 1)
+    float *part_dx;         // CB x m x k: row gradients per column block (mode 0)
+    float *part_dy;         // P x ldp x kp: Y-gradient partials per row chunk (mode 2)
+    float *part_h;          // P x ldp: column loss sums per row chunk (mode 2)
+};
+
+// ... and the per-row steps and decisions between them.
+struct XWideRowArgs {
+    int64_t m, mp;
+    int32_t k, ncb;
+    Reg rx;
+    float *X;               // m x k (decisions write the accepted rows)
+    float *alpha;           // m
+    const float *part_f;    // CB x mp (loss sums at X)
+    const float *part_fp;   // CB x mp (loss sums at X+)
+    const float *part_dx;   // CB x m x k
+    float *Xp;              // m x k trial rows
+    float *rsum;            // 3 x mp: loss sum at X, r(x), r(x+)
+    float step_up, step_down;
+    float *part_rowreg;     // grid: regularizers of the decided rows
+    int32_t *part_rej;      // grid: rejected rows
+};
+
 struct ReduceArgs {
     int64_t m, n, ldp;
     int32_t k, P, CB;
@@ -188,6 +222,10 @@ hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st);
 hipError_t launch_yshadow(const YShadowArgs &a, int kp, int prec, hipStream_t st);
 hipError_t launch_lossgrad(const LossGradArgs &a, int kp, int tpw, int prec, bool want_grad, int gx, int gy,
                            hipStream_t st);
+// mode: 0, 1 or 2 (XWideArgs); tpw 16 for kp <= 32, 4 for kp = 64; grid gx x gy.
+hipError_t launch_xwide(const XWideArgs &a, int mode, int kp, int tpw, int prec, int gx, int gy, hipStream_t st);
+hipError_t launch_xwide_step(const XWideRowArgs &a, hipStream_t st);
+hipError_t launch_xwide_decide(const XWideRowArgs &a, int grid, hipStream_t st);
 hipError_t launch_reduce_dy(const ReduceArgs &a, int kp, hipStream_t st);
 hipError_t launch_reduce_dx(const ReduceArgs &a, hipStream_t st);
 hipError_t launch_objective64(const Obj64Args &a, int grid, hipStream_t st);

@@ -101,8 +101,24 @@ def test_prox_and_fit_argument_errors():
     o = g._FitOpts(-1, g.FP32, 1, 1.0, 1.05, 0.7, 0.0, 0)
     assert g._L().glrm_fit(ctypes.byref(s), P, P, P, P, ctypes.byref(o), None, None, P, 1 << 40, None) == g.EINVAL
     o = g._FitOpts(5, g.FP32, 1, 1.0, 1.05, 0.7, 0.0, 0)
-    s, keep = _data(n=3000)
+    s, keep = _data(k=65)
     assert g._L().glrm_fit(ctypes.byref(s), P, P, P, P, ctypes.byref(o), None, None, P, 1 << 40, None) == g.EUNSUPPORTED
+
+
+def test_wide_dense_fit_workspace_holds_the_column_blocked_row_pass():
+    """A dense table wider than the fused row pass takes runs the row half-step
+    in column blocks; its workspace adds the per-block row sums, the trial rows
+    and the per-block row gradients (glrm_fit_workspace_size = glrm_workspace_size)."""
+    L = g._L()
+    for k, n_fused, n_wide in ((32, 1024, 1040), (64, 512, 528)):
+        sizes = {}
+        for n in (n_fused, n_wide):
+            s, keep = _data(m=1000, n=n, k=k)
+            sizes[n] = L.glrm_workspace_size(ctypes.byref(s))
+            o = g._FitOpts(5, g.FP32, 1, 1.0, 1.05, 0.7, 0.0, 0)
+            assert L.glrm_fit_workspace_size(ctypes.byref(s), ctypes.byref(o)) == sizes[n]
+        # the wide one holds at least the trial rows (m x k floats) more
+        assert sizes[n_wide] - sizes[n_fused] >= 4 * 1000 * k
 
 
 def test_an_empty_coo_needs_no_arrays():

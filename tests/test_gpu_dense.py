@@ -36,6 +36,10 @@ CASES = [
     dict(m=24, n=512, k=64, seed=9),                    # widest fit at kp = 64
     dict(m=20000, n=40, k=6, seed=10, missing=0.3),     # narrow and tall: several workgroups per CU
     dict(m=20, n=10, k=3, seed=11, missing=1.0),        # nothing observed: regularizers only
+    # wider than the fused row pass: the row half-step in column blocks
+    dict(m=40, n=1025, k=20, seed=12),                  # kp = 32: a second block of one ragged tile
+    dict(m=24, n=513, k=64, seed=13),                   # kp = 64: three blocks of 16 tiles, the last of one
+    dict(m=70, n=2100, k=10, seed=14, missing=0.4),     # kp = 16: three blocks, 132 tiles, ragged rows
 ]
 
 
@@ -233,13 +237,15 @@ def test_three_sweeps_nonsmooth_match_oracle(spec, prec):
     assert info["objective"] < F0
 
 
+@pytest.mark.parametrize("n", [60, 1100])
 @pytest.mark.parametrize("prec,tol", [(g.FP32, 1e-5), (g.BF16, 1e-4)])
-def test_fit_reaches_the_oracles_converged_objective(prec, tol):
+def test_fit_reaches_the_oracles_converged_objective(prec, tol, n):
     """Smooth convex losses with quadratic regularizers: after enough sweeps
     both the GPU and the oracle have converged (the oracle's last sweeps change
     F by < 1e-9 relative), and the objectives agree.  The first sweeps, before
-    any near-tie decision can separate the trajectories, agree closely too."""
-    case = synth.small_mixed(200, 60, 4, seed=31, missing=0.3, kinds=(0, 1, 2), rx=(1, 0.5), ry=(1, 0.5))
+    any near-tie decision can separate the trajectories, agree closely too.
+    n = 1100 takes the row half-step in column blocks."""
+    case = synth.small_mixed(200, n, 4, seed=31, missing=0.3, kinds=(0, 1, 2), rx=(1, 0.5), ry=(1, 0.5))
     data, X, Y, P = _setup(case)
     T = 1500
     ax = torch.empty(case.m, dtype=torch.float32, device=DEV)
@@ -288,8 +294,9 @@ def test_step_sizes_move_by_exact_factors_and_rejected_rows_stay():
         assert np.array_equal(Y1[dnc], Y0[dnc])
 
 
-def test_fit_is_deterministic():
-    case = synth.small_mixed(150, 90, 6, seed=51)
+@pytest.mark.parametrize("n", [90, 1300])
+def test_fit_is_deterministic(n):
+    case = synth.small_mixed(150, n, 6, seed=51)
     outs = []
     for _ in range(2):
         data, X, Y, P = _setup(case)
@@ -300,12 +307,10 @@ def test_fit_is_deterministic():
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
 
 
-@pytest.mark.parametrize("m,n,k", [(40, 1025, 20), (24, 513, 64), (10, 10, 65)])
-def test_fit_beyond_the_dense_limits_is_reported(m, n, k):
-    """The dense fit keeps a wavefront's tiles resident: n <= 1024 for
-    k <= 32 and n <= 512 for k <= 64; wider tables (and k > 64) are reported
-    as unsupported before any launch, with nothing written."""
-    case = synth.small_mixed(m, n, k, seed=12)
+def test_fit_beyond_the_rank_limit_is_reported():
+    """k > 64 is reported as unsupported before any launch, with nothing
+    written."""
+    case = synth.small_mixed(10, 10, 65, seed=12)
     data, X, Y, _ = _setup(case)
     ax = torch.zeros(case.m, dtype=torch.float32, device=DEV)
     ay = torch.zeros(case.n, dtype=torch.float32, device=DEV)
@@ -325,8 +330,6 @@ def test_overflowing_step_sizes_leave_the_factors_finite(layout, prec):
     with an infinite or NaN coordinate, or whose products overflow, is never
     accepted, so X and Y stay finite and every observed row and column keeps
     its start, as in the oracle; the objective equals the oracle's."""
-    if layout == "coo" and prec == g.BF16:
-        pytest.skip("the COO layout's BF16 form is covered by the sparse tests")
     case = synth.small_mixed(60, 30, 4, seed=81, missing=0.3, layout=layout, rx=(0, 0.0), ry=(0, 0.0),
                              empty_row=3, empty_col=7)
     data = g.Data.from_case(case, DEV)

@@ -95,6 +95,14 @@ def test_dense_quadratic_one_sweep_sampled(dense_quadratic, prec):
     _check_sampled_sweep(dense_quadratic, prec, 2)
 
 
+@pytest.mark.parametrize("prec", [g.FP32, g.BF16])
+def test_autograd_table_fit_one_sweep_sampled(prec):
+    """The 50,000 x 2,000, k = 64 table (half logistic columns) fitted in the
+    dense layout: too wide for the fused row pass, its row half-step runs in
+    eight column blocks.  Sampled rows and columns against the oracle."""
+    _check_sampled_sweep(synth.autograd_point(), prec, 4)
+
+
 def test_dense_quadratic_objective_full(dense_quadratic):
     case = dense_quadratic
     data = g.Data.from_case(case, DEV)

@@ -102,8 +102,6 @@ def test_fit_with_offset_and_scaled_losses_matches_oracle(layout, prec):
     """The offset (x_i0 = 1, y_j0 free) and the weights 1 / sigma_j^2 in the
     sweep: one sweep from the SVD start checked row by row and column by
     column, and the FP64 objective of the GPU's state."""
-    if layout == "coo" and prec == g.BF16:
-        pytest.skip("the COO layout's BF16 form is covered by the sparse tests")
     case = synth.small_mixed(200, 45, 4, seed=321, missing=0.3, layout=layout, rx=(1, 0.2), ry=(1, 0.2))
     P0 = oracle_problem(case)
     data = g.Data.from_case(case, DEV)
@@ -122,8 +120,8 @@ def test_fit_with_offset_and_scaled_losses_matches_oracle(layout, prec):
     info = g.glrm_fit(model, X, Y, ax, ay, 1, precision=prec)
     ax0, ay0 = init_alpha32(P, 1.0)
     Xg, Yg = X.cpu().numpy(), Y.cpu().numpy()
-    check_sweep(P, X0, Y0, ax0, ay0, Xg, Yg, ax.cpu().numpy(), ay.cpu().numpy(),
-                "fp32" if prec == g.FP32 else "bf16", tag=case.name)
+    pname = "fp32" if prec == g.FP32 else ("bf16" if layout == "dense" else "coo_bf16")
+    check_sweep(P, X0, Y0, ax0, ay0, Xg, Yg, ax.cpu().numpy(), ay.cpu().numpy(), pname, tag=case.name)
     assert np.all(Xg[:, 0] == 1.0)
     assert info["objective"] == pytest.approx(P.objective(Xg, Yg), rel=1e-10)
 

@@ -34,8 +34,6 @@ def _both(case, prec):
 @pytest.mark.parametrize("layout", ["dense", "coo"])
 @pytest.mark.parametrize("prec", [g.FP32, g.BF16])
 def test_noalloc_gradient_equals_workspace_gradient_on_two_calls(layout, prec):
-    if layout == "coo" and prec == g.BF16 and not getattr(g, "COO_BF16", False):
-        pytest.skip("the COO layout has no BF16 form in this build")
     big = synth.small_mixed(2000, 300, 20, seed=91, missing=0.3, layout=layout)
     small = synth.small_mixed(300, 70, 7, seed=92, missing=0.4, layout=layout)
     for case in (big, small):
