@@ -71,18 +71,20 @@ __global__ __launch_bounds__(256) void xwide_step_kernel(XWideRowArgs a)
 
 // The step rule of the rows (S5): keep the trial row if its objective (loss
 // sum over the column blocks, in block order, plus r) does not exceed the
-// old one; step sizes move by step_up / step_down.  A fixed grid of 16-row
-// panels, so the per-workgroup sums of the decided rows' regularizers and of
+// old one; step sizes move by step_up / step_down.  A fixed grid of 64-row
+// groups, so the per-workgroup sums of the decided rows' regularizers and of
 // the rejections come in a fixed number and order.
-__global__ __launch_bounds__(256) void xwide_decide_kernel(XWideRowArgs a)
+constexpr int XDEC_THREADS = 1024;
+__global__ __launch_bounds__(XDEC_THREADS) void xwide_decide_kernel(XWideRowArgs a)
 {
-    __shared__ float s_r[4];
-    __shared__ int s_j[4];
+    constexpr int NWV = XDEC_THREADS / 64, RPB = XDEC_THREADS / 16;
+    __shared__ float s_r[NWV];
+    __shared__ int s_j[NWV];
     const int ri = threadIdx.x >> 4, c0 = threadIdx.x & 15;
     float rr = 0.0f;
     int rj = 0;
-    for (int64_t p = blockIdx.x; p * 16 < a.m; p += gridDim.x) {
-        const int64_t i = p * 16 + ri;
+    for (int64_t p = blockIdx.x; p * RPB < a.m; p += gridDim.x) {
+        const int64_t i = p * RPB + ri;
         const bool rv = i < a.m;
         bool acc = false;
         float rx = 0.0f, rxp = 0.0f;
@@ -116,8 +118,15 @@ __global__ __launch_bounds__(256) void xwide_decide_kernel(XWideRowArgs a)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        a.part_rowreg[blockIdx.x] = ((s_r[0] + s_r[1]) + s_r[2]) + s_r[3];
-        a.part_rej[blockIdx.x] = s_j[0] + s_j[1] + s_j[2] + s_j[3];
+        float r = 0.0f;
+        int j = 0;
+#pragma unroll
+        for (int v = 0; v < NWV; ++v) {
+            r += s_r[v];
+            j += s_j[v];
+        }
+        a.part_rowreg[blockIdx.x] = r;
+        a.part_rej[blockIdx.x] = j;
     }
 }
 
@@ -191,6 +200,7 @@ template <int PREC> hipError_t launch_yaccept_p(const YAcceptArgs &, int, int, h
 template <int PREC> hipError_t launch_yshadow_p(const YShadowArgs &, int, hipStream_t);
 template <int PREC, int LKS> hipError_t launch_lossgrad_p(const LossGradArgs &, int, int, bool, int, int, hipStream_t);
 template <int PREC, int LKS> hipError_t launch_xwide_p(const XWideArgs &, int, int, int, int, int, hipStream_t);
+template <int PREC, int LKS> int xwide_blocks_p(int, int);
 
 #define GLRM_BY_PREC(PV, CALL)                                      \
     switch (PV) {                                                   \
@@ -277,7 +287,7 @@ hipError_t launch_xwide_step(const XWideRowArgs &a, hipStream_t st)
 
 hipError_t launch_xwide_decide(const XWideRowArgs &a, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(xwide_decide_kernel, dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(xwide_decide_kernel, dim3(grid), dim3(XDEC_THREADS), 0, st, a);
     return hipGetLastError();
 }
 
@@ -318,6 +328,17 @@ int xstep_blocks(int kp, int tpw, int prec, bool quad)
     case P_BF16: return quad ? xstep_blocks_p<P_BF16, 0>(kp, tpw) : xstep_blocks_p<P_BF16, 1>(kp, tpw);
     case P_BF16_PLAIN:
         return quad ? xstep_blocks_p<P_BF16_PLAIN, 0>(kp, tpw) : xstep_blocks_p<P_BF16_PLAIN, 1>(kp, tpw);
+    default: return 1;
+    }
+}
+
+int xwide_blocks(int kp, int tpw, int prec, bool quad)
+{
+    switch (prec) {
+    case P_FP32: return quad ? xwide_blocks_p<P_FP32, 0>(kp, tpw) : xwide_blocks_p<P_FP32, 1>(kp, tpw);
+    case P_BF16: return quad ? xwide_blocks_p<P_BF16, 0>(kp, tpw) : xwide_blocks_p<P_BF16, 1>(kp, tpw);
+    case P_BF16_PLAIN:
+        return quad ? xwide_blocks_p<P_BF16_PLAIN, 0>(kp, tpw) : xwide_blocks_p<P_BF16_PLAIN, 1>(kp, tpw);
     default: return 1;
     }
 }

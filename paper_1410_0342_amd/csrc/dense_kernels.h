@@ -1376,9 +1376,9 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void lossgrad_kernel(LossGradArgs a)
 //           partial over the workgroup's rows (S6)
 // with the row steps (S4) and the decisions between them, in dense.hip.  The
 // sums over column blocks are taken there, in block order.
-template <int KP, int TPW, int PREC>
+template <int KP, int TPW, int MODE>
 struct WideShared {
-    float red_g[NWX_OF<KP>][16][RS<KP>];   // MODE 0: dX partials of the panel
+    float red_g[MODE == 0 ? NWX_OF<KP> : 1][16][RS<KP>];   // MODE 0: dX partials of the panel
     float red_f[NWX_OF<KP>][16];           // MODE 0, 1: row loss partials of the panel
     LossTab lt;
     uint8_t s_codes[16 * NWX_OF<KP> * TPW];
@@ -1476,7 +1476,7 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void xwide_kernel(XWideArgs a)
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     constexpr bool SWZ = MODE == 2;
-    __shared__ WideShared<KP, TPW, PREC> sh;
+    __shared__ WideShared<KP, TPW, MODE> sh;
     // the panel buffers, LDS objects of their own (as in the fused row pass)
     __shared__ PanelBuf<KP, TPW, NWX_OF<KP>> sbuf0;
     __shared__ PanelBuf<KP, TPW, NWX_OF<KP>> sbuf1;

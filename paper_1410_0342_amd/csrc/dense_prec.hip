@@ -196,7 +196,19 @@ hipError_t launch_xwide_p(const XWideArgs &a, int mode, int kp, int tpw, int gx,
     return hipErrorInvalidValue;
 }
 
+// Workgroups of the column pass (mode 2) that fit on a CU.
+template <int PREC, int LKS>
+int xwide_blocks_p(int kp, int tpw)
+{
+    constexpr int LK = LK_OF<LKS>;
+    if (kp == 16 && tpw == 16) return blocks_per_cu(xwide_kernel<16, 16, PREC, LK, 2>, NTX_OF<16>);
+    if (kp == 32 && tpw == 16) return blocks_per_cu(xwide_kernel<32, 16, PREC, LK, 2>, NTX_OF<32>);
+    if (kp == 64 && tpw == 4) return blocks_per_cu(xwide_kernel<64, 4, PREC, LK, 2>, NTX_OF<64>);
+    return 1;
+}
+
 template hipError_t launch_xwide_p<GLRM_PREC, GLRM_LKS>(const XWideArgs &, int, int, int, int, int, hipStream_t);
+template int xwide_blocks_p<GLRM_PREC, GLRM_LKS>(int, int);
 template hipError_t launch_xstep_p<GLRM_PREC, GLRM_LKS>(const XStepArgs &, int, int, int, hipStream_t);
 template int xstep_blocks_p<GLRM_PREC, GLRM_LKS>(int, int);
 template int ycheck_blocks_p<GLRM_PREC, GLRM_LKS>(int, int);

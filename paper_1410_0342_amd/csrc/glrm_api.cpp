@@ -1357,9 +1357,13 @@ int glrm_fit(const glrm_data *d0, float *X, float *Y, float *alpha_x, float *alp
         // all) and of the decisions
         const int ncb_w = (int)L.wide_ncb;
         const int gx_rows = (int)std::min<int64_t>(P_GRAD, npanels);
-        const int gx_cols = wide ? (int)std::max<int64_t>(1, std::min<int64_t>(npanels, (P_GRAD + ncb_w - 1) / ncb_w))
+        // the column pass fills the device once (its partials, one per row
+        // chunk, are reduced by yprox)
+        const int gx_cols = wide ? (int)std::max<int64_t>(1, std::min<int64_t>(
+                                       {(int64_t)L.pmax, npanels,
+                                        (int64_t)cus * xwide_blocks((int)L.kp, L.wide_tpw, prec, quad) / ncb_w}))
                                  : 0;
-        const int grid_dec = (int)std::min<int64_t>(L.pmax, npanels);
+        const int grid_dec = (int)std::min<int64_t>(L.pmax, (L.m + 63) / 64);
         const int grid = wide ? gx_cols
                               : (int)std::min<int64_t>({(int64_t)L.pmax, npanels,
                                                         (int64_t)cus * xstep_blocks((int)L.kp, tpw, prec, quad)});

@@ -224,7 +224,9 @@ hipError_t launch_lossgrad(const LossGradArgs &a, int kp, int tpw, int prec, boo
                            hipStream_t st);
 // mode: 0, 1 or 2 (XWideArgs); tpw 16 for kp <= 32, 4 for kp = 64; grid gx x gy.
 hipError_t launch_xwide(const XWideArgs &a, int mode, int kp, int tpw, int prec, int gx, int gy, hipStream_t st);
+int xwide_blocks(int kp, int tpw, int prec, bool quad);   // column-pass workgroups per CU
 hipError_t launch_xwide_step(const XWideRowArgs &a, hipStream_t st);
+// grid: workgroups of 64 rows at a time, one row partial each (part_rowreg, part_rej)
 hipError_t launch_xwide_decide(const XWideRowArgs &a, int grid, hipStream_t st);
 hipError_t launch_reduce_dy(const ReduceArgs &a, int kp, hipStream_t st);
 hipError_t launch_reduce_dx(const ReduceArgs &a, hipStream_t st);
