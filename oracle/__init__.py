@@ -63,6 +63,8 @@ def lib():
         L.oracle_reg.argtypes = [I32, D, I32, P, I32]
         L.oracle_prox.restype = None
         L.oracle_prox.argtypes = [I32, D, I32, D, P, I32]
+        L.oracle_reg_subgrad.restype = None
+        L.oracle_reg_subgrad.argtypes = [I32, D, I32, P, I32, P]
         L.oracle_loss_sum.restype = D
         L.oracle_loss_sum.argtypes = [P, P, P]
         L.oracle_loss_grad_rows.restype = None
@@ -165,6 +167,19 @@ def reg(kind, w, x, offset=0):
     (held at 1 / free and unpenalized)."""
     x = _f64(x).ravel()
     return lib().oracle_reg(kind, float(w), int(offset), _ptr(x), x.size)
+
+
+def reg_subgrad(kind, w, V, offset=0):
+    """The minimum-norm subgradient of r at every row of V (rows x k; NaN
+    where r is +inf)."""
+    V = np.atleast_2d(_f64(V))
+    out = np.empty_like(V)
+    for i in range(V.shape[0]):
+        row = np.ascontiguousarray(V[i])
+        g = np.empty_like(row)
+        lib().oracle_reg_subgrad(kind, float(w), int(offset), _ptr(row), row.size, _ptr(g))
+        out[i] = g
+    return out
 
 
 def prox(kind, w, alpha, v, offset=0):

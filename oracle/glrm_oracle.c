@@ -152,6 +152,31 @@ void oracle_prox(int32_t kind, double w, int32_t offset, double alpha, double *v
     }
 }
 
+/* The minimum-norm element of the subdifferential of r at x, coordinate by
+ * coordinate (every r here is a sum over coordinates): the projection of 0
+ * onto the interval of subgradients.  quadratic {2 w x}; l1 {w sign x}, and
+ * [-w, w] at 0, so 0; nonnegative {0} for x > 0 and (-inf, 0] at 0, so 0;
+ * none {0}.  Outside r's domain (r = +inf: x < 0 under the nonnegative
+ * constraint, x_1 != 1 under the offset of the rows of X) there is no
+ * subgradient and the coordinate gets NaN.  The offset coordinate is
+ * otherwise unpenalized: 0. */
+void oracle_reg_subgrad(int32_t kind, double w, int32_t offset, const double *x, int32_t k, double *g)
+{
+    int c0 = 0;
+    if (offset) {
+        g[0] = (offset == 1 && x[0] != 1.0) ? NAN : 0.0;
+        c0 = 1;
+    }
+    for (int c = c0; c < k; ++c) {
+        switch (kind) {
+        case OR_RQUAD: g[c] = 2.0 * w * x[c]; break;
+        case OR_RL1: g[c] = x[c] > 0.0 ? w : (x[c] < 0.0 ? -w : 0.0); break;
+        case OR_RNONNEG: g[c] = x[c] < 0.0 ? NAN : 0.0; break;
+        default: g[c] = 0.0; break;
+        }
+    }
+}
+
 static double dot(const double *a, const double *b, int32_t k)
 {
     double s = 0.0;

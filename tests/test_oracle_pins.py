@@ -122,6 +122,63 @@ def test_regularizer_values():
     assert oracle.reg(3, 0.0, np.abs(x)) == 0.0
 
 
+@pytest.mark.parametrize("kind,w", [(0, 0.0), (1, 0.7), (2, 0.4), (3, 0.0)])
+def test_regularizer_subgradient_is_a_subgradient_of_least_norm(kind, w):
+    """The subgradient the regularized autograd objective uses (Section 3 for
+    r; the least-norm element of the subdifferential where r has a kink).
+    Checked by the subgradient inequality r(y) >= r(x) + g . (y - x) against
+    r's own values at random points (zeros included), by central differences
+    where r is differentiable, and by least norm at the kinks: any other
+    valid subgradient there is at least as long."""
+    gen = np.random.default_rng(50 + kind)
+    for _ in range(60):
+        x = gen.normal(size=5)
+        x[gen.random(5) < 0.3] = 0.0
+        if kind == 3:
+            x = np.abs(x)
+        g = oracle.reg_subgrad(kind, w, x)[0]
+        assert np.all(np.isfinite(g))
+        for _ in range(20):
+            y = gen.normal(size=5) * 2
+            if kind == 3:
+                y = np.abs(y)
+            assert oracle.reg(kind, w, y) >= oracle.reg(kind, w, x) + g @ (y - x) - 1e-12
+        h = 1e-6
+        for c in range(5):
+            if kind == 2 and x[c] == 0.0:
+                # the kink: every t in [-w, w] passes the inequality; least norm is t = 0
+                assert g[c] == 0.0
+                for t in (-w, w):
+                    gt = g.copy()
+                    gt[c] = t
+                    y = x.copy()
+                    y[c] = gen.normal()
+                    assert oracle.reg(kind, w, y) >= oracle.reg(kind, w, x) + gt @ (y - x) - 1e-12
+                continue
+            if kind == 3:
+                assert g[c] == 0.0          # {0} inside the orthant, (-inf, 0] on its boundary
+                continue
+            xp, xm = x.copy(), x.copy()
+            xp[c] += h
+            xm[c] -= h
+            fd = (oracle.reg(kind, w, xp) - oracle.reg(kind, w, xm)) / (2 * h)
+            assert g[c] == pytest.approx(fd, abs=1e-6)
+
+
+def test_regularizer_subgradient_outside_the_domain_and_at_the_offset():
+    """Where r = +inf there is no subgradient (NaN); the offset coordinate of
+    Section 3.3 is unpenalized (0) on the columns of Y and feasible only at 1
+    on the rows of X."""
+    g = oracle.reg_subgrad(3, 0.0, np.array([0.5, -1.0, 0.0]))[0]
+    assert g[0] == 0.0 and np.isnan(g[1]) and g[2] == 0.0
+    for kind in (1, 2, 3):
+        gy = oracle.reg_subgrad(kind, 0.5, np.array([-3.0, 2.0]), offset=2)[0]
+        assert gy[0] == 0.0 and gy[1] == oracle.reg_subgrad(kind, 0.5, np.array([2.0]))[0][0]
+        gx = oracle.reg_subgrad(kind, 0.5, np.array([1.0, 2.0]), offset=1)[0]
+        assert gx[0] == 0.0
+        assert np.isnan(oracle.reg_subgrad(kind, 0.5, np.array([0.9, 2.0]), offset=1)[0][0])
+
+
 def _problem(case):
     if case.layout == "coo":
         return oracle.Problem.from_coo(case.m, case.n, case.k, case.rows, case.cols, case.vals,
