@@ -172,6 +172,8 @@ int64_t glrm_embed_dim(const glrm_data *d);
                                  exact data (same pointers, sizes and contents); skip it */
 #define GLRM_TIME_KERNELS 2u  /* glrm_fit only: record HIP events on `stream` around every
                                  kernel launch and report per-kernel totals in glrm_fit_info */
+#define GLRM_GRAD_WITH_REG 4u /* glrm_grad, glrm_grad_noalloc: add the regularizers'
+                                 subgradients, so dX, dY are (sub)gradients of all of F */
 
 /* Bytes of device workspace any entry point needs for this problem.  The same
  * size serves glrm_prepare, glrm_objective, glrm_grad and glrm_fit, and the
@@ -197,7 +199,13 @@ int glrm_objective(const glrm_data *d, const float *X, const float *Y, int preci
 /* Loss-part gradients (Section 7.2, g = sum_j dL(x_i . y_j, A_ij) y_j):
  *   dX[i,:] = sum_{j:(i,j) in Omega} G_ij y_j        (m x k, row-major, device)
  *   dY[j,:] = sum_{i:(i,j) in Omega} G_ij x_i        (n x k, row-major, device)
- * with G_ij = dL_j(x_i . y_j, A_ij).  Regularizer gradients are not added.
+ * with G_ij = dL_j(x_i . y_j, A_ij).  Regularizer gradients are added only
+ * with GLRM_GRAD_WITH_REG in `flags`: then dX[i,:] += g(r, x_i) and
+ * dY[j,:] += g(rt, y_j), where g is, coordinate by coordinate, the subgradient
+ * of least magnitude of the regularizers of Section 3 (quadratic 2 w x; l1
+ * w sign(x), 0 at 0; nonnegative 0), NaN where the regularizer is +inf (a
+ * negative coordinate under the nonnegative constraint, x_i0 != 1 under the
+ * offset of Section 3.3); the offset coordinate is otherwise unpenalized.
  * Precision FP32, BF16 or BF16_PLAIN.  If obj_host is not NULL the objective
  * (as glrm_objective at the same precision) is written there and `stream` is
  * synchronized; otherwise the call is asynchronous. */

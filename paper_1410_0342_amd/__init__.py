@@ -28,6 +28,7 @@ FP32, BF16, FP64, BF16_PLAIN = 0, 1, 2, 3
 DENSE, COO_ROWSORTED = 0, 1
 WS_PREPARED = 1
 TIME_KERNELS = 2
+GRAD_WITH_REG = 4
 IMPUTE_ALL, IMPUTE_MISSING = 0, 1
 LOSS_QUADRATIC, LOSS_HUBER, LOSS_LOGISTIC, LOSS_HINGE, LOSS_ORDINAL, LOSS_CATEGORICAL, LOSS_MORDINAL = range(7)
 UPDATE_PROXGRAD, UPDATE_PROXPROX = 0, 1
@@ -302,7 +303,9 @@ def glrm_objective(data, X, Y, precision=FP32, flags=0, stream=None):
 
 
 def glrm_grad(data, X, Y, precision=FP32, dX=None, dY=None, want_objective=False, flags=0, stream=None):
-    """Loss-part gradients dX (m x k) and dY (n x k); optionally the objective."""
+    """Loss-part gradients dX (m x k) and dY (n x k); optionally the objective.
+    With GRAD_WITH_REG in flags the regularizers' least-magnitude subgradients
+    are added."""
     torch = _torch()
     if dX is None:
         dX = torch.empty((data.m, data.k), dtype=torch.float32, device=X.device)

@@ -93,6 +93,22 @@ hipError_t launch_prox(Reg r, float *V, int64_t rows, int32_t k, int64_t ldv, co
     return hipGetLastError();
 }
 
+// dV += the regularizer's least-magnitude subgradient at V, element-wise.
+__global__ void reg_grad_kernel(Reg r, const float *V, int64_t rows, int32_t k, float *dV)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= rows * k) return;
+    dV[t] += reg_grad_elem(r, V[t], (int)(t % k));
+}
+
+hipError_t launch_reg_grad(Reg r, const float *V, int64_t rows, int32_t k, float *dV, hipStream_t st)
+{
+    const int64_t total = rows * k;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reg_grad_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, r, V, rows, k, dV);
+    return hipGetLastError();
+}
+
 // Regularizer sum over a factor, in double; one partial per workgroup.
 __global__ __launch_bounds__(256) void regsum_kernel(Reg r, const float *V, int64_t rows, int32_t k, double *part)
 {

@@ -683,6 +683,10 @@ int grad_run(const glrm_data *d, const Layout &L, const float *X, const float *Y
                            precision, dX, dY, &po, &nparts, st)))
             return rc;
     }
+    if (flags & GLRM_GRAD_WITH_REG) {
+        HIP_TRY(launch_reg_grad(reg_x(d), X, L.m, (int32_t)L.k, dX, st));
+        HIP_TRY(launch_reg_grad(reg_y(d), Y, L.n, (int32_t)L.k, dY, st));
+    }
     if (obj_host) {
         double *res = at<double>(ws, L.scal);
         if ((rc = reg_sums(d, L, X, Y, ws, st))) return rc;

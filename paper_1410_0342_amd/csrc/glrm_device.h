@@ -245,6 +245,22 @@ __device__ __forceinline__ float reg_elem_trial(const Reg &r, float x, int c)
     return reg_elem(r, x, c) + 0.0f * x;
 }
 
+// One coordinate of the least-magnitude subgradient of r at x: the projection
+// of 0 onto the coordinate's interval of subgradients (quadratic 2 w x; l1
+// w sign x, the interval [-w, w] at 0; nonnegative 0 inside the orthant and on
+// its boundary); NaN outside r's domain, where no subgradient exists.
+__device__ __forceinline__ float reg_grad_elem(const Reg &r, float x, int c)
+{
+    const float qnan = __builtin_nanf("");
+    if (c == 0 && r.offset) return (r.offset == 1 && x != 1.0f) ? qnan : 0.0f;
+    switch (r.kind) {
+    case R_QUAD: return 2.0f * r.w * x;
+    case R_L1: return x > 0.0f ? r.w : (x < 0.0f ? -r.w : 0.0f);
+    case R_NONNEG: return x < 0.0f ? qnan : 0.0f;
+    default: return 0.0f;
+    }
+}
+
 // prox_{alpha r}(v), coordinate-wise (every supported r is separable); the
 // offset coordinate is projected onto 1 (X) or left as it is (Y).
 __device__ __forceinline__ float prox_elem(const Reg &r, float alpha, float v, int c)

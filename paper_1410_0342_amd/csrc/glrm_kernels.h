@@ -237,6 +237,7 @@ hipError_t launch_pack_dense(const PackArgs &a, hipStream_t st);
 hipError_t launch_init_alpha(const int32_t *count, int64_t len, float scale, float *alpha, hipStream_t st);
 hipError_t launch_prox(Reg r, float *V, int64_t rows, int32_t k, int64_t ldv, const float *alpha, hipStream_t st);
 hipError_t launch_regsum(Reg r, const float *V, int64_t rows, int32_t k, double *part, int blocks, hipStream_t st);
+hipError_t launch_reg_grad(Reg r, const float *V, int64_t rows, int32_t k, float *dV, hipStream_t st);
 hipError_t launch_sum_doubles(const double *a, int32_t na, const double *b, int32_t nb, double *out, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t len, int32_t v, hipStream_t st);
 hipError_t launch_pad_weights(const float *src, const int32_t *map, int64_t n, int64_t ldp, float *dst, hipStream_t st);
