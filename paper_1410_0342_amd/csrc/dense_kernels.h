@@ -131,19 +131,41 @@ __device__ __forceinline__ f32x4 zprod(const Frag<KP, PREC> &y, const Frag<KP, P
     return acc;
 }
 
-// Transpose the wave's 16x16 G tile through LDS.
-__device__ __forceinline__ void transpose_g(float *gsc, const float (&G)[4], float (&gT)[4], int li, int g)
+// Transpose the wave's 16x16 G tile in registers: lane li + 16 g holds
+// G[li][4g + r] in G[r] and receives G[4g + r][li] in gT[r].  First a 4x4
+// transpose inside every quad of lanes (the quad's four rows of one 4x4 block,
+// across the four registers) with DPP quad permutations; then lane
+// jj + 4 bj + 16 bi takes the registers of lane jj + 4 bi + 16 bj (one
+// ds_bpermute per register).  No LDS memory is touched, so nothing here waits
+// for the next panel's direct-to-LDS loads.
+__device__ __forceinline__ void transpose_g(const float (&G)[4], float (&gT)[4])
 {
+    const int lane = threadIdx.x & 63;
+    float m[4] = {G[0], G[1], G[2], G[3]};
+    {   // quad lanes q and q ^ 2 exchange registers r + 2 / r
+        const bool hi = (lane & 2) != 0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) gsc[(4 * g + r) * GS + li] = G[r];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    float4 v = *reinterpret_cast<const float4 *>(gsc + li * GS + 4 * g);
-    gT[0] = v.x; gT[1] = v.y; gT[2] = v.z; gT[3] = v.w;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int r = 0; r < 2; ++r) {
+            const float a = m[r], c = m[r + 2];
+            const float pa = dpp_mov<0x4E>(a), pc = dpp_mov<0x4E>(c);   // quad_perm [2,3,0,1]
+            m[r] = hi ? pc : a;
+            m[r + 2] = hi ? c : pa;
+        }
+    }
+    {   // quad lanes q and q ^ 1 exchange registers r + 1 / r
+        const bool hi = (lane & 1) != 0;
+#pragma unroll
+        for (int r = 0; r < 4; r += 2) {
+            const float a = m[r], c = m[r + 1];
+            const float pa = dpp_mov<0xB1>(a), pc = dpp_mov<0xB1>(c);   // quad_perm [1,0,3,2]
+            m[r] = hi ? pc : a;
+            m[r + 1] = hi ? c : pa;
+        }
+    }
+    const int src = (lane & 3) | (((lane >> 4) & 3) << 2) | (((lane >> 2) & 3) << 4);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        gT[r] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(4 * src, __builtin_bit_cast(int, m[r])));
 }
 
 // Wavefronts per workgroup of the two passes over the table (xstep_waves,
@@ -155,6 +177,10 @@ template <int KP>
 constexpr int NTX_OF = 64 * NWX_OF<KP>;
 template <int KP>
 constexpr int NWY_OF = ycheck_waves(KP);
+template <int KP>
+constexpr int NWG_OF = grad_waves(KP);
+template <int KP>
+constexpr int NTG_OF = 64 * NWG_OF<KP>;
 template <int KP>
 constexpr int NTY_OF = 64 * NWY_OF<KP>;
 
@@ -445,13 +471,15 @@ __device__ __attribute__((noinline)) LG4 tile_loss_table_call(const LossTab *tab
 // 16t + 4g + r.
 //
 // Under a per-column loss table each entry's loss and derivative are scaled
-// by its column's weight (tab.colw, padded to the table's width, all 1 unless
-// the caller gave weights); tw is the tile's index in the whole table (t may
-// count within a column block).
+// by its column's weight (all 1 unless the caller gave weights), staged in LDS
+// beside the loss codes (s_colw, indexed like s_codes): a global load here
+// would make the wait for its data also wait for the next panel's
+// direct-to-LDS loads, issued before it, and take the prefetch out of the
+// tile loop.
 template <int LK, bool WANT_G, bool TRANS = false, int TPW = 1>
 __device__ __forceinline__ void tile_loss(const LossU &lu, const LossTab &tab, const uint8_t *s_codes,
                                           const int8_t *s_tcode, int t, const f32x4 &z, const float4 &av,
-                                          float (&l)[4], float (&g)[4], int tw = -1)
+                                          float (&l)[4], float (&g)[4], const float *s_colw)
 {
     if constexpr (LK >= 0) {
         const float a4[4] = {av.x, av.y, av.z, av.w};
@@ -480,13 +508,12 @@ __device__ __forceinline__ void tile_loss(const LossU &lu, const LossTab &tab, c
         // unconditional (the weights are all 1 without a caller's weights): a
         // branch here would sit between a matrix-core product and its read
         const int lane = threadIdx.x & 63;
-        const int tt = tw >= 0 ? tw : t;
         float w[4];
         if constexpr (TRANS) {
-            const float wc = tab.colw[16 * tt + (lane & 15)];
+            const float wc = s_colw[16 * t + (lane & 15)];
             w[0] = w[1] = w[2] = w[3] = wc;
         } else {
-            const float4 w4 = *reinterpret_cast<const float4 *>(tab.colw + 16 * tt + 4 * (lane >> 4));
+            const float4 w4 = *reinterpret_cast<const float4 *>(s_colw + 16 * t + 4 * (lane >> 4));
             w[0] = w4.x; w[1] = w4.y; w[2] = w4.z; w[3] = w4.w;
         }
 #pragma unroll
@@ -495,6 +522,15 @@ __device__ __forceinline__ void tile_loss(const LossU &lu, const LossTab &tab, c
             g[q] *= w[q];
         }
     }
+}
+
+// The per-column weights of a loss table's columns c0 .. c0 + count - 1
+// (clamped to the padded width, as the codes), into LDS.
+__device__ __forceinline__ void stage_colw(const LossTab &lt, int64_t c0, int count, int64_t ldp, float *s_colw,
+                                           int nthreads)
+{
+    for (int j = threadIdx.x; j < count; j += nthreads)
+        s_colw[j] = lt.colw ? lt.colw[min<int64_t>(c0 + j, ldp - 1)] : 1.0f;
 }
 
 // Per-tile loss codes: the tile's code when its sixteen columns share one
@@ -567,7 +603,8 @@ struct XStepShared {
 template <int KP, int TPW, int PREC, int LK>
 __device__ __forceinline__ void xstep_s6(const XStepArgs &a, const float4 *__restrict__ apan,
                                          const LossTab *__restrict__ lt, const uint8_t *__restrict__ s_codes,
-                                         const int8_t *__restrict__ s_tcode, const Frag<KP, PREC> (&yfr)[TPW],
+                                         const int8_t *__restrict__ s_tcode, const float *__restrict__ s_colw,
+                                         const Frag<KP, PREC> (&yfr)[TPW],
                                          const XatFrag<KP, PREC> &xa, const Frag<KP, PREC> &xaf,
                                          f32x4 (&dyacc)[TPW][KP / 16], float (&hacc)[TPW])
 {
@@ -592,7 +629,7 @@ __device__ __forceinline__ void xstep_s6(const XStepArgs &a, const float4 *__res
         }
         if (t >= nt) continue;
         float L4[4], G[4];
-        tile_loss<LK, true, true, TPW>(a.lu, *lt, s_codes, s_tcode, t, zt, av, L4, G);
+        tile_loss<LK, true, true, TPW>(a.lu, *lt, s_codes, s_tcode, t, zt, av, L4, G, s_colw);
         hacc[s] += (L4[0] + L4[1]) + (L4[2] + L4[3]);
         s6_resident<KP, PREC>(dyacc[s], G, xa);
     }
@@ -608,7 +645,8 @@ __device__ __forceinline__ void xstep_s6(const XStepArgs &a, const float4 *__res
 template <int KP, int TPW, int PREC, int LK, int BUF>
 __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, TPW, PREC> &__restrict__ sh,
                                             PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ pb0,
-                                            PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ pb1, int64_t p,
+                                            PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ pb1,
+                                            const float *__restrict__ s_colw, int64_t p,
                                             int64_t p_next, const Frag<KP, PREC> (&yfr)[TPW],
                                             const YtFrag<KP, PREC> (&ytf)[TPW], f32x4 (&dyacc)[TPW][KP / 16],
                                             float (&hacc)[TPW], float &rowreg_acc, int &rej_acc)
@@ -659,7 +697,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         }
         if (t >= nt) continue;
         float L4[4], G[4];
-        tile_loss<LK, true, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, z, av, L4, G);
+        tile_loss<LK, true, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, z, av, L4, G, s_colw);
         fpart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
         s3_resident<KP, PREC>(dx, G, ytf[s]);
     }
@@ -731,7 +769,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
         }
         if (t >= nt) continue;
         float L4[4], G4[4];
-        tile_loss<LK, false, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av, L4, G4);
+        tile_loss<LK, false, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, t, zp, av, L4, G4, s_colw);
         fppart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
     }
     sh.red_fp[li][4 * w + g] = fppart;
@@ -785,7 +823,7 @@ __device__ __forceinline__ void xstep_panel(const XStepArgs a, XStepShared<KP, T
     xatfrag_load<KP, PREC>(xa, sh.xat, li, g);
     Frag<KP, PREC> xaf;
     frag_from_f32<KP, PREC>(xaf, &sh.xs[li][g * C]);
-    xstep_s6<KP, TPW, PREC, LK>(a, apan, &sh.lt, sh.s_codes, sh.s_tcode, yfr, xa, xaf, dyacc, hacc);
+    xstep_s6<KP, TPW, PREC, LK>(a, apan, &sh.lt, sh.s_codes, sh.s_tcode, s_colw, yfr, xa, xaf, dyacc, hacc);
 }
 
 // Waves per SIMD the row pass is compiled for.  Narrow tables (few tiles per
@@ -803,12 +841,14 @@ __global__ __launch_bounds__(NTX_OF<KP>, (XSTEP_MIN_WAVES<KP, TPW>)) void xstep_
     // the panel buffers, LDS objects of their own
     __shared__ PanelBuf<KP, TPW, NWX_OF<KP>> sbuf0;
     __shared__ PanelBuf<KP, TPW, NWX_OF<KP>> sbuf1;
+    __shared__ alignas(16) float s_colw[LK < 0 ? 16 * NWX_OF<KP> * TPW : 4];
     PanelBuf<KP, TPW, NWX_OF<KP>> *const pb0 = &sbuf0, *const pb1 = &sbuf1;
     const int nt = (int)(a.ldp / 16);
     const int64_t npanels = a.mp / 16;
     const int64_t G = gridDim.x;
 
     for (int j = threadIdx.x; j < a.ldp; j += NTX_OF<KP>) sh.s_codes[j] = a.codes[j];
+    if constexpr (LK < 0) stage_colw(a.lt, 0, (int)a.ldp, a.ldp, s_colw, NTX_OF<KP>);
     if (threadIdx.x == 0) sh.lt = a.lt;
     __syncthreads();
     tile_codes(sh.s_codes, nt, sh.s_tcode, NTX_OF<KP>);
@@ -837,11 +877,11 @@ __global__ __launch_bounds__(NTX_OF<KP>, (XSTEP_MIN_WAVES<KP, TPW>)) void xstep_
                                          a.alpha, blockIdx.x, w, lane);
     for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
         const int64_t p1 = p + G, p2 = p + 2 * G;
-        xstep_panel<KP, TPW, PREC, LK, 0>(a, sh, pb0, pb1, p, p1 < npanels ? p1 : -1, yfr, ytf, dyacc, hacc,
-                                          rowreg_acc, rej_acc);
+        xstep_panel<KP, TPW, PREC, LK, 0>(a, sh, pb0, pb1, s_colw, p, p1 < npanels ? p1 : -1, yfr, ytf, dyacc,
+                                          hacc, rowreg_acc, rej_acc);
         if (p1 < npanels)
-            xstep_panel<KP, TPW, PREC, LK, 1>(a, sh, pb0, pb1, p1, p2 < npanels ? p2 : -1, yfr, ytf, dyacc, hacc,
-                                              rowreg_acc, rej_acc);
+            xstep_panel<KP, TPW, PREC, LK, 1>(a, sh, pb0, pb1, s_colw, p1, p2 < npanels ? p2 : -1, yfr, ytf, dyacc,
+                                              hacc, rowreg_acc, rej_acc);
     }
     __syncthreads();
 
@@ -962,7 +1002,8 @@ struct YCheckShared {
 };
 
 template <int KP, int TPW, int PREC, int LK, int BUF>
-__device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP, TPW> &sh, int64_t p,
+__device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP, TPW> &sh,
+                                             const float *__restrict__ s_colw, int64_t p,
                                              int64_t p_next, int tile0, const Frag<KP, PREC> (&yfr)[TPW],
                                              f32x4 (&hacc)[TPW])
 {
@@ -1003,7 +1044,7 @@ __device__ __forceinline__ void ycheck_panel(const YCheckArgs a, YCheckShared<KP
         const int tl = min(tile0 + w + NWY_OF<KP> * s, nt - 1) - tile0;
         const f32x4 zp = zprod<KP, PREC>(yfr[s], xf);
         float L4[4], G4[4];
-        tile_loss<LK, false, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, tl, zp, av[s], L4, G4, tile0 + tl);
+        tile_loss<LK, false, false, TPW>(a.lu, sh.lt, sh.s_codes, sh.s_tcode, tl, zp, av[s], L4, G4, s_colw);
 #pragma unroll
         for (int r = 0; r < 4; ++r) hacc[s][r] += L4[r];
     }
@@ -1015,6 +1056,7 @@ __global__ __launch_bounds__(NTY_OF<KP>, 1) void ycheck_kernel(YCheckArgs a)
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     __shared__ YCheckShared<KP, TPW> sh;
+    __shared__ alignas(16) float s_colw[LK < 0 ? 16 * NWY_OF<KP> * TPW : 4];
     const int nt = (int)(a.ldp / 16);
     const int64_t npanels = a.mp / 16;
     // workgroup b takes column block b % ncb of the panels b / ncb, b / ncb + G, ...
@@ -1027,6 +1069,7 @@ __global__ __launch_bounds__(NTY_OF<KP>, 1) void ycheck_kernel(YCheckArgs a)
     // repeat its last code, as the padding columns do)
     for (int j = threadIdx.x; j < 16 * NWY_OF<KP> * TPW; j += NTY_OF<KP>)
         sh.s_codes[j] = a.codes[min<int64_t>(16 * (int64_t)tile0 + j, a.ldp - 1)];
+    if constexpr (LK < 0) stage_colw(a.lt, 16 * (int64_t)tile0, 16 * NWY_OF<KP> * TPW, a.ldp, s_colw, NTY_OF<KP>);
     if (threadIdx.x == 0) sh.lt = a.lt;
     __syncthreads();
     tile_codes(sh.s_codes, NWY_OF<KP> * TPW, sh.s_tcode, NTY_OF<KP>);
@@ -1044,8 +1087,9 @@ __global__ __launch_bounds__(NTY_OF<KP>, 1) void ycheck_kernel(YCheckArgs a)
         stage_panel<KP, TPW, NWY_OF<KP>>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, b0, w, lane, tile0);
     for (int64_t p = b0; p < npanels; p += 2 * G) {
         const int64_t p1 = p + G, p2 = p + 2 * G;
-        ycheck_panel<KP, TPW, PREC, LK, 0>(a, sh, p, p1 < npanels ? p1 : -1, tile0, yfr, hacc);
-        if (p1 < npanels) ycheck_panel<KP, TPW, PREC, LK, 1>(a, sh, p1, p2 < npanels ? p2 : -1, tile0, yfr, hacc);
+        ycheck_panel<KP, TPW, PREC, LK, 0>(a, sh, s_colw, p, p1 < npanels ? p1 : -1, tile0, yfr, hacc);
+        if (p1 < npanels)
+            ycheck_panel<KP, TPW, PREC, LK, 1>(a, sh, s_colw, p1, p2 < npanels ? p2 : -1, tile0, yfr, hacc);
     }
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
@@ -1179,21 +1223,20 @@ __global__ __launch_bounds__(256) void yshadow_kernel(YShadowArgs a)
 // barriers and the tile loop none.
 template <int KP, int TPW, int PREC>
 struct GradShared {
-    PanelBuf<KP, TPW, NWX_OF<KP>> buf0, buf1;
-    float red_g[NWX_OF<KP>][16][RS<KP>];            // dX partials of the panel just computed
-    float gsc[NWX_OF<KP>][16 * GS];                 // per-wavefront G transpose tiles
+    float red_g[NWG_OF<KP>][16][RS<KP>];            // dX partials of the panel just computed
     LossTab lt;
-    uint8_t s_codes[16 * NWX_OF<KP> * TPW];
-    int8_t s_tcode[NWX_OF<KP> * TPW];
-    double s_obj[NWX_OF<KP>];
+    uint8_t s_codes[16 * NWG_OF<KP> * TPW];
+    int8_t s_tcode[NWG_OF<KP> * TPW];
+    double s_obj[NWG_OF<KP>];
 };
 
 template <int KP, int TPW, int PREC, int LK, bool WANT_GRAD>
-__device__ __forceinline__ float grad_tiles(const LossGradArgs &a, PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ nxt,
-                                            int64_t p_next, const PanelBuf<KP, TPW, NWX_OF<KP>> *__restrict__ cur,
+__device__ __forceinline__ float grad_tiles(const LossGradArgs &a, PanelBuf<KP, TPW, NWG_OF<KP>> *__restrict__ nxt,
+                                            int64_t p_next, const PanelBuf<KP, TPW, NWG_OF<KP>> *__restrict__ cur,
                                             int rows, int tile0, int nt, float *__restrict__ red_g,
-                                            float *__restrict__ gsc, const LossTab *__restrict__ lt,
+                                            const LossTab *__restrict__ lt,
                                             const uint8_t *__restrict__ s_codes, const int8_t *__restrict__ s_tcode,
+                                            const float *__restrict__ s_colw,
                                             const Frag<KP, PREC> (&yfr)[TPW], const YtFrag<KP, PREC> (&ytf)[TPW],
                                             f32x4 (&dyacc)[TPW][KP / 16])
 {
@@ -1228,7 +1271,7 @@ __device__ __forceinline__ float grad_tiles(const LossGradArgs &a, PanelBuf<KP, 
         }
     }
     if (p_next >= 0)
-        stage_panel<KP, TPW, NWX_OF<KP>>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, p_next, w, lane, tile0);
+        stage_panel<KP, TPW, NWG_OF<KP>>(*nxt, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, p_next, w, lane, tile0);
     const float4 *apan = cur->apan[w];
     float opart = 0.0f;
     f32x4 dx[KP / 16];
@@ -1238,7 +1281,7 @@ __device__ __forceinline__ float grad_tiles(const LossGradArgs &a, PanelBuf<KP, 
     float4 an = apan[lane];
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = tile0 + w + NWX_OF<KP> * s;
+        const int t = tile0 + w + NWG_OF<KP> * s;
         const f32x4 z = zn;
         const float4 av = an;
         if (s + 1 < TPW) {
@@ -1247,12 +1290,12 @@ __device__ __forceinline__ float grad_tiles(const LossGradArgs &a, PanelBuf<KP, 
         }
         if (t >= nt) continue;
         float L4[4], G[4];
-        tile_loss<LK, WANT_GRAD, false, TPW>(a.lu, *lt, s_codes, s_tcode, t - tile0, z, av, L4, G, t);
+        tile_loss<LK, WANT_GRAD, false, TPW>(a.lu, *lt, s_codes, s_tcode, t - tile0, z, av, L4, G, s_colw);
         opart += (L4[0] + L4[1]) + (L4[2] + L4[3]);
         if constexpr (WANT_GRAD) {
             s3_resident<KP, PREC>(dx, G, ytf[s]);
             float gT[4];
-            transpose_g(gsc + w * 16 * GS, G, gT, li, g);
+            transpose_g(G, gT);
             s6_resident<KP, PREC>(dyacc[s], gT, xa);
         }
     }
@@ -1270,12 +1313,12 @@ template <int KP, int LK>
 __device__ __forceinline__ void grad_reduce_dx(const LossGradArgs &a, const float (*red_g)[16][RS<KP>], int64_t p)
 {
     const int64_t i0 = p * 16;
-    for (int t = threadIdx.x; t < 16 * KP; t += NTX_OF<KP>) {
+    for (int t = threadIdx.x; t < 16 * KP; t += NTG_OF<KP>) {
         const int i = t / KP, c = t % KP;
         if (i0 + i < a.m && c < a.k) {
             float s = 0.0f;
 #pragma unroll
-            for (int q = 0; q < NWX_OF<KP>; ++q) s += red_g[q][i][c];
+            for (int q = 0; q < NWG_OF<KP>; ++q) s += red_g[q][i][c];
             s *= GRAD_SCALE<LK>;
             if (a.part_dx) a.part_dx[((int64_t)blockIdx.y * a.m + i0 + i) * a.k + c] = s;
             else a.dX[(i0 + i) * a.k + c] = s;
@@ -1284,27 +1327,34 @@ __device__ __forceinline__ void grad_reduce_dx(const LossGradArgs &a, const floa
 }
 
 template <int KP, int TPW, int PREC, int LK, bool WANT_GRAD>
-__global__ __launch_bounds__(NTX_OF<KP>, 1) void lossgrad_kernel(LossGradArgs a)
+__global__ __launch_bounds__(NTG_OF<KP>, 1) void lossgrad_kernel(LossGradArgs a)
 {
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, g = lane >> 4;
     __shared__ GradShared<KP, TPW, PREC> sh;
+    // the panel buffers, LDS objects of their own: the compiler then tells the
+    // next panel's direct-to-LDS loads apart from the tile loop's LDS traffic
+    // and keeps them in flight through it
+    __shared__ PanelBuf<KP, TPW, NWG_OF<KP>> sbuf0;
+    __shared__ PanelBuf<KP, TPW, NWG_OF<KP>> sbuf1;
+    __shared__ alignas(16) float s_colw[LK < 0 ? 16 * NWG_OF<KP> * TPW : 4];
     const int nt = (int)(a.ldp / 16);
     const int64_t npanels = a.mp / 16;
     const int64_t G = gridDim.x;
-    const int tile0 = (int)blockIdx.y * NWX_OF<KP> * TPW;
-    const int ntb = min(NWX_OF<KP> * TPW, nt - tile0);   // tiles of this column block
+    const int tile0 = (int)blockIdx.y * NWG_OF<KP> * TPW;
+    const int ntb = min(NWG_OF<KP> * TPW, nt - tile0);   // tiles of this column block
 
-    for (int j = threadIdx.x; j < 16 * NWX_OF<KP> * TPW; j += NTX_OF<KP>)
+    for (int j = threadIdx.x; j < 16 * NWG_OF<KP> * TPW; j += NTG_OF<KP>)
         sh.s_codes[j] = a.codes[min(16 * tile0 + j, (int)a.ldp - 1)];
+    if constexpr (LK < 0) stage_colw(a.lt, 16 * (int64_t)tile0, 16 * NWG_OF<KP> * TPW, a.ldp, s_colw, NTG_OF<KP>);
     if (threadIdx.x == 0) sh.lt = a.lt;
     __syncthreads();
-    tile_codes(sh.s_codes, ntb, sh.s_tcode, NTX_OF<KP>);
+    tile_codes(sh.s_codes, ntb, sh.s_tcode, NTG_OF<KP>);
     Frag<KP, PREC> yfr[TPW];
     YtFrag<KP, PREC> ytf[TPW];
 #pragma unroll
     for (int s = 0; s < TPW; ++s) {
-        const int t = min(tile0 + w + NWX_OF<KP> * s, nt - 1);
+        const int t = min(tile0 + w + NWG_OF<KP> * s, nt - 1);
         frag_load_y<KP, PREC>(yfr[s], a.ycur, 16 * t + li, g);
         if constexpr (WANT_GRAD) ytfrag_load<KP, PREC>(ytf[s], a.ycur, a.ldp, 16 * t, li, g);
     }
@@ -1316,7 +1366,7 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void lossgrad_kernel(LossGradArgs a)
     double obj = 0.0;
 
     if (blockIdx.x < npanels)
-        stage_panel<KP, TPW, NWX_OF<KP>>(sh.buf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, blockIdx.x, w, lane,
+        stage_panel<KP, TPW, NWG_OF<KP>>(sbuf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, blockIdx.x, w, lane,
                                          tile0);
     int64_t prev = -1;
     for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
@@ -1325,15 +1375,18 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void lossgrad_kernel(LossGradArgs a)
             const int64_t pc = p + b * G;
             if (pc >= npanels) break;
             const int64_t pn = pc + G < npanels ? pc + G : -1;
-            PanelBuf<KP, TPW, NWX_OF<KP>> &cur = b == 0 ? sh.buf0 : sh.buf1;
-            PanelBuf<KP, TPW, NWX_OF<KP>> &nxt = b == 0 ? sh.buf1 : sh.buf0;
+            PanelBuf<KP, TPW, NWG_OF<KP>> &cur = b == 0 ? sbuf0 : sbuf1;
+            PanelBuf<KP, TPW, NWG_OF<KP>> &nxt = b == 0 ? sbuf1 : sbuf0;
             wait_staged();
             if (WANT_GRAD && prev >= 0) grad_reduce_dx<KP, LK>(a, sh.red_g, prev);
-            __syncthreads();
+            // orders the reads of red_g above before this panel's writes; an
+            // LDS-only barrier, so the stores of the reduced rows stay in flight
+            // through the tile loop instead of being waited for here
+            lds_barrier();
             const int rows = (int)min<int64_t>(16, a.m - pc * 16);
             obj += (double)grad_tiles<KP, TPW, PREC, LK, WANT_GRAD>(a, &nxt, pn, &cur, rows, tile0, nt, &sh.red_g[0][0][0],
-                                                                    &sh.gsc[0][0], &sh.lt, sh.s_codes, sh.s_tcode,
-                                                                    yfr, ytf, dyacc);
+                                                                    &sh.lt, sh.s_codes, sh.s_tcode,
+                                                                    s_colw, yfr, ytf, dyacc);
             prev = pc;
         }
     }
@@ -1342,8 +1395,8 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void lossgrad_kernel(LossGradArgs a)
     if constexpr (WANT_GRAD) {
 #pragma unroll
         for (int s = 0; s < TPW; ++s) {
-            const int t = tile0 + w + NWX_OF<KP> * s;
-            if (t < nt && w + NWX_OF<KP> * s < NWX_OF<KP> * TPW) {
+            const int t = tile0 + w + NWG_OF<KP> * s;
+            if (t < nt && w + NWG_OF<KP> * s < NWG_OF<KP> * TPW) {
                 const int64_t j0 = 16 * t;
 #pragma unroll
                 for (int kb = 0; kb < KP / 16; ++kb)
@@ -1359,7 +1412,7 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void lossgrad_kernel(LossGradArgs a)
     __syncthreads();
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int q = 0; q < NWX_OF<KP>; ++q) s += sh.s_obj[q];
+        for (int q = 0; q < NWG_OF<KP>; ++q) s += sh.s_obj[q];
         a.part_obj[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
     }
 }
@@ -1391,6 +1444,7 @@ __device__ __forceinline__ void xwide_tiles(const XWideArgs &a, PanelBuf<KP, TPW
                                             int rows, int tile0, int nt, float *__restrict__ red_g,
                                             float *__restrict__ red_f, const LossTab *__restrict__ lt,
                                             const uint8_t *__restrict__ s_codes, const int8_t *__restrict__ s_tcode,
+                                            const float *__restrict__ s_colw,
                                             const Frag<KP, PREC> (&yfr)[TPW], const YtFrag<KP, PREC> (&ytf)[TPW],
                                             f32x4 (&dyacc)[TPW][KP / 16], float (&hacc)[TPW])
 {
@@ -1446,7 +1500,7 @@ __device__ __forceinline__ void xwide_tiles(const XWideArgs &a, PanelBuf<KP, TPW
         }
         if (t >= nt) continue;
         float L4[4], G[4];
-        tile_loss<LK, MODE != 1, MODE == 2, TPW>(a.lu, *lt, s_codes, s_tcode, t - tile0, z, av, L4, G, t);
+        tile_loss<LK, MODE != 1, MODE == 2, TPW>(a.lu, *lt, s_codes, s_tcode, t - tile0, z, av, L4, G, s_colw);
         const float l4 = (L4[0] + L4[1]) + (L4[2] + L4[3]);
         if constexpr (MODE == 2) {
             hacc[s] += l4;
@@ -1470,6 +1524,31 @@ __device__ __forceinline__ void xwide_tiles(const XWideArgs &a, PanelBuf<KP, TPW
     }
 }
 
+// Panel p's rows (modes 0, 1): the wavefronts' partials in wavefront order.
+template <int KP, int LK, int MODE, typename SH>
+__device__ __forceinline__ void xwide_reduce_rows(const XWideArgs &a, const SH &sh, int64_t p, int cb)
+{
+    const int64_t i0 = p * 16;
+    const int rows = (int)min<int64_t>(16, a.m - i0);
+    if (threadIdx.x < 16 && threadIdx.x < rows) {
+        float f = 0.0f;
+#pragma unroll
+        for (int v = 0; v < NWX_OF<KP>; ++v) f += sh.red_f[v][threadIdx.x];
+        a.part_f[(int64_t)cb * a.mp + i0 + threadIdx.x] = f;
+    }
+    if constexpr (MODE == 0) {
+        for (int t = threadIdx.x; t < 16 * KP; t += NTX_OF<KP>) {
+            const int i = t / KP, c = t % KP;
+            if (i < rows && c < a.k) {
+                float s = 0.0f;
+#pragma unroll
+                for (int v = 0; v < NWX_OF<KP>; ++v) s += sh.red_g[v][i][c];
+                a.part_dx[((int64_t)cb * a.m + i0 + i) * a.k + c] = GRAD_SCALE<LK> * s;
+            }
+        }
+    }
+}
+
 template <int KP, int TPW, int PREC, int LK, int MODE>
 __global__ __launch_bounds__(NTX_OF<KP>, 1) void xwide_kernel(XWideArgs a)
 {
@@ -1477,6 +1556,7 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void xwide_kernel(XWideArgs a)
     const int li = lane & 15, g = lane >> 4;
     constexpr bool SWZ = MODE == 2;
     __shared__ WideShared<KP, TPW, MODE> sh;
+    __shared__ alignas(16) float s_colw[LK < 0 ? 16 * NWX_OF<KP> * TPW : 4];
     // the panel buffers, LDS objects of their own (as in the fused row pass)
     __shared__ PanelBuf<KP, TPW, NWX_OF<KP>> sbuf0;
     __shared__ PanelBuf<KP, TPW, NWX_OF<KP>> sbuf1;
@@ -1489,6 +1569,7 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void xwide_kernel(XWideArgs a)
 
     for (int j = threadIdx.x; j < 16 * NWX_OF<KP> * TPW; j += NTX_OF<KP>)
         sh.s_codes[j] = a.codes[min<int64_t>(16 * (int64_t)tile0 + j, a.ldp - 1)];
+    if constexpr (LK < 0) stage_colw(a.lt, 16 * (int64_t)tile0, 16 * NWX_OF<KP> * TPW, a.ldp, s_colw, NTX_OF<KP>);
     if (threadIdx.x == 0) sh.lt = a.lt;
     __syncthreads();
     tile_codes(sh.s_codes, ntb, sh.s_tcode, NTX_OF<KP>);
@@ -1512,6 +1593,7 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void xwide_kernel(XWideArgs a)
     if (blockIdx.x < npanels)
         stage_panel<KP, TPW, NWX_OF<KP>, SWZ>(sbuf0, a.Ap, a.ldp, nt, a.X, a.m, a.k, nullptr, blockIdx.x, w, lane,
                                               tile0);
+    int64_t prev = -1;
     for (int64_t p = blockIdx.x; p < npanels; p += 2 * G) {
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
@@ -1521,33 +1603,23 @@ __global__ __launch_bounds__(NTX_OF<KP>, 1) void xwide_kernel(XWideArgs a)
             PanelBuf<KP, TPW, NWX_OF<KP>> &cur = b == 0 ? sbuf0 : sbuf1;
             PanelBuf<KP, TPW, NWX_OF<KP>> &nxt = b == 0 ? sbuf1 : sbuf0;
             wait_staged();
+            // the previous panel's rows, reduced here so that their stores stay
+            // in flight through this panel's tile loop
+            if constexpr (MODE != 2) {
+                if (prev >= 0) xwide_reduce_rows<KP, LK, MODE>(a, sh, prev, cb);
+                lds_barrier();
+            }
             const int64_t i0 = pc * 16;
             const int rows = (int)min<int64_t>(16, a.m - i0);
             xwide_tiles<KP, TPW, PREC, LK, MODE>(a, &nxt, pn, &cur, rows, tile0, nt, &sh.red_g[0][0][0],
-                                                 &sh.red_f[0][0], &sh.lt, sh.s_codes, sh.s_tcode, yfr, ytf, dyacc,
-                                                 hacc);
-            if constexpr (MODE != 2) {
-                // the panel's rows: the wavefronts' partials in wavefront order
-                lds_barrier();
-                if (threadIdx.x < 16 && threadIdx.x < rows) {
-                    float f = 0.0f;
-#pragma unroll
-                    for (int v = 0; v < NWX_OF<KP>; ++v) f += sh.red_f[v][threadIdx.x];
-                    a.part_f[(int64_t)cb * a.mp + i0 + threadIdx.x] = f;
-                }
-                if constexpr (MODE == 0) {
-                    for (int t = threadIdx.x; t < 16 * KP; t += NTX_OF<KP>) {
-                        const int i = t / KP, c = t % KP;
-                        if (i < rows && c < a.k) {
-                            float s = 0.0f;
-#pragma unroll
-                            for (int v = 0; v < NWX_OF<KP>; ++v) s += sh.red_g[v][i][c];
-                            a.part_dx[((int64_t)cb * a.m + i0 + i) * a.k + c] = GRAD_SCALE<LK> * s;
-                        }
-                    }
-                }
-            }
+                                                 &sh.red_f[0][0], &sh.lt, sh.s_codes, sh.s_tcode, s_colw, yfr, ytf,
+                                                 dyacc, hacc);
+            prev = pc;
         }
+    }
+    if constexpr (MODE != 2) {
+        __syncthreads();
+        if (prev >= 0) xwide_reduce_rows<KP, LK, MODE>(a, sh, prev, cb);
     }
     if constexpr (MODE == 2) {
 #pragma unroll

@@ -161,13 +161,13 @@ hipError_t launch_lossgrad_p(const LossGradArgs &a, int kp, int tpw, bool want_g
     constexpr int LK = LK_OF<LKS>;
     if (want_grad) {
         GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW16(tpw,
-            if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
-            else hipLaunchKernelGGL((lossgrad_kernel<KP, TPW, PREC, LK, true>), dim3(gx, gy), dim3(NTX_OF<KP>), 0, st,
+            if constexpr (KP == 64 && TPW > 2) return hipErrorInvalidValue;
+            else hipLaunchKernelGGL((lossgrad_kernel<KP, TPW, PREC, LK, true>), dim3(gx, gy), dim3(NTG_OF<KP>), 0, st,
                                     a)));
     } else {
         GLRM_DISPATCH_KP(kp, GLRM_DISPATCH_TPW16(tpw,
-            if constexpr (KP == 64 && TPW == 16) return hipErrorInvalidValue;
-            else hipLaunchKernelGGL((lossgrad_kernel<KP, TPW, PREC, LK, false>), dim3(gx, gy), dim3(NTX_OF<KP>), 0, st,
+            if constexpr (KP == 64 && TPW > 2) return hipErrorInvalidValue;
+            else hipLaunchKernelGGL((lossgrad_kernel<KP, TPW, PREC, LK, false>), dim3(gx, gy), dim3(NTG_OF<KP>), 0, st,
                                     a)));
     }
     return hipGetLastError();

@@ -51,9 +51,8 @@ constexpr int AUX_SMALL = 16 * LA_MAXB * LA_MAXB;  // doubles of small matrices 
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-#ifndef GLRM_GRAD_TMAX64
-#define GLRM_GRAD_TMAX64 4
-#endif
+// Tiles per wavefront of the gradient pass at kp = 64 (its instances stop at 2).
+constexpr int GRAD_TMAX64 = 2;
 
 int kp_of(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : 64); }
 
@@ -130,10 +129,10 @@ bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false, int aux_
     L.mp = round_up(d->m, 16);
     L.ldp = round_up(d->n, 16);
     const int64_t ntiles = L.ldp / 16;
-    // the gradient pass: xstep_waves(kp) wavefronts of up to 16 tiles (4 at
+    // the gradient pass: grad_waves(kp) wavefronts of up to 16 tiles (2 at
     // kp = 64); wider tables take several column blocks
     {
-        const int tmax = L.kp == 64 ? GLRM_GRAD_TMAX64 : 16, nw = xstep_waves((int)L.kp);
+        const int tmax = L.kp == 64 ? GRAD_TMAX64 : 16, nw = grad_waves((int)L.kp);
         int t = 1;
         while (t < tmax && (int64_t)nw * t < ntiles) t *= 2;
         L.tpw_grad = t;

@@ -34,6 +34,10 @@ struct LossU {
 // SIMD while kp <= 32.
 constexpr int xstep_waves(int kp) { return 4; }
 constexpr int ycheck_waves(int kp) { return kp >= 64 ? 4 : 8; }
+// The objective-and-gradient pass: at kp = 64 eight wavefronts of two tiles,
+// whose resident operands leave room for two wavefronts per SIMD; four
+// elsewhere.
+constexpr int grad_waves(int kp) { return kp >= 64 ? 8 : 4; }
 
 struct XStepArgs {
     int64_t m, mp, ldp;
