@@ -1,7 +1,6 @@
 // The prox-prox update for quadratic losses (Sections 7.2, 7.3), dense layout.
 // See proxprox.h.  Per half-step: a Gram pass over the table (the dense
-// contraction: 4 x 4 register tiles of G_i per thread, the fixed factor's rows
-// staged in LDS), a solve pass (one wavefront per row: Cholesky of
+// contraction, on the matrix cores), a solve pass (one wavefront per row: Cholesky of
 // G_i + I / (2 alpha) in double in LDS, then `inner` prox-prox updates by
 // triangular solves), and a check pass (old and trial row objectives summed
 // from the table, the step rule of Section 7.2).  Every sum has a fixed order.
@@ -49,46 +48,60 @@ __device__ __forceinline__ void tile_of(int u, int &ta, int &tb)
 }
 
 // ---- Gram pass --------------------------------------------------------------------
+// On the matrix cores: for a 16-row panel, G(16 rows x 16 pairs) += M(16 x 4) .
+// W(4 x 16) with M_ij the entry's weight (0 where A_ij is unobserved) and
+// W_j[(a, b)] = v_ja v_jb over the sixteen pairs of one upper 4 x 4 tile of
+// G; b(16 rows x 16 coordinates) += (M o A)(16 x 4) . V(4 x 16).  The fp32
+// 16x16x4 product keeps the products and sums in fp32, as the solve needs.
+// Wavefront w owns the upper tiles u = w, w + 4, ... and the b tiles
+// t = w, w + 4, ...; tiles past the rank k stay zero and are skipped.
+// Columns go in chunks of 64 staged in LDS: the panel's 16 x 64 entries and
+// the chunk's rows of the fixed factor.
 template <int KP>
 __global__ __launch_bounds__(256) void pp_gram_kernel(PPArgs a)
 {
     constexpr int NT = PP_NT<KP>, UT = PP_UT<KP>, GSZ = PP_GSZ<KP>;
-    constexpr int R = KP <= 32 ? 16 : 4;       // rows per workgroup
-    constexpr int S = 256 / R;                 // threads per row
-    constexpr int TPT = (UT + S - 1) / S;      // tiles per thread
-    constexpr int CH = 64;                     // staged columns
+    constexpr int TW = (UT + 3) / 4;          // upper tiles per wavefront
+    constexpr int BTW = (KP / 16 + 3) / 4;    // b tiles per wavefront
+    constexpr int CH = 64;                    // staged columns
     __shared__ float sV[CH][KP + 4];
-    __shared__ float sT[R][CH + 1];
+    __shared__ float sT[16][CH + 4];
     __shared__ float sW[CH];
-    const int t = threadIdx.x, r = t / S, sl = t % S;
-    const int64_t i = (int64_t)blockIdx.x * R + r;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    const int64_t i0 = (int64_t)blockIdx.x * 16;
     const int64_t per = (a.cols + a.splits - 1) / a.splits;
     const int64_t c0 = (int64_t)blockIdx.y * per, c1 = min<int64_t>(a.cols, c0 + per);
-    int ta[TPT], tb[TPT];
+    const int k = a.k;
+    // this lane's coordinates of each of its upper tiles (a = 4 ta + li / 4, b = 4 tb + li % 4)
+    int ca[TW], cb[TW];
+    bool act[TW];
 #pragma unroll
-    for (int q = 0; q < TPT; ++q) {
-        const int u = sl + S * q;
-        if (u < UT) tile_of<NT>(u, ta[q], tb[q]);
-        else ta[q] = tb[q] = -1;
+    for (int q = 0; q < TW; ++q) {
+        const int u = w + 4 * q;
+        int ta = -1, tb = -1;
+        if (u < UT) tile_of<NT>(u, ta, tb);
+        act[q] = u < UT && 4 * tb < k;          // tb >= ta: the tile meets the rank
+        ca[q] = act[q] ? 4 * ta + (li >> 2) : 0;
+        cb[q] = act[q] ? 4 * tb + (li & 3) : 0;
     }
-    float acc[TPT][16];
+    f32x4 acc[TW], bacc[BTW];
 #pragma unroll
-    for (int q = 0; q < TPT; ++q)
+    for (int q = 0; q < TW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[q][e] = 0.0f;
-    float bacc[4] = {0.f, 0.f, 0.f, 0.f};
-    const float wr = (a.wrow && i < a.rows) ? a.wrow[i] : 1.0f;
+    for (int q = 0; q < BTW; ++q) bacc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const float wr = (a.wrow && i0 + li < a.rows) ? a.wrow[i0 + li] : 1.0f;
     const float qnan = __builtin_nanf("");
     for (int64_t j0 = c0; j0 < c1; j0 += CH) {
         __syncthreads();
         for (int e = t; e < CH * KP; e += 256) {
             const int jj = e / KP, c = e % KP;
             const int64_t j = j0 + jj;
-            sV[jj][c] = (j < c1 && c < a.k) ? a.V[j * a.k + c] : 0.0f;
+            sV[jj][c] = (j < c1 && c < k) ? a.V[j * k + c] : 0.0f;
         }
-        for (int e = t; e < R * CH; e += 256) {
+        for (int e = t; e < 16 * CH; e += 256) {
             const int rr = e / CH, jj = e % CH;
-            const int64_t ii = (int64_t)blockIdx.x * R + rr, j = j0 + jj;
+            const int64_t ii = i0 + rr, j = j0 + jj;
             sT[rr][jj] = (ii < a.rows && j < c1) ? a.T[ii * a.ldt + j] : qnan;
         }
         if (t < CH) {
@@ -96,43 +109,44 @@ __global__ __launch_bounds__(256) void pp_gram_kernel(PPArgs a)
             sW[t] = (a.wcol && j < c1) ? a.wcol[j] : 1.0f;
         }
         __syncthreads();
-        const int jn = (int)min<int64_t>(CH, c1 - j0);
-        for (int jj = 0; jj < jn; ++jj) {
-            const float av = sT[r][jj];
-            if (av == av) {
-                const float w = wr * sW[jj];
+        const int nks = (int)((min<int64_t>(CH, c1 - j0) + 3) / 4);
+        for (int ks = 0; ks < nks; ++ks) {
+            const int jj = 4 * ks + g;              // this lane's column of the step (k index g)
+            const float av = sT[li][jj];            // row li (A operand: row li, k g)
+            const bool obs = av == av;
+            const float m = obs ? wr * sW[jj] : 0.0f;
+            const float mb = obs ? m * av : 0.0f;
 #pragma unroll
-                for (int q = 0; q < TPT; ++q) {
-                    if (ta[q] < 0) continue;
-                    const float4 ya = *reinterpret_cast<const float4 *>(&sV[jj][4 * ta[q]]);
-                    const float4 yb = *reinterpret_cast<const float4 *>(&sV[jj][4 * tb[q]]);
-                    const float wa[4] = {w * ya.x, w * ya.y, w * ya.z, w * ya.w};
-                    const float bb[4] = {yb.x, yb.y, yb.z, yb.w};
+            for (int q = 0; q < TW; ++q) {
+                if (!act[q]) continue;
+                const float bv = sV[jj][ca[q]] * sV[jj][cb[q]];     // B operand: k g, column li
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bv, acc[q], 0, 0, 0);
+            }
 #pragma unroll
-                    for (int p = 0; p < 4; ++p)
-#pragma unroll
-                        for (int qq = 0; qq < 4; ++qq) acc[q][4 * p + qq] += wa[p] * bb[qq];
-                }
-                if (sl < NT) {
-                    const float4 y = *reinterpret_cast<const float4 *>(&sV[jj][4 * sl]);
-                    const float wa = w * av;
-                    bacc[0] += wa * y.x; bacc[1] += wa * y.y; bacc[2] += wa * y.z; bacc[3] += wa * y.w;
-                }
+            for (int q = 0; q < BTW; ++q) {
+                const int bt = w + 4 * q;
+                if (bt >= KP / 16 || 16 * bt >= k) continue;
+                bacc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(mb, sV[jj][16 * bt + li], bacc[q], 0, 0, 0);
             }
         }
     }
-    if (i >= a.rows) return;
-    float *out = a.splits > 1 ? a.gpart + ((int64_t)blockIdx.y * a.rows + i) * GSZ : a.gram + i * GSZ;
+    // lane (li, g) holds rows 4 g + r of column li of each tile
 #pragma unroll
-    for (int q = 0; q < TPT; ++q) {
-        const int u = sl + S * q;
-        if (u < UT)
+    for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + 4 * g + r;
+        if (i >= a.rows) continue;
+        float *out = a.splits > 1 ? a.gpart + ((int64_t)blockIdx.y * a.rows + i) * GSZ : a.gram + i * GSZ;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) out[u * 16 + e] = acc[q][e];
+        for (int q = 0; q < TW; ++q) {
+            const int u = w + 4 * q;
+            if (u < UT) out[u * 16 + li] = act[q] ? acc[q][r] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < BTW; ++q) {
+            const int bt = w + 4 * q;
+            if (bt < KP / 16) out[UT * 16 + 16 * bt + li] = 16 * bt < k ? bacc[q][r] : 0.0f;
+        }
     }
-    if (sl < NT)
-#pragma unroll
-        for (int p = 0; p < 4; ++p) out[UT * 16 + 4 * sl + p] = bacc[p];
 }
 
 __global__ void pp_reduce_kernel(const float *part, int32_t np, int64_t len, float *out)
@@ -147,8 +161,7 @@ __global__ void pp_reduce_kernel(const float *part, int32_t np, int64_t len, flo
 template <int KP>
 static hipError_t pp_gram(const PPArgs &a, hipStream_t st)
 {
-    constexpr int R = KP <= 32 ? 16 : 4;
-    hipLaunchKernelGGL(pp_gram_kernel<KP>, dim3(nblk(a.rows, R), a.splits), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(pp_gram_kernel<KP>, dim3(nblk(a.rows, 16), a.splits), dim3(256), 0, st, a);
     if (a.splits > 1) {
         const int64_t len = a.rows * (int64_t)PP_GSZ<KP>;
         hipLaunchKernelGGL(pp_reduce_kernel, dim3(nblk(len)), dim3(256), 0, st, a.gpart, a.splits, len, a.gram);
@@ -261,47 +274,108 @@ hipError_t launch_pp_solve(const PPArgs &a, hipStream_t st)
 }
 
 // ---- check pass: old and trial loss sums per row (split partials), then the rule
+// On the matrix cores: per 16-row panel and 16-column tile, Z = U . V^T and
+// Z+ = U+ . V^T (fp32 16x16x4 products over the rank), then w (a - z)^2 per
+// observed entry.  Columns go in chunks of 64 staged in LDS, one 16-column
+// tile per wavefront; each lane sums its rows over its columns, and the sums
+// over the sixteen columns of a tile and over the four wavefronts are taken
+// in a fixed order at the end.
 template <int KP>
 __global__ __launch_bounds__(256) void pp_check_kernel(PPArgs a)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= a.rows) return;
-    const int k = a.k;
-    float xo[KP], xt[KP];
-#pragma unroll
-    for (int c = 0; c < KP; ++c) {
-        xo[c] = c < k ? a.U[i * k + c] : 0.0f;
-        xt[c] = c < k ? a.trial[i * k + c] : 0.0f;
-    }
+    constexpr int CH = 64, KS = KP / 4;
+    __shared__ float sV[CH][KP + 4];
+    __shared__ float sT[16][CH + 4];
+    __shared__ float sW[CH];
+    __shared__ float sSum[4][16][2];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int li = lane & 15, g = lane >> 4;
+    const int64_t i0 = (int64_t)blockIdx.x * 16;
     const int64_t per = (a.cols + a.splits - 1) / a.splits;
     const int64_t c0 = (int64_t)blockIdx.y * per, c1 = min<int64_t>(a.cols, c0 + per);
-    const float wr = a.wrow ? a.wrow[i] : 1.0f;
-    float lo = 0.0f, lt = 0.0f;
-    for (int64_t j = c0 + lane; j < c1; j += 64) {
-        const float av = a.T[i * a.ldt + j];
-        if (av == av) {
-            const float w = wr * (a.wcol ? a.wcol[j] : 1.0f);
-            float z = 0.0f, zt = 0.0f;
-            for (int c = 0; c < k; ++c) {
-                const float v = a.V[j * k + c];
-                z += xo[c] * v;
-                zt += xt[c] * v;
-            }
-            const float d = av - z, dt = av - zt;
-            lo += w * d * d;
-            lt += w * dt * dt;
+    const int k = a.k;
+    // A operands: row li of the panel, coordinates 4 kk + g (old and trial rows)
+    float uo[KS], ut[KS];
+    {
+        const int64_t i = i0 + li;
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            const int c = 4 * kk + g;
+            const bool ok = i < a.rows && c < k;
+            uo[kk] = ok ? a.U[i * k + c] : 0.0f;
+            ut[kk] = ok ? a.trial[i * k + c] : 0.0f;
         }
     }
+    // this lane's rows 4 g + r: their weights and sums
+    float wr[4], lo[4] = {0.f, 0.f, 0.f, 0.f}, lt[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        lo += __shfl_xor(lo, o, 64);
-        lt += __shfl_xor(lt, o, 64);
+    for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + 4 * g + r;
+        wr[r] = (a.wrow && i < a.rows) ? a.wrow[i] : 1.0f;
     }
-    if (lane == 0) {
-        float *fp = a.fpart + ((int64_t)blockIdx.y * a.rows + i) * 2;
-        fp[0] = lo;
-        fp[1] = lt;
+    const float qnan = __builtin_nanf("");
+    for (int64_t j0 = c0; j0 < c1; j0 += CH) {
+        __syncthreads();
+        for (int e = t; e < CH * KP; e += 256) {
+            const int jj = e / KP, c = e % KP;
+            const int64_t j = j0 + jj;
+            sV[jj][c] = (j < c1 && c < k) ? a.V[j * k + c] : 0.0f;
+        }
+        for (int e = t; e < 16 * CH; e += 256) {
+            const int rr = e / CH, jj = e % CH;
+            const int64_t ii = i0 + rr, j = j0 + jj;
+            sT[rr][jj] = (ii < a.rows && j < c1) ? a.T[ii * a.ldt + j] : qnan;
+        }
+        if (t < CH) {
+            const int64_t j = j0 + t;
+            sW[t] = (a.wcol && j < c1) ? a.wcol[j] : 1.0f;
+        }
+        __syncthreads();
+        // this wavefront's tile of the chunk: columns 16 w .. 16 w + 15
+        const int jc = 16 * w + li;               // B operand column, and this lane's column of Z
+        f32x4 zo = {0.f, 0.f, 0.f, 0.f}, zt = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            const float bv = sV[jc][4 * kk + g];
+            zo = __builtin_amdgcn_mfma_f32_16x16x4f32(uo[kk], bv, zo, 0, 0, 0);
+            zt = __builtin_amdgcn_mfma_f32_16x16x4f32(ut[kk], bv, zt, 0, 0, 0);
+        }
+        const float wc = sW[jc];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float av = sT[4 * g + r][jc];      // unobserved, or past the rows / columns: NaN
+            const float d = av - zo[r], dt = av - zt[r];
+            const float ww = wr[r] * wc;
+            lo[r] += av == av ? ww * d * d : 0.0f;
+            lt[r] += av == av ? ww * dt * dt : 0.0f;
+        }
+    }
+    // rows 4 g + r: the sixteen columns of the lane's group, then the wavefronts
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        lo[r] = row16_sum(lo[r]);
+        lt[r] = row16_sum(lt[r]);
+    }
+    if (li == 0)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            sSum[w][4 * g + r][0] = lo[r];
+            sSum[w][4 * g + r][1] = lt[r];
+        }
+    __syncthreads();
+    if (t < 16) {
+        const int64_t i = i0 + t;
+        if (i < a.rows) {
+            float so = 0.0f, st = 0.0f;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                so += sSum[v][t][0];
+                st += sSum[v][t][1];
+            }
+            float *fp = a.fpart + ((int64_t)blockIdx.y * a.rows + i) * 2;
+            fp[0] = so;
+            fp[1] = st;
+        }
     }
 }
 
@@ -333,9 +407,9 @@ hipError_t launch_pp_check(const PPArgs &a, hipStream_t st)
 {
     if (a.rows <= 0) return hipSuccess;
     switch (a.kp) {
-    case 16: hipLaunchKernelGGL(pp_check_kernel<16>, dim3(nblk(a.rows, 4), a.splits), dim3(256), 0, st, a); break;
-    case 32: hipLaunchKernelGGL(pp_check_kernel<32>, dim3(nblk(a.rows, 4), a.splits), dim3(256), 0, st, a); break;
-    case 64: hipLaunchKernelGGL(pp_check_kernel<64>, dim3(nblk(a.rows, 4), a.splits), dim3(256), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(pp_check_kernel<16>, dim3(nblk(a.rows, 16), a.splits), dim3(256), 0, st, a); break;
+    case 32: hipLaunchKernelGGL(pp_check_kernel<32>, dim3(nblk(a.rows, 16), a.splits), dim3(256), 0, st, a); break;
+    case 64: hipLaunchKernelGGL(pp_check_kernel<64>, dim3(nblk(a.rows, 16), a.splits), dim3(256), 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(pp_decide_kernel, dim3(nblk(a.rows)), dim3(256), 0, st, a);
