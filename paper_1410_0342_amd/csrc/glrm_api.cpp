@@ -107,7 +107,7 @@ struct Layout {
     bool pp = false;
     int pp_gsz = 0;
     size_t pp_At = 0, pp_gram = 0, pp_gpart = 0, pp_trial = 0, pp_fpart = 0;
-    size_t pp_objx = 0, pp_objy = 0, pp_rejx = 0, pp_rejy = 0;
+    size_t pp_objx = 0, pp_objy = 0, pp_rejx = 0, pp_rejy = 0, pp_fin = 0;
 
     size_t take(size_t bytes)
     {
@@ -226,14 +226,15 @@ bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false, int aux_
         L.pp = true;
         L.pp_gsz = pp_gram_floats((int)kp);
         L.pp_At = L.take(sizeof(float) * ldp * L.mp);
-        L.pp_gram = L.take(sizeof(float) * rmax * L.pp_gsz);
-        L.pp_gpart = L.take(sizeof(float) * PP_SPLITS_MAX * n * L.pp_gsz);
+        L.pp_gram = L.take(sizeof(float) * round_up(rmax, 16) * L.pp_gsz);
+        L.pp_gpart = L.take(sizeof(float) * PP_SPLITS_MAX * round_up(n, 16) * L.pp_gsz);
         L.pp_trial = L.take(sizeof(float) * rmax * L.k);
         L.pp_fpart = L.take(sizeof(float) * 2 * std::max<int64_t>(m, (int64_t)PP_SPLITS_MAX * n));
         L.pp_objx = L.take(sizeof(double) * m);
         L.pp_objy = L.take(sizeof(double) * n);
         L.pp_rejx = L.take(sizeof(int32_t) * m);
         L.pp_rejy = L.take(sizeof(int32_t) * n);
+        L.pp_fin = L.take(sizeof(double) * pp_finalize_part_doubles());
     }
     return true;
 }
@@ -1334,8 +1335,8 @@ int glrm_fit(const glrm_data *d0, float *X, float *Y, float *alpha_x, float *alp
             HIP_TRY(launch_pp_check(py, st));
             HIP_TRY(timer.stop(st));
             HIP_TRY(timer.start(3, st));
-            HIP_TRY(launch_pp_finalize(px.rowobj, px.rej, L.m, py.rowobj, py.rej, L.n, nullptr, stats, istats, history,
-                                       t, st));
+            HIP_TRY(launch_pp_finalize(px.rowobj, px.rej, L.m, py.rowobj, py.rej, L.n, at<double>(ws, L.pp_fin), stats,
+                                       istats, history, t, st));
             HIP_TRY(timer.stop(st));
             sweeps = t + 1;
             if (o->tol > 0.0) {

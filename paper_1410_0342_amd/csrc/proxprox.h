@@ -15,7 +15,9 @@
 namespace glrm {
 
 // Floats of one row's Gram data: the upper 4 x 4 tiles of G (kp / 4 tiles a
-// side), b (kp) and the column count, padded to a multiple of 4.
+// side) in slots padded to a multiple of four tiles, then b in 64 floats.
+// The Gram pass writes whole 16-row panels: gram holds the rows padded to 16,
+// and gpart splits x (rows padded to 16) rows.
 int pp_gram_floats(int kp);
 // Column splits of a row (partials summed in a fixed order afterwards).
 constexpr int PP_SPLITS_MAX = 32;
@@ -32,8 +34,8 @@ struct PPArgs {
     Reg reg;
     int32_t inner;
     float step_up, step_down;
-    float *gram;                  // rows x gsz (final Gram data)
-    float *gpart;                 // splits x rows x gsz (partials)
+    float *gram;                  // rows (padded to 16) x gsz (final Gram data)
+    float *gpart;                 // splits x rows (padded to 16) x gsz (partials)
     int32_t splits;
     float *trial;                 // rows x k
     float *fpart;                 // splits x rows x 2 (old and trial loss sums)
@@ -47,7 +49,9 @@ hipError_t launch_pp_solve(const PPArgs &a, hipStream_t st);
 hipError_t launch_pp_check(const PPArgs &a, hipStream_t st);
 // Padded transposed copy: dst (ldp x mp) from src (mp x ldp); NaN stays NaN.
 hipError_t launch_transpose(const float *src, int64_t rows, int64_t cols, float *dst, hipStream_t st);
-// out = sum of a double array and an int array (fixed order, one workgroup): stats[0] += sum(d), istats[slot] = sum(i)
+// The sweep's F (the rows' and columns' decided values) and rejection counts,
+// summed in a fixed order through `part` (pp_finalize_part_doubles() doubles).
+int pp_finalize_part_doubles();
 hipError_t launch_pp_finalize(const double *rowobj_x, const int32_t *rej_x, int64_t m, const double *rowobj_y,
                               const int32_t *rej_y, int64_t n, double *part, double *stats, long long *istats,
                               double *history, int32_t sweep, hipStream_t st);

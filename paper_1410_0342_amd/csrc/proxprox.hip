@@ -17,8 +17,14 @@ template <int KP>
 constexpr int PP_NT = KP / 4;                         // 4 x 4 tiles a side
 template <int KP>
 constexpr int PP_UT = PP_NT<KP> * (PP_NT<KP> + 1) / 2;  // upper tiles
+// One row's Gram data: the upper tiles, padded to four per wavefront of the
+// Gram pass (its stores then take no branch), then b in four 16-wide slots.
 template <int KP>
-constexpr int PP_GSZ = PP_UT<KP> * 16 + KP;           // floats of one row's Gram data
+constexpr int PP_TW = (PP_UT<KP> + 3) / 4;            // upper tiles per wavefront of the Gram pass
+template <int KP>
+constexpr int PP_BOFF = 4 * PP_TW<KP> * 16;           // offset of b
+template <int KP>
+constexpr int PP_GSZ = PP_BOFF<KP> + 64;              // floats of one row's Gram data
 
 int pp_gram_floats(int kp)
 {
@@ -47,6 +53,51 @@ __device__ __forceinline__ void tile_of(int u, int &ta, int &tb)
     ta = tb = -1;
 }
 
+// One 64-column chunk of a panel pass in registers: the fixed factor's 64
+// rows, the panel's 16 x 64 entries (NaN past the rows and columns) and the
+// column weights.  A chunk is loaded while the previous one computes, then
+// stored into LDS.
+template <int KP>
+struct PPChunk {
+    static constexpr int CH = 64, NV = CH * KP / 256, NE = 16 * CH / 256;
+    float v[NV], e[NE], w;
+
+    __device__ __forceinline__ void load(const PPArgs &a, int64_t i0, int64_t j0, int64_t c1)
+    {
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const int f = t + 256 * q, jj = f / KP, c = f % KP;
+            const int64_t j = j0 + jj;
+            v[q] = (j < c1 && c < a.k) ? a.V[j * a.k + c] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int f = t + 256 * q, rr = f / CH, jj = f % CH;
+            const int64_t ii = i0 + rr, j = j0 + jj;
+            e[q] = (ii < a.rows && j < c1) ? a.T[ii * a.ldt + j] : __builtin_nanf("");
+        }
+        const int64_t j = j0 + (t & (CH - 1));
+        w = (a.wcol && j < c1) ? a.wcol[j] : 1.0f;
+    }
+
+    __device__ __forceinline__ void store(float (*sV)[KP + 4], float (*sT)[CH + 4], float *sW) const
+    {
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            const int f = t + 256 * q;
+            sV[f / KP][f % KP] = v[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int f = t + 256 * q;
+            sT[f / CH][f % CH] = e[q];
+        }
+        if (t < CH) sW[t] = w;
+    }
+};
+
 // ---- Gram pass --------------------------------------------------------------------
 // On the matrix cores: for a 16-row panel, G(16 rows x 16 pairs) += M(16 x 4) .
 // W(4 x 16) with M_ij the entry's weight (0 where A_ij is unobserved) and
@@ -60,9 +111,9 @@ __device__ __forceinline__ void tile_of(int u, int &ta, int &tb)
 template <int KP>
 __global__ __launch_bounds__(256) void pp_gram_kernel(PPArgs a)
 {
-    constexpr int NT = PP_NT<KP>, UT = PP_UT<KP>, GSZ = PP_GSZ<KP>;
-    constexpr int TW = (UT + 3) / 4;          // upper tiles per wavefront
-    constexpr int BTW = (KP / 16 + 3) / 4;    // b tiles per wavefront
+    constexpr int NT = PP_NT<KP>, UT = PP_UT<KP>, GSZ = PP_GSZ<KP>, BOFF = PP_BOFF<KP>;
+    constexpr int TW = PP_TW<KP>;             // upper tiles per wavefront
+    static_assert(KP / 16 <= 4, "one b tile per wavefront");
     constexpr int CH = 64;                    // staged columns
     __shared__ float sV[CH][KP + 4];
     __shared__ float sT[16][CH + 4];
@@ -85,30 +136,21 @@ __global__ __launch_bounds__(256) void pp_gram_kernel(PPArgs a)
         ca[q] = act[q] ? 4 * ta + (li >> 2) : 0;
         cb[q] = act[q] ? 4 * tb + (li & 3) : 0;
     }
-    f32x4 acc[TW], bacc[BTW];
+    f32x4 acc[TW], bacc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < TW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int q = 0; q < BTW; ++q) bacc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bool bact = w < KP / 16 && 16 * w < k;   // this wavefront's b tile: coordinates 16 w ..
     const float wr = (a.wrow && i0 + li < a.rows) ? a.wrow[i0 + li] : 1.0f;
-    const float qnan = __builtin_nanf("");
+    // where the panel's rows go (chosen here, away from the products' results)
+    const int64_t rowsp = (a.rows + 15) / 16 * 16;
+    float *const obase = a.splits > 1 ? a.gpart + (int64_t)blockIdx.y * rowsp * GSZ : a.gram;
+    PPChunk<KP> chunk;
+    if (c0 < c1) chunk.load(a, i0, c0, c1);
     for (int64_t j0 = c0; j0 < c1; j0 += CH) {
         __syncthreads();
-        for (int e = t; e < CH * KP; e += 256) {
-            const int jj = e / KP, c = e % KP;
-            const int64_t j = j0 + jj;
-            sV[jj][c] = (j < c1 && c < k) ? a.V[j * k + c] : 0.0f;
-        }
-        for (int e = t; e < 16 * CH; e += 256) {
-            const int rr = e / CH, jj = e % CH;
-            const int64_t ii = i0 + rr, j = j0 + jj;
-            sT[rr][jj] = (ii < a.rows && j < c1) ? a.T[ii * a.ldt + j] : qnan;
-        }
-        if (t < CH) {
-            const int64_t j = j0 + t;
-            sW[t] = (a.wcol && j < c1) ? a.wcol[j] : 1.0f;
-        }
+        chunk.store(sV, sT, sW);
         __syncthreads();
+        if (j0 + CH < c1) chunk.load(a, i0, j0 + CH, c1);   // in flight while this chunk computes
         const int nks = (int)((min<int64_t>(CH, c1 - j0) + 3) / 4);
         for (int ks = 0; ks < nks; ++ks) {
             const int jj = 4 * ks + g;              // this lane's column of the step (k index g)
@@ -122,39 +164,35 @@ __global__ __launch_bounds__(256) void pp_gram_kernel(PPArgs a)
                 const float bv = sV[jj][ca[q]] * sV[jj][cb[q]];     // B operand: k g, column li
                 acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bv, acc[q], 0, 0, 0);
             }
-#pragma unroll
-            for (int q = 0; q < BTW; ++q) {
-                const int bt = w + 4 * q;
-                if (bt >= KP / 16 || 16 * bt >= k) continue;
-                bacc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(mb, sV[jj][16 * bt + li], bacc[q], 0, 0, 0);
-            }
+            if (bact) bacc = __builtin_amdgcn_mfma_f32_16x16x4f32(mb, sV[jj][16 * w + li], bacc, 0, 0, 0);
         }
     }
+    // One more product into every accumulator, so that the reads below follow
+    // a product in straight-line code: the wait states the reads need are then
+    // the compiler's straight-line ones, not counted across the loop's exit
+    // branch.  Every store below is unconditional (the output holds padded
+    // rows and padded tile slots).
+#pragma unroll
+    for (int q = 0; q < TW; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(0.0f, 0.0f, acc[q], 0, 0, 0);
+    bacc = __builtin_amdgcn_mfma_f32_16x16x4f32(0.0f, 0.0f, bacc, 0, 0, 0);
     // lane (li, g) holds rows 4 g + r of column li of each tile
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + 4 * g + r;
-        if (i >= a.rows) continue;
-        float *out = a.splits > 1 ? a.gpart + ((int64_t)blockIdx.y * a.rows + i) * GSZ : a.gram + i * GSZ;
+        const int64_t i = i0 + 4 * g + r;          // < rowsp
+        float *out = obase + i * GSZ;
 #pragma unroll
-        for (int q = 0; q < TW; ++q) {
-            const int u = w + 4 * q;
-            if (u < UT) out[u * 16 + li] = act[q] ? acc[q][r] : 0.0f;
-        }
-#pragma unroll
-        for (int q = 0; q < BTW; ++q) {
-            const int bt = w + 4 * q;
-            if (bt < KP / 16) out[UT * 16 + 16 * bt + li] = 16 * bt < k ? bacc[q][r] : 0.0f;
-        }
+        for (int q = 0; q < TW; ++q) out[(w + 4 * q) * 16 + li] = act[q] ? acc[q][r] : 0.0f;
+        out[BOFF + 16 * w + li] = bact ? bacc[r] : 0.0f;
     }
 }
 
-__global__ void pp_reduce_kernel(const float *part, int32_t np, int64_t len, float *out)
+// out[e] = sum over the np partial sets (each `stride` floats apart) of part[e], in order.
+__global__ void pp_reduce_kernel(const float *part, int32_t np, int64_t len, int64_t stride, float *out)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= len) return;
     float s = 0.0f;
-    for (int p = 0; p < np; ++p) s += part[(int64_t)p * len + e];
+    for (int p = 0; p < np; ++p) s += part[(int64_t)p * stride + e];
     out[e] = s;
 }
 
@@ -163,8 +201,9 @@ static hipError_t pp_gram(const PPArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(pp_gram_kernel<KP>, dim3(nblk(a.rows, 16), a.splits), dim3(256), 0, st, a);
     if (a.splits > 1) {
-        const int64_t len = a.rows * (int64_t)PP_GSZ<KP>;
-        hipLaunchKernelGGL(pp_reduce_kernel, dim3(nblk(len)), dim3(256), 0, st, a.gpart, a.splits, len, a.gram);
+        const int64_t len = a.rows * (int64_t)PP_GSZ<KP>, stride = (a.rows + 15) / 16 * 16 * (int64_t)PP_GSZ<KP>;
+        hipLaunchKernelGGL(pp_reduce_kernel, dim3(nblk(len)), dim3(256), 0, st, a.gpart, a.splits, len, stride,
+                           a.gram);
     }
     return hipGetLastError();
 }
@@ -238,7 +277,7 @@ __global__ __launch_bounds__(64) void pp_solve_kernel(PPArgs a)
         }
         __syncthreads();
     }
-    const double bc = lane < k ? (double)g[UT * 16 + lane] : 0.0;
+    const double bc = lane < k ? (double)g[PP_BOFF<KP> + lane] : 0.0;
     double x = lane < k ? (double)a.U[i * k + lane] : 0.0;
     for (int it = 0; it < a.inner; ++it) {
         if (lane < KP) sR[lane] = bc + h * x;
@@ -313,24 +352,13 @@ __global__ __launch_bounds__(256) void pp_check_kernel(PPArgs a)
         const int64_t i = i0 + 4 * g + r;
         wr[r] = (a.wrow && i < a.rows) ? a.wrow[i] : 1.0f;
     }
-    const float qnan = __builtin_nanf("");
+    PPChunk<KP> chunk;
+    if (c0 < c1) chunk.load(a, i0, c0, c1);
     for (int64_t j0 = c0; j0 < c1; j0 += CH) {
         __syncthreads();
-        for (int e = t; e < CH * KP; e += 256) {
-            const int jj = e / KP, c = e % KP;
-            const int64_t j = j0 + jj;
-            sV[jj][c] = (j < c1 && c < k) ? a.V[j * k + c] : 0.0f;
-        }
-        for (int e = t; e < 16 * CH; e += 256) {
-            const int rr = e / CH, jj = e % CH;
-            const int64_t ii = i0 + rr, j = j0 + jj;
-            sT[rr][jj] = (ii < a.rows && j < c1) ? a.T[ii * a.ldt + j] : qnan;
-        }
-        if (t < CH) {
-            const int64_t j = j0 + t;
-            sW[t] = (a.wcol && j < c1) ? a.wcol[j] : 1.0f;
-        }
+        chunk.store(sV, sT, sW);
         __syncthreads();
+        if (j0 + CH < c1) chunk.load(a, i0, j0 + CH, c1);   // in flight while this chunk computes
         // this wavefront's tile of the chunk: columns 16 w .. 16 w + 15
         const int jc = 16 * w + li;               // B operand column, and this lane's column of Z
         f32x4 zo = {0.f, 0.f, 0.f, 0.f}, zt = {0.f, 0.f, 0.f, 0.f};
@@ -440,17 +468,24 @@ hipError_t launch_transpose(const float *src, int64_t rows, int64_t cols, float 
 }
 
 // ---- the sweep's objective: decided column objectives + r of the decided rows ----
-__global__ __launch_bounds__(256) void pp_finalize_kernel(const double *rx, const int32_t *jx, int64_t m,
-                                                          const double *ry, const int32_t *jy, int64_t n,
-                                                          double *stats, long long *istats, double *history,
-                                                          int32_t sweep)
+// Two launches in a fixed order: PP_FIN_BLOCKS workgroups each sum a
+// contiguous range of the rows' and the columns' values into part (F, row
+// rejections, column rejections per workgroup), then one workgroup sums the
+// parts in order.
+constexpr int PP_FIN_BLOCKS = 128;
+
+__global__ __launch_bounds__(256) void pp_finalize_part_kernel(const double *rx, const int32_t *jx, int64_t m,
+                                                               const double *ry, const int32_t *jy, int64_t n,
+                                                               double *part)
 {
     __shared__ double sF[256];
-    __shared__ long long sa[256], sb[256];
-    double F = 0.0;
-    long long ra = 0, rb = 0;
-    for (int64_t q = threadIdx.x; q < n; q += 256) { F += ry[q]; rb += jy[q]; }
-    for (int64_t q = threadIdx.x; q < m; q += 256) { F += rx[q]; ra += jx[q]; }
+    __shared__ double sa[256], sb[256];
+    const int64_t mb = (m + PP_FIN_BLOCKS - 1) / PP_FIN_BLOCKS, nb = (n + PP_FIN_BLOCKS - 1) / PP_FIN_BLOCKS;
+    const int64_t m0 = blockIdx.x * mb, m1 = min<int64_t>(m, m0 + mb);
+    const int64_t n0 = blockIdx.x * nb, n1 = min<int64_t>(n, n0 + nb);
+    double F = 0.0, ra = 0.0, rb = 0.0;
+    for (int64_t q = n0 + threadIdx.x; q < n1; q += 256) { F += ry[q]; rb += jy[q]; }
+    for (int64_t q = m0 + threadIdx.x; q < m1; q += 256) { F += rx[q]; ra += jx[q]; }
     sF[threadIdx.x] = F;
     sa[threadIdx.x] = ra;
     sb[threadIdx.x] = rb;
@@ -464,20 +499,45 @@ __global__ __launch_bounds__(256) void pp_finalize_kernel(const double *rx, cons
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        part[blockIdx.x] = sF[0];
+        part[PP_FIN_BLOCKS + blockIdx.x] = sa[0];   // counts below 2^53: exact in double
+        part[2 * PP_FIN_BLOCKS + blockIdx.x] = sb[0];
+    }
+}
+
+__global__ __launch_bounds__(PP_FIN_BLOCKS) void pp_finalize_kernel(const double *part, double *stats,
+                                                                    long long *istats, double *history, int32_t sweep)
+{
+    __shared__ double sF[PP_FIN_BLOCKS], sa[PP_FIN_BLOCKS], sb[PP_FIN_BLOCKS];
+    sF[threadIdx.x] = part[threadIdx.x];
+    sa[threadIdx.x] = part[PP_FIN_BLOCKS + threadIdx.x];
+    sb[threadIdx.x] = part[2 * PP_FIN_BLOCKS + threadIdx.x];
+    __syncthreads();
+    for (int o = PP_FIN_BLOCKS / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sF[threadIdx.x] += sF[threadIdx.x + o];
+            sa[threadIdx.x] += sa[threadIdx.x + o];
+            sb[threadIdx.x] += sb[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
         stats[0] = sF[0];
-        istats[0] = sa[0];
-        istats[1] = sb[0];
+        istats[0] = (long long)sa[0];
+        istats[1] = (long long)sb[0];
         if (history) history[sweep] = sF[0];
     }
 }
+
+int pp_finalize_part_doubles() { return 3 * PP_FIN_BLOCKS; }
 
 hipError_t launch_pp_finalize(const double *rowobj_x, const int32_t *rej_x, int64_t m, const double *rowobj_y,
                               const int32_t *rej_y, int64_t n, double *part, double *stats, long long *istats,
                               double *history, int32_t sweep, hipStream_t st)
 {
-    (void)part;
-    hipLaunchKernelGGL(pp_finalize_kernel, dim3(1), dim3(256), 0, st, rowobj_x, rej_x, m, rowobj_y, rej_y, n, stats,
-                       istats, history, sweep);
+    hipLaunchKernelGGL(pp_finalize_part_kernel, dim3(PP_FIN_BLOCKS), dim3(256), 0, st, rowobj_x, rej_x, m, rowobj_y,
+                       rej_y, n, part);
+    hipLaunchKernelGGL(pp_finalize_kernel, dim3(1), dim3(PP_FIN_BLOCKS), 0, st, part, stats, istats, history, sweep);
     return hipGetLastError();
 }
 

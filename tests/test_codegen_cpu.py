@@ -137,3 +137,20 @@ def test_bf16_forms_do_not_spill(dense_asm, unit):
     sc = _scratch(dense_asm[unit][1])
     assert len(sc) > 20
     assert {k: v for k, v in sc.items() if v} == {}
+
+
+@pytest.mark.parametrize("src", ["proxprox.hip", "linalg.hip"])
+def test_no_short_wait_paths_in_the_other_matrix_core_kernels(dense_asm, learned_needs, src, tmp_path):
+    """The prox-prox passes and the linear-algebra kernels use fp32 matrix-core
+    products too; their paths are held to the same wait states (learned from
+    the dense units and from the file itself)."""
+    out = str(tmp_path / (src + ".s"))
+    cmd = [HIPCC] + B.FLAGS + ["-x", "hip", "--cuda-device-only", "-S", os.path.join(B.CSRC, src), "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    text = open(out).read()
+    need = dict(learned_needs)
+    for op, n in asm_hazards.straight_line_needs(asm_hazards.parse(text)[0]).items():
+        need[op] = max(need.get(op, 0), n)
+    found, _ = asm_hazards.check(text, need)
+    assert found == [], found[:5]
