@@ -262,15 +262,17 @@ __global__ __launch_bounds__(64) void pp_solve_kernel(PPArgs a)
         if (lane < k) sM[lane][lane] += h;
     }
     __syncthreads();
-    // Cholesky, lower triangle in place
-    for (int j = 0; j < KP; ++j) {
+    // Cholesky, lower triangle in place.  Coordinates past k are identity
+    // rows with a zero right-hand side: their factor and solution are exact
+    // without a step, so the steps stop at k.
+    for (int j = 0; j < k; ++j) {
         if (lane == j) {
             double d = sM[j][j];
             for (int l = 0; l < j; ++l) d -= sM[j][l] * sM[j][l];
             sM[j][j] = sqrt(d);
         }
         __syncthreads();
-        if (lane > j && lane < KP) {
+        if (lane > j && lane < k) {
             double s = sM[lane][j];
             for (int l = 0; l < j; ++l) s -= sM[lane][l] * sM[j][l];
             sM[lane][j] = s / sM[j][j];
@@ -282,13 +284,13 @@ __global__ __launch_bounds__(64) void pp_solve_kernel(PPArgs a)
     for (int it = 0; it < a.inner; ++it) {
         if (lane < KP) sR[lane] = bc + h * x;
         __syncthreads();
-        for (int j = 0; j < KP; ++j) {        // L y = rhs
+        for (int j = 0; j < k; ++j) {         // L y = rhs
             if (lane == j) sR[j] = sR[j] / sM[j][j];
             __syncthreads();
-            if (lane > j && lane < KP) sR[lane] -= sM[lane][j] * sR[j];
+            if (lane > j && lane < k) sR[lane] -= sM[lane][j] * sR[j];
             __syncthreads();
         }
-        for (int j = KP - 1; j >= 0; --j) {   // L^T x = y
+        for (int j = k - 1; j >= 0; --j) {    // L^T x = y
             if (lane == j) sR[j] = sR[j] / sM[j][j];
             __syncthreads();
             if (lane < j) sR[lane] -= sM[j][lane] * sR[j];
