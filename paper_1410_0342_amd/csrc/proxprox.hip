@@ -5,6 +5,7 @@
 // triangular solves), and a check pass (old and trial row objectives summed
 // from the table, the step rule of Section 7.2).  Every sum has a fixed order.
 #include <algorithm>
+#include <utility>
 
 #include "glrm_kernels.h"
 #include "proxprox.h"
@@ -32,6 +33,26 @@ int pp_gram_floats(int kp)
     case 16: return PP_GSZ<16>;
     case 32: return PP_GSZ<32>;
     default: return PP_GSZ<64>;
+    }
+}
+
+// The Gram data keeps only the upper 4 x 4 tiles that meet the rank: tile
+// rows and columns 0 .. nt - 1 with nt = ceil(k / 4), in the order of the
+// upper triangle's rows (slot u of `nt (nt + 1) / 2`).
+__device__ __forceinline__ int pp_nt(int k) { return (k + 3) / 4; }
+
+// slot u -> (ta, tb), ta <= tb, for nt tile rows (runtime)
+__device__ __forceinline__ void tile_of_rt(int u, int nt, int &ta, int &tb)
+{
+    ta = tb = -1;
+    for (int r = 0; r < nt; ++r) {
+        const int len = nt - r;
+        if (u < len) {
+            ta = r;
+            tb = r + u;
+            return;
+        }
+        u -= len;
     }
 }
 
@@ -104,15 +125,15 @@ struct PPChunk {
 // W_j[(a, b)] = v_ja v_jb over the sixteen pairs of one upper 4 x 4 tile of
 // G; b(16 rows x 16 coordinates) += (M o A)(16 x 4) . V(4 x 16).  The fp32
 // 16x16x4 product keeps the products and sums in fp32, as the solve needs.
-// Wavefront w owns the upper tiles u = w, w + 4, ... and the b tiles
-// t = w, w + 4, ...; tiles past the rank k stay zero and are skipped.
+// Wavefront w owns the slots u = w, w + 4, ... of the tiles that meet the
+// rank (TW of them, the instance chosen for k) and the b tile w.
 // Columns go in chunks of 64 staged in LDS: the panel's 16 x 64 entries and
 // the chunk's rows of the fixed factor.
-template <int KP>
+template <int KP, int TW>
 __global__ __launch_bounds__(256) void pp_gram_kernel(PPArgs a)
 {
-    constexpr int NT = PP_NT<KP>, UT = PP_UT<KP>, GSZ = PP_GSZ<KP>, BOFF = PP_BOFF<KP>;
-    constexpr int TW = PP_TW<KP>;             // upper tiles per wavefront
+    constexpr int GSZ = PP_GSZ<KP>, BOFF = PP_BOFF<KP>;
+    static_assert(4 * TW <= 4 * PP_TW<KP>, "slots");
     static_assert(KP / 16 <= 4, "one b tile per wavefront");
     constexpr int CH = 64;                    // staged columns
     __shared__ float sV[CH][KP + 4];
@@ -125,14 +146,15 @@ __global__ __launch_bounds__(256) void pp_gram_kernel(PPArgs a)
     const int64_t c0 = (int64_t)blockIdx.y * per, c1 = min<int64_t>(a.cols, c0 + per);
     const int k = a.k;
     // this lane's coordinates of each of its upper tiles (a = 4 ta + li / 4, b = 4 tb + li % 4)
+    const int nt = pp_nt(k), ut = nt * (nt + 1) / 2;
     int ca[TW], cb[TW];
     bool act[TW];
 #pragma unroll
     for (int q = 0; q < TW; ++q) {
         const int u = w + 4 * q;
         int ta = -1, tb = -1;
-        if (u < UT) tile_of<NT>(u, ta, tb);
-        act[q] = u < UT && 4 * tb < k;          // tb >= ta: the tile meets the rank
+        if (u < ut) tile_of_rt(u, nt, ta, tb);
+        act[q] = u < ut;
         ca[q] = act[q] ? 4 * ta + (li >> 2) : 0;
         cb[q] = act[q] ? 4 * tb + (li & 3) : 0;
     }
@@ -196,10 +218,33 @@ __global__ void pp_reduce_kernel(const float *part, int32_t np, int64_t len, int
     out[e] = s;
 }
 
+// Slots per wavefront of the Gram pass for rank k: the smallest instance
+// that holds ceil(nt (nt + 1) / 2 / 4) of them.
+template <int KP, int... TWS>
+static hipError_t pp_gram_launch(const PPArgs &a, int need, hipStream_t st, std::integer_sequence<int, TWS...>)
+{
+    hipError_t e = hipErrorInvalidValue;
+    bool done = false;
+    auto one = [&](auto twc) {
+        constexpr int TW = decltype(twc)::value;
+        if constexpr (TW <= PP_TW<KP>) {
+            if (!done && need <= TW) {
+                hipLaunchKernelGGL((pp_gram_kernel<KP, TW>), dim3(nblk(a.rows, 16), a.splits), dim3(256), 0, st, a);
+                e = hipGetLastError();
+                done = true;
+            }
+        }
+    };
+    (one(std::integral_constant<int, TWS>{}), ...);
+    return e;
+}
+
 template <int KP>
 static hipError_t pp_gram(const PPArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(pp_gram_kernel<KP>, dim3(nblk(a.rows, 16), a.splits), dim3(256), 0, st, a);
+    const int nt = (a.k + 3) / 4, need = (nt * (nt + 1) / 2 + 3) / 4;
+    hipError_t e = pp_gram_launch<KP>(a, need, st, std::integer_sequence<int, 1, 2, 3, 4, 6, 9, 12, 17, 23, 34>{});
+    if (e != hipSuccess) return e;
     if (a.splits > 1) {
         const int64_t len = a.rows * (int64_t)PP_GSZ<KP>, stride = (a.rows + 15) / 16 * 16 * (int64_t)PP_GSZ<KP>;
         hipLaunchKernelGGL(pp_reduce_kernel, dim3(nblk(len)), dim3(256), 0, st, a.gpart, a.splits, len, stride,
@@ -245,10 +290,12 @@ __global__ __launch_bounds__(64) void pp_solve_kernel(PPArgs a)
     const int k = a.k;
     const double al = (double)a.alpha[i];
     const double h = 1.0 / (2.0 * al);
-    // the symmetric matrix from its upper tiles
-    for (int e = lane; e < UT * 16; e += 64) {
+    // the symmetric matrix from the upper tiles that meet the rank (the rest
+    // of its lower triangle is set below)
+    const int nt = pp_nt(k), ut = nt * (nt + 1) / 2;
+    for (int e = lane; e < ut * 16; e += 64) {
         int ta, tb;
-        tile_of<NT>(e >> 4, ta, tb);
+        tile_of_rt(e >> 4, nt, ta, tb);
         const int rr = 4 * ta + ((e >> 2) & 3), cc = 4 * tb + (e & 3);
         const double v = (double)g[e];
         sM[rr][cc] = v;

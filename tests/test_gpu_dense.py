@@ -322,7 +322,7 @@ def test_fit_beyond_the_rank_limit_is_reported():
 
 
 
-@pytest.mark.parametrize("layout", ["dense", "coo"])
+@pytest.mark.parametrize("layout", ["dense", "coo", "dense_wide"])
 @pytest.mark.parametrize("prec", [g.FP32, g.BF16])
 def test_overflowing_step_sizes_leave_the_factors_finite(layout, prec):
     """Step sizes that overflow float32 (alpha_scale 3e38, zero regularizers,
@@ -330,7 +330,8 @@ def test_overflowing_step_sizes_leave_the_factors_finite(layout, prec):
     with an infinite or NaN coordinate, or whose products overflow, is never
     accepted, so X and Y stay finite and every observed row and column keeps
     its start, as in the oracle; the objective equals the oracle's."""
-    case = synth.small_mixed(60, 30, 4, seed=81, missing=0.3, layout=layout, rx=(0, 0.0), ry=(0, 0.0),
+    n = 1030 if layout == "dense_wide" else 30      # 1030: the row half-step in column blocks
+    case = synth.small_mixed(60, n, 4, seed=81, missing=0.3, layout=layout.split("_")[0], rx=(0, 0.0), ry=(0, 0.0),
                              empty_row=3, empty_col=7)
     data = g.Data.from_case(case, DEV)
     X, Y = to_dev(case.X0, DEV), to_dev(case.Y0, DEV)
