@@ -103,6 +103,7 @@ struct Layout {
     size_t aux_part = 0;                 // partial sums
     size_t aux_small = 0;                // AUX_SMALL doubles of small matrices
     size_t aux_cols = 0;                 // 8 n doubles of per-column state
+    size_t aux_colout = 0;               // COL_SLOTS n doubles: the column passes' results
     // prox-prox region (dense fits with the prox-prox update)
     bool pp = false;
     int pp_gsz = 0;
@@ -216,10 +217,12 @@ bool make_layout(const glrm_data *d, Layout &L, bool grad_only = false, int aux_
         L.aux_n2 = L.take(sizeof(double) * n * b);
         const int64_t kb = std::max<int64_t>(kp, b);
         const int64_t parts = std::max<int64_t>({(int64_t)LA_TCHUNKS * n * b,
-                                                 (int64_t)tall_tmul_blocks(std::max(m, n)) * kb * kb, 256});
+                                                 (int64_t)tall_tmul_blocks(std::max(m, n)) * kb * kb, 256,
+                                                 d->layout == GLRM_DENSE ? col_part_doubles(m, n) : 0});
         L.aux_part = L.take(sizeof(double) * parts);
         L.aux_small = L.take(sizeof(double) * AUX_SMALL);
         L.aux_cols = L.take(sizeof(double) * 8 * n);
+        L.aux_colout = L.take(sizeof(double) * COL_SLOTS * n);
     }
     if (proxprox && d->layout == GLRM_DENSE) {
         const int64_t rmax = std::max(m, n);
@@ -1040,16 +1043,19 @@ int glrm_column_scaling(const glrm_data *d0, float *mu, float *sigma2, void *ws,
     }
     a.codes = at<uint8_t>(ws, L.codes);
     a.lt = make_losstab(d, L, ws);
-    double *lo = at<double>(ws, L.aux_cols), *hi = lo + L.n, *mid = hi + L.n, *out = mid + L.n;
-    a.mid = mid;
+    // per column: the bracket and its midpoint, and the passes' results
+    double *lo = at<double>(ws, L.aux_cols), *hi = lo + L.n, *mid = hi + L.n;
+    double *out = at<double>(ws, L.aux_colout);
+    a.lo = lo; a.hi = hi; a.mid = mid;
     double *part = at<double>(ws, L.aux_part);
     const int32_t *count = at<int32_t>(ws, L.col_count);
     HIP_TRY(launch_col_pass(a, 0, coo, part, out, st));
     HIP_TRY(launch_bracket(lo, hi, mid, out, count, L.n, true, st));
-    // bisection on the sign of the derivative sum: the bracket [min a - 1,
-    // max a + 1] holds a minimizer of every loss here, and 64 halvings take it
-    // to double rounding
-    for (int it = 0; it < 64; ++it) {
+    // a search on the sign of the derivative sum: the bracket [min a - 1,
+    // max a + 1] holds a minimizer of every loss here; each pass keeps one of
+    // COL_PTS + 1 = 16 sub-intervals, so 16 passes take it as far as 64
+    // halvings, to double rounding
+    for (int it = 0; it < 16; ++it) {
         HIP_TRY(launch_col_pass(a, 1, coo, part, out, st));
         HIP_TRY(launch_bracket(lo, hi, mid, out, count, L.n, false, st));
     }

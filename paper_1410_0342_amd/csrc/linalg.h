@@ -81,6 +81,14 @@ hipError_t launch_to_float(const double *src, int64_t rows, int32_t b, int32_t c
 // 2: sum of L_j(mid_j, a).  Dense: partials over row chunks (part: R x 2 x n
 // doubles) then a fixed-order reduction into out (2 x n); COO: one wavefront
 // per column of the column-grouped copy, straight into out.
+// The per-column passes of the loss scaling (Section 4.3): mode 0 the least
+// and largest value, mode 1 the derivative sums at COL_PTS points of each
+// column's bracket [lo, hi], mode 2 the loss sum at mid.  out holds the
+// results as slot-major arrays of n (slot p of column j at p n + j).
+constexpr int COL_PTS = 15;
+constexpr int COL_SLOTS = 16;                  // partial slots per row chunk and column
+constexpr int COL_CHUNKS_MAX = 256;
+constexpr int64_t COL_PART_BUDGET = int64_t(1) << 22;   // doubles of partials, at most (or one chunk)
 struct ColArgs {
     int64_t m, n, mp, ldp;
     const float *Ap;            // dense table (NaN = unobserved)
@@ -88,12 +96,15 @@ struct ColArgs {
     const float *csc_val;
     const uint8_t *codes;
     LossTab lt;
-    const double *mid;          // n: the point of modes 1 and 2
+    const double *lo, *hi;      // n: the bracket (mode 1)
+    const double *mid;          // n: the point of mode 2
 };
-int col_pass_chunks(int64_t m);
+int col_pass_chunks(int64_t m, int64_t n);
+int64_t col_part_doubles(int64_t m, int64_t n);     // partials of the dense passes
 hipError_t launch_col_pass(const ColArgs &a, int mode, bool coo, double *part, double *out, hipStream_t st);
 // lo, hi (n): the bracket; mid = (lo + hi) / 2.  init: lo = min - 1, hi = max + 1
-// from out (mode 0); step: the half whose end keeps the derivative's sign change.
+// from out (mode 0); step: the sub-interval, between two of mode 1's points,
+// that keeps the derivative's sign change.
 hipError_t launch_bracket(double *lo, double *hi, double *mid, const double *out, const int32_t *count, int64_t n,
                           bool init, hipStream_t st);
 // mu_j = mid_j (0 for an empty column); sigma2_j = S_j / (n_j - 1), or 1 when

@@ -451,22 +451,98 @@ hipError_t launch_to_float(const double *src, int64_t rows, int32_t b, int32_t c
 }
 
 // ---- per-column sums (loss scaling) ------------------------------------------------
+// Mode 0: each column's least and largest value; mode 1: the derivative sums
+// at the COL_PTS points lo + (hi - lo) p / (COL_PTS + 1), p = 1..COL_PTS, of
+// the column's bracket; mode 2: the loss sum at mid.  Partial sums per row
+// chunk, COL_SLOTS of them per column, combined in chunk order.
 
-constexpr int COL_CHUNKS = 32;
+int col_pass_chunks(int64_t m, int64_t n)
+{
+    const int64_t by_budget = COL_PART_BUDGET / ((int64_t)COL_SLOTS * std::max<int64_t>(n, 1));
+    return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)COL_CHUNKS_MAX, (m + 255) / 256, by_budget}));
+}
 
-int col_pass_chunks(int64_t m) { return (int)std::min<int64_t>(COL_CHUNKS, std::max<int64_t>(1, (m + 255) / 256)); }
+int64_t col_part_doubles(int64_t m, int64_t n) { return (int64_t)col_pass_chunks(m, n) * COL_SLOTS * n; }
+
+__device__ __forceinline__ double col_point(double lo, double hi, int p)
+{
+    return lo + (hi - lo) * (double)(p + 1) / (double)(COL_PTS + 1);
+}
 
 template <int MODE>
-__device__ __forceinline__ void col_term(const ColArgs &a, int64_t j, float av, double &s0, double &s1)
+struct ColAcc {
+    double s[MODE == 1 ? COL_PTS : 2];
+};
+
+template <int MODE>
+__device__ __forceinline__ void col_init(ColAcc<MODE> &c)
 {
     if constexpr (MODE == 0) {
-        s0 = fmin(s0, (double)av);
-        s1 = fmax(s1, (double)av);
+        c.s[0] = __builtin_huge_val();
+        c.s[1] = -__builtin_huge_val();
+    } else {
+#pragma unroll
+        for (int p = 0; p < (MODE == 1 ? COL_PTS : 2); ++p) c.s[p] = 0.0;
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void col_term(const ColArgs &a, int64_t j, float av, ColAcc<MODE> &c)
+{
+    if constexpr (MODE == 0) {
+        c.s[0] = fmin(c.s[0], (double)av);
+        c.s[1] = fmax(c.s[1], (double)av);
     } else {
         const int q = a.lt.uniform >= 0 ? a.lt.uniform : a.codes[j];
-        const double mu = a.mid[j];
-        if constexpr (MODE == 1) s0 += loss_g64(a.lt.kind[q], a.lt.levels[q], (double)a.lt.param[q], mu, (double)av);
-        else s0 += loss_l64(a.lt.kind[q], a.lt.levels[q], (double)a.lt.param[q], mu, (double)av);
+        const int kind = a.lt.kind[q], lev = a.lt.levels[q];
+        const double par = (double)a.lt.param[q];
+        if constexpr (MODE == 1) {
+            const double lo = a.lo[j], hi = a.hi[j];
+#pragma unroll
+            for (int p = 0; p < COL_PTS; ++p) c.s[p] += loss_g64(kind, lev, par, col_point(lo, hi, p), (double)av);
+        } else {
+            c.s[0] += loss_l64(kind, lev, par, a.mid[j], (double)av);
+        }
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void col_merge(ColAcc<MODE> &c, const ColAcc<MODE> &o)
+{
+    if constexpr (MODE == 0) {
+        c.s[0] = fmin(c.s[0], o.s[0]);
+        c.s[1] = fmax(c.s[1], o.s[1]);
+    } else {
+#pragma unroll
+        for (int p = 0; p < (MODE == 1 ? COL_PTS : 2); ++p) c.s[p] += o.s[p];
+    }
+}
+
+template <int MODE>
+constexpr int col_nslots() { return MODE == 1 ? COL_PTS : 2; }
+
+// The rows r0 .. r1 - 1 of column j under loss kind KIND (a constant, so
+// the loss's code is selected once per column, not per entry and point).
+template <int MODE, int KIND>
+__device__ __forceinline__ void col_rows(const ColArgs &a, int64_t j, int64_t r0, int64_t r1, int lev, double par,
+                                         ColAcc<MODE> &c)
+{
+    double x[MODE == 1 ? COL_PTS : 1];
+    if constexpr (MODE == 1) {
+#pragma unroll
+        for (int p = 0; p < COL_PTS; ++p) x[p] = col_point(a.lo[j], a.hi[j], p);
+    } else {
+        x[0] = a.mid[j];
+    }
+    for (int64_t i = r0; i < r1; ++i) {
+        const float av = a.Ap[i * a.ldp + j];
+        if (!(av == av)) continue;
+        if constexpr (MODE == 1) {
+#pragma unroll
+            for (int p = 0; p < COL_PTS; ++p) c.s[p] += loss_g64(KIND, lev, par, x[p], (double)av);
+        } else {
+            c.s[0] += loss_l64(KIND, lev, par, x[0], (double)av);
+        }
     }
 }
 
@@ -477,13 +553,27 @@ __global__ __launch_bounds__(256) void col_pass_dense_kernel(ColArgs a, int64_t 
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= a.n) return;
     const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min<int64_t>(a.m, r0 + per);
-    double s0 = MODE == 0 ? __builtin_huge_val() : 0.0, s1 = MODE == 0 ? -__builtin_huge_val() : 0.0;
-    for (int64_t i = r0; i < r1; ++i) {
-        const float av = a.Ap[i * a.ldp + j];
-        if (av == av) col_term<MODE>(a, j, av, s0, s1);
+    ColAcc<MODE> c;
+    col_init<MODE>(c);
+    if constexpr (MODE == 0) {
+        for (int64_t i = r0; i < r1; ++i) {
+            const float av = a.Ap[i * a.ldp + j];
+            if (av == av) col_term<MODE>(a, j, av, c);
+        }
+    } else {
+        const int q = a.lt.uniform >= 0 ? a.lt.uniform : a.codes[j];
+        const int lev = a.lt.levels[q];
+        const double par = (double)a.lt.param[q];
+        switch (a.lt.kind[q]) {
+        case L_QUAD: col_rows<MODE, L_QUAD>(a, j, r0, r1, lev, par, c); break;
+        case L_HUBER: col_rows<MODE, L_HUBER>(a, j, r0, r1, lev, par, c); break;
+        case L_LOGISTIC: col_rows<MODE, L_LOGISTIC>(a, j, r0, r1, lev, par, c); break;
+        case L_HINGE: col_rows<MODE, L_HINGE>(a, j, r0, r1, lev, par, c); break;
+        default: col_rows<MODE, L_ORDINAL>(a, j, r0, r1, lev, par, c); break;
+        }
     }
-    part[((int64_t)blockIdx.y * 2) * a.n + j] = s0;
-    part[((int64_t)blockIdx.y * 2 + 1) * a.n + j] = s1;
+#pragma unroll
+    for (int p = 0; p < col_nslots<MODE>(); ++p) part[((int64_t)blockIdx.y * COL_SLOTS + p) * a.n + j] = c.s[p];
 }
 
 template <int MODE>
@@ -491,14 +581,16 @@ __global__ void col_reduce_kernel(const double *part, int32_t R, int64_t n, doub
 {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
-    double s0 = MODE == 0 ? __builtin_huge_val() : 0.0, s1 = MODE == 0 ? -__builtin_huge_val() : 0.0;
+    ColAcc<MODE> c;
+    col_init<MODE>(c);
     for (int r = 0; r < R; ++r) {
-        const double p0 = part[((int64_t)r * 2) * n + j], p1 = part[((int64_t)r * 2 + 1) * n + j];
-        if constexpr (MODE == 0) { s0 = fmin(s0, p0); s1 = fmax(s1, p1); }
-        else s0 += p0;
+        ColAcc<MODE> o;
+#pragma unroll
+        for (int p = 0; p < col_nslots<MODE>(); ++p) o.s[p] = part[((int64_t)r * COL_SLOTS + p) * n + j];
+        col_merge<MODE>(c, o);
     }
-    out[j] = s0;
-    out[n + j] = s1;
+#pragma unroll
+    for (int p = 0; p < col_nslots<MODE>(); ++p) out[(int64_t)p * n + j] = c.s[p];
 }
 
 // one wavefront per column of the column-grouped copy
@@ -508,18 +600,19 @@ __global__ __launch_bounds__(256) void col_pass_coo_kernel(ColArgs a, double *ou
     const int lane = threadIdx.x & 63;
     const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= a.n) return;
-    double s0 = MODE == 0 ? __builtin_huge_val() : 0.0, s1 = MODE == 0 ? -__builtin_huge_val() : 0.0;
-    for (int32_t e = a.col_ptr[j] + lane; e < a.col_ptr[j + 1]; e += 64) col_term<MODE>(a, j, a.csc_val[e], s0, s1);
+    ColAcc<MODE> c;
+    col_init<MODE>(c);
+    for (int32_t e = a.col_ptr[j] + lane; e < a.col_ptr[j + 1]; e += 64) col_term<MODE>(a, j, a.csc_val[e], c);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
-        const double t0 = __shfl_xor(s0, o, 64), t1 = __shfl_xor(s1, o, 64);
-        if constexpr (MODE == 0) { s0 = fmin(s0, t0); s1 = fmax(s1, t1); }
-        else { s0 += t0; s1 += t1; }
+        ColAcc<MODE> t;
+#pragma unroll
+        for (int p = 0; p < col_nslots<MODE>(); ++p) t.s[p] = __shfl_xor(c.s[p], o, 64);
+        col_merge<MODE>(c, t);
     }
-    if (lane == 0) {
-        out[j] = s0;
-        out[a.n + j] = s1;
-    }
+    if (lane == 0)
+#pragma unroll
+        for (int p = 0; p < col_nslots<MODE>(); ++p) out[(int64_t)p * a.n + j] = c.s[p];
 }
 
 template <int MODE>
@@ -528,7 +621,7 @@ static hipError_t col_pass(const ColArgs &a, bool coo, double *part, double *out
     if (coo) {
         hipLaunchKernelGGL(col_pass_coo_kernel<MODE>, dim3(nblk(a.n, 4)), dim3(256), 0, st, a, out);
     } else {
-        const int R = col_pass_chunks(a.m);
+        const int R = col_pass_chunks(a.m, a.n);
         const int64_t per = (a.m + R - 1) / R;
         hipLaunchKernelGGL(col_pass_dense_kernel<MODE>, dim3(nblk(a.n), R), dim3(256), 0, st, a, per, part);
         hipLaunchKernelGGL(col_reduce_kernel<MODE>, dim3(nblk(a.n)), dim3(256), 0, st, part, R, a.n, out);
@@ -545,6 +638,11 @@ hipError_t launch_col_pass(const ColArgs &a, int mode, bool coo, double *part, d
     }
 }
 
+// init: lo = min - 1, hi = max + 1 (out: mode 0).  Step (out: mode 1): the
+// bracket becomes the sub-interval ending at the first of its points where
+// the derivative sum is not negative (the rule of a bisection step, at
+// COL_PTS points at once): the minimum lies at or below that point and above
+// the one before it.
 __global__ void bracket_kernel(double *lo, double *hi, double *mid, const double *out, const int32_t *count, int64_t n,
                                bool init)
 {
@@ -558,9 +656,16 @@ __global__ void bracket_kernel(double *lo, double *hi, double *mid, const double
             lo[j] = hi[j] = 0.0;
         }
     } else {
-        // a negative derivative at mid: the minimum lies above it
-        if (out[j] < 0.0) lo[j] = mid[j];
-        else hi[j] = mid[j];
+        const double l = lo[j], h = hi[j];
+        double nl = col_point(l, h, COL_PTS - 1), nh = h;
+        for (int p = COL_PTS - 1; p >= 0; --p) {
+            if (!(out[(int64_t)p * n + j] < 0.0)) {
+                nh = col_point(l, h, p);
+                nl = p > 0 ? col_point(l, h, p - 1) : l;
+            }
+        }
+        lo[j] = nl;
+        hi[j] = nh;
     }
     mid[j] = 0.5 * (lo[j] + hi[j]);
 }
