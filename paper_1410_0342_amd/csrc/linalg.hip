@@ -159,10 +159,34 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(const float *V, int64_
     }
 }
 
+// One vector (b = 1): out_i = alpha sum_j V_ij x_j, one wavefront per row
+// (lane l takes the columns l, l + 64, ..., coalesced), the lanes' sums
+// combined by a butterfly.
+__global__ __launch_bounds__(256) void dense_gemv_kernel(const float *V, int64_t m, int64_t n, int64_t ldp,
+                                                         const double *x, double alpha, double *out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < m; i += nw) {
+        const float *row = V + i * ldp;
+        double acc = 0.0;
+        for (int64_t j = lane; j < n; j += 64) acc += (double)row[j] * x[j];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) out[i] = alpha * acc;
+    }
+}
+
 hipError_t launch_dense_apply(const float *V, int64_t m, int64_t n, int64_t ldp, const double *B, int32_t b,
                               double alpha, double *out, hipStream_t st)
 {
     if (b < 1 || b > LA_MAXB) return hipErrorInvalidValue;
+    if (b == 1) {
+        const int64_t blocks = std::min<int64_t>((m + 3) / 4, 8192);
+        hipLaunchKernelGGL(dense_gemv_kernel, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, st, V, m, n,
+                           ldp, B, alpha, out);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(dense_apply_kernel, dim3(nblk(m, 16)), dim3(256), 0, st, V, m, n, ldp, B, b, alpha, out);
     return hipGetLastError();
 }
@@ -230,10 +254,39 @@ int dense_apply_t_chunks(int64_t m, int64_t n)
     return (int)std::min<int64_t>({want, (int64_t)LA_TCHUNKS, std::max<int64_t>(1, (m + 63) / 64)});
 }
 
+// One vector (b = 1): partials of V^T q per row chunk.  A workgroup takes 64
+// columns (lane -> column, coalesced) and a chunk of rows, its four
+// wavefronts every fourth row; the four sums are combined in order.
+__global__ __launch_bounds__(256) void dense_gemv_t_kernel(const float *V, int64_t m, int64_t n, int64_t ldp,
+                                                           const double *q, int64_t per, double *part)
+{
+    __shared__ double sAcc[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min<int64_t>(m, r0 + per);
+    double acc = 0.0;
+    if (j < n)
+        for (int64_t i = r0 + w; i < r1; i += 4) acc += (double)V[i * ldp + j] * q[i];
+    sAcc[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && j < n) part[(int64_t)blockIdx.y * n + j] = ((sAcc[0][lane] + sAcc[1][lane]) + sAcc[2][lane]) + sAcc[3][lane];
+}
+
 hipError_t launch_dense_apply_t(const float *V, int64_t m, int64_t n, int64_t ldp, const double *Q, int32_t b,
                                 double alpha, double *part, double *out, hipStream_t st)
 {
     if (b < 1 || b > LA_MAXB) return hipErrorInvalidValue;
+    if (b == 1) {
+        // row chunks: enough workgroups to fill the device, partials within LA_TCHUNKS n
+        const int64_t cblocks = (n + 63) / 64;
+        const int ch = (int)std::min<int64_t>({(int64_t)LA_TCHUNKS, std::max<int64_t>(1, 4096 / cblocks),
+                                               std::max<int64_t>(1, (m + 255) / 256)});
+        const int64_t per = (m + ch - 1) / ch;
+        hipLaunchKernelGGL(dense_gemv_t_kernel, dim3((unsigned)cblocks, ch), dim3(256), 0, st, V, m, n, ldp, Q, per,
+                           part);
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(n)), dim3(256), 0, st, part, ch, n, alpha, out);
+        return hipGetLastError();
+    }
     const int ch = dense_apply_t_chunks(m, n);
     const int64_t per = (m + ch - 1) / ch;
     hipLaunchKernelGGL(dense_apply_t_kernel, dim3(nblk(n, 16), ch), dim3(256), 0, st, V, m, n, ldp, Q, b, per,
