@@ -112,139 +112,249 @@ hipError_t launch_permute(const int32_t *perm, const float *in, int64_t nnz, flo
 
 // ---- the table's matrix times a block of vectors -----------------------------------
 
-constexpr int LA_Q = LA_MAXB / 16;   // outputs per thread along the block
+// Blocks of vectors go through the matrix cores in double: v_mfma_f64_16x16x4f64
+// adds A (16 x 4) B (4 x 16) to a 16 x 16 accumulator.  Lane l supplies
+// A[l & 15][l >> 4] and B[l >> 4][l & 15] and holds D[(l >> 4) + 4 v][l & 15]
+// in element v of the accumulator (rows interleaved by four, unlike the fp32
+// 16 x 16 x 4 product's consecutive rows).  The table's floats convert to double
+// exactly, so a product differs from the plain double sum in its order only.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// out (m x b) = alpha V B.  A workgroup owns 16 rows; 64-column slices of V and
-// of B go through LDS; thread (r, cl) accumulates row r's outputs cl + 16 q.
+__device__ __forceinline__ dbl4 mfma64(double a, double b, dbl4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int LA_NT = (LA_MAXB + 15) / 16;   // 16-wide tiles of the widest block
+
+// out (m x b) = alpha V B.  A wavefront owns R tiles of 16 rows and every
+// 16-wide tile of the block (NT of them).  The table's columns are the
+// contraction, 16 per step: lane (i, q) loads four consecutive floats of row
+// i, and the step's product s contracts column 4 q + s, with the rows of B
+// loaded to match.  The accumulators pass through LDS on their way out, so no
+// branch separates the last product from the first read of its result.
+template <int NT, int R>
 __global__ __launch_bounds__(256) void dense_apply_kernel(const float *V, int64_t m, int64_t n, int64_t ldp,
                                                           const double *B, int32_t b, double alpha, double *out)
 {
-    __shared__ float sV[16][65];
-    __shared__ double sB[64][LA_MAXB + 1];
-    const int t = threadIdx.x, r = t >> 4, cl = t & 15;
-    const int64_t i0 = (int64_t)blockIdx.x * 16;
-    double acc[LA_Q];
+    __shared__ double sOut[4][R * NT][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lq = lane >> 4;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * (16 * R);
+    dbl4 acc[R][NT];
 #pragma unroll
-    for (int q = 0; q < LA_Q; ++q) acc[q] = 0.0;
-    for (int64_t j0 = 0; j0 < n; j0 += 64) {
-        for (int e = t; e < 16 * 64; e += 256) {
-            const int rr = e >> 6, jj = e & 63;
-            const int64_t i = i0 + rr, j = j0 + jj;
-            sV[rr][jj] = (i < m && j < n) ? V[i * ldp + j] : 0.0f;
-        }
-        for (int e = t; e < 64 * b; e += 256) {
-            const int jj = e / b, c = e % b;
-            const int64_t j = j0 + jj;
-            sB[jj][c] = j < n ? B[j * b + c] : 0.0;
-        }
-        __syncthreads();
-        const int jn = (int)min<int64_t>(64, n - j0);
-        for (int jj = 0; jj < jn; ++jj) {
-            const double v = (double)sV[r][jj];
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int q = 0; q < LA_Q; ++q) {
-                const int c = cl + 16 * q;
-                if (c < b) acc[q] += v * sB[jj][c];
+        for (int t = 0; t < NT; ++t) acc[r][t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    if (row0 < m) {
+#pragma unroll 2
+        for (int64_t j0 = 0; j0 < n; j0 += 16) {
+            const int64_t j = j0 + 4 * lq;
+            double bf[NT][4];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int c = 16 * t + li;
+                    bf[t][s] = (j + s < n && c < b) ? B[(j + s) * b + c] : 0.0;
+                }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t i = row0 + 16 * r + li;
+                float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                // j0 + 16 <= ldp (a multiple of 16), so the four floats lie in the row
+                if (i < m) v = *reinterpret_cast<const float4 *>(V + i * ldp + j);
+                const double vs[4] = {j < n ? (double)v.x : 0.0, j + 1 < n ? (double)v.y : 0.0,
+                                      j + 2 < n ? (double)v.z : 0.0, j + 3 < n ? (double)v.w : 0.0};
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) acc[r][t] = mfma64(vs[s], bf[t][s], acc[r][t]);
             }
         }
-        __syncthreads();
     }
-    const int64_t i = i0 + r;
-    if (i < m) {
 #pragma unroll
-        for (int q = 0; q < LA_Q; ++q) {
-            const int c = cl + 16 * q;
-            if (c < b) out[i * b + c] = alpha * acc[q];
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            acc[r][t] = mfma64(0.0, 0.0, acc[r][t]);   // in order behind the last product
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sOut[w][r * NT + t][64 * v + lane] = acc[r][t][v];
         }
-    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t i = row0 + 16 * r + lq + 4 * v;
+                const int c = 16 * t + li;
+                if (i < m && c < b) out[i * b + c] = alpha * sOut[w][r * NT + t][64 * v + lane];
+            }
 }
 
-// One vector (b = 1): out_i = alpha sum_j V_ij x_j, one wavefront per row
-// (lane l takes the columns l, l + 64, ..., coalesced), the lanes' sums
+template <int NT>
+static void apply_launch(const float *V, int64_t m, int64_t n, int64_t ldp, const double *B, int32_t b, double alpha,
+                         double *out, hipStream_t st)
+{
+    constexpr int R = NT <= 2 ? 2 : 1;
+    hipLaunchKernelGGL((dense_apply_kernel<NT, R>), dim3(nblk(m, 64 * R)), dim3(256), 0, st, V, m, n, ldp, B, b,
+                       alpha, out);
+}
+
+// One vector (b = 1): out_i = alpha sum_j V_ij x_j.  A wavefront takes
+// GEMV_R rows at once and lane l four consecutive columns of every 256
+// (16-byte loads), so each load of x serves GEMV_R rows; the lanes' sums are
 // combined by a butterfly.
+constexpr int GEMV_R = 4;
+
 __global__ __launch_bounds__(256) void dense_gemv_kernel(const float *V, int64_t m, int64_t n, int64_t ldp,
                                                          const double *x, double alpha, double *out)
 {
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * 4;
-    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < m; i += nw) {
-        const float *row = V + i * ldp;
-        double acc = 0.0;
-        for (int64_t j = lane; j < n; j += 64) acc += (double)row[j] * x[j];
+    for (int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * GEMV_R; i0 < m; i0 += nw * GEMV_R) {
+        double acc[GEMV_R];
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (lane == 0) out[i] = alpha * acc;
+        for (int r = 0; r < GEMV_R; ++r) acc[r] = 0.0;
+        // j < n <= ldp, and ldp is a multiple of 16: the four floats lie in the row
+        for (int64_t j = 4 * lane; j < n; j += 256) {
+            const double x0 = x[j], x1 = j + 1 < n ? x[j + 1] : 0.0, x2 = j + 2 < n ? x[j + 2] : 0.0,
+                         x3 = j + 3 < n ? x[j + 3] : 0.0;
+#pragma unroll
+            for (int r = 0; r < GEMV_R; ++r) {
+                // rows past the last re-read it; their sums are not stored
+                const int64_t i = min<int64_t>(i0 + r, m - 1);
+                const float4 v = *reinterpret_cast<const float4 *>(V + i * ldp + j);
+                acc[r] += (double)v.x * x0;
+                acc[r] += j + 1 < n ? (double)v.y * x1 : 0.0;
+                acc[r] += j + 2 < n ? (double)v.z * x2 : 0.0;
+                acc[r] += j + 3 < n ? (double)v.w * x3 : 0.0;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < GEMV_R; ++r) {
+            double t = acc[r];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
+            if (lane == 0 && i0 + r < m) out[i0 + r] = alpha * t;
+        }
     }
 }
 
 hipError_t launch_dense_apply(const float *V, int64_t m, int64_t n, int64_t ldp, const double *B, int32_t b,
                               double alpha, double *out, hipStream_t st)
 {
-    if (b < 1 || b > LA_MAXB) return hipErrorInvalidValue;
+    if (b < 1 || b > LA_MAXB || ldp % 16 != 0 || ldp < n) return hipErrorInvalidValue;
+    if (m <= 0) return hipSuccess;
     if (b == 1) {
-        const int64_t blocks = std::min<int64_t>((m + 3) / 4, 8192);
+        const int64_t blocks = std::min<int64_t>((m + 4 * GEMV_R - 1) / (4 * GEMV_R), 8192);
         hipLaunchKernelGGL(dense_gemv_kernel, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(256), 0, st, V, m, n,
                            ldp, B, alpha, out);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(dense_apply_kernel, dim3(nblk(m, 16)), dim3(256), 0, st, V, m, n, ldp, B, b, alpha, out);
+    switch ((b + 15) / 16) {
+    case 1: apply_launch<1>(V, m, n, ldp, B, b, alpha, out, st); break;
+    case 2: apply_launch<2>(V, m, n, ldp, B, b, alpha, out, st); break;
+    case 3: apply_launch<3>(V, m, n, ldp, B, b, alpha, out, st); break;
+    case 4: apply_launch<4>(V, m, n, ldp, B, b, alpha, out, st); break;
+    case 5: apply_launch<5>(V, m, n, ldp, B, b, alpha, out, st); break;
+    default: apply_launch<LA_NT>(V, m, n, ldp, B, b, alpha, out, st); break;
+    }
     return hipGetLastError();
 }
 
-// Partials of V^T Q: workgroup (column block of 16, row chunk); rows go through
-// LDS in slices of 64.
-__global__ __launch_bounds__(256) void dense_apply_t_kernel(const float *V, int64_t m, int64_t n, int64_t ldp,
-                                                            const double *Q, int32_t b, int64_t per, double *part)
+// Partials of U^T B, for U (rows x P, leading dimension ldu) and B (rows x b,
+// leading dimension ldb): workgroup (x, y) takes the 16 columns 16 x of U and
+// row chunk y, and writes part[y][p][c] for its p and every c < b.  The
+// chunk's rows are the contraction: its four wavefronts take four consecutive
+// runs of them, four rows per product, and their sums are added in wavefront
+// order through LDS.
+template <typename TU, typename TB, int NT>
+__global__ __launch_bounds__(256) void tmul_kernel(const TU *U, int64_t rows, int64_t P, int64_t ldu, const TB *B,
+                                                   int64_t ldb, int32_t b, int64_t per, double *part)
 {
-    __shared__ float sV[64][17];
-    __shared__ double sQ[64][LA_MAXB + 1];
-    const int t = threadIdx.x, jj = t >> 4, cl = t & 15;
-    const int64_t j0 = (int64_t)blockIdx.x * 16;
-    const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min<int64_t>(m, r0 + per);
-    double acc[LA_Q];
+    __shared__ double sAcc[4][NT][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int64_t p0 = (int64_t)blockIdx.x * 16;
+    const int64_t c0 = (int64_t)blockIdx.y * per, c1 = min<int64_t>(rows, c0 + per);
+    const int64_t run = (max<int64_t>(c1 - c0, 0) + 3) / 4;
+    const int64_t r0 = min<int64_t>(c1, c0 + w * run), r1 = min<int64_t>(c1, r0 + run);
+    const bool pin = p0 + li < P;
+    dbl4 acc[NT];
 #pragma unroll
-    for (int q = 0; q < LA_Q; ++q) acc[q] = 0.0;
-    for (int64_t i0 = r0; i0 < r1; i0 += 64) {
-        for (int e = t; e < 64 * 16; e += 256) {
-            const int ii = e >> 4, c = e & 15;
-            const int64_t i = i0 + ii, j = j0 + c;
-            sV[ii][c] = (i < r1 && j < n) ? V[i * ldp + j] : 0.0f;
-        }
-        for (int e = t; e < 64 * b; e += 256) {
-            const int ii = e / b, c = e % b;
-            const int64_t i = i0 + ii;
-            sQ[ii][c] = i < r1 ? Q[i * b + c] : 0.0;
-        }
-        __syncthreads();
-        const int in_ = (int)min<int64_t>(64, r1 - i0);
-        for (int ii = 0; ii < in_; ++ii) {
-            const double v = (double)sV[ii][jj];
+    for (int t = 0; t < NT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int64_t i0 = r0; i0 < r1; i0 += 4) {
+        const int64_t i = i0 + lk;
+        const bool in = i < r1;
+        const double a = (in && pin) ? (double)U[i * ldu + p0 + li] : 0.0;
 #pragma unroll
-            for (int q = 0; q < LA_Q; ++q) {
-                const int c = cl + 16 * q;
-                if (c < b) acc[q] += v * sQ[ii][c];
-            }
+        for (int t = 0; t < NT; ++t) {
+            const int c = 16 * t + li;
+            const double bv = (in && c < b) ? (double)B[i * ldb + c] : 0.0;
+            acc[t] = mfma64(a, bv, acc[t]);
         }
-        __syncthreads();
     }
-    const int64_t j = j0 + jj;
-    if (j < n) {
 #pragma unroll
-        for (int q = 0; q < LA_Q; ++q) {
-            const int c = cl + 16 * q;
-            if (c < b) part[((int64_t)blockIdx.y * n + j) * b + c] = acc[q];
-        }
+    for (int t = 0; t < NT; ++t) {
+        acc[t] = mfma64(0.0, 0.0, acc[t]);   // in order behind the last product
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sAcc[w][t][64 * v + lane] = acc[t][v];
+    }
+    __syncthreads();
+    const int e = threadIdx.x, v = e >> 6, l2 = e & 63;
+    const int64_t p = p0 + (l2 >> 4) + 4 * v;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = 16 * t + (l2 & 15);
+        if (p < P && c < b)
+            part[((int64_t)blockIdx.y * P + p) * b + c] =
+                ((sAcc[0][t][e] + sAcc[1][t][e]) + sAcc[2][t][e]) + sAcc[3][t][e];
     }
 }
 
-// out[e] = alpha * sum_p part[p][e] over p = 0..np-1, in that order.
-__global__ void reduce_parts_kernel(const double *part, int32_t np, int64_t len, double alpha, double *out)
+template <typename TU, typename TB>
+static hipError_t tmul_launch(const TU *U, int64_t rows, int64_t P, int64_t ldu, const TB *B, int64_t ldb, int32_t b,
+                              int chunks, double *part, hipStream_t st)
 {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= len) return;
-    double s = 0.0;
-    for (int p = 0; p < np; ++p) s += part[(int64_t)p * len + e];
-    out[e] = alpha * s;
+    if (b < 1 || b > LA_MAXB) return hipErrorInvalidValue;
+    const int64_t per = (rows + chunks - 1) / chunks;
+    const dim3 grid((unsigned)((P + 15) / 16), (unsigned)chunks);
+    switch ((b + 15) / 16) {
+    case 1: hipLaunchKernelGGL((tmul_kernel<TU, TB, 1>), grid, dim3(256), 0, st, U, rows, P, ldu, B, ldb, b, per, part); break;
+    case 2: hipLaunchKernelGGL((tmul_kernel<TU, TB, 2>), grid, dim3(256), 0, st, U, rows, P, ldu, B, ldb, b, per, part); break;
+    case 3: hipLaunchKernelGGL((tmul_kernel<TU, TB, 3>), grid, dim3(256), 0, st, U, rows, P, ldu, B, ldb, b, per, part); break;
+    case 4: hipLaunchKernelGGL((tmul_kernel<TU, TB, 4>), grid, dim3(256), 0, st, U, rows, P, ldu, B, ldb, b, per, part); break;
+    case 5: hipLaunchKernelGGL((tmul_kernel<TU, TB, 5>), grid, dim3(256), 0, st, U, rows, P, ldu, B, ldb, b, per, part); break;
+    default: hipLaunchKernelGGL((tmul_kernel<TU, TB, LA_NT>), grid, dim3(256), 0, st, U, rows, P, ldu, B, ldb, b, per, part); break;
+    }
+    return hipGetLastError();
+}
+
+// out[e] = alpha * sum over p of part[p][e].  A workgroup takes 64 consecutive
+// e; wavefront w sums the partials p = w, w + 4, ... in order, and the four
+// sums are added in wavefront order.
+__global__ __launch_bounds__(256) void reduce_parts_kernel(const double *part, int32_t np, int64_t len, double alpha,
+                                                           double *out)
+{
+    __shared__ double s[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+    double acc = 0.0;
+    if (e < len) {
+        // loads run ahead; the sum keeps the order of p
+#pragma unroll 8
+        for (int p = w; p < np; p += 4) acc += part[(int64_t)p * len + e];
+    }
+    s[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && e < len) out[e] = alpha * (((s[0][lane] + s[1][lane]) + s[2][lane]) + s[3][lane]);
+}
+
+static void reduce_parts(const double *part, int32_t np, int64_t len, double alpha, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(len, 64)), dim3(256), 0, st, part, np, len, alpha, out);
 }
 
 int dense_apply_t_chunks(int64_t m, int64_t n)
@@ -254,44 +364,60 @@ int dense_apply_t_chunks(int64_t m, int64_t n)
     return (int)std::min<int64_t>({want, (int64_t)LA_TCHUNKS, std::max<int64_t>(1, (m + 63) / 64)});
 }
 
-// One vector (b = 1): partials of V^T q per row chunk.  A workgroup takes 64
-// columns (lane -> column, coalesced) and a chunk of rows, its four
-// wavefronts every fourth row; the four sums are combined in order.
+// One vector (b = 1): partials of V^T q per row chunk.  A workgroup takes 256
+// columns (lane -> four consecutive columns, 16-byte loads) and a chunk of
+// rows, its four wavefronts every fourth row; the four sums are combined in
+// order.
 __global__ __launch_bounds__(256) void dense_gemv_t_kernel(const float *V, int64_t m, int64_t n, int64_t ldp,
                                                            const double *q, int64_t per, double *part)
 {
-    __shared__ double sAcc[4][64];
+    __shared__ double sAcc[4][256];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t j = ((int64_t)blockIdx.x * 64 + lane) * 4;
     const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min<int64_t>(m, r0 + per);
-    double acc = 0.0;
-    if (j < n)
-        for (int64_t i = r0 + w; i < r1; i += 4) acc += (double)V[i * ldp + j] * q[i];
-    sAcc[w][lane] = acc;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    // j < n <= ldp, and ldp is a multiple of 16: the four floats lie in the row
+    if (j < n) {
+#pragma unroll 4
+        for (int64_t i = r0 + w; i < r1; i += 4) {
+            const float4 v = *reinterpret_cast<const float4 *>(V + i * ldp + j);
+            const double qi = q[i];
+            a0 += (double)v.x * qi;
+            a1 += (double)v.y * qi;
+            a2 += (double)v.z * qi;
+            a3 += (double)v.w * qi;
+        }
+    }
+    sAcc[w][4 * lane] = a0;
+    sAcc[w][4 * lane + 1] = a1;
+    sAcc[w][4 * lane + 2] = a2;
+    sAcc[w][4 * lane + 3] = a3;
     __syncthreads();
-    if (w == 0 && j < n) part[(int64_t)blockIdx.y * n + j] = ((sAcc[0][lane] + sAcc[1][lane]) + sAcc[2][lane]) + sAcc[3][lane];
+    const int t = threadIdx.x;
+    const int64_t jj = (int64_t)blockIdx.x * 256 + t;
+    if (jj < n) part[(int64_t)blockIdx.y * n + jj] = ((sAcc[0][t] + sAcc[1][t]) + sAcc[2][t]) + sAcc[3][t];
 }
 
 hipError_t launch_dense_apply_t(const float *V, int64_t m, int64_t n, int64_t ldp, const double *Q, int32_t b,
                                 double alpha, double *part, double *out, hipStream_t st)
 {
-    if (b < 1 || b > LA_MAXB) return hipErrorInvalidValue;
+    if (b < 1 || b > LA_MAXB || ldp % 16 != 0 || ldp < n) return hipErrorInvalidValue;
+    if (n <= 0) return hipSuccess;
     if (b == 1) {
         // row chunks: enough workgroups to fill the device, partials within LA_TCHUNKS n
-        const int64_t cblocks = (n + 63) / 64;
+        const int64_t cblocks = (n + 255) / 256;
         const int ch = (int)std::min<int64_t>({(int64_t)LA_TCHUNKS, std::max<int64_t>(1, 4096 / cblocks),
                                                std::max<int64_t>(1, (m + 255) / 256)});
         const int64_t per = (m + ch - 1) / ch;
         hipLaunchKernelGGL(dense_gemv_t_kernel, dim3((unsigned)cblocks, ch), dim3(256), 0, st, V, m, n, ldp, Q, per,
                            part);
-        hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(n)), dim3(256), 0, st, part, ch, n, alpha, out);
+        reduce_parts(part, ch, n, alpha, out, st);
         return hipGetLastError();
     }
     const int ch = dense_apply_t_chunks(m, n);
-    const int64_t per = (m + ch - 1) / ch;
-    hipLaunchKernelGGL(dense_apply_t_kernel, dim3(nblk(n, 16), ch), dim3(256), 0, st, V, m, n, ldp, Q, b, per,
-                       part);
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk(n * b)), dim3(256), 0, st, part, ch, n * b, alpha, out);
+    hipError_t e = tmul_launch<float, double>(V, m, n, ldp, Q, b, b, ch, part, st);
+    if (e != hipSuccess) return e;
+    reduce_parts(part, ch, n * b, alpha, out, st);
     return hipGetLastError();
 }
 
@@ -345,38 +471,23 @@ hipError_t launch_seg_apply(const int32_t *ptr, const int32_t *idx, const float 
 
 // ---- tall-skinny products ----------------------------------------------------------
 
-constexpr int TALL_ROWS = 1024;     // rows per workgroup of U^T B
+constexpr int TALL_ROWS = 256;       // rows per workgroup of U^T B, at least
+constexpr int TALL_CHUNKS = 1024;    // workgroups along the rows, at most
 
-int tall_tmul_blocks(int64_t rows) { return (int)std::min<int64_t>(4096, std::max<int64_t>(1, (rows + TALL_ROWS - 1) / TALL_ROWS)); }
-
-// part[blk][l b + c] = sum over the workgroup's rows of U[i, l] B[i, c]
-template <typename TU, typename TB>
-__global__ __launch_bounds__(256) void tall_tmul_kernel(const TU *U, int64_t rows, int32_t k, int64_t ldu,
-                                                        const TB *B, int64_t ldb, int32_t b, int64_t per,
-                                                        double *part)
+int tall_tmul_blocks(int64_t rows)
 {
-    const int64_t i0 = (int64_t)blockIdx.x * per, i1 = min<int64_t>(rows, i0 + per);
-    const int np = k * b;
-    for (int p0 = 0; p0 < np; p0 += 256) {
-        const int p = p0 + threadIdx.x;
-        if (p < np) {
-            const int l = p / b, c = p % b;
-            double acc = 0.0;
-            for (int64_t i = i0; i < i1; ++i) acc += (double)U[i * ldu + l] * (double)B[i * ldb + c];
-            part[(int64_t)blockIdx.x * np + p] = acc;
-        }
-    }
+    return (int)std::min<int64_t>(TALL_CHUNKS, std::max<int64_t>(1, (rows + TALL_ROWS - 1) / TALL_ROWS));
 }
 
 template <typename TU, typename TB>
 static hipError_t tall_tmul(const TU *U, int64_t rows, int32_t k, int64_t ldu, const TB *B, int64_t ldb, int32_t b,
                             double *part, double *out, hipStream_t st)
 {
+    if (k < 1 || b < 1 || b > LA_MAXB) return hipErrorInvalidValue;
     const int nb = tall_tmul_blocks(rows);
-    const int64_t per = (rows + nb - 1) / nb;
-    hipLaunchKernelGGL((tall_tmul_kernel<TU, TB>), dim3(nb), dim3(256), 0, st, U, rows, k, ldu, B, ldb, b, per, part);
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(nblk((int64_t)k * b)), dim3(256), 0, st, part, nb, (int64_t)k * b,
-                       1.0, out);
+    hipError_t e = tmul_launch<TU, TB>(U, rows, k, ldu, B, ldb, b, nb, part, st);
+    if (e != hipSuccess) return e;
+    reduce_parts(part, nb, (int64_t)k * b, 1.0, out, st);
     return hipGetLastError();
 }
 
@@ -447,7 +558,7 @@ __global__ __launch_bounds__(256) void sumsq_kernel(const double *v, int64_t len
 hipError_t launch_sumsq(const double *v, int64_t len, double *part, double *nrm2, hipStream_t st)
 {
     hipLaunchKernelGGL(sumsq_kernel, dim3(SUMSQ_BLOCKS), dim3(256), 0, st, v, len, part);
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, st, part, SUMSQ_BLOCKS, (int64_t)1, 1.0, nrm2);
+    reduce_parts(part, SUMSQ_BLOCKS, 1, 1.0, nrm2, st);
     return hipGetLastError();
 }
 
@@ -629,17 +740,33 @@ __global__ __launch_bounds__(256) void col_pass_dense_kernel(ColArgs a, int64_t 
     for (int p = 0; p < col_nslots<MODE>(); ++p) part[((int64_t)blockIdx.y * COL_SLOTS + p) * a.n + j] = c.s[p];
 }
 
+// A workgroup takes 64 columns; wavefront w merges the chunks r = w, w + 4,
+// ... in order, and the four results are merged in wavefront order.
 template <int MODE>
-__global__ void col_reduce_kernel(const double *part, int32_t R, int64_t n, double *out)
+__global__ __launch_bounds__(256) void col_reduce_kernel(const double *part, int32_t R, int64_t n, double *out)
 {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
+    __shared__ double sAcc[4][COL_SLOTS][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + lane;
     ColAcc<MODE> c;
     col_init<MODE>(c);
-    for (int r = 0; r < R; ++r) {
+    if (j < n) {
+#pragma unroll 2
+        for (int r = w; r < R; r += 4) {
+            ColAcc<MODE> o;
+#pragma unroll
+            for (int p = 0; p < col_nslots<MODE>(); ++p) o.s[p] = part[((int64_t)r * COL_SLOTS + p) * n + j];
+            col_merge<MODE>(c, o);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < col_nslots<MODE>(); ++p) sAcc[w][p][lane] = c.s[p];
+    __syncthreads();
+    if (w != 0 || j >= n) return;
+    for (int q = 1; q < 4; ++q) {
         ColAcc<MODE> o;
 #pragma unroll
-        for (int p = 0; p < col_nslots<MODE>(); ++p) o.s[p] = part[((int64_t)r * COL_SLOTS + p) * n + j];
+        for (int p = 0; p < col_nslots<MODE>(); ++p) o.s[p] = sAcc[q][p][lane];
         col_merge<MODE>(c, o);
     }
 #pragma unroll
@@ -677,7 +804,7 @@ static hipError_t col_pass(const ColArgs &a, bool coo, double *part, double *out
         const int R = col_pass_chunks(a.m, a.n);
         const int64_t per = (a.m + R - 1) / R;
         hipLaunchKernelGGL(col_pass_dense_kernel<MODE>, dim3(nblk(a.n), R), dim3(256), 0, st, a, per, part);
-        hipLaunchKernelGGL(col_reduce_kernel<MODE>, dim3(nblk(a.n)), dim3(256), 0, st, part, R, a.n, out);
+        hipLaunchKernelGGL(col_reduce_kernel<MODE>, dim3(nblk(a.n, 64)), dim3(256), 0, st, part, R, a.n, out);
     }
     return hipGetLastError();
 }

@@ -48,12 +48,23 @@ def straight_line_needs(ins):
     """Wait states the compiler puts between a product and an immediate read of
     its result (s_nop N then the read), per product opcode: the largest seen."""
     need = {}
-    for a, b, c in zip(ins, ins[1:], ins[2:]):
-        if a.startswith('v_mfma') and b.startswith('s_nop') and c.startswith('v_') and not c.startswith('v_mfma'):
+    for i, a in enumerate(ins):
+        if not a.startswith('v_mfma'):
+            continue
+        # a run of s_nop (the compiler splits long waits: s_nop 15, s_nop 1)
+        j, w = i + 1, 0
+        while j < len(ins) and ins[j].startswith('s_nop'):
+            w += _waits(ins[j])
+            j += 1
+        if w == 0 or j >= len(ins):
+            continue
+        c = ins[j]
+        stores = c.startswith(('ds_write', 'global_store', 'buffer_store'))
+        if (c.startswith('v_') and not c.startswith('v_mfma')) or stores:
             dst = _regs(a.split()[1])
-            if any(_regs(x) & dst for x in c.split()[2:]):
+            if any(_regs(x) & dst for x in c.split()[1 if stores else 2:]):
                 op = a.split()[0]
-                need[op] = max(need.get(op, 0), _waits(b))
+                need[op] = max(need.get(op, 0), w)
     return need
 
 
