@@ -139,7 +139,8 @@ __global__ __launch_bounds__(256) void pp_gram_kernel(PPArgs a)
     __shared__ float sV[CH][KP + 4];
     __shared__ float sT[16][CH + 4];
     __shared__ float sW[CH];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    // w as a scalar: the tile tests below are then scalar branches, not exec-mask ones
+    const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int li = lane & 15, g = lane >> 4;
     const int64_t i0 = (int64_t)blockIdx.x * 16;
     const int64_t per = (a.cols + a.splits - 1) / a.splits;
@@ -162,6 +163,7 @@ __global__ __launch_bounds__(256) void pp_gram_kernel(PPArgs a)
 #pragma unroll
     for (int q = 0; q < TW; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bool bact = w < KP / 16 && 16 * w < k;   // this wavefront's b tile: coordinates 16 w ..
+    const int bcol = bact ? 16 * w + li : li;        // (an inactive tile reads column li, never stored)
     const float wr = (a.wrow && i0 + li < a.rows) ? a.wrow[i0 + li] : 1.0f;
     // where the panel's rows go (chosen here, away from the products' results)
     const int64_t rowsp = (a.rows + 15) / 16 * 16;
@@ -174,19 +176,23 @@ __global__ __launch_bounds__(256) void pp_gram_kernel(PPArgs a)
         __syncthreads();
         if (j0 + CH < c1) chunk.load(a, i0, j0 + CH, c1);   // in flight while this chunk computes
         const int nks = (int)((min<int64_t>(CH, c1 - j0) + 3) / 4);
+#pragma unroll 4
         for (int ks = 0; ks < nks; ++ks) {
             const int jj = 4 * ks + g;              // this lane's column of the step (k index g)
             const float av = sT[li][jj];            // row li (A operand: row li, k g)
+            const float sw = sW[jj];
             const bool obs = av == av;
-            const float m = obs ? wr * sW[jj] : 0.0f;
+            const float m = obs ? wr * sw : 0.0f;
             const float mb = obs ? m * av : 0.0f;
+            // Every slot's product runs, inactive ones on coordinates 0 (never
+            // stored): a branch per slot made the compiler move the
+            // accumulators between register files around each product.
 #pragma unroll
             for (int q = 0; q < TW; ++q) {
-                if (!act[q]) continue;
                 const float bv = sV[jj][ca[q]] * sV[jj][cb[q]];     // B operand: k g, column li
                 acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(m, bv, acc[q], 0, 0, 0);
             }
-            if (bact) bacc = __builtin_amdgcn_mfma_f32_16x16x4f32(mb, sV[jj][16 * w + li], bacc, 0, 0, 0);
+            bacc = __builtin_amdgcn_mfma_f32_16x16x4f32(mb, sV[jj][bcol], bacc, 0, 0, 0);
         }
     }
     // One more product into every accumulator, so that the reads below follow
@@ -376,7 +382,8 @@ __global__ __launch_bounds__(256) void pp_check_kernel(PPArgs a)
     __shared__ float sT[16][CH + 4];
     __shared__ float sW[CH];
     __shared__ float sSum[4][16][2];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    // w as a scalar: the tile tests below are then scalar branches, not exec-mask ones
+    const int t = threadIdx.x, lane = t & 63, w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int li = lane & 15, g = lane >> 4;
     const int64_t i0 = (int64_t)blockIdx.x * 16;
     const int64_t per = (a.cols + a.splits - 1) / a.splits;
