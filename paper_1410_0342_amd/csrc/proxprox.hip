@@ -288,10 +288,16 @@ template <int KP>
 __global__ __launch_bounds__(64) void pp_solve_kernel(PPArgs a)
 {
     constexpr int NT = PP_NT<KP>, UT = PP_UT<KP>, GSZ = PP_GSZ<KP>;
-    __shared__ double sM[KP][KP + 1];
-    __shared__ double sR[KP];
-    const int lane = threadIdx.x;
-    const int64_t i = blockIdx.x;
+    // 64 / KP rows per wavefront, KP lanes each: the rows share every barrier
+    // of the factorization and the solves
+    constexpr int NR = 64 / KP;
+    __shared__ double sMall[NR][KP][KP + 1];
+    __shared__ double sRall[NR][KP];
+    const int sub = threadIdx.x / KP, lane = threadIdx.x % KP;
+    double (&sM)[KP][KP + 1] = sMall[sub];
+    double *sR = sRall[sub];
+    const int64_t irow = (int64_t)blockIdx.x * NR + sub;
+    const int64_t i = min<int64_t>(irow, a.rows - 1);   // a row past the end repeats the last, not stored
     const float *g = a.gram + i * GSZ;
     const int k = a.k;
     const double al = (double)a.alpha[i];
@@ -299,7 +305,7 @@ __global__ __launch_bounds__(64) void pp_solve_kernel(PPArgs a)
     // the symmetric matrix from the upper tiles that meet the rank (the rest
     // of its lower triangle is set below)
     const int nt = pp_nt(k), ut = nt * (nt + 1) / 2;
-    for (int e = lane; e < ut * 16; e += 64) {
+    for (int e = lane; e < ut * 16; e += KP) {
         int ta, tb;
         tile_of_rt(e >> 4, nt, ta, tb);
         const int rr = 4 * ta + ((e >> 2) & 3), cc = 4 * tb + (e & 3);
@@ -309,11 +315,9 @@ __global__ __launch_bounds__(64) void pp_solve_kernel(PPArgs a)
     }
     __syncthreads();
     // coordinates past k: identity rows (the lower part is all the factorization reads)
-    if (lane < KP) {
-        for (int c = 0; c <= lane; ++c)
-            if (lane >= k || c >= k) sM[lane][c] = lane == c ? 1.0 : 0.0;
-        if (lane < k) sM[lane][lane] += h;
-    }
+    for (int c = 0; c <= lane; ++c)
+        if (lane >= k || c >= k) sM[lane][c] = lane == c ? 1.0 : 0.0;
+    if (lane < k) sM[lane][lane] += h;
     __syncthreads();
     // Cholesky, lower triangle in place.  Coordinates past k are identity
     // rows with a zero right-hand side: their factor and solution are exact
@@ -335,7 +339,7 @@ __global__ __launch_bounds__(64) void pp_solve_kernel(PPArgs a)
     const double bc = lane < k ? (double)g[PP_BOFF<KP> + lane] : 0.0;
     double x = lane < k ? (double)a.U[i * k + lane] : 0.0;
     for (int it = 0; it < a.inner; ++it) {
-        if (lane < KP) sR[lane] = bc + h * x;
+        sR[lane] = bc + h * x;
         __syncthreads();
         for (int j = 0; j < k; ++j) {         // L y = rhs
             if (lane == j) sR[j] = sR[j] / sM[j][j];
@@ -352,15 +356,15 @@ __global__ __launch_bounds__(64) void pp_solve_kernel(PPArgs a)
         x = lane < k ? prox_elem64(a.reg, al, sR[lane], lane) : 0.0;
         __syncthreads();
     }
-    if (lane < k) a.trial[i * k + lane] = (float)x;
+    if (lane < k && irow < a.rows) a.trial[i * k + lane] = (float)x;
 }
 
 hipError_t launch_pp_solve(const PPArgs &a, hipStream_t st)
 {
     if (a.rows <= 0) return hipSuccess;
     switch (a.kp) {
-    case 16: hipLaunchKernelGGL(pp_solve_kernel<16>, dim3((unsigned)a.rows), dim3(64), 0, st, a); break;
-    case 32: hipLaunchKernelGGL(pp_solve_kernel<32>, dim3((unsigned)a.rows), dim3(64), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(pp_solve_kernel<16>, dim3((unsigned)((a.rows + 3) / 4)), dim3(64), 0, st, a); break;
+    case 32: hipLaunchKernelGGL(pp_solve_kernel<32>, dim3((unsigned)((a.rows + 1) / 2)), dim3(64), 0, st, a); break;
     case 64: hipLaunchKernelGGL(pp_solve_kernel<64>, dim3((unsigned)a.rows), dim3(64), 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
