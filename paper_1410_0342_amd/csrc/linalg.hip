@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void dense_apply_kernel(const float *V, int64_
                                                           const double *B, int32_t b, double alpha, double *out)
 {
     __shared__ double sOut[4][R * NT][256];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lq = lane >> 4;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), li = lane & 15, lq = lane >> 4;
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * (16 * R);
     dbl4 acc[R][NT];
 #pragma unroll
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(const float *V, int64_t
 {
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * 4;
-    for (int64_t i0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * GEMV_R; i0 < m; i0 += nw * GEMV_R) {
+    for (int64_t i0 = ((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * GEMV_R; i0 < m; i0 += nw * GEMV_R) {
         double acc[GEMV_R];
 #pragma unroll
         for (int r = 0; r < GEMV_R; ++r) acc[r] = 0.0;
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256) void tmul_kernel(const TU *U, int64_t rows, in
                                                    int64_t ldb, int32_t b, int64_t per, double *part)
 {
     __shared__ double sAcc[4][NT][256];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), li = lane & 15, lk = lane >> 4;
     const int64_t p0 = (int64_t)blockIdx.x * 16;
     const int64_t c0 = (int64_t)blockIdx.y * per, c1 = min<int64_t>(rows, c0 + per);
     const int64_t run = (max<int64_t>(c1 - c0, 0) + 3) / 4;
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void reduce_parts_kernel(const double *part, i
                                                            double *out)
 {
     __shared__ double s[4][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // scalar: loops over w stay uniform
     const int64_t e = (int64_t)blockIdx.x * 64 + lane;
     double acc = 0.0;
     if (e < len) {
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(256) void dense_gemv_t_kernel(const float *V, int64
                                                            const double *q, int64_t per, double *part)
 {
     __shared__ double sAcc[4][256];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // scalar: loops over w stay uniform
     const int64_t j = ((int64_t)blockIdx.x * 64 + lane) * 4;
     const int64_t r0 = (int64_t)blockIdx.y * per, r1 = min<int64_t>(m, r0 + per);
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(256) void seg_apply_kernel(const int32_t *ptr, cons
                                                         double *out)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t r = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (r >= rows) return;
     const int32_t beg = ptr[r], end = ptr[r + 1];
     if (b <= 4) {
@@ -746,7 +746,7 @@ template <int MODE>
 __global__ __launch_bounds__(256) void col_reduce_kernel(const double *part, int32_t R, int64_t n, double *out)
 {
     __shared__ double sAcc[4][COL_SLOTS][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // scalar: loops over w stay uniform
     const int64_t j = (int64_t)blockIdx.x * 64 + lane;
     ColAcc<MODE> c;
     col_init<MODE>(c);
@@ -778,7 +778,7 @@ template <int MODE>
 __global__ __launch_bounds__(256) void col_pass_coo_kernel(ColArgs a, double *out)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t j = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (j >= a.n) return;
     ColAcc<MODE> c;
     col_init<MODE>(c);
