@@ -348,10 +348,8 @@ struct Part {
     float4 v[C / 4];
 };
 
-// row is an unsigned index: gathering by a 32-bit index zero-extends it, one
-// shift-and-add per address instead of a sign extension and a 64-bit shift.
 template <int KP, int C>
-__device__ __forceinline__ Part<C> load_part(const float4 *__restrict__ F4, uint64_t row, int q)
+__device__ __forceinline__ Part<C> load_part(const float4 *__restrict__ F4, int64_t row, int q)
 {
     Part<C> r;
 #pragma unroll
@@ -388,7 +386,7 @@ struct PartB {
 };
 
 template <int KP, int C>
-__device__ __forceinline__ PartB<C> load_partb(const __bf16 *__restrict__ F, uint64_t row, int q)
+__device__ __forceinline__ PartB<C> load_partb(const __bf16 *__restrict__ F, int64_t row, int q)
 {
     PartB<C> r;
     const uint32_t *p = reinterpret_cast<const uint32_t *>(F + row * KP + (int64_t)q * C);
@@ -467,7 +465,7 @@ __device__ __forceinline__ void chunk_load(const T *__restrict__ idx, const floa
     for (int s = 0; s < NS; ++s) {
         if (b + s * E >= end) break;
         const int32_t e = b + s * E + slot;
-        const uint32_t ee = (uint32_t)(e < end ? e : first);   // entry indices are nonnegative
+        const int32_t ee = e < end ? e : first;
         i[s] = idx[ee];
         v[s] = val[ee];
     }
@@ -549,10 +547,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
     constexpr int C = cb_c<KP>(), L = KP / C, E = 64 / L, NS = CB_NS;
     const int lane = threadIdx.x & 63;
     const int slot = lane / L, q = lane % L;
-    // the wavefront's index as a scalar: the row index, the row's bounds and
-    // every chunk test that follows from them stay scalar (no exec-mask branches)
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t wave = (int64_t)blockIdx.x * CW + wid;
+    const int64_t wave = (int64_t)blockIdx.x * CW + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * CW;
     double wsum = 0.0;
     int wrej = 0;
@@ -561,7 +556,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
     auto code_of = [&](int32_t j, int rowcode) { return a.codes_by_entry ? (int)a.codes[j] : rowcode; };
     constexpr bool BT = MODE == 3;
     __shared__ float zbuf[BT ? CW : 1][BT ? ZMAX : 1];
-    float *zrow = zbuf[BT ? wid : 0];
+    float *zrow = zbuf[BT ? (threadIdx.x >> 6) : 0];
     for (int64_t i = wave; i < a.rows; i += nwaves) {
         const int32_t beg = a.ptr[i], end = a.ptr[i + 1];
         const Part<C> x = load_part<KP, C>(U4, i, q);
@@ -576,7 +571,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (b + s * E >= end) break;
-                    y[s] = load_part<KP, C>(V4, (uint32_t)j[s], q);
+                    y[s] = load_part<KP, C>(V4, j[s], q);
                 }
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -608,7 +603,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 if (b + s * E >= end) break;
-                y[s] = load_part<KP, C>(V4, (uint32_t)j[s], q);
+                y[s] = load_part<KP, C>(V4, j[s], q);
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -680,7 +675,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
 #pragma unroll
                     for (int s = 0; s < NS; ++s) {
                         if (b + s * E >= end) break;
-                        yb[s] = load_partb<KP, C>(Vb, (uint32_t)j[s], q);
+                        yb[s] = load_partb<KP, C>(Vb, j[s], q);
                     }
 #pragma unroll
                     for (int s = 0; s < NS; ++s) {
@@ -706,7 +701,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (b + s * E >= end) break;
-                    y[s] = load_part<KP, C>(V4, (uint32_t)j[s], q);
+                    y[s] = load_part<KP, C>(V4, j[s], q);
                 }
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -827,9 +822,8 @@ __global__ __launch_bounds__(256) void colblk_kernel(ColBlkArgs a)
     const int lane = threadIdx.x & 63, slot = lane / L, q = lane % L;
     const int xcd = (int)(blockIdx.x % NX);
     const int64_t V = (int64_t)(gridDim.x / NX) * CW;
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // scalar: wv, jc and the column loop stay uniform
-    const int64_t wv = (int64_t)(blockIdx.x / NX) * CW + wid;
-    float *acc = cb_lds + (size_t)wid * a.jw * W;
+    const int64_t wv = (int64_t)(blockIdx.x / NX) * CW + (threadIdx.x >> 6);
+    float *acc = cb_lds + (size_t)(threadIdx.x >> 6) * a.jw * W;
     const bool owner = GRAD ? slot == 0 : lane == 0;     // lanes holding accumulator slots
     for (int jl = 0; jl < a.jw; ++jl) {
         if (GRAD && owner) {
@@ -851,9 +845,6 @@ __global__ __launch_bounds__(256) void colblk_kernel(ColBlkArgs a)
             pe = a.seg[o + 1];
         }
         const int64_t rbase = rb << a.rb_shift;
-        // the block's rows from a scalar base, each gather by a 32-bit offset
-        const float4 *X4b = X4 + rbase * (KP / 4);
-        const __bf16 *Xbb = BT ? a.Xsb + rbase * KP : nullptr;
         // the first non-empty segment at or after jl
         auto next_seg = [&](int jl) {
             while (jl < jc && __builtin_amdgcn_readlane(pb, jl) == __builtin_amdgcn_readlane(pe, jl)) ++jl;
@@ -881,8 +872,8 @@ __global__ __launch_bounds__(256) void colblk_kernel(ColBlkArgs a)
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 if (b + s * E >= end) break;
-                if constexpr (BT) xb[s] = load_partb<KP, C>(Xbb, i[s] & rmask, q);
-                else x[s] = load_part<KP, C>(X4b, i[s] & rmask, q);
+                if constexpr (BT) xb[s] = load_partb<KP, C>(a.Xsb, rbase + (i[s] & rmask), q);
+                else x[s] = load_part<KP, C>(X4, rbase + (i[s] & rmask), q);
             }
             // the next chunk: the rest of this segment, else the next non-empty one
             int jl2 = jl;

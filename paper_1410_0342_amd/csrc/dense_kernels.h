@@ -933,8 +933,7 @@ template <int KP, int PREC>
 __global__ __launch_bounds__(64 * YPROX_SPLIT) void yprox_kernel(YProxArgs a)
 {
     __shared__ float s_part[YPROX_SPLIT][64];
-    // ps as a scalar: the partial-sum loops below start at it and stay uniform
-    const int el = threadIdx.x & 63, ps = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int el = threadIdx.x & 63, ps = threadIdx.x >> 6;
     const int64_t t = (int64_t)blockIdx.x * 64 + el;
     const int64_t j = t / KP;
     const int c = (int)(t % KP);
