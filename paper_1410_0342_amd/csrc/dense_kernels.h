@@ -946,6 +946,7 @@ __global__ __launch_bounds__(64 * YPROX_SPLIT) void yprox_kernel(YProxArgs a)
     if (ps == 0 && valid) {
         if (c < a.k) y = a.Y[j * a.k + c];
         al = a.alpha[j];
+#pragma unroll 8
         for (int p = c; p < a.P; p += KP) h += a.part_h[(int64_t)p * a.ldp + j];
     }
     // fixed-order reduction of this wavefront's partials, eight running sums
@@ -1132,6 +1133,8 @@ __global__ __launch_bounds__(256) void yaccept_kernel(YAcceptArgs a)
             yhi = a.yplus.hi[j * KP + c];
             if constexpr (PREC == P_BF16) ylo = a.yplus.lo[j * KP + c];
         }
+        // the loads run ahead of the sum, which keeps the order of p
+#pragma unroll 8
         for (int p = c; p < a.P; p += KP) hp += a.part_hp[(int64_t)p * a.ldp + j];
     }
     hp = sum_lanes<KP>(hp);   // the same value in every lane of the column
