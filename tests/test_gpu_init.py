@@ -67,6 +67,20 @@ INIT_CASES = [
 @pytest.mark.parametrize("layout", ["dense", "coo"])
 @pytest.mark.parametrize("spec,q", INIT_CASES)
 def test_svd_initialization_matches_the_exact_svd(layout, spec, q):
+    _check_init_svd(layout, spec, q, None)
+
+
+@pytest.mark.parametrize("layout", ["dense", "coo"])
+@pytest.mark.parametrize("l", [33, 50, 70, 96])
+def test_svd_initialization_with_wide_test_blocks(layout, l):
+    """Test blocks of 33 to 96 vectors: the block products run at every
+    width of their 16-wide tiles (three to six), on 300 rows and 90 columns
+    (ragged against the tiles and the row chunks); 96 exceeds the 90 columns,
+    so the range finder also drops directions of rank."""
+    _check_init_svd(layout, INIT_CASES[1][0], INIT_CASES[1][1], l)
+
+
+def _check_init_svd(layout, spec, q, l):
     sp = dict(spec)
     case = synth.small_mixed(sp.pop("m"), sp.pop("n"), sp.pop("k"), layout=layout, **sp)
     P = oracle_problem(case)
@@ -75,7 +89,7 @@ def test_svd_initialization_matches_the_exact_svd(layout, spec, q):
     mu, s2 = g.glrm_column_scaling(data)
     k = case.k + 1
     model = data.variant(k=k, offset=True, col_weight=1.0 / s2)
-    l = case.k + 10
+    l = case.k + 10 if l is None else l
     omega = torch.from_numpy(synth.rng(300, 5, spec["seed"]).standard_normal((case.n, l)).astype(np.float32)).to(DEV)
     X, Y, sv = g.glrm_init_svd(model, omega, mu=mu, sigma2=s2, power_iters=q)
     Xg, Yg = X.cpu().numpy().astype(np.float64), Y.cpu().numpy().astype(np.float64)
