@@ -291,48 +291,47 @@ __global__ __launch_bounds__(64) void pp_solve_kernel(PPArgs a)
     // 64 / KP rows per wavefront, KP lanes each: the rows share every barrier
     // of the factorization and the solves
     constexpr int NR = 64 / KP;
-    __shared__ double sMall[NR][KP][KP + 1];
-    __shared__ double sRall[NR][KP];
+    // Per row, the lower triangle of the first k coordinates, packed by rows
+    // (entry (r, c), c <= r < k, at r (r + 1) / 2 + c), then the right-hand
+    // side (KP): pp_solve_lds_doubles(k) doubles, sized at launch, so the LDS
+    // follows the rank and the wavefronts per CU grow as it falls.
+    extern __shared__ double pp_solve_lds[];
     const int sub = threadIdx.x / KP, lane = threadIdx.x % KP;
-    double (&sM)[KP][KP + 1] = sMall[sub];
-    double *sR = sRall[sub];
+    const int k = a.k, tri = k * (k + 1) / 2;
+    double *sM = pp_solve_lds + (size_t)sub * (tri + KP);
+    double *sR = sM + tri;
+    auto at = [](int r, int c) { return r * (r + 1) / 2 + c; };
     const int64_t irow = (int64_t)blockIdx.x * NR + sub;
     const int64_t i = min<int64_t>(irow, a.rows - 1);   // a row past the end repeats the last, not stored
     const float *g = a.gram + i * GSZ;
-    const int k = a.k;
     const double al = (double)a.alpha[i];
     const double h = 1.0 / (2.0 * al);
-    // the symmetric matrix from the upper tiles that meet the rank (the rest
-    // of its lower triangle is set below)
+    // the lower triangle from the upper tiles that meet the rank (G is
+    // symmetric: tile entry (rr, cc) is entry (cc, rr)); tile coordinates
+    // past k are padding
     const int nt = pp_nt(k), ut = nt * (nt + 1) / 2;
     for (int e = lane; e < ut * 16; e += KP) {
         int ta, tb;
         tile_of_rt(e >> 4, nt, ta, tb);
         const int rr = 4 * ta + ((e >> 2) & 3), cc = 4 * tb + (e & 3);
-        const double v = (double)g[e];
-        sM[rr][cc] = v;
-        sM[cc][rr] = v;
+        if (rr < k && cc < k) sM[at(max(rr, cc), min(rr, cc))] = (double)g[e];
     }
     __syncthreads();
-    // coordinates past k: identity rows (the lower part is all the factorization reads)
-    for (int c = 0; c <= lane; ++c)
-        if (lane >= k || c >= k) sM[lane][c] = lane == c ? 1.0 : 0.0;
-    if (lane < k) sM[lane][lane] += h;
+    if (lane < k) sM[at(lane, lane)] += h;
     __syncthreads();
-    // Cholesky, lower triangle in place.  Coordinates past k are identity
-    // rows with a zero right-hand side: their factor and solution are exact
-    // without a step, so the steps stop at k.
+    // Cholesky, lower triangle in place.  Coordinates past k take no part:
+    // their right-hand side and solution are 0.
     for (int j = 0; j < k; ++j) {
         if (lane == j) {
-            double d = sM[j][j];
-            for (int l = 0; l < j; ++l) d -= sM[j][l] * sM[j][l];
-            sM[j][j] = sqrt(d);
+            double d = sM[at(j, j)];
+            for (int l = 0; l < j; ++l) d -= sM[at(j, l)] * sM[at(j, l)];
+            sM[at(j, j)] = sqrt(d);
         }
         __syncthreads();
         if (lane > j && lane < k) {
-            double s = sM[lane][j];
-            for (int l = 0; l < j; ++l) s -= sM[lane][l] * sM[j][l];
-            sM[lane][j] = s / sM[j][j];
+            double s = sM[at(lane, j)];
+            for (int l = 0; l < j; ++l) s -= sM[at(lane, l)] * sM[at(j, l)];
+            sM[at(lane, j)] = s / sM[at(j, j)];
         }
         __syncthreads();
     }
@@ -342,15 +341,15 @@ __global__ __launch_bounds__(64) void pp_solve_kernel(PPArgs a)
         sR[lane] = bc + h * x;
         __syncthreads();
         for (int j = 0; j < k; ++j) {         // L y = rhs
-            if (lane == j) sR[j] = sR[j] / sM[j][j];
+            if (lane == j) sR[j] = sR[j] / sM[at(j, j)];
             __syncthreads();
-            if (lane > j && lane < k) sR[lane] -= sM[lane][j] * sR[j];
+            if (lane > j && lane < k) sR[lane] -= sM[at(lane, j)] * sR[j];
             __syncthreads();
         }
         for (int j = k - 1; j >= 0; --j) {    // L^T x = y
-            if (lane == j) sR[j] = sR[j] / sM[j][j];
+            if (lane == j) sR[j] = sR[j] / sM[at(j, j)];
             __syncthreads();
-            if (lane < j) sR[lane] -= sM[j][lane] * sR[j];
+            if (lane < j) sR[lane] -= sM[at(j, lane)] * sR[j];
             __syncthreads();
         }
         x = lane < k ? prox_elem64(a.reg, al, sR[lane], lane) : 0.0;
@@ -359,13 +358,21 @@ __global__ __launch_bounds__(64) void pp_solve_kernel(PPArgs a)
     if (lane < k && irow < a.rows) a.trial[i * k + lane] = (float)x;
 }
 
+// LDS of one solve workgroup: 64 / kp rows, each the packed lower triangle of
+// k coordinates and a right-hand side of kp.
+static size_t pp_solve_lds_bytes(int k, int kp)
+{
+    return sizeof(double) * (size_t)(64 / kp) * ((size_t)k * (k + 1) / 2 + kp);
+}
+
 hipError_t launch_pp_solve(const PPArgs &a, hipStream_t st)
 {
+    if (a.k < 1 || a.k > a.kp) return hipErrorInvalidValue;
     if (a.rows <= 0) return hipSuccess;
     switch (a.kp) {
-    case 16: hipLaunchKernelGGL(pp_solve_kernel<16>, dim3((unsigned)((a.rows + 3) / 4)), dim3(64), 0, st, a); break;
-    case 32: hipLaunchKernelGGL(pp_solve_kernel<32>, dim3((unsigned)((a.rows + 1) / 2)), dim3(64), 0, st, a); break;
-    case 64: hipLaunchKernelGGL(pp_solve_kernel<64>, dim3((unsigned)a.rows), dim3(64), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(pp_solve_kernel<16>, dim3((unsigned)((a.rows + 3) / 4)), dim3(64), pp_solve_lds_bytes(a.k, 16), st, a); break;
+    case 32: hipLaunchKernelGGL(pp_solve_kernel<32>, dim3((unsigned)((a.rows + 1) / 2)), dim3(64), pp_solve_lds_bytes(a.k, 32), st, a); break;
+    case 64: hipLaunchKernelGGL(pp_solve_kernel<64>, dim3((unsigned)a.rows), dim3(64), pp_solve_lds_bytes(a.k, 64), st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
