@@ -23,6 +23,8 @@ SPECS = [
     dict(m=120, n=50, k=4, seed=201, kinds=(0, 1, 2), rx=(1, 0.5), ry=(1, 0.5), missing=0.3),
     dict(m=200, n=60, k=6, seed=202, kinds=(0,), rx=(1, 2.0), ry=(1, 2.0), missing=0.2),
     dict(m=64, n=130, k=12, seed=203, kinds=(0, 1, 2, 3, 4), rx=(1, 0.3), ry=(1, 0.3), missing=0.5),
+    # a table smaller than one tile in both directions
+    dict(m=9, n=7, k=2, seed=206, kinds=(0,), rx=(1, 0.5), ry=(1, 0.5), missing=0.2),
     # a rank whose Gram products take three 16-wide tiles (ragged at 36)
     dict(m=300, n=80, k=36, seed=205, kinds=(0, 1), rx=(1, 0.5), ry=(1, 0.5), missing=0.3),
 ]

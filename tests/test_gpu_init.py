@@ -80,6 +80,13 @@ def test_svd_initialization_with_wide_test_blocks(layout, l):
     _check_init_svd(layout, INIT_CASES[1][0], INIT_CASES[1][1], l)
 
 
+@pytest.mark.parametrize("layout", ["dense", "coo"])
+def test_svd_initialization_on_a_table_smaller_than_one_tile(layout):
+    """9 x 6 with two factors: every product is one ragged tile in both
+    directions, and the test block (8 vectors) is wider than the table."""
+    _check_init_svd(layout, dict(m=9, n=6, k=2, seed=303, kinds=(0, 1), missing=0.2), 4, 8)
+
+
 def _check_init_svd(layout, spec, q, l):
     sp = dict(spec)
     case = synth.small_mixed(sp.pop("m"), sp.pop("n"), sp.pop("k"), layout=layout, **sp)
