@@ -13,51 +13,99 @@ namespace glrm_host {
 
 void sym_eig(int n, const double *A, double *w, double *V)
 {
-    std::vector<double> a(A, A + (size_t)n * n);
+    if (n <= 0) return;
+    std::vector<double> a(A, A + (size_t)n * n), u(n), p(n), d(n), e(n, 0.0);
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) V[i * n + j] = i == j ? 1.0 : 0.0;
-    double frob = 0.0;
-    for (double x : a) frob += x * x;
-    for (int sweep = 0; sweep < 64; ++sweep) {
-        double off = 0.0;
-        for (int p = 0; p < n; ++p)
-            for (int q = p + 1; q < n; ++q) off += a[p * n + q] * a[p * n + q];
-        if (off <= 1e-32 * frob || off == 0.0) break;
-        for (int p = 0; p < n; ++p) {
-            for (int q = p + 1; q < n; ++q) {
-                const double apq = a[p * n + q];
-                if (apq == 0.0) continue;
-                // rotation in the (p, q) plane that zeroes a_pq: t = tan(phi)
-                // is the smaller root of t^2 + 2 theta t - 1 = 0
-                const double theta = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
-                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-                for (int r = 0; r < n; ++r) {
-                    const double arp = a[r * n + p], arq = a[r * n + q];
-                    a[r * n + p] = c * arp - s * arq;
-                    a[r * n + q] = s * arp + c * arq;
-                }
-                for (int r = 0; r < n; ++r) {
-                    const double apr = a[p * n + r], aqr = a[q * n + r];
-                    a[p * n + r] = c * apr - s * aqr;
-                    a[q * n + r] = s * apr + c * aqr;
-                }
-                a[p * n + q] = a[q * n + p] = 0.0;
-                for (int r = 0; r < n; ++r) {
-                    const double vrp = V[r * n + p], vrq = V[r * n + q];
-                    V[r * n + p] = c * vrp - s * vrq;
-                    V[r * n + q] = s * vrp + c * vrq;
-                }
+    // work on A / max |a_ij| (squares of tiny or huge entries neither
+    // underflow nor overflow); the eigenvalues are scaled back at the end
+    double scale = 0.0;
+    for (double x : a) scale = std::max(scale, std::fabs(x));
+    if (scale > 0.0)
+        for (double &x : a) x /= scale;
+    // Householder reduction to tridiagonal form: step k reflects column k
+    // below the diagonal onto its first coordinate with H = I - beta u u^T,
+    // B <- H B H on the trailing block as B - u q^T - q u^T (p = beta B u,
+    // q = p - (beta u^T p / 2) u), and V <- V H.
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m0 = k + 1;
+        double norm2 = 0.0;
+        for (int i = m0; i < n; ++i) norm2 += a[i * n + k] * a[i * n + k];
+        const double x0 = a[m0 * n + k];
+        const double alpha = x0 >= 0.0 ? -std::sqrt(norm2) : std::sqrt(norm2);
+        const double uu = 2.0 * (norm2 - alpha * x0);   // u^T u for u = x - alpha e1
+        if (!(uu > 0.0)) continue;                      // the column is already reduced
+        const double beta = 2.0 / uu;
+        for (int i = m0; i < n; ++i) u[i] = a[i * n + k];
+        u[m0] = x0 - alpha;
+        double up = 0.0;
+        for (int i = m0; i < n; ++i) {
+            double s = 0.0;
+            for (int j = m0; j < n; ++j) s += a[i * n + j] * u[j];
+            p[i] = beta * s;
+            up += u[i] * p[i];
+        }
+        const double K = 0.5 * beta * up;
+        for (int i = m0; i < n; ++i) p[i] -= K * u[i];   // p now holds q
+        for (int i = m0; i < n; ++i)
+            for (int j = m0; j < n; ++j) a[i * n + j] -= u[i] * p[j] + p[i] * u[j];
+        for (int i = m0; i < n; ++i) a[i * n + k] = a[k * n + i] = 0.0;
+        a[m0 * n + k] = a[k * n + m0] = alpha;
+        for (int r = 0; r < n; ++r) {
+            double s = 0.0;
+            for (int j = m0; j < n; ++j) s += V[r * n + j] * u[j];
+            s *= beta;
+            for (int j = m0; j < n; ++j) V[r * n + j] -= s * u[j];
+        }
+    }
+    for (int i = 0; i < n; ++i) d[i] = a[i * n + i];
+    for (int i = 0; i + 1 < n; ++i) e[i] = a[(i + 1) * n + i];
+    // Implicit symmetric QR steps with the Wilkinson shift on the unreduced
+    // block lo..hi (e[i] couples i and i + 1): a Givens rotation in the plane
+    // (k, k + 1), G = [c -s; s c], takes T to G^T T G and chases the bulge
+    // down the block; V <- V G.  A coupling is dropped once it is below the
+    // rounding of its two diagonal entries.
+    const double eps = 2.220446049250313e-16;
+    int guard = 64 * n;
+    for (int hi = n - 1; hi > 0 && guard > 0;) {
+        if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
+            e[hi - 1] = 0.0;
+            --hi;
+            continue;
+        }
+        int lo = hi - 1;
+        while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+        --guard;
+        const double delta = 0.5 * (d[hi - 1] - d[hi]), eh = e[hi - 1];
+        const double mu = d[hi] - eh * eh / (delta + (delta >= 0.0 ? 1.0 : -1.0) * std::hypot(delta, eh));
+        double x = d[lo] - mu, z = e[lo];
+        for (int k = lo; k < hi; ++k) {
+            const double r = std::hypot(x, z);
+            const double c = r > 0.0 ? x / r : 1.0, s = r > 0.0 ? z / r : 0.0;
+            if (k > lo) e[k - 1] = r;
+            const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+            d[k] = c * c * dk + 2.0 * c * s * ek + s * s * dk1;
+            d[k + 1] = s * s * dk - 2.0 * c * s * ek + c * c * dk1;
+            e[k] = c * s * (dk1 - dk) + (c * c - s * s) * ek;
+            if (k + 1 < hi) {
+                x = e[k];
+                z = s * e[k + 1];
+                e[k + 1] *= c;
+            }
+            for (int row = 0; row < n; ++row) {
+                const double vk = V[row * n + k], vk1 = V[row * n + k + 1];
+                V[row * n + k] = c * vk + s * vk1;
+                V[row * n + k + 1] = c * vk1 - s * vk;
             }
         }
     }
     // eigenvalues in descending order, vectors permuted alike
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](int x, int y) { return a[x * n + x] > a[y * n + y]; });
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return d[x] > d[y]; });
     std::vector<double> Vs((size_t)n * n);
     for (int c = 0; c < n; ++c) {
-        w[c] = a[order[c] * n + order[c]];
+        w[c] = d[order[c]] * scale;
         for (int r = 0; r < n; ++r) Vs[r * n + c] = V[r * n + order[c]];
     }
     std::copy(Vs.begin(), Vs.end(), V);

@@ -4,7 +4,8 @@
 namespace glrm_host {
 
 // A (n x n, symmetric, row-major) = V diag(w) V^T, w descending, V's columns
-// the eigenvectors (cyclic Jacobi rotations).
+// the eigenvectors (Householder tridiagonalization, then implicit QR steps
+// with the Wilkinson shift).
 void sym_eig(int n, const double *A, double *w, double *V);
 
 // For factors X (m x k) and Y (n x k) with Gram matrices Gx = X^T X and
