@@ -1053,9 +1053,9 @@ int glrm_column_scaling(const glrm_data *d0, float *mu, float *sigma2, void *ws,
     HIP_TRY(launch_bracket(lo, hi, mid, out, count, L.n, true, st));
     // a search on the sign of the derivative sum: the bracket [min a - 1,
     // max a + 1] holds a minimizer of every loss here; each pass keeps one of
-    // COL_PTS + 1 = 16 sub-intervals, so 16 passes take it as far as 64
+    // COL_PTS + 1 sub-intervals, so COL_PASSES passes take it as far as 64
     // halvings, to double rounding
-    for (int it = 0; it < 16; ++it) {
+    for (int it = 0; it < COL_PASSES; ++it) {
         HIP_TRY(launch_col_pass(a, 1, coo, part, out, st));
         HIP_TRY(launch_bracket(lo, hi, mid, out, count, L.n, false, st));
     }

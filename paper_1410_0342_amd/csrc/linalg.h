@@ -85,9 +85,17 @@ hipError_t launch_to_float(const double *src, int64_t rows, int32_t b, int32_t c
 // and largest value, mode 1 the derivative sums at COL_PTS points of each
 // column's bracket [lo, hi], mode 2 the loss sum at mid.  out holds the
 // results as slot-major arrays of n (slot p of column j at p n + j).
-constexpr int COL_PTS = 15;
+// Each search pass keeps one of 2^COL_BITS sub-intervals of every bracket, at
+// COL_PTS = 2^COL_BITS - 1 points; COL_PASSES passes take it past 64 halvings.
+#ifndef GLRM_COL_BITS
+#define GLRM_COL_BITS 4
+#endif
+constexpr int COL_BITS = GLRM_COL_BITS;
+constexpr int COL_PTS = (1 << COL_BITS) - 1;
+constexpr int COL_PASSES = (64 + COL_BITS - 1) / COL_BITS;
 constexpr int COL_SLOTS = 16;                  // partial slots per row chunk and column
-constexpr int COL_CHUNKS_MAX = 256;
+static_assert(COL_BITS >= 1 && COL_PTS < COL_SLOTS, "a pass's points fit the slots");
+constexpr int COL_CHUNKS_MAX = 1024;
 constexpr int64_t COL_PART_BUDGET = int64_t(1) << 22;   // doubles of partials, at most (or one chunk)
 struct ColArgs {
     int64_t m, n, mp, ldp;

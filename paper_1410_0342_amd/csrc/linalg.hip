@@ -620,10 +620,17 @@ hipError_t launch_to_float(const double *src, int64_t rows, int32_t b, int32_t c
 // the column's bracket; mode 2: the loss sum at mid.  Partial sums per row
 // chunk, COL_SLOTS of them per column, combined in chunk order.
 
+// Row chunks of the dense column passes: a thread per column and chunk walks
+// the chunk's rows, so a narrow table needs many chunks to fill the device.
+// The chunks make at most 1024 workgroups in all, the number resident at once
+// (four per CU on 256 CUs at this kernel's registers): one more would run
+// alone in a second round.  Within the partials' budget.
 int col_pass_chunks(int64_t m, int64_t n)
 {
+    const int64_t cblocks = (std::max<int64_t>(n, 1) + 255) / 256;
+    const int64_t want = std::max<int64_t>(1, 1024 / cblocks);
     const int64_t by_budget = COL_PART_BUDGET / ((int64_t)COL_SLOTS * std::max<int64_t>(n, 1));
-    return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)COL_CHUNKS_MAX, (m + 255) / 256, by_budget}));
+    return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)COL_CHUNKS_MAX, want, (m + 255) / 256, by_budget}));
 }
 
 int64_t col_part_doubles(int64_t m, int64_t n) { return (int64_t)col_pass_chunks(m, n) * COL_SLOTS * n; }
@@ -698,6 +705,35 @@ __device__ __forceinline__ void col_rows(const ColArgs &a, int64_t j, int64_t r0
     } else {
         x[0] = a.mid[j];
     }
+    if constexpr (KIND == L_LOGISTIC) {
+        // The labels are +1 and -1, so at each point the term takes one of two
+        // values: the rows are counted by label and each value is taken once
+        // per column, n+ t(x, +1) + n- t(x, -1) (any other label takes the
+        // formula in the loop).  Nothing is held per point during the loop.
+        double cnt_p = 0.0, cnt_m = 0.0;
+        for (int64_t i = r0; i < r1; ++i) {
+            const float av = a.Ap[i * a.ldp + j];
+            if (!(av == av)) continue;
+            if (av == 1.0f) {
+                cnt_p += 1.0;
+            } else if (av == -1.0f) {
+                cnt_m += 1.0;
+            } else {
+#pragma unroll
+                for (int p = 0; p < (MODE == 1 ? COL_PTS : 1); ++p)
+                    c.s[p] += MODE == 1 ? loss_g64(KIND, lev, par, col_point(a.lo[j], a.hi[j], p), (double)av)
+                                        : loss_l64(KIND, lev, par, x[0], (double)av);
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < (MODE == 1 ? COL_PTS : 1); ++p) {
+            const double xp = MODE == 1 ? x[p] : x[0];
+            const double tp = MODE == 1 ? loss_g64(KIND, lev, par, xp, 1.0) : loss_l64(KIND, lev, par, xp, 1.0);
+            const double tm = MODE == 1 ? loss_g64(KIND, lev, par, xp, -1.0) : loss_l64(KIND, lev, par, xp, -1.0);
+            c.s[p] += cnt_p * tp + cnt_m * tm;
+        }
+        return;
+    }
     for (int64_t i = r0; i < r1; ++i) {
         const float av = a.Ap[i * a.ldp + j];
         if (!(av == av)) continue;
@@ -751,7 +787,7 @@ __global__ __launch_bounds__(256) void col_reduce_kernel(const double *part, int
     ColAcc<MODE> c;
     col_init<MODE>(c);
     if (j < n) {
-#pragma unroll 2
+#pragma unroll 8
         for (int r = w; r < R; r += 4) {
             ColAcc<MODE> o;
 #pragma unroll
