@@ -109,14 +109,22 @@ hipError_t launch_reg_grad(Reg r, const float *V, int64_t rows, int32_t k, float
     return hipGetLastError();
 }
 
-// Regularizer sum over a factor, in double; one partial per workgroup.
+// Regularizer sum over a factor, in double; one partial per workgroup.  A
+// thread's coordinate advances with its flat index (one division per thread,
+// then a compare and subtract per step).
 __global__ __launch_bounds__(256) void regsum_kernel(Reg r, const float *V, int64_t rows, int32_t k, double *part)
 {
     __shared__ double s[4];
     double acc = 0.0;
-    const int64_t total = rows * k;
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256)
-        acc += reg_elem64(r, (double)V[t], (int)(t % k));
+    const int64_t total = rows * k, stride = (int64_t)gridDim.x * 256;
+    const int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int dc = (int)(stride % k);
+    int c = (int)(t0 % k);
+    for (int64_t t = t0; t < total; t += stride) {
+        acc += reg_elem64(r, (double)V[t], c);
+        c += dc;
+        if (c >= k) c -= k;
+    }
     acc = sum_lanes64<64>(acc);
     if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = acc;
     __syncthreads();

@@ -45,7 +45,7 @@ int fail(int code, const char *fmt, ...)
 constexpr int P_MAX = 1024;    // workgroups (and partials) of the persistent dense fit passes, at most
 constexpr int64_t P_BYTES = 64ll << 20;  // ... and the Y-gradient partials within this (256 at least)
 constexpr int P_GRAD = 256;    // row chunks of the one-pass loss gradient
-constexpr int REG_BLOCKS = 64; // partials of a regularizer sum
+constexpr int REG_BLOCKS = 1024; // partials of a regularizer sum (workgroups: four per CU)
 constexpr int OBJ64_BLOCKS = 2048;  // workgroups (and partials) of the FP64 objective
 constexpr int AUX_SMALL = 16 * LA_MAXB * LA_MAXB;  // doubles of small matrices in the linear-algebra region
 
