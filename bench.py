@@ -211,8 +211,16 @@ def run_adjacent(name, case, steps, warmup):
         ms = e0.elapsed_time(e1) / max(steps, 1)
         out[tag] = dict(ms_per_step=ms, value=case.nnz / (ms * 1e-3), objective=info["objective"],
                         rows_rejected=info["rows_rejected"], cols_rejected=info["cols_rejected"])
+        # the dominant launch (slot 0: the fused row pass, or the rows' Gram
+        # pass of the prox-prox update), timed with HIP events around each
+        # launch on the fit's stream, in a shorter fit from the same state
+        kinfo = g.glrm_fit(data, X.clone(), Y.clone(), ax.clone(), ay.clone(), min(max(steps, 1), 10),
+                           precision=prec, init_alpha=False, flags=g.WS_PREPARED | g.TIME_KERNELS, update=upd)
+        out[tag]["launch0_ms"] = kinfo["kernel_ms"][0] / max(kinfo["kernel_calls"][0], 1)
         log("%s: %.4f ms/sweep, %.4g entries/s, F after %d sweeps = %.10g"
             % (tag, ms, out[tag]["value"], steps + warmup, info["objective"]))
+    if name == "census":
+        out["embedded_columns"] = int(data.d)   # the width of the table the row pass reads
     return out
 
 
@@ -406,6 +414,64 @@ def cpu_baseline(case, rows, sweeps, grad_only=False):
                 cpu=cpu, host_cpus=os.cpu_count())
 
 
+def _host_cpu():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "unknown")
+    except OSError:
+        return "unknown"
+
+
+def proxprox_cpu_baseline(case, rows, sweeps):
+    """The FP64 oracle's prox-prox sweeps (one thread) on the first `rows` rows."""
+    import numpy as np
+
+    P = _sub_problem(case, rows)
+    X = case.X0[:rows].astype(np.float64).copy()
+    Y = case.Y0.astype(np.float64).copy()
+    ax, ay = P.init_alpha(1.0)
+    t0 = time.perf_counter()
+    for _ in range(sweeps):
+        P.half_step_x_pp(X, Y, ax)
+        P.half_step_y_pp(X, Y, ay)
+    dt = time.perf_counter() - t0
+    return dict(value=P.nnz * sweeps / dt, unit="entries/s", cores=1, kind="oracle",
+                sample="first %d of %d rows (%d observed entries), %d prox-prox sweep(s) of the FP64 oracle, "
+                       "single thread, %.1f s" % (rows, case.m, P.nnz, sweeps, dt), cpu=_host_cpu())
+
+
+def impute_cpu_baseline(case, rows):
+    """The oracle's decode of every entry (one thread) on the first `rows` rows."""
+    import numpy as np
+
+    import oracle
+    X = case.X0[:rows].astype(np.float64)
+    Y = case.Y0.astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.impute(X, Y, case.col_loss, case.losses)
+    dt = time.perf_counter() - t0
+    return dict(value=rows * case.n / dt, unit="entries/s", cores=1, kind="oracle",
+                sample="first %d of %d rows (%d entries), every entry decoded by the oracle, single thread, "
+                       "%.1f s" % (rows, case.m, rows * case.n, dt), cpu=_host_cpu())
+
+
+def svd_cpu_baseline(case, rows):
+    """The oracle's SVD initialization (its exact SVD, LAPACK held to one
+    thread) on the first `rows` rows, scaled to the whole table by rows (the
+    SVD of a tall rows x n table costs in proportion to rows)."""
+    from threadpoolctl import threadpool_limits
+
+    P = _sub_problem(case, rows)
+    mu, s2 = P.column_scaling()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        P.init_svd(mu, s2, case.k)
+        dt = time.perf_counter() - t0
+    return dict(value=dt * 1e3 * case.m / rows, unit="ms", cores=1, kind="oracle",
+                sample="first %d of %d rows: the oracle's exact SVD initialization, one thread, %.1f s, "
+                       "scaled by %d / %d rows" % (rows, case.m, dt, case.m, rows), cpu=_host_cpu())
+
+
 def census_cpu_baseline(case, rows, sweeps):
     """The feature-level FP64 oracle (one thread) on the first `rows` rows."""
     import numpy as np
@@ -466,6 +532,8 @@ def main():
                     "steps": 3, "warmup": 1, "data": "synthetic", "dtype": "f32/f64",
                     "config": {"workload": "linalg_" + case.name, "m": case.m, "n": case.n, "k": case.k}}
             line.update(res)
+            if not args.no_cpu_baseline:
+                line["cpu_baseline"] = svd_cpu_baseline(case, min(args.cpu_rows // 10, case.m))
         else:
             head = next(iter(res))
             line = {"metric": "observed entries/s per sweep", "value": res[head]["value"], "unit": "entries/s",
@@ -475,8 +543,26 @@ def main():
                     "config": {"workload": args.workload + "_" + case.name, "m": case.m, "n": case.n, "k": case.k,
                                "observed_entries": int(case.nnz), "precision": head}}
             line.update(res)
-            if not args.no_cpu_baseline and args.workload == "census":
-                line["cpu_baseline"] = census_cpu_baseline(case, min(args.cpu_rows * 10, case.m), args.cpu_sweeps)
+            t0 = res[head]["launch0_ms"]
+            if args.workload == "proxprox":
+                # the rows' Gram pass: per observed entry the upper triangle of
+                # w v v^T (k (k + 1) / 2 multiply-adds) and w a v (k)
+                flops = float(case.nnz) * (case.k * (case.k + 1) + 2 * case.k)
+                line["roofline"] = {"bound": "mfma", "kernel": "pp_gram (the rows' Gram pass, fp32 matrix cores)",
+                                    "achieved": flops / (t0 * 1e-3) / 1e12, "peak": 157.3, "unit": "TFLOP/s",
+                                    "frac": flops / (t0 * 1e-3) / 1e12 / 157.3, "traffic": None,
+                                    "avg_launch_ms": t0, "algorithmic_flops_per_launch": flops}
+                if not args.no_cpu_baseline:
+                    line["cpu_baseline"] = proxprox_cpu_baseline(case, min(args.cpu_rows // 5, case.m), 1)
+            else:
+                d = int(line.get("embedded_columns") or 0) or case.n
+                alg = 5.0 * case.m * d + 8.0 * case.m * case.k + 8.0 * case.m
+                line["roofline"] = {"bound": "hbm", "kernel": "xstep (fused row pass on the embedded table)",
+                                    "achieved": alg / (t0 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": alg / (t0 * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                                    "avg_launch_ms": t0, "algorithmic_bytes_per_launch": alg}
+                if not args.no_cpu_baseline:
+                    line["cpu_baseline"] = census_cpu_baseline(case, min(args.cpu_rows * 10, case.m), args.cpu_sweeps)
         print(json.dumps(line), flush=True)
         return
     if args.workload in ("impute", "impute_dense"):
@@ -511,6 +597,8 @@ def main():
                              "frac": res["missing"]["achieved"] / HBM_PEAK_GBS,
                              "algorithmic_bytes_per_launch": res["missing"]["alg_bytes"]},
         }
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = impute_cpu_baseline(case, min(args.cpu_rows * 10, case.m))
         print(json.dumps(line), flush=True)
         return
     if args.workload == "autograd":

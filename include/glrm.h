@@ -332,7 +332,8 @@ typedef struct {
     /* with GLRM_TIME_KERNELS: summed event time (ms) and launch count per kernel kind.
      * Dense: [0] fused row pass (X step + column partials), [1] column prox, [2] column
      * check pass, [3] column accept + objective.  COO: [0] row walk, [1] column walk,
-     * [3] objective. */
+     * [3] objective.  Prox-prox update: [0] the rows' Gram pass, [1] the rows' solves
+     * and check, [2] the columns' Gram pass, solves and check, [3] the sweep's F. */
     double  kernel_ms[4];
     int32_t kernel_calls[4];
 } glrm_fit_info;

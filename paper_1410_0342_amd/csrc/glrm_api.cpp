@@ -1332,6 +1332,8 @@ int glrm_fit(const glrm_data *d0, float *X, float *Y, float *alpha_x, float *alp
         for (int t = 0; t < o->max_sweeps; ++t) {
             HIP_TRY(timer.start(0, st));
             HIP_TRY(launch_pp_gram(px, st));
+            HIP_TRY(timer.stop(st));
+            HIP_TRY(timer.start(1, st));
             HIP_TRY(launch_pp_solve(px, st));
             HIP_TRY(launch_pp_check(px, st));
             HIP_TRY(timer.stop(st));
