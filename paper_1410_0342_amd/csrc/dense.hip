@@ -140,26 +140,31 @@ __global__ __launch_bounds__(256) void reduce_dx_kernel(ReduceArgs a)
 }
 
 // FP64 objective: z in double from the fp32 factors, loss in double.  A
-// workgroup takes 16 rows x 256 columns; each thread owns one column, keeps
-// y_j in registers and reads the 16 x rows as LDS broadcasts.
-template <int KP>
+// workgroup takes PPB panels of 16 rows x 256 / PPB columns (PPB = 2 for a
+// table at most 128 columns wide, so that fewer threads idle past its
+// width); each thread owns one column of one panel, keeps y_j in registers
+// and reads the panel's 16 x rows as LDS broadcasts.
+template <int KP, int PPB>
 __global__ __launch_bounds__(256) void objective64_kernel(Obj64Args a)
 {
-    __shared__ double xsd[16][KP];
+    constexpr int CW = 256 / PPB;              // columns per panel and workgroup
+    __shared__ double xsd[PPB][16][KP];
     __shared__ double sred[4];
-    const int64_t ntile_j = (a.ldp + 255) / 256;
-    const int64_t npanels = a.mp / 16;
+    const int sub = threadIdx.x / CW, tc = threadIdx.x % CW;
+    const int64_t ntile_j = (a.ldp + CW - 1) / CW;
+    const int64_t npanels = a.mp / 16, ngroups = (npanels + PPB - 1) / PPB;
     double acc = 0.0;
-    for (int64_t blk = blockIdx.x; blk < npanels * ntile_j; blk += gridDim.x) {
-        const int64_t p = blk / ntile_j, jt = blk % ntile_j;
-        const int64_t i0 = p * 16, j = jt * 256 + threadIdx.x;
+    for (int64_t blk = blockIdx.x; blk < ngroups * ntile_j; blk += gridDim.x) {
+        const int64_t p = (blk / ntile_j) * PPB, jt = blk % ntile_j;
         __syncthreads();
-        for (int t = threadIdx.x; t < 16 * KP; t += 256) {
-            const int i = t / KP, c = t % KP;
-            xsd[i][c] = (i0 + i < a.m && c < a.k) ? (double)a.X[(i0 + i) * a.k + c] : 0.0;
+        for (int t = threadIdx.x; t < PPB * 16 * KP; t += 256) {
+            const int q = t / (16 * KP), i = (t / KP) % 16, c = t % KP;
+            const int64_t row = (p + q) * 16 + i;
+            xsd[q][i][c] = (p + q < npanels && row < a.m && c < a.k) ? (double)a.X[row * a.k + c] : 0.0;
         }
         __syncthreads();
-        if (j < a.n) {
+        const int64_t i0 = (p + sub) * 16, j = jt * CW + tc;
+        if (p + sub < npanels && j < a.n) {
             float avs[16];   // the column's 16 entries, all loads in flight at once
 #pragma unroll
             for (int ii = 0; ii < 16; ++ii) avs[ii] = a.Ap[(i0 + ii) * a.ldp + j];
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(256) void objective64_kernel(Obj64Args a)
                 if (i0 + ii < a.m && av == av) {
                     double z = 0.0;
 #pragma unroll
-                    for (int c = 0; c < KP; ++c) z += xsd[ii][c] * y[c];
+                    for (int c = 0; c < KP; ++c) z += xsd[sub][ii][c] * y[c];
                     acc += wj * loss_l64(kind, lev, par, z, (double)av);
                 }
             }
@@ -310,14 +315,23 @@ hipError_t launch_reduce_dx(const ReduceArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_objective64(const Obj64Args &a, int grid, hipStream_t st)
+template <int PPB>
+static void objective64_launch(const Obj64Args &a, int grid, hipStream_t st)
 {
     const int kp = a.k <= 16 ? 16 : (a.k <= 32 ? 32 : 64);
     switch (kp) {
-    case 16: hipLaunchKernelGGL((objective64_kernel<16>), dim3(grid), dim3(256), 0, st, a); break;
-    case 32: hipLaunchKernelGGL((objective64_kernel<32>), dim3(grid), dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((objective64_kernel<64>), dim3(grid), dim3(256), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((objective64_kernel<16, PPB>), dim3(grid), dim3(256), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((objective64_kernel<32, PPB>), dim3(grid), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((objective64_kernel<64, PPB>), dim3(grid), dim3(256), 0, st, a); break;
     }
+}
+
+static int objective64_panels_per_block(int64_t ldp) { return ldp <= 128 ? 2 : 1; }
+
+hipError_t launch_objective64(const Obj64Args &a, int grid, hipStream_t st)
+{
+    if (objective64_panels_per_block(a.ldp) == 2) objective64_launch<2>(a, grid, st);
+    else objective64_launch<1>(a, grid, st);
     return hipGetLastError();
 }
 
