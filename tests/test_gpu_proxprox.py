@@ -32,6 +32,12 @@ CASES = [
     dict(m=50, n=129, k=40, seed=405),
     dict(m=33, n=17, k=7, seed=406, empty_row=5, empty_col=3),
     dict(m=3000, n=1300, k=9, seed=407, missing=0.5),
+    # the solve's packed factor at its edges: one coordinate, a rank that
+    # fills kp = 16 and kp = 32 exactly, and the largest rank
+    dict(m=41, n=29, k=1, seed=408),
+    dict(m=90, n=60, k=16, seed=409),
+    dict(m=120, n=80, k=32, seed=410, missing=0.3),
+    dict(m=150, n=110, k=64, seed=411, missing=0.2),
 ]
 REGS = [((0, 0.0), (0, 0.0)), ((1, 0.2), (1, 0.2)), ((2, 0.05), (3, 0.0))]
 
