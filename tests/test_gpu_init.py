@@ -58,6 +58,29 @@ def test_column_scaling_matches_oracle(layout, spec):
     assert np.all(f_gpu <= f_min * (1 + 1e-6) + 1e-9)
 
 
+@pytest.mark.parametrize("layout", ["dense", "coo"])
+def test_column_scaling_wide_table_and_other_logistic_labels(layout):
+    """300 columns (two column blocks of the dense passes) over 2,000 rows
+    (several row chunks), with logistic columns whose labels include 0.5 as
+    well as -1 and +1: those entries take the per-entry formula beside the
+    labels counted by sign."""
+    case = synth.small_mixed(2000, 300, 3, seed=314, missing=0.2, kinds=(0, 1, 2), layout=layout)
+    logistic = np.array([case.losses[c][0] == 2 for c in case.col_loss])
+    if layout == "coo":
+        sel = logistic[case.cols] & (np.arange(case.vals.size) % 7 == 0)
+        case.vals[sel] = 0.5
+    else:
+        rows = np.arange(case.m)[:, None] % 7 == 0
+        case.A[rows & logistic[None, :] & (case.mask > 0)] = 0.5
+    P = oracle_problem(case)
+    mu_o, s2_o = P.column_scaling()
+    data = g.Data.from_case(case, DEV)
+    mu, s2 = g.glrm_column_scaling(data)
+    mu, s2 = mu.cpu().numpy().astype(np.float64), s2.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(s2, s2_o, rtol=1e-6)
+    np.testing.assert_allclose(mu, mu_o, rtol=1e-6, atol=1e-6)
+
+
 INIT_CASES = [
     (dict(m=400, n=60, k=5, seed=301, kinds=(0, 1), missing=0.2), 6),
     (dict(m=300, n=90, k=8, seed=302, kinds=(0, 1, 2, 3, 4), missing=0.3), 8),
