@@ -457,17 +457,64 @@ constexpr int cb_c() { return KP == 16 ? 4 : 8; }
 // caller runs exactly as many).  An entry past the segment's end repeats the
 // segment's first one, so every load and gather stays in bounds, and the
 // caller masks it out.
-template <int NS, int E, typename T>
+// O32: byte offsets of the entries fit 32 bits (checked on the host), so each
+// load takes the array's base in scalar registers and one 32-bit vector
+// offset instead of a 64-bit address per lane.
+template <int NS, int E, typename T, bool O32 = false>
 __device__ __forceinline__ void chunk_load(const T *__restrict__ idx, const float *__restrict__ val, int32_t b,
                                            int32_t end, int32_t first, int slot, T (&i)[NS], float (&v)[NS])
 {
+    static_assert(sizeof(T) == sizeof(float), "one 32-bit word per entry");
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         if (b + s * E >= end) break;
         const int32_t e = b + s * E + slot;
         const int32_t ee = e < end ? e : first;
-        i[s] = idx[ee];
-        v[s] = val[ee];
+        if constexpr (O32) {
+            const uint32_t off = (uint32_t)ee * 4u;
+            i[s] = *reinterpret_cast<const T *>(reinterpret_cast<const char *>(idx) + off);
+            v[s] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(val) + off);
+        } else {
+            i[s] = idx[ee];
+            v[s] = val[ee];
+        }
+    }
+}
+
+// A gathered factor row (the lane's C coordinates of row `row` of a padded
+// rows x KP factor).  O32: the row's byte offset fits 32 bits (checked on the
+// host), as for chunk_load.
+template <int KP, int C, bool O32>
+__device__ __forceinline__ Part<C> gather_part(const float *__restrict__ F, int32_t row, int q)
+{
+    if constexpr (O32) {
+        const float4 *p = reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(F) +
+                                                           ((uint32_t)row * KP + (uint32_t)(q * C)) * 4u);
+        Part<C> r;
+#pragma unroll
+        for (int u = 0; u < C / 4; ++u) r.v[u] = p[u];
+        return r;
+    } else {
+        return load_part<KP, C>(reinterpret_cast<const float4 *>(F), row, q);
+    }
+}
+
+template <int KP, int C, bool O32>
+__device__ __forceinline__ PartB<C> gather_partb(const __bf16 *__restrict__ F, int32_t row, int q)
+{
+    if constexpr (O32) {
+        const char *p = reinterpret_cast<const char *>(F) + ((uint32_t)row * KP + (uint32_t)(q * C)) * 2u;
+        PartB<C> r;
+        if constexpr (C == 8) {
+            const uint4 u = *reinterpret_cast<const uint4 *>(p);
+            r.w[0] = u.x; r.w[1] = u.y; r.w[2] = u.z; r.w[3] = u.w;
+        } else {
+            const uint2 u = *reinterpret_cast<const uint2 *>(p);
+            r.w[0] = u.x; r.w[1] = u.y;
+        }
+        return r;
+    } else {
+        return load_partb<KP, C>(F, row, q);
     }
 }
 
@@ -493,6 +540,8 @@ struct WalkArgs {
     // the bfloat16 trial (MODE 3): bf16 copies of both padded factors
     const __bf16 *Vsb;
     __bf16 *Usb;
+    int64_t nnz;             // entries of the walked view
+    int64_t vrows;           // rows of the gathered factor Vs (and Vsb)
 };
 
 // The bfloat16 trial keeps a row's products z_ij in LDS between the two
@@ -541,7 +590,7 @@ __device__ __forceinline__ float walk_l(const LossTab &lt, int code, int wcol, f
 // loads the indices and values of its entries, then issues their factor
 // gathers, and only then reduces (a row's last chunk runs only the steps it
 // has; entries past the row's end repeat its first entry and are masked).
-template <int KP, int MODE, int LK>
+template <int KP, int MODE, int LK, bool O32>
 __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
 {
     constexpr int C = cb_c<KP>(), L = KP / C, E = 64 / L, NS = CB_NS;
@@ -551,7 +600,6 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
     const int64_t nwaves = (int64_t)gridDim.x * CW;
     double wsum = 0.0;
     int wrej = 0;
-    const float4 *V4 = reinterpret_cast<const float4 *>(a.Vs);
     const float4 *U4 = reinterpret_cast<const float4 *>(a.Us);
     auto code_of = [&](int32_t j, int rowcode) { return a.codes_by_entry ? (int)a.codes[j] : rowcode; };
     constexpr bool BT = MODE == 3;
@@ -567,11 +615,11 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
                 int32_t j[NS];
                 float v[NS];
                 Part<C> y[NS];
-                chunk_load<NS, E>(a.idx, a.val, b, end, beg, slot, j, v);
+                chunk_load<NS, E, int32_t, O32>(a.idx, a.val, b, end, beg, slot, j, v);
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (b + s * E >= end) break;
-                    y[s] = load_part<KP, C>(V4, j[s], q);
+                    y[s] = gather_part<KP, C, O32>(a.Vs, j[s], q);
                 }
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -599,11 +647,11 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
             int32_t j[NS];
             float v[NS];
             Part<C> y[NS];
-            chunk_load<NS, E>(a.idx, a.val, b, end, beg, slot, j, v);
+            chunk_load<NS, E, int32_t, O32>(a.idx, a.val, b, end, beg, slot, j, v);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 if (b + s * E >= end) break;
-                y[s] = load_part<KP, C>(V4, j[s], q);
+                y[s] = gather_part<KP, C, O32>(a.Vs, j[s], q);
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -671,11 +719,11 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
                     int32_t j[NS];
                     float v[NS];
                     PartB<C> yb[NS];
-                    chunk_load<NS, E>(a.idx, a.val, b, end, beg, slot, j, v);
+                    chunk_load<NS, E, int32_t, O32>(a.idx, a.val, b, end, beg, slot, j, v);
 #pragma unroll
                     for (int s = 0; s < NS; ++s) {
                         if (b + s * E >= end) break;
-                        yb[s] = load_partb<KP, C>(Vb, j[s], q);
+                        yb[s] = gather_partb<KP, C, O32>(Vb, j[s], q);
                     }
 #pragma unroll
                     for (int s = 0; s < NS; ++s) {
@@ -697,11 +745,11 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkArgs a)
                 int32_t j[NS];
                 float v[NS];
                 Part<C> y[NS];
-                chunk_load<NS, E>(a.idx, a.val, b, end, beg, slot, j, v);
+                chunk_load<NS, E, int32_t, O32>(a.idx, a.val, b, end, beg, slot, j, v);
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (b + s * E >= end) break;
-                    y[s] = load_part<KP, C>(V4, j[s], q);
+                    y[s] = gather_part<KP, C, O32>(a.Vs, j[s], q);
                 }
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -1088,16 +1136,34 @@ static int walk_grid(int64_t rows)
     return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, COO_MAX_WAVES / CW));
 }
 
-template <int MODE, int LK>
-static hipError_t launch_walk_lk(const WalkArgs &a, int kp, int grid, hipStream_t st)
+template <int MODE, int LK, bool O32>
+static hipError_t launch_walk_o(const WalkArgs &a, int kp, int grid, hipStream_t st)
 {
     switch (kp) {
-    case 16: hipLaunchKernelGGL((walk_kernel<16, MODE, LK>), dim3(grid), dim3(256), 0, st, a); break;
-    case 32: hipLaunchKernelGGL((walk_kernel<32, MODE, LK>), dim3(grid), dim3(256), 0, st, a); break;
-    case 64: hipLaunchKernelGGL((walk_kernel<64, MODE, LK>), dim3(grid), dim3(256), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((walk_kernel<16, MODE, LK, O32>), dim3(grid), dim3(256), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((walk_kernel<32, MODE, LK, O32>), dim3(grid), dim3(256), 0, st, a); break;
+    case 64: hipLaunchKernelGGL((walk_kernel<64, MODE, LK, O32>), dim3(grid), dim3(256), 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// 32-bit byte offsets when every entry's offset (nnz * 4 bytes of indices,
+// as of values) and every gathered row's (vrows * kp floats) fit 32 bits;
+// the FP64 objective keeps the 64-bit form.
+static bool walk_offsets_fit_32(const WalkArgs &a, int kp)
+{
+    const int64_t lim = (int64_t)1 << 32;
+    return a.nnz * 4 <= lim && a.vrows * kp * 4 <= lim;
+}
+
+template <int MODE, int LK>
+static hipError_t launch_walk_lk(const WalkArgs &a, int kp, int grid, hipStream_t st)
+{
+    if constexpr (MODE != 2) {
+        if (walk_offsets_fit_32(a, kp)) return launch_walk_o<MODE, LK, true>(a, kp, grid, st);
+    }
+    return launch_walk_o<MODE, LK, false>(a, kp, grid, st);
 }
 
 // A table with the quadratic loss everywhere gets its own instances.
@@ -1122,6 +1188,7 @@ static WalkArgs row_walk(const glrm_data *d, const CooPtrs &p, const uint8_t *co
     a.codes = codes; a.codes_by_entry = true;
     a.lt = lt;
     a.Us = p.xs; a.Vs = p.ys;
+    a.nnz = d->nnz; a.vrows = d->n;
     return a;
 }
 
@@ -1134,6 +1201,7 @@ static WalkArgs col_walk(const glrm_data *d, const CooPtrs &p, const uint8_t *co
     a.codes = codes; a.codes_by_entry = false;
     a.lt = lt;
     a.Us = p.ys; a.Vs = p.xs;
+    a.nnz = d->nnz; a.vrows = d->m;
     return a;
 }
 
