@@ -882,7 +882,6 @@ __global__ __launch_bounds__(256) void colblk_kernel(ColBlkArgs a)
     }
     // columns of this wave: j = wv + jl * V, jl < jc (<= 64, one per lane)
     const int jc = wv < a.n ? (int)((a.n - wv + V - 1) / V) : 0;
-    const float4 *X4 = reinterpret_cast<const float4 *>(a.Xs);
     const float4 *Y4 = reinterpret_cast<const float4 *>(a.Ys);
     const uint32_t rmask = (1u << a.rb_shift) - 1;
     for (int64_t rb = xcd; rb < a.nb; rb += NX) {
@@ -920,8 +919,9 @@ __global__ __launch_bounds__(256) void colblk_kernel(ColBlkArgs a)
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 if (b + s * E >= end) break;
-                if constexpr (BT) xb[s] = load_partb<KP, C>(a.Xsb, rbase + (i[s] & rmask), q);
-                else x[s] = load_part<KP, C>(X4, rbase + (i[s] & rmask), q);
+                // within the row block (a row below 2^16 of it): 32-bit offsets from the block's base
+                if constexpr (BT) xb[s] = gather_partb<KP, C, true>(a.Xsb + rbase * KP, (int32_t)(i[s] & rmask), q);
+                else x[s] = gather_part<KP, C, true>(a.Xs + rbase * KP, (int32_t)(i[s] & rmask), q);
             }
             // the next chunk: the rest of this segment, else the next non-empty one
             int jl2 = jl;
